@@ -1,0 +1,207 @@
+/*
+ * nbound.h -- C ABI of libnbound, a HIP (gfx950) implementation of the
+ * data-parallel hot path of Neural Bounding (Liu, Fischer, Yoo, Ritschel,
+ * "Neural Bounding", SIGGRAPH 2024, arXiv 2310.06822).
+ *
+ * The problem (Sec. 3.1, "Method"): an indicator f(x) in {0,1} is 1 inside an
+ * object and on its surface; a query g(r) over a region r is 1 iff f is 1
+ * somewhere in r (for points g = f).  A bound h_theta(r) in {0,1} must be 1
+ * wherever g(r) = 1 and may also be 1 elsewhere (false positives).  h_theta
+ * is an MLP with a sigmoid output rounded to {0,1} (Sec. 3.4,
+ * "Architecture"), trained with the asymmetric weighted cross-entropy of
+ * Eq. 1 by Adam (Sec. 3.4, "Training"), on regions drawn uniformly and
+ * labelled by the exact query (Alg. 1).
+ *
+ * Conventions shared by every call
+ *   - Every call returns nb_status.  NB_OK is 0.  On failure the call has
+ *     enqueued no work, and nb_last_error() returns a message (per thread).
+ *   - Array arguments are DEVICE pointers owned by the caller unless the
+ *     argument name ends in _host.  Arrays are dense and row-major.
+ *   - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL is
+ *     the null stream) and runs asynchronously: results are valid once the
+ *     stream has been synchronised.  Only set-up calls synchronise: the
+ *     *_create / *_destroy calls (which allocate or free memory),
+ *     nb_voxelize_metaballs, and nb_bound_train_step when its batch grows
+ *     beyond every earlier batch (it then enlarges its work space).
+ *   - Queries are float32 rows:  point [n, d] (d = 2, 3 or 4: x, y, z, t);
+ *     ray [n, 6] = (origin, unit direction); box [n, 6] = (min corner,
+ *     max corner); plane [n, 6] = (point p0, unit normal).  These follow the
+ *     supplemental "Parameterization" paragraph.
+ *   - Parameters theta are float32 in linear-layer layout: for each layer in
+ *     order, W[out][in] row-major, then b[out].  A bound "in_dim x w^H"
+ *     has layers in_dim -> w -> ... -> w (H hidden layers) -> 1 logit.
+ *   - The decision uses the output epsilon of the supplemental "Numerics"
+ *     paragraph: h = 1 iff sigmoid(z) + eps >= 1/2, evaluated as
+ *     !(z < tau) with tau = ln((1/2 - eps)/(1/2 + eps)) rounded to float32.
+ *     NaN logits give h = 1 (the conservative side).
+ *   - The handles (nb_indicator, nb_bound) own device memory on the device
+ *     that was current when they were created; use them with that device
+ *     current.  A handle may be used from one stream at a time.
+ */
+#ifndef NBOUND_H
+#define NBOUND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nb_status;
+enum {
+  NB_OK = 0,
+  NB_ERR_INVALID_ARG = 1, /* NULL pointer, bad size, shape or kind */
+  NB_ERR_NO_DEVICE = 2,   /* no HIP device visible */
+  NB_ERR_HIP = 3,         /* a HIP runtime call failed (message has the code) */
+  NB_ERR_OOM = 4,         /* device allocation failed */
+  NB_ERR_NONFINITE = 5,   /* reserved: non-finite loss detected */
+  NB_ERR_UNSUPPORTED = 6  /* valid request this build has no kernel for */
+};
+
+/* Query kinds (Sec. 4.2, "Query types"). */
+enum { NB_QUERY_POINT = 0, NB_QUERY_RAY = 1, NB_QUERY_BOX = 2, NB_QUERY_PLANE = 3 };
+
+/* Arithmetic of the hidden layers. */
+enum { NB_F32 = 0, NB_BF16 = 1 };
+
+typedef struct nb_indicator nb_indicator;
+typedef struct nb_bound nb_bound;
+
+/* Message of the last failed call on this thread ("" if none).  The string
+ * is owned by the library and valid until the next call on this thread. */
+const char* nb_last_error(void);
+
+/* Library version (major, minor); never fails for non-NULL pointers. */
+nb_status nb_version(int* major, int* minor);
+
+/* Number of visible HIP devices (0 is not an error here). */
+nb_status nb_device_count(int* count);
+
+/* ------------------------------------------------------------------------
+ * Indicators f (Sec. 3.1).  Synthetic scenes stand in for the paper's
+ * images, voxelised meshes and animations (Sec. 4.2, "Indicators").
+ * ---------------------------------------------------------------------- */
+
+/* 2-D union of discs: f(x, y) = 1 iff (x-cx)^2 + (y-cy)^2 <= r^2 for some
+ * disc.  discs_host: [k, 3] rows (cx, cy, r), copied.  1 <= k <= 64. */
+nb_status nb_indicator_discs2d(const float* discs_host, int k, nb_indicator** out);
+
+/* 3-D voxel grid over [-1, 1]^3: grid is uint8[n^3] (device), x fastest,
+ * index (k*n + j)*n + i, any non-zero byte is occupied; copied into the
+ * handle.  The cell of a coordinate p is floor((p + 1) * (n/2)) (p = 1 maps
+ * to n - 1); points outside the cube have f = 0.  n is 2..1024. */
+nb_status nb_indicator_voxels(const uint8_t* grid, int n, nb_indicator** out);
+
+/* 4-D moving metaballs: ball b moves from a_b (t = 0) to b_b (t = 1) along
+ * c_b(t) = a_b + t (b_b - a_b); f(x, t) = 1 iff
+ * sum_b R_b^2 / |x - c_b(t)|^2 >= iso.  Arrays [k,3], [k,3], [k] on the
+ * host, copied.  1 <= k <= 64. */
+nb_status nb_indicator_metaballs4d(const float* a_host, const float* b_host, const float* radii_host,
+                                   int k, float iso, nb_indicator** out);
+
+/* Dimension of the indicator's domain (2, 3 or 4). */
+nb_status nb_indicator_dim(const nb_indicator* ind, int* dim);
+
+nb_status nb_indicator_destroy(nb_indicator* ind);
+
+/* Voxelise a 3-D metaball field: grid[(k*n + j)*n + i] = 1 iff
+ * sum_b R_b^2 / |c_ijk - c_b|^2 >= iso at the cell centre
+ * c_i = (2i + 1)/n - 1.  centres_host [k,3], radii_host [k]; grid is a
+ * device uint8[n^3] written by the call.  1 <= k <= 64, 2 <= n <= 1024.
+ * A set-up call: it synchronises `stream` before returning. */
+nb_status nb_voxelize_metaballs(const float* centres_host, const float* radii_host, int k, float iso,
+                                int n, uint8_t* grid, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Exact query g (Sec. 3.1; Sec. 4.2: any() of the indicator over the region)
+ *   point  g = f(x)                       (any indicator; d = its dimension)
+ *   ray    g = max_j f(o + t_j d), t_j = 4 j / 255 for j = 0..255
+ *                                          (voxel indicators)
+ *   box    g = 1 iff an occupied cell meets the closed box [lo, hi]
+ *                                          (voxel indicators)
+ *   plane  g = 1 iff an occupied cell meets the plane through p0 with unit
+ *          normal n: |n.(c - p0)| <= (|n_x| + |n_y| + |n_z|) / grid_n
+ *                                          (voxel indicators)
+ * q: [n, d] float32; g: uint8[n] (0/1).  All geometry is float32, one IEEE
+ * operation at a time, no fused multiply-add.
+ * ---------------------------------------------------------------------- */
+nb_status nb_query_exact(const nb_indicator* ind, int kind, const float* q, int64_t n, uint8_t* g,
+                         void* stream);
+
+/* ------------------------------------------------------------------------
+ * Region sampling for training (Alg. 1, "Uniform").  Draws n regions of the
+ * given kind from Philox4x32-10 (Salmon et al., SC'11) with key = seed and
+ * counter = (i, step, stream, attempt); u = (word >> 8) * 2^-24.
+ *   point (dim 2, 3): 2u - 1 per coordinate; dim 4: xyz = 2u - 1, t = u
+ *   ray:   origin 4u - 2 accepted inside the radius-2 ball (stream 1),
+ *          direction by normalised rejection from the unit ball (stream 2)
+ *   box:   centre 2u - 1 (stream 3), half extents 0.01 + 0.19u (stream 4)
+ *   plane: p0 = 2u - 1 (stream 5), normal as the ray direction (stream 6)
+ * q: [n, d] float32 written by the call (d = dim for points, else 6).
+ * ---------------------------------------------------------------------- */
+nb_status nb_sample_queries(int kind, int dim, uint64_t seed, uint64_t step, int64_t n, float* q,
+                            void* stream);
+
+/* ------------------------------------------------------------------------
+ * Bound h_theta (Sec. 3.4): in_dim -> width x n_hidden (ReLU) -> 1 logit.
+ * Supported: NB_F32 with width 16, 32 or 64 and in_dim 1..7; n_hidden 1..8.
+ * The handle owns float32 master parameters, Adam moments and work space.
+ * Parameters start at zero; set them with nb_bound_set_params.
+ * ---------------------------------------------------------------------- */
+nb_status nb_bound_create(int in_dim, int n_hidden, int width, int precision, nb_bound** out);
+nb_status nb_bound_destroy(nb_bound* b);
+nb_status nb_bound_num_params(const nb_bound* b, int64_t* n_params);
+/* Shape of the bound as created (any output pointer may be NULL). */
+nb_status nb_bound_shape(const nb_bound* b, int* in_dim, int* n_hidden, int* width, int* precision);
+
+/* Copy theta (device, float32[n_params]) into the bound; resets the Adam
+ * moments and step count to zero. */
+nb_status nb_bound_set_params(nb_bound* b, const float* theta, int64_t n_params, void* stream);
+/* Copy the float32 master parameters out (device float32[n_params]). */
+nb_status nb_bound_get_params(const nb_bound* b, float* theta, int64_t n_params, void* stream);
+
+/* Optimiser state for checkpoints: m, v are device float32[n_params]; the
+ * Adam step count travels through the host integer. */
+nb_status nb_bound_get_state(const nb_bound* b, float* m, float* v, int64_t n_params, int64_t* step_host,
+                             void* stream);
+nb_status nb_bound_set_state(nb_bound* b, const float* m, const float* v, int64_t n_params, int64_t step,
+                             void* stream);
+
+/* Forward pass and decision over n queries q [n, in_dim].
+ *   logits: float32[n] or NULL;  h: uint8[n] decisions or NULL.
+ *   g, counts: if both non-NULL, counts (uint64[4], device) is overwritten
+ *   with (TP, FP, TN, FN) of h against the exact answers g (uint8[n]).
+ * eps is the output epsilon (the paper uses 1e-5), 0 <= eps < 0.5. */
+nb_status nb_bound_forward(const nb_bound* b, const float* q, int64_t n, float eps, float* logits,
+                           uint8_t* h, const uint8_t* g, uint64_t* counts, void* stream);
+
+/* Loss of Eq. 1 and its gradient on a labelled batch (q [n, in_dim],
+ * y uint8[n]): L = (1/n) sum_i [alpha y_i softplus(-z_i) +
+ * beta (1 - y_i) softplus(z_i)].  grad: float32[n_params] overwritten with
+ * dL/dtheta; loss: float32[1] or NULL; counts: uint64[4] (TP, FP, TN, FN of
+ * the decision at eps = 1e-5 against y) or NULL.  The result is
+ * deterministic: the reduction order depends on n only. */
+nb_status nb_bound_loss_grad(nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha, float beta,
+                             float* grad, float* loss, uint64_t* counts, void* stream);
+
+/* One Adam step (Kingma & Ba 2014) on the master parameters with gradient
+ * grad (device float32[n_params]) plus lam1 sign(W) + 2 lam2 W on weight
+ * matrices (L1 + L2 regularisation, supplemental "Regularization"). */
+nb_status nb_bound_adam_step(nb_bound* b, const float* grad, float lr, float beta1, float beta2, float adam_eps,
+                             float lam1, float lam2, void* stream);
+
+/* One training step of Alg. 1 on the device: sample `batch` regions of
+ * `kind` (nb_sample_queries with this seed and step), label them with the
+ * exact query on `ind`, evaluate loss and gradient, and take one Adam step
+ * (lr, beta1 0.9, beta2 0.999, eps 1e-8).  loss: float32[1] or NULL;
+ * counts: uint64[4] on the training batch, or NULL. */
+nb_status nb_bound_train_step(nb_bound* b, const nb_indicator* ind, int kind, uint64_t seed, uint64_t step,
+                              int64_t batch, float alpha, float beta, float lr, float lam1, float lam2,
+                              float* loss, uint64_t* counts, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBOUND_H */

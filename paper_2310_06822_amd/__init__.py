@@ -1,0 +1,317 @@
+"""Neural Bounding on MI355X: Python binding of libnbound (HIP, gfx950).
+
+The functions below carry the names of the C ABI in include/nbound.h and do
+argument marshalling only: every step of the hot path (sampling, exact
+queries, MLP forward / backward, loss, Adam) runs in the library's kernels.
+Tensors must be contiguous CUDA (HIP) tensors of the documented dtype; the
+work is enqueued on torch's current stream unless a stream is given.
+
+Higher-level helpers (Indicator, Bound) own the C handles.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+
+POINT, RAY, BOX, PLANE = 0, 1, 2, 3
+KINDS = {"point": POINT, "ray": RAY, "box": BOX, "plane": PLANE}
+F32, BF16 = 0, 1
+EPS_OUT = 1e-5
+
+STATUS = {0: "NB_OK", 1: "NB_ERR_INVALID_ARG", 2: "NB_ERR_NO_DEVICE", 3: "NB_ERR_HIP", 4: "NB_ERR_OOM",
+          5: "NB_ERR_NONFINITE", 6: "NB_ERR_UNSUPPORTED"}
+
+
+class NBError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib():
+    return _lib.load()
+
+
+def _check(st: int):
+    if st != 0:
+        raise NBError(st, lib().nb_last_error().decode(errors="replace"))
+
+
+def _dev(t, dtype, name, numel=None):
+    """Device pointer of a contiguous CUDA tensor of the given dtype (None -> NULL)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _host(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+# ------------------------------------------------------------------- C ABI
+
+def nb_version():
+    ma, mi = C.c_int(), C.c_int()
+    _check(lib().nb_version(C.byref(ma), C.byref(mi)))
+    return ma.value, mi.value
+
+
+def nb_device_count() -> int:
+    n = C.c_int()
+    _check(lib().nb_device_count(C.byref(n)))
+    return n.value
+
+
+def nb_indicator_discs2d(discs) -> C.c_void_p:
+    a, p = _host(discs)
+    if a.ndim != 2 or a.shape[1] != 3:
+        raise ValueError("discs must be [k, 3]")
+    h = C.c_void_p()
+    _check(lib().nb_indicator_discs2d(p, a.shape[0], C.byref(h)))
+    return h
+
+
+def nb_indicator_voxels(grid: torch.Tensor, n: int) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(lib().nb_indicator_voxels(_dev(grid, torch.uint8, "grid", n ** 3), int(n), C.byref(h)))
+    return h
+
+
+def nb_indicator_metaballs4d(a, b, radii, iso: float = 1.0) -> C.c_void_p:
+    aa, pa = _host(a)
+    bb, pb = _host(b)
+    rr, pr = _host(radii)
+    k = rr.shape[0]
+    if aa.shape != (k, 3) or bb.shape != (k, 3):
+        raise ValueError("a and b must be [k, 3], radii [k]")
+    h = C.c_void_p()
+    _check(lib().nb_indicator_metaballs4d(pa, pb, pr, k, float(iso), C.byref(h)))
+    return h
+
+
+def nb_indicator_dim(ind) -> int:
+    d = C.c_int()
+    _check(lib().nb_indicator_dim(ind, C.byref(d)))
+    return d.value
+
+
+def nb_indicator_destroy(ind):
+    _check(lib().nb_indicator_destroy(ind))
+
+
+def nb_voxelize_metaballs(centres, radii, iso: float, n: int, grid: torch.Tensor, stream=None):
+    cc, pc = _host(centres)
+    rr, pr = _host(radii)
+    if cc.shape != (rr.shape[0], 3):
+        raise ValueError("centres must be [k, 3], radii [k]")
+    _check(lib().nb_voxelize_metaballs(pc, pr, rr.shape[0], float(iso), int(n),
+                                       _dev(grid, torch.uint8, "grid", n ** 3), _stream(stream)))
+
+
+def _rows(q, d=None):
+    if q.dim() != 2 or (d is not None and q.shape[1] != d):
+        raise ValueError(f"queries must be [n, {d if d is not None else 'd'}]")
+    return q.shape[0]
+
+
+def _query_cols(kind: int, point_dim: int) -> int:
+    return point_dim if kind == POINT else 6
+
+
+def nb_query_exact(ind, kind: int, q: torch.Tensor, g: torch.Tensor, stream=None):
+    n = _rows(q, _query_cols(int(kind), nb_indicator_dim(ind)))
+    _check(lib().nb_query_exact(ind, int(kind), _dev(q, torch.float32, "q"), n,
+                                _dev(g, torch.uint8, "g", n), _stream(stream)))
+
+
+def nb_sample_queries(kind: int, dim: int, seed: int, step: int, q: torch.Tensor, stream=None):
+    n = _rows(q, _query_cols(int(kind), int(dim)))
+    _check(lib().nb_sample_queries(int(kind), int(dim), int(seed), int(step), n,
+                                   _dev(q, torch.float32, "q"), _stream(stream)))
+
+
+def nb_bound_create(in_dim: int, n_hidden: int, width: int, precision: int = F32) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(lib().nb_bound_create(int(in_dim), int(n_hidden), int(width), int(precision), C.byref(h)))
+    return h
+
+
+def nb_bound_destroy(b):
+    _check(lib().nb_bound_destroy(b))
+
+
+def nb_bound_num_params(b) -> int:
+    n = C.c_int64()
+    _check(lib().nb_bound_num_params(b, C.byref(n)))
+    return n.value
+
+
+def nb_bound_shape(b):
+    """(in_dim, n_hidden, width, precision)."""
+    v = [C.c_int() for _ in range(4)]
+    _check(lib().nb_bound_shape(b, *[C.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def nb_bound_set_params(b, theta: torch.Tensor, stream=None):
+    _check(lib().nb_bound_set_params(b, _dev(theta, torch.float32, "theta"), theta.numel(), _stream(stream)))
+
+
+def nb_bound_get_params(b, theta: torch.Tensor, stream=None):
+    _check(lib().nb_bound_get_params(b, _dev(theta, torch.float32, "theta"), theta.numel(), _stream(stream)))
+
+
+def nb_bound_get_state(b, m: torch.Tensor, v: torch.Tensor, stream=None) -> int:
+    t = C.c_int64()
+    _check(lib().nb_bound_get_state(b, _dev(m, torch.float32, "m"), _dev(v, torch.float32, "v", m.numel()),
+                                    m.numel(), C.byref(t), _stream(stream)))
+    return t.value
+
+
+def nb_bound_set_state(b, m: torch.Tensor, v: torch.Tensor, step: int, stream=None):
+    _check(lib().nb_bound_set_state(b, _dev(m, torch.float32, "m"), _dev(v, torch.float32, "v", m.numel()),
+                                    m.numel(), int(step), _stream(stream)))
+
+
+def nb_bound_forward(b, q: torch.Tensor, eps: float = EPS_OUT, logits=None, h=None, g=None, counts=None,
+                     stream=None):
+    n = _rows(q, nb_bound_shape(b)[0])
+    _check(lib().nb_bound_forward(b, _dev(q, torch.float32, "q"), n, float(eps),
+                                  _dev(logits, torch.float32, "logits", n), _dev(h, torch.uint8, "h", n),
+                                  _dev(g, torch.uint8, "g", n), _dev(counts, torch.int64, "counts", 4),
+                                  _stream(stream)))
+
+
+def nb_bound_loss_grad(b, q: torch.Tensor, y: torch.Tensor, alpha: float, beta: float, grad: torch.Tensor,
+                       loss=None, counts=None, stream=None):
+    n = _rows(q, nb_bound_shape(b)[0])
+    _check(lib().nb_bound_loss_grad(b, _dev(q, torch.float32, "q"), _dev(y, torch.uint8, "y", n), n,
+                                    float(alpha), float(beta), _dev(grad, torch.float32, "grad", nb_bound_num_params(b)),
+                                    _dev(loss, torch.float32, "loss", 1), _dev(counts, torch.int64, "counts", 4),
+                                    _stream(stream)))
+
+
+def nb_bound_adam_step(b, grad: torch.Tensor, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+                       adam_eps: float = 1e-8, lam1: float = 0.0, lam2: float = 0.0, stream=None):
+    _check(lib().nb_bound_adam_step(b, _dev(grad, torch.float32, "grad", nb_bound_num_params(b)), float(lr), float(beta1), float(beta2),
+                                    float(adam_eps), float(lam1), float(lam2), _stream(stream)))
+
+
+def nb_bound_train_step(b, ind, kind: int, seed: int, step: int, batch: int, alpha: float, beta: float = 1.0,
+                        lr: float = 1e-3, lam1: float = 0.0, lam2: float = 0.0, loss=None, counts=None,
+                        stream=None):
+    _check(lib().nb_bound_train_step(b, ind, int(kind), int(seed), int(step), int(batch), float(alpha),
+                                     float(beta), float(lr), float(lam1), float(lam2),
+                                     _dev(loss, torch.float32, "loss", 1), _dev(counts, torch.int64, "counts", 4),
+                                     _stream(stream)))
+
+
+# ------------------------------------------------------------ conveniences
+
+class Indicator:
+    """Owns an nb_indicator handle."""
+
+    def __init__(self, handle, dim: int, grid: torch.Tensor | None = None, n: int = 0):
+        self.handle, self.dim, self.grid, self.n = handle, dim, grid, n
+
+    @classmethod
+    def discs2d(cls, discs):
+        return cls(nb_indicator_discs2d(discs), 2)
+
+    @classmethod
+    def voxels(cls, grid: torch.Tensor, n: int):
+        return cls(nb_indicator_voxels(grid, n), 3, grid, n)
+
+    @classmethod
+    def metaball_voxels(cls, centres, radii, n: int, iso: float = 1.0, device="cuda"):
+        grid = torch.empty(n ** 3, dtype=torch.uint8, device=device)
+        nb_voxelize_metaballs(centres, radii, iso, n, grid)
+        return cls.voxels(grid, n)
+
+    @classmethod
+    def metaballs4d(cls, a, b, radii, iso: float = 1.0):
+        return cls(nb_indicator_metaballs4d(a, b, radii, iso), 4)
+
+    def query(self, kind, q: torch.Tensor, g: torch.Tensor | None = None) -> torch.Tensor:
+        kind = KINDS.get(kind, kind)
+        if g is None:
+            g = torch.empty(q.shape[0], dtype=torch.uint8, device=q.device)
+        nb_query_exact(self.handle, kind, q, g)
+        return g
+
+    def close(self):
+        if self.handle:
+            nb_indicator_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Bound:
+    """Owns an nb_bound handle: in_dim -> width^n_hidden -> 1 logit."""
+
+    def __init__(self, in_dim: int, n_hidden: int, width: int, precision: int = F32):
+        self.in_dim, self.n_hidden, self.width, self.precision = in_dim, n_hidden, width, precision
+        self.handle = nb_bound_create(in_dim, n_hidden, width, precision)
+        self.n_params = nb_bound_num_params(self.handle)
+
+    def set_params(self, theta):
+        if isinstance(theta, np.ndarray):
+            theta = torch.from_numpy(np.ascontiguousarray(theta, dtype=np.float32)).cuda()
+        nb_bound_set_params(self.handle, theta)
+
+    def params(self) -> torch.Tensor:
+        t = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        nb_bound_get_params(self.handle, t)
+        return t
+
+    def forward(self, q: torch.Tensor, eps: float = EPS_OUT, want_logits=True, want_h=True):
+        n = q.shape[0]
+        z = torch.empty(n, dtype=torch.float32, device=q.device) if want_logits else None
+        h = torch.empty(n, dtype=torch.uint8, device=q.device) if want_h else None
+        nb_bound_forward(self.handle, q, eps, logits=z, h=h)
+        return z, h
+
+    def counts(self, q: torch.Tensor, g: torch.Tensor, eps: float = EPS_OUT) -> torch.Tensor:
+        c = torch.zeros(4, dtype=torch.int64, device=q.device)
+        nb_bound_forward(self.handle, q, eps, g=g, counts=c)
+        return c
+
+    def close(self):
+        if self.handle:
+            nb_bound_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,61 @@
+"""ctypes loader for libnbound.so: signatures of every nbound.h entry point.
+
+Loading fails loudly if the library has not been built: there is no
+fallback implementation anywhere in the package.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnbound.so")
+
+vp, i32, i64, u64, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_float
+PP = C.POINTER(C.c_void_p)
+
+# name -> (restype, argtypes); mirrors include/nbound.h
+SIGNATURES = {
+    "nb_last_error": (C.c_char_p, []),
+    "nb_version": (i32, [C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "nb_device_count": (i32, [C.POINTER(C.c_int)]),
+    "nb_indicator_discs2d": (i32, [vp, C.c_int, PP]),
+    "nb_indicator_voxels": (i32, [vp, C.c_int, PP]),
+    "nb_indicator_metaballs4d": (i32, [vp, vp, vp, C.c_int, f32, PP]),
+    "nb_indicator_dim": (i32, [vp, C.POINTER(C.c_int)]),
+    "nb_indicator_destroy": (i32, [vp]),
+    "nb_voxelize_metaballs": (i32, [vp, vp, C.c_int, f32, C.c_int, vp, vp]),
+    "nb_query_exact": (i32, [vp, C.c_int, vp, i64, vp, vp]),
+    "nb_sample_queries": (i32, [C.c_int, C.c_int, u64, u64, i64, vp, vp]),
+    "nb_bound_create": (i32, [C.c_int, C.c_int, C.c_int, C.c_int, PP]),
+    "nb_bound_destroy": (i32, [vp]),
+    "nb_bound_num_params": (i32, [vp, C.POINTER(i64)]),
+    "nb_bound_shape": (i32, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "nb_bound_set_params": (i32, [vp, vp, i64, vp]),
+    "nb_bound_get_params": (i32, [vp, vp, i64, vp]),
+    "nb_bound_get_state": (i32, [vp, vp, vp, i64, C.POINTER(i64), vp]),
+    "nb_bound_set_state": (i32, [vp, vp, vp, i64, i64, vp]),
+    "nb_bound_forward": (i32, [vp, vp, i64, f32, vp, vp, vp, vp, vp]),
+    "nb_bound_loss_grad": (i32, [vp, vp, vp, i64, f32, f32, vp, vp, vp, vp]),
+    "nb_bound_adam_step": (i32, [vp, vp, f32, f32, f32, f32, f32, f32, vp]),
+    "nb_bound_train_step": (i32, [vp, vp, C.c_int, u64, u64, i64, f32, f32, f32, f32, f32, vp, vp, vp]),
+}
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libnbound.so once; raise if it is missing (build it first)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2310_06822_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

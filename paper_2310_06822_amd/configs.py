@@ -1,0 +1,48 @@
+"""Synthetic workloads of the bound hot path, with their sizes and seeds.
+
+The paper's images, voxelised meshes and animations (Sec. 4.2 "Indicators")
+are replaced by seeded synthetic scenes of the same kind; network shapes are
+"in_dim -> width^n_hidden -> 1".  Seeds: scene 1000+i, training stream
+2000+i, held-out evaluation 3000+i, initial weights 4000+i for workload i.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    index: int
+    kind: str              # point / ray / box / plane
+    dim: int               # indicator dimension
+    in_dim: int            # network input size
+    width: int
+    n_hidden: int
+    precision: str         # "f32" or "bf16"
+    scene: dict = field(default_factory=dict)
+    train_steps: int = 0
+    batch: int = 0
+    eval_n: int = 0
+    alpha_max: float = 100.0
+
+    @property
+    def seeds(self):
+        return {"scene": 1000 + self.index, "train": 2000 + self.index, "eval": 3000 + self.index,
+                "init": 4000 + self.index}
+
+
+DISC2D_POINT = Workload("disc2d_point", 0, "point", 2, 2, 32, 3, "f32",
+                        scene={"type": "discs", "k": 8}, train_steps=200, batch=1024, eval_n=1 << 16)
+VOXEL3D_POINT = Workload("voxel3d_point", 1, "point", 3, 3, 64, 3, "f32",
+                         scene={"type": "metaball_voxels", "k": 16, "n": 128, "rlo": 0.05, "rhi": 0.25},
+                         train_steps=5000, batch=1 << 16, eval_n=1 << 24)
+VOXEL3D_RAY = Workload("voxel3d_ray", 2, "ray", 3, 6, 128, 4, "bf16",
+                       scene={"type": "metaball_voxels", "k": 16, "n": 128, "rlo": 0.05, "rhi": 0.25, "seed_of": 1},
+                       train_steps=5000, batch=1 << 18, eval_n=1 << 24)
+METABALL4D_POINT = Workload("metaball4d_point", 4, "point", 4, 4, 256, 6, "bf16",
+                            scene={"type": "metaballs4d", "k": 24, "rlo": 0.05, "rhi": 0.2},
+                            train_steps=2000, batch=1 << 20, eval_n=1 << 24)
+
+WORKLOADS = {w.name: w for w in (DISC2D_POINT, VOXEL3D_POINT, VOXEL3D_RAY, METABALL4D_POINT)}

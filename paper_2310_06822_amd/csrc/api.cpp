@@ -1,0 +1,441 @@
+// extern "C" entry points of libnbound (declared and documented in nbound.h):
+// argument checks, handle life cycle, and the launch sequences.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <vector>
+
+#include "nb_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+nb_status require_device() {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+    nb_set_error("no HIP device is visible");
+    return NB_ERR_NO_DEVICE;
+  }
+  return NB_OK;
+}
+
+template <class T>
+nb_status dev_alloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return NB_OK;
+  NB_HIP(hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)));
+  return NB_OK;
+}
+
+template <class T>
+void dev_free(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+// Logit threshold of the decision sigmoid(z) + eps >= 1/2.
+float tau_of(float eps) { return (float)std::log((0.5 - (double)eps) / (0.5 + (double)eps)); }
+
+int64_t mlp_params(int in_dim, int n_hidden, int width) {
+  return (int64_t)width * in_dim + width + (int64_t)(n_hidden - 1) * ((int64_t)width * width + width) + width + 1;
+}
+
+int kind_dim(int kind, int point_dim) { return kind == NB_QUERY_POINT ? point_dim : 6; }
+
+#define NB_TRY(expr)                 \
+  do {                               \
+    nb_status nb_s_ = (expr);        \
+    if (nb_s_ != NB_OK) return nb_s_; \
+  } while (0)
+
+}  // namespace
+
+void nb_set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+extern "C" {
+
+const char* nb_last_error(void) { return g_err; }
+
+nb_status nb_version(int* major, int* minor) {
+  NB_REQUIRE(major && minor, "NULL argument");
+  *major = 0;
+  *minor = 1;
+  return NB_OK;
+}
+
+nb_status nb_device_count(int* count) {
+  NB_REQUIRE(count, "count is NULL");
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) n = 0;
+  *count = n;
+  return NB_OK;
+}
+
+// --------------------------------------------------------------- indicators
+
+nb_status nb_indicator_discs2d(const float* discs_host, int k, nb_indicator** out) {
+  NB_REQUIRE(out && discs_host, "NULL argument");
+  *out = nullptr;
+  NB_REQUIRE(k >= 1 && k <= 64, "k must be in 1..64");
+  NB_TRY(require_device());
+  auto* ind = new nb_indicator();
+  ind->type = IND_DISCS2D;
+  ind->dim = 2;
+  ind->k = k;
+  hipGetDevice(&ind->device);
+  nb_status st = dev_alloc(&ind->params, (size_t)3 * k);
+  if (st == NB_OK && hipMemcpy(ind->params, discs_host, sizeof(float) * 3 * k, hipMemcpyHostToDevice) != hipSuccess) {
+    nb_set_error("hipMemcpy of the disc table failed");
+    st = NB_ERR_HIP;
+  }
+  if (st != NB_OK) {
+    nb_indicator_destroy(ind);
+    return st;
+  }
+  *out = ind;
+  return NB_OK;
+}
+
+nb_status nb_indicator_voxels(const uint8_t* grid, int n, nb_indicator** out) {
+  NB_REQUIRE(out && grid, "NULL argument");
+  *out = nullptr;
+  NB_REQUIRE(n >= 2 && n <= 1024, "grid size n must be in 2..1024");
+  NB_TRY(require_device());
+  auto* ind = new nb_indicator();
+  ind->type = IND_VOXELS;
+  ind->dim = 3;
+  ind->n = n;
+  hipGetDevice(&ind->device);
+  const int64_t cells = (int64_t)n * n * n;
+  nb_status st = dev_alloc(&ind->grid, (size_t)cells);
+  if (st == NB_OK) st = dev_alloc(&ind->ray_t, 256);
+  if (st == NB_OK) st = dev_alloc(&ind->occupied, (size_t)cells);
+  if (st == NB_OK) st = dev_alloc(&ind->occupied_count, 1);
+  if (st == NB_OK) {
+    // ray sample parameters t_j = 4 j / 255, computed in double and rounded once
+    float t[256];
+    for (int j = 0; j < 256; ++j) t[j] = (float)(4.0 * j / 255.0);
+    if (hipMemcpy(ind->grid, grid, (size_t)cells, hipMemcpyDeviceToDevice) != hipSuccess ||
+        hipMemcpy(ind->ray_t, t, sizeof(t), hipMemcpyHostToDevice) != hipSuccess) {
+      nb_set_error("hipMemcpy of the voxel grid failed");
+      st = NB_ERR_HIP;
+    }
+  }
+  if (st == NB_OK) st = launch_collect_occupied(ind->grid, cells, ind->occupied, ind->occupied_count, nullptr);
+  if (st == NB_OK && hipDeviceSynchronize() != hipSuccess) {
+    nb_set_error("building the occupied-cell list failed");
+    st = NB_ERR_HIP;
+  }
+  if (st != NB_OK) {
+    nb_indicator_destroy(ind);
+    return st;
+  }
+  *out = ind;
+  return NB_OK;
+}
+
+nb_status nb_indicator_metaballs4d(const float* a_host, const float* b_host, const float* radii_host, int k,
+                                   float iso, nb_indicator** out) {
+  NB_REQUIRE(out && a_host && b_host && radii_host, "NULL argument");
+  *out = nullptr;
+  NB_REQUIRE(k >= 1 && k <= 64, "k must be in 1..64");
+  NB_TRY(require_device());
+  std::vector<float> prm((size_t)7 * k);
+  for (int i = 0; i < 3 * k; ++i) {
+    prm[i] = a_host[i];
+    prm[3 * k + i] = b_host[i] - a_host[i];  // path direction, one float32 subtraction
+  }
+  for (int i = 0; i < k; ++i) prm[6 * k + i] = radii_host[i];
+  auto* ind = new nb_indicator();
+  ind->type = IND_METABALLS4D;
+  ind->dim = 4;
+  ind->k = k;
+  ind->iso = iso;
+  hipGetDevice(&ind->device);
+  nb_status st = dev_alloc(&ind->params, prm.size());
+  if (st == NB_OK && hipMemcpy(ind->params, prm.data(), prm.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+    nb_set_error("hipMemcpy of the metaball table failed");
+    st = NB_ERR_HIP;
+  }
+  if (st != NB_OK) {
+    nb_indicator_destroy(ind);
+    return st;
+  }
+  *out = ind;
+  return NB_OK;
+}
+
+nb_status nb_indicator_dim(const nb_indicator* ind, int* dim) {
+  NB_REQUIRE(ind && dim, "NULL argument");
+  *dim = ind->dim;
+  return NB_OK;
+}
+
+nb_status nb_indicator_destroy(nb_indicator* ind) {
+  if (!ind) return NB_OK;
+  dev_free(ind->params);
+  dev_free(ind->grid);
+  dev_free(ind->ray_t);
+  dev_free(ind->occupied);
+  dev_free(ind->occupied_count);
+  delete ind;
+  return NB_OK;
+}
+
+nb_status nb_voxelize_metaballs(const float* centres_host, const float* radii_host, int k, float iso, int n,
+                                uint8_t* grid, void* stream) {
+  NB_REQUIRE(centres_host && radii_host && grid, "NULL argument");
+  NB_REQUIRE(k >= 1 && k <= 64, "k must be in 1..64");
+  NB_REQUIRE(n >= 2 && n <= 1024, "grid size n must be in 2..1024");
+  NB_TRY(require_device());
+  // Set-up call: the ball table goes through a temporary device buffer that
+  // is freed after the kernel has run on `stream`.
+  std::vector<float> prm((size_t)4 * k);
+  std::memcpy(prm.data(), centres_host, sizeof(float) * 3 * k);
+  std::memcpy(prm.data() + 3 * k, radii_host, sizeof(float) * k);
+  float* prm_dev = nullptr;
+  NB_TRY(dev_alloc(&prm_dev, prm.size()));
+  hipStream_t s = as_stream(stream);
+  nb_status st = NB_OK;
+  if (hipMemcpyAsync(prm_dev, prm.data(), prm.size() * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess) {
+    nb_set_error("hipMemcpyAsync of the ball table failed");
+    st = NB_ERR_HIP;
+  }
+  if (st == NB_OK) st = launch_voxelize(prm_dev, k, iso, n, grid, s);
+  if (hipStreamSynchronize(s) != hipSuccess && st == NB_OK) {
+    nb_set_error("voxelisation failed");
+    st = NB_ERR_HIP;
+  }
+  dev_free(prm_dev);
+  return st;
+}
+
+// ------------------------------------------------------------------ queries
+
+nb_status nb_query_exact(const nb_indicator* ind, int kind, const float* q, int64_t n, uint8_t* g, void* stream) {
+  NB_REQUIRE(ind, "indicator is NULL");
+  NB_REQUIRE(kind >= NB_QUERY_POINT && kind <= NB_QUERY_PLANE, "unknown query kind %d", kind);
+  return launch_query_exact(ind, kind, q, n, g, as_stream(stream));
+}
+
+nb_status nb_sample_queries(int kind, int dim, uint64_t seed, uint64_t step, int64_t n, float* q, void* stream) {
+  NB_REQUIRE(kind >= NB_QUERY_POINT && kind <= NB_QUERY_PLANE, "unknown query kind %d", kind);
+  return launch_sample(kind, dim, seed, step, n, q, as_stream(stream));
+}
+
+// -------------------------------------------------------------------- bound
+
+nb_status nb_bound_create(int in_dim, int n_hidden, int width, int precision, nb_bound** out) {
+  NB_REQUIRE(out, "out is NULL");
+  *out = nullptr;
+  NB_REQUIRE(in_dim >= 1 && in_dim <= 8, "in_dim must be in 1..8");
+  NB_REQUIRE(n_hidden >= 1 && n_hidden <= 8, "n_hidden must be in 1..8");
+  NB_REQUIRE(width >= 16 && width <= 256 && width % 16 == 0, "width must be a multiple of 16 in 16..256");
+  NB_REQUIRE(precision == NB_F32 || precision == NB_BF16, "unknown precision %d", precision);
+  if (precision != NB_F32 || !f32_supported(in_dim, n_hidden, width)) {
+    nb_set_error("no kernel for a %s bound %d x %d^%d", precision == NB_F32 ? "float32" : "bfloat16", in_dim, width,
+                 n_hidden);
+    return NB_ERR_UNSUPPORTED;
+  }
+  NB_TRY(require_device());
+  auto* b = new nb_bound();
+  b->in_dim = in_dim;
+  b->n_hidden = n_hidden;
+  b->width = width;
+  b->precision = precision;
+  hipGetDevice(&b->device);
+  b->n_params = mlp_params(in_dim, n_hidden, width);
+  b->pack_floats = f32_pack_floats(in_dim, n_hidden, width);
+  const size_t P = (size_t)b->n_params;
+  nb_status st = dev_alloc(&b->theta, P);
+  if (st == NB_OK) st = dev_alloc(&b->m, P);
+  if (st == NB_OK) st = dev_alloc(&b->v, P);
+  if (st == NB_OK) st = dev_alloc(&b->grad, P);
+  if (st == NB_OK) st = dev_alloc(&b->pack, (size_t)b->pack_floats);
+  if (st == NB_OK) st = dev_alloc(&b->partial, (size_t)f32_max_workgroups() * P);
+  if (st == NB_OK) st = dev_alloc(&b->aux, (size_t)f32_max_workgroups() * 8);
+  if (st == NB_OK) {
+    if (hipMemset(b->theta, 0, P * 4) != hipSuccess || hipMemset(b->m, 0, P * 4) != hipSuccess ||
+        hipMemset(b->v, 0, P * 4) != hipSuccess || hipMemset(b->pack, 0, (size_t)b->pack_floats * 4) != hipSuccess) {
+      nb_set_error("hipMemset of the bound state failed");
+      st = NB_ERR_HIP;
+    }
+  }
+  if (st != NB_OK) {
+    nb_bound_destroy(b);
+    return st;
+  }
+  *out = b;
+  return NB_OK;
+}
+
+nb_status nb_bound_destroy(nb_bound* b) {
+  if (!b) return NB_OK;
+  dev_free(b->theta);
+  dev_free(b->m);
+  dev_free(b->v);
+  dev_free(b->grad);
+  dev_free(b->pack);
+  dev_free(b->partial);
+  dev_free(b->aux);
+  dev_free(b->batch_q);
+  dev_free(b->batch_y);
+  delete b;
+  return NB_OK;
+}
+
+nb_status nb_bound_num_params(const nb_bound* b, int64_t* n_params) {
+  NB_REQUIRE(b && n_params, "NULL argument");
+  *n_params = b->n_params;
+  return NB_OK;
+}
+
+nb_status nb_bound_shape(const nb_bound* b, int* in_dim, int* n_hidden, int* width, int* precision) {
+  NB_REQUIRE(b, "bound is NULL");
+  if (in_dim) *in_dim = b->in_dim;
+  if (n_hidden) *n_hidden = b->n_hidden;
+  if (width) *width = b->width;
+  if (precision) *precision = b->precision;
+  return NB_OK;
+}
+
+nb_status nb_bound_set_params(nb_bound* b, const float* theta, int64_t n_params, void* stream) {
+  NB_REQUIRE(b && theta, "NULL argument");
+  NB_REQUIRE(n_params == b->n_params, "bound has %lld parameters, got %lld", (long long)b->n_params,
+             (long long)n_params);
+  hipStream_t s = as_stream(stream);
+  NB_HIP(hipMemcpyAsync(b->theta, theta, n_params * 4, hipMemcpyDeviceToDevice, s));
+  NB_HIP(hipMemsetAsync(b->m, 0, n_params * 4, s));
+  NB_HIP(hipMemsetAsync(b->v, 0, n_params * 4, s));
+  b->adam_t = 0;
+  return f32_pack(b, s);
+}
+
+nb_status nb_bound_get_params(const nb_bound* b, float* theta, int64_t n_params, void* stream) {
+  NB_REQUIRE(b && theta, "NULL argument");
+  NB_REQUIRE(n_params == b->n_params, "bound has %lld parameters, got %lld", (long long)b->n_params,
+             (long long)n_params);
+  NB_HIP(hipMemcpyAsync(theta, b->theta, n_params * 4, hipMemcpyDeviceToDevice, as_stream(stream)));
+  return NB_OK;
+}
+
+nb_status nb_bound_get_state(const nb_bound* b, float* m, float* v, int64_t n_params, int64_t* step_host,
+                             void* stream) {
+  NB_REQUIRE(b && m && v && step_host, "NULL argument");
+  NB_REQUIRE(n_params == b->n_params, "parameter count mismatch");
+  hipStream_t s = as_stream(stream);
+  NB_HIP(hipMemcpyAsync(m, b->m, n_params * 4, hipMemcpyDeviceToDevice, s));
+  NB_HIP(hipMemcpyAsync(v, b->v, n_params * 4, hipMemcpyDeviceToDevice, s));
+  *step_host = b->adam_t;
+  return NB_OK;
+}
+
+nb_status nb_bound_set_state(nb_bound* b, const float* m, const float* v, int64_t n_params, int64_t step,
+                             void* stream) {
+  NB_REQUIRE(b && m && v, "NULL argument");
+  NB_REQUIRE(n_params == b->n_params, "parameter count mismatch");
+  NB_REQUIRE(step >= 0, "step must be >= 0");
+  hipStream_t s = as_stream(stream);
+  NB_HIP(hipMemcpyAsync(b->m, m, n_params * 4, hipMemcpyDeviceToDevice, s));
+  NB_HIP(hipMemcpyAsync(b->v, v, n_params * 4, hipMemcpyDeviceToDevice, s));
+  b->adam_t = step;
+  return NB_OK;
+}
+
+nb_status nb_bound_forward(const nb_bound* b, const float* q, int64_t n, float eps, float* logits, uint8_t* h,
+                           const uint8_t* g, uint64_t* counts, void* stream) {
+  NB_REQUIRE(b && q, "NULL argument");
+  NB_REQUIRE(n > 0 && n <= (int64_t(1) << 40), "n must be positive");
+  NB_REQUIRE(eps >= 0.0f && eps < 0.5f, "eps must be in [0, 0.5)");
+  NB_REQUIRE(logits || h || (g && counts), "nothing to compute: logits, h and (g, counts) are all NULL");
+  NB_REQUIRE((g == nullptr) == (counts == nullptr), "g and counts must be given together");
+  hipStream_t s = as_stream(stream);
+  auto* cnt = reinterpret_cast<unsigned long long*>(counts);
+  if (cnt) NB_TRY(launch_zero_u64(cnt, 4, s));
+  return f32_forward(b, q, n, tau_of(eps), logits, h, g, cnt, s);
+}
+
+nb_status nb_bound_loss_grad(nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha, float beta,
+                             float* grad, float* loss, uint64_t* counts, void* stream) {
+  NB_REQUIRE(b && q && y && grad, "NULL argument");
+  NB_REQUIRE(n > 0 && n <= (int64_t(1) << 30), "n must be in 1..2^30");
+  NB_REQUIRE(std::isfinite(alpha) && std::isfinite(beta) && alpha >= 0 && beta >= 0,
+             "alpha and beta must be finite and >= 0");
+  hipStream_t s = as_stream(stream);
+  int n_wg = 0;
+  NB_TRY(f32_train_partials(b, q, y, n, alpha, beta, tau_of(1e-5f), &n_wg, s));
+  AdamArgs none{};
+  return launch_reduce(b, n_wg, grad, loss, (float)(1.0 / (double)n), reinterpret_cast<unsigned long long*>(counts),
+                       none, s);
+}
+
+namespace {
+AdamArgs adam_args(nb_bound* b, float lr, float b1, float b2, float eps, float lam1, float lam2) {
+  b->adam_t += 1;
+  AdamArgs a{};
+  a.enabled = 1;
+  a.lr = lr;
+  a.b1 = b1;
+  a.b2 = b2;
+  a.eps = eps;
+  a.bc1 = (float)(1.0 - std::pow((double)b1, (double)b->adam_t));
+  a.bc2 = (float)(1.0 - std::pow((double)b2, (double)b->adam_t));
+  a.lam1 = lam1;
+  a.lam2 = lam2;
+  return a;
+}
+}  // namespace
+
+nb_status nb_bound_adam_step(nb_bound* b, const float* grad, float lr, float beta1, float beta2, float adam_eps,
+                             float lam1, float lam2, void* stream) {
+  NB_REQUIRE(b && grad, "NULL argument");
+  NB_REQUIRE(lr > 0 && beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && adam_eps >= 0 && lam1 >= 0 && lam2 >= 0,
+             "invalid Adam constants");
+  hipStream_t s = as_stream(stream);
+  const AdamArgs a = adam_args(b, lr, beta1, beta2, adam_eps, lam1, lam2);
+  NB_TRY(launch_adam(b, grad, a, s));
+  return f32_pack(b, s);
+}
+
+nb_status nb_bound_train_step(nb_bound* b, const nb_indicator* ind, int kind, uint64_t seed, uint64_t step,
+                              int64_t batch, float alpha, float beta, float lr, float lam1, float lam2, float* loss,
+                              uint64_t* counts, void* stream) {
+  NB_REQUIRE(b && ind, "NULL argument");
+  NB_REQUIRE(kind >= NB_QUERY_POINT && kind <= NB_QUERY_PLANE, "unknown query kind %d", kind);
+  NB_REQUIRE(batch > 0 && batch <= (int64_t(1) << 30), "batch must be in 1..2^30");
+  NB_REQUIRE(lr > 0 && lam1 >= 0 && lam2 >= 0, "invalid learning rate or regularisation");
+  NB_REQUIRE(std::isfinite(alpha) && std::isfinite(beta) && alpha >= 0 && beta >= 0,
+             "alpha and beta must be finite and >= 0");
+  const int d = kind_dim(kind, ind->dim);
+  NB_REQUIRE(d == b->in_dim, "bound input dimension %d does not match the %d-D query", b->in_dim, d);
+  hipStream_t s = as_stream(stream);
+  if (b->batch_cap < batch || b->batch_cap_dim < d) {
+    // grows the work space: synchronising allocation, only when the batch grows
+    NB_HIP(hipStreamSynchronize(s));
+    dev_free(b->batch_q);
+    dev_free(b->batch_y);
+    b->batch_cap = 0;
+    NB_TRY(dev_alloc(&b->batch_q, (size_t)batch * d));
+    NB_TRY(dev_alloc(&b->batch_y, (size_t)batch));
+    b->batch_cap = batch;
+    b->batch_cap_dim = d;
+  }
+  NB_TRY(launch_sample(kind, ind->dim, seed, step, batch, b->batch_q, s));
+  NB_TRY(launch_query_exact(ind, kind, b->batch_q, batch, b->batch_y, s));
+  int n_wg = 0;
+  NB_TRY(f32_train_partials(b, b->batch_q, b->batch_y, batch, alpha, beta, tau_of(1e-5f), &n_wg, s));
+  const AdamArgs a = adam_args(b, lr, 0.9f, 0.999f, 1e-8f, lam1, lam2);
+  NB_TRY(launch_reduce(b, n_wg, nullptr, loss, (float)(1.0 / (double)batch),
+                       reinterpret_cast<unsigned long long*>(counts), a, s));
+  return f32_pack(b, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,584 @@
+// The bound h_theta as a float32 MLP on the matrix cores (Sec. 3.4,
+// "Architecture": an MLP whose output logit goes through a sigmoid and is
+// rounded to {0,1}; ReLU hidden layers here).
+//
+// Matrix-core mapping (v_mfma_f32_16x16x4f32, one wave of 64 lanes):
+//   neurons are MFMA rows, queries are MFMA columns.  A wave takes 16
+//   queries at a time; lane l owns query column c = l % 16 and, after every
+//   layer, the four neurons 16*mo + 4*(l/16) + r (r = 0..3) of each 16-row
+//   block mo.  Those four values are exactly the B operand the next layer
+//   needs if the next layer's reduction index is visited in the order
+//   (block mi, r) with lane group l/16 supplying neuron 16*mi + 4*(l/16) + r,
+//   so activations never leave registers; the weights are pre-arranged
+//   ("packed") in that order, one 64-float fragment per MFMA, so each
+//   fragment load is one coalesced 256-byte read.
+//   The first layer (in_dim <= 8 inputs) is the same product with the inputs
+//   as B operand (zero-padded to a multiple of 4).  The last layer (width ->
+//   1) is a per-lane dot product plus two cross-lane adds.
+//
+// Training (Alg. 1 steps 4-5, Eq. 1): one fused kernel runs forward, loss,
+// dL/dz and backward for the queries of a workgroup:
+//   delta_{l-1} = (W_l^T delta_l) * [a_{l-1} > 0]   (MFMA, transposed packs)
+//   dW_l += delta_l a_{l-1}^T                          (MFMA over queries; the
+//            two operands are transposed through a per-wave LDS tile)
+// and writes one partial gradient per workgroup; a second kernel sums the
+// partials in a fixed order (deterministic) and applies Adam.
+#include <algorithm>
+
+#include "nb_internal.h"
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Orders LDS traffic of one wave: the hardware executes a wave's LDS
+// operations in issue order; this keeps the compiler from moving them.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Geometry of an in_dim -> W^NH -> 1 network with KIN 4-wide input steps.
+template <int KIN, int W, int NH>
+struct Net {
+  static constexpr int RB = W / 16;             // 16-row blocks per layer
+  static constexpr int F1 = RB * KIN;           // first-layer fragments
+  static constexpr int FH = RB * RB * 4;        // fragments of one W x W layer
+  static constexpr int NFWD = F1 + (NH - 1) * FH;
+  static constexpr int NPACK = NFWD + (NH - 1) * FH;  // + transposed copies
+};
+
+// Offsets into theta (linear-layer layout), runtime in_dim.
+__host__ __device__ inline int64_t w_off(int l, int in_dim, int W) {
+  return l == 0 ? 0 : (int64_t)W * in_dim + W + (int64_t)(l - 1) * ((int64_t)W * W + W);
+}
+__host__ __device__ inline int64_t b_off(int l, int in_dim, int W, int NH) {
+  return w_off(l, in_dim, W) + (int64_t)(l == 0 ? in_dim : W) * (l == NH ? 1 : W);
+}
+
+// ------------------------------------------------------------------ packing
+
+// pack[f*64 + lane]:
+//   f < F1            first layer, block mo = f / KIN, step s = f % KIN:
+//                     W0[16mo + c][4s + g]   (0 beyond in_dim)
+//   f < NFWD          hidden layer l (1-based), fragment (mo, mi, r):
+//                     W_l[16mo + c][16mi + 4g + r]
+//   else              transposed copy of hidden layer l, fragment (mo, mi, r):
+//                     W_l[16mi + 4g + r][16mo + c]
+// with c = lane % 16, g = lane / 16.
+__global__ void k_pack(const float* __restrict__ theta, int in_dim, int W, int NH, float* __restrict__ pack,
+                       int64_t total) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int f = (int)(idx >> 6), lane = (int)(idx & 63), c = lane & 15, g = lane >> 4;
+  const int RB = W / 16, KIN = (in_dim + 3) / 4, F1 = RB * KIN, FH = RB * RB * 4;
+  const int NFWD = F1 + (NH - 1) * FH;
+  float v;
+  if (f < F1) {
+    const int mo = f / KIN, s = f % KIN, k = 4 * s + g;
+    v = k < in_dim ? theta[(int64_t)(16 * mo + c) * in_dim + k] : 0.0f;
+  } else {
+    const bool tr = f >= NFWD;
+    const int t = f - (tr ? NFWD : F1);
+    const int l = 1 + t / FH, rem = t % FH;
+    const int mo = rem / (RB * 4), mi = (rem / 4) % RB, r = rem % 4;
+    const float* Wl = theta + w_off(l, in_dim, W);
+    v = tr ? Wl[(int64_t)(16 * mi + 4 * g + r) * W + 16 * mo + c] : Wl[(int64_t)(16 * mo + c) * W + 16 * mi + 4 * g + r];
+  }
+  pack[idx] = v;
+}
+
+// ------------------------------------------------------------------ forward
+
+template <int KIN, int W, int NH>
+__global__ __launch_bounds__(256) void k_fwd(const float* __restrict__ q, int64_t n, int in_dim,
+                                             const float* __restrict__ pack, const float* __restrict__ theta,
+                                             float tau, float* __restrict__ logits, uint8_t* __restrict__ hout,
+                                             const uint8_t* __restrict__ g, unsigned long long* __restrict__ counts) {
+  using N = Net<KIN, W, NH>;
+  constexpr int RB = N::RB;
+  const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4;
+
+  float w1[N::F1];
+#pragma unroll
+  for (int f = 0; f < N::F1; ++f) w1[f] = pack[f * 64 + lane];
+  constexpr int NWH = (NH - 1) * N::FH > 0 ? (NH - 1) * N::FH : 1;
+  float wh[NWH];
+#pragma unroll
+  for (int f = 0; f < (NH - 1) * N::FH; ++f) wh[f] = pack[(N::F1 + f) * 64 + lane];
+  float wo[RB * 4];
+#pragma unroll
+  for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) wo[mo * 4 + r] = theta[w_off(NH, in_dim, W) + 16 * mo + 4 * grp + r];
+  const float bo = theta[b_off(NH, in_dim, W, NH)];
+
+  unsigned cnt[4] = {0u, 0u, 0u, 0u};
+  const int64_t nblk = (n + 15) / 16;
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t blk = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); blk < nblk; blk += nwaves) {
+    const int64_t qi = blk * 16 + c;
+    const bool valid = qi < n;
+    float a[RB * 4];
+    {
+      const float* b0 = theta + b_off(0, in_dim, W, NH);
+      floatx4 acc[RB];
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo)
+        acc[mo] = floatx4{b0[16 * mo + 4 * grp], b0[16 * mo + 4 * grp + 1], b0[16 * mo + 4 * grp + 2],
+                          b0[16 * mo + 4 * grp + 3]};
+#pragma unroll
+      for (int s = 0; s < KIN; ++s) {
+        const int k = 4 * s + grp;
+        const float x = (valid && k < in_dim) ? q[qi * in_dim + k] : 0.0f;
+#pragma unroll
+        for (int mo = 0; mo < RB; ++mo) acc[mo] = mfma4(w1[mo * KIN + s], x, acc[mo]);
+      }
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[mo * 4 + r] = fmaxf(acc[mo][r], 0.0f);
+    }
+#pragma unroll
+    for (int l = 1; l < NH; ++l) {
+      const float* bl = theta + b_off(l, in_dim, W, NH);
+      floatx4 acc[RB];
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo)
+        acc[mo] = floatx4{bl[16 * mo + 4 * grp], bl[16 * mo + 4 * grp + 1], bl[16 * mo + 4 * grp + 2],
+                          bl[16 * mo + 4 * grp + 3]};
+#pragma unroll
+      for (int mi = 0; mi < RB; ++mi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int mo = 0; mo < RB; ++mo)
+            acc[mo] = mfma4(wh[(l - 1) * N::FH + (mo * RB + mi) * 4 + r], a[mi * 4 + r], acc[mo]);
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[mo * 4 + r] = fmaxf(acc[mo][r], 0.0f);
+    }
+    float p = 0.0f;
+#pragma unroll
+    for (int i = 0; i < RB * 4; ++i) p = fmaf(wo[i], a[i], p);
+    p += __shfl_xor(p, 16);
+    p += __shfl_xor(p, 32);
+    const float z = p + bo;
+    const bool pos = !(z < tau);
+    const bool own = grp == 0 && valid;
+    if (own) {
+      if (logits) logits[qi] = z;
+      if (hout) hout[qi] = pos;
+    }
+    if (counts) {
+      const bool gv = own && g[qi] != 0;
+      cnt[0] += __popcll(__ballot(own && pos && gv));
+      cnt[1] += __popcll(__ballot(own && pos && !gv));
+      cnt[2] += __popcll(__ballot(own && !pos && !gv));
+      cnt[3] += __popcll(__ballot(own && !pos && gv));
+    }
+  }
+  if (counts && lane == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (cnt[i]) atomicAdd(&counts[i], (unsigned long long)cnt[i]);
+  }
+}
+
+// ------------------------------------------------------------------ training
+
+constexpr int kLDT = 17;  // row stride of the per-wave transpose tiles (16 queries + pad)
+
+template <int KIN, int W, int NH>
+struct TrainLds {
+  using N = Net<KIN, W, NH>;
+  __host__ __device__ static int64_t P(int in_dim) { return b_off(NH, in_dim, W, NH) + 1; }
+  static constexpr int kTile = W * kLDT;                 // one [W][17] tile
+  static constexpr int kBias = NH * W + W + 1;           // hidden biases, output weights, output bias
+  static int64_t floats(int in_dim) {
+    const int64_t head = std::max<int64_t>((int64_t)N::NPACK * 64, P(in_dim));
+    return head + kBias + 4 * 2 * kTile + 4 * 8;
+  }
+};
+
+template <int KIN, int W, int NH>
+__global__ __launch_bounds__(256, 1) void k_train(const float* __restrict__ q, const uint8_t* __restrict__ y,
+                                                  int64_t n, int in_dim, int bpw, const float* __restrict__ pack,
+                                                  const float* __restrict__ theta, float alpha, float beta,
+                                                  float inv_n, float tau, float* __restrict__ partial,
+                                                  float* __restrict__ aux) {
+  using N = Net<KIN, W, NH>;
+  using L = TrainLds<KIN, W, NH>;
+  constexpr int RB = N::RB;
+  extern __shared__ float smem[];
+  const int64_t P = L::P(in_dim);
+  const int64_t head = std::max<int64_t>((int64_t)N::NPACK * 64, P);
+  float* spack = smem;                        // packed weights; later the reduction buffer
+  float* sbias = smem + head;                 // [NH][W] biases, [W] output weights, output bias
+  float* tiles = sbias + L::kBias;            // 4 waves x (delta tile, activation tile)
+  float* saux = tiles + 4 * 2 * L::kTile;     // [4][8] per-wave loss / counts
+
+  for (int i = threadIdx.x; i < N::NPACK * 64; i += blockDim.x) spack[i] = pack[i];
+  for (int i = threadIdx.x; i < NH * W; i += blockDim.x) {
+    const int l = i / W, j = i % W;
+    sbias[i] = theta[b_off(l, in_dim, W, NH) + j];
+  }
+  for (int i = threadIdx.x; i < W + 1; i += blockDim.x) sbias[NH * W + i] = theta[w_off(NH, in_dim, W) + i];
+  __syncthreads();
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4;
+  float* dt = tiles + wave * 2 * L::kTile;    // delta tile [W][kLDT]
+  float* at = dt + L::kTile;                  // activation / input tile [W][kLDT]
+  const float* swo = sbias + NH * W;
+  const float bo = swo[W];
+
+  floatx4 gW0[RB];
+  floatx4 gWh[NH > 1 ? NH - 1 : 1][RB][RB];
+  float gb[NH][RB * 4];
+  float gwo[RB * 4];
+  float gbo = 0.0f, lsum = 0.0f;
+  unsigned cnt[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int i = 0; i < RB; ++i) gW0[i] = floatx4{0, 0, 0, 0};
+#pragma unroll
+  for (int l = 0; l < NH - 1; ++l)
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int j = 0; j < RB; ++j) gWh[l][i][j] = floatx4{0, 0, 0, 0};
+#pragma unroll
+  for (int l = 0; l < NH; ++l)
+#pragma unroll
+    for (int i = 0; i < RB * 4; ++i) gb[l][i] = 0.0f;
+#pragma unroll
+  for (int i = 0; i < RB * 4; ++i) gwo[i] = 0.0f;
+
+  const int64_t nblk = (n + 15) / 16;
+  const int64_t blk0 = (int64_t)blockIdx.x * bpw;
+  const int64_t blk1 = blk0 + bpw < nblk ? blk0 + bpw : nblk;
+  for (int64_t blk = blk0 + wave; blk < blk1; blk += 4) {
+    const int64_t qi = blk * 16 + c;
+    const bool valid = qi < n;
+    float xin[KIN];
+#pragma unroll
+    for (int s = 0; s < KIN; ++s) {
+      const int k = 4 * s + grp;
+      xin[s] = (valid && k < in_dim) ? q[qi * in_dim + k] : 0.0f;
+    }
+    // forward, keeping every layer's activations
+    float act[NH][RB * 4];
+    {
+      floatx4 acc[RB];
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo) {
+        const float* b = sbias + 16 * mo + 4 * grp;
+        acc[mo] = floatx4{b[0], b[1], b[2], b[3]};
+      }
+#pragma unroll
+      for (int s = 0; s < KIN; ++s)
+#pragma unroll
+        for (int mo = 0; mo < RB; ++mo) acc[mo] = mfma4(spack[(mo * KIN + s) * 64 + lane], xin[s], acc[mo]);
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) act[0][mo * 4 + r] = fmaxf(acc[mo][r], 0.0f);
+    }
+#pragma unroll
+    for (int l = 1; l < NH; ++l) {
+      floatx4 acc[RB];
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo) {
+        const float* b = sbias + l * W + 16 * mo + 4 * grp;
+        acc[mo] = floatx4{b[0], b[1], b[2], b[3]};
+      }
+      const float* fr = spack + (N::F1 + (l - 1) * N::FH) * 64 + lane;
+#pragma unroll
+      for (int mi = 0; mi < RB; ++mi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int mo = 0; mo < RB; ++mo) acc[mo] = mfma4(fr[((mo * RB + mi) * 4 + r) * 64], act[l - 1][mi * 4 + r], acc[mo]);
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) act[l][mo * 4 + r] = fmaxf(acc[mo][r], 0.0f);
+    }
+    float p = 0.0f;
+#pragma unroll
+    for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) p = fmaf(swo[16 * mo + 4 * grp + r], act[NH - 1][mo * 4 + r], p);
+    p += __shfl_xor(p, 16);
+    p += __shfl_xor(p, 32);
+    const float z = p + bo;
+
+    // Eq. 1 on logits: alpha y softplus(-z) + beta (1 - y) softplus(z);
+    // dl/dz = beta (1 - y) sigmoid(z) - alpha y (1 - sigmoid(z)).
+    const bool yv = valid && y[qi] != 0;
+    const float e = expf(-fabsf(z));
+    const float inv1pe = 1.0f / (1.0f + e);
+    const float sig = z >= 0.0f ? inv1pe : e * inv1pe;        // sigmoid(z)
+    const float sigm = z >= 0.0f ? e * inv1pe : inv1pe;       // 1 - sigmoid(z)
+    const float dz = valid ? inv_n * (yv ? -alpha * sigm : beta * sig) : 0.0f;
+    const bool own = grp == 0 && valid;
+    if (own) {
+      const float sp = log1pf(e);
+      lsum += yv ? alpha * (fmaxf(-z, 0.0f) + sp) : beta * (fmaxf(z, 0.0f) + sp);
+      gbo += dz;
+    }
+    const bool pos = !(z < tau);
+    cnt[0] += __popcll(__ballot(own && pos && yv));
+    cnt[1] += __popcll(__ballot(own && pos && !yv));
+    cnt[2] += __popcll(__ballot(own && !pos && !yv));
+    cnt[3] += __popcll(__ballot(own && !pos && yv));
+
+    float d[RB * 4];
+#pragma unroll
+    for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = mo * 4 + r;
+        gwo[i] = fmaf(dz, act[NH - 1][i], gwo[i]);
+        d[i] = act[NH - 1][i] > 0.0f ? dz * swo[16 * mo + 4 * grp + r] : 0.0f;
+      }
+
+#pragma unroll
+    for (int l = NH - 1; l >= 1; --l) {
+#pragma unroll
+      for (int i = 0; i < RB * 4; ++i) gb[l][i] += d[i];
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          dt[(16 * mo + 4 * grp + r) * kLDT + c] = d[mo * 4 + r];
+          at[(16 * mo + 4 * grp + r) * kLDT + c] = act[l - 1][mo * 4 + r];
+        }
+      wave_lds_sync();
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int no = 0; no < RB; ++no) {
+          const float av = dt[(16 * no + c) * kLDT + 4 * s + grp];
+#pragma unroll
+          for (int ko = 0; ko < RB; ++ko)
+            gWh[l - 1][no][ko] = mfma4(av, at[(16 * ko + c) * kLDT + 4 * s + grp], gWh[l - 1][no][ko]);
+        }
+      floatx4 acc[RB];
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo) acc[mo] = floatx4{0, 0, 0, 0};
+      const float* fr = spack + (N::NFWD + (l - 1) * N::FH) * 64 + lane;
+#pragma unroll
+      for (int mi = 0; mi < RB; ++mi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int mo = 0; mo < RB; ++mo) acc[mo] = mfma4(fr[((mo * RB + mi) * 4 + r) * 64], d[mi * 4 + r], acc[mo]);
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) d[mo * 4 + r] = act[l - 1][mo * 4 + r] > 0.0f ? acc[mo][r] : 0.0f;
+      wave_lds_sync();
+    }
+
+    // first layer: dW0 += delta_0 x^T (inputs as a [16][16] tile, zero-padded)
+#pragma unroll
+    for (int i = 0; i < RB * 4; ++i) gb[0][i] += d[i];
+#pragma unroll
+    for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dt[(16 * mo + 4 * grp + r) * kLDT + c] = d[mo * 4 + r];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) at[(4 * s + grp) * kLDT + c] = s < KIN ? xin[s < KIN ? s : 0] : 0.0f;
+    wave_lds_sync();
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int no = 0; no < RB; ++no)
+        gW0[no] = mfma4(dt[(16 * no + c) * kLDT + 4 * s + grp], at[c * kLDT + 4 * s + grp], gW0[no]);
+    wave_lds_sync();
+  }
+
+  // ---- workgroup reduction in a fixed order: wave 0 stores, waves 1..3 add
+  __syncthreads();
+  float* red = smem;
+#pragma unroll
+  for (int i = 0; i < RB * 4; ++i) {
+#pragma unroll
+    for (int m = 1; m < 16; m <<= 1) gwo[i] += __shfl_xor(gwo[i], m);
+#pragma unroll
+    for (int l = 0; l < NH; ++l)
+#pragma unroll
+      for (int m = 1; m < 16; m <<= 1) gb[l][i] += __shfl_xor(gb[l][i], m);
+  }
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    gbo += __shfl_xor(gbo, m);
+    lsum += __shfl_xor(lsum, m);
+  }
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+      auto put = [&](int64_t idx, float v) {
+        if (w == 0)
+          red[idx] = v;
+        else
+          red[idx] += v;
+      };
+#pragma unroll
+      for (int no = 0; no < RB; ++no)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int nrow = 16 * no + 4 * grp + r;
+          if (c < in_dim) put((int64_t)nrow * in_dim + c, gW0[no][r]);
+        }
+#pragma unroll
+      for (int l = 1; l < NH; ++l)
+#pragma unroll
+        for (int no = 0; no < RB; ++no)
+#pragma unroll
+          for (int ko = 0; ko < RB; ++ko)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              put(w_off(l, in_dim, W) + (int64_t)(16 * no + 4 * grp + r) * W + 16 * ko + c, gWh[l - 1][no][ko][r]);
+      if (c == 0) {
+#pragma unroll
+        for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int nrow = 16 * mo + 4 * grp + r;
+#pragma unroll
+            for (int l = 0; l < NH; ++l) put(b_off(l, in_dim, W, NH) + nrow, gb[l][mo * 4 + r]);
+            put(w_off(NH, in_dim, W) + nrow, gwo[mo * 4 + r]);
+          }
+      }
+      if (lane == 0) {
+        put(b_off(NH, in_dim, W, NH), gbo);
+        saux[w * 8 + 0] = lsum;
+        for (int i = 0; i < 4; ++i) saux[w * 8 + 1 + i] = __uint_as_float(cnt[i]);
+      }
+    }
+    __syncthreads();
+  }
+  float* out = partial + (int64_t)blockIdx.x * P;
+  for (int64_t i = threadIdx.x; i < P; i += blockDim.x) out[i] = red[i];
+  if (threadIdx.x == 0) {
+    float ls = 0.0f;
+    unsigned cs[4] = {0u, 0u, 0u, 0u};
+    for (int w = 0; w < 4; ++w) {
+      ls += saux[w * 8];
+      for (int i = 0; i < 4; ++i) cs[i] += __float_as_uint(saux[w * 8 + 1 + i]);
+    }
+    aux[blockIdx.x * 8] = ls;
+    for (int i = 0; i < 4; ++i) aux[blockIdx.x * 8 + 1 + i] = __uint_as_float(cs[i]);
+  }
+}
+
+// ---------------------------------------------------------------- dispatch
+
+constexpr int kMaxWG = 256;
+
+int cu_count() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cus[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cus[dev] = v;
+  }
+  return cus[dev];
+}
+
+template <int KIN, int W, int NH>
+nb_status fwd_launch(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
+                     const uint8_t* g, unsigned long long* counts, hipStream_t s) {
+  const int64_t nblk = (n + 15) / 16;
+  const int64_t want = (nblk + 3) / 4;
+  const int64_t cap = (int64_t)cu_count() * 2;
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min(want, cap));
+  k_fwd<KIN, W, NH><<<grid, 256, 0, s>>>(q, n, b->in_dim, b->pack, b->theta, tau, logits, h, g, counts);
+  NB_LAUNCHED();
+  return NB_OK;
+}
+
+template <int KIN, int W, int NH>
+nb_status train_launch(const nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha, float beta,
+                       float tau, int* n_wg, hipStream_t s) {
+  using L = TrainLds<KIN, W, NH>;
+  const int64_t nblk = (n + 15) / 16;
+  const int bpw = (int)((nblk + kMaxWG - 1) / kMaxWG);
+  const int grid = (int)((nblk + bpw - 1) / bpw);
+  const size_t lds = (size_t)L::floats(b->in_dim) * sizeof(float);
+  static bool attr_set[64] = {false};
+  int dev = 0;
+  NB_HIP(hipGetDevice(&dev));
+  if (dev >= 0 && dev < 64 && !attr_set[dev]) {
+    NB_HIP(hipFuncSetAttribute((const void*)k_train<KIN, W, NH>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    attr_set[dev] = true;
+  }
+  k_train<KIN, W, NH><<<grid, 256, lds, s>>>(q, y, n, b->in_dim, bpw, b->pack, b->theta, alpha, beta,
+                                             (float)(1.0 / (double)n), tau, b->partial, b->aux);
+  NB_LAUNCHED();
+  *n_wg = grid;
+  return NB_OK;
+}
+
+// (KIN, W, NH) instances: inputs 1..8, widths 16/32/64, 1..4 hidden layers.
+#define NB_F32_CASES(X) \
+  X(1, 16, 1) X(1, 16, 2) X(1, 16, 3) X(1, 16, 4) \
+  X(1, 32, 1) X(1, 32, 2) X(1, 32, 3) X(1, 32, 4) \
+  X(1, 64, 1) X(1, 64, 2) X(1, 64, 3) X(1, 64, 4) \
+  X(2, 16, 1) X(2, 16, 2) X(2, 16, 3) X(2, 16, 4) \
+  X(2, 32, 1) X(2, 32, 2) X(2, 32, 3) X(2, 32, 4) \
+  X(2, 64, 1) X(2, 64, 2) X(2, 64, 3) X(2, 64, 4)
+
+inline int kin_of(int in_dim) { return (in_dim + 3) / 4; }
+
+}  // namespace
+
+bool f32_supported(int in_dim, int n_hidden, int width) {
+  return in_dim >= 1 && in_dim <= 8 && n_hidden >= 1 && n_hidden <= 4 && (width == 16 || width == 32 || width == 64);
+}
+
+int64_t f32_pack_floats(int in_dim, int n_hidden, int width) {
+  const int RB = width / 16, F1 = RB * kin_of(in_dim), FH = RB * RB * 4;
+  return (int64_t)(F1 + 2 * (n_hidden - 1) * FH) * 64;
+}
+
+int f32_max_workgroups() { return kMaxWG; }
+
+nb_status f32_pack(const nb_bound* b, hipStream_t s) {
+  const int64_t total = b->pack_floats;
+  k_pack<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(b->theta, b->in_dim, b->width, b->n_hidden, b->pack, total);
+  NB_LAUNCHED();
+  return NB_OK;
+}
+
+nb_status f32_forward(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
+                      const uint8_t* g, unsigned long long* counts, hipStream_t s) {
+  const int kin = kin_of(b->in_dim);
+#define X(K, WW, H) \
+  if (kin == K && b->width == WW && b->n_hidden == H) return fwd_launch<K, WW, H>(b, q, n, tau, logits, h, g, counts, s);
+  NB_F32_CASES(X)
+#undef X
+  nb_set_error("float32 bound %d x %d^%d has no kernel", b->in_dim, b->width, b->n_hidden);
+  return NB_ERR_UNSUPPORTED;
+}
+
+nb_status f32_train_partials(const nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha,
+                             float beta, float tau, int* n_wg, hipStream_t s) {
+  const int kin = kin_of(b->in_dim);
+#define X(K, WW, H)                                                  \
+  if (kin == K && b->width == WW && b->n_hidden == H)                \
+    return train_launch<K, WW, H>(b, q, y, n, alpha, beta, tau, n_wg, s);
+  NB_F32_CASES(X)
+#undef X
+  nb_set_error("float32 bound %d x %d^%d has no kernel", b->in_dim, b->width, b->n_hidden);
+  return NB_ERR_UNSUPPORTED;
+}

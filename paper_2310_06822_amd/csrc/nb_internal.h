@@ -1,0 +1,123 @@
+// Internal declarations shared by the libnbound translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+
+#include "nbound.h"
+
+// ----------------------------------------------------------------- errors
+
+void nb_set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+
+#define NB_REQUIRE(cond, ...)              \
+  do {                                     \
+    if (!(cond)) {                         \
+      nb_set_error(__VA_ARGS__);           \
+      return NB_ERR_INVALID_ARG;           \
+    }                                      \
+  } while (0)
+
+#define NB_HIP(call)                                                                     \
+  do {                                                                                   \
+    hipError_t nb_e_ = (call);                                                           \
+    if (nb_e_ != hipSuccess) {                                                           \
+      nb_set_error("%s failed: %s (%d)", #call, hipGetErrorString(nb_e_), (int)nb_e_);   \
+      return nb_e_ == hipErrorOutOfMemory ? NB_ERR_OOM : NB_ERR_HIP;                      \
+    }                                                                                    \
+  } while (0)
+
+// Launch check: hipGetLastError after an async launch.
+#define NB_LAUNCHED() NB_HIP(hipGetLastError())
+
+// ------------------------------------------------------------- the handles
+
+enum IndicatorType { IND_DISCS2D = 0, IND_VOXELS = 1, IND_METABALLS4D = 2 };
+
+struct nb_indicator {
+  int type = 0;
+  int dim = 0;
+  int device = 0;
+  // discs: k rows (cx, cy, r); metaballs4d: a[k][3], d[k][3] = b - a, r2[k]
+  int k = 0;
+  float iso = 1.0f;
+  float* params = nullptr;
+  // voxels
+  int n = 0;
+  uint8_t* grid = nullptr;
+  float* ray_t = nullptr;        // 256 sample parameters of the ray query
+  int32_t* occupied = nullptr;        // linear indices of occupied cells (plane query)
+  int64_t* occupied_count = nullptr;  // device int64: number of entries in `occupied`
+};
+
+struct nb_bound {
+  int in_dim = 0, n_hidden = 0, width = 0, precision = 0;
+  int device = 0;
+  int64_t n_params = 0;
+  float* theta = nullptr;    // float32 master parameters
+  float* m = nullptr;        // Adam first moment
+  float* v = nullptr;        // Adam second moment
+  float* pack = nullptr;     // weights in MFMA fragment order
+  int64_t pack_floats = 0;
+  int64_t adam_t = 0;        // Adam steps taken
+  // work space
+  float* partial = nullptr;  // [max_wg][n_params] per-workgroup gradient partials
+  float* aux = nullptr;      // [max_wg][8] per-workgroup loss / counts
+  float* grad = nullptr;     // [n_params] reduced gradient
+  float* batch_q = nullptr;  // training batch
+  uint8_t* batch_y = nullptr;
+  int64_t batch_cap = 0;
+  int batch_cap_dim = 0;
+};
+
+// ------------------------------------------------------- kernel launchers
+
+// sampler.hip
+nb_status launch_sample(int kind, int dim, uint64_t seed, uint64_t step, int64_t n, float* q,
+                        hipStream_t s);
+
+// indicators.hip
+nb_status launch_query_exact(const nb_indicator* ind, int kind, const float* q, int64_t n, uint8_t* g,
+                             hipStream_t s);
+nb_status launch_voxelize(const float* params_dev, int k, float iso, int n, uint8_t* grid, hipStream_t s);
+nb_status launch_collect_occupied(const uint8_t* grid, int64_t cells, int32_t* out, int64_t* count_dev,
+                                  hipStream_t s);
+
+// mlp_f32.hip
+bool f32_supported(int in_dim, int n_hidden, int width);
+int64_t f32_pack_floats(int in_dim, int n_hidden, int width);
+nb_status f32_pack(const nb_bound* b, hipStream_t s);
+nb_status f32_forward(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
+                      const uint8_t* g, unsigned long long* counts, hipStream_t s);
+// Per-workgroup partial gradients into b->partial / b->aux; returns the
+// number of workgroups used through n_wg.
+nb_status f32_train_partials(const nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha,
+                             float beta, float tau, int* n_wg, hipStream_t s);
+int f32_max_workgroups();
+
+// optim.hip
+// Reduce partials over n_wg workgroups: writes grad (if non-null), loss and
+// counts (if non-null); with adam != 0 also applies one Adam step to theta.
+struct AdamArgs {
+  int enabled;
+  float lr, b1, b2, eps, bc1, bc2, lam1, lam2;
+};
+nb_status launch_reduce(const nb_bound* b, int n_wg, float* grad, float* loss, float loss_scale,
+                        unsigned long long* counts, const AdamArgs& adam, hipStream_t s);
+nb_status launch_adam(const nb_bound* b, const float* grad, const AdamArgs& adam, hipStream_t s);
+nb_status launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+// 1 for entries of theta that belong to a weight matrix (regularised), 0 for biases.
+__host__ __device__ inline int nb_is_weight(int64_t p, int in_dim, int width, int n_hidden) {
+  int64_t off = 0;
+  for (int l = 0; l <= n_hidden; ++l) {
+    const int64_t fin = l == 0 ? in_dim : width;
+    const int64_t fout = l == n_hidden ? 1 : width;
+    if (p < off + fin * fout) return 1;
+    off += fin * fout;
+    if (p < off + fout) return 0;
+    off += fout;
+  }
+  return 0;
+}

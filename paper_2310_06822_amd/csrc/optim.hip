@@ -1,0 +1,111 @@
+// Gradient reduction and Adam (Sec. 3.4, "Training": Adam at learning rate
+// 1e-3; Kingma & Ba 2014, Algorithm 1, with beta1 0.9, beta2 0.999,
+// epsilon 1e-8 unless the caller says otherwise).
+//
+// The training kernel leaves one partial gradient per workgroup.  The sum
+// over workgroups is taken here in a fixed order (8 interleaved strided
+// partial sums per parameter, then added 0..7), so a given batch size always
+// gives bit-identical gradients.  Optional L1 + L2 regularisation of the
+// weight matrices (supplemental "Regularization") adds
+// lam1 sign(W) + 2 lam2 W to their gradient.
+#include "nb_internal.h"
+
+namespace {
+
+constexpr int kParamsPerBlock = 32;
+constexpr int kParts = 8;
+
+__device__ __forceinline__ void adam_update(int64_t p, float g, float* __restrict__ theta, float* __restrict__ m,
+                                            float* __restrict__ v, const AdamArgs& a, int in_dim, int width,
+                                            int n_hidden) {
+  float th = theta[p];
+  if ((a.lam1 != 0.0f || a.lam2 != 0.0f) && nb_is_weight(p, in_dim, width, n_hidden)) {
+    const float sg = th > 0.0f ? 1.0f : (th < 0.0f ? -1.0f : 0.0f);
+    g = g + (a.lam1 * sg + 2.0f * a.lam2 * th);
+  }
+  const float mm = a.b1 * m[p] + (1.0f - a.b1) * g;
+  const float vv = a.b2 * v[p] + (1.0f - a.b2) * (g * g);
+  m[p] = mm;
+  v[p] = vv;
+  const float mhat = mm / a.bc1;
+  const float vhat = vv / a.bc2;
+  theta[p] = th - a.lr * mhat / (sqrtf(vhat) + a.eps);
+}
+
+__global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partial, const float* __restrict__ aux,
+                                                int n_wg, int64_t P, float* __restrict__ grad,
+                                                float* __restrict__ theta, float* __restrict__ m,
+                                                float* __restrict__ v, AdamArgs adam, int in_dim, int width,
+                                                int n_hidden, float* __restrict__ loss, float loss_scale,
+                                                unsigned long long* __restrict__ counts) {
+  __shared__ float part[kParts][kParamsPerBlock];
+  const int t = threadIdx.x, j = t % kParamsPerBlock, k = t / kParamsPerBlock;
+  const int64_t p = (int64_t)blockIdx.x * kParamsPerBlock + j;
+  float s = 0.0f;
+  if (p < P)
+    for (int w = k; w < n_wg; w += kParts) s += partial[(int64_t)w * P + p];
+  part[k][j] = s;
+  __syncthreads();
+  if (t < kParamsPerBlock && p < P) {
+    float tot = part[0][t];
+#pragma unroll
+    for (int i = 1; i < kParts; ++i) tot += part[i][t];
+    if (grad) grad[p] = tot;
+    if (adam.enabled) adam_update(p, tot, theta, m, v, adam, in_dim, width, n_hidden);
+  }
+  // loss and counts: the last block's first wave, lanes strided over workgroups
+  if (blockIdx.x == gridDim.x - 1 && t < 64 && (loss || counts)) {
+    float ls = 0.0f;
+    unsigned long long cs[4] = {0, 0, 0, 0};
+    for (int w = t; w < n_wg; w += 64) {
+      ls += aux[w * 8];
+      for (int i = 0; i < 4; ++i) cs[i] += __float_as_uint(aux[w * 8 + 1 + i]);
+    }
+    for (int msk = 1; msk < 64; msk <<= 1) {
+      ls += __shfl_xor(ls, msk);
+      for (int i = 0; i < 4; ++i) cs[i] += __shfl_xor(cs[i], msk);
+    }
+    if (t == 0) {
+      if (loss) *loss = ls * loss_scale;
+      if (counts)
+        for (int i = 0; i < 4; ++i) counts[i] = cs[i];
+    }
+  }
+}
+
+__global__ void k_adam(const float* __restrict__ grad, int64_t P, float* __restrict__ theta, float* __restrict__ m,
+                       float* __restrict__ v, AdamArgs adam, int in_dim, int width, int n_hidden) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < P) adam_update(p, grad[p], theta, m, v, adam, in_dim, width, n_hidden);
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+}  // namespace
+
+nb_status launch_reduce(const nb_bound* b, int n_wg, float* grad, float* loss, float loss_scale,
+                        unsigned long long* counts, const AdamArgs& adam, hipStream_t s) {
+  const int64_t P = b->n_params;
+  const unsigned grid = (unsigned)((P + kParamsPerBlock - 1) / kParamsPerBlock);
+  k_reduce<<<grid, 256, 0, s>>>(b->partial, b->aux, n_wg, P, grad, b->theta, b->m, b->v, adam, b->in_dim,
+                                b->width, b->n_hidden, loss, loss_scale, counts);
+  NB_LAUNCHED();
+  return NB_OK;
+}
+
+nb_status launch_adam(const nb_bound* b, const float* grad, const AdamArgs& adam, hipStream_t s) {
+  const int64_t P = b->n_params;
+  k_adam<<<(unsigned)((P + 255) / 256), 256, 0, s>>>(grad, P, b->theta, b->m, b->v, adam, b->in_dim, b->width,
+                                                     b->n_hidden);
+  NB_LAUNCHED();
+  return NB_OK;
+}
+
+nb_status launch_zero_u64(unsigned long long* p, int n, hipStream_t s) {
+  k_zero_u64<<<1, 64, 0, s>>>(p, n);
+  NB_LAUNCHED();
+  return NB_OK;
+}

@@ -1,0 +1,270 @@
+"""GPU parity: every kernel of the hot path against the CPU oracle on the
+same seeded inputs, called through the C ABI.
+
+Bars: integer results (samples' bits, indicator answers, counts) are
+bit-exact; float32 logits satisfy |dz| <= 1e-5 * max(|z|, s) with
+s = |W_L| |a_{L-1}| + |b_L| (the magnitude sum of the last layer's terms);
+decisions may differ only where |z| < 1e-4; gradients match per tensor to
+1e-5 in relative Frobenius norm.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import indicators as I, loss as L, mlp, sampling
+from oracle.adam import Adam
+
+pytestmark = pytest.mark.gpu
+
+nb = pytest.importorskip("paper_2310_06822_amd")
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def bits(a):
+    return np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
+
+
+@pytest.fixture(scope="module")
+def c2_grid():
+    c, r = synth.metaballs3d(1001, k=16)
+    return c, r, I.voxelize_metaballs(c, r, 128)
+
+
+# ---------------------------------------------------------------- sampling
+
+@pytest.mark.parametrize("kind,dim,n", [("point", 2, 4099), ("point", 3, 65536 + 17), ("point", 4, 1000),
+                                        ("ray", 3, 5003), ("box", 3, 4097), ("plane", 3, 3001)])
+def test_sampler_bit_exact(kind, dim, n):
+    d = dim if kind == "point" else 6
+    for seed, step in [(2001, 0), (2001, 7), (0xDEADBEEF12345, 123456)]:
+        q = torch.empty((n, d), dtype=torch.float32, device="cuda")
+        nb.nb_sample_queries(nb.KINDS[kind], dim, seed, step, q)
+        ref = sampling.sample(kind, seed, step, n, dim)
+        assert np.array_equal(bits(host(q)), bits(ref)), (kind, seed, step)
+
+
+# --------------------------------------------------------------- indicators
+
+@pytest.mark.parametrize("n,k", [(8, 3), (32, 16), (33, 5), (128, 16)])
+def test_voxelize_bit_exact(n, k):
+    c, r = synth.metaballs3d(1001 + n, k=k)
+    grid = torch.empty(n ** 3, dtype=torch.uint8, device="cuda")
+    nb.nb_voxelize_metaballs(c, r, 1.0, n, grid)
+    ref = I.voxelize_metaballs(c, r, n)
+    assert np.array_equal(host(grid), ref)
+    assert 0 < ref.sum() < ref.size
+
+
+def test_exact_discs():
+    discs = synth.discs2d(1000)
+    ind = nb.Indicator.discs2d(discs)
+    q = synth.points(5, 70001, 2) * np.float32(1.2)
+    g = ind.query("point", cuda(q))
+    assert np.array_equal(host(g), I.discs2d(q, discs))
+
+
+def test_exact_voxel_points(c2_grid):
+    _, _, grid = c2_grid
+    ind = nb.Indicator.voxels(cuda(grid), 128)
+    q = synth.points(6, 100003, 3) * np.float32(1.1)
+    q[:5] = [[1, 1, 1], [-1, -1, -1], [1.0000001, 0, 0], [np.nan, 0, 0], [0, 0, 0]]
+    g = ind.query("point", cuda(q))
+    assert np.array_equal(host(g), I.voxel_points(q, grid, 128))
+
+
+def test_exact_rays(c2_grid):
+    _, _, grid = c2_grid
+    ind = nb.Indicator.voxels(cuda(grid), 128)
+    q = synth.rays(7, 8195)
+    g = ind.query("ray", cuda(q))
+    ref = I.voxel_rays(q, grid, 128)
+    assert np.array_equal(host(g), ref)
+    assert 0.05 < ref.mean() < 0.95
+
+
+@pytest.mark.parametrize("n", [32, 128])
+def test_exact_boxes(n):
+    c, r = synth.metaballs3d(77, k=12)
+    grid = I.voxelize_metaballs(c, r, n)
+    ind = nb.Indicator.voxels(cuda(grid), n)
+    q = synth.boxes(8, 3001)
+    q[0] = [-2, -2, -2, 2, 2, 2]
+    q[1] = [1.5, 0, 0, 2, 1, 1]
+    q[2] = [0.1, 0.1, 0.1, 0.1, 0.1, 0.1]
+    g = ind.query("box", cuda(q))
+    assert np.array_equal(host(g), I.voxel_boxes(q, grid, n))
+
+
+def test_exact_planes():
+    n = 16
+    c, r = synth.metaballs3d(78, k=6)
+    grid = I.voxelize_metaballs(c, r, n)
+    ind = nb.Indicator.voxels(cuda(grid), n)
+    q = synth.planes(9, 1501)
+    g = ind.query("plane", cuda(q))
+    ref = I.voxel_planes(q, grid, n)
+    assert np.array_equal(host(g), ref)
+    assert 0.05 < ref.mean() < 0.95
+
+
+def test_exact_metaballs4d():
+    a, b, r = synth.metaballs4d(1004)
+    ind = nb.Indicator.metaballs4d(a, b, r)
+    q = synth.points4d(10, 65537)
+    g = ind.query("point", cuda(q))
+    assert np.array_equal(host(g), I.metaballs4d(q, a, b, r))
+
+
+# ------------------------------------------------------------ MLP forward
+
+SHAPES = [(2, 32, 3), (3, 64, 3), (6, 16, 2), (4, 32, 4), (3, 16, 1), (6, 64, 4), (8, 64, 2)]
+
+
+def _check_logits(z, theta, in_dim, widths, q, rtol=1e-5):
+    ref = mlp.forward(theta, in_dim, widths, q)
+    s = mlp.abs_forward(theta, in_dim, widths, q)
+    err = np.abs(z.astype(np.float64) - ref)
+    bound = rtol * np.maximum(np.abs(ref), s)
+    assert np.all(err <= bound), f"max err/bound {np.max(err / bound):.3g}"
+    return ref
+
+
+@pytest.mark.parametrize("in_dim,width,nh", SHAPES)
+@pytest.mark.parametrize("n", [1, 16, 17, 3005])
+def test_forward_parity(in_dim, width, nh, n):
+    widths = [width] * nh
+    theta = synth.init_params(40 + in_dim + width + nh, in_dim, widths)
+    q = synth.points(41, n, in_dim)
+    b = nb.Bound(in_dim, nh, width)
+    b.set_params(theta)
+    z, h = b.forward(cuda(q))
+    z, h = host(z), host(h)
+    ref = _check_logits(z, theta, in_dim, widths, q)
+    band = np.abs(ref) < 1e-4
+    assert np.array_equal(h[~band], L.decide(ref)[~band])
+    assert np.array_equal(h, L.decide(z))
+
+
+def test_forward_counts_and_edge_logits(c2_grid):
+    _, _, grid = c2_grid
+    in_dim, widths = 3, [64] * 3
+    theta = synth.init_params(4001, in_dim, widths)
+    b = nb.Bound(in_dim, 3, 64)
+    b.set_params(theta)
+    q = synth.points(3001, 50001, 3)
+    g = I.voxel_points(q, grid, 128)
+    cnt = b.counts(cuda(q), cuda(g))
+    z, _ = b.forward(cuda(q))
+    ref = mlp.forward(theta, in_dim, widths, q)
+    band = np.abs(ref) < 1e-4
+    want = L.counts(L.decide(host(z)), g)
+    assert host(cnt).tolist() == want.tolist()
+    assert np.array_equal(L.decide(host(z))[~band], L.decide(ref)[~band])
+
+
+# ---------------------------------------------------------- loss / gradient
+
+def _rel_frob(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+@pytest.mark.parametrize("in_dim,width,nh", SHAPES)
+@pytest.mark.parametrize("n", [5, 4099])
+def test_loss_grad_parity(in_dim, width, nh, n):
+    widths = [width] * nh
+    theta = synth.init_params(50 + width, in_dim, widths)
+    q = synth.points(51, n, in_dim)
+    y = (synth.points(52, n, 1)[:, 0] > 0.3).astype(np.uint8)
+    alpha, beta = 7.5, 1.25
+    b = nb.Bound(in_dim, nh, width)
+    b.set_params(theta)
+    grad = torch.empty(b.n_params, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    cnt = torch.empty(4, dtype=torch.int64, device="cuda")
+    nb.nb_bound_loss_grad(b.handle, cuda(q), cuda(y), alpha, beta, grad, loss, cnt)
+    z = mlp.forward(theta, in_dim, widths, q)
+    gref = mlp.backward(theta, in_dim, widths, q, L.dloss_dz(z, y, alpha, beta))
+    g = host(grad).astype(np.float64)
+    assert abs(host(loss)[0] - L.loss(z, y, alpha, beta)) <= 1e-5 * L.loss(z, y, alpha, beta)
+    for (Wg, bg), (Wr, br) in zip(mlp.unpack(g, in_dim, widths), mlp.unpack(gref, in_dim, widths)):
+        assert _rel_frob(Wg, Wr) <= 1e-5
+        assert _rel_frob(bg, br) <= 1e-5
+    band = np.abs(z) < 1e-4
+    if not band.any():
+        assert host(cnt).tolist() == L.counts(L.decide(z), y).tolist()
+
+
+def test_loss_grad_deterministic():
+    in_dim, widths = 3, [64] * 3
+    theta = synth.init_params(60, in_dim, widths)
+    q = cuda(synth.points(61, 65536, 3))
+    y = cuda((synth.points(62, 65536, 1)[:, 0] > 0).astype(np.uint8))
+    b = nb.Bound(3, 3, 64)
+    b.set_params(theta)
+    outs = []
+    for _ in range(2):
+        grad = torch.empty(b.n_params, dtype=torch.float32, device="cuda")
+        nb.nb_bound_loss_grad(b.handle, q, y, 3.0, 1.0, grad)
+        outs.append(host(grad))
+    assert np.array_equal(bits(outs[0]), bits(outs[1]))
+
+
+# ----------------------------------------------------------------- Adam
+
+def test_adam_step_parity():
+    in_dim, widths = 3, [64] * 3
+    theta = synth.init_params(70, in_dim, widths)
+    b = nb.Bound(3, 3, 64)
+    b.set_params(theta)
+    opt = Adam(theta.size)
+    th = theta.astype(np.float64)
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        g = (rng.normal(size=theta.size) * 1e-2).astype(np.float32)
+        nb.nb_bound_adam_step(b.handle, cuda(g))
+        th = opt.step(th, g)
+    got = host(b.params()).astype(np.float64)
+    assert np.max(np.abs(got - th)) <= 1e-6
+
+
+# ---------------------------------------------------------- training steps
+
+@pytest.mark.parametrize("cfg", ["disc", "voxel"])
+def test_train_steps_parity(cfg, c2_grid):
+    if cfg == "disc":
+        discs = synth.discs2d(1000)
+        ind = nb.Indicator.discs2d(discs)
+        label = lambda q: I.discs2d(q, discs)
+        in_dim, width, dim = 2, 32, 2
+    else:
+        _, _, grid = c2_grid
+        ind = nb.Indicator.voxels(cuda(grid), 128)
+        label = lambda q: I.voxel_points(q, grid, 128)
+        in_dim, width, dim = 3, 64, 3
+    widths = [width] * 3
+    theta0 = synth.init_params(4000, in_dim, widths)
+    steps, batch, seed = 10, 2048, 2000
+    b = nb.Bound(in_dim, 3, width)
+    b.set_params(theta0)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    cnt = torch.empty(4, dtype=torch.int64, device="cuda")
+    from oracle import train as T
+    th, hist = T.train(label, "point", dim, in_dim, widths, theta0, seed, steps, batch)
+    for t in range(steps):
+        a = T.alpha_ramp(t, steps)
+        nb.nb_bound_train_step(b.handle, ind.handle, nb.POINT, seed, t, batch, a, 1.0, 1e-3, loss=loss, counts=cnt)
+        lv = host(loss)[0]
+        assert abs(lv - hist[t][0]) <= 1e-4 * abs(hist[t][0]), (t, lv, hist[t][0])
+    got = host(b.params()).astype(np.float64)
+    d_gpu, d_ref = got - theta0, th - theta0
+    assert _rel_frob(d_gpu, d_ref) <= 1e-2
