@@ -36,6 +36,27 @@ def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
+def committed_traffic(name: str, source: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or None
+    if the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(os.path.join(ROOT, source), "rb").read()).hexdigest()
+    if kv.get("source_sha256") != sha:
+        return None
+    try:
+        return int(float(kv["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(theta, in_dim, widths, target_s: float = 10.0):
     """Oracle forward + decision on a bounded sample of held-out queries."""
     import synth
@@ -67,7 +88,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--train-steps", type=int, default=None)
     ap.add_argument("--eval-n", type=int, default=None)
+    ap.add_argument("--no-adapt", action="store_true", help="ramp phase only (no step-wise continuation)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (scales HBM byte counters in profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the bound's queries are "
@@ -82,7 +106,6 @@ def main():
 
     torch.cuda.set_device(0)
     dev = "cuda"
-    T = args.train_steps if args.train_steps is not None else W.train_steps
     n_eval = args.eval_n if args.eval_n is not None else W.eval_n
     seeds = W.seeds
     widths = [W.width] * W.n_hidden
@@ -99,24 +122,17 @@ def main():
     theta0 = synth.init_params(seeds["init"], W.in_dim, widths)
     bound.set_params(theta0)
 
-    # ---- training (Alg. 1 on the device), FN weight ramped 1 -> alpha_max
-    loss = torch.empty(1, dtype=torch.float32, device=dev)
-    cnt = torch.zeros(4, dtype=torch.int64, device=dev)
+    # ---- training (Alg. 1 on the device): ramp, then the step-wise schedule
+    from paper_2310_06822_amd import trainer
+    sched = W.schedule(**({"steps": args.train_steps} if args.train_steps is not None else {}))
+    if args.no_adapt:
+        sched.max_iters = 0
     nb.nb_bound_train_step(bound.handle, ind.handle, nb.POINT, seeds["train"], 0, W.batch, 1.0)   # work space
     bound.set_params(theta0)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for t in range(T):
-        a = 1.0 + (W.alpha_max - 1.0) * (t / (T - 1) if T > 1 else 1.0)
-        nb.nb_bound_train_step(bound.handle, ind.handle, nb.POINT, seeds["train"], t, W.batch, a, 1.0, 1e-3,
-                               loss=loss if t == T - 1 else None, counts=cnt if t == T - 1 else None)
-    e1.record()
-    torch.cuda.synchronize()
-    train_ms = e0.elapsed_time(e1)
-    train_sps = T * W.batch / (train_ms / 1e3)
-    log(f"train: {T} steps x {W.batch} in {train_ms:.1f} ms -> {train_sps:.3e} samples/s; "
-        f"last loss {loss.item():.5f} counts {cnt.tolist()}")
+    res = trainer.train(bound, ind, W.kind, seeds["train"], sched, val_seed=seeds["val"], log=None)
+    train_sps = res.samples_per_s
+    log(f"train: {res.steps} steps x {W.batch} in {res.seconds:.2f} s -> {train_sps:.3e} samples/s; "
+        f"alpha final {res.alpha_final:g}, schedule iterations {res.iters}, converged {res.converged}")
 
     # ---- held-out queries and exact answers
     q = torch.empty((n_eval, W.in_dim), dtype=torch.float32, device=dev)
@@ -167,7 +183,9 @@ def main():
     flop_per_q = 2 * macs
     achieved = flop_per_q * n_eval / (avg_kern / 1e3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
+                "traffic": committed_traffic("k_fwd_f32_voxel3d_point_traffic.txt",
+                                             "paper_2310_06822_amd/csrc/mlp_f32.hip"),
                 "kernel": "k_fwd<1,64,3> (float32 MLP forward + decision)",
                 "flop_per_query": flop_per_q, "avg_launch_ms": round(avg_kern, 4)}
 
@@ -177,14 +195,24 @@ def main():
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": W.name, "queries_per_step": n_eval, "grid": gn, "metaballs": W.scene["k"],
-                   "net": f"{W.in_dim}x{W.width}^{W.n_hidden}x1 relu", "train_steps": T, "train_batch": W.batch},
+                   "net": f"{W.in_dim}x{W.width}^{W.n_hidden}x1 relu", "train_steps": res.steps, "train_batch": W.batch},
         "train_samples_per_s": train_sps,
+        "train": {"steps": res.steps, "batch": W.batch, "seconds": res.seconds, "alpha_final": res.alpha_final,
+                  "schedule_iterations": res.iters, "validation_fn_zero": res.converged,
+                  "validation_n": sched.val_n if sched.max_iters else 0},
         "exact_queries_per_s": exact_qps,
         "bound_vs_exact": value / exact_qps,
         "heldout": {"n": n_eval, "tp": tp, "fp": fp, "tn": tn, "fn": fn, "fp_rate": fp / n_eval},
         "fn_zero": fn == 0,
         "roofline": roofline,
     }
+    if args.copy_calibration:
+        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 2 x 256 MiB device-to-device copies")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(bound.params().cpu().numpy(), W.in_dim, widths)
     print(json.dumps(out), flush=True)

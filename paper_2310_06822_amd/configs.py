@@ -4,6 +4,12 @@ The paper's images, voxelised meshes and animations (Sec. 4.2 "Indicators")
 are replaced by seeded synthetic scenes of the same kind; network shapes are
 "in_dim -> width^n_hidden -> 1".  Seeds: scene 1000+i, training stream
 2000+i, held-out evaluation 3000+i, initial weights 4000+i for workload i.
+
+Training follows Alg. 1 with the FN weight ramped linearly 1 -> alpha_max
+over `train_steps`, then (if `adapt_iters` > 0) the paper's step-wise
+schedule: every `adapt_k` steps alpha grows by `adapt_inc` while a
+validation set (seed 5000+i) still has false negatives; stop after six
+FN-free iterations.
 """
 
 from __future__ import annotations
@@ -26,11 +32,21 @@ class Workload:
     batch: int = 0
     eval_n: int = 0
     alpha_max: float = 100.0
+    adapt_k: int = 250
+    adapt_inc: float = 50.0
+    adapt_iters: int = 400
 
     @property
     def seeds(self):
         return {"scene": 1000 + self.index, "train": 2000 + self.index, "eval": 3000 + self.index,
-                "init": 4000 + self.index}
+                "init": 4000 + self.index, "val": 5000 + self.index}
+
+    def schedule(self, **kw):
+        from .trainer import Schedule
+        args = dict(steps=self.train_steps, batch=self.batch, alpha_max=self.alpha_max, k=self.adapt_k,
+                    inc=self.adapt_inc, max_iters=self.adapt_iters, val_n=min(self.eval_n, 1 << 24))
+        args.update(kw)
+        return Schedule(**args)
 
 
 DISC2D_POINT = Workload("disc2d_point", 0, "point", 2, 2, 32, 3, "f32",
