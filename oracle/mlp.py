@@ -10,10 +10,15 @@ layers here use ReLU.
 Parameters are one flat vector, layer by layer: W_l[out, in] row-major, then
 b_l[out].  Forward and backward run in float64 on float32 inputs.
 
-bfloat16 mode models where a bfloat16 kernel rounds: the first layer stays
-float32-exact; every later layer sees its weights rounded to bfloat16 and its
-input activations rounded first to float32 and then to bfloat16 (round to
-nearest, ties to even).  Products and sums stay in float64.
+bfloat16 mode models where a bfloat16 matrix-core kernel rounds (the paper
+states no precision; this is the reading used for the bfloat16 workloads):
+  * first layer, "bf16x3": with v_hi = bf16(v) and v_lo = bf16(v - v_hi) for
+    the float32 weights and inputs, W x is replaced by
+    W_hi x_hi + W_hi x_lo + W_lo x_hi (about 16 significant bits);
+  * hidden -> hidden layers: weights rounded to bfloat16, input activations
+    rounded first to float32 and then to bfloat16;
+  * output layer: float32 weights on float32 activations.
+Rounding is to nearest, ties to even.  Products and sums stay in float64.
 """
 
 from __future__ import annotations
@@ -58,6 +63,19 @@ def bf16_round(x) -> np.ndarray:
     return u.astype(np.uint32).view(np.float32)
 
 
+def bf16_split(v):
+    """(hi, lo) with hi = bf16(v), lo = bf16(v - hi), both as float64; v is
+    rounded to float32 first.  v - hi is exact in float32."""
+    v32 = np.asarray(v, dtype=np.float32)
+    hi = bf16_round(v32)
+    lo = bf16_round((v32 - hi).astype(np.float32))
+    return hi.astype(np.float64), lo.astype(np.float64)
+
+
+def _hidden_bf16(l: int, n_layers: int) -> bool:
+    return 0 < l < n_layers - 1
+
+
 def forward(theta, in_dim: int, widths, x, bf16: bool = False, keep: bool = False):
     """Logits z [n] (float64).  With keep=True also returns the per-layer
     inputs a_{l-1} and pre-activations z_l used by the backward pass."""
@@ -65,11 +83,16 @@ def forward(theta, in_dim: int, widths, x, bf16: bool = False, keep: bool = Fals
     a = np.asarray(x, dtype=np.float32).astype(np.float64)
     inputs, pre = [], []
     for l, (W, b) in enumerate(layers):
-        if bf16 and l > 0:
+        if bf16 and _hidden_bf16(l, len(layers)):
             W = bf16_round(W.astype(np.float32)).astype(np.float64)
             a = bf16_round(a.astype(np.float32)).astype(np.float64)
         inputs.append(a)
-        z = a @ W.T + b
+        if bf16 and l == 0:
+            Wh, Wl = bf16_split(W)
+            xh, xl = bf16_split(a)
+            z = xh @ Wh.T + xl @ Wh.T + xh @ Wl.T + b
+        else:
+            z = a @ W.T + b
         pre.append(z)
         a = np.maximum(z, 0.0) if l + 1 < len(layers) else z
     z = a[:, 0]
@@ -84,8 +107,6 @@ def abs_forward(theta, in_dim: int, widths, x, bf16: bool = False) -> np.ndarray
     layers = unpack(theta, in_dim, widths)
     _, inputs, _ = forward(theta, in_dim, widths, x, bf16=bf16, keep=True)
     W, b = layers[-1]
-    if bf16:
-        W = bf16_round(W.astype(np.float32)).astype(np.float64)
     return (np.abs(inputs[-1]) @ np.abs(W).T)[:, 0] + abs(b[0])
 
 
@@ -94,15 +115,16 @@ def backward(theta, in_dim: int, widths, x, dz, bf16: bool = False) -> np.ndarra
     delta_L = dz; delta_{l-1} = (W_l^T delta_l) * 1[z_{l-1} > 0];
     dW_l = sum_i delta_l a_{l-1}^T, db_l = sum_i delta_l.
     In bfloat16 mode the weights and layer inputs are the rounded ones the
-    forward pass used; the gradient is taken with respect to the float32
-    master weights (straight through the rounding)."""
+    forward pass used (the first layer's input is the float32 query); the
+    gradient is taken with respect to the float32 master weights (straight
+    through the rounding)."""
     layers = unpack(theta, in_dim, widths)
     _, inputs, pre = forward(theta, in_dim, widths, x, bf16=bf16, keep=True)
     delta = np.asarray(dz, dtype=np.float64)[:, None]
     grads = [None] * len(layers)
     for l in range(len(layers) - 1, -1, -1):
         W, _ = layers[l]
-        if bf16 and l > 0:
+        if bf16 and _hidden_bf16(l, len(layers)):
             W = bf16_round(W.astype(np.float32)).astype(np.float64)
         grads[l] = (delta.T @ inputs[l], delta.sum(axis=0))
         if l:

@@ -108,23 +108,79 @@ def test_bf16_round_matches_torch():
     assert mlp.bf16_round(np.float32(1 + 3 * 2 ** -8)) == np.float32(1 + 2 ** -6)
 
 
+def test_bf16_split_bounds():
+    rng = np.random.default_rng(9)
+    v = rng.normal(size=10000).astype(np.float32)
+    hi, lo = mlp.bf16_split(v)
+    # hi + lo carries about 16 significant bits: |v - hi - lo| <= 2^-16 |v|
+    assert np.all(np.abs(v - hi - lo) <= 2.0 ** -16 * np.abs(v.astype(np.float64)))
+    assert np.array_equal(hi, mlp.bf16_round(v))
+
+
 def test_bf16_forward_quantisation_points():
-    in_dim, widths = 6, [32, 32]
+    """Independent route: torch float64 with explicit bfloat16 casts."""
+    in_dim, widths = 6, [32, 32, 32]
     theta = synth.init_params(3, in_dim, widths)
     x = synth.points(4, 100, in_dim)
     layers = mlp.unpack(theta, in_dim, widths)
     a = torch.from_numpy(x.astype(np.float64))
     for l, (W, b) in enumerate(layers):
         Wt = torch.from_numpy(W)
-        if l > 0:
-            Wt = Wt.float().to(torch.bfloat16).double()
-            a = a.float().to(torch.bfloat16).double()
-        a = a @ Wt.T + torch.from_numpy(b)
+        if l == 0:
+            Wf, af = Wt.float(), a.float()
+            Wh = Wf.to(torch.bfloat16).double()
+            Wl = (Wf - Wh.float()).to(torch.bfloat16).double()
+            ah = af.to(torch.bfloat16).double()
+            al = (af - ah.float()).to(torch.bfloat16).double()
+            a = ah @ Wh.T + al @ Wh.T + ah @ Wl.T + torch.from_numpy(b)
+        elif l < len(layers) - 1:
+            Wq = Wt.float().to(torch.bfloat16).double()
+            aq = a.float().to(torch.bfloat16).double()
+            a = aq @ Wq.T + torch.from_numpy(b)
+        else:
+            a = a @ Wt.T + torch.from_numpy(b)
         if l + 1 < len(layers):
             a = torch.relu(a)
     z = mlp.forward(theta, in_dim, widths, x, bf16=True)
     assert np.allclose(z, a[:, 0].numpy(), rtol=1e-12, atol=1e-13)
-    assert not np.allclose(z, mlp.forward(theta, in_dim, widths, x), rtol=1e-6)
+    z32 = mlp.forward(theta, in_dim, widths, x)
+    assert not np.allclose(z, z32, rtol=1e-6)
+    assert np.allclose(z, z32, rtol=0.05, atol=0.05)
+
+
+def test_bf16_backward_vs_torch():
+    """bfloat16-mode gradient = float64 autograd through the rounded forward
+    with straight-through rounding."""
+    in_dim, widths = 4, [16, 16, 16]
+    theta = synth.init_params(13, in_dim, widths)
+    x = synth.points(14, 50, in_dim)
+    y = (synth.points(15, 50, 1)[:, 0] > 0).astype(np.uint8)
+    z = mlp.forward(theta, in_dim, widths, x, bf16=True)
+    dz = L.dloss_dz(z, y, 5.0, 1.0)
+    g = mlp.backward(theta, in_dim, widths, x, dz, bf16=True)
+    layers = mlp.unpack(theta, in_dim, widths)
+    params = []
+    a = torch.from_numpy(x.astype(np.float64))
+    for l, (W, b) in enumerate(layers):
+        Wp = torch.from_numpy(W.copy()).requires_grad_(True)
+        bp = torch.from_numpy(b.copy()).requires_grad_(True)
+        params += [Wp, bp]
+        if l == 0:
+            Wh, Wl = [torch.from_numpy(v) for v in mlp.bf16_split(W)]
+            xh, xl = [torch.from_numpy(v) for v in mlp.bf16_split(x)]
+            eff = (xh @ Wh.T + xl @ Wh.T + xh @ Wl.T).detach()
+            a = eff + (a @ Wp.T - (a @ Wp.T).detach()) + bp       # value of the split, gradient of W x
+        elif l < len(layers) - 1:
+            Wq = torch.from_numpy(mlp.bf16_round(W.astype(np.float32)).astype(np.float64))
+            aq = torch.from_numpy(mlp.bf16_round(a.detach().numpy().astype(np.float32)).astype(np.float64))
+            a = aq @ (Wq + (Wp - Wp.detach())).T + (a - a.detach()) @ Wq.T + bp
+        else:
+            a = a @ Wp.T + bp
+        if l + 1 < len(layers):
+            a = torch.relu(a)
+    (a[:, 0] * torch.from_numpy(dz)).sum().backward()
+    ref = np.concatenate([p.grad.numpy().ravel() for p in params])
+    assert np.allclose(g, ref, rtol=1e-10, atol=1e-14)
 
 
 # ------------------------------------------------------------------- loss
