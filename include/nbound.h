@@ -145,7 +145,9 @@ nb_status nb_sample_queries(int kind, int dim, uint64_t seed, uint64_t step, int
 
 /* ------------------------------------------------------------------------
  * Bound h_theta (Sec. 3.4): in_dim -> width x n_hidden (ReLU) -> 1 logit.
- * Supported: NB_F32 with width 16, 32 or 64 and in_dim 1..7; n_hidden 1..8.
+ * Supported: in_dim 1..8;  NB_F32: width 16, 32 or 64 with n_hidden 1..4;
+ * NB_BF16 (forward only in this build): width 32 or 64 with n_hidden 1..4,
+ * width 128 with n_hidden 1..5.  Other shapes give NB_ERR_UNSUPPORTED.
  * The handle owns float32 master parameters, Adam moments and work space.
  * Parameters start at zero; set them with nb_bound_set_params.
  * ---------------------------------------------------------------------- */
@@ -191,7 +193,8 @@ nb_status nb_bound_loss_grad(nb_bound* b, const float* q, const uint8_t* y, int6
 nb_status nb_bound_adam_step(nb_bound* b, const float* grad, float lr, float beta1, float beta2, float adam_eps,
                              float lam1, float lam2, void* stream);
 
-/* One training step of Alg. 1 on the device: sample `batch` regions of
+/* (Training calls return NB_ERR_UNSUPPORTED for NB_BF16 bounds in this build.)
+ * One training step of Alg. 1 on the device: sample `batch` regions of
  * `kind` (nb_sample_queries with this seed and step), label them with the
  * exact query on `ind`, evaluate loss and gradient, and take one Adam step
  * (lr, beta1 0.9, beta2 0.999, eps 1e-8).  loss: float32[1] or NULL;

@@ -45,6 +45,19 @@ int64_t mlp_params(int in_dim, int n_hidden, int width) {
 
 int kind_dim(int kind, int point_dim) { return kind == NB_QUERY_POINT ? point_dim : 6; }
 
+// Rebuild the weight fragments the forward / training kernels read.
+nb_status repack(const nb_bound* b, hipStream_t s) {
+  return b->precision == NB_BF16 ? bf16_pack(b, s) : f32_pack(b, s);
+}
+
+nb_status require_f32_training(const nb_bound* b) {
+  if (b->precision != NB_F32) {
+    nb_set_error("training a bfloat16 bound has no kernel in this build");
+    return NB_ERR_UNSUPPORTED;
+  }
+  return NB_OK;
+}
+
 #define NB_TRY(expr)                 \
   do {                               \
     nb_status nb_s_ = (expr);        \
@@ -240,7 +253,8 @@ nb_status nb_bound_create(int in_dim, int n_hidden, int width, int precision, nb
   NB_REQUIRE(n_hidden >= 1 && n_hidden <= 8, "n_hidden must be in 1..8");
   NB_REQUIRE(width >= 16 && width <= 256 && width % 16 == 0, "width must be a multiple of 16 in 16..256");
   NB_REQUIRE(precision == NB_F32 || precision == NB_BF16, "unknown precision %d", precision);
-  if (precision != NB_F32 || !f32_supported(in_dim, n_hidden, width)) {
+  const bool ok = precision == NB_F32 ? f32_supported(in_dim, n_hidden, width) : bf16_supported(in_dim, n_hidden, width);
+  if (!ok) {
     nb_set_error("no kernel for a %s bound %d x %d^%d", precision == NB_F32 ? "float32" : "bfloat16", in_dim, width,
                  n_hidden);
     return NB_ERR_UNSUPPORTED;
@@ -253,18 +267,22 @@ nb_status nb_bound_create(int in_dim, int n_hidden, int width, int precision, nb
   b->precision = precision;
   hipGetDevice(&b->device);
   b->n_params = mlp_params(in_dim, n_hidden, width);
-  b->pack_floats = f32_pack_floats(in_dim, n_hidden, width);
+  b->pack_floats = precision == NB_F32 ? f32_pack_floats(in_dim, n_hidden, width) : 0;
+  b->pack16_elems = precision == NB_BF16 ? bf16_pack_elems(in_dim, n_hidden, width) : 0;
   const size_t P = (size_t)b->n_params;
   nb_status st = dev_alloc(&b->theta, P);
   if (st == NB_OK) st = dev_alloc(&b->m, P);
   if (st == NB_OK) st = dev_alloc(&b->v, P);
   if (st == NB_OK) st = dev_alloc(&b->grad, P);
   if (st == NB_OK) st = dev_alloc(&b->pack, (size_t)b->pack_floats);
+  if (st == NB_OK) st = dev_alloc(&b->pack16, (size_t)b->pack16_elems);
   if (st == NB_OK) st = dev_alloc(&b->partial, (size_t)f32_max_workgroups() * P);
   if (st == NB_OK) st = dev_alloc(&b->aux, (size_t)f32_max_workgroups() * 8);
   if (st == NB_OK) {
     if (hipMemset(b->theta, 0, P * 4) != hipSuccess || hipMemset(b->m, 0, P * 4) != hipSuccess ||
-        hipMemset(b->v, 0, P * 4) != hipSuccess || hipMemset(b->pack, 0, (size_t)b->pack_floats * 4) != hipSuccess) {
+        hipMemset(b->v, 0, P * 4) != hipSuccess ||
+        (b->pack && hipMemset(b->pack, 0, (size_t)b->pack_floats * 4) != hipSuccess) ||
+        (b->pack16 && hipMemset(b->pack16, 0, (size_t)b->pack16_elems * 2) != hipSuccess)) {
       nb_set_error("hipMemset of the bound state failed");
       st = NB_ERR_HIP;
     }
@@ -284,6 +302,7 @@ nb_status nb_bound_destroy(nb_bound* b) {
   dev_free(b->v);
   dev_free(b->grad);
   dev_free(b->pack);
+  dev_free(b->pack16);
   dev_free(b->partial);
   dev_free(b->aux);
   dev_free(b->batch_q);
@@ -316,7 +335,7 @@ nb_status nb_bound_set_params(nb_bound* b, const float* theta, int64_t n_params,
   NB_HIP(hipMemsetAsync(b->m, 0, n_params * 4, s));
   NB_HIP(hipMemsetAsync(b->v, 0, n_params * 4, s));
   b->adam_t = 0;
-  return f32_pack(b, s);
+  return repack(b, s);
 }
 
 nb_status nb_bound_get_params(const nb_bound* b, float* theta, int64_t n_params, void* stream) {
@@ -360,6 +379,7 @@ nb_status nb_bound_forward(const nb_bound* b, const float* q, int64_t n, float e
   hipStream_t s = as_stream(stream);
   auto* cnt = reinterpret_cast<unsigned long long*>(counts);
   if (cnt) NB_TRY(launch_zero_u64(cnt, 4, s));
+  if (b->precision == NB_BF16) return bf16_forward(b, q, n, tau_of(eps), logits, h, g, cnt, s);
   return f32_forward(b, q, n, tau_of(eps), logits, h, g, cnt, s);
 }
 
@@ -369,6 +389,7 @@ nb_status nb_bound_loss_grad(nb_bound* b, const float* q, const uint8_t* y, int6
   NB_REQUIRE(n > 0 && n <= (int64_t(1) << 30), "n must be in 1..2^30");
   NB_REQUIRE(std::isfinite(alpha) && std::isfinite(beta) && alpha >= 0 && beta >= 0,
              "alpha and beta must be finite and >= 0");
+  NB_TRY(require_f32_training(b));
   hipStream_t s = as_stream(stream);
   int n_wg = 0;
   NB_TRY(f32_train_partials(b, q, y, n, alpha, beta, tau_of(1e-5f), &n_wg, s));
@@ -402,7 +423,7 @@ nb_status nb_bound_adam_step(nb_bound* b, const float* grad, float lr, float bet
   hipStream_t s = as_stream(stream);
   const AdamArgs a = adam_args(b, lr, beta1, beta2, adam_eps, lam1, lam2);
   NB_TRY(launch_adam(b, grad, a, s));
-  return f32_pack(b, s);
+  return repack(b, s);
 }
 
 nb_status nb_bound_train_step(nb_bound* b, const nb_indicator* ind, int kind, uint64_t seed, uint64_t step,
@@ -414,6 +435,7 @@ nb_status nb_bound_train_step(nb_bound* b, const nb_indicator* ind, int kind, ui
   NB_REQUIRE(lr > 0 && lam1 >= 0 && lam2 >= 0, "invalid learning rate or regularisation");
   NB_REQUIRE(std::isfinite(alpha) && std::isfinite(beta) && alpha >= 0 && beta >= 0,
              "alpha and beta must be finite and >= 0");
+  NB_TRY(require_f32_training(b));
   const int d = kind_dim(kind, ind->dim);
   NB_REQUIRE(d == b->in_dim, "bound input dimension %d does not match the %d-D query", b->in_dim, d);
   hipStream_t s = as_stream(stream);
@@ -435,7 +457,7 @@ nb_status nb_bound_train_step(nb_bound* b, const nb_indicator* ind, int kind, ui
   const AdamArgs a = adam_args(b, lr, 0.9f, 0.999f, 1e-8f, lam1, lam2);
   NB_TRY(launch_reduce(b, n_wg, nullptr, loss, (float)(1.0 / (double)batch),
                        reinterpret_cast<unsigned long long*>(counts), a, s));
-  return f32_pack(b, s);
+  return repack(b, s);
 }
 
 }  // extern "C"

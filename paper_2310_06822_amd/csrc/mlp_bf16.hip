@@ -1,0 +1,297 @@
+// The bound h_theta as a bfloat16 MLP on the matrix cores (Sec. 3.4,
+// "Architecture"; ReLU hidden layers), v_mfma_f32_16x16x32_bf16 with float32
+// accumulation.
+//
+// Rounding points (the paper states no precision; these are the ones the CPU
+// oracle models):
+//   first layer   "bf16x3": with v_hi = bf16(v), v_lo = bf16(v - v_hi),
+//                 W x -> W_hi x_hi + W_hi x_lo + W_lo x_hi, one K = 32 MFMA
+//                 (input dimension <= 8): lane group 0 feeds x_hi against
+//                 W_hi, group 1 x_lo against W_hi, group 2 x_hi against W_lo,
+//                 group 3 zeros.
+//   hidden layers weights and input activations rounded to bfloat16.
+//   output layer  float32 dot product of float32 activations.
+//
+// Register layout (as in the float32 kernel): neurons are MFMA rows, queries
+// MFMA columns; after a layer, lane l holds neurons 16*mo + 4*(l/16) + r of
+// query l % 16.  A K = 32 step of the next layer takes the 8 values of row
+// blocks 2*ks and 2*ks + 1 that a lane already holds; the weight fragments
+// are packed in that K order, one 16-byte slice per lane.
+//
+// Each wave works on NB blocks of 16 queries at once so that one 1 KiB weight
+// fragment read from LDS feeds NB matrix-core instructions.
+#include <algorithm>
+
+#include "nb_internal.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ floatx4 mfma32(bf16x8 a, bf16x8 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// bfloat16 round-to-nearest-even of a float32, from its bit pattern.
+__host__ __device__ inline uint16_t bf16_bits(float v) {
+  uint32_t u;
+  __builtin_memcpy(&u, &v, 4);
+  u = u + 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float v;
+  __builtin_memcpy(&v, &u, 4);
+  return v;
+}
+
+__host__ __device__ inline int64_t w_off(int l, int in_dim, int W) {
+  return l == 0 ? 0 : (int64_t)W * in_dim + W + (int64_t)(l - 1) * ((int64_t)W * W + W);
+}
+__host__ __device__ inline int64_t b_off(int l, int in_dim, int W, int NH) {
+  return w_off(l, in_dim, W) + (int64_t)(l == 0 ? in_dim : W) * (l == NH ? 1 : W);
+}
+
+// ------------------------------------------------------------------ packing
+//
+// pack[(f*64 + lane)*8 + j] (bfloat16 bits), c = lane % 16, g = lane / 16:
+//   f < RB            first layer, block mo = f:
+//                       g = 0, 1: W0_hi[16mo + c][j];  g = 2: W0_lo[16mo + c][j];
+//                       g = 3: 0;  (0 for j >= in_dim)
+//   f < NFWD          hidden layer l (1-based), fragment (mo, ks), f = RB + (l-1)*FH + mo*KS + ks:
+//                       W_l[16mo + c][32ks + 16(j/4) + 4g + (j%4)]
+__global__ void k_pack_bf16(const float* __restrict__ theta, int in_dim, int W, int NH, uint16_t* __restrict__ pack,
+                            int64_t total) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int j = (int)(idx & 7), lane = (int)((idx >> 3) & 63);
+  const int f = (int)(idx >> 9);
+  const int c = lane & 15, g = lane >> 4;
+  const int RB = W / 16, KS = W / 32, FH = RB * KS;
+  uint16_t v = 0;
+  if (f < RB) {
+    if (j < in_dim && g < 3) {
+      const float w = theta[(int64_t)(16 * f + c) * in_dim + j];
+      const uint16_t hi = bf16_bits(w);
+      v = g < 2 ? hi : bf16_bits(w - bf16_value(hi));
+    }
+  } else {
+    const int t = f - RB;
+    const int l = 1 + t / FH, rem = t % FH, mo = rem / KS, ks = rem % KS;
+    const float* Wl = theta + w_off(l, in_dim, W);
+    v = bf16_bits(Wl[(int64_t)(16 * mo + c) * W + 32 * ks + 16 * (j / 4) + 4 * g + (j % 4)]);
+  }
+  pack[idx] = v;
+}
+
+// ------------------------------------------------------------------ forward
+
+template <int W, int NH>
+struct B16 {
+  static constexpr int RB = W / 16;
+  static constexpr int KS = W / 32;
+  static constexpr int FH = RB * KS;
+  static constexpr int NFWD = RB + (NH - 1) * FH;
+  static constexpr int kBias = NH * W + W + 1;   // hidden biases, output weights, output bias
+  static constexpr size_t lds_bytes() { return (size_t)NFWD * 64 * 16 + (size_t)kBias * 4; }
+};
+
+template <int NB>
+__device__ __forceinline__ void load_inputs(const float* __restrict__ q, int64_t n, int in_dim, int64_t q0, int c,
+                                            int grp, bf16x8 (&xb)[NB]) {
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int64_t qi = q0 + nb * 16 + c;
+    const bool valid = qi < n;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float x = (valid && j < in_dim) ? q[qi * in_dim + j] : 0.0f;
+      const __bf16 hi = (__bf16)x;
+      const __bf16 lo = (__bf16)(x - (float)hi);
+      xb[nb][j] = grp == 1 ? lo : (grp == 3 ? (__bf16)0.0f : hi);
+    }
+  }
+}
+
+template <int W, int NH, int NB, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_fwd_bf16(const float* __restrict__ q, int64_t n, int in_dim,
+                                                  const bf16x8* __restrict__ pack, const float* __restrict__ theta,
+                                                  float tau, float* __restrict__ logits, uint8_t* __restrict__ hout,
+                                                  const uint8_t* __restrict__ g, unsigned long long* __restrict__ counts) {
+  using N = B16<W, NH>;
+  constexpr int RB = N::RB, KS = N::KS;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  bf16x8* swt = reinterpret_cast<bf16x8*>(smem_raw);
+  float* sbias = reinterpret_cast<float*>(smem_raw + (size_t)N::NFWD * 64 * 16);
+  const float* swo = sbias + NH * W;
+
+  for (int i = threadIdx.x; i < N::NFWD * 64; i += blockDim.x) swt[i] = pack[i];
+  for (int i = threadIdx.x; i < NH * W; i += blockDim.x) sbias[i] = theta[b_off(i / W, in_dim, W, NH) + i % W];
+  for (int i = threadIdx.x; i < W + 1; i += blockDim.x) sbias[NH * W + i] = theta[w_off(NH, in_dim, W) + i];
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4;
+  const int waves = blockDim.x >> 6;
+  const float bo = swo[W];
+
+  unsigned cnt[4] = {0u, 0u, 0u, 0u};
+  const int64_t tiles = (n + NB * 16 - 1) / (NB * 16);
+  for (int64_t tile = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6); tile < tiles;
+       tile += (int64_t)gridDim.x * waves) {
+    const int64_t q0 = tile * NB * 16;
+    floatx4 acc[NB][RB];
+    {
+      bf16x8 xb[NB];
+      load_inputs<NB>(q, n, in_dim, q0, c, grp, xb);
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo) {
+        const float* b = sbias + 16 * mo + 4 * grp;
+        const floatx4 bi = floatx4{b[0], b[1], b[2], b[3]};
+        const bf16x8 a = swt[mo * 64 + lane];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = mfma32(a, xb[nb], bi);
+      }
+    }
+#pragma unroll
+    for (int l = 1; l < NH; ++l) {
+      bf16x8 act[NB][KS];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) act[nb][ks][j] = (__bf16)fmaxf(acc[nb][2 * ks + j / 4][j % 4], 0.0f);
+      const bf16x8* fr = swt + (RB + (l - 1) * N::FH) * 64 + lane;
+      // two fragment slots: row block mo computes while mo + 1's fragments load
+      bf16x8 fa[KS], fb[KS];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) fa[ks] = fr[ks * 64];
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo) {
+        bf16x8(&cur)[KS] = (mo & 1) ? fb : fa;
+        bf16x8(&nxt)[KS] = (mo & 1) ? fa : fb;
+        if (mo + 1 < RB) {
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) nxt[ks] = fr[((mo + 1) * KS + ks) * 64];
+        }
+        const float* b = sbias + l * W + 16 * mo + 4 * grp;
+        const floatx4 bi = floatx4{b[0], b[1], b[2], b[3]};
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = bi;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = mfma32(cur[ks], act[nb][ks], acc[nb][mo]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      float p = 0.0f;
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) p = fmaf(swo[16 * mo + 4 * grp + r], fmaxf(acc[nb][mo][r], 0.0f), p);
+      p += __shfl_xor(p, 16);
+      p += __shfl_xor(p, 32);
+      const float z = p + bo;
+      const int64_t qi = q0 + nb * 16 + c;
+      const bool own = grp == 0 && qi < n;
+      const bool pos = !(z < tau);
+      if (own) {
+        if (logits) logits[qi] = z;
+        if (hout) hout[qi] = pos;
+      }
+      if (counts) {
+        const bool gv = own && g[qi] != 0;
+        cnt[0] += __popcll(__ballot(own && pos && gv));
+        cnt[1] += __popcll(__ballot(own && pos && !gv));
+        cnt[2] += __popcll(__ballot(own && !pos && !gv));
+        cnt[3] += __popcll(__ballot(own && !pos && gv));
+      }
+    }
+  }
+  if (counts && lane == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (cnt[i]) atomicAdd(&counts[i], (unsigned long long)cnt[i]);
+  }
+}
+
+int cu_count() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cus[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cus[dev] = v;
+  }
+  return cus[dev];
+}
+
+template <int W, int NH, int NB, int THREADS>
+nb_status fwd_launch(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
+                     const uint8_t* g, unsigned long long* counts, hipStream_t s) {
+  using N = B16<W, NH>;
+  const size_t lds = N::lds_bytes();
+  static bool attr_set[64] = {false};
+  int dev = 0;
+  NB_HIP(hipGetDevice(&dev));
+  if (dev >= 0 && dev < 64 && !attr_set[dev]) {
+    NB_HIP(hipFuncSetAttribute((const void*)k_fwd_bf16<W, NH, NB, THREADS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    attr_set[dev] = true;
+  }
+  const int64_t tiles = (n + NB * 16 - 1) / (NB * 16);
+  const int64_t want = (tiles + THREADS / 64 - 1) / (THREADS / 64);
+  const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(4, (160 * 1024) / (int64_t)lds));
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, per_cu * cu_count()));
+  k_fwd_bf16<W, NH, NB, THREADS><<<grid, THREADS, lds, s>>>(q, n, b->in_dim, reinterpret_cast<const bf16x8*>(b->pack16),
+                                                    b->theta, tau, logits, h, g, counts);
+  NB_LAUNCHED();
+  return NB_OK;
+}
+
+// (W, NH) instances with every hidden layer resident in LDS.
+#define NB_BF16_CASES(X) \
+  X(32, 1) X(32, 2) X(32, 3) X(32, 4) X(64, 1) X(64, 2) X(64, 3) X(64, 4) \
+  X(128, 1) X(128, 2) X(128, 3) X(128, 4) X(128, 5)
+
+}  // namespace
+
+bool bf16_supported(int in_dim, int n_hidden, int width) {
+  if (in_dim < 1 || in_dim > 8) return false;
+#define X(WW, H) \
+  if (width == WW && n_hidden == H) return true;
+  NB_BF16_CASES(X)
+#undef X
+  return false;
+}
+
+int64_t bf16_pack_elems(int in_dim, int n_hidden, int width) {
+  (void)in_dim;
+  const int RB = width / 16, KS = width / 32;
+  return (int64_t)(RB + (n_hidden - 1) * RB * KS) * 64 * 8;
+}
+
+nb_status bf16_pack(const nb_bound* b, hipStream_t s) {
+  const int64_t total = b->pack16_elems;
+  k_pack_bf16<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(b->theta, b->in_dim, b->width, b->n_hidden,
+                                                              b->pack16, total);
+  NB_LAUNCHED();
+  return NB_OK;
+}
+
+nb_status bf16_forward(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
+                       const uint8_t* g, unsigned long long* counts, hipStream_t s) {
+#define X(WW, H)                                 \
+  if (b->width == WW && b->n_hidden == H)        \
+    return fwd_launch<WW, H, 4, 256>(b, q, n, tau, logits, h, g, counts, s);
+  NB_BF16_CASES(X)
+#undef X
+  nb_set_error("bfloat16 bound %d x %d^%d has no kernel", b->in_dim, b->width, b->n_hidden);
+  return NB_ERR_UNSUPPORTED;
+}

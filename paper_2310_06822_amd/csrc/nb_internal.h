@@ -59,8 +59,10 @@ struct nb_bound {
   float* theta = nullptr;    // float32 master parameters
   float* m = nullptr;        // Adam first moment
   float* v = nullptr;        // Adam second moment
-  float* pack = nullptr;     // weights in MFMA fragment order
+  float* pack = nullptr;     // float32 weights in MFMA fragment order (NB_F32)
   int64_t pack_floats = 0;
+  uint16_t* pack16 = nullptr;  // bfloat16 weight fragments (NB_BF16)
+  int64_t pack16_elems = 0;
   int64_t adam_t = 0;        // Adam steps taken
   // work space
   float* partial = nullptr;  // [max_wg][n_params] per-workgroup gradient partials
@@ -96,6 +98,13 @@ nb_status f32_forward(const nb_bound* b, const float* q, int64_t n, float tau, f
 nb_status f32_train_partials(const nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha,
                              float beta, float tau, int* n_wg, hipStream_t s);
 int f32_max_workgroups();
+
+// mlp_bf16.hip
+bool bf16_supported(int in_dim, int n_hidden, int width);
+int64_t bf16_pack_elems(int in_dim, int n_hidden, int width);
+nb_status bf16_pack(const nb_bound* b, hipStream_t s);
+nb_status bf16_forward(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
+                       const uint8_t* g, unsigned long long* counts, hipStream_t s);
 
 // optim.hip
 // Reduce partials over n_wg workgroups: writes grad (if non-null), loss and

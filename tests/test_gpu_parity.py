@@ -172,6 +172,35 @@ def test_forward_counts_and_edge_logits(c2_grid):
     assert np.array_equal(L.decide(host(z))[~band], L.decide(ref)[~band])
 
 
+BF16_SHAPES = [(6, 128, 4), (4, 64, 3), (6, 32, 2), (8, 128, 5), (3, 64, 1), (2, 32, 4)]
+
+
+@pytest.mark.parametrize("in_dim,width,nh", BF16_SHAPES)
+@pytest.mark.parametrize("n", [1, 17, 4099])
+def test_forward_bf16_parity(in_dim, width, nh, n):
+    """bfloat16 forward vs the oracle's bfloat16 model: |dz| <= 1e-3 max(|z|, s);
+    decisions identical wherever that bar cannot flip the sign."""
+    widths = [width] * nh
+    theta = synth.init_params(80 + in_dim + width + nh, in_dim, widths)
+    q = synth.points(81, n, in_dim)
+    b = nb.Bound(in_dim, nh, width, nb.BF16)
+    b.set_params(theta)
+    z, h = b.forward(cuda(q))
+    z, h = host(z).astype(np.float64), host(h)
+    ref = mlp.forward(theta, in_dim, widths, q, bf16=True)
+    s = mlp.abs_forward(theta, in_dim, widths, q, bf16=True)
+    bound = 1e-3 * np.maximum(np.abs(ref), s)
+    err = np.abs(z - ref)
+    assert np.all(err <= bound), f"max err/bound {np.max(err / bound):.3g}"
+    sure = np.abs(ref) > np.maximum(1e-4, bound)
+    assert np.array_equal(h[sure], L.decide(ref)[sure])
+    assert np.array_equal(h, L.decide(z))
+    # the bfloat16 path is not the float32 one: its error is visible against float32
+    if n > 1000:
+        z32 = mlp.forward(theta, in_dim, widths, q)
+        assert np.max(np.abs(z - z32)) > 1e-6
+
+
 # ---------------------------------------------------------- loss / gradient
 
 def _rel_frob(a, b):
