@@ -157,6 +157,12 @@ nb_status nb_bound_num_params(const nb_bound* b, int64_t* n_params);
 /* Shape of the bound as created (any output pointer may be NULL). */
 nb_status nb_bound_shape(const nb_bound* b, int* in_dim, int* n_hidden, int* width, int* precision);
 
+/* Forward kernel variants (tile shapes: query blocks per wave and threads
+ * per workgroup) for this bound; every variant computes the same result, so
+ * a tuner may time them and keep the fastest.  Variant 0 is the default. */
+nb_status nb_bound_num_variants(const nb_bound* b, int* count);
+nb_status nb_bound_set_variant(nb_bound* b, int variant);
+
 /* Copy theta (device, float32[n_params]) into the bound; resets the Adam
  * moments and step count to zero. */
 nb_status nb_bound_set_params(nb_bound* b, const float* theta, int64_t n_params, void* stream);

@@ -177,6 +177,16 @@ def nb_bound_shape(b):
     return tuple(x.value for x in v)
 
 
+def nb_bound_num_variants(b) -> int:
+    n = C.c_int()
+    _check(lib().nb_bound_num_variants(b, C.byref(n)))
+    return n.value
+
+
+def nb_bound_set_variant(b, variant: int):
+    _check(lib().nb_bound_set_variant(b, int(variant)))
+
+
 def nb_bound_set_params(b, theta: torch.Tensor, stream=None):
     _check(lib().nb_bound_set_params(b, _dev(theta, torch.float32, "theta"), theta.numel(), _stream(stream)))
 

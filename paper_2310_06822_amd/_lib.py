@@ -32,6 +32,8 @@ SIGNATURES = {
     "nb_bound_destroy": (i32, [vp]),
     "nb_bound_num_params": (i32, [vp, C.POINTER(i64)]),
     "nb_bound_shape": (i32, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "nb_bound_num_variants": (i32, [vp, C.POINTER(C.c_int)]),
+    "nb_bound_set_variant": (i32, [vp, C.c_int]),
     "nb_bound_set_params": (i32, [vp, vp, i64, vp]),
     "nb_bound_get_params": (i32, [vp, vp, i64, vp]),
     "nb_bound_get_state": (i32, [vp, vp, vp, i64, C.POINTER(i64), vp]),

@@ -1,0 +1,54 @@
+"""Tile-shape tuner for the bound's forward kernels.
+
+Every forward variant of a bound computes the same logits; they differ in how
+many 16-query blocks a wave carries and how many waves share the weights a
+workgroup holds in LDS.  The tuner times each variant on the caller's query
+batch with HIP events, keeps the fastest, and remembers the choice per
+(precision, in_dim, width, n_hidden, batch size class, device).
+"""
+
+from __future__ import annotations
+
+import torch
+
+from . import Bound, nb_bound_forward, nb_bound_num_variants, nb_bound_set_variant
+
+_CACHE: dict = {}
+
+
+def _key(b: Bound, n: int):
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return (b.precision, b.in_dim, b.width, b.n_hidden, max(n, 1).bit_length(), props.name)
+
+
+def time_variants(b: Bound, q: torch.Tensor, reps: int = 5) -> list:
+    """Mean milliseconds per forward (decision only) for every variant."""
+    n = q.shape[0]
+    h = torch.empty(n, dtype=torch.uint8, device=q.device)
+    out = []
+    for v in range(nb_bound_num_variants(b.handle)):
+        nb_bound_set_variant(b.handle, v)
+        nb_bound_forward(b.handle, q, h=h)                  # warm-up
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            nb_bound_forward(b.handle, q, h=h)
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1) / reps)
+    return out
+
+
+def tune(b: Bound, q: torch.Tensor, reps: int = 5) -> int:
+    """Select the fastest forward variant for this bound and batch; returns it."""
+    k = _key(b, q.shape[0])
+    if k not in _CACHE:
+        ms = time_variants(b, q, reps)
+        _CACHE[k] = (min(range(len(ms)), key=ms.__getitem__), ms)
+    v = _CACHE[k][0]
+    nb_bound_set_variant(b.handle, v)
+    return v
+
+
+def report() -> dict:
+    return {str(k): {"variant": v, "ms": ms} for k, (v, ms) in _CACHE.items()}

@@ -326,6 +326,21 @@ nb_status nb_bound_shape(const nb_bound* b, int* in_dim, int* n_hidden, int* wid
   return NB_OK;
 }
 
+nb_status nb_bound_num_variants(const nb_bound* b, int* count) {
+  NB_REQUIRE(b && count, "NULL argument");
+  *count = b->precision == NB_BF16 ? bf16_variants() : 1;
+  return NB_OK;
+}
+
+nb_status nb_bound_set_variant(nb_bound* b, int variant) {
+  NB_REQUIRE(b, "bound is NULL");
+  int n = 0;
+  nb_bound_num_variants(b, &n);
+  NB_REQUIRE(variant >= 0 && variant < n, "variant %d out of range 0..%d", variant, n - 1);
+  b->variant = variant;
+  return NB_OK;
+}
+
 nb_status nb_bound_set_params(nb_bound* b, const float* theta, int64_t n_params, void* stream) {
   NB_REQUIRE(b && theta, "NULL argument");
   NB_REQUIRE(n_params == b->n_params, "bound has %lld parameters, got %lld", (long long)b->n_params,

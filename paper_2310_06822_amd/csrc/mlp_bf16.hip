@@ -285,11 +285,24 @@ nb_status bf16_pack(const nb_bound* b, hipStream_t s) {
   return NB_OK;
 }
 
+int bf16_variants() { return 6; }
+
+// Variant v: (query blocks per wave, threads per workgroup) =
+//   0: (2, 768)   1: (2, 512)   2: (3, 512)   3: (1, 1024)   4: (4, 256)   5: (2, 256)
+// Variant 0 (three waves per SIMD) measured fastest for widths 32..128.
 nb_status bf16_forward(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
                        const uint8_t* g, unsigned long long* counts, hipStream_t s) {
-#define X(WW, H)                                 \
-  if (b->width == WW && b->n_hidden == H)        \
-    return fwd_launch<WW, H, 4, 256>(b, q, n, tau, logits, h, g, counts, s);
+#define X(WW, H)                                                                  \
+  if (b->width == WW && b->n_hidden == H) {                                       \
+    switch (b->variant) {                                                         \
+      case 1: return fwd_launch<WW, H, 2, 512>(b, q, n, tau, logits, h, g, counts, s);  \
+      case 2: return fwd_launch<WW, H, 3, 512>(b, q, n, tau, logits, h, g, counts, s);  \
+      case 3: return fwd_launch<WW, H, 1, 1024>(b, q, n, tau, logits, h, g, counts, s); \
+      case 4: return fwd_launch<WW, H, 4, 256>(b, q, n, tau, logits, h, g, counts, s);  \
+      case 5: return fwd_launch<WW, H, 2, 256>(b, q, n, tau, logits, h, g, counts, s);  \
+      default: return fwd_launch<WW, H, 2, 768>(b, q, n, tau, logits, h, g, counts, s); \
+    }                                                                             \
+  }
   NB_BF16_CASES(X)
 #undef X
   nb_set_error("bfloat16 bound %d x %d^%d has no kernel", b->in_dim, b->width, b->n_hidden);

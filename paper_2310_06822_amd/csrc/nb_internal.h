@@ -64,6 +64,7 @@ struct nb_bound {
   uint16_t* pack16 = nullptr;  // bfloat16 weight fragments (NB_BF16)
   int64_t pack16_elems = 0;
   int64_t adam_t = 0;        // Adam steps taken
+  int variant = 0;           // forward kernel variant (tile shape), see nb_bound_set_variant
   // work space
   float* partial = nullptr;  // [max_wg][n_params] per-workgroup gradient partials
   float* aux = nullptr;      // [max_wg][8] per-workgroup loss / counts
@@ -103,6 +104,7 @@ int f32_max_workgroups();
 bool bf16_supported(int in_dim, int n_hidden, int width);
 int64_t bf16_pack_elems(int in_dim, int n_hidden, int width);
 nb_status bf16_pack(const nb_bound* b, hipStream_t s);
+int bf16_variants();
 nb_status bf16_forward(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
                        const uint8_t* g, unsigned long long* counts, hipStream_t s);
 
