@@ -21,8 +21,8 @@
  *     the null stream) and runs asynchronously: results are valid once the
  *     stream has been synchronised.  Only set-up calls synchronise: the
  *     *_create / *_destroy calls (which allocate or free memory),
- *     nb_voxelize_metaballs, and nb_bound_train_step when its batch grows
- *     beyond every earlier batch (it then enlarges its work space).
+ *     nb_voxelize_metaballs, and nb_bound_train_step / nb_cascade when their
+ *     batch grows beyond every earlier one (they then enlarge work space).
  *   - Queries are float32 rows:  point [n, d] (d = 2, 3 or 4: x, y, z, t);
  *     ray [n, 6] = (origin, unit direction); box [n, 6] = (min corner,
  *     max corner); plane [n, 6] = (point p0, unit normal).  These follow the
@@ -208,6 +208,18 @@ nb_status nb_bound_adam_step(nb_bound* b, const float* grad, float lr, float bet
 nb_status nb_bound_train_step(nb_bound* b, const nb_indicator* ind, int kind, uint64_t seed, uint64_t step,
                               int64_t batch, float alpha, float beta, float lr, float lam1, float lam2,
                               float* loss, uint64_t* counts, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Cascade (Sec. 1, Sec. 6 "Tightness"): the bound screens the queries and
+ * only the ones it calls positive reach the exact test.
+ *   answer[i] = g(q_i) if h(q_i) = 1, else 0        (uint8[n], device)
+ * so answer equals g for every query iff the bound has no false negative.
+ * n_exact (uint64[1], device) is overwritten with the number of exact tests
+ * run (= number of positives).  The bound's input dimension must match the
+ * query.  Keeps an int32[n] index list in the bound: the first call with a
+ * larger n than before synchronises `stream` to enlarge it.  n < 2^31. */
+nb_status nb_cascade(nb_bound* b, const nb_indicator* ind, int kind, const float* q, int64_t n, float eps,
+                     uint8_t* answer, uint64_t* n_exact, void* stream);
 
 #ifdef __cplusplus
 }

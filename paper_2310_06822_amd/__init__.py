@@ -240,6 +240,16 @@ def nb_bound_train_step(b, ind, kind: int, seed: int, step: int, batch: int, alp
                                      _stream(stream)))
 
 
+def nb_cascade(b, ind, kind: int, q: torch.Tensor, answer: torch.Tensor, n_exact: torch.Tensor,
+               eps: float = EPS_OUT, stream=None):
+    n = _rows(q, nb_bound_shape(b)[0])
+    if _query_cols(int(kind), nb_indicator_dim(ind)) != q.shape[1]:
+        raise ValueError("query width does not match the indicator and kind")
+    _check(lib().nb_cascade(b, ind, int(kind), _dev(q, torch.float32, "q"), n, float(eps),
+                            _dev(answer, torch.uint8, "answer", n), _dev(n_exact, torch.int64, "n_exact", 1),
+                            _stream(stream)))
+
+
 # ------------------------------------------------------------ conveniences
 
 class Indicator:

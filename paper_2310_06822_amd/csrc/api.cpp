@@ -307,6 +307,7 @@ nb_status nb_bound_destroy(nb_bound* b) {
   dev_free(b->aux);
   dev_free(b->batch_q);
   dev_free(b->batch_y);
+  dev_free(b->cascade_idx);
   delete b;
   return NB_OK;
 }
@@ -473,6 +474,31 @@ nb_status nb_bound_train_step(nb_bound* b, const nb_indicator* ind, int kind, ui
   NB_TRY(launch_reduce(b, n_wg, nullptr, loss, (float)(1.0 / (double)batch),
                        reinterpret_cast<unsigned long long*>(counts), a, s));
   return repack(b, s);
+}
+
+nb_status nb_cascade(nb_bound* b, const nb_indicator* ind, int kind, const float* q, int64_t n, float eps,
+                     uint8_t* answer, uint64_t* n_exact, void* stream) {
+  NB_REQUIRE(b && ind && q && answer && n_exact, "NULL argument");
+  NB_REQUIRE(kind >= NB_QUERY_POINT && kind <= NB_QUERY_PLANE, "unknown query kind %d", kind);
+  NB_REQUIRE(n > 0 && n <= (int64_t)0x7FFFFFFF, "n must be in 1..2^31-1");
+  NB_REQUIRE(eps >= 0.0f && eps < 0.5f, "eps must be in [0, 0.5)");
+  NB_REQUIRE(kind_dim(kind, ind->dim) == b->in_dim, "bound input dimension %d does not match the query", b->in_dim);
+  hipStream_t s = as_stream(stream);
+  if (b->cascade_cap < n) {
+    NB_HIP(hipStreamSynchronize(s));
+    dev_free(b->cascade_idx);
+    b->cascade_cap = 0;
+    NB_TRY(dev_alloc(&b->cascade_idx, (size_t)n));
+    b->cascade_cap = n;
+  }
+  auto* cnt = reinterpret_cast<unsigned long long*>(n_exact);
+  NB_TRY(launch_zero_u64(cnt, 1, s));
+  const float tau = tau_of(eps);
+  if (b->precision == NB_BF16)
+    NB_TRY(bf16_forward(b, q, n, tau, nullptr, answer, nullptr, nullptr, s));
+  else
+    NB_TRY(f32_forward(b, q, n, tau, nullptr, answer, nullptr, nullptr, s));
+  return launch_cascade_exact(ind, kind, q, answer, n, b->cascade_idx, cnt, answer, s);
 }
 
 }  // extern "C"

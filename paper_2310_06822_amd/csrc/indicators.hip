@@ -10,6 +10,8 @@
 // coordinate p in [-1, 1] lies in cell floor((p + 1) * (n/2)), clamped to
 // n - 1 at p = 1; a point with a coordinate outside the cube (or NaN) has
 // f = 0.
+#include <algorithm>
+
 #include "nb_internal.h"
 
 namespace {
@@ -31,34 +33,40 @@ __device__ __forceinline__ uint8_t voxel_at(const uint8_t* __restrict__ grid, in
   return grid[((int64_t)k * n + j) * n + i] != 0;
 }
 
+// Everything an exact query needs, passed to kernels by value.
+struct IndView {
+  int type, k, n;
+  float iso;
+  const float* params;
+  const uint8_t* grid;
+  const float* ray_t;
+  const int32_t* occupied;
+  const int64_t* occupied_count;
+};
+
+IndView view_of(const nb_indicator* ind) {
+  return IndView{ind->type, ind->k, ind->n, ind->iso, ind->params, ind->grid, ind->ray_t, ind->occupied,
+                 ind->occupied_count};
+}
+
 // ------------------------------------------------------------------- points
 
-__global__ void k_discs2d(const float* __restrict__ q, int64_t n, const float* __restrict__ discs, int k,
-                          uint8_t* __restrict__ g) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float x = q[2 * i], y = q[2 * i + 1];
+// f = OR_b ((x - cx)^2 + (y - cy)^2 <= r^2).
+__device__ __forceinline__ uint8_t discs2d_at(const float* __restrict__ row, const float* __restrict__ discs, int k) {
+  const float x = row[0], y = row[1];
   uint8_t hit = 0;
   for (int b = 0; b < k; ++b) {
     const float dx = x - discs[3 * b], dy = y - discs[3 * b + 1], r = discs[3 * b + 2];
     const float d2 = dx * dx + dy * dy;
     hit |= (d2 <= r * r);
   }
-  g[i] = hit;
+  return hit;
 }
 
-__global__ void k_voxel_points(const float* __restrict__ q, int64_t n, const uint8_t* __restrict__ grid, int gn,
-                               uint8_t* __restrict__ g) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  g[i] = voxel_at(grid, gn, (float)gn * 0.5f, q[3 * i], q[3 * i + 1], q[3 * i + 2]);
-}
-
-__global__ void k_metaballs4d(const float* __restrict__ q, int64_t n, const float* __restrict__ prm, int k,
-                              float iso, uint8_t* __restrict__ g) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float x = q[4 * i], y = q[4 * i + 1], z = q[4 * i + 2], t = q[4 * i + 3];
+// f = 1 iff sum_b R_b^2 / |x - (a_b + t d_b)|^2 >= iso.
+__device__ __forceinline__ uint8_t metaballs4d_at(const float* __restrict__ row, const float* __restrict__ prm, int k,
+                                                  float iso) {
+  const float x = row[0], y = row[1], z = row[2], t = row[3];
   const float* a = prm;           // [k][3] path starts
   const float* d = prm + 3 * k;   // [k][3] b - a
   const float* r = prm + 6 * k;   // [k] radii
@@ -70,86 +78,115 @@ __global__ void k_metaballs4d(const float* __restrict__ q, int64_t n, const floa
     const float d2 = (dx * dx + dy * dy) + dz * dz;
     acc = acc + (r[b] * r[b]) / d2;
   }
-  g[i] = acc >= iso;
+  return acc >= iso;
 }
 
 // --------------------------------------------------------------------- rays
 
 // g = max_j f(o + t_j d) over the sample table; stops at the first hit.
-__global__ void k_voxel_rays(const float* __restrict__ q, int64_t n, const uint8_t* __restrict__ grid, int gn,
-                             const float* __restrict__ ray_t, uint8_t* __restrict__ g) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float ox = q[6 * i], oy = q[6 * i + 1], oz = q[6 * i + 2];
-  const float dx = q[6 * i + 3], dy = q[6 * i + 4], dz = q[6 * i + 5];
+__device__ __forceinline__ uint8_t voxel_ray_at(const float* __restrict__ row, const uint8_t* __restrict__ grid, int gn,
+                                                const float* __restrict__ ray_t) {
+  const float ox = row[0], oy = row[1], oz = row[2], dx = row[3], dy = row[4], dz = row[5];
   const float half_n = (float)gn * 0.5f;
   uint8_t hit = 0;
   for (int j = 0; j < 256 && !hit; ++j) {
     const float t = ray_t[j];
     hit = voxel_at(grid, gn, half_n, ox + t * dx, oy + t * dy, oz + t * dz);
   }
-  g[i] = hit;
+  return hit;
 }
 
 // -------------------------------------------------------------------- boxes
 
 // g = OR over cells cell(max(lo,-1)) .. cell(min(hi,1)) per axis; a box
 // with hi < -1, lo > 1 or lo > hi on some axis is empty.
-__global__ void k_voxel_boxes(const float* __restrict__ q, int64_t n, const uint8_t* __restrict__ grid, int gn,
-                              uint8_t* __restrict__ g) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+__device__ __forceinline__ uint8_t voxel_box_at(const float* __restrict__ row, const uint8_t* __restrict__ grid, int gn) {
   const float half_n = (float)gn * 0.5f;
   int a[3], b[3];
-  bool empty = false;
   for (int ax = 0; ax < 3; ++ax) {
-    const float lo = q[6 * i + ax], hi = q[6 * i + 3 + ax];
-    if (!(hi >= -1.0f && lo <= 1.0f && lo <= hi)) {
-      empty = true;
-      break;
-    }
+    const float lo = row[ax], hi = row[3 + ax];
+    if (!(hi >= -1.0f && lo <= 1.0f && lo <= hi)) return 0;
     cell_of(fmaxf(lo, -1.0f), gn, half_n, a[ax]);
     cell_of(fminf(hi, 1.0f), gn, half_n, b[ax]);
   }
-  uint8_t hit = 0;
-  if (!empty) {
-    for (int kz = a[2]; kz <= b[2] && !hit; ++kz)
-      for (int jy = a[1]; jy <= b[1] && !hit; ++jy) {
-        const uint8_t* row = grid + ((int64_t)kz * gn + jy) * gn;
-        for (int ix = a[0]; ix <= b[0]; ++ix)
-          if (row[ix]) {
-            hit = 1;
-            break;
-          }
-      }
-  }
-  g[i] = hit;
+  for (int kz = a[2]; kz <= b[2]; ++kz)
+    for (int jy = a[1]; jy <= b[1]; ++jy) {
+      const uint8_t* r = grid + ((int64_t)kz * gn + jy) * gn;
+      for (int ix = a[0]; ix <= b[0]; ++ix)
+        if (r[ix]) return 1;
+    }
+  return 0;
 }
 
 // ------------------------------------------------------------------- planes
 
 // g = 1 iff an occupied cell (centre c, half width 1/n) meets the plane:
 // |n.(c - p0)| <= (1/n) (|n_x| + |n_y| + |n_z|), dot product summed x, y, z.
-__global__ void k_voxel_planes(const float* __restrict__ q, int64_t n, const int32_t* __restrict__ occ,
-                               const int64_t* __restrict__ n_occ, int gn, uint8_t* __restrict__ g) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float px = q[6 * i], py = q[6 * i + 1], pz = q[6 * i + 2];
-  const float nx = q[6 * i + 3], ny = q[6 * i + 4], nz = q[6 * i + 5];
+__device__ __forceinline__ uint8_t voxel_plane_at(const float* __restrict__ row, const int32_t* __restrict__ occ,
+                                                  const int64_t* __restrict__ n_occ, int gn) {
+  const float px = row[0], py = row[1], pz = row[2], nx = row[3], ny = row[4], nz = row[5];
   const float h = (float)(1.0 / (double)gn);
   const float rad = h * ((fabsf(nx) + fabsf(ny)) + fabsf(nz));
   const int64_t m = *n_occ;
-  uint8_t hit = 0;
-  for (int64_t c = 0; c < m && !hit; ++c) {
+  for (int64_t c = 0; c < m; ++c) {
     const int32_t idx = occ[c];
     const int ix = idx % gn, jy = (idx / gn) % gn, kz = idx / (gn * gn);
     const float cx = (float)((2.0 * ix + 1.0) / gn - 1.0);
     const float cy = (float)((2.0 * jy + 1.0) / gn - 1.0);
     const float cz = (float)((2.0 * kz + 1.0) / gn - 1.0);
     const float e = (nx * (cx - px) + ny * (cy - py)) + nz * (cz - pz);
-    hit = fabsf(e) <= rad;
+    if (fabsf(e) <= rad) return 1;
   }
-  g[i] = hit;
+  return 0;
+}
+
+// ------------------------------------------------------------- dispatch
+
+template <int KIND>
+__device__ __forceinline__ uint8_t exact_at(const IndView& v, const float* __restrict__ q, int64_t i) {
+  if (KIND == NB_QUERY_POINT) {
+    if (v.type == IND_DISCS2D) return discs2d_at(q + 2 * i, v.params, v.k);
+    if (v.type == IND_METABALLS4D) return metaballs4d_at(q + 4 * i, v.params, v.k, v.iso);
+    const float* r = q + 3 * i;
+    return voxel_at(v.grid, v.n, (float)v.n * 0.5f, r[0], r[1], r[2]);
+  }
+  if (KIND == NB_QUERY_RAY) return voxel_ray_at(q + 6 * i, v.grid, v.n, v.ray_t);
+  if (KIND == NB_QUERY_BOX) return voxel_box_at(q + 6 * i, v.grid, v.n);
+  return voxel_plane_at(q + 6 * i, v.occupied, v.occupied_count, v.n);
+}
+
+template <int KIND>
+__global__ void k_exact(IndView v, const float* __restrict__ q, int64_t n, uint8_t* __restrict__ g) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  g[i] = exact_at<KIND>(v, q, i);
+}
+
+// ------------------------------------------------------------- cascade
+
+// Indices of the queries the bound calls positive (order within the list is
+// arbitrary; every positive appears once).
+__global__ void k_compact_positive(const uint8_t* __restrict__ h, int64_t n, int32_t* __restrict__ idx,
+                                   unsigned long long* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool pos = i < n && h[i] != 0;
+  const unsigned long long m = __ballot(pos);
+  const int lane = threadIdx.x & 63;
+  unsigned long long base = 0;
+  if (lane == 0 && m) base = atomicAdd(count, (unsigned long long)__popcll(m));
+  base = __shfl(base, 0);
+  if (pos) idx[base + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)i;
+}
+
+// answer[idx[t]] = g(q[idx[t]]) for every listed positive (grid-stride).
+template <int KIND>
+__global__ void k_cascade_exact(IndView v, const float* __restrict__ q, const int32_t* __restrict__ idx,
+                                const unsigned long long* __restrict__ count, uint8_t* __restrict__ answer) {
+  const int64_t m = (int64_t)*count;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx[t];
+    answer[i] = exact_at<KIND>(v, q, i);
+  }
 }
 
 // ----------------------------------------------------------- voxelisation
@@ -215,38 +252,34 @@ nb_status launch_query_exact(const nb_indicator* ind, int kind, const float* q, 
   NB_REQUIRE(q != nullptr && g != nullptr, "q and g must be non-NULL");
   NB_REQUIRE(n > 0, "n must be positive");
   NB_REQUIRE(n <= (int64_t(1) << 40), "n too large");
+  NB_REQUIRE(kind == NB_QUERY_POINT || ind->type == IND_VOXELS, "ray, box and plane queries need a voxel indicator");
   const unsigned blocks = blocks_for(n);
-  if (kind == NB_QUERY_POINT) {
-    switch (ind->type) {
-      case IND_DISCS2D:
-        k_discs2d<<<blocks, kThreads, 0, s>>>(q, n, ind->params, ind->k, g);
-        break;
-      case IND_VOXELS:
-        k_voxel_points<<<blocks, kThreads, 0, s>>>(q, n, ind->grid, ind->n, g);
-        break;
-      case IND_METABALLS4D:
-        k_metaballs4d<<<blocks, kThreads, 0, s>>>(q, n, ind->params, ind->k, ind->iso, g);
-        break;
-      default:
-        NB_REQUIRE(false, "unknown indicator type");
-    }
-  } else {
-    NB_REQUIRE(ind->type == IND_VOXELS, "ray, box and plane queries need a voxel indicator");
-    switch (kind) {
-      case NB_QUERY_RAY:
-        k_voxel_rays<<<blocks, kThreads, 0, s>>>(q, n, ind->grid, ind->n, ind->ray_t, g);
-        break;
-      case NB_QUERY_BOX:
-        k_voxel_boxes<<<blocks, kThreads, 0, s>>>(q, n, ind->grid, ind->n, g);
-        break;
-      case NB_QUERY_PLANE:
-        NB_REQUIRE(ind->occupied != nullptr, "plane query: occupied-cell list missing");
-        k_voxel_planes<<<blocks, kThreads, 0, s>>>(q, n, ind->occupied, ind->occupied_count,
-                                                   ind->n, g);
-        break;
-      default:
-        NB_REQUIRE(false, "unknown query kind %d", kind);
-    }
+  const IndView v = view_of(ind);
+  switch (kind) {
+    case NB_QUERY_POINT: k_exact<NB_QUERY_POINT><<<blocks, kThreads, 0, s>>>(v, q, n, g); break;
+    case NB_QUERY_RAY: k_exact<NB_QUERY_RAY><<<blocks, kThreads, 0, s>>>(v, q, n, g); break;
+    case NB_QUERY_BOX: k_exact<NB_QUERY_BOX><<<blocks, kThreads, 0, s>>>(v, q, n, g); break;
+    case NB_QUERY_PLANE: k_exact<NB_QUERY_PLANE><<<blocks, kThreads, 0, s>>>(v, q, n, g); break;
+    default: NB_REQUIRE(false, "unknown query kind %d", kind);
+  }
+  NB_LAUNCHED();
+  return NB_OK;
+}
+
+nb_status launch_cascade_exact(const nb_indicator* ind, int kind, const float* q, const uint8_t* h, int64_t n,
+                               int32_t* idx, unsigned long long* count, uint8_t* answer, hipStream_t s) {
+  NB_REQUIRE(kind == NB_QUERY_POINT || ind->type == IND_VOXELS, "ray, box and plane queries need a voxel indicator");
+  NB_REQUIRE(n <= (int64_t)0x7FFFFFFF, "cascade handles at most 2^31 - 1 queries per call");
+  k_compact_positive<<<blocks_for(n), kThreads, 0, s>>>(h, n, idx, count);
+  NB_LAUNCHED();
+  const IndView v = view_of(ind);
+  const unsigned blocks = (unsigned)std::min<int64_t>(blocks_for(n), 4096);
+  switch (kind) {
+    case NB_QUERY_POINT: k_cascade_exact<NB_QUERY_POINT><<<blocks, kThreads, 0, s>>>(v, q, idx, count, answer); break;
+    case NB_QUERY_RAY: k_cascade_exact<NB_QUERY_RAY><<<blocks, kThreads, 0, s>>>(v, q, idx, count, answer); break;
+    case NB_QUERY_BOX: k_cascade_exact<NB_QUERY_BOX><<<blocks, kThreads, 0, s>>>(v, q, idx, count, answer); break;
+    case NB_QUERY_PLANE: k_cascade_exact<NB_QUERY_PLANE><<<blocks, kThreads, 0, s>>>(v, q, idx, count, answer); break;
+    default: NB_REQUIRE(false, "unknown query kind %d", kind);
   }
   NB_LAUNCHED();
   return NB_OK;

@@ -73,6 +73,8 @@ struct nb_bound {
   uint8_t* batch_y = nullptr;
   int64_t batch_cap = 0;
   int batch_cap_dim = 0;
+  int32_t* cascade_idx = nullptr;  // positive-query index list of nb_cascade
+  int64_t cascade_cap = 0;
 };
 
 // ------------------------------------------------------- kernel launchers
@@ -85,6 +87,8 @@ nb_status launch_sample(int kind, int dim, uint64_t seed, uint64_t step, int64_t
 nb_status launch_query_exact(const nb_indicator* ind, int kind, const float* q, int64_t n, uint8_t* g,
                              hipStream_t s);
 nb_status launch_voxelize(const float* params_dev, int k, float iso, int n, uint8_t* grid, hipStream_t s);
+nb_status launch_cascade_exact(const nb_indicator* ind, int kind, const float* q, const uint8_t* h, int64_t n,
+                               int32_t* idx, unsigned long long* count, uint8_t* answer, hipStream_t s);
 nb_status launch_collect_occupied(const uint8_t* grid, int64_t cells, int32_t* out, int64_t* count_dev,
                                   hipStream_t s);
 

@@ -297,3 +297,73 @@ def test_train_steps_parity(cfg, c2_grid):
     got = host(b.params()).astype(np.float64)
     d_gpu, d_ref = got - theta0, th - theta0
     assert _rel_frob(d_gpu, d_ref) <= 1e-2
+
+
+# ------------------------------------------------------------------ cascade
+
+@pytest.mark.parametrize("kind,prec", [("point", nb.F32), ("ray", nb.BF16), ("box", nb.BF16), ("point", nb.BF16)])
+def test_cascade(kind, prec, c2_grid):
+    _, _, grid = c2_grid
+    ind = nb.Indicator.voxels(cuda(grid), 128)
+    in_dim = 3 if kind == "point" else 6
+    if prec == nb.F32:
+        width, nh = 64, 3
+    else:
+        width, nh = 128, 4
+    theta = synth.init_params(90, in_dim, [width] * nh)
+    n = 20011
+    q = {"point": lambda: synth.points(91, n, 3), "ray": lambda: synth.rays(92, n),
+         "box": lambda: synth.boxes(93, n)}[kind]()
+    # centre the output bias so that about half of the queries are positive
+    theta[-1] -= np.float32(np.median(mlp.forward(theta, in_dim, [width] * nh, q, bf16=prec == nb.BF16)))
+    b = nb.Bound(in_dim, nh, width, prec)
+    b.set_params(theta)
+    qd = cuda(q)
+    ans = torch.empty(n, dtype=torch.uint8, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    nb.nb_cascade(b.handle, ind.handle, nb.KINDS[kind], qd, ans, cnt)
+    _, h = b.forward(qd)
+    h = host(h)
+    g = {"point": I.voxel_points, "ray": I.voxel_rays, "box": I.voxel_boxes}[kind](q, grid, 128)
+    assert np.array_equal(host(ans), h & g)
+    assert int(host(cnt)[0]) == int(h.sum())
+    assert 0 < h.sum() < n
+
+
+def test_cascade_equals_exact_for_conservative_bound(c2_grid):
+    """A bound that says 1 everywhere (large output bias) is conservative: the
+    cascade answer is exactly g and every query reaches the exact test."""
+    _, _, grid = c2_grid
+    ind = nb.Indicator.voxels(cuda(grid), 128)
+    theta = synth.init_params(94, 3, [64] * 3)
+    theta[-1] = 1e3
+    b = nb.Bound(3, 3, 64)
+    b.set_params(theta)
+    q = synth.points(95, 9999, 3)
+    ans = torch.empty(9999, dtype=torch.uint8, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    nb.nb_cascade(b.handle, ind.handle, nb.POINT, cuda(q), ans, cnt)
+    assert np.array_equal(host(ans), I.voxel_points(q, grid, 128))
+    assert int(host(cnt)[0]) == 9999
+
+
+# ----------------------------------------------------------------- autograd
+
+def test_autograd_bound_loss():
+    from paper_2310_06822_amd.autograd import bound_loss
+    in_dim, widths = 3, [64] * 3
+    theta0 = synth.init_params(96, in_dim, widths)
+    q = synth.points(97, 5000, 3)
+    y = (synth.points(98, 5000, 1)[:, 0] > 0.5).astype(np.uint8)
+    b = nb.Bound(3, 3, 64)
+    theta = cuda(theta0).requires_grad_(True)
+    loss = bound_loss(theta, b, cuda(q), cuda(y), 20.0, 1.0)
+    (2.0 * loss).backward()
+    z = mlp.forward(theta0, in_dim, widths, q)
+    gref = 2.0 * mlp.backward(theta0, in_dim, widths, q, L.dloss_dz(z, y, 20.0, 1.0))
+    assert abs(loss.item() - L.loss(z, y, 20.0, 1.0)) <= 1e-5 * L.loss(z, y, 20.0, 1.0)
+    assert _rel_frob(host(theta.grad).astype(np.float64), gref) <= 1e-5
+    # a torch optimiser steps theta with the kernel's gradient
+    opt = torch.optim.Adam([theta], lr=1e-3)
+    opt.step()
+    assert np.max(np.abs(host(theta.detach()) - theta0)) > 0
