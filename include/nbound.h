@@ -146,8 +146,8 @@ nb_status nb_sample_queries(int kind, int dim, uint64_t seed, uint64_t step, int
 /* ------------------------------------------------------------------------
  * Bound h_theta (Sec. 3.4): in_dim -> width x n_hidden (ReLU) -> 1 logit.
  * Supported: in_dim 1..8;  NB_F32: width 16, 32 or 64 with n_hidden 1..4;
- * NB_BF16 (forward only in this build): width 32 or 64 with n_hidden 1..4,
- * width 128 with n_hidden 1..5.  Other shapes give NB_ERR_UNSUPPORTED.
+ * NB_BF16: width 32 or 64 with n_hidden 1..6, width 128 with n_hidden 1..5
+ * (training needs n_hidden >= 2).  Other shapes give NB_ERR_UNSUPPORTED.
  * The handle owns float32 master parameters, Adam moments and work space.
  * Parameters start at zero; set them with nb_bound_set_params.
  * ---------------------------------------------------------------------- */
@@ -189,7 +189,10 @@ nb_status nb_bound_forward(const nb_bound* b, const float* q, int64_t n, float e
  * beta (1 - y_i) softplus(z_i)].  grad: float32[n_params] overwritten with
  * dL/dtheta; loss: float32[1] or NULL; counts: uint64[4] (TP, FP, TN, FN of
  * the decision at eps = 1e-5 against y) or NULL.  The result is
- * deterministic: the reduction order depends on n only. */
+ * deterministic: the reduction order depends on n only.  A bfloat16 bound
+ * keeps its activations in HBM for the backward pass ((n_hidden + 1) x n x
+ * width x 2 bytes); the first call with a larger n than before synchronises
+ * `stream` to enlarge that space. */
 nb_status nb_bound_loss_grad(nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha, float beta,
                              float* grad, float* loss, uint64_t* counts, void* stream);
 
@@ -199,8 +202,7 @@ nb_status nb_bound_loss_grad(nb_bound* b, const float* q, const uint8_t* y, int6
 nb_status nb_bound_adam_step(nb_bound* b, const float* grad, float lr, float beta1, float beta2, float adam_eps,
                              float lam1, float lam2, void* stream);
 
-/* (Training calls return NB_ERR_UNSUPPORTED for NB_BF16 bounds in this build.)
- * One training step of Alg. 1 on the device: sample `batch` regions of
+/* One training step of Alg. 1 on the device: sample `batch` regions of
  * `kind` (nb_sample_queries with this seed and step), label them with the
  * exact query on `ind`, evaluate loss and gradient, and take one Adam step
  * (lr, beta1 0.9, beta2 0.999, eps 1e-8).  loss: float32[1] or NULL;

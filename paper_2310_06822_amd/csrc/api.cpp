@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "nb_internal.h"
+#include "nb_mlp.h"
 
 namespace {
 
@@ -47,24 +48,61 @@ int kind_dim(int kind, int point_dim) { return kind == NB_QUERY_POINT ? point_di
 
 // Rebuild the weight fragments the forward / training kernels read.
 nb_status repack(const nb_bound* b, hipStream_t s) {
-  return b->precision == NB_BF16 ? bf16_pack(b, s) : f32_pack(b, s);
+  if (b->precision != NB_BF16) return f32_pack(b, s);
+  NB_TRY(bf16_pack(b, s));
+  return bf16_pack_t(b, s);
 }
 
-nb_status require_f32_training(const nb_bound* b) {
-  if (b->precision != NB_F32) {
-    nb_set_error("training a bfloat16 bound has no kernel in this build");
+nb_status require_training(const nb_bound* b) {
+  if (b->precision == NB_BF16 && !bf16_train_supported(b->in_dim, b->n_hidden, b->width)) {
+    nb_set_error("training a bfloat16 bound %d x %d^%d has no kernel in this build", b->in_dim, b->width,
+                 b->n_hidden);
     return NB_ERR_UNSUPPORTED;
   }
   return NB_OK;
 }
 
-#define NB_TRY(expr)                 \
-  do {                               \
-    nb_status nb_s_ = (expr);        \
-    if (nb_s_ != NB_OK) return nb_s_; \
-  } while (0)
+void dev_free_u16(uint16_t*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+// Per-workgroup gradient partials for a labelled batch, either precision;
+// returns the number of partials through n_wg.
+nb_status train_partials(nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha, float beta,
+                         int* n_wg, hipStream_t s) {
+  const float tau = tau_of(1e-5f);
+  if (b->precision != NB_BF16) return f32_train_partials(b, q, y, n, alpha, beta, tau, n_wg, s);
+  const BF16TrainPlan plan = bf16_train_plan(n);
+  if (b->tr_cap < plan.padded) {
+    // grows the activation / gradient work space (synchronising)
+    NB_HIP(hipStreamSynchronize(s));
+    dev_free_u16(b->tr_act);
+    dev_free_u16(b->tr_grad);
+    b->tr_cap = 0;
+    const size_t per = (size_t)plan.padded * b->width;
+    NB_HIP(hipMalloc(reinterpret_cast<void**>(&b->tr_act), per * (b->n_hidden - 1) * sizeof(uint16_t)));
+    NB_HIP(hipMalloc(reinterpret_cast<void**>(&b->tr_grad), per * 2 * sizeof(uint16_t)));
+    b->tr_cap = plan.padded;
+  }
+  *n_wg = plan.n_wg;
+  return bf16_train_partials(b, q, y, n, alpha, beta, tau, plan, s);
+}
+
 
 }  // namespace
+
+int nb_cu_count() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cus[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cus[dev] = v;
+  }
+  return cus[dev];
+}
 
 void nb_set_error(const char* fmt, ...) {
   va_list ap;
@@ -269,6 +307,8 @@ nb_status nb_bound_create(int in_dim, int n_hidden, int width, int precision, nb
   b->n_params = mlp_params(in_dim, n_hidden, width);
   b->pack_floats = precision == NB_F32 ? f32_pack_floats(in_dim, n_hidden, width) : 0;
   b->pack16_elems = precision == NB_BF16 ? bf16_pack_elems(in_dim, n_hidden, width) : 0;
+  b->pack16t_elems =
+      precision == NB_BF16 && bf16_train_supported(in_dim, n_hidden, width) ? bf16_packt_elems(n_hidden, width) : 0;
   const size_t P = (size_t)b->n_params;
   nb_status st = dev_alloc(&b->theta, P);
   if (st == NB_OK) st = dev_alloc(&b->m, P);
@@ -276,6 +316,7 @@ nb_status nb_bound_create(int in_dim, int n_hidden, int width, int precision, nb
   if (st == NB_OK) st = dev_alloc(&b->grad, P);
   if (st == NB_OK) st = dev_alloc(&b->pack, (size_t)b->pack_floats);
   if (st == NB_OK) st = dev_alloc(&b->pack16, (size_t)b->pack16_elems);
+  if (st == NB_OK) st = dev_alloc(&b->pack16t, (size_t)b->pack16t_elems);
   if (st == NB_OK) st = dev_alloc(&b->partial, (size_t)f32_max_workgroups() * P);
   if (st == NB_OK) st = dev_alloc(&b->aux, (size_t)f32_max_workgroups() * 8);
   if (st == NB_OK) {
@@ -303,6 +344,9 @@ nb_status nb_bound_destroy(nb_bound* b) {
   dev_free(b->grad);
   dev_free(b->pack);
   dev_free(b->pack16);
+  dev_free(b->pack16t);
+  dev_free(b->tr_act);
+  dev_free(b->tr_grad);
   dev_free(b->partial);
   dev_free(b->aux);
   dev_free(b->batch_q);
@@ -405,10 +449,10 @@ nb_status nb_bound_loss_grad(nb_bound* b, const float* q, const uint8_t* y, int6
   NB_REQUIRE(n > 0 && n <= (int64_t(1) << 30), "n must be in 1..2^30");
   NB_REQUIRE(std::isfinite(alpha) && std::isfinite(beta) && alpha >= 0 && beta >= 0,
              "alpha and beta must be finite and >= 0");
-  NB_TRY(require_f32_training(b));
+  NB_TRY(require_training(b));
   hipStream_t s = as_stream(stream);
   int n_wg = 0;
-  NB_TRY(f32_train_partials(b, q, y, n, alpha, beta, tau_of(1e-5f), &n_wg, s));
+  NB_TRY(train_partials(b, q, y, n, alpha, beta, &n_wg, s));
   AdamArgs none{};
   return launch_reduce(b, n_wg, grad, loss, (float)(1.0 / (double)n), reinterpret_cast<unsigned long long*>(counts),
                        none, s);
@@ -451,7 +495,7 @@ nb_status nb_bound_train_step(nb_bound* b, const nb_indicator* ind, int kind, ui
   NB_REQUIRE(lr > 0 && lam1 >= 0 && lam2 >= 0, "invalid learning rate or regularisation");
   NB_REQUIRE(std::isfinite(alpha) && std::isfinite(beta) && alpha >= 0 && beta >= 0,
              "alpha and beta must be finite and >= 0");
-  NB_TRY(require_f32_training(b));
+  NB_TRY(require_training(b));
   const int d = kind_dim(kind, ind->dim);
   NB_REQUIRE(d == b->in_dim, "bound input dimension %d does not match the %d-D query", b->in_dim, d);
   hipStream_t s = as_stream(stream);
@@ -469,7 +513,7 @@ nb_status nb_bound_train_step(nb_bound* b, const nb_indicator* ind, int kind, ui
   NB_TRY(launch_sample(kind, ind->dim, seed, step, batch, b->batch_q, s));
   NB_TRY(launch_query_exact(ind, kind, b->batch_q, batch, b->batch_y, s));
   int n_wg = 0;
-  NB_TRY(f32_train_partials(b, b->batch_q, b->batch_y, batch, alpha, beta, tau_of(1e-5f), &n_wg, s));
+  NB_TRY(train_partials(b, b->batch_q, b->batch_y, batch, alpha, beta, &n_wg, s));
   const AdamArgs a = adam_args(b, lr, 0.9f, 0.999f, 1e-8f, lam1, lam2);
   NB_TRY(launch_reduce(b, n_wg, nullptr, loss, (float)(1.0 / (double)batch),
                        reinterpret_cast<unsigned long long*>(counts), a, s));

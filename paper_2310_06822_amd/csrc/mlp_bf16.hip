@@ -23,36 +23,14 @@
 #include <algorithm>
 
 #include "nb_internal.h"
+#include "nb_mlp.h"
 
 namespace {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef nb_bf16x8 bf16x8;
+typedef nb_floatx4 floatx4;
 
-__device__ __forceinline__ floatx4 mfma32(bf16x8 a, bf16x8 b, floatx4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-// bfloat16 round-to-nearest-even of a float32, from its bit pattern.
-__host__ __device__ inline uint16_t bf16_bits(float v) {
-  uint32_t u;
-  __builtin_memcpy(&u, &v, 4);
-  u = u + 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__host__ __device__ inline float bf16_value(uint16_t h) {
-  const uint32_t u = (uint32_t)h << 16;
-  float v;
-  __builtin_memcpy(&v, &u, 4);
-  return v;
-}
-
-__host__ __device__ inline int64_t w_off(int l, int in_dim, int W) {
-  return l == 0 ? 0 : (int64_t)W * in_dim + W + (int64_t)(l - 1) * ((int64_t)W * W + W);
-}
-__host__ __device__ inline int64_t b_off(int l, int in_dim, int W, int NH) {
-  return w_off(l, in_dim, W) + (int64_t)(l == 0 ? in_dim : W) * (l == NH ? 1 : W);
-}
+__device__ __forceinline__ floatx4 mfma32(bf16x8 a, bf16x8 b, floatx4 c) { return nb_mfma_bf16(a, b, c); }
 
 // ------------------------------------------------------------------ packing
 //
@@ -74,14 +52,14 @@ __global__ void k_pack_bf16(const float* __restrict__ theta, int in_dim, int W, 
   if (f < RB) {
     if (j < in_dim && g < 3) {
       const float w = theta[(int64_t)(16 * f + c) * in_dim + j];
-      const uint16_t hi = bf16_bits(w);
-      v = g < 2 ? hi : bf16_bits(w - bf16_value(hi));
+      const uint16_t hi = nb_bf16_bits(w);
+      v = g < 2 ? hi : nb_bf16_bits(w - nb_bf16_value(hi));
     }
   } else {
     const int t = f - RB;
     const int l = 1 + t / FH, rem = t % FH, mo = rem / KS, ks = rem % KS;
-    const float* Wl = theta + w_off(l, in_dim, W);
-    v = bf16_bits(Wl[(int64_t)(16 * mo + c) * W + 32 * ks + 16 * (j / 4) + 4 * g + (j % 4)]);
+    const float* Wl = theta + nb_w_off(l, in_dim, W);
+    v = nb_bf16_bits(Wl[(int64_t)(16 * mo + c) * W + 32 * ks + 16 * (j / 4) + 4 * g + (j % 4)]);
   }
   pack[idx] = v;
 }
@@ -128,8 +106,8 @@ __global__ __launch_bounds__(THREADS) void k_fwd_bf16(const float* __restrict__ 
   const float* swo = sbias + NH * W;
 
   for (int i = threadIdx.x; i < N::NFWD * 64; i += blockDim.x) swt[i] = pack[i];
-  for (int i = threadIdx.x; i < NH * W; i += blockDim.x) sbias[i] = theta[b_off(i / W, in_dim, W, NH) + i % W];
-  for (int i = threadIdx.x; i < W + 1; i += blockDim.x) sbias[NH * W + i] = theta[w_off(NH, in_dim, W) + i];
+  for (int i = threadIdx.x; i < NH * W; i += blockDim.x) sbias[i] = theta[nb_b_off(i / W, in_dim, W, NH) + i % W];
+  for (int i = threadIdx.x; i < W + 1; i += blockDim.x) sbias[NH * W + i] = theta[nb_w_off(NH, in_dim, W) + i];
   __syncthreads();
 
   const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4;
@@ -220,18 +198,6 @@ __global__ __launch_bounds__(THREADS) void k_fwd_bf16(const float* __restrict__ 
   }
 }
 
-int cu_count() {
-  static int cus[64] = {0};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (!cus[dev]) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
-    cus[dev] = v;
-  }
-  return cus[dev];
-}
-
 template <int W, int NH, int NB, int THREADS>
 nb_status fwd_launch(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
                      const uint8_t* g, unsigned long long* counts, hipStream_t s) {
@@ -248,7 +214,7 @@ nb_status fwd_launch(const nb_bound* b, const float* q, int64_t n, float tau, fl
   const int64_t tiles = (n + NB * 16 - 1) / (NB * 16);
   const int64_t want = (tiles + THREADS / 64 - 1) / (THREADS / 64);
   const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(4, (160 * 1024) / (int64_t)lds));
-  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, per_cu * cu_count()));
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, per_cu * nb_cu_count()));
   k_fwd_bf16<W, NH, NB, THREADS><<<grid, THREADS, lds, s>>>(q, n, b->in_dim, reinterpret_cast<const bf16x8*>(b->pack16),
                                                     b->theta, tau, logits, h, g, counts);
   NB_LAUNCHED();
@@ -257,7 +223,8 @@ nb_status fwd_launch(const nb_bound* b, const float* q, int64_t n, float tau, fl
 
 // (W, NH) instances with every hidden layer resident in LDS.
 #define NB_BF16_CASES(X) \
-  X(32, 1) X(32, 2) X(32, 3) X(32, 4) X(64, 1) X(64, 2) X(64, 3) X(64, 4) \
+  X(32, 1) X(32, 2) X(32, 3) X(32, 4) X(32, 5) X(32, 6) \
+  X(64, 1) X(64, 2) X(64, 3) X(64, 4) X(64, 5) X(64, 6) \
   X(128, 1) X(128, 2) X(128, 3) X(128, 4) X(128, 5)
 
 }  // namespace

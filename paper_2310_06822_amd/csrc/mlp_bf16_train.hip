@@ -1,0 +1,477 @@
+// Training of a bfloat16 bound (Alg. 1 steps 4-5, gradient of Eq. 1),
+// layer by layer on the matrix cores (v_mfma_f32_16x16x32_bf16, float32
+// accumulation), with the same rounding points as the bfloat16 forward: a
+// bf16x3 first layer, bfloat16 hidden layers, a float32 output layer.
+//
+// One kernel per layer keeps a single layer's weights in LDS (at most
+// 128 KiB for width 256); activations A_l (post-ReLU, bfloat16) and
+// back-propagated gradients D_l (bfloat16) live in HBM as row-major
+// [queries][width] arrays.
+//
+//   first   x -> A_0
+//   hidden  A_{l-1} -> A_l                         (l = 1 .. H-2)
+//   head    A_{H-2} -> layer H-1 -> z (float32 output layer), Eq. 1 loss,
+//           dz = dL/dz, D_{H-1} = dz w_out [a > 0], dw_out, db_out
+//   data    D_{l-1} = (W_l^T D_l) [A_{l-1} > 0]     (transposed weight fragments)
+//   weight  dW_l = sum_q D_l[q] A_{l-1}[q]^T, db_l = sum_q D_l[q]
+//           (both operands transposed through LDS; K = queries)
+//   first'  dW_0 = sum_q D_0[q] x[q]^T, db_0 = sum_q D_0[q]   (float32 inputs)
+//
+// The batch is cut into fixed chunks, one per workgroup; every kernel that
+// produces gradient terms writes one partial per chunk, summed afterwards in
+// a fixed order, so a step is bit-reproducible.
+#include <algorithm>
+
+#include "nb_internal.h"
+#include "nb_mlp.h"
+
+namespace {
+
+typedef nb_bf16x8 bf16x8;
+typedef nb_floatx4 floatx4;
+
+__device__ __forceinline__ uint16_t bits_of(__bf16 v) { return __builtin_bit_cast(uint16_t, v); }
+__device__ __forceinline__ __bf16 bf16_of(uint16_t v) { return __builtin_bit_cast(__bf16, v); }
+
+// Four float32 values rounded to bfloat16 and packed for one 8-byte store.
+__device__ __forceinline__ uint2 pack4(float a, float b, float c, float d) {
+  return uint2{(uint32_t)bits_of((__bf16)a) | ((uint32_t)bits_of((__bf16)b) << 16),
+               (uint32_t)bits_of((__bf16)c) | ((uint32_t)bits_of((__bf16)d) << 16)};
+}
+
+__device__ __forceinline__ void unpack4(uint2 u, float v[4]) {
+  v[0] = (float)bf16_of((uint16_t)(u.x & 0xFFFF));
+  v[1] = (float)bf16_of((uint16_t)(u.x >> 16));
+  v[2] = (float)bf16_of((uint16_t)(u.y & 0xFFFF));
+  v[3] = (float)bf16_of((uint16_t)(u.y >> 16));
+}
+
+// B operand of a forward K = 32 step in the permuted order of the forward
+// pack: lane group g takes neurons 32ks + 4g + {0..3} and 32ks + 16 + 4g + {0..3}.
+__device__ __forceinline__ bf16x8 gather_fwd_operand(const uint16_t* __restrict__ row, int ks, int g) {
+  const uint2 lo = *reinterpret_cast<const uint2*>(row + 32 * ks + 4 * g);
+  const uint2 hi = *reinterpret_cast<const uint2*>(row + 32 * ks + 16 + 4 * g);
+  bf16x8 v;
+  v[0] = bf16_of((uint16_t)(lo.x & 0xFFFF));
+  v[1] = bf16_of((uint16_t)(lo.x >> 16));
+  v[2] = bf16_of((uint16_t)(lo.y & 0xFFFF));
+  v[3] = bf16_of((uint16_t)(lo.y >> 16));
+  v[4] = bf16_of((uint16_t)(hi.x & 0xFFFF));
+  v[5] = bf16_of((uint16_t)(hi.x >> 16));
+  v[6] = bf16_of((uint16_t)(hi.y & 0xFFFF));
+  v[7] = bf16_of((uint16_t)(hi.y >> 16));
+  return v;
+}
+
+// ---------------------------------------------------------- transposed pack
+//
+// packT[((l-1)*FH + mo*KS + ks)*64 + lane][j] = W_l[32ks + 8g + j][16mo + c]:
+// the A operand of (W_l^T D) with the reduction over W_l's output neurons in
+// natural order.
+__global__ void k_pack_bf16_t(const float* __restrict__ theta, int in_dim, int W, int NH, uint16_t* __restrict__ pack,
+                              int64_t total) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int j = (int)(idx & 7), lane = (int)((idx >> 3) & 63), f = (int)(idx >> 9);
+  const int c = lane & 15, g = lane >> 4;
+  const int RB = W / 16, KS = W / 32, FH = RB * KS;
+  const int l = 1 + f / FH, rem = f % FH, mo = rem / KS, ks = rem % KS;
+  const float* Wl = theta + nb_w_off(l, in_dim, W);
+  pack[idx] = nb_bf16_bits(Wl[(int64_t)(32 * ks + 8 * g + j) * W + 16 * mo + c]);
+}
+
+// ------------------------------------------------------------ first layer
+
+template <int W>
+__global__ __launch_bounds__(256) void k_tr_first(const float* __restrict__ q, int64_t n, int in_dim, int64_t CH,
+                                                  const bf16x8* __restrict__ pack, const float* __restrict__ theta,
+                                                  uint16_t* __restrict__ A0) {
+  constexpr int RB = W / 16;
+  __shared__ bf16x8 sw[RB * 64];
+  __shared__ float sb[W];
+  for (int i = threadIdx.x; i < RB * 64; i += blockDim.x) sw[i] = pack[i];
+  for (int i = threadIdx.x; i < W; i += blockDim.x) sb[i] = theta[(int64_t)W * in_dim + i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4, wave = threadIdx.x >> 6;
+  const int64_t base = (int64_t)blockIdx.x * CH;
+  for (int64_t blk = wave; blk < CH / 16; blk += blockDim.x >> 6) {
+    const int64_t qi = base + blk * 16 + c;
+    const bool valid = qi < n;
+    bf16x8 xb;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float x = (valid && j < in_dim) ? q[qi * in_dim + j] : 0.0f;
+      const __bf16 hi = (__bf16)x;
+      const __bf16 lo = (__bf16)(x - (float)hi);
+      xb[j] = grp == 1 ? lo : (grp == 3 ? (__bf16)0.0f : hi);
+    }
+    uint16_t* out = A0 + qi * W;
+#pragma unroll
+    for (int mo = 0; mo < RB; ++mo) {
+      const float* b = sb + 16 * mo + 4 * grp;
+      floatx4 acc = nb_mfma_bf16(sw[mo * 64 + lane], xb, floatx4{b[0], b[1], b[2], b[3]});
+      *reinterpret_cast<uint2*>(out + 16 * mo + 4 * grp) =
+          pack4(fmaxf(acc[0], 0.0f), fmaxf(acc[1], 0.0f), fmaxf(acc[2], 0.0f), fmaxf(acc[3], 0.0f));
+    }
+  }
+}
+
+// ------------------------------------------------- hidden layers and head
+
+template <int W>
+struct TrHidden {
+  static constexpr int RB = W / 16, KS = W / 32, FH = RB * KS;
+  static constexpr size_t lds_bytes() { return (size_t)FH * 64 * 16 + (size_t)(2 * W + 1) * 4; }
+};
+
+// A_l = relu(W_l A_{l-1} + b_l) (HEAD = false), or for the last hidden layer
+// (HEAD = true) the output logit, Eq. 1 and its gradient.
+template <int W, bool HEAD>
+__global__ __launch_bounds__(256) void k_tr_hidden(const uint16_t* __restrict__ Ain, int64_t n, int64_t CH, int l,
+                                                   int in_dim, int NH, const bf16x8* __restrict__ pack,
+                                                   const float* __restrict__ theta, uint16_t* __restrict__ Aout,
+                                                   const uint8_t* __restrict__ y, float alpha, float beta, float inv_n,
+                                                   float tau, float* __restrict__ partial, int64_t P,
+                                                   float* __restrict__ aux) {
+  using T = TrHidden<W>;
+  constexpr int RB = T::RB, KS = T::KS;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  bf16x8* sw = reinterpret_cast<bf16x8*>(smem_raw);
+  float* sb = reinterpret_cast<float*>(smem_raw + (size_t)T::FH * 64 * 16);   // [W] bias, [W] w_out, b_out
+  const bf16x8* src = pack + (RB + (l - 1) * T::FH) * 64;
+  for (int i = threadIdx.x; i < T::FH * 64; i += blockDim.x) sw[i] = src[i];
+  for (int i = threadIdx.x; i < W; i += blockDim.x) sb[i] = theta[nb_b_off(l, in_dim, W, NH) + i];
+  if (HEAD)
+    for (int i = threadIdx.x; i < W + 1; i += blockDim.x) sb[W + i] = theta[nb_w_off(NH, in_dim, W) + i];
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4, wave = threadIdx.x >> 6;
+  const int64_t base = (int64_t)blockIdx.x * CH;
+  float gwo[HEAD ? RB * 4 : 1];
+#pragma unroll
+  for (int i = 0; i < (HEAD ? RB * 4 : 1); ++i) gwo[i] = 0.0f;
+  float gbo = 0.0f, lsum = 0.0f;
+  unsigned cnt[4] = {0u, 0u, 0u, 0u};
+
+  for (int64_t blk = wave; blk < CH / 16; blk += blockDim.x >> 6) {
+    const int64_t qi = base + blk * 16 + c;
+    const uint16_t* row = Ain + qi * W;
+    bf16x8 bop[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) bop[ks] = gather_fwd_operand(row, ks, grp);
+    floatx4 acc[RB];
+#pragma unroll
+    for (int mo = 0; mo < RB; ++mo) {
+      const float* b = sb + 16 * mo + 4 * grp;
+      acc[mo] = floatx4{b[0], b[1], b[2], b[3]};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) acc[mo] = nb_mfma_bf16(sw[(mo * KS + ks) * 64 + lane], bop[ks], acc[mo]);
+    }
+    if (!HEAD) {
+      uint16_t* out = Aout + qi * W;
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo)
+        *reinterpret_cast<uint2*>(out + 16 * mo + 4 * grp) = pack4(fmaxf(acc[mo][0], 0.0f), fmaxf(acc[mo][1], 0.0f),
+                                                                  fmaxf(acc[mo][2], 0.0f), fmaxf(acc[mo][3], 0.0f));
+    } else {
+      const float* wo = sb + W;
+      float p = 0.0f;
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) p = fmaf(wo[16 * mo + 4 * grp + r], fmaxf(acc[mo][r], 0.0f), p);
+      p += __shfl_xor(p, 16);
+      p += __shfl_xor(p, 32);
+      const float z = p + wo[W];
+      const bool valid = qi < n;
+      const bool yv = valid && y[qi] != 0;
+      const float e = expf(-fabsf(z));
+      const float inv1pe = 1.0f / (1.0f + e);
+      const float sig = z >= 0.0f ? inv1pe : e * inv1pe;
+      const float sigm = z >= 0.0f ? e * inv1pe : inv1pe;
+      const float dz = valid ? inv_n * (yv ? -alpha * sigm : beta * sig) : 0.0f;
+      const bool own = grp == 0 && valid;
+      if (own) {
+        const float sp = log1pf(e);
+        lsum += yv ? alpha * (fmaxf(-z, 0.0f) + sp) : beta * (fmaxf(z, 0.0f) + sp);
+        gbo += dz;
+      }
+      const bool pos = !(z < tau);
+      cnt[0] += __popcll(__ballot(own && pos && yv));
+      cnt[1] += __popcll(__ballot(own && pos && !yv));
+      cnt[2] += __popcll(__ballot(own && !pos && !yv));
+      cnt[3] += __popcll(__ballot(own && !pos && yv));
+      uint16_t* out = Aout + qi * W;   // D_{H-1}
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo) {
+        float d[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float a = fmaxf(acc[mo][r], 0.0f);
+          gwo[mo * 4 + r] = fmaf(dz, a, gwo[mo * 4 + r]);
+          d[r] = acc[mo][r] > 0.0f ? dz * wo[16 * mo + 4 * grp + r] : 0.0f;
+        }
+        *reinterpret_cast<uint2*>(out + 16 * mo + 4 * grp) = pack4(d[0], d[1], d[2], d[3]);
+      }
+    }
+  }
+  if (HEAD) {
+    // fixed-order workgroup reduction of the output-layer terms
+    __syncthreads();
+    float* red = reinterpret_cast<float*>(smem_raw);   // reuse the weight area: [W + 1] + [4][8]
+    float* saux = red + W + 8;
+#pragma unroll
+    for (int i = 0; i < RB * 4; ++i)
+#pragma unroll
+      for (int m = 1; m < 16; m <<= 1) gwo[i] += __shfl_xor(gwo[i], m);
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+      gbo += __shfl_xor(gbo, m);
+      lsum += __shfl_xor(lsum, m);
+    }
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      if (wave == w) {
+        if (c == 0) {
+#pragma unroll
+          for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int i = 16 * mo + 4 * grp + r;
+              red[i] = w == 0 ? gwo[mo * 4 + r] : red[i] + gwo[mo * 4 + r];
+            }
+        }
+        if (lane == 0) {
+          red[W] = w == 0 ? gbo : red[W] + gbo;
+          saux[w * 8] = lsum;
+          for (int i = 0; i < 4; ++i) saux[w * 8 + 1 + i] = __uint_as_float(cnt[i]);
+        }
+      }
+      __syncthreads();
+    }
+    float* out = partial + (int64_t)blockIdx.x * P;
+    for (int i = threadIdx.x; i < W + 1; i += blockDim.x) out[nb_w_off(NH, in_dim, W) + i] = red[i];
+    if (threadIdx.x == 0) {
+      float ls = 0.0f;
+      unsigned cs[4] = {0u, 0u, 0u, 0u};
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        ls += saux[w * 8];
+        for (int i = 0; i < 4; ++i) cs[i] += __float_as_uint(saux[w * 8 + 1 + i]);
+      }
+      aux[blockIdx.x * 8] = ls;
+      for (int i = 0; i < 4; ++i) aux[blockIdx.x * 8 + 1 + i] = __uint_as_float(cs[i]);
+    }
+  }
+}
+
+// ------------------------------------------------------- data gradient
+
+// D_{l-1} = (W_l^T D_l) * [A_{l-1} > 0]
+template <int W>
+__global__ __launch_bounds__(256) void k_tr_data(const uint16_t* __restrict__ Dl, const uint16_t* __restrict__ Aprev,
+                                                 int64_t CH, int l, const bf16x8* __restrict__ packT,
+                                                 uint16_t* __restrict__ Dprev) {
+  using T = TrHidden<W>;
+  constexpr int RB = T::RB, KS = T::KS;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  bf16x8* sw = reinterpret_cast<bf16x8*>(smem_raw);
+  const bf16x8* src = packT + (l - 1) * T::FH * 64;
+  for (int i = threadIdx.x; i < T::FH * 64; i += blockDim.x) sw[i] = src[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4, wave = threadIdx.x >> 6;
+  const int64_t base = (int64_t)blockIdx.x * CH;
+  for (int64_t blk = wave; blk < CH / 16; blk += blockDim.x >> 6) {
+    const int64_t qi = base + blk * 16 + c;
+    bf16x8 bop[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) bop[ks] = *reinterpret_cast<const bf16x8*>(Dl + qi * W + 32 * ks + 8 * grp);
+    const uint16_t* arow = Aprev + qi * W;
+    uint16_t* out = Dprev + qi * W;
+#pragma unroll
+    for (int mo = 0; mo < RB; ++mo) {
+      floatx4 acc = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) acc = nb_mfma_bf16(sw[(mo * KS + ks) * 64 + lane], bop[ks], acc);
+      float a[4];
+      unpack4(*reinterpret_cast<const uint2*>(arow + 16 * mo + 4 * grp), a);
+      *reinterpret_cast<uint2*>(out + 16 * mo + 4 * grp) =
+          pack4(a[0] > 0.0f ? acc[0] : 0.0f, a[1] > 0.0f ? acc[1] : 0.0f, a[2] > 0.0f ? acc[2] : 0.0f,
+                a[3] > 0.0f ? acc[3] : 0.0f);
+    }
+  }
+}
+
+// ----------------------------------------------------- weight gradient
+
+constexpr int kTS = 40;   // LDS row stride of a [width][32 queries] bfloat16 tile (+ 8 pad)
+
+template <int W, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_tr_weight(const uint16_t* __restrict__ Dl,
+                                                          const uint16_t* __restrict__ Aprev, int64_t CH, int l,
+                                                          int in_dim, int NH, float* __restrict__ partial, int64_t P) {
+  constexpr int RB = W / 16, TILES = RB * RB, TPW = TILES / WAVES;
+  static_assert(TILES % WAVES == 0, "tiles must split evenly over the waves");
+  __shared__ __attribute__((aligned(16))) uint16_t sD[W * kTS];
+  __shared__ __attribute__((aligned(16))) uint16_t sA[W * kTS];
+  const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4, wave = threadIdx.x >> 6;
+  const int64_t base = (int64_t)blockIdx.x * CH;
+  floatx4 acc[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) acc[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+  float db = 0.0f;
+  constexpr int PIECES = 32 * W / 8;   // 16-byte pieces of one [32][W] slab
+  for (int64_t k0 = 0; k0 < CH; k0 += 32) {
+    __syncthreads();
+    for (int p = threadIdx.x; p < PIECES; p += blockDim.x) {
+      const int qq = p / (W / 8), n0 = (p % (W / 8)) * 8;
+      const int64_t qi = base + k0 + qq;
+      const bf16x8 dv = *reinterpret_cast<const bf16x8*>(Dl + qi * W + n0);
+      const bf16x8 av = *reinterpret_cast<const bf16x8*>(Aprev + qi * W + n0);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        sD[(n0 + i) * kTS + qq] = bits_of(dv[i]);
+        sA[(n0 + i) * kTS + qq] = bits_of(av[i]);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < W) {
+      const uint16_t* r = sD + threadIdx.x * kTS;
+      for (int i = 0; i < 32; ++i) db += (float)bf16_of(r[i]);
+    }
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int T = wave * TPW + t, no = T / RB, ko = T % RB;
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(sD + (16 * no + c) * kTS + 8 * grp);
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(sA + (16 * ko + c) * kTS + 8 * grp);
+      acc[t] = nb_mfma_bf16(a, b, acc[t]);
+    }
+  }
+  float* out = partial + (int64_t)blockIdx.x * P;
+  const int64_t wo = nb_w_off(l, in_dim, W);
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int T = wave * TPW + t, no = T / RB, ko = T % RB;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[wo + (int64_t)(16 * no + 4 * grp + r) * W + 16 * ko + c] = acc[t][r];
+  }
+  if (threadIdx.x < W) out[nb_b_off(l, in_dim, W, NH) + threadIdx.x] = db;
+}
+
+// dW_0 = sum_q D_0[q] x[q]^T, db_0 = sum_q D_0[q]  (one thread per neuron)
+__global__ __launch_bounds__(256) void k_tr_first_grad(const uint16_t* __restrict__ D0, const float* __restrict__ q,
+                                                       int64_t n, int64_t CH, int in_dim, int W, int NH,
+                                                       float* __restrict__ partial, int64_t P) {
+  const int64_t base = (int64_t)blockIdx.x * CH;
+  for (int nn = threadIdx.x; nn < W; nn += blockDim.x) {
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    float db = 0.0f;
+    const int64_t end = base + CH < n ? base + CH : n;
+    for (int64_t qi = base; qi < end; ++qi) {
+      const float d = (float)bf16_of(D0[qi * W + nn]);
+      db += d;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (k < in_dim) acc[k] = fmaf(d, q[qi * in_dim + k], acc[k]);
+    }
+    float* out = partial + (int64_t)blockIdx.x * P;
+    for (int k = 0; k < in_dim; ++k) out[(int64_t)nn * in_dim + k] = acc[k];
+    out[nb_b_off(0, in_dim, W, NH) + nn] = db;
+  }
+}
+
+// Raise a kernel's dynamic-LDS limit once per device.
+template <class K>
+nb_status allow_lds(K kernel, size_t bytes) {
+  static bool done[64] = {false};
+  int dev = 0;
+  NB_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64 || done[dev]) return NB_OK;
+  NB_HIP(hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  done[dev] = true;
+  return NB_OK;
+}
+
+template <int W>
+nb_status train_w(const nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha, float beta,
+                  float tau, const BF16TrainPlan& pl, hipStream_t s) {
+  using T = TrHidden<W>;
+  const int NH = b->n_hidden, in_dim = b->in_dim;
+  const int64_t P = b->n_params, CH = pl.chunk;
+  const unsigned grid = (unsigned)pl.n_wg;
+  const auto* pack = reinterpret_cast<const bf16x8*>(b->pack16);
+  const auto* packT = reinterpret_cast<const bf16x8*>(b->pack16t);
+  const float inv_n = (float)(1.0 / (double)n);
+  const size_t lds = T::lds_bytes();
+  uint16_t* A = b->tr_act;                                   // A_l at A + l * Bp * W
+  const int64_t stride = pl.padded * W;
+  uint16_t* D[2] = {b->tr_grad, b->tr_grad + stride};
+
+  k_tr_first<W><<<grid, 256, 0, s>>>(q, n, in_dim, CH, pack, b->theta, A);
+  NB_LAUNCHED();
+  NB_TRY(allow_lds(k_tr_hidden<W, false>, lds));
+  NB_TRY(allow_lds(k_tr_hidden<W, true>, lds));
+  NB_TRY(allow_lds(k_tr_data<W>, (size_t)T::FH * 64 * 16));
+  for (int l = 1; l < NH - 1; ++l) {
+    k_tr_hidden<W, false><<<grid, 256, lds, s>>>(A + (l - 1) * stride, n, CH, l, in_dim, NH, pack, b->theta,
+                                                 A + l * stride, nullptr, 0, 0, 0, tau, nullptr, P, nullptr);
+    NB_LAUNCHED();
+  }
+  // head: layer NH-1, output layer, loss, D_{NH-1}
+  int cur = 0;
+  k_tr_hidden<W, true><<<grid, 256, lds, s>>>(A + (NH - 2) * stride, n, CH, NH - 1, in_dim, NH, pack, b->theta,
+                                              D[cur], y, alpha, beta, inv_n, tau, b->partial, P, b->aux);
+  NB_LAUNCHED();
+  constexpr int WW = W >= 256 ? 8 : 4;
+  for (int l = NH - 1; l >= 1; --l) {
+    k_tr_weight<W, WW><<<grid, WW * 64, 0, s>>>(D[cur], A + (l - 1) * stride, CH, l, in_dim, NH, b->partial, P);
+    NB_LAUNCHED();
+    k_tr_data<W><<<grid, 256, (size_t)T::FH * 64 * 16, s>>>(D[cur], A + (l - 1) * stride, CH, l, packT, D[cur ^ 1]);
+    NB_LAUNCHED();
+    cur ^= 1;
+  }
+  k_tr_first_grad<<<grid, 256, 0, s>>>(D[cur], q, n, CH, in_dim, W, NH, b->partial, P);
+  NB_LAUNCHED();
+  return NB_OK;
+}
+
+}  // namespace
+
+BF16TrainPlan bf16_train_plan(int64_t n) {
+  BF16TrainPlan p;
+  p.n_wg = (int)std::min<int64_t>(256, (n + 63) / 64);
+  const int64_t per = (n + p.n_wg - 1) / p.n_wg;
+  p.chunk = (per + 63) / 64 * 64;
+  p.n_wg = (int)((n + p.chunk - 1) / p.chunk);
+  p.padded = p.chunk * p.n_wg;
+  return p;
+}
+
+bool bf16_train_supported(int in_dim, int n_hidden, int width) {
+  return in_dim >= 1 && in_dim <= 8 && n_hidden >= 2 && n_hidden <= 8 &&
+         (width == 32 || width == 64 || width == 128);
+}
+
+int64_t bf16_packt_elems(int n_hidden, int width) {
+  const int RB = width / 16, KS = width / 32;
+  return (int64_t)(n_hidden - 1) * RB * KS * 64 * 8;
+}
+
+nb_status bf16_pack_t(const nb_bound* b, hipStream_t s) {
+  const int64_t total = b->pack16t_elems;
+  if (total == 0) return NB_OK;
+  k_pack_bf16_t<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(b->theta, b->in_dim, b->width, b->n_hidden,
+                                                                b->pack16t, total);
+  NB_LAUNCHED();
+  return NB_OK;
+}
+
+nb_status bf16_train_partials(const nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha,
+                              float beta, float tau, const BF16TrainPlan& plan, hipStream_t s) {
+  switch (b->width) {
+    case 32: return train_w<32>(b, q, y, n, alpha, beta, tau, plan, s);
+    case 64: return train_w<64>(b, q, y, n, alpha, beta, tau, plan, s);
+    case 128: return train_w<128>(b, q, y, n, alpha, beta, tau, plan, s);
+    default: break;
+  }
+  nb_set_error("bfloat16 training has no kernel for width %d", b->width);
+  return NB_ERR_UNSUPPORTED;
+}

@@ -26,6 +26,7 @@
 #include <algorithm>
 
 #include "nb_internal.h"
+#include "nb_mlp.h"
 
 namespace {
 
@@ -53,14 +54,6 @@ struct Net {
   static constexpr int NPACK = NFWD + (NH - 1) * FH;  // + transposed copies
 };
 
-// Offsets into theta (linear-layer layout), runtime in_dim.
-__host__ __device__ inline int64_t w_off(int l, int in_dim, int W) {
-  return l == 0 ? 0 : (int64_t)W * in_dim + W + (int64_t)(l - 1) * ((int64_t)W * W + W);
-}
-__host__ __device__ inline int64_t b_off(int l, int in_dim, int W, int NH) {
-  return w_off(l, in_dim, W) + (int64_t)(l == 0 ? in_dim : W) * (l == NH ? 1 : W);
-}
-
 // ------------------------------------------------------------------ packing
 
 // pack[f*64 + lane]:
@@ -87,7 +80,7 @@ __global__ void k_pack(const float* __restrict__ theta, int in_dim, int W, int N
     const int t = f - (tr ? NFWD : F1);
     const int l = 1 + t / FH, rem = t % FH;
     const int mo = rem / (RB * 4), mi = (rem / 4) % RB, r = rem % 4;
-    const float* Wl = theta + w_off(l, in_dim, W);
+    const float* Wl = theta + nb_w_off(l, in_dim, W);
     v = tr ? Wl[(int64_t)(16 * mi + 4 * g + r) * W + 16 * mo + c] : Wl[(int64_t)(16 * mo + c) * W + 16 * mi + 4 * g + r];
   }
   pack[idx] = v;
@@ -115,8 +108,8 @@ __global__ __launch_bounds__(256) void k_fwd(const float* __restrict__ q, int64_
 #pragma unroll
   for (int mo = 0; mo < RB; ++mo)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) wo[mo * 4 + r] = theta[w_off(NH, in_dim, W) + 16 * mo + 4 * grp + r];
-  const float bo = theta[b_off(NH, in_dim, W, NH)];
+    for (int r = 0; r < 4; ++r) wo[mo * 4 + r] = theta[nb_w_off(NH, in_dim, W) + 16 * mo + 4 * grp + r];
+  const float bo = theta[nb_b_off(NH, in_dim, W, NH)];
 
   unsigned cnt[4] = {0u, 0u, 0u, 0u};
   const int64_t nblk = (n + 15) / 16;
@@ -126,7 +119,7 @@ __global__ __launch_bounds__(256) void k_fwd(const float* __restrict__ q, int64_
     const bool valid = qi < n;
     float a[RB * 4];
     {
-      const float* b0 = theta + b_off(0, in_dim, W, NH);
+      const float* b0 = theta + nb_b_off(0, in_dim, W, NH);
       floatx4 acc[RB];
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo)
@@ -146,7 +139,7 @@ __global__ __launch_bounds__(256) void k_fwd(const float* __restrict__ q, int64_
     }
 #pragma unroll
     for (int l = 1; l < NH; ++l) {
-      const float* bl = theta + b_off(l, in_dim, W, NH);
+      const float* bl = theta + nb_b_off(l, in_dim, W, NH);
       floatx4 acc[RB];
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo)
@@ -198,7 +191,7 @@ constexpr int kLDT = 17;  // row stride of the per-wave transpose tiles (16 quer
 template <int KIN, int W, int NH>
 struct TrainLds {
   using N = Net<KIN, W, NH>;
-  __host__ __device__ static int64_t P(int in_dim) { return b_off(NH, in_dim, W, NH) + 1; }
+  __host__ __device__ static int64_t P(int in_dim) { return nb_b_off(NH, in_dim, W, NH) + 1; }
   static constexpr int kTile = W * kLDT;                 // one [W][17] tile
   static constexpr int kBias = NH * W + W + 1;           // hidden biases, output weights, output bias
   static int64_t floats(int in_dim) {
@@ -227,9 +220,9 @@ __global__ __launch_bounds__(256, 1) void k_train(const float* __restrict__ q, c
   for (int i = threadIdx.x; i < N::NPACK * 64; i += blockDim.x) spack[i] = pack[i];
   for (int i = threadIdx.x; i < NH * W; i += blockDim.x) {
     const int l = i / W, j = i % W;
-    sbias[i] = theta[b_off(l, in_dim, W, NH) + j];
+    sbias[i] = theta[nb_b_off(l, in_dim, W, NH) + j];
   }
-  for (int i = threadIdx.x; i < W + 1; i += blockDim.x) sbias[NH * W + i] = theta[w_off(NH, in_dim, W) + i];
+  for (int i = threadIdx.x; i < W + 1; i += blockDim.x) sbias[NH * W + i] = theta[nb_w_off(NH, in_dim, W) + i];
   __syncthreads();
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4;
@@ -444,7 +437,7 @@ __global__ __launch_bounds__(256, 1) void k_train(const float* __restrict__ q, c
           for (int ko = 0; ko < RB; ++ko)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-              put(w_off(l, in_dim, W) + (int64_t)(16 * no + 4 * grp + r) * W + 16 * ko + c, gWh[l - 1][no][ko][r]);
+              put(nb_w_off(l, in_dim, W) + (int64_t)(16 * no + 4 * grp + r) * W + 16 * ko + c, gWh[l - 1][no][ko][r]);
       if (c == 0) {
 #pragma unroll
         for (int mo = 0; mo < RB; ++mo)
@@ -452,12 +445,12 @@ __global__ __launch_bounds__(256, 1) void k_train(const float* __restrict__ q, c
           for (int r = 0; r < 4; ++r) {
             const int nrow = 16 * mo + 4 * grp + r;
 #pragma unroll
-            for (int l = 0; l < NH; ++l) put(b_off(l, in_dim, W, NH) + nrow, gb[l][mo * 4 + r]);
-            put(w_off(NH, in_dim, W) + nrow, gwo[mo * 4 + r]);
+            for (int l = 0; l < NH; ++l) put(nb_b_off(l, in_dim, W, NH) + nrow, gb[l][mo * 4 + r]);
+            put(nb_w_off(NH, in_dim, W) + nrow, gwo[mo * 4 + r]);
           }
       }
       if (lane == 0) {
-        put(b_off(NH, in_dim, W, NH), gbo);
+        put(nb_b_off(NH, in_dim, W, NH), gbo);
         saux[w * 8 + 0] = lsum;
         for (int i = 0; i < 4; ++i) saux[w * 8 + 1 + i] = __uint_as_float(cnt[i]);
       }
@@ -482,24 +475,12 @@ __global__ __launch_bounds__(256, 1) void k_train(const float* __restrict__ q, c
 
 constexpr int kMaxWG = 256;
 
-int cu_count() {
-  static int cus[64] = {0};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (!cus[dev]) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
-    cus[dev] = v;
-  }
-  return cus[dev];
-}
-
 template <int KIN, int W, int NH>
 nb_status fwd_launch(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
                      const uint8_t* g, unsigned long long* counts, hipStream_t s) {
   const int64_t nblk = (n + 15) / 16;
   const int64_t want = (nblk + 3) / 4;
-  const int64_t cap = (int64_t)cu_count() * 2;
+  const int64_t cap = (int64_t)nb_cu_count() * 2;
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min(want, cap));
   k_fwd<KIN, W, NH><<<grid, 256, 0, s>>>(q, n, b->in_dim, b->pack, b->theta, tau, logits, h, g, counts);
   NB_LAUNCHED();

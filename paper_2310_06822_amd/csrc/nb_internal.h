@@ -32,6 +32,12 @@ void nb_set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
 // Launch check: hipGetLastError after an async launch.
 #define NB_LAUNCHED() NB_HIP(hipGetLastError())
 
+#define NB_TRY(expr)                  \
+  do {                                \
+    nb_status nb_s_ = (expr);         \
+    if (nb_s_ != NB_OK) return nb_s_; \
+  } while (0)
+
 // ------------------------------------------------------------- the handles
 
 enum IndicatorType { IND_DISCS2D = 0, IND_VOXELS = 1, IND_METABALLS4D = 2 };
@@ -75,6 +81,12 @@ struct nb_bound {
   int batch_cap_dim = 0;
   int32_t* cascade_idx = nullptr;  // positive-query index list of nb_cascade
   int64_t cascade_cap = 0;
+  // bfloat16 training: transposed weight fragments, activations and gradients in HBM
+  uint16_t* pack16t = nullptr;
+  int64_t pack16t_elems = 0;
+  uint16_t* tr_act = nullptr;      // (n_hidden - 1) x [padded batch][width]
+  uint16_t* tr_grad = nullptr;     // 2 x [padded batch][width]
+  int64_t tr_cap = 0;              // padded batch the two above hold
 };
 
 // ------------------------------------------------------- kernel launchers
@@ -111,6 +123,19 @@ nb_status bf16_pack(const nb_bound* b, hipStream_t s);
 int bf16_variants();
 nb_status bf16_forward(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
                        const uint8_t* g, unsigned long long* counts, hipStream_t s);
+
+// mlp_bf16_train.hip
+struct BF16TrainPlan {
+  int n_wg = 0;          // workgroups = batch chunks
+  int64_t chunk = 0;     // queries per chunk (multiple of 64)
+  int64_t padded = 0;    // n_wg * chunk
+};
+BF16TrainPlan bf16_train_plan(int64_t n);
+bool bf16_train_supported(int in_dim, int n_hidden, int width);
+int64_t bf16_packt_elems(int n_hidden, int width);
+nb_status bf16_pack_t(const nb_bound* b, hipStream_t s);
+nb_status bf16_train_partials(const nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha,
+                              float beta, float tau, const BF16TrainPlan& plan, hipStream_t s);
 
 // optim.hip
 // Reduce partials over n_wg workgroups: writes grad (if non-null), loss and

@@ -367,3 +367,66 @@ def test_autograd_bound_loss():
     opt = torch.optim.Adam([theta], lr=1e-3)
     opt.step()
     assert np.max(np.abs(host(theta.detach()) - theta0)) > 0
+
+
+# ------------------------------------------------------- bfloat16 training
+
+BF16_TRAIN_SHAPES = [(6, 128, 4), (4, 64, 3), (6, 32, 2), (3, 128, 2), (8, 64, 5)]
+
+
+def _bf16_grad_check(in_dim, width, nh, q, y, alpha, beta):
+    widths = [width] * nh
+    theta = synth.init_params(100 + width + nh, in_dim, widths)
+    b = nb.Bound(in_dim, nh, width, nb.BF16)
+    b.set_params(theta)
+    grad = torch.empty(b.n_params, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    cnt = torch.empty(4, dtype=torch.int64, device="cuda")
+    nb.nb_bound_loss_grad(b.handle, cuda(q), cuda(y), alpha, beta, grad, loss, cnt)
+    z = mlp.forward(theta, in_dim, widths, q, bf16=True)
+    gref = mlp.backward(theta, in_dim, widths, q, L.dloss_dz(z, y, alpha, beta), bf16=True)
+    lref = L.loss(z, y, alpha, beta)
+    assert abs(host(loss)[0] - lref) <= 1e-3 * lref
+    g = host(grad).astype(np.float64)
+    worst = 0.0
+    for (Wg, bg), (Wr, br) in zip(mlp.unpack(g, in_dim, widths), mlp.unpack(gref, in_dim, widths)):
+        worst = max(worst, _rel_frob(Wg, Wr), _rel_frob(bg, br))
+    assert worst <= 1e-2, worst
+    return b, g
+
+
+@pytest.mark.parametrize("in_dim,width,nh", BF16_TRAIN_SHAPES)
+@pytest.mark.parametrize("n", [7, 4099])
+def test_loss_grad_bf16_parity(in_dim, width, nh, n):
+    q = synth.points(101, n, in_dim)
+    y = (synth.points(102, n, 1)[:, 0] > 0.2).astype(np.uint8)
+    _bf16_grad_check(in_dim, width, nh, q, y, 9.0, 1.5)
+
+
+def test_loss_grad_bf16_deterministic():
+    q = synth.points(103, 70001, 6)
+    y = (synth.points(104, 70001, 1)[:, 0] > 0).astype(np.uint8)
+    b, g1 = _bf16_grad_check(6, 128, 4, q, y, 3.0, 1.0)
+    grad = torch.empty(b.n_params, dtype=torch.float32, device="cuda")
+    nb.nb_bound_loss_grad(b.handle, cuda(q), cuda(y), 3.0, 1.0, grad)
+    assert np.array_equal(bits(host(grad)), bits(g1.astype(np.float32)))
+
+
+def test_train_steps_bf16_rays(c2_grid):
+    _, _, grid = c2_grid
+    ind = nb.Indicator.voxels(cuda(grid), 128)
+    widths = [64] * 3
+    theta0 = synth.init_params(4002, 6, widths)
+    steps, batch, seed = 5, 2048, 2002
+    b = nb.Bound(6, 3, 64, nb.BF16)
+    b.set_params(theta0)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    from oracle import train as T
+    th, hist = T.train(lambda q: I.voxel_rays(q, grid, 128), "ray", 3, 6, widths, theta0, seed, steps, batch,
+                       bf16=True)
+    for t in range(steps):
+        nb.nb_bound_train_step(b.handle, ind.handle, nb.RAY, seed, t, batch, T.alpha_ramp(t, steps), 1.0, 1e-3,
+                               loss=loss)
+        assert abs(host(loss)[0] - hist[t][0]) <= 2e-3 * abs(hist[t][0]), t
+    d_gpu = host(b.params()).astype(np.float64) - theta0
+    assert _rel_frob(d_gpu, th - theta0) <= 5e-2
