@@ -1,23 +1,29 @@
 """Throughput of the Neural Bounding hot path on one GPU.
 
-Workload (default): 3-D point queries against a 128^3 voxel grid of 16 seeded
-metaballs; bound 3 -> 64^3 -> 1 (ReLU, float32 on the matrix cores); trained
-for 5000 Adam steps on batches of 2^16 regions drawn and labelled on the
-device, with the FN weight ramped 1 -> 100; evaluated on 2^24 held-out
-queries (disjoint seed).
+Default workload (`voxel3d_point`): 3-D point queries against a 128^3 voxel
+grid of 16 seeded metaballs; bound 3 -> 64^3 -> 1 (ReLU, float32 on the
+matrix cores); trained on the device (batches of 2^16 regions drawn and
+labelled per step; FN weight ramped 1 -> 100 over 5000 steps, then the
+paper's step-wise schedule until a validation set shows FN = 0); evaluated
+on 2^24 held-out queries (disjoint seed).
 
-A timed step is one pass of the deployed bound over the 2^24 held-out queries
-(forward + decision, all resident in HBM).  Reported beside it: training
+A timed step is one pass of the trained bound over the 2^24 held-out queries
+(forward + decision, inputs resident in HBM).  Reported beside it: training
 samples/s over the whole training run, the exact indicator test on the same
-queries and GPU, FN / FP on the held-out set, the roofline of the forward
-kernel, and the CPU oracle timed on a bounded sample.
+queries and GPU, the cascade (bound, then exact test on the positives), FN /
+FP on the held-out set, the roofline of the forward kernel, and the CPU
+oracle timed on a bounded sample.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--also]
+
+--workload picks another workload (voxel3d_ray: 6 -> 128^4 bfloat16 bound
+over rays); --also appends the other workloads' measurements under "also".
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,8 +34,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP32_MFMA_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
-HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}   # MI355X dense matrix peaks (FP32, BF16)
 
 
 def log(msg: str):
@@ -39,7 +44,6 @@ def log(msg: str):
 def committed_traffic(name: str, source: str):
     """HBM bytes per launch from a committed rocprofv3 counter summary, or None
     if the kernel source has changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -57,7 +61,7 @@ def committed_traffic(name: str, source: str):
         return None
 
 
-def cpu_baseline(theta, in_dim, widths, target_s: float = 10.0):
+def cpu_baseline(W, theta, seconds: float = 10.0):
     """Oracle forward + decision on a bounded sample of held-out queries."""
     import synth
     from oracle import loss as L, mlp
@@ -66,19 +70,139 @@ def cpu_baseline(theta, in_dim, widths, target_s: float = 10.0):
         cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count() or 1
-    chunk = 1 << 16
-    q = synth.points(3001, chunk, in_dim)
+    widths = [W.width] * W.n_hidden
+    bf16 = W.precision == "bf16"
+    chunk = 1 << 14
+    q = synth.points(W.seeds["eval"], chunk, W.in_dim)
     t0 = time.perf_counter()
-    L.decide(mlp.forward(theta, in_dim, widths, q))
+    L.decide(mlp.forward(theta, W.in_dim, widths, q, bf16=bf16))
     dt = time.perf_counter() - t0
-    reps = max(1, int(target_s / max(dt, 1e-3)))
+    reps = max(1, int(seconds / max(dt, 1e-3)))
     t0 = time.perf_counter()
     for _ in range(reps):
-        L.decide(mlp.forward(theta, in_dim, widths, q))
+        L.decide(mlp.forward(theta, W.in_dim, widths, q, bf16=bf16))
     dt = time.perf_counter() - t0
     return {"value": reps * chunk / dt, "unit": "bound queries/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{reps} x {chunk} held-out queries, float64 numpy forward + decision, "
-                      f"{dt:.1f} s on {os.cpu_count()} host cores"}
+            "sample": f"{reps} x {chunk} queries of the {W.name} workload, float64 numpy forward"
+                      f"{' (bfloat16 rounding model)' if bf16 else ''} + decision, {dt:.1f} s, "
+                      f"{os.cpu_count()} host cores"}
+
+
+def build_indicator(W, nb, synth):
+    sc = W.scene
+    if sc["type"] == "discs":
+        return nb.Indicator.discs2d(synth.discs2d(W.seeds["scene"], k=sc["k"]))
+    if sc["type"] == "metaball_voxels":
+        seed = 1000 + sc.get("seed_of", W.index)
+        c, r = synth.metaballs3d(seed, k=sc["k"], rlo=sc["rlo"], rhi=sc["rhi"])
+        return nb.Indicator.metaball_voxels(c, r, sc["n"])
+    if sc["type"] == "metaballs4d":
+        a, b, r = synth.metaballs4d(W.seeds["scene"], k=sc["k"], rlo=sc["rlo"], rhi=sc["rhi"])
+        return nb.Indicator.metaballs4d(a, b, r)
+    raise ValueError(sc["type"])
+
+
+def timed(fn, steps, warmup, torch):
+    """(mean ms per call from HIP events around each call, wall seconds)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return float(np.mean([a.elapsed_time(b) for a, b in ev])), wall
+
+
+def run_workload(W, args, with_cpu: bool):
+    import torch
+
+    import paper_2310_06822_amd as nb
+    import synth
+    from paper_2310_06822_amd import autotune, trainer
+
+    dev = "cuda"
+    seeds = W.seeds
+    widths = [W.width] * W.n_hidden
+    kind = nb.KINDS[W.kind]
+    prec = nb.BF16 if W.precision == "bf16" else nb.F32
+    n_eval = args.eval_n if args.eval_n is not None else W.eval_n
+
+    ind = build_indicator(W, nb, synth)
+    bound = nb.Bound(W.in_dim, W.n_hidden, W.width, prec)
+    theta0 = synth.init_params(seeds["init"], W.in_dim, widths)
+
+    # ---- training (Alg. 1 on the device): ramp, then the step-wise schedule
+    sched = W.schedule(**({"steps": args.train_steps} if args.train_steps is not None else {}))
+    if args.no_adapt:
+        sched.max_iters = 0
+    bound.set_params(theta0)
+    nb.nb_bound_train_step(bound.handle, ind.handle, kind, seeds["train"], 0, W.batch, 1.0)   # work space
+    bound.set_params(theta0)
+    res = trainer.train(bound, ind, W.kind, seeds["train"], sched, val_seed=seeds["val"])
+    log(f"[{W.name}] train: {res.steps} steps x {W.batch} in {res.seconds:.2f} s -> {res.samples_per_s:.3e} "
+        f"samples/s; alpha final {res.alpha_final:g}, schedule iterations {res.iters}, converged {res.converged}")
+
+    # ---- held-out queries and exact answers
+    q = torch.empty((n_eval, W.in_dim), dtype=torch.float32, device=dev)
+    nb.nb_sample_queries(kind, W.dim, seeds["eval"], 0, q)
+    g = torch.empty(n_eval, dtype=torch.uint8, device=dev)
+    ind.query(W.kind, q, g)
+    variant = autotune.tune(bound, q) if prec == nb.BF16 else 0
+    counts = bound.counts(q, g)
+    torch.cuda.synchronize()
+    tp, fp, tn, fn = counts.tolist()
+    log(f"[{W.name}] held-out {n_eval}: TP {tp} FP {fp} TN {tn} FN {fn} (forward variant {variant})")
+
+    # ---- timed: bound forward + decision over the held-out set
+    h = torch.empty(n_eval, dtype=torch.uint8, device=dev)
+    kern_ms, wall = timed(lambda: nb.nb_bound_forward(bound.handle, q, nb.EPS_OUT, h=h), args.steps, args.warmup,
+                          torch)
+    value = n_eval * args.steps / wall
+
+    # ---- exact test and cascade on the same queries, same GPU
+    exact_ms, _ = timed(lambda: ind.query(W.kind, q, g), args.steps, args.warmup, torch)
+    ans = torch.empty(n_eval, dtype=torch.uint8, device=dev)
+    n_exact = torch.empty(1, dtype=torch.int64, device=dev)
+    casc_ms, _ = timed(lambda: nb.nb_cascade(bound.handle, ind.handle, kind, q, ans, n_exact), args.steps,
+                       args.warmup, torch)
+    casc_ok = bool(torch.equal(ans, g))
+
+    macs = W.in_dim * W.width + (W.n_hidden - 1) * W.width * W.width + W.width
+    flop_per_q = 2 * macs
+    peak = PEAK_TFLOPS[W.precision]
+    achieved = flop_per_q * n_eval / (kern_ms / 1e3) / 1e12
+    src = "paper_2310_06822_amd/csrc/" + ("mlp_bf16.hip" if prec == nb.BF16 else "mlp_f32.hip")
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4),
+                "traffic": committed_traffic(f"{W.name}_forward_traffic.txt", src),
+                "kernel": f"{'k_fwd_bf16' if prec == nb.BF16 else 'k_fwd'} ({W.precision} MLP forward + decision)",
+                "flop_per_query": flop_per_q, "avg_launch_ms": round(kern_ms, 4)}
+    out = {
+        "value": value, "ms_per_step": wall * 1e3 / args.steps, "dtype": W.precision,
+        "config": {"workload": W.name, "query": W.kind, "queries_per_step": n_eval,
+                   "net": f"{W.in_dim}x{W.width}^{W.n_hidden}x1 relu {W.precision}",
+                   "train_steps": res.steps, "train_batch": W.batch, "scene": W.scene},
+        "train_samples_per_s": res.samples_per_s,
+        "train": {"steps": res.steps, "batch": W.batch, "seconds": res.seconds, "alpha_final": res.alpha_final,
+                  "schedule_iterations": res.iters, "validation_fn_zero": res.converged,
+                  "validation_n": sched.val_n if sched.max_iters else 0,
+                  "validation_fn_history": res.val_fn_history[-20:]},
+        "exact_queries_per_s": n_eval / (exact_ms / 1e3),
+        "bound_speedup_vs_exact": exact_ms / kern_ms,
+        "cascade": {"queries_per_s": n_eval / (casc_ms / 1e3), "exact_tests": int(n_exact.item()),
+                    "answer_equals_exact": casc_ok},
+        "heldout": {"n": n_eval, "tp": tp, "fp": fp, "tn": tn, "fn": fn, "fp_rate": fp / n_eval},
+        "fn_zero": fn == 0,
+        "roofline": roofline,
+    }
+    if with_cpu:
+        out["cpu_baseline"] = cpu_baseline(W, bound.params().cpu().numpy())
+    return out
 
 
 def main():
@@ -86,6 +210,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="voxel3d_point")
+    ap.add_argument("--also", action="store_true", help="also measure the other workloads")
     ap.add_argument("--train-steps", type=int, default=None)
     ap.add_argument("--eval-n", type=int, default=None)
     ap.add_argument("--no-adapt", action="store_true", help="ramp phase only (no step-wise continuation)")
@@ -99,122 +225,32 @@ def main():
         sys.exit(2)
 
     import torch
-
-    import paper_2310_06822_amd as nb
-    import synth
-    from paper_2310_06822_amd.configs import VOXEL3D_POINT as W
+    from paper_2310_06822_amd.configs import WORKLOADS
 
     torch.cuda.set_device(0)
-    dev = "cuda"
-    n_eval = args.eval_n if args.eval_n is not None else W.eval_n
-    seeds = W.seeds
-    widths = [W.width] * W.n_hidden
-
-    # scene: metaball field voxelised on the GPU
-    c, r = synth.metaballs3d(seeds["scene"], k=W.scene["k"], rlo=W.scene["rlo"], rhi=W.scene["rhi"])
-    gn = W.scene["n"]
-    grid = torch.empty(gn ** 3, dtype=torch.uint8, device=dev)
-    nb.nb_voxelize_metaballs(c, r, 1.0, gn, grid)
-    ind = nb.Indicator.voxels(grid, gn)
-    log(f"scene: {gn}^3 grid, occupancy {grid.float().mean().item():.4f}")
-
-    bound = nb.Bound(W.in_dim, W.n_hidden, W.width)
-    theta0 = synth.init_params(seeds["init"], W.in_dim, widths)
-    bound.set_params(theta0)
-
-    # ---- training (Alg. 1 on the device): ramp, then the step-wise schedule
-    from paper_2310_06822_amd import trainer
-    sched = W.schedule(**({"steps": args.train_steps} if args.train_steps is not None else {}))
-    if args.no_adapt:
-        sched.max_iters = 0
-    nb.nb_bound_train_step(bound.handle, ind.handle, nb.POINT, seeds["train"], 0, W.batch, 1.0)   # work space
-    bound.set_params(theta0)
-    res = trainer.train(bound, ind, W.kind, seeds["train"], sched, val_seed=seeds["val"], log=None)
-    train_sps = res.samples_per_s
-    log(f"train: {res.steps} steps x {W.batch} in {res.seconds:.2f} s -> {train_sps:.3e} samples/s; "
-        f"alpha final {res.alpha_final:g}, schedule iterations {res.iters}, converged {res.converged}")
-
-    # ---- held-out queries and exact answers
-    q = torch.empty((n_eval, W.in_dim), dtype=torch.float32, device=dev)
-    nb.nb_sample_queries(nb.POINT, W.dim, seeds["eval"], 0, q)
-    g = torch.empty(n_eval, dtype=torch.uint8, device=dev)
-    ind.query("point", q, g)
-    counts = bound.counts(q, g)
-    torch.cuda.synchronize()
-    tp, fp, tn, fn = counts.tolist()
-    log(f"held-out {n_eval}: TP {tp} FP {fp} TN {tn} FN {fn}")
-
-    # ---- timed: bound forward + decision over the held-out set
-    h = torch.empty(n_eval, dtype=torch.uint8, device=dev)
-
-    def step():
-        nb.nb_bound_forward(bound.handle, q, nb.EPS_OUT, h=h)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    t0 = time.perf_counter()
-    for a, b in ev:
-        a.record()
-        step()
-        b.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kern_ms = [a.elapsed_time(b) for a, b in ev]
-    ms_step = wall * 1e3 / args.steps
-    avg_kern = float(np.mean(kern_ms))
-    value = n_eval * args.steps / wall
-
-    # ---- exact test on the same queries, same GPU
-    for _ in range(args.warmup):
-        ind.query("point", q, g)
-    torch.cuda.synchronize()
-    x0, x1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    x0.record()
-    for _ in range(args.steps):
-        ind.query("point", q, g)
-    x1.record()
-    torch.cuda.synchronize()
-    exact_ms = x0.elapsed_time(x1) / args.steps
-    exact_qps = n_eval / (exact_ms / 1e3)
-
-    macs = W.in_dim * W.width + (W.n_hidden - 1) * W.width * W.width + W.width
-    flop_per_q = 2 * macs
-    achieved = flop_per_q * n_eval / (avg_kern / 1e3) / 1e12
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
-                "traffic": committed_traffic("k_fwd_f32_voxel3d_point_traffic.txt",
-                                             "paper_2310_06822_amd/csrc/mlp_f32.hip"),
-                "kernel": "k_fwd<1,64,3> (float32 MLP forward + decision)",
-                "flop_per_query": flop_per_q, "avg_launch_ms": round(avg_kern, 4)}
-
-    out = {
-        "metric": "bound queries/s & train samples/s at FN=0 vs exact indicator test, same GPU",
-        "value": value, "unit": "bound queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": W.name, "queries_per_step": n_eval, "grid": gn, "metaballs": W.scene["k"],
-                   "net": f"{W.in_dim}x{W.width}^{W.n_hidden}x1 relu", "train_steps": res.steps, "train_batch": W.batch},
-        "train_samples_per_s": train_sps,
-        "train": {"steps": res.steps, "batch": W.batch, "seconds": res.seconds, "alpha_final": res.alpha_final,
-                  "schedule_iterations": res.iters, "validation_fn_zero": res.converged,
-                  "validation_n": sched.val_n if sched.max_iters else 0},
-        "exact_queries_per_s": exact_qps,
-        "bound_vs_exact": value / exact_qps,
-        "heldout": {"n": n_eval, "tp": tp, "fp": fp, "tn": tn, "fn": fn, "fp_rate": fp / n_eval},
-        "fn_zero": fn == 0,
-        "roofline": roofline,
-    }
+    W = WORKLOADS[args.workload]
+    r = run_workload(W, args, with_cpu=not args.no_cpu)
+    out = {"metric": "bound queries/s & train samples/s at FN=0 vs exact indicator test, same GPU",
+           "value": r.pop("value"), "unit": "bound queries/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": r.pop("ms_per_step"), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": r.pop("dtype"), "data": "synthetic",
+           "config": r.pop("config")}
+    out.update(r)
+    if args.also:
+        out["also"] = {}
+        for name, W2 in WORKLOADS.items():
+            if name == args.workload or not W2.bench_also:
+                continue
+            r2 = run_workload(W2, args, with_cpu=False)
+            r2["bound_queries_per_s"] = r2.pop("value")
+            out["also"][name] = r2
     if args.copy_calibration:
-        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev).fill_(1)
+        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
         dst = torch.empty_like(src)
         for _ in range(2):
             dst.copy_(src)
         torch.cuda.synchronize()
         log("copy calibration: 2 x 256 MiB device-to-device copies")
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(bound.params().cpu().numpy(), W.in_dim, widths)
     print(json.dumps(out), flush=True)
 
 

@@ -35,6 +35,7 @@ class Workload:
     adapt_k: int = 250
     adapt_inc: float = 50.0
     adapt_iters: int = 400
+    bench_also: bool = False   # measured by `bench.py --also`
 
     @property
     def seeds(self):
@@ -56,7 +57,7 @@ VOXEL3D_POINT = Workload("voxel3d_point", 1, "point", 3, 3, 64, 3, "f32",
                          train_steps=5000, batch=1 << 16, eval_n=1 << 24)
 VOXEL3D_RAY = Workload("voxel3d_ray", 2, "ray", 3, 6, 128, 4, "bf16",
                        scene={"type": "metaball_voxels", "k": 16, "n": 128, "rlo": 0.05, "rhi": 0.25, "seed_of": 1},
-                       train_steps=5000, batch=1 << 18, eval_n=1 << 24)
+                       train_steps=5000, batch=1 << 18, eval_n=1 << 24, bench_also=True)
 METABALL4D_POINT = Workload("metaball4d_point", 4, "point", 4, 4, 256, 6, "bf16",
                             scene={"type": "metaballs4d", "k": 24, "rlo": 0.05, "rhi": 0.2},
                             train_steps=2000, batch=1 << 20, eval_n=1 << 24)

@@ -83,13 +83,41 @@ __device__ __forceinline__ uint8_t metaballs4d_at(const float* __restrict__ row,
 
 // --------------------------------------------------------------------- rays
 
+// Sample index range [j0, j1] that can reach the cube [-1, 1]^3: the slab
+// interval of the segment o + t d, widened by one sample on each side and by
+// 1e-4 in t, so every sample inside the cube is kept (float rounding of the
+// sample positions moves them by far less than the 4/255 sample spacing).
+// Returns false if no sample can be inside.
+__device__ __forceinline__ bool ray_sample_range(const float* __restrict__ row, int& j0, int& j1) {
+  float tlo = 0.0f, thi = 4.0f;
+  for (int a = 0; a < 3; ++a) {
+    const float o = row[a], d = row[3 + a];
+    if (fabsf(d) < 1e-30f) {
+      if (!(o >= -1.0f && o <= 1.0f)) return false;   // parallel to the slab and outside (or NaN)
+      continue;
+    }
+    const float t1 = (-1.0f - o) / d, t2 = (1.0f - o) / d;
+    tlo = fmaxf(tlo, fminf(t1, t2));
+    thi = fminf(thi, fmaxf(t1, t2));
+  }
+  if (!(tlo <= thi + 1e-4f)) return false;
+  const float scale = 255.0f / 4.0f;
+  j0 = max(0, (int)floorf((tlo - 1e-4f) * scale) - 1);
+  j1 = min(255, (int)ceilf((thi + 1e-4f) * scale) + 1);
+  return j0 <= j1;
+}
+
 // g = max_j f(o + t_j d) over the sample table; stops at the first hit.
+// Only samples in the clipped range are evaluated; the others lie outside
+// the cube, where f = 0.
 __device__ __forceinline__ uint8_t voxel_ray_at(const float* __restrict__ row, const uint8_t* __restrict__ grid, int gn,
                                                 const float* __restrict__ ray_t) {
   const float ox = row[0], oy = row[1], oz = row[2], dx = row[3], dy = row[4], dz = row[5];
+  int j0, j1;
+  if (!ray_sample_range(row, j0, j1)) return 0;
   const float half_n = (float)gn * 0.5f;
   uint8_t hit = 0;
-  for (int j = 0; j < 256 && !hit; ++j) {
+  for (int j = j0; j <= j1 && !hit; ++j) {
     const float t = ray_t[j];
     hit = voxel_at(grid, gn, half_n, ox + t * dx, oy + t * dy, oz + t * dz);
   }
@@ -164,18 +192,42 @@ __global__ void k_exact(IndView v, const float* __restrict__ q, int64_t n, uint8
 
 // ------------------------------------------------------------- cascade
 
-// Indices of the queries the bound calls positive (order within the list is
+// Indices of the queries the bound calls positive.  Each block takes 4096
+// queries, builds its list with wave ballots and an LDS prefix, and reserves
+// its slice of the output with a single atomic (order between blocks is
 // arbitrary; every positive appears once).
-__global__ void k_compact_positive(const uint8_t* __restrict__ h, int64_t n, int32_t* __restrict__ idx,
-                                   unsigned long long* __restrict__ count) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool pos = i < n && h[i] != 0;
-  const unsigned long long m = __ballot(pos);
-  const int lane = threadIdx.x & 63;
-  unsigned long long base = 0;
-  if (lane == 0 && m) base = atomicAdd(count, (unsigned long long)__popcll(m));
-  base = __shfl(base, 0);
-  if (pos) idx[base + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)i;
+constexpr int kCompactPer = 16;   // queries per thread
+
+__global__ __launch_bounds__(256) void k_compact_positive(const uint8_t* __restrict__ h, int64_t n,
+                                                          int32_t* __restrict__ idx,
+                                                          unsigned long long* __restrict__ count) {
+  __shared__ int wave_tot[4];
+  __shared__ unsigned long long block_base;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t base = (int64_t)blockIdx.x * 256 * kCompactPer;
+  unsigned long long masks[kCompactPer];
+  int tot = 0;
+#pragma unroll
+  for (int k = 0; k < kCompactPer; ++k) {
+    const int64_t i = base + (int64_t)k * 256 + threadIdx.x;
+    masks[k] = __ballot(i < n && h[i] != 0);
+    tot += __popcll(masks[k]);
+  }
+  if (lane == 0) wave_tot[wave] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int all = wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
+    block_base = all ? atomicAdd(count, (unsigned long long)all) : 0ull;
+  }
+  __syncthreads();
+  unsigned long long off = block_base;
+  for (int w = 0; w < wave; ++w) off += wave_tot[w];
+  const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int k = 0; k < kCompactPer; ++k) {
+    if (masks[k] >> lane & 1ull) idx[off + __popcll(masks[k] & below)] = (int32_t)(base + (int64_t)k * 256 + threadIdx.x);
+    off += __popcll(masks[k]);
+  }
 }
 
 // answer[idx[t]] = g(q[idx[t]]) for every listed positive (grid-stride).
@@ -270,7 +322,7 @@ nb_status launch_cascade_exact(const nb_indicator* ind, int kind, const float* q
                                int32_t* idx, unsigned long long* count, uint8_t* answer, hipStream_t s) {
   NB_REQUIRE(kind == NB_QUERY_POINT || ind->type == IND_VOXELS, "ray, box and plane queries need a voxel indicator");
   NB_REQUIRE(n <= (int64_t)0x7FFFFFFF, "cascade handles at most 2^31 - 1 queries per call");
-  k_compact_positive<<<blocks_for(n), kThreads, 0, s>>>(h, n, idx, count);
+  k_compact_positive<<<(unsigned)((n + 256 * kCompactPer - 1) / (256 * kCompactPer)), 256, 0, s>>>(h, n, idx, count);
   NB_LAUNCHED();
   const IndView v = view_of(ind);
   const unsigned blocks = (unsigned)std::min<int64_t>(blocks_for(n), 4096);

@@ -83,7 +83,7 @@ __global__ void k_pack_bf16_t(const float* __restrict__ theta, int in_dim, int W
 // ------------------------------------------------------------ first layer
 
 template <int W>
-__global__ __launch_bounds__(256) void k_tr_first(const float* __restrict__ q, int64_t n, int in_dim, int64_t CH,
+__global__ __launch_bounds__(256) void k_tr_first(const float* __restrict__ q, int64_t n, int in_dim, int64_t Bp,
                                                   const bf16x8* __restrict__ pack, const float* __restrict__ theta,
                                                   uint16_t* __restrict__ A0) {
   constexpr int RB = W / 16;
@@ -92,10 +92,10 @@ __global__ __launch_bounds__(256) void k_tr_first(const float* __restrict__ q, i
   for (int i = threadIdx.x; i < RB * 64; i += blockDim.x) sw[i] = pack[i];
   for (int i = threadIdx.x; i < W; i += blockDim.x) sb[i] = theta[(int64_t)W * in_dim + i];
   __syncthreads();
-  const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4, wave = threadIdx.x >> 6;
-  const int64_t base = (int64_t)blockIdx.x * CH;
-  for (int64_t blk = wave; blk < CH / 16; blk += blockDim.x >> 6) {
-    const int64_t qi = base + blk * 16 + c;
+  const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t blk = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); blk < Bp / 16; blk += waves) {
+    const int64_t qi = blk * 16 + c;
     const bool valid = qi < n;
     bf16x8 xb;
 #pragma unroll
@@ -146,14 +146,19 @@ __global__ __launch_bounds__(256) void k_tr_hidden(const uint16_t* __restrict__ 
   __syncthreads();
 
   const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4, wave = threadIdx.x >> 6;
-  const int64_t base = (int64_t)blockIdx.x * CH;
+  // the head writes one partial per chunk (workgroup = chunk of CH queries);
+  // the other layers stride over all blocks of the padded batch (CH = Bp)
+  const int64_t base = HEAD ? (int64_t)blockIdx.x * CH : 0;
+  const int64_t nblk = CH / 16;
+  const int64_t first = HEAD ? wave : (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  const int64_t stride = HEAD ? (blockDim.x >> 6) : (int64_t)gridDim.x * (blockDim.x >> 6);
   float gwo[HEAD ? RB * 4 : 1];
 #pragma unroll
   for (int i = 0; i < (HEAD ? RB * 4 : 1); ++i) gwo[i] = 0.0f;
   float gbo = 0.0f, lsum = 0.0f;
   unsigned cnt[4] = {0u, 0u, 0u, 0u};
 
-  for (int64_t blk = wave; blk < CH / 16; blk += blockDim.x >> 6) {
+  for (int64_t blk = first; blk < nblk; blk += stride) {
     const int64_t qi = base + blk * 16 + c;
     const uint16_t* row = Ain + qi * W;
     bf16x8 bop[KS];
@@ -268,7 +273,7 @@ __global__ __launch_bounds__(256) void k_tr_hidden(const uint16_t* __restrict__ 
 // D_{l-1} = (W_l^T D_l) * [A_{l-1} > 0]
 template <int W>
 __global__ __launch_bounds__(256) void k_tr_data(const uint16_t* __restrict__ Dl, const uint16_t* __restrict__ Aprev,
-                                                 int64_t CH, int l, const bf16x8* __restrict__ packT,
+                                                 int64_t Bp, int l, const bf16x8* __restrict__ packT,
                                                  uint16_t* __restrict__ Dprev) {
   using T = TrHidden<W>;
   constexpr int RB = T::RB, KS = T::KS;
@@ -277,10 +282,10 @@ __global__ __launch_bounds__(256) void k_tr_data(const uint16_t* __restrict__ Dl
   const bf16x8* src = packT + (l - 1) * T::FH * 64;
   for (int i = threadIdx.x; i < T::FH * 64; i += blockDim.x) sw[i] = src[i];
   __syncthreads();
-  const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4, wave = threadIdx.x >> 6;
-  const int64_t base = (int64_t)blockIdx.x * CH;
-  for (int64_t blk = wave; blk < CH / 16; blk += blockDim.x >> 6) {
-    const int64_t qi = base + blk * 16 + c;
+  const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t blk = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); blk < Bp / 16; blk += waves) {
+    const int64_t qi = blk * 16 + c;
     bf16x8 bop[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) bop[ks] = *reinterpret_cast<const bf16x8*>(Dl + qi * W + 32 * ks + 8 * grp);
@@ -304,47 +309,81 @@ __global__ __launch_bounds__(256) void k_tr_data(const uint16_t* __restrict__ Dl
 
 constexpr int kTS = 40;   // LDS row stride of a [width][32 queries] bfloat16 tile (+ 8 pad)
 
+// Staging: thread t owns the neuron pair (2p, 2p + 1), p = t % (W/2), and
+// QPT consecutive queries of the 32-query slab, group j = t / (W/2); per
+// query it loads 4 bytes (a wave reads whole 256-byte rows, coalesced) and
+// writes QPT consecutive bf16 per neuron into the [neuron][query] tiles.
 template <int W, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_tr_weight(const uint16_t* __restrict__ Dl,
                                                           const uint16_t* __restrict__ Aprev, int64_t CH, int l,
                                                           int in_dim, int NH, float* __restrict__ partial, int64_t P) {
   constexpr int RB = W / 16, TILES = RB * RB, TPW = TILES / WAVES;
   static_assert(TILES % WAVES == 0, "tiles must split evenly over the waves");
-  __shared__ __attribute__((aligned(16))) uint16_t sD[W * kTS];
-  __shared__ __attribute__((aligned(16))) uint16_t sA[W * kTS];
+  constexpr int THREADS = WAVES * 64;
+  constexpr int PAIRS = W / 2;
+  constexpr int GROUPS = THREADS / PAIRS;      // query groups per slab
+  constexpr int QPT = 32 / GROUPS;             // queries per thread per slab
+  static_assert(THREADS % PAIRS == 0 && 32 % GROUPS == 0 && QPT % 2 == 0, "staging shape");
+  __shared__ __attribute__((aligned(16))) uint16_t sD[2][W * kTS];
+  __shared__ __attribute__((aligned(16))) uint16_t sA[2][W * kTS];
+  __shared__ float sdb[GROUPS][W];
   const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4, wave = threadIdx.x >> 6;
+  const int pr = threadIdx.x % PAIRS, gq = threadIdx.x / PAIRS;
   const int64_t base = (int64_t)blockIdx.x * CH;
   floatx4 acc[TPW];
 #pragma unroll
   for (int i = 0; i < TPW; ++i) acc[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-  float db = 0.0f;
-  constexpr int PIECES = 32 * W / 8;   // 16-byte pieces of one [32][W] slab
-  for (int64_t k0 = 0; k0 < CH; k0 += 32) {
-    __syncthreads();
-    for (int p = threadIdx.x; p < PIECES; p += blockDim.x) {
-      const int qq = p / (W / 8), n0 = (p % (W / 8)) * 8;
-      const int64_t qi = base + k0 + qq;
-      const bf16x8 dv = *reinterpret_cast<const bf16x8*>(Dl + qi * W + n0);
-      const bf16x8 av = *reinterpret_cast<const bf16x8*>(Aprev + qi * W + n0);
+  float db0 = 0.0f, db1 = 0.0f;
+  uint32_t pd[QPT], pa[QPT];
+  auto fetch = [&](int64_t k0) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        sD[(n0 + i) * kTS + qq] = bits_of(dv[i]);
-        sA[(n0 + i) * kTS + qq] = bits_of(av[i]);
-      }
+    for (int i = 0; i < QPT; ++i) {
+      const int64_t qi = base + k0 + gq * QPT + i;
+      pd[i] = *reinterpret_cast<const uint32_t*>(Dl + qi * W + 2 * pr);
+      pa[i] = *reinterpret_cast<const uint32_t*>(Aprev + qi * W + 2 * pr);
     }
-    __syncthreads();
-    if (threadIdx.x < W) {
-      const uint16_t* r = sD + threadIdx.x * kTS;
-      for (int i = 0; i < 32; ++i) db += (float)bf16_of(r[i]);
+  };
+  auto stash = [&](int bufi) {
+    uint16_t d0[QPT], d1[QPT], a0[QPT], a1[QPT];
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+      d0[i] = (uint16_t)(pd[i] & 0xFFFF);
+      d1[i] = (uint16_t)(pd[i] >> 16);
+      a0[i] = (uint16_t)(pa[i] & 0xFFFF);
+      a1[i] = (uint16_t)(pa[i] >> 16);
+      db0 += (float)bf16_of(d0[i]);
+      db1 += (float)bf16_of(d1[i]);
     }
+    uint16_t* rd0 = sD[bufi] + (2 * pr) * kTS + gq * QPT;
+    uint16_t* ra0 = sA[bufi] + (2 * pr) * kTS + gq * QPT;
+#pragma unroll
+    for (int i = 0; i < QPT; i += 2) {
+      *reinterpret_cast<uint32_t*>(rd0 + i) = (uint32_t)d0[i] | ((uint32_t)d0[i + 1] << 16);
+      *reinterpret_cast<uint32_t*>(rd0 + kTS + i) = (uint32_t)d1[i] | ((uint32_t)d1[i + 1] << 16);
+      *reinterpret_cast<uint32_t*>(ra0 + i) = (uint32_t)a0[i] | ((uint32_t)a0[i + 1] << 16);
+      *reinterpret_cast<uint32_t*>(ra0 + kTS + i) = (uint32_t)a1[i] | ((uint32_t)a1[i + 1] << 16);
+    }
+  };
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = 0; k0 < CH; k0 += 32) {
+    const bool more = k0 + 32 < CH;
+    if (more) fetch(k0 + 32);              // next slab in flight during this step's products
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
       const int T = wave * TPW + t, no = T / RB, ko = T % RB;
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(sD + (16 * no + c) * kTS + 8 * grp);
-      const bf16x8 b = *reinterpret_cast<const bf16x8*>(sA + (16 * ko + c) * kTS + 8 * grp);
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(sD[buf] + (16 * no + c) * kTS + 8 * grp);
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(sA[buf] + (16 * ko + c) * kTS + 8 * grp);
       acc[t] = nb_mfma_bf16(a, b, acc[t]);
     }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
   }
+  sdb[gq][2 * pr] = db0;
+  sdb[gq][2 * pr + 1] = db1;
   float* out = partial + (int64_t)blockIdx.x * P;
   const int64_t wo = nb_w_off(l, in_dim, W);
 #pragma unroll
@@ -353,28 +392,56 @@ __global__ __launch_bounds__(WAVES * 64) void k_tr_weight(const uint16_t* __rest
 #pragma unroll
     for (int r = 0; r < 4; ++r) out[wo + (int64_t)(16 * no + 4 * grp + r) * W + 16 * ko + c] = acc[t][r];
   }
-  if (threadIdx.x < W) out[nb_b_off(l, in_dim, W, NH) + threadIdx.x] = db;
+  __syncthreads();
+  if (threadIdx.x < W) {
+    float db = sdb[0][threadIdx.x];
+    for (int j = 1; j < GROUPS; ++j) db += sdb[j][threadIdx.x];
+    out[nb_b_off(l, in_dim, W, NH) + threadIdx.x] = db;
+  }
 }
 
-// dW_0 = sum_q D_0[q] x[q]^T, db_0 = sum_q D_0[q]  (one thread per neuron)
-__global__ __launch_bounds__(256) void k_tr_first_grad(const uint16_t* __restrict__ D0, const float* __restrict__ q,
+// dW_0 = sum_q D_0[q] x[q]^T, db_0 = sum_q D_0[q].  1024 threads: thread t
+// takes neuron t % W and every S-th query of each 256-query slab (S = 1024 / W,
+// subset t / W); the slab's inputs sit in LDS; the S subset sums are added in
+// subset order at the end.
+constexpr int kFG = 1024;
+constexpr int kFGSlab = 256;
+
+__global__ __launch_bounds__(kFG) void k_tr_first_grad(const uint16_t* __restrict__ D0, const float* __restrict__ q,
                                                        int64_t n, int64_t CH, int in_dim, int W, int NH,
                                                        float* __restrict__ partial, int64_t P) {
+  __shared__ float red[kFG * 9];
+  __shared__ float sx[kFGSlab * 8];
+  const int S = kFG / W, nn = threadIdx.x % W, sub = threadIdx.x / W;
   const int64_t base = (int64_t)blockIdx.x * CH;
-  for (int nn = threadIdx.x; nn < W; nn += blockDim.x) {
-    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    float db = 0.0f;
-    const int64_t end = base + CH < n ? base + CH : n;
-    for (int64_t qi = base; qi < end; ++qi) {
-      const float d = (float)bf16_of(D0[qi * W + nn]);
-      db += d;
+  const int64_t end = base + CH < n ? base + CH : n;
+  float acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // dW_0[nn][0..7], db_0[nn]
+  for (int64_t s0 = base; s0 < end; s0 += kFGSlab) {
+    const int len = (int)(end - s0 < kFGSlab ? end - s0 : kFGSlab);
+    __syncthreads();
+    for (int i = threadIdx.x; i < len * in_dim; i += kFG) sx[(i / in_dim) * 8 + i % in_dim] = q[s0 * in_dim + i];
+    __syncthreads();
+    for (int j = sub; j < len; j += S) {
+      const float d = (float)bf16_of(D0[(s0 + j) * W + nn]);
+      acc[8] += d;
 #pragma unroll
       for (int k = 0; k < 8; ++k)
-        if (k < in_dim) acc[k] = fmaf(d, q[qi * in_dim + k], acc[k]);
+        if (k < in_dim) acc[k] = fmaf(d, sx[j * 8 + k], acc[k]);
     }
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) red[threadIdx.x * 9 + k] = acc[k];
+  __syncthreads();
+  if (threadIdx.x < W) {
+    float tot[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) tot[k] = red[threadIdx.x * 9 + k];
+    for (int s2 = 1; s2 < S; ++s2)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) tot[k] += red[(s2 * W + threadIdx.x) * 9 + k];
     float* out = partial + (int64_t)blockIdx.x * P;
-    for (int k = 0; k < in_dim; ++k) out[(int64_t)nn * in_dim + k] = acc[k];
-    out[nb_b_off(0, in_dim, W, NH) + nn] = db;
+    for (int k = 0; k < in_dim; ++k) out[(int64_t)threadIdx.x * in_dim + k] = tot[k];
+    out[nb_b_off(0, in_dim, W, NH) + threadIdx.x] = tot[8];
   }
 }
 
@@ -405,13 +472,14 @@ nb_status train_w(const nb_bound* b, const float* q, const uint8_t* y, int64_t n
   const int64_t stride = pl.padded * W;
   uint16_t* D[2] = {b->tr_grad, b->tr_grad + stride};
 
-  k_tr_first<W><<<grid, 256, 0, s>>>(q, n, in_dim, CH, pack, b->theta, A);
+  const unsigned wide = (unsigned)std::max<int64_t>(1, std::min<int64_t>(pl.padded / 64, 4 * (int64_t)nb_cu_count()));
+  k_tr_first<W><<<wide, 256, 0, s>>>(q, n, in_dim, pl.padded, pack, b->theta, A);
   NB_LAUNCHED();
   NB_TRY(allow_lds(k_tr_hidden<W, false>, lds));
   NB_TRY(allow_lds(k_tr_hidden<W, true>, lds));
   NB_TRY(allow_lds(k_tr_data<W>, (size_t)T::FH * 64 * 16));
   for (int l = 1; l < NH - 1; ++l) {
-    k_tr_hidden<W, false><<<grid, 256, lds, s>>>(A + (l - 1) * stride, n, CH, l, in_dim, NH, pack, b->theta,
+    k_tr_hidden<W, false><<<wide, 256, lds, s>>>(A + (l - 1) * stride, n, pl.padded, l, in_dim, NH, pack, b->theta,
                                                  A + l * stride, nullptr, 0, 0, 0, tau, nullptr, P, nullptr);
     NB_LAUNCHED();
   }
@@ -424,11 +492,12 @@ nb_status train_w(const nb_bound* b, const float* q, const uint8_t* y, int64_t n
   for (int l = NH - 1; l >= 1; --l) {
     k_tr_weight<W, WW><<<grid, WW * 64, 0, s>>>(D[cur], A + (l - 1) * stride, CH, l, in_dim, NH, b->partial, P);
     NB_LAUNCHED();
-    k_tr_data<W><<<grid, 256, (size_t)T::FH * 64 * 16, s>>>(D[cur], A + (l - 1) * stride, CH, l, packT, D[cur ^ 1]);
+    k_tr_data<W><<<wide, 256, (size_t)T::FH * 64 * 16, s>>>(D[cur], A + (l - 1) * stride, pl.padded, l, packT,
+                                                           D[cur ^ 1]);
     NB_LAUNCHED();
     cur ^= 1;
   }
-  k_tr_first_grad<<<grid, 256, 0, s>>>(D[cur], q, n, CH, in_dim, W, NH, b->partial, P);
+  k_tr_first_grad<<<grid, kFG, 0, s>>>(D[cur], q, n, CH, in_dim, W, NH, b->partial, P);
   NB_LAUNCHED();
   return NB_OK;
 }

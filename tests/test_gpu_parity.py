@@ -86,10 +86,20 @@ def test_exact_rays(c2_grid):
     _, _, grid = c2_grid
     ind = nb.Indicator.voxels(cuda(grid), 128)
     q = synth.rays(7, 8195)
+    # edge cases: axis-parallel directions, origins on the cube faces, d = 0,
+    # segments that end exactly on a face, rays starting inside the cube
+    edge = np.array([[-2, 0.1, 0.1, 1, 0, 0], [0.3, -2, 0.2, 0, 1, 0], [0.1, 0.2, 3, 0, 0, -1],
+                     [-1, -1, -1, 0.57735, 0.57735, 0.57735], [1, 1, 1, -0.57735, -0.57735, -0.57735],
+                     [0.2, 0.3, 0.1, 0, 0, 0], [-5, 0, 0, 1, 0, 0], [-3, 0.05, -0.1, 1, 0, 0],
+                     [0, 0, 0, 0, 0, 1], [0.99, 0.99, 0.99, 1, 0, 0], [1.5, 1.5, 1.5, 0, 0, 1]], np.float32)
+    q = np.concatenate([edge, q]).astype(np.float32)
     g = ind.query("ray", cuda(q))
     ref = I.voxel_rays(q, grid, 128)
     assert np.array_equal(host(g), ref)
     assert 0.05 < ref.mean() < 0.95
+    # a grid occupied everywhere: g = 1 iff some sample lies in the closed cube
+    full = nb.Indicator.voxels(cuda(np.ones(32 ** 3, np.uint8)), 32)
+    assert np.array_equal(host(full.query("ray", cuda(q))), I.voxel_rays(q, np.ones(32 ** 3, np.uint8), 32))
 
 
 @pytest.mark.parametrize("n", [32, 128])
