@@ -146,8 +146,9 @@ nb_status nb_sample_queries(int kind, int dim, uint64_t seed, uint64_t step, int
 /* ------------------------------------------------------------------------
  * Bound h_theta (Sec. 3.4): in_dim -> width x n_hidden (ReLU) -> 1 logit.
  * Supported: in_dim 1..8;  NB_F32: width 16, 32 or 64 with n_hidden 1..4;
- * NB_BF16: width 32 or 64 with n_hidden 1..6, width 128 with n_hidden 1..5
- * (training needs n_hidden >= 2).  Other shapes give NB_ERR_UNSUPPORTED.
+ * NB_BF16: width 32 or 64 with n_hidden 1..6, width 128 with n_hidden 1..5,
+ * width 256 with n_hidden 2..8 (its layers stream through LDS); training
+ * needs n_hidden >= 2.  Other shapes give NB_ERR_UNSUPPORTED.
  * The handle owns float32 master parameters, Adam moments and work space.
  * Parameters start at zero; set them with nb_bound_set_params.
  * ---------------------------------------------------------------------- */

@@ -231,6 +231,7 @@ nb_status fwd_launch(const nb_bound* b, const float* q, int64_t n, float tau, fl
 
 bool bf16_supported(int in_dim, int n_hidden, int width) {
   if (in_dim < 1 || in_dim > 8) return false;
+  if (width == 256) return n_hidden >= 2 && n_hidden <= 8;
 #define X(WW, H) \
   if (width == WW && n_hidden == H) return true;
   NB_BF16_CASES(X)
@@ -252,13 +253,217 @@ nb_status bf16_pack(const nb_bound* b, hipStream_t s) {
   return NB_OK;
 }
 
+// ------------------------------------------------- width 256: streamed weights
+//
+// A 256-wide hidden layer is 128 KiB of bfloat16 fragments, so the layers
+// stream through LDS in 64 KiB half-layer chunks (row blocks 0..7, then
+// 8..15), double-buffered: while the waves multiply chunk c, each thread
+// holds its share of chunk c + 1 in registers and stores it to the other
+// buffer afterwards.  A workgroup of 4 waves takes 128 queries per pass
+// (2 blocks of 16 per wave); the first-layer fragments and biases stay
+// resident.
+template <int NH>
+struct Stream256 {
+  static constexpr int W = 256, RB = 16, KS = 8, FH = RB * KS, HALF = FH / 2;
+  static constexpr int NB = 3, THREADS = 256, WAVES = THREADS / 64;
+  static constexpr int PER = HALF * 64 / THREADS;    // 16-byte fragment slices per thread per chunk
+  static constexpr size_t lds_bytes() {
+    return (size_t)(RB * 64 + 2 * HALF * 64) * 16 + (size_t)(NH * W + W + 1) * 4;
+  }
+};
+
+template <int NH>
+__global__ __launch_bounds__(256, 1) void k_fwd_bf16_stream(const float* __restrict__ q, int64_t n, int in_dim,
+                                                          const bf16x8* __restrict__ pack,
+                                                          const float* __restrict__ theta, float tau,
+                                                          float* __restrict__ logits, uint8_t* __restrict__ hout,
+                                                          const uint8_t* __restrict__ g,
+                                                          unsigned long long* __restrict__ counts) {
+  using S = Stream256<NH>;
+  constexpr int W = S::W, RB = S::RB, KS = S::KS, NB = S::NB;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  bf16x8* sfirst = reinterpret_cast<bf16x8*>(smem_raw);
+  bf16x8* sbuf = sfirst + RB * 64;                                        // [2][HALF * 64]
+  float* sbias = reinterpret_cast<float*>(sbuf + 2 * S::HALF * 64);
+  const float* swo = sbias + NH * W;
+
+  for (int i = threadIdx.x; i < RB * 64; i += S::THREADS) sfirst[i] = pack[i];
+  for (int i = threadIdx.x; i < NH * W; i += S::THREADS) sbias[i] = theta[nb_b_off(i / W, in_dim, W, NH) + i % W];
+  for (int i = threadIdx.x; i < W + 1; i += S::THREADS) sbias[NH * W + i] = theta[nb_w_off(NH, in_dim, W) + i];
+
+  const int nchunk = 2 * (NH - 1);
+  const int64_t tiles = (n + S::WAVES * NB * 16 - 1) / (S::WAVES * NB * 16);
+  const int64_t my_tiles = blockIdx.x < tiles ? (tiles - 1 - blockIdx.x) / gridDim.x + 1 : 0;
+  const int64_t total_chunks = my_tiles * nchunk;
+  // chunk k of this workgroup's stream: layer 1 + (k % nchunk) / 2, half (k % nchunk) % 2
+  auto chunk_src = [&](int64_t k) {
+    const int c = (int)(k % nchunk), l = 1 + c / 2, h = c % 2;
+    return pack + (RB + (l - 1) * S::FH + h * S::HALF) * 64;
+  };
+  // chunk k + 1 goes straight from global memory into the idle LDS buffer
+  // (global_load_lds: lane i of a wave fills the i-th 16-byte slot after the
+  // wave-uniform LDS base), waited for before the end-of-chunk barrier.
+  auto prefetch = [&](int64_t kk, bf16x8* dst) {
+    const bf16x8* src = chunk_src(kk);
+#pragma unroll
+    for (int i = 0; i < S::PER; ++i) {
+      const int slot = i * S::THREADS + (threadIdx.x & ~63);
+      __builtin_amdgcn_global_load_lds((const void*)(src + slot + (threadIdx.x & 63)),
+                                       (__attribute__((address_space(3))) void*)(dst + slot), 16, 0, 0);
+    }
+  };
+  if (total_chunks > 0) {
+    const bf16x8* src = chunk_src(0);
+#pragma unroll
+    for (int i = 0; i < S::PER; ++i) sbuf[threadIdx.x + i * S::THREADS] = src[threadIdx.x + i * S::THREADS];
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4, wave = threadIdx.x >> 6;
+  const float bo = swo[W];
+  unsigned cnt[4] = {0u, 0u, 0u, 0u};
+  int64_t k = 0;
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t q0 = (tile * S::WAVES + wave) * NB * 16;
+    floatx4 acc[NB][RB];
+    {
+      bf16x8 xb[NB];
+      load_inputs<NB>(q, n, in_dim, q0, c, grp, xb);
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo) {
+        const float* b = sbias + 16 * mo + 4 * grp;
+        const floatx4 bi = floatx4{b[0], b[1], b[2], b[3]};
+        const bf16x8 a = sfirst[mo * 64 + lane];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = mfma32(a, xb[nb], bi);
+      }
+    }
+    bf16x8 act[NB][KS];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) act[nb][ks][j] = (__bf16)fmaxf(acc[nb][2 * ks + j / 4][j % 4], 0.0f);
+
+#pragma unroll 1
+    for (int l = 1; l < NH; ++l) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h, ++k) {
+        const bf16x8* buf = sbuf + (k & 1) * S::HALF * 64;
+        const bool more = k + 1 < total_chunks;
+        if (more) prefetch(k + 1, sbuf + ((k + 1) & 1) * S::HALF * 64);
+        // four row blocks at a time: 4 x NB independent accumulation chains per K step
+#pragma unroll
+        for (int m4 = 0; m4 < RB / 2; m4 += 4) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int mo = h * (RB / 2) + m4 + u;
+            const float* b = sbias + l * W + 16 * mo + 4 * grp;
+            const floatx4 bi = floatx4{b[0], b[1], b[2], b[3]};
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = bi;
+          }
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) {
+            bf16x8 a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] = buf[((m4 + u) * KS + ks) * 64 + lane];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int nb = 0; nb < NB; ++nb) {
+                const int mo = h * (RB / 2) + m4 + u;
+                acc[nb][mo] = mfma32(a[u], act[nb][ks], acc[nb][mo]);
+              }
+          }
+        }
+        if (h == 1 && l < NH - 1) {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+              for (int j = 0; j < 8; ++j) act[nb][ks][j] = (__bf16)fmaxf(acc[nb][2 * ks + j / 4][j % 4], 0.0f);
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      float p = 0.0f;
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) p = fmaf(swo[16 * mo + 4 * grp + r], fmaxf(acc[nb][mo][r], 0.0f), p);
+      p += __shfl_xor(p, 16);
+      p += __shfl_xor(p, 32);
+      const float z = p + bo;
+      const int64_t qi = q0 + nb * 16 + c;
+      const bool own = grp == 0 && qi < n;
+      const bool pos = !(z < tau);
+      if (own) {
+        if (logits) logits[qi] = z;
+        if (hout) hout[qi] = pos;
+      }
+      if (counts) {
+        const bool gv = own && g[qi] != 0;
+        cnt[0] += __popcll(__ballot(own && pos && gv));
+        cnt[1] += __popcll(__ballot(own && pos && !gv));
+        cnt[2] += __popcll(__ballot(own && !pos && !gv));
+        cnt[3] += __popcll(__ballot(own && !pos && gv));
+      }
+    }
+  }
+  if (counts && lane == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (cnt[i]) atomicAdd(&counts[i], (unsigned long long)cnt[i]);
+  }
+}
+
+template <int NH>
+nb_status stream_launch(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
+                        const uint8_t* g, unsigned long long* counts, hipStream_t s) {
+  using S = Stream256<NH>;
+  const size_t lds = S::lds_bytes();
+  static bool attr_set[64] = {false};
+  int dev = 0;
+  NB_HIP(hipGetDevice(&dev));
+  if (dev >= 0 && dev < 64 && !attr_set[dev]) {
+    NB_HIP(hipFuncSetAttribute((const void*)k_fwd_bf16_stream<NH>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    attr_set[dev] = true;
+  }
+  const int64_t tiles = (n + S::WAVES * S::NB * 16 - 1) / (S::WAVES * S::NB * 16);
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, nb_cu_count()));
+  k_fwd_bf16_stream<NH><<<grid, S::THREADS, lds, s>>>(q, n, b->in_dim, reinterpret_cast<const bf16x8*>(b->pack16),
+                                                      b->theta, tau, logits, h, g, counts);
+  NB_LAUNCHED();
+  return NB_OK;
+}
+
 int bf16_variants() { return 6; }
+int bf16_variants_for(int width) { return width == 256 ? 1 : 6; }
 
 // Variant v: (query blocks per wave, threads per workgroup) =
 //   0: (2, 768)   1: (2, 512)   2: (3, 512)   3: (1, 1024)   4: (4, 256)   5: (2, 256)
 // Variant 0 (three waves per SIMD) measured fastest for widths 32..128.
 nb_status bf16_forward(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
                        const uint8_t* g, unsigned long long* counts, hipStream_t s) {
+  if (b->width == 256) {
+    switch (b->n_hidden) {
+      case 2: return stream_launch<2>(b, q, n, tau, logits, h, g, counts, s);
+      case 3: return stream_launch<3>(b, q, n, tau, logits, h, g, counts, s);
+      case 4: return stream_launch<4>(b, q, n, tau, logits, h, g, counts, s);
+      case 5: return stream_launch<5>(b, q, n, tau, logits, h, g, counts, s);
+      case 6: return stream_launch<6>(b, q, n, tau, logits, h, g, counts, s);
+      case 7: return stream_launch<7>(b, q, n, tau, logits, h, g, counts, s);
+      case 8: return stream_launch<8>(b, q, n, tau, logits, h, g, counts, s);
+      default: break;
+    }
+  }
 #define X(WW, H)                                                                  \
   if (b->width == WW && b->n_hidden == H) {                                       \
     switch (b->variant) {                                                         \

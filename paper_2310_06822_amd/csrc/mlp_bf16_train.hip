@@ -324,9 +324,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_tr_weight(const uint16_t* __rest
   constexpr int GROUPS = THREADS / PAIRS;      // query groups per slab
   constexpr int QPT = 32 / GROUPS;             // queries per thread per slab
   static_assert(THREADS % PAIRS == 0 && 32 % GROUPS == 0 && QPT % 2 == 0, "staging shape");
-  __shared__ __attribute__((aligned(16))) uint16_t sD[2][W * kTS];
-  __shared__ __attribute__((aligned(16))) uint16_t sA[2][W * kTS];
-  __shared__ float sdb[GROUPS][W];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  uint16_t (*sD)[W * kTS] = reinterpret_cast<uint16_t (*)[W * kTS]>(smem_raw);
+  uint16_t (*sA)[W * kTS] = reinterpret_cast<uint16_t (*)[W * kTS]>(smem_raw + 2 * W * kTS * 2);
+  float (*sdb)[W] = reinterpret_cast<float (*)[W]>(smem_raw + 4 * W * kTS * 2);
   const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4, wave = threadIdx.x >> 6;
   const int pr = threadIdx.x % PAIRS, gq = threadIdx.x / PAIRS;
   const int64_t base = (int64_t)blockIdx.x * CH;
@@ -489,8 +490,10 @@ nb_status train_w(const nb_bound* b, const float* q, const uint8_t* y, int64_t n
                                               D[cur], y, alpha, beta, inv_n, tau, b->partial, P, b->aux);
   NB_LAUNCHED();
   constexpr int WW = W >= 256 ? 8 : 4;
+  const size_t wlds = (size_t)4 * W * kTS * 2 + (size_t)(WW * 64 / (W / 2)) * W * 4;
+  NB_TRY(allow_lds(k_tr_weight<W, WW>, wlds));
   for (int l = NH - 1; l >= 1; --l) {
-    k_tr_weight<W, WW><<<grid, WW * 64, 0, s>>>(D[cur], A + (l - 1) * stride, CH, l, in_dim, NH, b->partial, P);
+    k_tr_weight<W, WW><<<grid, WW * 64, wlds, s>>>(D[cur], A + (l - 1) * stride, CH, l, in_dim, NH, b->partial, P);
     NB_LAUNCHED();
     k_tr_data<W><<<wide, 256, (size_t)T::FH * 64 * 16, s>>>(D[cur], A + (l - 1) * stride, pl.padded, l, packT,
                                                            D[cur ^ 1]);
@@ -516,7 +519,7 @@ BF16TrainPlan bf16_train_plan(int64_t n) {
 
 bool bf16_train_supported(int in_dim, int n_hidden, int width) {
   return in_dim >= 1 && in_dim <= 8 && n_hidden >= 2 && n_hidden <= 8 &&
-         (width == 32 || width == 64 || width == 128);
+         (width == 32 || width == 64 || width == 128 || width == 256);
 }
 
 int64_t bf16_packt_elems(int n_hidden, int width) {
@@ -539,6 +542,7 @@ nb_status bf16_train_partials(const nb_bound* b, const float* q, const uint8_t* 
     case 32: return train_w<32>(b, q, y, n, alpha, beta, tau, plan, s);
     case 64: return train_w<64>(b, q, y, n, alpha, beta, tau, plan, s);
     case 128: return train_w<128>(b, q, y, n, alpha, beta, tau, plan, s);
+    case 256: return train_w<256>(b, q, y, n, alpha, beta, tau, plan, s);
     default: break;
   }
   nb_set_error("bfloat16 training has no kernel for width %d", b->width);

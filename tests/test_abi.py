@@ -62,6 +62,7 @@ def test_unsupported_shape_reported():
     assert lib.nb_bound_create(3, 3, 48, 0, C.byref(h)) == 6
     assert lib.nb_bound_create(3, 5, 64, 0, C.byref(h)) == 6
     assert lib.nb_bound_create(3, 6, 128, 1, C.byref(h)) == 6
+    assert lib.nb_bound_create(3, 1, 256, 1, C.byref(h)) == 6
     assert lib.nb_bound_create(3, 9, 64, 0, C.byref(h)) == 1
 
 

@@ -182,7 +182,8 @@ def test_forward_counts_and_edge_logits(c2_grid):
     assert np.array_equal(L.decide(host(z))[~band], L.decide(ref)[~band])
 
 
-BF16_SHAPES = [(6, 128, 4), (4, 64, 3), (6, 32, 2), (8, 128, 5), (3, 64, 1), (2, 32, 4)]
+BF16_SHAPES = [(6, 128, 4), (4, 64, 3), (6, 32, 2), (8, 128, 5), (3, 64, 1), (2, 32, 4), (4, 256, 6),
+               (6, 256, 2), (3, 256, 3)]
 
 
 @pytest.mark.parametrize("in_dim,width,nh", BF16_SHAPES)
@@ -381,7 +382,7 @@ def test_autograd_bound_loss():
 
 # ------------------------------------------------------- bfloat16 training
 
-BF16_TRAIN_SHAPES = [(6, 128, 4), (4, 64, 3), (6, 32, 2), (3, 128, 2), (8, 64, 5)]
+BF16_TRAIN_SHAPES = [(6, 128, 4), (4, 64, 3), (6, 32, 2), (3, 128, 2), (8, 64, 5), (4, 256, 6), (6, 256, 2)]
 
 
 def _bf16_grad_check(in_dim, width, nh, q, y, alpha, beta):
