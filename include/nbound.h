@@ -224,6 +224,60 @@ nb_status nb_bound_train_step(nb_bound* b, const nb_indicator* ind, int kind, ui
 nb_status nb_cascade(nb_bound* b, const nb_indicator* ind, int kind, const float* q, int64_t n, float eps,
                      uint8_t* answer, uint64_t* n_exact, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Groups of per-object bounds.  The paper fits one bound per object and does
+ * not generalise across objects (Sec. 3.4, "Training"); a group holds n_obj
+ * bfloat16 bounds with a common input size and depth (2..4 hidden layers)
+ * but their own widths (32, 64 or 128), each with its own voxel grid, so
+ * hundreds of bounds train and answer queries in a few launches.
+ * Parameters are the objects' theta vectors concatenated in object order
+ * (offsets from nb_group_param_offsets).  Queries are grouped by object:
+ * qoff (device int64[n_obj + 1], non-decreasing) gives object o the rows
+ * qoff[o] .. qoff[o+1]-1 of q.
+ * ---------------------------------------------------------------------- */
+typedef struct nb_group nb_group;
+
+nb_status nb_group_create(int n_obj, int in_dim, const int* widths_host, int n_hidden, int precision,
+                          nb_group** out);
+nb_status nb_group_destroy(nb_group* g);
+nb_status nb_group_num_params(const nb_group* g, int64_t* n_params);
+/* offsets_host: int64[n_obj + 1], object o's parameters are theta[off[o] .. off[o+1]). */
+nb_status nb_group_param_offsets(const nb_group* g, int64_t* offsets_host);
+/* Copy all objects' parameters in (resets the Adam state) / out (device float32). */
+nb_status nb_group_set_params(nb_group* g, const float* theta, int64_t n_params, void* stream);
+nb_status nb_group_get_params(const nb_group* g, float* theta, int64_t n_params, void* stream);
+/* Per-object voxel grids over [-1, 1]^3 (as nb_indicator_voxels), concatenated
+ * in object order on the device; n_host[o] is object o's grid size.  Copied;
+ * synchronises the device. */
+nb_status nb_group_set_voxels(nb_group* g, const uint8_t* grids, const int* n_host);
+/* Exact point / ray / box query of every row against its object's grid;
+ * g: uint8[n] (rows outside qoff[0] .. qoff[n_obj]-1 are left untouched). */
+nb_status nb_group_query_exact(const nb_group* g, int kind, const float* q, const int64_t* qoff, int64_t n,
+                               uint8_t* g_out, void* stream);
+/* Forward + decision (Eq. 1's logit, h = !(z < tau(eps)) as for a single
+ * bound) of every row with its object's bound in one persistent launch:
+ * tiles of queries of one object, objects ordered by width, runs of tiles of
+ * equal estimated cost per workgroup, weights loaded into LDS once per run.
+ * logits float32[n] and/or h uint8[n]; with g_exact (uint8[n]) and counts
+ * (uint64[n_obj][4], overwritten) also each object's TP, FP, TN, FN. */
+nb_status nb_group_forward(const nb_group* g, const float* q, const int64_t* qoff, int64_t n, float eps,
+                           float* logits, uint8_t* h, const uint8_t* g_exact, uint64_t* counts, void* stream);
+/* Tile-shape variants of the grouped forward (threads per workgroup and
+ * query blocks per wave); all give identical results.  Default 0. */
+nb_status nb_group_num_variants(const nb_group* g, int* count);
+nb_status nb_group_set_variant(nb_group* g, int variant);
+/* One training step of Alg. 1 for every object: per_obj regions of `kind`
+ * per object (nb_sample_queries with n = n_obj * per_obj; object o takes rows
+ * o*per_obj ..), labelled on the object's grid, Eq. 1 with FN weight alpha
+ * (or alpha_obj[o], device float32[n_obj], when alpha_obj is non-NULL) and
+ * beta, one Adam step (lr, 0.9, 0.999, 1e-8) per object.  loss:
+ * float32[n_obj] per-object mean loss or NULL; counts: uint64[n_obj][4] or
+ * NULL.  The first step with a new per_obj synchronises `stream` to size the
+ * work space. */
+nb_status nb_group_train_step(nb_group* g, int kind, uint64_t seed, uint64_t step, int64_t per_obj, float alpha,
+                              const float* alpha_obj, float beta, float lr, float* loss, uint64_t* counts,
+                              void* stream);
+
 #ifdef __cplusplus
 }
 #endif

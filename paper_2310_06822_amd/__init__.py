@@ -250,6 +250,140 @@ def nb_cascade(b, ind, kind: int, q: torch.Tensor, answer: torch.Tensor, n_exact
                             _stream(stream)))
 
 
+# ------------------------------------------------------------------ groups
+
+def nb_group_create(in_dim: int, widths, n_hidden: int, precision: int = BF16) -> C.c_void_p:
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    h = C.c_void_p()
+    _check(lib().nb_group_create(int(w.size), int(in_dim), w.ctypes.data_as(C.c_void_p), int(n_hidden),
+                                 int(precision), C.byref(h)))
+    return h
+
+
+def nb_group_destroy(g):
+    _check(lib().nb_group_destroy(g))
+
+
+def nb_group_num_params(g) -> int:
+    n = C.c_int64()
+    _check(lib().nb_group_num_params(g, C.byref(n)))
+    return n.value
+
+
+def nb_group_param_offsets(g, n_obj: int) -> np.ndarray:
+    off = np.zeros(n_obj + 1, dtype=np.int64)
+    _check(lib().nb_group_param_offsets(g, off.ctypes.data_as(C.c_void_p)))
+    return off
+
+
+def nb_group_set_params(g, theta: torch.Tensor, stream=None):
+    _check(lib().nb_group_set_params(g, _dev(theta, torch.float32, "theta"), theta.numel(), _stream(stream)))
+
+
+def nb_group_get_params(g, theta: torch.Tensor, stream=None):
+    _check(lib().nb_group_get_params(g, _dev(theta, torch.float32, "theta"), theta.numel(), _stream(stream)))
+
+
+def nb_group_set_voxels(g, grids: torch.Tensor, sizes):
+    n = np.ascontiguousarray(sizes, dtype=np.int32)
+    if grids.numel() != int((n.astype(np.int64) ** 3).sum()):
+        raise ValueError("grids must hold sum(n^3) bytes")
+    _check(lib().nb_group_set_voxels(g, _dev(grids, torch.uint8, "grids"), n.ctypes.data_as(C.c_void_p)))
+
+
+def _qoff(qoff: torch.Tensor, n_obj: int, n: int):
+    if qoff.numel() != n_obj + 1:
+        raise ValueError("qoff must have n_obj + 1 entries")
+    return _dev(qoff, torch.int64, "qoff")
+
+
+def nb_group_query_exact(g, n_obj: int, kind: int, q: torch.Tensor, qoff: torch.Tensor, out: torch.Tensor,
+                         stream=None):
+    n = _rows(q)
+    _check(lib().nb_group_query_exact(g, int(kind), _dev(q, torch.float32, "q"), _qoff(qoff, n_obj, n), n,
+                                      _dev(out, torch.uint8, "g", n), _stream(stream)))
+
+
+def nb_group_forward(g, n_obj: int, in_dim: int, q: torch.Tensor, qoff: torch.Tensor, eps: float = EPS_OUT,
+                     logits=None, h=None, g_exact=None, counts=None, stream=None):
+    n = _rows(q, in_dim)
+    _check(lib().nb_group_forward(g, _dev(q, torch.float32, "q"), _qoff(qoff, n_obj, n), n, float(eps),
+                                  _dev(logits, torch.float32, "logits", n), _dev(h, torch.uint8, "h", n),
+                                  _dev(g_exact, torch.uint8, "g", n), _dev(counts, torch.int64, "counts", 4 * n_obj),
+                                  _stream(stream)))
+
+
+def nb_group_num_variants(g) -> int:
+    c = C.c_int()
+    _check(lib().nb_group_num_variants(g, C.byref(c)))
+    return c.value
+
+
+def nb_group_set_variant(g, variant: int):
+    _check(lib().nb_group_set_variant(g, int(variant)))
+
+
+def nb_group_train_step(g, n_obj: int, kind: int, seed: int, step: int, per_obj: int, alpha: float,
+                        beta: float = 1.0, lr: float = 1e-3, loss=None, counts=None, alpha_obj=None, stream=None):
+    _check(lib().nb_group_train_step(g, int(kind), int(seed), int(step), int(per_obj), float(alpha),
+                                     _dev(alpha_obj, torch.float32, "alpha_obj", n_obj), float(beta),
+                                     float(lr), _dev(loss, torch.float32, "loss", n_obj),
+                                     _dev(counts, torch.int64, "counts", 4 * n_obj), _stream(stream)))
+
+
+class Group:
+    """Owns an nb_group handle: n_obj bfloat16 bounds in_dim -> w_o^n_hidden -> 1."""
+
+    def __init__(self, in_dim: int, widths, n_hidden: int):
+        self.in_dim, self.widths, self.n_hidden = in_dim, list(widths), n_hidden
+        self.n_obj = len(self.widths)
+        self.handle = nb_group_create(in_dim, self.widths, n_hidden)
+        self.n_params = nb_group_num_params(self.handle)
+        self.offsets = nb_group_param_offsets(self.handle, self.n_obj)
+
+    def set_params(self, theta):
+        if isinstance(theta, np.ndarray):
+            theta = torch.from_numpy(np.ascontiguousarray(theta, dtype=np.float32)).cuda()
+        nb_group_set_params(self.handle, theta)
+
+    def params(self) -> torch.Tensor:
+        t = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        nb_group_get_params(self.handle, t)
+        return t
+
+    def set_voxels(self, grids: torch.Tensor, sizes):
+        nb_group_set_voxels(self.handle, grids, sizes)
+
+    def forward(self, q: torch.Tensor, qoff: torch.Tensor, eps: float = EPS_OUT):
+        n = q.shape[0]
+        z = torch.empty(n, dtype=torch.float32, device=q.device)
+        h = torch.empty(n, dtype=torch.uint8, device=q.device)
+        nb_group_forward(self.handle, self.n_obj, self.in_dim, q, qoff, eps, logits=z, h=h)
+        return z, h
+
+    def counts(self, q: torch.Tensor, qoff: torch.Tensor, g: torch.Tensor, eps: float = EPS_OUT) -> torch.Tensor:
+        """Per-object (TP, FP, TN, FN) of the bound's decisions against g: int64[n_obj, 4]."""
+        c = torch.empty(4 * self.n_obj, dtype=torch.int64, device=q.device)
+        nb_group_forward(self.handle, self.n_obj, self.in_dim, q, qoff, eps, g_exact=g, counts=c)
+        return c.view(self.n_obj, 4)
+
+    def query(self, kind, q: torch.Tensor, qoff: torch.Tensor) -> torch.Tensor:
+        out = torch.zeros(q.shape[0], dtype=torch.uint8, device=q.device)
+        nb_group_query_exact(self.handle, self.n_obj, KINDS.get(kind, kind), q, qoff, out)
+        return out
+
+    def close(self):
+        if self.handle:
+            nb_group_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # ------------------------------------------------------------ conveniences
 
 class Indicator:

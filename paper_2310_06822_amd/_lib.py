@@ -43,6 +43,18 @@ SIGNATURES = {
     "nb_bound_adam_step": (i32, [vp, vp, f32, f32, f32, f32, f32, f32, vp]),
     "nb_bound_train_step": (i32, [vp, vp, C.c_int, u64, u64, i64, f32, f32, f32, f32, f32, vp, vp, vp]),
     "nb_cascade": (i32, [vp, vp, C.c_int, vp, i64, f32, vp, vp, vp]),
+    "nb_group_create": (i32, [C.c_int, C.c_int, vp, C.c_int, C.c_int, PP]),
+    "nb_group_destroy": (i32, [vp]),
+    "nb_group_num_params": (i32, [vp, C.POINTER(i64)]),
+    "nb_group_param_offsets": (i32, [vp, vp]),
+    "nb_group_set_params": (i32, [vp, vp, i64, vp]),
+    "nb_group_get_params": (i32, [vp, vp, i64, vp]),
+    "nb_group_set_voxels": (i32, [vp, vp, vp]),
+    "nb_group_query_exact": (i32, [vp, C.c_int, vp, vp, i64, vp, vp]),
+    "nb_group_forward": (i32, [vp, vp, vp, i64, f32, vp, vp, vp, vp, vp]),
+    "nb_group_num_variants": (i32, [vp, C.POINTER(C.c_int)]),
+    "nb_group_set_variant": (i32, [vp, C.c_int]),
+    "nb_group_train_step": (i32, [vp, C.c_int, u64, u64, i64, f32, vp, f32, f32, vp, vp, vp]),
 }
 
 _lib = None

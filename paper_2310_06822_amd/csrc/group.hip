@@ -1,0 +1,358 @@
+// Many per-object bounds in one launch.
+//
+// The paper trains one bound per object (Sec. 3.4, "Training": no
+// generalisation across objects).  A group holds n_obj bfloat16 bounds of a
+// common depth and input size but their own widths (32, 64 or 128), each
+// with its own voxel grid.  Queries arrive grouped by object (CSR offsets).
+//
+// Forward: one persistent launch.  A single-block planner lays the work out
+// as tiles of 128 queries, objects ordered by decreasing width, and gives
+// each workgroup a contiguous run of tiles of equal estimated cost
+// (proportional to width^2 per tile); a workgroup reloads weights into LDS
+// only when its run crosses into the next object, so every object's weights
+// are read about once per workgroup that touches it.
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "nb_internal.h"
+#include "nb_mlp.h"
+#include "nb_adam.h"
+#include "nb_bf16_fwd.h"
+#include "nb_voxel.h"
+
+namespace {
+
+// Forward tile shapes (the variants the tuner picks from): threads per
+// workgroup and 16-query blocks per wave; a work item (tile) is
+// threads / 64 * blocks * 16 queries of one object.
+struct GroupShape {
+  int threads, blocks, wg_per_cu;
+};
+constexpr GroupShape kGroupShapes[] = {{256, 2, 4}, {512, 2, 2}, {256, 1, 4}, {512, 1, 2}, {1024, 1, 1}};
+constexpr int kGroupVariants = sizeof(kGroupShapes) / sizeof(kGroupShapes[0]);
+
+__host__ __device__ inline int frags_fwd(int W, int NH) { return W / 16 + (NH - 1) * (W / 16) * (W / 32); }
+
+// Work plan: item_off[p] = first tile of the p-th object in width order;
+// wg_first[w] = first tile of workgroup w (wg_first[G] = total tiles).  One
+// block: thread 0 takes the prefix sums over objects (tiles and cost), then
+// every thread places its workgroup boundaries by binary search, cutting the
+// tile sequence at equal shares of the total cost.
+constexpr int kMaxGroup = 4096;
+
+__global__ __launch_bounds__(256) void k_group_plan(const int64_t* __restrict__ qoff, int64_t n, int tile_q, int n_obj,
+                                                    const int* __restrict__ perm, const int* __restrict__ widths,
+                                                    int G, int64_t* __restrict__ item_off,
+                                                    int64_t* __restrict__ wg_first) {
+  __shared__ double cum[kMaxGroup + 1];   // cost of the tiles before object p (width order)
+  __shared__ int64_t sitem[kMaxGroup + 1];
+  if (threadIdx.x == 0) {
+    cum[0] = 0.0;
+    sitem[0] = 0;
+    for (int p = 0; p < n_obj; ++p) {
+      const int o = perm[p];
+      // an object whose rows are not inside [0, n) gets no tiles
+      const int64_t a = qoff[o], b = qoff[o + 1];
+      const int64_t nq = (a >= 0 && b <= n && b > a) ? b - a : 0;
+      const int64_t tiles = (nq + tile_q - 1) / tile_q;
+      sitem[p + 1] = sitem[p] + tiles;
+      cum[p + 1] = cum[p] + (double)tiles * ((double)widths[o] * widths[o] + 256.0);
+    }
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p <= n_obj; p += blockDim.x) item_off[p] = sitem[p];
+  const double total = cum[n_obj];
+  const int64_t n_tiles = sitem[n_obj];
+  for (int w = threadIdx.x; w <= G; w += blockDim.x) {
+    int64_t t;
+    if (w == 0) {
+      t = 0;
+    } else if (w == G) {
+      t = n_tiles;
+    } else {
+      // smallest t with cost(tiles [0, t)) >= target
+      const double target = total * (double)w / (double)G;
+      int lo = 0, hi = n_obj;   // last p with cum[p] < target (cum[0] = 0)
+      if (target <= 0.0) {
+        t = 0;
+      } else {
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) / 2;
+          if (cum[mid] < target) lo = mid; else hi = mid;
+        }
+        const int o = perm[lo];
+        const double cost = (double)widths[o] * widths[o] + 256.0;
+        const int64_t k = (int64_t)ceil((target - cum[lo]) / cost);
+        t = sitem[lo] + k;
+        if (t > sitem[lo + 1]) t = sitem[lo + 1];
+      }
+    }
+    wg_first[w] = t;
+  }
+}
+
+template <int NH>
+struct GroupLds {
+  static constexpr size_t bytes() {
+    return (size_t)frags_fwd(128, NH) * 64 * 16 + (size_t)(NH * 128 + 129) * 4;
+  }
+};
+
+// Adds a wave's confusion counts for object o to counts[o] and clears them.
+__device__ __forceinline__ void flush_counts(unsigned long long* __restrict__ counts, int o, unsigned (&cnt)[4]) {
+  if (counts && o >= 0) {
+    if ((threadIdx.x & 63) == 0)
+      for (int i = 0; i < 4; ++i)
+        if (cnt[i]) atomicAdd(counts + (int64_t)o * 4 + i, (unsigned long long)cnt[i]);
+    cnt[0] = cnt[1] = cnt[2] = cnt[3] = 0u;
+  }
+}
+
+template <int NH, int THREADS, int NB>
+__global__ __launch_bounds__(THREADS) void k_group_fwd(
+    const float* __restrict__ q, const int64_t* __restrict__ qoff, int n_obj, int in_dim,
+    const int* __restrict__ perm, const int* __restrict__ widths, const int64_t* __restrict__ poff,
+    const int64_t* __restrict__ pkoff, const float* __restrict__ theta, const bf16x8* __restrict__ pack,
+    const int64_t* __restrict__ item_off, const int64_t* __restrict__ wg_first, float tau,
+    float* __restrict__ logits, uint8_t* __restrict__ hout, const uint8_t* __restrict__ g,
+    unsigned long long* __restrict__ counts) {
+  constexpr int TILE = THREADS / 64 * NB * 16;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  bf16x8* swt = reinterpret_cast<bf16x8*>(smem_raw);
+  float* sbias = reinterpret_cast<float*>(smem_raw + (size_t)frags_fwd(128, NH) * 64 * 16);
+  const int64_t s = wg_first[blockIdx.x], e = wg_first[blockIdx.x + 1];
+  if (s >= e) return;
+  // object (in width order) of the first tile
+  int p = 0;
+  {
+    int lo = 0, hi = n_obj;   // last p with item_off[p] <= s
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) / 2;
+      if (item_off[mid] <= s) lo = mid; else hi = mid;
+    }
+    p = lo;
+  }
+  int cur = -1, W = 0;
+  unsigned cnt[4] = {0u, 0u, 0u, 0u};
+  const int wave = threadIdx.x >> 6;
+  for (int64_t it = s; it < e; ++it) {
+    while (it >= item_off[p + 1]) ++p;
+    const int o = perm[p];
+    if (o != cur) {
+      flush_counts(counts, cur, cnt);
+      __syncthreads();
+      W = widths[o];
+      const int nf = frags_fwd(W, NH);
+      const bf16x8* src = pack + pkoff[o];
+      for (int i = threadIdx.x; i < nf * 64; i += THREADS) swt[i] = src[i];
+      const float* th = theta + poff[o];
+      for (int i = threadIdx.x; i < NH * W; i += THREADS) sbias[i] = th[nb_b_off(i / W, in_dim, W, NH) + i % W];
+      for (int i = threadIdx.x; i < W + 1; i += THREADS) sbias[NH * W + i] = th[nb_w_off(NH, in_dim, W) + i];
+      __syncthreads();
+      cur = o;
+    }
+    const int64_t q0 = qoff[o] + (it - item_off[p]) * TILE + wave * (NB * 16);
+    const int64_t n_end = qoff[o + 1];
+    if (W == 32)
+      bf16_fwd_tile<32, NH, NB>(swt, sbias, q, n_end, in_dim, q0, tau, logits, hout, g, counts, cnt);
+    else if (W == 64)
+      bf16_fwd_tile<64, NH, NB>(swt, sbias, q, n_end, in_dim, q0, tau, logits, hout, g, counts, cnt);
+    else
+      bf16_fwd_tile<128, NH, NB>(swt, sbias, q, n_end, in_dim, q0, tau, logits, hout, g, counts, cnt);
+  }
+  flush_counts(counts, cur, cnt);
+}
+
+// Grouped exact query: every query finds its object by binary search over
+// the CSR offsets and runs the voxel test on that object's grid.
+__global__ void k_group_exact(int kind, const float* __restrict__ q, const int64_t* __restrict__ qoff, int n_obj,
+                              int64_t n, const uint8_t* __restrict__ grids, const int64_t* __restrict__ goff,
+                              const int* __restrict__ gn, const float* __restrict__ ray_t, uint8_t* __restrict__ g) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || i < qoff[0] || i >= qoff[n_obj]) return;
+  int lo = 0, hi = n_obj;   // last o with qoff[o] <= i
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (qoff[mid] <= i) lo = mid; else hi = mid;
+  }
+  g[i] = nb_voxel_query(kind, q, i, grids + goff[lo], gn[lo], ray_t);
+}
+
+// Grouped pack: every element of every object's forward (and, for training,
+// transposed) fragments.
+__global__ void k_group_pack(const float* __restrict__ theta, const int64_t* __restrict__ poff,
+                             const int64_t* __restrict__ pkoff, const int64_t* __restrict__ ptoff,
+                             const int* __restrict__ widths, int n_obj, int in_dim, int NH,
+                             uint16_t* __restrict__ pack, uint16_t* __restrict__ packT, int64_t total_fwd,
+                             int64_t total_t) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool t = idx >= total_fwd;
+  const int64_t e = t ? idx - total_fwd : idx;
+  if (e >= (t ? total_t : total_fwd)) return;
+  const int64_t* off = t ? ptoff : pkoff;   // in 16-byte slices
+  int lo = 0, hi = n_obj;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (off[mid] * 8 <= e) lo = mid; else hi = mid;
+  }
+  const int64_t local = e - off[lo] * 8;
+  if (t)
+    packT[e] = nb_bf16_pack_t_elem(theta + poff[lo], in_dim, widths[lo], NH, local);
+  else
+    pack[e] = nb_bf16_pack_elem(theta + poff[lo], in_dim, widths[lo], NH, local);
+}
+
+// Sum of the per-chunk partials of every parameter of every object, in chunk
+// order, then one Adam step.  32 parameters per block, 8 strided partial
+// sums per parameter added in order (as for a single bound).
+__global__ __launch_bounds__(256) void k_group_reduce(const float* __restrict__ partial, int n_wg, int n_obj,
+                                                      const int64_t* __restrict__ poff, const int* __restrict__ widths,
+                                                      int in_dim, int NH, float* __restrict__ theta,
+                                                      float* __restrict__ m, float* __restrict__ v, AdamArgs adam) {
+  __shared__ float part[8][32];
+  const int t = threadIdx.x, j = t % 32, k = t / 32;
+  const int64_t p = (int64_t)blockIdx.x * 32 + j;
+  const int64_t P_all = poff[n_obj];
+  int o = 0;
+  float sacc = 0.0f;
+  if (p < P_all) {
+    int lo = 0, hi = n_obj;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) / 2;
+      if (poff[mid] <= p) lo = mid; else hi = mid;
+    }
+    o = lo;
+    const int64_t Po = poff[o + 1] - poff[o], pl = p - poff[o];
+    const float* base = partial + (int64_t)n_wg * poff[o] + pl;
+    for (int w = k; w < n_wg; w += 8) sacc += base[(int64_t)w * Po];
+  }
+  part[k][j] = sacc;
+  __syncthreads();
+  if (t < 32 && p < P_all) {
+    float tot = part[0][t];
+#pragma unroll
+    for (int i = 1; i < 8; ++i) tot += part[i][t];
+    const int64_t pl = p - poff[o];
+    nb_adam_update(p, tot, theta, m, v, adam, nb_is_weight(pl, in_dim, widths[o], NH) != 0);
+  }
+}
+
+// Per-object mean loss and confusion counts of a grouped training step.
+__global__ void k_group_aux(const float* __restrict__ aux, int n_wg, int n_obj, float loss_scale,
+                            float* __restrict__ loss, unsigned long long* __restrict__ counts) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n_obj) return;
+  float ls = 0.0f;
+  unsigned long long cs[4] = {0, 0, 0, 0};
+  const float* a = aux + (int64_t)o * n_wg * 8;
+  for (int w = 0; w < n_wg; ++w) {
+    ls += a[w * 8];
+    for (int i = 0; i < 4; ++i) cs[i] += __float_as_uint(a[w * 8 + 1 + i]);
+  }
+  if (loss) loss[o] = ls * loss_scale;
+  if (counts)
+    for (int i = 0; i < 4; ++i) counts[(int64_t)o * 4 + i] = cs[i];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host side
+
+nb_status group_reduce_adam(const nb_group* gr, int n_wg, const AdamArgs& adam, float* loss,
+                            unsigned long long* counts, float loss_scale, hipStream_t s) {
+  const unsigned blocks = (unsigned)((gr->n_params + 31) / 32);
+  k_group_reduce<<<blocks, 256, 0, s>>>(gr->partial, n_wg, gr->n_obj, gr->d_poff, gr->d_widths, gr->in_dim,
+                                        gr->n_hidden, gr->theta, gr->m, gr->v, adam);
+  NB_LAUNCHED();
+  if (loss || counts) {
+    k_group_aux<<<(unsigned)((gr->n_obj + 255) / 256), 256, 0, s>>>(gr->aux, n_wg, gr->n_obj, loss_scale, loss,
+                                                                   counts);
+    NB_LAUNCHED();
+  }
+  return NB_OK;
+}
+
+int group_variants() { return kGroupVariants; }
+
+namespace {
+
+int group_wgs(const GroupShape& sh) { return std::max(1, std::min(sh.wg_per_cu * nb_cu_count(), 1 << 14)); }
+
+template <int NH, int THREADS, int NB>
+nb_status group_fwd_launch(const nb_group* gr, const float* q, const int64_t* qoff, int G, float tau,
+                           float* logits, uint8_t* h, const uint8_t* g, unsigned long long* counts, hipStream_t s) {
+  const size_t lds = GroupLds<NH>::bytes();
+  static bool attr[64] = {false};
+  int dev = 0;
+  NB_HIP(hipGetDevice(&dev));
+  if (dev >= 0 && dev < 64 && !attr[dev]) {
+    NB_HIP(hipFuncSetAttribute((const void*)k_group_fwd<NH, THREADS, NB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds));
+    attr[dev] = true;
+  }
+  k_group_fwd<NH, THREADS, NB><<<G, THREADS, lds, s>>>(
+      q, qoff, gr->n_obj, gr->in_dim, gr->d_perm, gr->d_widths, gr->d_poff, gr->d_pkoff, gr->theta,
+      reinterpret_cast<const bf16x8*>(gr->pack16), gr->d_item_off, gr->d_wg_first, tau, logits, h, g, counts);
+  NB_LAUNCHED();
+  return NB_OK;
+}
+
+template <int NH>
+nb_status group_fwd_nh(const nb_group* gr, int variant, const float* q, const int64_t* qoff, int G, float tau,
+                       float* logits, uint8_t* h, const uint8_t* g, unsigned long long* counts, hipStream_t s) {
+  switch (variant) {
+    case 0: return group_fwd_launch<NH, 256, 2>(gr, q, qoff, G, tau, logits, h, g, counts, s);
+    case 1: return group_fwd_launch<NH, 512, 2>(gr, q, qoff, G, tau, logits, h, g, counts, s);
+    case 2: return group_fwd_launch<NH, 256, 1>(gr, q, qoff, G, tau, logits, h, g, counts, s);
+    case 3: return group_fwd_launch<NH, 512, 1>(gr, q, qoff, G, tau, logits, h, g, counts, s);
+    case 4: return group_fwd_launch<NH, 1024, 1>(gr, q, qoff, G, tau, logits, h, g, counts, s);
+    default: break;
+  }
+  nb_set_error("grouped forward variant %d out of range", variant);
+  return NB_ERR_INVALID_ARG;
+}
+
+}  // namespace
+
+nb_status group_forward(const nb_group* gr, const float* q, const int64_t* qoff, int64_t n, float tau,
+                        float* logits, uint8_t* h, const uint8_t* g, unsigned long long* counts, hipStream_t s) {
+  const int v = gr->variant;
+  if (v < 0 || v >= kGroupVariants) {
+    nb_set_error("grouped forward variant %d out of range", v);
+    return NB_ERR_INVALID_ARG;
+  }
+  const GroupShape sh = kGroupShapes[v];
+  const int G = std::min(group_wgs(sh), gr->n_wg_cap);
+  const int tile_q = sh.threads / 64 * sh.blocks * 16;
+  if (counts) NB_TRY(launch_zero_u64(counts, 4 * gr->n_obj, s));
+  k_group_plan<<<1, 256, 0, s>>>(qoff, n, tile_q, gr->n_obj, gr->d_perm, gr->d_widths, G, gr->d_item_off,
+                                 gr->d_wg_first);
+  NB_LAUNCHED();
+  switch (gr->n_hidden) {
+    case 2: return group_fwd_nh<2>(gr, v, q, qoff, G, tau, logits, h, g, counts, s);
+    case 3: return group_fwd_nh<3>(gr, v, q, qoff, G, tau, logits, h, g, counts, s);
+    case 4: return group_fwd_nh<4>(gr, v, q, qoff, G, tau, logits, h, g, counts, s);
+    default: break;
+  }
+  nb_set_error("grouped forward supports 2..4 hidden layers");
+  return NB_ERR_UNSUPPORTED;
+}
+
+nb_status group_exact(const nb_group* gr, int kind, const float* q, const int64_t* qoff, int64_t n, uint8_t* g,
+                      hipStream_t s) {
+  k_group_exact<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(kind, q, qoff, gr->n_obj, n, gr->grids, gr->d_goff,
+                                                           gr->d_gn, gr->ray_t, g);
+  NB_LAUNCHED();
+  return NB_OK;
+}
+
+nb_status group_pack(const nb_group* gr, hipStream_t s) {
+  const int64_t tf = gr->pack_elems, tt = gr->packt_elems;
+  const int64_t total = tf + tt;
+  k_group_pack<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(gr->theta, gr->d_poff, gr->d_pkoff, gr->d_ptoff,
+                                                              gr->d_widths, gr->n_obj, gr->in_dim, gr->n_hidden,
+                                                              gr->pack16, gr->pack16t, tf, tt);
+  NB_LAUNCHED();
+  return NB_OK;
+}

@@ -24,74 +24,21 @@
 
 #include "nb_internal.h"
 #include "nb_mlp.h"
+#include "nb_bf16_fwd.h"
 
 namespace {
 
-typedef nb_bf16x8 bf16x8;
-typedef nb_floatx4 floatx4;
-
-__device__ __forceinline__ floatx4 mfma32(bf16x8 a, bf16x8 b, floatx4 c) { return nb_mfma_bf16(a, b, c); }
-
 // ------------------------------------------------------------------ packing
-//
-// pack[(f*64 + lane)*8 + j] (bfloat16 bits), c = lane % 16, g = lane / 16:
-//   f < RB            first layer, block mo = f:
-//                       g = 0, 1: W0_hi[16mo + c][j];  g = 2: W0_lo[16mo + c][j];
-//                       g = 3: 0;  (0 for j >= in_dim)
-//   f < NFWD          hidden layer l (1-based), fragment (mo, ks), f = RB + (l-1)*FH + mo*KS + ks:
-//                       W_l[16mo + c][32ks + 16(j/4) + 4g + (j%4)]
+
+// Forward fragment pack (layout in nb_bf16_pack_elem).
 __global__ void k_pack_bf16(const float* __restrict__ theta, int in_dim, int W, int NH, uint16_t* __restrict__ pack,
                             int64_t total) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  const int j = (int)(idx & 7), lane = (int)((idx >> 3) & 63);
-  const int f = (int)(idx >> 9);
-  const int c = lane & 15, g = lane >> 4;
-  const int RB = W / 16, KS = W / 32, FH = RB * KS;
-  uint16_t v = 0;
-  if (f < RB) {
-    if (j < in_dim && g < 3) {
-      const float w = theta[(int64_t)(16 * f + c) * in_dim + j];
-      const uint16_t hi = nb_bf16_bits(w);
-      v = g < 2 ? hi : nb_bf16_bits(w - nb_bf16_value(hi));
-    }
-  } else {
-    const int t = f - RB;
-    const int l = 1 + t / FH, rem = t % FH, mo = rem / KS, ks = rem % KS;
-    const float* Wl = theta + nb_w_off(l, in_dim, W);
-    v = nb_bf16_bits(Wl[(int64_t)(16 * mo + c) * W + 32 * ks + 16 * (j / 4) + 4 * g + (j % 4)]);
-  }
-  pack[idx] = v;
+  pack[idx] = nb_bf16_pack_elem(theta, in_dim, W, NH, idx);
 }
 
 // ------------------------------------------------------------------ forward
-
-template <int W, int NH>
-struct B16 {
-  static constexpr int RB = W / 16;
-  static constexpr int KS = W / 32;
-  static constexpr int FH = RB * KS;
-  static constexpr int NFWD = RB + (NH - 1) * FH;
-  static constexpr int kBias = NH * W + W + 1;   // hidden biases, output weights, output bias
-  static constexpr size_t lds_bytes() { return (size_t)NFWD * 64 * 16 + (size_t)kBias * 4; }
-};
-
-template <int NB>
-__device__ __forceinline__ void load_inputs(const float* __restrict__ q, int64_t n, int in_dim, int64_t q0, int c,
-                                            int grp, bf16x8 (&xb)[NB]) {
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    const int64_t qi = q0 + nb * 16 + c;
-    const bool valid = qi < n;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const float x = (valid && j < in_dim) ? q[qi * in_dim + j] : 0.0f;
-      const __bf16 hi = (__bf16)x;
-      const __bf16 lo = (__bf16)(x - (float)hi);
-      xb[nb][j] = grp == 1 ? lo : (grp == 3 ? (__bf16)0.0f : hi);
-    }
-  }
-}
 
 template <int W, int NH, int NB, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_fwd_bf16(const float* __restrict__ q, int64_t n, int in_dim,
@@ -99,98 +46,22 @@ __global__ __launch_bounds__(THREADS) void k_fwd_bf16(const float* __restrict__ 
                                                   float tau, float* __restrict__ logits, uint8_t* __restrict__ hout,
                                                   const uint8_t* __restrict__ g, unsigned long long* __restrict__ counts) {
   using N = B16<W, NH>;
-  constexpr int RB = N::RB, KS = N::KS;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   bf16x8* swt = reinterpret_cast<bf16x8*>(smem_raw);
   float* sbias = reinterpret_cast<float*>(smem_raw + (size_t)N::NFWD * 64 * 16);
-  const float* swo = sbias + NH * W;
 
   for (int i = threadIdx.x; i < N::NFWD * 64; i += blockDim.x) swt[i] = pack[i];
   for (int i = threadIdx.x; i < NH * W; i += blockDim.x) sbias[i] = theta[nb_b_off(i / W, in_dim, W, NH) + i % W];
   for (int i = threadIdx.x; i < W + 1; i += blockDim.x) sbias[NH * W + i] = theta[nb_w_off(NH, in_dim, W) + i];
   __syncthreads();
 
-  const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4;
+  const int lane = threadIdx.x & 63;
   const int waves = blockDim.x >> 6;
-  const float bo = swo[W];
-
   unsigned cnt[4] = {0u, 0u, 0u, 0u};
   const int64_t tiles = (n + NB * 16 - 1) / (NB * 16);
   for (int64_t tile = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6); tile < tiles;
-       tile += (int64_t)gridDim.x * waves) {
-    const int64_t q0 = tile * NB * 16;
-    floatx4 acc[NB][RB];
-    {
-      bf16x8 xb[NB];
-      load_inputs<NB>(q, n, in_dim, q0, c, grp, xb);
-#pragma unroll
-      for (int mo = 0; mo < RB; ++mo) {
-        const float* b = sbias + 16 * mo + 4 * grp;
-        const floatx4 bi = floatx4{b[0], b[1], b[2], b[3]};
-        const bf16x8 a = swt[mo * 64 + lane];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = mfma32(a, xb[nb], bi);
-      }
-    }
-#pragma unroll
-    for (int l = 1; l < NH; ++l) {
-      bf16x8 act[NB][KS];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-          for (int j = 0; j < 8; ++j) act[nb][ks][j] = (__bf16)fmaxf(acc[nb][2 * ks + j / 4][j % 4], 0.0f);
-      const bf16x8* fr = swt + (RB + (l - 1) * N::FH) * 64 + lane;
-      // two fragment slots: row block mo computes while mo + 1's fragments load
-      bf16x8 fa[KS], fb[KS];
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) fa[ks] = fr[ks * 64];
-#pragma unroll
-      for (int mo = 0; mo < RB; ++mo) {
-        bf16x8(&cur)[KS] = (mo & 1) ? fb : fa;
-        bf16x8(&nxt)[KS] = (mo & 1) ? fa : fb;
-        if (mo + 1 < RB) {
-#pragma unroll
-          for (int ks = 0; ks < KS; ++ks) nxt[ks] = fr[((mo + 1) * KS + ks) * 64];
-        }
-        const float* b = sbias + l * W + 16 * mo + 4 * grp;
-        const floatx4 bi = floatx4{b[0], b[1], b[2], b[3]};
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = bi;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = mfma32(cur[ks], act[nb][ks], acc[nb][mo]);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      float p = 0.0f;
-#pragma unroll
-      for (int mo = 0; mo < RB; ++mo)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) p = fmaf(swo[16 * mo + 4 * grp + r], fmaxf(acc[nb][mo][r], 0.0f), p);
-      p += __shfl_xor(p, 16);
-      p += __shfl_xor(p, 32);
-      const float z = p + bo;
-      const int64_t qi = q0 + nb * 16 + c;
-      const bool own = grp == 0 && qi < n;
-      const bool pos = !(z < tau);
-      if (own) {
-        if (logits) logits[qi] = z;
-        if (hout) hout[qi] = pos;
-      }
-      if (counts) {
-        const bool gv = own && g[qi] != 0;
-        cnt[0] += __popcll(__ballot(own && pos && gv));
-        cnt[1] += __popcll(__ballot(own && pos && !gv));
-        cnt[2] += __popcll(__ballot(own && !pos && !gv));
-        cnt[3] += __popcll(__ballot(own && !pos && gv));
-      }
-    }
-  }
+       tile += (int64_t)gridDim.x * waves)
+    bf16_fwd_tile<W, NH, NB>(swt, sbias, q, n, in_dim, tile * NB * 16, tau, logits, hout, g, counts, cnt);
   if (counts && lane == 0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)

@@ -30,6 +30,33 @@ namespace {
 typedef nb_bf16x8 bf16x8;
 typedef nb_floatx4 floatx4;
 
+// Which bound a workgroup trains: blockIdx.y selects a member of a list of
+// same-width bounds (a group's width class); a single bound has no list.
+struct TrObjs {
+  const int* objs;        // member -> object id (nullptr: one bound, object 0)
+  const int64_t* poff;    // parameter offset per object (nullptr: 0)
+  const int64_t* pkoff;   // forward-pack offset per object, 16-byte slices
+  const int64_t* ptoff;   // transposed-pack offset per object, 16-byte slices
+  int64_t q_stride;       // batch rows per object
+  int64_t ms_a, ms_d;     // activation / gradient workspace elements per member
+  int64_t P;              // parameters of the single bound (objs == nullptr)
+  const float* alpha;     // per-object FN weight of Eq. 1 (nullptr: the scalar alpha)
+};
+
+struct TrObj {
+  int o, member;
+  int64_t poff, P;
+};
+
+__device__ __forceinline__ TrObj tr_obj(const TrObjs& T) {
+  TrObj r;
+  r.member = blockIdx.y;
+  r.o = T.objs ? T.objs[r.member] : 0;
+  r.poff = T.poff ? T.poff[r.o] : 0;
+  r.P = T.poff ? T.poff[r.o + 1] - r.poff : T.P;
+  return r;
+}
+
 __device__ __forceinline__ uint16_t bits_of(__bf16 v) { return __builtin_bit_cast(uint16_t, v); }
 __device__ __forceinline__ __bf16 bf16_of(uint16_t v) { return __builtin_bit_cast(__bf16, v); }
 
@@ -72,12 +99,7 @@ __global__ void k_pack_bf16_t(const float* __restrict__ theta, int in_dim, int W
                               int64_t total) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  const int j = (int)(idx & 7), lane = (int)((idx >> 3) & 63), f = (int)(idx >> 9);
-  const int c = lane & 15, g = lane >> 4;
-  const int RB = W / 16, KS = W / 32, FH = RB * KS;
-  const int l = 1 + f / FH, rem = f % FH, mo = rem / KS, ks = rem % KS;
-  const float* Wl = theta + nb_w_off(l, in_dim, W);
-  pack[idx] = nb_bf16_bits(Wl[(int64_t)(32 * ks + 8 * g + j) * W + 16 * mo + c]);
+  pack[idx] = nb_bf16_pack_t_elem(theta, in_dim, W, NH, idx);
 }
 
 // ------------------------------------------------------------ first layer
@@ -85,8 +107,13 @@ __global__ void k_pack_bf16_t(const float* __restrict__ theta, int in_dim, int W
 template <int W>
 __global__ __launch_bounds__(256) void k_tr_first(const float* __restrict__ q, int64_t n, int in_dim, int64_t Bp,
                                                   const bf16x8* __restrict__ pack, const float* __restrict__ theta,
-                                                  uint16_t* __restrict__ A0) {
+                                                  uint16_t* __restrict__ A0, TrObjs T) {
   constexpr int RB = W / 16;
+  const TrObj ob = tr_obj(T);
+  q += ob.o * T.q_stride * in_dim;
+  pack += T.pkoff ? T.pkoff[ob.o] : 0;
+  theta += ob.poff;
+  A0 += ob.member * T.ms_a;
   __shared__ bf16x8 sw[RB * 64];
   __shared__ float sb[W];
   for (int i = threadIdx.x; i < RB * 64; i += blockDim.x) sw[i] = pack[i];
@@ -131,10 +158,22 @@ __global__ __launch_bounds__(256) void k_tr_hidden(const uint16_t* __restrict__ 
                                                    int in_dim, int NH, const bf16x8* __restrict__ pack,
                                                    const float* __restrict__ theta, uint16_t* __restrict__ Aout,
                                                    const uint8_t* __restrict__ y, float alpha, float beta, float inv_n,
-                                                   float tau, float* __restrict__ partial, int64_t P,
-                                                   float* __restrict__ aux) {
+                                                   float tau, float* __restrict__ partial,
+                                                   float* __restrict__ aux, TrObjs TO) {
   using T = TrHidden<W>;
   constexpr int RB = T::RB, KS = T::KS;
+  const TrObj ob = tr_obj(TO);
+  const int64_t P = ob.P;
+  pack += TO.pkoff ? TO.pkoff[ob.o] : 0;
+  theta += ob.poff;
+  Ain += ob.member * TO.ms_a;
+  Aout += ob.member * (HEAD ? TO.ms_d : TO.ms_a);
+  if (HEAD) {
+    if (TO.alpha) alpha = TO.alpha[ob.o];
+    y += ob.o * TO.q_stride;
+    partial += (int64_t)gridDim.x * ob.poff;
+    aux += (int64_t)ob.o * gridDim.x * 8;
+  }
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   bf16x8* sw = reinterpret_cast<bf16x8*>(smem_raw);
   float* sb = reinterpret_cast<float*>(smem_raw + (size_t)T::FH * 64 * 16);   // [W] bias, [W] w_out, b_out
@@ -274,8 +313,13 @@ __global__ __launch_bounds__(256) void k_tr_hidden(const uint16_t* __restrict__ 
 template <int W>
 __global__ __launch_bounds__(256) void k_tr_data(const uint16_t* __restrict__ Dl, const uint16_t* __restrict__ Aprev,
                                                  int64_t Bp, int l, const bf16x8* __restrict__ packT,
-                                                 uint16_t* __restrict__ Dprev) {
+                                                 uint16_t* __restrict__ Dprev, TrObjs TO) {
   using T = TrHidden<W>;
+  const TrObj ob = tr_obj(TO);
+  packT += TO.ptoff ? TO.ptoff[ob.o] : 0;
+  Dl += ob.member * TO.ms_d;
+  Dprev += ob.member * TO.ms_d;
+  Aprev += ob.member * TO.ms_a;
   constexpr int RB = T::RB, KS = T::KS;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   bf16x8* sw = reinterpret_cast<bf16x8*>(smem_raw);
@@ -316,8 +360,13 @@ constexpr int kTS = 40;   // LDS row stride of a [width][32 queries] bfloat16 ti
 template <int W, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_tr_weight(const uint16_t* __restrict__ Dl,
                                                           const uint16_t* __restrict__ Aprev, int64_t CH, int l,
-                                                          int in_dim, int NH, float* __restrict__ partial, int64_t P) {
+                                                          int in_dim, int NH, float* __restrict__ partial, TrObjs TO) {
   constexpr int RB = W / 16, TILES = RB * RB, TPW = TILES / WAVES;
+  const TrObj ob = tr_obj(TO);
+  const int64_t P = ob.P;
+  Dl += ob.member * TO.ms_d;
+  Aprev += ob.member * TO.ms_a;
+  partial += (int64_t)gridDim.x * ob.poff;
   static_assert(TILES % WAVES == 0, "tiles must split evenly over the waves");
   constexpr int THREADS = WAVES * 64;
   constexpr int PAIRS = W / 2;
@@ -410,7 +459,12 @@ constexpr int kFGSlab = 256;
 
 __global__ __launch_bounds__(kFG) void k_tr_first_grad(const uint16_t* __restrict__ D0, const float* __restrict__ q,
                                                        int64_t n, int64_t CH, int in_dim, int W, int NH,
-                                                       float* __restrict__ partial, int64_t P) {
+                                                       float* __restrict__ partial, TrObjs TO) {
+  const TrObj ob = tr_obj(TO);
+  const int64_t P = ob.P;
+  D0 += ob.member * TO.ms_d;
+  q += ob.o * TO.q_stride * in_dim;
+  partial += (int64_t)gridDim.x * ob.poff;
   __shared__ float red[kFG * 9];
   __shared__ float sx[kFGSlab * 8];
   const int S = kFG / W, nn = threadIdx.x % W, sub = threadIdx.x / W;
@@ -458,51 +512,80 @@ nb_status allow_lds(K kernel, size_t bytes) {
   return NB_OK;
 }
 
-template <int W>
-nb_status train_w(const nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha, float beta,
-                  float tau, const BF16TrainPlan& pl, hipStream_t s) {
-  using T = TrHidden<W>;
-  const int NH = b->n_hidden, in_dim = b->in_dim;
-  const int64_t P = b->n_params, CH = pl.chunk;
-  const unsigned grid = (unsigned)pl.n_wg;
-  const auto* pack = reinterpret_cast<const bf16x8*>(b->pack16);
-  const auto* packT = reinterpret_cast<const bf16x8*>(b->pack16t);
-  const float inv_n = (float)(1.0 / (double)n);
-  const size_t lds = T::lds_bytes();
-  uint16_t* A = b->tr_act;                                   // A_l at A + l * Bp * W
-  const int64_t stride = pl.padded * W;
-  uint16_t* D[2] = {b->tr_grad, b->tr_grad + stride};
+// One training pass over `members` same-width bounds (gridDim.y).
+struct TrainJob {
+  int in_dim = 0, NH = 0, members = 1;
+  int64_t n = 0;                    // valid queries per bound
+  BF16TrainPlan plan;
+  const float* q = nullptr;
+  const uint8_t* y = nullptr;
+  const float* theta = nullptr;
+  const bf16x8* pack = nullptr;
+  const bf16x8* packT = nullptr;
+  uint16_t* act = nullptr;          // member 0: A_l at act + l * Bp * W
+  uint16_t* grad = nullptr;         // member 0: D ping-pong at grad + k * Bp * W
+  float* partial = nullptr;
+  float* aux = nullptr;
+  float alpha = 1, beta = 1, inv_n = 1, tau = 0;
+  TrObjs T{};
+};
 
-  const unsigned wide = (unsigned)std::max<int64_t>(1, std::min<int64_t>(pl.padded / 64, 4 * (int64_t)nb_cu_count()));
-  k_tr_first<W><<<wide, 256, 0, s>>>(q, n, in_dim, pl.padded, pack, b->theta, A);
+template <int W>
+nb_status train_w(const TrainJob& J, hipStream_t s) {
+  using T = TrHidden<W>;
+  const int NH = J.NH, in_dim = J.in_dim;
+  const int64_t CH = J.plan.chunk;
+  const dim3 grid((unsigned)J.plan.n_wg, (unsigned)J.members);
+  const size_t lds = T::lds_bytes();
+  const int64_t stride = J.plan.padded * W;
+  uint16_t* A = J.act;
+  uint16_t* D[2] = {J.grad, J.grad + stride};
+  const unsigned wx = (unsigned)std::max<int64_t>(
+      1, std::min<int64_t>(J.plan.padded / 64, std::max<int64_t>(1, 4 * (int64_t)nb_cu_count() / J.members)));
+  const dim3 wide(wx, (unsigned)J.members);
+
+  k_tr_first<W><<<wide, 256, 0, s>>>(J.q, J.n, in_dim, J.plan.padded, J.pack, J.theta, A, J.T);
   NB_LAUNCHED();
   NB_TRY(allow_lds(k_tr_hidden<W, false>, lds));
   NB_TRY(allow_lds(k_tr_hidden<W, true>, lds));
   NB_TRY(allow_lds(k_tr_data<W>, (size_t)T::FH * 64 * 16));
   for (int l = 1; l < NH - 1; ++l) {
-    k_tr_hidden<W, false><<<wide, 256, lds, s>>>(A + (l - 1) * stride, n, pl.padded, l, in_dim, NH, pack, b->theta,
-                                                 A + l * stride, nullptr, 0, 0, 0, tau, nullptr, P, nullptr);
+    k_tr_hidden<W, false><<<wide, 256, lds, s>>>(A + (l - 1) * stride, J.n, J.plan.padded, l, in_dim, NH, J.pack,
+                                                 J.theta, A + l * stride, nullptr, 0, 0, 0, J.tau, nullptr, nullptr,
+                                                 J.T);
     NB_LAUNCHED();
   }
   // head: layer NH-1, output layer, loss, D_{NH-1}
   int cur = 0;
-  k_tr_hidden<W, true><<<grid, 256, lds, s>>>(A + (NH - 2) * stride, n, CH, NH - 1, in_dim, NH, pack, b->theta,
-                                              D[cur], y, alpha, beta, inv_n, tau, b->partial, P, b->aux);
+  k_tr_hidden<W, true><<<grid, 256, lds, s>>>(A + (NH - 2) * stride, J.n, CH, NH - 1, in_dim, NH, J.pack, J.theta,
+                                              D[cur], J.y, J.alpha, J.beta, J.inv_n, J.tau, J.partial, J.aux, J.T);
   NB_LAUNCHED();
   constexpr int WW = W >= 256 ? 8 : 4;
   const size_t wlds = (size_t)4 * W * kTS * 2 + (size_t)(WW * 64 / (W / 2)) * W * 4;
   NB_TRY(allow_lds(k_tr_weight<W, WW>, wlds));
   for (int l = NH - 1; l >= 1; --l) {
-    k_tr_weight<W, WW><<<grid, WW * 64, wlds, s>>>(D[cur], A + (l - 1) * stride, CH, l, in_dim, NH, b->partial, P);
+    k_tr_weight<W, WW><<<grid, WW * 64, wlds, s>>>(D[cur], A + (l - 1) * stride, CH, l, in_dim, NH, J.partial, J.T);
     NB_LAUNCHED();
-    k_tr_data<W><<<wide, 256, (size_t)T::FH * 64 * 16, s>>>(D[cur], A + (l - 1) * stride, pl.padded, l, packT,
-                                                           D[cur ^ 1]);
+    k_tr_data<W><<<wide, 256, (size_t)T::FH * 64 * 16, s>>>(D[cur], A + (l - 1) * stride, J.plan.padded, l, J.packT,
+                                                           D[cur ^ 1], J.T);
     NB_LAUNCHED();
     cur ^= 1;
   }
-  k_tr_first_grad<<<grid, kFG, 0, s>>>(D[cur], q, n, CH, in_dim, W, NH, b->partial, P);
+  k_tr_first_grad<<<grid, kFG, 0, s>>>(D[cur], J.q, J.n, CH, in_dim, W, NH, J.partial, J.T);
   NB_LAUNCHED();
   return NB_OK;
+}
+
+nb_status train_dispatch(int W, const TrainJob& J, hipStream_t s) {
+  switch (W) {
+    case 32: return train_w<32>(J, s);
+    case 64: return train_w<64>(J, s);
+    case 128: return train_w<128>(J, s);
+    case 256: return train_w<256>(J, s);
+    default: break;
+  }
+  nb_set_error("bfloat16 training has no kernel for width %d", W);
+  return NB_ERR_UNSUPPORTED;
 }
 
 }  // namespace
@@ -538,13 +621,55 @@ nb_status bf16_pack_t(const nb_bound* b, hipStream_t s) {
 
 nb_status bf16_train_partials(const nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha,
                               float beta, float tau, const BF16TrainPlan& plan, hipStream_t s) {
-  switch (b->width) {
-    case 32: return train_w<32>(b, q, y, n, alpha, beta, tau, plan, s);
-    case 64: return train_w<64>(b, q, y, n, alpha, beta, tau, plan, s);
-    case 128: return train_w<128>(b, q, y, n, alpha, beta, tau, plan, s);
-    case 256: return train_w<256>(b, q, y, n, alpha, beta, tau, plan, s);
-    default: break;
-  }
-  nb_set_error("bfloat16 training has no kernel for width %d", b->width);
-  return NB_ERR_UNSUPPORTED;
+  TrainJob J;
+  J.in_dim = b->in_dim;
+  J.NH = b->n_hidden;
+  J.members = 1;
+  J.n = n;
+  J.plan = plan;
+  J.q = q;
+  J.y = y;
+  J.theta = b->theta;
+  J.pack = reinterpret_cast<const bf16x8*>(b->pack16);
+  J.packT = reinterpret_cast<const bf16x8*>(b->pack16t);
+  J.act = b->tr_act;
+  J.grad = b->tr_grad;
+  J.partial = b->partial;
+  J.aux = b->aux;
+  J.alpha = alpha;
+  J.beta = beta;
+  J.inv_n = (float)(1.0 / (double)n);
+  J.tau = tau;
+  J.T = TrObjs{nullptr, nullptr, nullptr, nullptr, 0, 0, 0, b->n_params, nullptr};
+  return train_dispatch(b->width, J, s);
+}
+
+nb_status bf16_group_train_class(const nb_group* gr, int width, const int* d_members, int n_members,
+                                 const float* q, const uint8_t* y, int64_t per_obj, float alpha,
+                                 const float* alpha_obj, float beta,
+                                 float tau, const BF16TrainPlan& plan, uint16_t* act, uint16_t* grad,
+                                 hipStream_t s) {
+  TrainJob J;
+  J.in_dim = gr->in_dim;
+  J.NH = gr->n_hidden;
+  J.members = n_members;
+  J.n = per_obj;
+  J.plan = plan;
+  J.q = q;
+  J.y = y;
+  J.theta = gr->theta;
+  J.pack = reinterpret_cast<const bf16x8*>(gr->pack16);
+  J.packT = reinterpret_cast<const bf16x8*>(gr->pack16t);
+  J.act = act;
+  J.grad = grad;
+  J.partial = gr->partial;
+  J.aux = gr->aux;
+  J.alpha = alpha;
+  J.beta = beta;
+  J.inv_n = (float)(1.0 / (double)per_obj);
+  J.tau = tau;
+  const int64_t per_a = (int64_t)(gr->n_hidden - 1) * plan.padded * width;
+  const int64_t per_d = (int64_t)2 * plan.padded * width;
+  J.T = TrObjs{d_members, gr->d_poff, gr->d_pkoff, gr->d_ptoff, per_obj, per_a, per_d, 0, alpha_obj};
+  return train_dispatch(width, J, s);
 }

@@ -1,0 +1,134 @@
+// The bfloat16 forward pass of one wave over NB blocks of 16 queries, shared
+// by the single-bound and grouped kernels (weights already in LDS).
+//
+// Rounding points: first layer "bf16x3" (W_hi x_hi + W_hi x_lo + W_lo x_hi,
+// one K = 32 MFMA, input dimension <= 8: lane group 0 feeds x_hi against
+// W_hi, group 1 x_lo against W_hi, group 2 x_hi against W_lo, group 3
+// zeros); hidden layers bfloat16 weights and activations; output layer a
+// float32 dot product.  Lane l holds neurons 16*mo + 4*(l/16) + r of query
+// l % 16 after every layer; a K = 32 step of the next layer takes the 8
+// values of row blocks 2*ks and 2*ks + 1 that the lane already holds.
+#pragma once
+
+#include "nb_mlp.h"
+
+typedef nb_bf16x8 bf16x8;
+typedef nb_floatx4 floatx4;
+
+__device__ __forceinline__ floatx4 mfma32(bf16x8 a, bf16x8 b, floatx4 c) { return nb_mfma_bf16(a, b, c); }
+
+template <int W, int NH>
+struct B16 {
+  static constexpr int RB = W / 16;
+  static constexpr int KS = W / 32;
+  static constexpr int FH = RB * KS;
+  static constexpr int NFWD = RB + (NH - 1) * FH;
+  static constexpr int kBias = NH * W + W + 1;   // hidden biases, output weights, output bias
+  static constexpr size_t lds_bytes() { return (size_t)NFWD * 64 * 16 + (size_t)kBias * 4; }
+};
+
+template <int NB>
+__device__ __forceinline__ void load_inputs(const float* __restrict__ q, int64_t n, int in_dim, int64_t q0, int c,
+                                            int grp, bf16x8 (&xb)[NB]) {
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int64_t qi = q0 + nb * 16 + c;
+    const bool valid = qi < n;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float x = (valid && j < in_dim) ? q[qi * in_dim + j] : 0.0f;
+      const __bf16 hi = (__bf16)x;
+      const __bf16 lo = (__bf16)(x - (float)hi);
+      xb[nb][j] = grp == 1 ? lo : (grp == 3 ? (__bf16)0.0f : hi);
+    }
+  }
+}
+
+// One wave's share of the forward pass: NB blocks of 16 queries starting at
+// q0 (queries >= n_end are padding), weights and biases already in LDS.
+// Writes logits / decisions of the valid queries and adds their confusion
+// counts against g to cnt (when counts is non-null).
+template <int W, int NH, int NB>
+__device__ __forceinline__ void bf16_fwd_tile(const bf16x8* __restrict__ swt, const float* __restrict__ sbias,
+                                         const float* __restrict__ q, int64_t n, int in_dim, int64_t q0, float tau,
+                                         float* __restrict__ logits, uint8_t* __restrict__ hout,
+                                         const uint8_t* __restrict__ g, const unsigned long long* counts,
+                                         unsigned (&cnt)[4]) {
+  using N = B16<W, NH>;
+  constexpr int RB = N::RB, KS = N::KS;
+  const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4;
+  const float* swo = sbias + NH * W;
+  const float bo = swo[W];
+    floatx4 acc[NB][RB];
+    {
+      bf16x8 xb[NB];
+      load_inputs<NB>(q, n, in_dim, q0, c, grp, xb);
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo) {
+        const float* b = sbias + 16 * mo + 4 * grp;
+        const floatx4 bi = floatx4{b[0], b[1], b[2], b[3]};
+        const bf16x8 a = swt[mo * 64 + lane];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = mfma32(a, xb[nb], bi);
+      }
+    }
+#pragma unroll
+    for (int l = 1; l < NH; ++l) {
+      bf16x8 act[NB][KS];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) act[nb][ks][j] = (__bf16)fmaxf(acc[nb][2 * ks + j / 4][j % 4], 0.0f);
+      const bf16x8* fr = swt + (RB + (l - 1) * N::FH) * 64 + lane;
+      // two fragment slots: row block mo computes while mo + 1's fragments load
+      bf16x8 fa[KS], fb[KS];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) fa[ks] = fr[ks * 64];
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo) {
+        bf16x8(&cur)[KS] = (mo & 1) ? fb : fa;
+        bf16x8(&nxt)[KS] = (mo & 1) ? fa : fb;
+        if (mo + 1 < RB) {
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) nxt[ks] = fr[((mo + 1) * KS + ks) * 64];
+        }
+        const float* b = sbias + l * W + 16 * mo + 4 * grp;
+        const floatx4 bi = floatx4{b[0], b[1], b[2], b[3]};
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = bi;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = mfma32(cur[ks], act[nb][ks], acc[nb][mo]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      float p = 0.0f;
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) p = fmaf(swo[16 * mo + 4 * grp + r], fmaxf(acc[nb][mo][r], 0.0f), p);
+      p += __shfl_xor(p, 16);
+      p += __shfl_xor(p, 32);
+      const float z = p + bo;
+      const int64_t qi = q0 + nb * 16 + c;
+      const bool own = grp == 0 && qi < n;
+      const bool pos = !(z < tau);
+      if (own) {
+        if (logits) logits[qi] = z;
+        if (hout) hout[qi] = pos;
+      }
+      if (counts) {
+        const bool gv = own && g[qi] != 0;
+        cnt[0] += __popcll(__ballot(own && pos && gv));
+        cnt[1] += __popcll(__ballot(own && pos && !gv));
+        cnt[2] += __popcll(__ballot(own && !pos && !gv));
+        cnt[3] += __popcll(__ballot(own && !pos && gv));
+      }
+    }
+  }
+

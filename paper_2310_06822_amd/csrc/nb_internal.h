@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <vector>
 
 #include "nbound.h"
 
@@ -89,6 +90,52 @@ struct nb_bound {
   int64_t tr_cap = 0;              // padded batch the two above hold
 };
 
+struct AdamArgs {
+  int enabled;
+  float lr, b1, b2, eps, bc1, bc2, lam1, lam2;
+};
+
+// A group of per-object bfloat16 bounds of a common depth and input size.
+struct nb_group {
+  int n_obj = 0, in_dim = 0, n_hidden = 0, precision = 0, device = 0;
+  std::vector<int> widths;          // per object
+  std::vector<int64_t> poff;        // parameter offsets [n_obj + 1]
+  std::vector<int64_t> pkoff;       // forward-pack offsets, 16-byte slices [n_obj + 1]
+  std::vector<int64_t> ptoff;       // transposed-pack offsets, 16-byte slices [n_obj + 1]
+  std::vector<std::vector<int>> classes;   // object ids per width class (32, 64, 128)
+  int* d_widths = nullptr;
+  int64_t* d_poff = nullptr;
+  int64_t* d_pkoff = nullptr;
+  int64_t* d_ptoff = nullptr;
+  int* d_perm = nullptr;            // objects by decreasing width
+  int* d_class = nullptr;           // concatenated class member lists
+  int64_t n_params = 0, pack_elems = 0, packt_elems = 0;
+  float* theta = nullptr;
+  float* m = nullptr;
+  float* v = nullptr;
+  uint16_t* pack16 = nullptr;
+  uint16_t* pack16t = nullptr;
+  int64_t adam_t = 0;
+  // voxel grids, one per object
+  uint8_t* grids = nullptr;
+  int64_t* d_goff = nullptr;
+  int* d_gn = nullptr;
+  float* ray_t = nullptr;
+  // forward plan
+  int n_wg_cap = 0;                 // capacity of d_wg_first - 1 (workgroups of the widest variant grid)
+  int variant = 0;                  // grouped forward tile shape
+  int64_t* d_item_off = nullptr;
+  int64_t* d_wg_first = nullptr;
+  // training work space
+  int64_t tr_per_obj = 0;
+  float* partial = nullptr;         // [n_wg x P_o] blocks at n_wg * poff[o]
+  float* aux = nullptr;             // [n_obj][n_wg][8]
+  uint16_t* tr_ws = nullptr;        // activations / gradients of every class member
+  float* batch_q = nullptr;
+  uint8_t* batch_y = nullptr;
+  int64_t* d_qoff_train = nullptr;
+};
+
 // ------------------------------------------------------- kernel launchers
 
 // sampler.hip
@@ -138,13 +185,27 @@ nb_status bf16_pack_t(const nb_bound* b, hipStream_t s);
 nb_status bf16_train_partials(const nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha,
                               float beta, float tau, const BF16TrainPlan& plan, hipStream_t s);
 
+nb_status bf16_group_train_class(const nb_group* gr, int width, const int* d_members, int n_members,
+                                 const float* q, const uint8_t* y, int64_t per_obj, float alpha,
+                                 const float* alpha_obj, float beta,
+                                 float tau, const BF16TrainPlan& plan, uint16_t* act, uint16_t* grad,
+                                 hipStream_t s);
+
+// group.hip
+int group_variants();
+// Forward + decision with the group's current variant; with g and counts
+// (uint64[n_obj][4], zeroed here) also per-object TP, FP, TN, FN against g.
+nb_status group_forward(const nb_group* gr, const float* q, const int64_t* qoff, int64_t n, float tau,
+                        float* logits, uint8_t* h, const uint8_t* g, unsigned long long* counts, hipStream_t s);
+nb_status group_exact(const nb_group* gr, int kind, const float* q, const int64_t* qoff, int64_t n, uint8_t* g,
+                      hipStream_t s);
+nb_status group_pack(const nb_group* gr, hipStream_t s);
+nb_status group_reduce_adam(const nb_group* gr, int n_wg, const AdamArgs& adam, float* loss, unsigned long long* counts,
+                            float loss_scale, hipStream_t s);
+
 // optim.hip
 // Reduce partials over n_wg workgroups: writes grad (if non-null), loss and
 // counts (if non-null); with adam != 0 also applies one Adam step to theta.
-struct AdamArgs {
-  int enabled;
-  float lr, b1, b2, eps, bc1, bc2, lam1, lam2;
-};
 nb_status launch_reduce(const nb_bound* b, int n_wg, float* grad, float* loss, float loss_scale,
                         unsigned long long* counts, const AdamArgs& adam, hipStream_t s);
 nb_status launch_adam(const nb_bound* b, const float* grad, const AdamArgs& adam, hipStream_t s);

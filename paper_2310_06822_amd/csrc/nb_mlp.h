@@ -36,5 +36,53 @@ __device__ __forceinline__ nb_floatx4 nb_mfma_bf16(nb_bf16x8 a, nb_bf16x8 b, nb_
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// Element e (bfloat16 bits) of a bound's forward fragment pack, from its
+// float32 parameters th: e = (f*64 + lane)*8 + j with c = lane % 16,
+// g = lane / 16:
+//   f < RB            first layer, block mo = f, "bf16x3" split:
+//                       g = 0, 1: W0_hi[16mo + c][j];  g = 2: W0_lo[16mo + c][j];
+//                       g = 3: 0;  (0 for j >= in_dim)
+//   otherwise         hidden layer l (1-based), fragment (mo, ks),
+//                       f = RB + (l-1)*FH + mo*KS + ks:
+//                       W_l[16mo + c][32ks + 16(j/4) + 4g + (j%4)]
+__host__ __device__ inline uint16_t nb_bf16_pack_elem(const float* th, int in_dim, int W, int NH, int64_t e) {
+  (void)NH;
+  const int j = (int)(e & 7), lane = (int)((e >> 3) & 63);
+  const int f = (int)(e >> 9);
+  const int c = lane & 15, g = lane >> 4;
+  const int RB = W / 16, KS = W / 32, FH = RB * KS;
+  if (f < RB) {
+    if (j >= in_dim || g == 3) return 0;
+    const float w = th[(int64_t)(16 * f + c) * in_dim + j];
+    const uint16_t hi = nb_bf16_bits(w);
+    return g < 2 ? hi : nb_bf16_bits(w - nb_bf16_value(hi));
+  }
+  const int t = f - RB;
+  const int l = 1 + t / FH, rem = t % FH, mo = rem / KS, ks = rem % KS;
+  const float* Wl = th + nb_w_off(l, in_dim, W);
+  return nb_bf16_bits(Wl[(int64_t)(16 * mo + c) * W + 32 * ks + 16 * (j / 4) + 4 * g + (j % 4)]);
+}
+
+// Element e of the transposed (backward) pack of the hidden layers:
+// packT[((l-1)*FH + mo*KS + ks)*64 + lane][j] = W_l[32ks + 8g + j][16mo + c]
+// (the A operand of W_l^T D with the reduction over W_l's outputs in order).
+__host__ __device__ inline uint16_t nb_bf16_pack_t_elem(const float* th, int in_dim, int W, int NH, int64_t e) {
+  (void)NH;
+  const int j = (int)(e & 7), lane = (int)((e >> 3) & 63), f = (int)(e >> 9);
+  const int c = lane & 15, g = lane >> 4;
+  const int RB = W / 16, KS = W / 32, FH = RB * KS;
+  const int l = 1 + f / FH, rem = f % FH, mo = rem / KS, ks = rem % KS;
+  const float* Wl = th + nb_w_off(l, in_dim, W);
+  return nb_bf16_bits(Wl[(int64_t)(32 * ks + 8 * g + j) * W + 16 * mo + c]);
+}
+
+// Number of 16-byte fragment slices of the forward / transposed packs.
+__host__ __device__ inline int64_t nb_bf16_fwd_slices(int W, int NH) {
+  return (int64_t)(W / 16 + (NH - 1) * (W / 16) * (W / 32)) * 64;
+}
+__host__ __device__ inline int64_t nb_bf16_t_slices(int W, int NH) {
+  return (int64_t)(NH - 1) * (W / 16) * (W / 32) * 64;
+}
+
 // Number of compute units of the current device (cached per device).
 int nb_cu_count();

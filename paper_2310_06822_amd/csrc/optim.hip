@@ -9,6 +9,7 @@
 // weight matrices (supplemental "Regularization") adds
 // lam1 sign(W) + 2 lam2 W to their gradient.
 #include "nb_internal.h"
+#include "nb_adam.h"
 
 namespace {
 
@@ -18,18 +19,7 @@ constexpr int kParts = 8;
 __device__ __forceinline__ void adam_update(int64_t p, float g, float* __restrict__ theta, float* __restrict__ m,
                                             float* __restrict__ v, const AdamArgs& a, int in_dim, int width,
                                             int n_hidden) {
-  float th = theta[p];
-  if ((a.lam1 != 0.0f || a.lam2 != 0.0f) && nb_is_weight(p, in_dim, width, n_hidden)) {
-    const float sg = th > 0.0f ? 1.0f : (th < 0.0f ? -1.0f : 0.0f);
-    g = g + (a.lam1 * sg + 2.0f * a.lam2 * th);
-  }
-  const float mm = a.b1 * m[p] + (1.0f - a.b1) * g;
-  const float vv = a.b2 * v[p] + (1.0f - a.b2) * (g * g);
-  m[p] = mm;
-  v[p] = vv;
-  const float mhat = mm / a.bc1;
-  const float vhat = vv / a.bc2;
-  theta[p] = th - a.lr * mhat / (sqrtf(vhat) + a.eps);
+  nb_adam_update(p, g, theta, m, v, a, nb_is_weight(p, in_dim, width, n_hidden) != 0);
 }
 
 __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partial, const float* __restrict__ aux,
@@ -105,7 +95,8 @@ nb_status launch_adam(const nb_bound* b, const float* grad, const AdamArgs& adam
 }
 
 nb_status launch_zero_u64(unsigned long long* p, int n, hipStream_t s) {
-  k_zero_u64<<<1, 64, 0, s>>>(p, n);
+  if (n <= 0) return NB_OK;
+  k_zero_u64<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n);
   NB_LAUNCHED();
   return NB_OK;
 }

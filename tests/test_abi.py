@@ -74,3 +74,23 @@ def test_no_device_status():
     import numpy as np
     d = np.zeros((8, 3), np.float32)
     assert lib.nb_indicator_discs2d(d.ctypes.data_as(C.c_void_p), 8, C.byref(h)) == 2
+
+
+def test_group_arguments():
+    import numpy as np
+    lib = _lib.load()
+    h = C.c_void_p()
+    w = np.array([32, 64, 128], np.int32)
+    wp = w.ctypes.data_as(C.c_void_p)
+    assert lib.nb_group_create(3, 6, wp, 3, 1, None) == 1
+    assert lib.nb_group_create(0, 6, wp, 3, 1, C.byref(h)) == 1
+    assert lib.nb_group_create(3, 6, wp, 1, 1, C.byref(h)) == 1    # depth outside 2..4
+    assert lib.nb_group_create(3, 6, wp, 3, 0, C.byref(h)) == 1    # float32 groups: none
+    bad = np.array([32, 48, 128], np.int32)
+    assert lib.nb_group_create(3, 6, bad.ctypes.data_as(C.c_void_p), 3, 1, C.byref(h)) == 1
+    assert lib.nb_group_destroy(None) == 0
+    assert lib.nb_group_forward(None, None, None, 10, 1e-5, None, None, None, None, None) == 1
+    assert lib.nb_group_train_step(None, 2, 1, 0, 64, 1.0, None, 1.0, 1e-3, None, None, None) == 1
+    assert lib.nb_group_set_variant(None, 0) == 1
+    if nb.nb_device_count() == 0:
+        assert lib.nb_group_create(3, 6, wp, 3, 1, C.byref(h)) == 2

@@ -1,0 +1,239 @@
+"""GPU parity of grouped per-object bounds (Sec. 3.4: one network per object)
+against the CPU oracle, object by object, through the C ABI.
+
+Bars as for single bounds: exact answers bit-exact; bfloat16 logits within
+1e-3 max(|z|, s); per-object losses within 2e-3 relative and parameter
+updates within 5e-2 relative Frobenius norm over a few Adam steps.  A group's
+object 0 also trains bit-identically to a single bound on the same rows.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import indicators as I, loss as L, mlp, sampling
+from oracle import train as T
+from oracle.adam import Adam
+
+pytestmark = pytest.mark.gpu
+
+nb = pytest.importorskip("paper_2310_06822_amd")
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def bits(a):
+    return np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
+
+
+def _objects(seed, sizes):
+    """Per-object metaball grids (4..32 balls) of the given sizes."""
+    g = np.random.default_rng(seed)
+    grids = []
+    for o, n in enumerate(sizes):
+        c, r = synth.metaballs3d(seed * 100 + o, k=int(g.integers(4, 33)))
+        grids.append(I.voxelize_metaballs(c, r, n))
+    return grids
+
+
+def _group(in_dim, widths, nh, seed):
+    thetas = [synth.init_params(seed + o, in_dim, [w] * nh) for o, w in enumerate(widths)]
+    gr = nb.Group(in_dim, widths, nh)
+    assert gr.n_params == sum(t.size for t in thetas)
+    assert np.array_equal(np.diff(gr.offsets), [t.size for t in thetas])
+    gr.set_params(np.concatenate(thetas).astype(np.float32))
+    return gr, thetas
+
+
+GROUPS = [
+    (6, [32, 128, 64, 32, 64, 128, 32], 3, [0, 1, 17, 300, 129, 4099, 128]),
+    (3, [64, 32, 128], 2, [1000, 0, 257]),
+    (6, [128, 64, 32, 64], 4, [33, 2048, 5, 0]),
+    (4, [32], 3, [4099]),
+]
+
+
+@pytest.mark.parametrize("in_dim,widths,nh,counts", GROUPS)
+def test_group_forward_parity(in_dim, widths, nh, counts):
+    gr, thetas = _group(in_dim, widths, nh, 300 + nh)
+    qs = [synth.points(310 + o, c, in_dim) for o, c in enumerate(counts)]
+    pre = 5   # rows before qoff[0] are not the group's: left untouched
+    q = np.concatenate([synth.points(309, pre, in_dim)] + qs)
+    qoff = np.concatenate([[0], np.cumsum(counts)]) + pre
+    z = torch.full((q.shape[0],), -7.0, dtype=torch.float32, device="cuda")
+    h = torch.full((q.shape[0],), 9, dtype=torch.uint8, device="cuda")
+    nb.nb_group_forward(gr.handle, gr.n_obj, in_dim, cuda(q), cuda(qoff.astype(np.int64)), logits=z, h=h)
+    z, h = host(z), host(h)
+    assert np.all(z[:pre] == -7.0) and np.all(h[:pre] == 9)
+    for o, (w, th, qo) in enumerate(zip(widths, thetas, qs)):
+        if qo.shape[0] == 0:
+            continue
+        zo = z[qoff[o]:qoff[o + 1]].astype(np.float64)
+        ho = h[qoff[o]:qoff[o + 1]]
+        ref = mlp.forward(th, in_dim, [w] * nh, qo, bf16=True)
+        s = mlp.abs_forward(th, in_dim, [w] * nh, qo, bf16=True)
+        bound = 1e-3 * np.maximum(np.abs(ref), s)
+        err = np.abs(zo - ref)
+        assert np.all(err <= bound), f"object {o}: max err/bound {np.max(err / bound):.3g}"
+        assert np.array_equal(ho, L.decide(zo))
+        # the same network as a single bound gives the same bits
+        b = nb.Bound(in_dim, nh, w, nb.BF16)
+        b.set_params(th)
+        zs, _ = b.forward(cuda(qo))
+        assert np.array_equal(bits(host(zs)), bits(zo.astype(np.float32))), o
+
+
+def test_group_variants_and_counts():
+    """Every tile shape gives the same bits; per-object counts equal the
+    oracle's decisions against exact answers (ties |z| < 1e-4 aside)."""
+    in_dim, widths, nh, counts = 6, [64, 32, 128, 32, 128], 3, [700, 1, 0, 3000, 129]
+    gr, thetas = _group(in_dim, widths, nh, 330)
+    qs = [synth.points(340 + o, c, in_dim) for o, c in enumerate(counts)]
+    q = cuda(np.concatenate(qs))
+    qoff = cuda(np.concatenate([[0], np.cumsum(counts)]).astype(np.int64))
+    ys = [(synth.points(350 + o, c, 1)[:, 0] > 0.3).astype(np.uint8) for o, c in enumerate(counts)]
+    y = cuda(np.concatenate(ys))
+    nv = nb.nb_group_num_variants(gr.handle)
+    assert nv >= 2
+    ref_bits = None
+    for v in range(nv):
+        nb.nb_group_set_variant(gr.handle, v)
+        z, h = gr.forward(q, qoff)
+        zb = bits(host(z))
+        if ref_bits is None:
+            ref_bits = zb
+        assert np.array_equal(zb, ref_bits), v
+        c = host(gr.counts(q, qoff, y))
+        for o, (w, th, qo, yo) in enumerate(zip(widths, thetas, qs, ys)):
+            if qo.shape[0] == 0:
+                assert np.all(c[o] == 0)
+                continue
+            zr = mlp.forward(th, in_dim, [w] * nh, qo, bf16=True)
+            sure = np.abs(zr) >= 1e-4
+            ho = L.decide(host(z)[qoff[o].item():qoff[o + 1].item()].astype(np.float64))
+            assert np.array_equal(ho[sure], L.decide(zr)[sure])
+            assert np.array_equal(c[o], L.counts(ho, yo)), (v, o)
+
+
+def test_group_forward_many_objects():
+    """256 objects (the batched workload's count), 1..600 queries each."""
+    rng = np.random.default_rng(5)
+    widths = [int(w) for w in rng.choice([32, 64, 128], 256)]
+    counts = rng.integers(0, 600, 256)
+    counts[[3, 100]] = 0
+    gr, thetas = _group(6, widths, 3, 900)
+    q = synth.boxes(901, int(counts.sum()))
+    qoff = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    z, h = gr.forward(cuda(q), cuda(qoff))
+    z = host(z).astype(np.float64)
+    for o in rng.choice(256, 24, replace=False):
+        a, b = qoff[o], qoff[o + 1]
+        if a == b:
+            continue
+        ref = mlp.forward(thetas[o], 6, [widths[o]] * 3, q[a:b], bf16=True)
+        s = mlp.abs_forward(thetas[o], 6, [widths[o]] * 3, q[a:b], bf16=True)
+        assert np.all(np.abs(z[a:b] - ref) <= 1e-3 * np.maximum(np.abs(ref), s)), o
+
+
+@pytest.mark.parametrize("kind", ["box", "point", "ray"])
+def test_group_exact(kind):
+    sizes = [32, 64, 8, 128, 32]
+    grids = _objects(41, sizes)
+    in_dim = 3 if kind == "point" else 6
+    gr = nb.Group(in_dim, [32] * len(sizes), 2)
+    gr.set_voxels(cuda(np.concatenate(grids)), sizes)
+    counts = [1000, 0, 333, 2049, 64]
+    gen = {"box": synth.boxes, "ray": synth.rays, "point": lambda s, n: synth.points(s, n, 3)}[kind]
+    qs = [gen(420 + o, c) for o, c in enumerate(counts)]
+    q = np.concatenate(qs)
+    qoff = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    out = host(gr.query(kind, cuda(q), cuda(qoff)))
+    fn = {"box": I.voxel_boxes, "ray": I.voxel_rays, "point": I.voxel_points}[kind]
+    for o, (qo, grid, n) in enumerate(zip(qs, grids, sizes)):
+        if qo.shape[0]:
+            assert np.array_equal(out[qoff[o]:qoff[o + 1]], fn(qo, grid, n)), o
+
+
+def _oracle_group_steps(widths, nh, grids, sizes, thetas, seed, steps, per_obj, alpha_obj=None):
+    """Alg. 1 for every object on its rows of one shared draw of regions
+    (FN weight alpha_obj[o] if given, else the linear ramp)."""
+    n_obj = len(widths)
+    th = [t.astype(np.float64).copy() for t in thetas]
+    opts = [Adam(t.size, lr=1e-3) for t in th]
+    losses = []
+    for t in range(steps):
+        qall = sampling.sample("box", seed, t, n_obj * per_obj, 3)
+        a = T.alpha_ramp(t, steps)
+        row = []
+        for o in range(n_obj):
+            q = qall[o * per_obj:(o + 1) * per_obj]
+            y = I.voxel_boxes(q, grids[o], sizes[o])
+            ao = a if alpha_obj is None else float(alpha_obj[o])
+            lv, g, _ = T.step_grad(th[o], 6, [widths[o]] * nh, q, y, ao, 1.0, bf16=True)
+            row.append(lv)
+            th[o] = opts[o].step(th[o], g)
+        losses.append(row)
+    return th, np.array(losses)
+
+
+@pytest.mark.parametrize("per_obj,per_alpha", [(1000, False), (4096, False), (777, True)])
+def test_group_train_steps_parity(per_obj, per_alpha):
+    widths, nh, sizes = [32, 128, 64, 64], 3, [32, 64, 32, 128]
+    grids = _objects(51, sizes)
+    gr, thetas = _group(6, widths, nh, 520)
+    gr.set_voxels(cuda(np.concatenate(grids)), sizes)
+    steps, seed = 4, 7007
+    alpha_obj = np.array([1.0, 40.0, 7.5, 100.0], np.float32) if per_alpha else None
+    th_ref, loss_ref = _oracle_group_steps(widths, nh, grids, sizes, thetas, seed, steps, per_obj, alpha_obj)
+    loss = torch.empty(len(widths), dtype=torch.float32, device="cuda")
+    cnt = torch.empty(4 * len(widths), dtype=torch.int64, device="cuda")
+    a_dev = cuda(alpha_obj) if per_alpha else None
+    for t in range(steps):
+        nb.nb_group_train_step(gr.handle, gr.n_obj, nb.BOX, seed, t, per_obj, T.alpha_ramp(t, steps), 1.0, 1e-3,
+                               loss=loss, counts=cnt, alpha_obj=a_dev)
+        lg = host(loss)
+        assert np.all(np.abs(lg - loss_ref[t]) <= 2e-3 * np.abs(loss_ref[t])), (t, lg, loss_ref[t])
+        assert np.all(host(cnt).reshape(-1, 4).sum(1) == per_obj)
+    th = host(gr.params()).astype(np.float64)
+    for o in range(len(widths)):
+        d = th[gr.offsets[o]:gr.offsets[o + 1]] - thetas[o]
+        dr = th_ref[o] - thetas[o]
+        assert np.linalg.norm(d - dr) <= 5e-2 * np.linalg.norm(dr), o
+
+
+def test_group_object0_matches_single_bound():
+    """Object 0 takes rows 0 .. per_obj - 1 of the draw: exactly a single
+    bound's batch, so its trajectory is bit-identical to the single path."""
+    widths, nh, sizes = [64, 32, 128], 3, [64, 32, 32]
+    grids = _objects(61, sizes)
+    gr, thetas = _group(6, widths, nh, 620)
+    gr.set_voxels(cuda(np.concatenate(grids)), sizes)
+    ind = nb.Indicator.voxels(cuda(grids[0]), sizes[0])
+    b = nb.Bound(6, nh, widths[0], nb.BF16)
+    b.set_params(thetas[0])
+    per_obj = 3000
+    for t in range(3):
+        nb.nb_group_train_step(gr.handle, gr.n_obj, nb.BOX, 11, t, per_obj, 5.0, 1.0, 1e-3)
+        nb.nb_bound_train_step(b.handle, ind.handle, nb.BOX, 11, t, per_obj, 5.0, 1.0, 1e-3)
+    th = host(gr.params())
+    assert np.array_equal(bits(th[:gr.offsets[1]]), bits(host(b.params())))
+
+
+def test_group_errors():
+    with pytest.raises(nb.NBError):
+        nb.Group(6, [48], 3)   # width not 32/64/128
+    with pytest.raises(nb.NBError):
+        nb.Group(6, [32], 1)   # grouped bounds take 2..4 hidden layers
+    gr = nb.Group(6, [32, 64], 3)
+    with pytest.raises(nb.NBError):   # no grids yet
+        nb.nb_group_train_step(gr.handle, 2, nb.BOX, 1, 0, 64, 1.0)
+    with pytest.raises(nb.NBError):
+        gr.set_params(torch.zeros(gr.n_params + 1, device="cuda"))
