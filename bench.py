@@ -205,6 +205,121 @@ def run_workload(W, args, with_cpu: bool):
     return out
 
 
+def build_group(GW, nb, synth, torch):
+    """The object set of a grouped workload on the device: grids voxelised
+    per object, a Group with per-object initial weights."""
+    objs = synth.object_set(GW.seeds["scene"], GW.n_obj, GW.grid_sizes, GW.widths, GW.k_range)
+    sizes = [o["n"] for o in objs]
+    grids = torch.empty(int(sum(n ** 3 for n in sizes)), dtype=torch.uint8, device="cuda")
+    off = 0
+    for o in objs:
+        nb.nb_voxelize_metaballs(o["centres"], o["radii"], 1.0, o["n"], grids[off:off + o["n"] ** 3])
+        off += o["n"] ** 3
+    widths = [o["width"] for o in objs]
+    group = nb.Group(GW.in_dim, widths, GW.n_hidden)
+    group.set_voxels(grids, sizes)
+    theta0 = np.concatenate([synth.init_params(GW.seeds["init"] * 1000 + i, GW.in_dim, [w] * GW.n_hidden)
+                             for i, w in enumerate(widths)]).astype(np.float32)
+    return group, objs, theta0
+
+
+def run_group_workload(GW, args):
+    import torch
+
+    import paper_2310_06822_amd as nb
+    import synth
+    from paper_2310_06822_amd import autotune, trainer
+
+    kind = nb.KINDS[GW.kind]
+    group, objs, theta0 = build_group(GW, nb, synth, torch)
+    widths = group.widths
+    sched = trainer.Schedule(steps=args.train_steps if args.train_steps is not None else GW.train_steps,
+                             batch=GW.per_obj, alpha_max=GW.alpha_max, k=GW.adapt_k, inc=GW.adapt_inc,
+                             patience=GW.patience, max_iters=0 if args.no_adapt else GW.adapt_iters,
+                             val_n=GW.val_per_obj)
+    group.set_params(theta0)
+    nb.nb_group_train_step(group.handle, group.n_obj, kind, GW.seeds["train"], 0, GW.per_obj, 1.0)   # work space
+    group.set_params(theta0)
+    res = trainer.train_group(group, GW.kind, GW.seeds["train"], sched, val_seed=GW.seeds["val"], log=log)
+    log(f"[{GW.name}] train: {res.steps} steps x {GW.n_obj} x {GW.per_obj} in {res.seconds:.2f} s -> "
+        f"{res.samples_per_s:.3e} samples/s; converged {res.converged}")
+
+    per = args.eval_n // GW.n_obj if args.eval_n is not None else GW.eval_per_obj
+    n_eval = per * GW.n_obj
+    q = torch.empty((n_eval, GW.in_dim), dtype=torch.float32, device="cuda")
+    nb.nb_sample_queries(kind, 3, GW.seeds["eval"], 0, q)
+    qoff = torch.arange(0, n_eval + 1, per, dtype=torch.int64, device="cuda")
+    g = torch.empty(n_eval, dtype=torch.uint8, device="cuda")
+    nb.nb_group_query_exact(group.handle, group.n_obj, kind, q, qoff, g)
+    variant = autotune.tune_group(group, q, qoff)
+    cnt = group.counts(q, qoff, g).cpu().numpy()
+    tp, fp, tn, fn = (int(x) for x in cnt.sum(0))
+    log(f"[{GW.name}] held-out {n_eval}: TP {tp} FP {fp} TN {tn} FN {fn}; objects with FN "
+        f"{int((cnt[:, 3] > 0).sum())} (tile variant {variant})")
+
+    h = torch.empty(n_eval, dtype=torch.uint8, device="cuda")
+    kern_ms, wall = timed(lambda: nb.nb_group_forward(group.handle, group.n_obj, GW.in_dim, q, qoff, h=h),
+                          args.steps, args.warmup, torch)
+    exact_ms, _ = timed(lambda: nb.nb_group_query_exact(group.handle, group.n_obj, kind, q, qoff, g), args.steps,
+                        args.warmup, torch)
+    # the exact box test by its definition (scan every cell in the box)
+    nb.nb_group_set_box_method(group.handle, nb.BOX_SCAN)
+    g_scan = torch.empty_like(g)
+    scan_ms, _ = timed(lambda: nb.nb_group_query_exact(group.handle, group.n_obj, kind, q, qoff, g_scan),
+                       max(1, args.steps // 4), 1, torch)
+    nb.nb_group_set_box_method(group.handle, nb.BOX_TABLE)
+    scan_same = bool(torch.equal(g_scan, g))
+    del g_scan
+
+    def flop(w):
+        return 2 * (GW.in_dim * w + (GW.n_hidden - 1) * w * w + w)
+
+    total_flop = float(sum(flop(w) for w in widths)) * per
+    achieved = total_flop / (kern_ms / 1e3) / 1e12
+    # per width class: the same launch over that class's objects only
+    by_width = {}
+    for w in sorted(set(widths)):
+        mask = np.array([x == w for x in widths])
+        rows = torch.from_numpy(np.repeat(mask, per)).cuda()
+        qc = q[rows].contiguous()
+        counts_c = np.where(mask, per, 0)
+        qoff_c = torch.from_numpy(np.concatenate([[0], np.cumsum(counts_c)]).astype(np.int64)).cuda()
+        hc = torch.empty(qc.shape[0], dtype=torch.uint8, device="cuda")
+        ms_c, _ = timed(lambda: nb.nb_group_forward(group.handle, group.n_obj, GW.in_dim, qc, qoff_c, h=hc),
+                        args.steps, args.warmup, torch)
+        f_c = flop(w) * qc.shape[0]
+        by_width[str(w)] = {"objects": int(mask.sum()), "queries": int(qc.shape[0]), "ms": round(ms_c, 4),
+                            "tflops": round(f_c / (ms_c / 1e3) / 1e12, 2),
+                            "frac": round(f_c / (ms_c / 1e3) / 1e12 / PEAK_TFLOPS["bf16"], 4)}
+        del qc, hc
+    return {
+        "bound_queries_per_s": n_eval * args.steps / wall,
+        "config": {"workload": GW.name, "query": GW.kind, "objects": GW.n_obj, "queries_per_step": n_eval,
+                   "net": f"{GW.in_dim}x{{32|64|128}}^{GW.n_hidden}x1 relu bf16, width per object",
+                   "widths": {str(w): widths.count(w) for w in sorted(set(widths))},
+                   "grids": {str(n): [o["n"] for o in objs].count(n) for n in GW.grid_sizes},
+                   "train_per_object": GW.per_obj},
+        "train_samples_per_s": res.samples_per_s,
+        "train": {"steps": res.steps, "seconds": res.seconds, "schedule_iterations": res.iters,
+                  "validation_fn_zero": res.converged, "validation_per_object": sched.val_n if sched.max_iters else 0,
+                  "validation_fn_history": res.val_fn_history[-20:],
+                  "objects_with_fn_history": res.objects_with_fn[-20:], "alpha_max_final": res.alpha_final},
+        "exact_queries_per_s": n_eval / (exact_ms / 1e3),
+        "exact_method": "count table per object (constant time per box)",
+        "bound_speedup_vs_exact": exact_ms / kern_ms,
+        "exact_scan_queries_per_s": n_eval / (scan_ms / 1e3),
+        "bound_speedup_vs_exact_scan": scan_ms / kern_ms,
+        "exact_scan_equals_table": scan_same,
+        "heldout": {"n": n_eval, "tp": tp, "fp": fp, "tn": tn, "fn": fn, "fp_rate": fp / n_eval,
+                    "objects_with_fn": int((cnt[:, 3] > 0).sum())},
+        "fn_zero": fn == 0,
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["bf16"],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["bf16"], 4), "traffic": None,
+                     "kernel": "k_group_fwd (grouped bf16 forward + decision)", "avg_launch_ms": round(kern_ms, 4),
+                     "tile_variant": variant, "by_width": by_width},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,7 +340,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2310_06822_amd.configs import WORKLOADS
+    from paper_2310_06822_amd.configs import GROUP_WORKLOADS, WORKLOADS
 
     torch.cuda.set_device(0)
     W = WORKLOADS[args.workload]
@@ -244,6 +359,9 @@ def main():
             r2 = run_workload(W2, args, with_cpu=False)
             r2["bound_queries_per_s"] = r2.pop("value")
             out["also"][name] = r2
+    if args.also:
+        for name, GW in GROUP_WORKLOADS.items():
+            out["also"][name] = run_group_workload(GW, args)
     if args.copy_calibration:
         src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
         dst = torch.empty_like(src)

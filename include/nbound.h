@@ -250,6 +250,12 @@ nb_status nb_group_get_params(const nb_group* g, float* theta, int64_t n_params,
  * in object order on the device; n_host[o] is object o's grid size.  Copied;
  * synchronises the device. */
 nb_status nb_group_set_voxels(nb_group* g, const uint8_t* grids, const int* n_host);
+/* How the grouped exact test answers boxes: 1 (default) through each
+ * object's occupied-cell count table, (n+1)^3 int32 built by
+ * nb_group_set_voxels (any occupied cell in the box's cell range <=> a
+ * positive count: the same answer in constant time); 0 by scanning the
+ * box's cells.  Both give identical results. */
+nb_status nb_group_set_box_method(nb_group* g, int method);
 /* Exact point / ray / box query of every row against its object's grid;
  * g: uint8[n] (rows outside qoff[0] .. qoff[n_obj]-1 are left untouched). */
 nb_status nb_group_query_exact(const nb_group* g, int kind, const float* q, const int64_t* qoff, int64_t n,
@@ -270,13 +276,16 @@ nb_status nb_group_set_variant(nb_group* g, int variant);
  * per object (nb_sample_queries with n = n_obj * per_obj; object o takes rows
  * o*per_obj ..), labelled on the object's grid, Eq. 1 with FN weight alpha
  * (or alpha_obj[o], device float32[n_obj], when alpha_obj is non-NULL) and
- * beta, one Adam step (lr, 0.9, 0.999, 1e-8) per object.  loss:
+ * beta, one Adam step (0.9, 0.999, 1e-8) per object with learning rate lr
+ * (or lr_obj[o], device float32[n_obj]; 0 freezes object o: its parameters
+ * and Adam moments are left as they are, which is how an object that has
+ * met its stopping rule stops training while the others go on).  loss:
  * float32[n_obj] per-object mean loss or NULL; counts: uint64[n_obj][4] or
  * NULL.  The first step with a new per_obj synchronises `stream` to size the
  * work space. */
 nb_status nb_group_train_step(nb_group* g, int kind, uint64_t seed, uint64_t step, int64_t per_obj, float alpha,
-                              const float* alpha_obj, float beta, float lr, float* loss, uint64_t* counts,
-                              void* stream);
+                              const float* alpha_obj, float beta, float lr, const float* lr_obj, float* loss,
+                              uint64_t* counts, void* stream);
 
 #ifdef __cplusplus
 }

@@ -291,6 +291,13 @@ def nb_group_set_voxels(g, grids: torch.Tensor, sizes):
     _check(lib().nb_group_set_voxels(g, _dev(grids, torch.uint8, "grids"), n.ctypes.data_as(C.c_void_p)))
 
 
+BOX_SCAN, BOX_TABLE = 0, 1
+
+
+def nb_group_set_box_method(g, method: int):
+    _check(lib().nb_group_set_box_method(g, int(method)))
+
+
 def _qoff(qoff: torch.Tensor, n_obj: int, n: int):
     if qoff.numel() != n_obj + 1:
         raise ValueError("qoff must have n_obj + 1 entries")
@@ -324,10 +331,12 @@ def nb_group_set_variant(g, variant: int):
 
 
 def nb_group_train_step(g, n_obj: int, kind: int, seed: int, step: int, per_obj: int, alpha: float,
-                        beta: float = 1.0, lr: float = 1e-3, loss=None, counts=None, alpha_obj=None, stream=None):
+                        beta: float = 1.0, lr: float = 1e-3, loss=None, counts=None, alpha_obj=None, lr_obj=None,
+                        stream=None):
     _check(lib().nb_group_train_step(g, int(kind), int(seed), int(step), int(per_obj), float(alpha),
                                      _dev(alpha_obj, torch.float32, "alpha_obj", n_obj), float(beta),
-                                     float(lr), _dev(loss, torch.float32, "loss", n_obj),
+                                     float(lr), _dev(lr_obj, torch.float32, "lr_obj", n_obj),
+                                     _dev(loss, torch.float32, "loss", n_obj),
                                      _dev(counts, torch.int64, "counts", 4 * n_obj), _stream(stream)))
 
 

@@ -63,3 +63,40 @@ METABALL4D_POINT = Workload("metaball4d_point", 4, "point", 4, 4, 256, 6, "bf16"
                             train_steps=2000, batch=1 << 20, eval_n=1 << 24)
 
 WORKLOADS = {w.name: w for w in (DISC2D_POINT, VOXEL3D_POINT, VOXEL3D_RAY, METABALL4D_POINT)}
+
+
+@dataclass(frozen=True)
+class GroupWorkload:
+    """Many per-object bounds trained and queried together (one network per
+    object, Sec. 3.4): n_obj voxelised metaball scenes with grid size and
+    hidden width drawn per object, box queries."""
+    name: str
+    index: int
+    n_obj: int
+    kind: str
+    in_dim: int
+    n_hidden: int
+    grid_sizes: tuple
+    widths: tuple
+    k_range: tuple
+    train_steps: int
+    per_obj: int              # training regions per object per step
+    eval_per_obj: int
+    val_per_obj: int
+    alpha_max: float = 100.0
+    adapt_k: int = 250
+    adapt_inc: float = 50.0
+    adapt_iters: int = 400
+    patience: int = 6
+
+    @property
+    def seeds(self):
+        return {"scene": 1000 + self.index, "train": 2000 + self.index, "eval": 3000 + self.index,
+                "init": 4000 + self.index, "val": 5000 + self.index}
+
+
+BATCHED_BOX = GroupWorkload("batched_box", 3, 256, "box", 6, 3, grid_sizes=(32, 64, 128), widths=(32, 64, 128),
+                            k_range=(4, 32), train_steps=2000, per_obj=1 << 12, eval_per_obj=1 << 16,
+                            val_per_obj=1 << 16)
+
+GROUP_WORKLOADS = {BATCHED_BOX.name: BATCHED_BOX}

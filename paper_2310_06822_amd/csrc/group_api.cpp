@@ -62,6 +62,8 @@ nb_status nb_group_destroy(nb_group* g) {
   free_p(g->d_goff);
   free_p(g->d_gn);
   free_p(g->ray_t);
+  free_p(g->table);
+  free_p(g->d_toff);
   free_p(g->d_item_off);
   free_p(g->d_wg_first);
   free_p(g->partial);
@@ -184,19 +186,35 @@ nb_status nb_group_get_params(const nb_group* g, float* theta, int64_t n_params,
 
 nb_status nb_group_set_voxels(nb_group* g, const uint8_t* grids, const int* n_host) {
   NB_REQUIRE(g && grids && n_host, "NULL argument");
-  std::vector<int64_t> goff(g->n_obj + 1, 0);
+  std::vector<int64_t> goff(g->n_obj + 1, 0), toff(g->n_obj + 1, 0);
   std::vector<int> gn(n_host, n_host + g->n_obj);
+  int max_n = 0;
   for (int o = 0; o < g->n_obj; ++o) {
     NB_REQUIRE(gn[o] >= 2 && gn[o] <= 1024, "object %d: grid size %d out of range", o, gn[o]);
     goff[o + 1] = goff[o] + (int64_t)gn[o] * gn[o] * gn[o];
+    toff[o + 1] = toff[o] + (int64_t)(gn[o] + 1) * (gn[o] + 1) * (gn[o] + 1);
+    max_n = std::max(max_n, gn[o]);
   }
   free_p(g->grids);
   free_p(g->d_goff);
   free_p(g->d_gn);
+  free_p(g->table);
+  free_p(g->d_toff);
   NB_TRY(alloc_n(&g->grids, (size_t)goff[g->n_obj]));
   NB_HIP(hipMemcpy(g->grids, grids, (size_t)goff[g->n_obj], hipMemcpyDeviceToDevice));
   NB_TRY(upload(&g->d_goff, goff));
   NB_TRY(upload(&g->d_gn, gn));
+  NB_TRY(upload(&g->d_toff, toff));
+  NB_TRY(alloc_n(&g->table, (size_t)toff[g->n_obj]));
+  NB_TRY(group_build_tables(g, max_n, nullptr));
+  NB_HIP(hipDeviceSynchronize());
+  return NB_OK;
+}
+
+nb_status nb_group_set_box_method(nb_group* g, int method) {
+  NB_REQUIRE(g, "group is NULL");
+  NB_REQUIRE(method == 0 || method == 1, "box method must be 0 (scan) or 1 (count table)");
+  g->box_method = method;
   return NB_OK;
 }
 
@@ -237,17 +255,20 @@ nb_status nb_group_set_variant(nb_group* g, int variant) {
 }
 
 nb_status nb_group_train_step(nb_group* g, int kind, uint64_t seed, uint64_t step, int64_t per_obj, float alpha,
-                              const float* alpha_obj, float beta, float lr, float* loss, uint64_t* counts,
-                              void* stream) {
+                              const float* alpha_obj, float beta, float lr, const float* lr_obj, float* loss,
+                              uint64_t* counts, void* stream) {
   NB_REQUIRE(g, "group is NULL");
   NB_REQUIRE(g->grids, "the group has no voxel grids (nb_group_set_voxels)");
   NB_REQUIRE(kind == NB_QUERY_BOX || kind == NB_QUERY_RAY || kind == NB_QUERY_POINT, "unsupported query kind");
   NB_REQUIRE((kind == NB_QUERY_POINT ? 3 : 6) == g->in_dim, "query kind does not match the group's input size");
   NB_REQUIRE(per_obj >= 1 && per_obj * g->n_obj <= (int64_t(1) << 31), "per_obj out of range");
-  NB_REQUIRE(lr > 0 && std::isfinite(alpha) && std::isfinite(beta) && alpha >= 0 && beta >= 0,
+  NB_REQUIRE((lr > 0 || lr_obj) && std::isfinite(alpha) && std::isfinite(beta) && alpha >= 0 && beta >= 0,
              "invalid learning rate or loss weights");
   hipStream_t s = as_stream(stream);
-  const BF16TrainPlan plan = bf16_train_plan(per_obj);
+  // fewer, longer chunks for large groups: the class launches have
+  // members x chunks workgroups, and the partial gradients cost
+  // chunks x parameters of memory traffic
+  const BF16TrainPlan plan = bf16_train_plan(per_obj, std::max(16, 4096 / g->n_obj));
   const int64_t total = per_obj * g->n_obj;
   if (g->tr_per_obj != per_obj) {
     // (re)sizes the work space: synchronising, only when per_obj changes
@@ -301,7 +322,7 @@ nb_status nb_group_train_step(nb_group* g, int kind, uint64_t seed, uint64_t ste
   // bias corrections from the float32 constants, as for a single bound
   a.bc1 = (float)(1.0 - std::pow((double)a.b1, (double)g->adam_t));
   a.bc2 = (float)(1.0 - std::pow((double)a.b2, (double)g->adam_t));
-  NB_TRY(group_reduce_adam(g, plan.n_wg, a, loss, reinterpret_cast<unsigned long long*>(counts),
+  NB_TRY(group_reduce_adam(g, plan.n_wg, a, lr_obj, loss, reinterpret_cast<unsigned long long*>(counts),
                            (float)(1.0 / (double)per_obj), s));
   return group_pack(g, s);
 }

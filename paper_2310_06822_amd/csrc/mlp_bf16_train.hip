@@ -590,9 +590,9 @@ nb_status train_dispatch(int W, const TrainJob& J, hipStream_t s) {
 
 }  // namespace
 
-BF16TrainPlan bf16_train_plan(int64_t n) {
+BF16TrainPlan bf16_train_plan(int64_t n, int max_wg) {
   BF16TrainPlan p;
-  p.n_wg = (int)std::min<int64_t>(256, (n + 63) / 64);
+  p.n_wg = (int)std::min<int64_t>(std::max(1, std::min(256, max_wg)), (n + 63) / 64);
   const int64_t per = (n + p.n_wg - 1) / p.n_wg;
   p.chunk = (per + 63) / 64 * 64;
   p.n_wg = (int)((n + p.chunk - 1) / p.chunk);

@@ -27,33 +27,55 @@ struct B16 {
   static constexpr size_t lds_bytes() { return (size_t)NFWD * 64 * 16 + (size_t)kBias * 4; }
 };
 
+// Raw float32 inputs of NB blocks of 16 queries (lane column c); zeros for
+// queries >= n and features >= in_dim.
 template <int NB>
-__device__ __forceinline__ void load_inputs(const float* __restrict__ q, int64_t n, int in_dim, int64_t q0, int c,
-                                            int grp, bf16x8 (&xb)[NB]) {
+__device__ __forceinline__ void load_raw(const float* __restrict__ q, int64_t n, int in_dim, int64_t q0, int c,
+                                         float (&xr)[NB][8]) {
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     const int64_t qi = q0 + nb * 16 + c;
     const bool valid = qi < n;
 #pragma unroll
+    for (int j = 0; j < 8; ++j) xr[nb][j] = (valid && j < in_dim) ? q[qi * in_dim + j] : 0.0f;
+  }
+}
+
+// bf16x3 operand of the first layer: lane group 0 and 2 take x_hi, group 1
+// x_lo = x - x_hi, group 3 zeros.
+template <int NB>
+__device__ __forceinline__ void split_inputs(const float (&xr)[NB][8], int grp, bf16x8 (&xb)[NB]) {
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const float x = (valid && j < in_dim) ? q[qi * in_dim + j] : 0.0f;
+      const float x = xr[nb][j];
       const __bf16 hi = (__bf16)x;
       const __bf16 lo = (__bf16)(x - (float)hi);
       xb[nb][j] = grp == 1 ? lo : (grp == 3 ? (__bf16)0.0f : hi);
     }
-  }
+}
+
+template <int NB>
+__device__ __forceinline__ void load_inputs(const float* __restrict__ q, int64_t n, int in_dim, int64_t q0, int c,
+                                            int grp, bf16x8 (&xb)[NB]) {
+  float xr[NB][8];
+  load_raw<NB>(q, n, in_dim, q0, c, xr);
+  split_inputs<NB>(xr, grp, xb);
 }
 
 // One wave's share of the forward pass: NB blocks of 16 queries starting at
 // q0 (queries >= n_end are padding), weights and biases already in LDS.
 // Writes logits / decisions of the valid queries and adds their confusion
 // counts against g to cnt (when counts is non-null).
+// As bf16_fwd_tile, with the tile's raw inputs already in registers (the
+// grouped kernel loads the next tile's inputs while this one computes).
 template <int W, int NH, int NB>
-__device__ __forceinline__ void bf16_fwd_tile(const bf16x8* __restrict__ swt, const float* __restrict__ sbias,
-                                         const float* __restrict__ q, int64_t n, int in_dim, int64_t q0, float tau,
-                                         float* __restrict__ logits, uint8_t* __restrict__ hout,
-                                         const uint8_t* __restrict__ g, const unsigned long long* counts,
-                                         unsigned (&cnt)[4]) {
+__device__ __forceinline__ void bf16_fwd_tile_x(const bf16x8* __restrict__ swt, const float* __restrict__ sbias,
+                                                const float (&xr)[NB][8], int64_t n, int64_t q0, float tau,
+                                                float* __restrict__ logits, uint8_t* __restrict__ hout,
+                                                const uint8_t* __restrict__ g, const unsigned long long* counts,
+                                                unsigned (&cnt)[4]) {
   using N = B16<W, NH>;
   constexpr int RB = N::RB, KS = N::KS;
   const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4;
@@ -62,7 +84,7 @@ __device__ __forceinline__ void bf16_fwd_tile(const bf16x8* __restrict__ swt, co
     floatx4 acc[NB][RB];
     {
       bf16x8 xb[NB];
-      load_inputs<NB>(q, n, in_dim, q0, c, grp, xb);
+      split_inputs<NB>(xr, grp, xb);
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo) {
         const float* b = sbias + 16 * mo + 4 * grp;
@@ -132,3 +154,13 @@ __device__ __forceinline__ void bf16_fwd_tile(const bf16x8* __restrict__ swt, co
     }
   }
 
+template <int W, int NH, int NB>
+__device__ __forceinline__ void bf16_fwd_tile(const bf16x8* __restrict__ swt, const float* __restrict__ sbias,
+                                              const float* __restrict__ q, int64_t n, int in_dim, int64_t q0,
+                                              float tau, float* __restrict__ logits, uint8_t* __restrict__ hout,
+                                              const uint8_t* __restrict__ g, const unsigned long long* counts,
+                                              unsigned (&cnt)[4]) {
+  float xr[NB][8];
+  load_raw<NB>(q, n, in_dim, q0, threadIdx.x & 15, xr);
+  bf16_fwd_tile_x<W, NH, NB>(swt, sbias, xr, n, q0, tau, logits, hout, g, counts, cnt);
+}

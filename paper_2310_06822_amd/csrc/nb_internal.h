@@ -121,6 +121,9 @@ struct nb_group {
   int64_t* d_goff = nullptr;
   int* d_gn = nullptr;
   float* ray_t = nullptr;
+  int32_t* table = nullptr;         // occupied-cell count tables, (n+1)^3 per object
+  int64_t* d_toff = nullptr;
+  int box_method = 1;               // 0: scan the box's cells, 1: count table
   // forward plan
   int n_wg_cap = 0;                 // capacity of d_wg_first - 1 (workgroups of the widest variant grid)
   int variant = 0;                  // grouped forward tile shape
@@ -178,7 +181,9 @@ struct BF16TrainPlan {
   int64_t chunk = 0;     // queries per chunk (multiple of 64)
   int64_t padded = 0;    // n_wg * chunk
 };
-BF16TrainPlan bf16_train_plan(int64_t n);
+// Chunks of a training batch of n: at most max_wg chunks of a multiple of 64
+// queries (every chunk a workgroup writing one partial gradient).
+BF16TrainPlan bf16_train_plan(int64_t n, int max_wg = 256);
 bool bf16_train_supported(int in_dim, int n_hidden, int width);
 int64_t bf16_packt_elems(int n_hidden, int width);
 nb_status bf16_pack_t(const nb_bound* b, hipStream_t s);
@@ -200,8 +205,9 @@ nb_status group_forward(const nb_group* gr, const float* q, const int64_t* qoff,
 nb_status group_exact(const nb_group* gr, int kind, const float* q, const int64_t* qoff, int64_t n, uint8_t* g,
                       hipStream_t s);
 nb_status group_pack(const nb_group* gr, hipStream_t s);
-nb_status group_reduce_adam(const nb_group* gr, int n_wg, const AdamArgs& adam, float* loss, unsigned long long* counts,
-                            float loss_scale, hipStream_t s);
+nb_status group_build_tables(const nb_group* gr, int max_n, hipStream_t s);
+nb_status group_reduce_adam(const nb_group* gr, int n_wg, const AdamArgs& adam, const float* lr_obj, float* loss,
+                            unsigned long long* counts, float loss_scale, hipStream_t s);
 
 // optim.hip
 // Reduce partials over n_wg workgroups: writes grad (if non-null), loss and

@@ -72,17 +72,24 @@ __device__ __forceinline__ uint8_t voxel_ray_at(const float* __restrict__ row, c
 
 // -------------------------------------------------------------------- boxes
 
-// g = OR over cells cell(max(lo,-1)) .. cell(min(hi,1)) per axis; a box
-// with hi < -1, lo > 1 or lo > hi on some axis is empty.
-__device__ __forceinline__ uint8_t voxel_box_at(const float* __restrict__ row, const uint8_t* __restrict__ grid, int gn) {
+// Cells a[ax] .. b[ax] per axis that meet the closed box [lo, hi]:
+// cell(max(lo,-1)) .. cell(min(hi,1)); false for a box with hi < -1,
+// lo > 1 or lo > hi on some axis (it meets no cell).
+__device__ __forceinline__ bool box_cell_range(const float* __restrict__ row, int gn, int (&a)[3], int (&b)[3]) {
   const float half_n = (float)gn * 0.5f;
-  int a[3], b[3];
   for (int ax = 0; ax < 3; ++ax) {
     const float lo = row[ax], hi = row[3 + ax];
-    if (!(hi >= -1.0f && lo <= 1.0f && lo <= hi)) return 0;
+    if (!(hi >= -1.0f && lo <= 1.0f && lo <= hi)) return false;
     cell_of(fmaxf(lo, -1.0f), gn, half_n, a[ax]);
     cell_of(fminf(hi, 1.0f), gn, half_n, b[ax]);
   }
+  return true;
+}
+
+// g = OR over the box's cells, scanned row by row with an early exit.
+__device__ __forceinline__ uint8_t voxel_box_at(const float* __restrict__ row, const uint8_t* __restrict__ grid, int gn) {
+  int a[3], b[3];
+  if (!box_cell_range(row, gn, a, b)) return 0;
   for (int kz = a[2]; kz <= b[2]; ++kz)
     for (int jy = a[1]; jy <= b[1]; ++jy) {
       const uint8_t* r = grid + ((int64_t)kz * gn + jy) * gn;
@@ -90,6 +97,22 @@ __device__ __forceinline__ uint8_t voxel_box_at(const float* __restrict__ row, c
         if (r[ix]) return 1;
     }
   return 0;
+}
+
+// Occupied-cell count table of a grid: S[(k*(n+1) + j)*(n+1) + i] is the
+// number of occupied cells with z < k, y < j, x < i.  The box's OR is then
+// "count over its cell range > 0", an integer inclusion-exclusion over the
+// range's 8 corners: the same answer as the scan, in constant time.
+__device__ __forceinline__ uint8_t voxel_box_table_at(const float* __restrict__ row,
+                                                      const int32_t* __restrict__ S, int gn) {
+  int a[3], b[3];
+  if (!box_cell_range(row, gn, a, b)) return 0;
+  const int64_t m = gn + 1;
+  const int64_t x0 = a[0], x1 = b[0] + 1, y0 = a[1] * m, y1 = (b[1] + 1) * m, z0 = a[2] * m * m,
+                z1 = (int64_t)(b[2] + 1) * m * m;
+  const int32_t cnt = S[z1 + y1 + x1] - S[z0 + y1 + x1] - S[z1 + y0 + x1] - S[z1 + y1 + x0] + S[z0 + y0 + x1] +
+                      S[z0 + y1 + x0] + S[z1 + y0 + x0] - S[z0 + y0 + x0];
+  return cnt > 0;
 }
 
 // Point, ray or box query on one grid (query kinds as in nbound.h: 0 point,

@@ -9,9 +9,11 @@ Two phases, both run entirely on the GPU kernels:
    schedule): in scheduling iterations of K steps, alpha is incremented by
    `inc` after every iteration whose validation set still has a false
    negative; training stops once FN = 0 has held for `patience` consecutive
-   iterations (six in the paper) or after `max_iters` iterations.  The
-   validation set is drawn with its own seed, disjoint from the training
-   stream and from any held-out test set.
+   iterations (six in the paper) or after `max_iters` iterations.  Every
+   iteration checks a fresh validation draw (its own seed, the iteration
+   number as the sampler's step), disjoint from the training stream and from
+   any held-out test set, so six FN-free iterations have seen six distinct
+   validation sets.
 
 Optional L1 + L2 regularisation ramps lambda linearly from 0 to lam_max over
 the ramp phase and keeps it there (supplemental "Regularization").
@@ -58,12 +60,14 @@ class TrainResult:
         return self.samples / self.seconds if self.seconds > 0 else 0.0
 
 
-def validation_set(ind: Indicator, kind: str, seed: int, n: int):
+def validation_set(ind: Indicator, kind: str, seed: int, n: int, draw: int = 0, out=None):
+    """Validation regions (draw `draw` of the stream `seed`) and their exact
+    answers; refills `out` = (q, g) when given."""
     k = KINDS[kind]
     d = ind.dim if k == POINT else 6
-    q = torch.empty((n, d), dtype=torch.float32, device="cuda")
-    nb_sample_queries(k, ind.dim, seed, 0, q)
-    g = torch.empty(n, dtype=torch.uint8, device="cuda")
+    q, g = out if out is not None else (torch.empty((n, d), dtype=torch.float32, device="cuda"),
+                                        torch.empty(n, dtype=torch.uint8, device="cuda"))
+    nb_sample_queries(k, ind.dim, seed, draw, q)
     nb_query_exact(ind.handle, k, q, g)
     return q, g
 
@@ -92,6 +96,7 @@ def train(bound: Bound, ind: Indicator, kind: str, seed: int, sched: Schedule, v
                 nb_bound_train_step(bound.handle, ind.handle, k, seed, step, sched.batch, a, sched.beta, sched.lr,
                                     lam, lam)
                 step += 1
+            val = validation_set(ind, kind, val_seed, sched.val_n, draw=res.iters, out=val)
             fn = int(bound.counts(*val)[3].item())
             res.val_fn_history.append(fn)
             res.iters += 1
@@ -108,4 +113,95 @@ def train(bound: Bound, ind: Indicator, kind: str, seed: int, sched: Schedule, v
     res.steps = step
     res.samples = step * sched.batch
     res.alpha_final = a
+    return res
+
+
+# ------------------------------------------------------------------ groups
+
+@dataclass
+class GroupTrainResult(TrainResult):
+    alpha_obj: list = field(default_factory=list)       # final per-object FN weights
+    objects_with_fn: list = field(default_factory=list)  # per iteration: objects whose validation FN > 0
+
+
+def group_validation_set(group, kind: str, seed: int, per_obj: int, draw: int = 0, out=None):
+    """per_obj regions per object (object o: rows o*per_obj ..; draw `draw`
+    of the stream `seed`) and their exact answers on each object's own grid;
+    refills `out` = (q, qoff, g) when given."""
+    from . import nb_group_query_exact
+    k = KINDS[kind]
+    n = group.n_obj * per_obj
+    if out is None:
+        out = (torch.empty((n, 3 if k == POINT else 6), dtype=torch.float32, device="cuda"),
+               torch.arange(0, n + 1, per_obj, dtype=torch.int64, device="cuda"),
+               torch.empty(n, dtype=torch.uint8, device="cuda"))
+    q, qoff, g = out
+    nb_sample_queries(k, 3, seed, draw, q)
+    nb_group_query_exact(group.handle, group.n_obj, k, q, qoff, g)
+    return q, qoff, g
+
+
+def train_group(group, kind: str, seed: int, sched: Schedule, val_seed: int | None = None,
+                log=None) -> GroupTrainResult:
+    """Alg. 1 for every object of a group at once.  Ramp: alpha rises
+    linearly 1 -> alpha_max for all objects.  Continuation in iterations of k
+    steps, each followed by a fresh validation draw of sched.val_n regions
+    per object: an object with a false negative gets alpha += inc (and
+    trains); an object FN-free for `patience` iterations in a row stops
+    training (learning rate 0) until a later draw shows it a false negative
+    again.  Training ends once the whole group has been FN-free for
+    `patience` iterations in a row (the paper's stopping rule applied to all
+    of the group's validation regions), or after max_iters iterations.
+    sched.batch is the per-object batch."""
+    import numpy as np
+
+    from . import nb_group_train_step
+    k = KINDS[kind]
+    res = GroupTrainResult()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T = sched.steps
+    step = 0
+    for t in range(T):
+        a = 1.0 + (sched.alpha_max - 1.0) * (t / (T - 1) if T > 1 else 1.0)
+        nb_group_train_step(group.handle, group.n_obj, k, seed, step, sched.batch, a, sched.beta, sched.lr)
+        step += 1
+    alpha = np.full(group.n_obj, sched.alpha_max, dtype=np.float32)
+    lr = np.full(group.n_obj, sched.lr, dtype=np.float32)
+    clean = np.zeros(group.n_obj, dtype=np.int64)
+    clean_all = 0
+    if val_seed is not None and sched.max_iters > 0:
+        val = None
+        a_dev = torch.from_numpy(alpha).cuda()
+        lr_dev = torch.from_numpy(lr).cuda()
+        while clean_all < sched.patience and res.iters < sched.max_iters:
+            if (lr > 0).any():
+                for _ in range(sched.k):
+                    nb_group_train_step(group.handle, group.n_obj, k, seed, step, sched.batch, 0.0, sched.beta,
+                                        sched.lr, alpha_obj=a_dev, lr_obj=lr_dev)
+                    step += 1
+            val = group_validation_set(group, kind, val_seed, sched.val_n, draw=res.iters, out=val)
+            fn = group.counts(*val)[:, 3].cpu().numpy()
+            bad = fn > 0
+            alpha[bad] += sched.inc
+            lr[bad] = sched.lr
+            clean[bad] = 0
+            clean[~bad] += 1
+            lr[clean >= sched.patience] = 0.0
+            clean_all = 0 if bad.any() else clean_all + 1
+            a_dev.copy_(torch.from_numpy(alpha))
+            lr_dev.copy_(torch.from_numpy(lr))
+            res.val_fn_history.append(int(fn.sum()))
+            res.objects_with_fn.append(int(bad.sum()))
+            res.iters += 1
+            if log:
+                log(f"group schedule iteration {res.iters}: step {step}, validation FN {int(fn.sum())} over "
+                    f"{int(bad.sum())} objects, {int((lr > 0).sum())} training, alpha max {alpha.max():g}")
+        res.converged = clean_all >= sched.patience
+    torch.cuda.synchronize()
+    res.seconds = time.perf_counter() - t0
+    res.steps = step
+    res.samples = step * sched.batch * group.n_obj
+    res.alpha_final = float(alpha.max())
+    res.alpha_obj = alpha.tolist()
     return res

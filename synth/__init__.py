@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "rng", "discs2d", "metaballs3d", "metaballs4d", "random_grid",
     "points", "points4d", "rays", "boxes", "planes", "init_params",
-    "layer_shapes", "num_params", "seed_for",
+    "layer_shapes", "num_params", "seed_for", "object_set",
 ]
 
 # Seed bases per stream: scene / training stream / held-out eval / init.
@@ -67,6 +67,22 @@ def metaballs4d(seed: int, k: int = 24, rlo: float = 0.05, rhi: float = 0.2):
     b = g.uniform(-0.7, 0.7, size=(k, 3)).astype(np.float32)
     r = g.uniform(rlo, rhi, size=(k,)).astype(np.float32)
     return np.ascontiguousarray(a), np.ascontiguousarray(b), np.ascontiguousarray(r)
+
+
+def object_set(seed: int, n_obj: int, grid_sizes=(32, 64, 128), widths=(32, 64, 128), k_range=(4, 32),
+               rlo: float = 0.05, rhi: float = 0.25):
+    """Per-object draws of a batch of bounds: a list of dicts with the
+    object's grid size n, hidden width w, and metaball scene (centres,
+    radii; k balls with k uniform in k_range inclusive)."""
+    g = rng(seed)
+    out = []
+    for o in range(n_obj):
+        n = int(g.choice(grid_sizes))
+        w = int(g.choice(widths))
+        k = int(g.integers(k_range[0], k_range[1] + 1))
+        c, r = metaballs3d(int(seed) * 1000 + o, k=k, rlo=rlo, rhi=rhi)
+        out.append({"n": n, "width": w, "k": k, "centres": c, "radii": r})
+    return out
 
 
 def random_grid(seed: int, n: int, density: float = 0.1) -> np.ndarray:

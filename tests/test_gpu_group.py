@@ -155,19 +155,27 @@ def test_group_exact(kind):
     qs = [gen(420 + o, c) for o, c in enumerate(counts)]
     q = np.concatenate(qs)
     qoff = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
-    out = host(gr.query(kind, cuda(q), cuda(qoff)))
+    if kind == "box":   # edge boxes: whole cube, outside, degenerate, inverted, touching faces
+        qs[0][:6] = [[-2, -2, -2, 2, 2, 2], [1.5, 0, 0, 2, 1, 1], [0.1, 0.1, 0.1, 0.1, 0.1, 0.1],
+                     [0.3, 0.3, 0.3, 0.2, 0.4, 0.4], [-1, -1, -1, -1, -1, -1], [1, 1, 1, 1, 1, 1]]
+        q = np.concatenate(qs)
     fn = {"box": I.voxel_boxes, "ray": I.voxel_rays, "point": I.voxel_points}[kind]
-    for o, (qo, grid, n) in enumerate(zip(qs, grids, sizes)):
-        if qo.shape[0]:
-            assert np.array_equal(out[qoff[o]:qoff[o + 1]], fn(qo, grid, n)), o
+    for method in ([nb.BOX_TABLE, nb.BOX_SCAN] if kind == "box" else [nb.BOX_TABLE]):
+        nb.nb_group_set_box_method(gr.handle, method)
+        out = host(gr.query(kind, cuda(q), cuda(qoff)))
+        for o, (qo, grid, n) in enumerate(zip(qs, grids, sizes)):
+            if qo.shape[0]:
+                assert np.array_equal(out[qoff[o]:qoff[o + 1]], fn(qo, grid, n)), (method, o)
 
 
-def _oracle_group_steps(widths, nh, grids, sizes, thetas, seed, steps, per_obj, alpha_obj=None):
+def _oracle_group_steps(widths, nh, grids, sizes, thetas, seed, steps, per_obj, alpha_obj=None, lr_obj=None):
     """Alg. 1 for every object on its rows of one shared draw of regions
-    (FN weight alpha_obj[o] if given, else the linear ramp)."""
+    (FN weight alpha_obj[o] if given, else the linear ramp; learning rate
+    lr_obj[o] if given, 0 = no update)."""
     n_obj = len(widths)
     th = [t.astype(np.float64).copy() for t in thetas]
-    opts = [Adam(t.size, lr=1e-3) for t in th]
+    lrs = [1e-3] * n_obj if lr_obj is None else [float(x) for x in lr_obj]
+    opts = [Adam(t.size, lr=lr) if lr > 0 else None for t, lr in zip(th, lrs)]
     losses = []
     for t in range(steps):
         qall = sampling.sample("box", seed, t, n_obj * per_obj, 3)
@@ -179,7 +187,8 @@ def _oracle_group_steps(widths, nh, grids, sizes, thetas, seed, steps, per_obj, 
             ao = a if alpha_obj is None else float(alpha_obj[o])
             lv, g, _ = T.step_grad(th[o], 6, [widths[o]] * nh, q, y, ao, 1.0, bf16=True)
             row.append(lv)
-            th[o] = opts[o].step(th[o], g)
+            if opts[o] is not None:
+                th[o] = opts[o].step(th[o], g)
         losses.append(row)
     return th, np.array(losses)
 
@@ -192,18 +201,23 @@ def test_group_train_steps_parity(per_obj, per_alpha):
     gr.set_voxels(cuda(np.concatenate(grids)), sizes)
     steps, seed = 4, 7007
     alpha_obj = np.array([1.0, 40.0, 7.5, 100.0], np.float32) if per_alpha else None
-    th_ref, loss_ref = _oracle_group_steps(widths, nh, grids, sizes, thetas, seed, steps, per_obj, alpha_obj)
+    lr_obj = np.array([1e-3, 0.0, 1e-3, 5e-4], np.float32) if per_alpha else None
+    th_ref, loss_ref = _oracle_group_steps(widths, nh, grids, sizes, thetas, seed, steps, per_obj, alpha_obj, lr_obj)
     loss = torch.empty(len(widths), dtype=torch.float32, device="cuda")
     cnt = torch.empty(4 * len(widths), dtype=torch.int64, device="cuda")
     a_dev = cuda(alpha_obj) if per_alpha else None
+    lr_dev = cuda(lr_obj) if per_alpha else None
     for t in range(steps):
         nb.nb_group_train_step(gr.handle, gr.n_obj, nb.BOX, seed, t, per_obj, T.alpha_ramp(t, steps), 1.0, 1e-3,
-                               loss=loss, counts=cnt, alpha_obj=a_dev)
+                               loss=loss, counts=cnt, alpha_obj=a_dev, lr_obj=lr_dev)
         lg = host(loss)
         assert np.all(np.abs(lg - loss_ref[t]) <= 2e-3 * np.abs(loss_ref[t])), (t, lg, loss_ref[t])
         assert np.all(host(cnt).reshape(-1, 4).sum(1) == per_obj)
     th = host(gr.params()).astype(np.float64)
     for o in range(len(widths)):
+        if lr_obj is not None and lr_obj[o] == 0:   # frozen: untouched, bit for bit
+            assert np.array_equal(th[gr.offsets[o]:gr.offsets[o + 1]], thetas[o].astype(np.float32)), o
+            continue
         d = th[gr.offsets[o]:gr.offsets[o + 1]] - thetas[o]
         dr = th_ref[o] - thetas[o]
         assert np.linalg.norm(d - dr) <= 5e-2 * np.linalg.norm(dr), o
