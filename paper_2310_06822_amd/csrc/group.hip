@@ -288,67 +288,50 @@ __global__ void k_table_yz(const int* __restrict__ gns, const int64_t* __restric
   }
 }
 
-// Grouped pack: every element of every object's forward (and, for training,
-// transposed) fragments.
+// Grouped pack: every element of every object's forward and transposed
+// fragments; blockIdx.y is the object, x strides over its elements (forward
+// pack first, then the transposed one).
 __global__ void k_group_pack(const float* __restrict__ theta, const int64_t* __restrict__ poff,
                              const int64_t* __restrict__ pkoff, const int64_t* __restrict__ ptoff,
-                             const int* __restrict__ widths, int n_obj, int in_dim, int NH,
-                             uint16_t* __restrict__ pack, uint16_t* __restrict__ packT, int64_t total_fwd,
-                             int64_t total_t) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool t = idx >= total_fwd;
-  const int64_t e = t ? idx - total_fwd : idx;
-  if (e >= (t ? total_t : total_fwd)) return;
-  const int64_t* off = t ? ptoff : pkoff;   // in 16-byte slices
-  int lo = 0, hi = n_obj;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) / 2;
-    if (off[mid] * 8 <= e) lo = mid; else hi = mid;
+                             const int* __restrict__ widths, int in_dim, int NH, uint16_t* __restrict__ pack,
+                             uint16_t* __restrict__ packT) {
+  const int o = blockIdx.y;
+  const int64_t nf = (pkoff[o + 1] - pkoff[o]) * 8, nt = (ptoff[o + 1] - ptoff[o]) * 8;
+  const float* th = theta + poff[o];
+  const int W = widths[o];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nf + nt;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < nf)
+      pack[pkoff[o] * 8 + e] = nb_bf16_pack_elem(th, in_dim, W, NH, e);
+    else
+      packT[ptoff[o] * 8 + (e - nf)] = nb_bf16_pack_t_elem(th, in_dim, W, NH, e - nf);
   }
-  const int64_t local = e - off[lo] * 8;
-  if (t)
-    packT[e] = nb_bf16_pack_t_elem(theta + poff[lo], in_dim, widths[lo], NH, local);
-  else
-    pack[e] = nb_bf16_pack_elem(theta + poff[lo], in_dim, widths[lo], NH, local);
 }
 
-// Sum of the per-chunk partials of every parameter of every object, in chunk
-// order, then one Adam step.  32 parameters per block, 8 strided partial
-// sums per parameter added in order (as for a single bound).
-__global__ __launch_bounds__(256) void k_group_reduce(const float* __restrict__ partial, int n_wg, int n_obj,
+// Sum of the per-chunk partials of every parameter of every object, then one
+// Adam step.  blockIdx.y is the object, one thread per parameter; the chunks
+// are summed as for a single bound (eight strided partial sums, each in
+// chunk order, then added in order), so a group member's update is bit for
+// bit a single bound's.
+__global__ __launch_bounds__(256) void k_group_reduce(const float* __restrict__ partial, int n_wg,
                                                       const int64_t* __restrict__ poff, const int* __restrict__ widths,
                                                       int in_dim, int NH, float* __restrict__ theta,
                                                       float* __restrict__ m, float* __restrict__ v, AdamArgs adam,
                                                       const float* __restrict__ lr_obj) {
-  __shared__ float part[8][32];
-  const int t = threadIdx.x, j = t % 32, k = t / 32;
-  const int64_t p = (int64_t)blockIdx.x * 32 + j;
-  const int64_t P_all = poff[n_obj];
-  int o = 0;
-  float sacc = 0.0f;
-  if (p < P_all) {
-    int lo = 0, hi = n_obj;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) / 2;
-      if (poff[mid] <= p) lo = mid; else hi = mid;
-    }
-    o = lo;
-    const int64_t Po = poff[o + 1] - poff[o], pl = p - poff[o];
-    const float* base = partial + (int64_t)n_wg * poff[o] + pl;
-    for (int w = k; w < n_wg; w += 8) sacc += base[(int64_t)w * Po];
-  }
-  part[k][j] = sacc;
-  __syncthreads();
-  if (t < 32 && p < P_all) {
-    float tot = part[0][t];
+  const int o = blockIdx.y;
+  const int64_t Po = poff[o + 1] - poff[o];
+  const int64_t pl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pl >= Po) return;
+  const float* base = partial + (int64_t)n_wg * poff[o] + pl;
+  float part[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  for (int w = 0; w < n_wg; ++w) part[w & 7] += base[(int64_t)w * Po];
+  float tot = part[0];
 #pragma unroll
-    for (int i = 1; i < 8; ++i) tot += part[i][t];
-    const int64_t pl = p - poff[o];
-    AdamArgs a = adam;
-    if (lr_obj) a.lr = lr_obj[o];
-    // a learning rate of 0 freezes the object: parameters and moments stay
-    if (a.lr != 0.0f) nb_adam_update(p, tot, theta, m, v, a, nb_is_weight(pl, in_dim, widths[o], NH) != 0);
-  }
+  for (int i = 1; i < 8; ++i) tot += part[i];
+  AdamArgs a = adam;
+  if (lr_obj) a.lr = lr_obj[o];
+  // a learning rate of 0 freezes the object: parameters and moments stay
+  if (a.lr != 0.0f) nb_adam_update(poff[o] + pl, tot, theta, m, v, a, nb_is_weight(pl, in_dim, widths[o], NH) != 0);
 }
 
 // Per-object mean loss and confusion counts of a grouped training step.
@@ -374,9 +357,9 @@ __global__ void k_group_aux(const float* __restrict__ aux, int n_wg, int n_obj, 
 
 nb_status group_reduce_adam(const nb_group* gr, int n_wg, const AdamArgs& adam, const float* lr_obj, float* loss,
                             unsigned long long* counts, float loss_scale, hipStream_t s) {
-  const unsigned blocks = (unsigned)((gr->n_params + 31) / 32);
-  k_group_reduce<<<blocks, 256, 0, s>>>(gr->partial, n_wg, gr->n_obj, gr->d_poff, gr->d_widths, gr->in_dim,
-                                        gr->n_hidden, gr->theta, gr->m, gr->v, adam, lr_obj);
+  const dim3 grid((unsigned)((gr->max_obj_params + 255) / 256), (unsigned)gr->n_obj);
+  k_group_reduce<<<grid, 256, 0, s>>>(gr->partial, n_wg, gr->d_poff, gr->d_widths, gr->in_dim, gr->n_hidden, gr->theta,
+                                      gr->m, gr->v, adam, lr_obj);
   NB_LAUNCHED();
   if (loss || counts) {
     k_group_aux<<<(unsigned)((gr->n_obj + 255) / 256), 256, 0, s>>>(gr->aux, n_wg, gr->n_obj, loss_scale, loss,
@@ -489,11 +472,9 @@ nb_status group_build_tables(const nb_group* gr, int max_n, hipStream_t s) {
 }
 
 nb_status group_pack(const nb_group* gr, hipStream_t s) {
-  const int64_t tf = gr->pack_elems, tt = gr->packt_elems;
-  const int64_t total = tf + tt;
-  k_group_pack<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(gr->theta, gr->d_poff, gr->d_pkoff, gr->d_ptoff,
-                                                              gr->d_widths, gr->n_obj, gr->in_dim, gr->n_hidden,
-                                                              gr->pack16, gr->pack16t, tf, tt);
+  const dim3 grid(64, (unsigned)gr->n_obj);
+  k_group_pack<<<grid, 256, 0, s>>>(gr->theta, gr->d_poff, gr->d_pkoff, gr->d_ptoff, gr->d_widths, gr->in_dim,
+                                    gr->n_hidden, gr->pack16, gr->pack16t);
   NB_LAUNCHED();
   return NB_OK;
 }

@@ -108,6 +108,7 @@ nb_status nb_group_create(int n_obj, int in_dim, const int* widths_host, int n_h
     g->ptoff[o + 1] = g->ptoff[o] + nb_bf16_t_slices(g->widths[o], n_hidden);
   }
   g->n_params = g->poff[n_obj];
+  for (int o = 0; o < n_obj; ++o) g->max_obj_params = std::max(g->max_obj_params, g->poff[o + 1] - g->poff[o]);
   g->pack_elems = g->pkoff[n_obj] * 8;
   g->packt_elems = g->ptoff[n_obj] * 8;
   std::vector<int> perm(n_obj);

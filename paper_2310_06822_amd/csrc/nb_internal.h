@@ -109,7 +109,7 @@ struct nb_group {
   int64_t* d_ptoff = nullptr;
   int* d_perm = nullptr;            // objects by decreasing width
   int* d_class = nullptr;           // concatenated class member lists
-  int64_t n_params = 0, pack_elems = 0, packt_elems = 0;
+  int64_t n_params = 0, pack_elems = 0, packt_elems = 0, max_obj_params = 0;
   float* theta = nullptr;
   float* m = nullptr;
   float* v = nullptr;
