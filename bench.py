@@ -137,7 +137,12 @@ def run_workload(W, args, with_cpu: bool):
     theta0 = synth.init_params(seeds["init"], W.in_dim, widths)
 
     # ---- training (Alg. 1 on the device): ramp, then the step-wise schedule
-    sched = W.schedule(**({"steps": args.train_steps} if args.train_steps is not None else {}))
+    over = {"steps": args.train_steps} if args.train_steps is not None else {}
+    if getattr(args, "lr_decay", None) is not None:
+        over["lr_decay"] = args.lr_decay
+    if getattr(args, "adapt_iters", None) is not None:
+        over["max_iters"] = args.adapt_iters
+    sched = W.schedule(**over)
     if args.no_adapt:
         sched.max_iters = 0
     bound.set_params(theta0)
@@ -236,7 +241,11 @@ def run_group_workload(GW, args):
     sched = trainer.Schedule(steps=args.train_steps if args.train_steps is not None else GW.train_steps,
                              batch=GW.per_obj, alpha_max=GW.alpha_max, k=GW.adapt_k, inc=GW.adapt_inc,
                              patience=GW.patience, max_iters=0 if args.no_adapt else GW.adapt_iters,
-                             val_n=GW.val_per_obj)
+                             val_n=GW.val_per_obj, lr_decay=GW.lr_decay)
+    if getattr(args, "lr_decay", None) is not None:
+        sched.lr_decay = args.lr_decay
+    if getattr(args, "adapt_iters", None) is not None and not args.no_adapt:
+        sched.max_iters = args.adapt_iters
     group.set_params(theta0)
     nb.nb_group_train_step(group.handle, group.n_obj, kind, GW.seeds["train"], 0, GW.per_obj, 1.0)   # work space
     group.set_params(theta0)
@@ -254,6 +263,9 @@ def run_group_workload(GW, args):
     variant = autotune.tune_group(group, q, qoff)
     cnt = group.counts(q, qoff, g).cpu().numpy()
     tp, fp, tn, fn = (int(x) for x in cnt.sum(0))
+    fn_objects = [{"object": int(o), "width": widths[o], "grid": objs[o]["n"], "balls": objs[o]["k"],
+                   "alpha": round(res.alpha_obj[o], 1) if res.alpha_obj else None, "fn": int(cnt[o, 3]),
+                   "positives": int(cnt[o, 0] + cnt[o, 3])} for o in np.nonzero(cnt[:, 3])[0]]
     log(f"[{GW.name}] held-out {n_eval}: TP {tp} FP {fp} TN {tn} FN {fn}; objects with FN "
         f"{int((cnt[:, 3] > 0).sum())} (tile variant {variant})")
 
@@ -311,7 +323,7 @@ def run_group_workload(GW, args):
         "bound_speedup_vs_exact_scan": scan_ms / kern_ms,
         "exact_scan_equals_table": scan_same,
         "heldout": {"n": n_eval, "tp": tp, "fp": fp, "tn": tn, "fn": fn, "fp_rate": fp / n_eval,
-                    "objects_with_fn": int((cnt[:, 3] > 0).sum())},
+                    "objects_with_fn": int((cnt[:, 3] > 0).sum()), "fn_objects": fn_objects[:32]},
         "fn_zero": fn == 0,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["bf16"],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["bf16"], 4), "traffic": None,
@@ -330,6 +342,9 @@ def main():
     ap.add_argument("--train-steps", type=int, default=None)
     ap.add_argument("--eval-n", type=int, default=None)
     ap.add_argument("--no-adapt", action="store_true", help="ramp phase only (no step-wise continuation)")
+    ap.add_argument("--adapt-iters", type=int, default=None, help="cap on step-wise scheduling iterations")
+    ap.add_argument("--lr-decay", type=float, default=None,
+                    help="learning-rate factor per scheduling iteration (default: the workload's)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (scales HBM byte counters in profiles)")

@@ -164,6 +164,15 @@ nb_status nb_bound_shape(const nb_bound* b, int* in_dim, int* n_hidden, int* wid
 nb_status nb_bound_num_variants(const nb_bound* b, int* count);
 nb_status nb_bound_set_variant(nb_bound* b, int variant);
 
+/* Activation recomputation for bfloat16 training of wide or deep bounds.
+ * every = 0 (default) keeps all n_hidden - 1 hidden activations of the batch
+ * for the backward pass.  every = k (2..64) keeps only the checkpoints A_0,
+ * A_k, A_2k, ... and one segment of k - 1 scratch buffers; the backward
+ * recomputes each segment's activations from its checkpoint with the forward
+ * kernel (identical bits, so identical gradients) at the cost of about one
+ * more forward pass.  Float32 bounds accept only 0. */
+nb_status nb_bound_set_recompute(nb_bound* b, int every);
+
 /* Copy theta (device, float32[n_params]) into the bound; resets the Adam
  * moments and step count to zero. */
 nb_status nb_bound_set_params(nb_bound* b, const float* theta, int64_t n_params, void* stream);

@@ -183,6 +183,10 @@ def nb_bound_num_variants(b) -> int:
     return n.value
 
 
+def nb_bound_set_recompute(b, every: int):
+    _check(lib().nb_bound_set_recompute(b, int(every)))
+
+
 def nb_bound_set_variant(b, variant: int):
     _check(lib().nb_bound_set_variant(b, int(variant)))
 

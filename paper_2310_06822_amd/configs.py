@@ -7,9 +7,11 @@ are replaced by seeded synthetic scenes of the same kind; network shapes are
 
 Training follows Alg. 1 with the FN weight ramped linearly 1 -> alpha_max
 over `train_steps`, then (if `adapt_iters` > 0) the paper's step-wise
-schedule: every `adapt_k` steps alpha grows by `adapt_inc` while a
-validation set (seed 5000+i) still has false negatives; stop after six
-FN-free iterations.
+schedule: every `adapt_k` steps alpha grows by `adapt_inc` while a fresh
+validation draw (seed 5000+i) still has false negatives; stop after six
+FN-free iterations.  `lr_decay` < 1 multiplies the learning rate by that
+factor after every scheduling iteration (a continuation-phase setting of
+this implementation; the paper keeps lr = 1e-3).
 """
 
 from __future__ import annotations
@@ -35,6 +37,7 @@ class Workload:
     adapt_k: int = 250
     adapt_inc: float = 50.0
     adapt_iters: int = 400
+    lr_decay: float = 1.0
     bench_also: bool = False   # measured by `bench.py --also`
 
     @property
@@ -45,7 +48,8 @@ class Workload:
     def schedule(self, **kw):
         from .trainer import Schedule
         args = dict(steps=self.train_steps, batch=self.batch, alpha_max=self.alpha_max, k=self.adapt_k,
-                    inc=self.adapt_inc, max_iters=self.adapt_iters, val_n=min(self.eval_n, 1 << 24))
+                    inc=self.adapt_inc, max_iters=self.adapt_iters, val_n=min(self.eval_n, 1 << 24),
+                    lr_decay=self.lr_decay)
         args.update(kw)
         return Schedule(**args)
 
@@ -57,10 +61,11 @@ VOXEL3D_POINT = Workload("voxel3d_point", 1, "point", 3, 3, 64, 3, "f32",
                          train_steps=5000, batch=1 << 16, eval_n=1 << 24)
 VOXEL3D_RAY = Workload("voxel3d_ray", 2, "ray", 3, 6, 128, 4, "bf16",
                        scene={"type": "metaball_voxels", "k": 16, "n": 128, "rlo": 0.05, "rhi": 0.25, "seed_of": 1},
-                       train_steps=5000, batch=1 << 18, eval_n=1 << 24, bench_also=True)
+                       train_steps=5000, batch=1 << 18, eval_n=1 << 24, lr_decay=0.99, bench_also=True)
 METABALL4D_POINT = Workload("metaball4d_point", 4, "point", 4, 4, 256, 6, "bf16",
                             scene={"type": "metaballs4d", "k": 24, "rlo": 0.05, "rhi": 0.2},
-                            train_steps=2000, batch=1 << 20, eval_n=1 << 24)
+                            train_steps=2000, batch=1 << 20, eval_n=1 << 24, adapt_k=100, adapt_iters=150,
+                            lr_decay=0.99)
 
 WORKLOADS = {w.name: w for w in (DISC2D_POINT, VOXEL3D_POINT, VOXEL3D_RAY, METABALL4D_POINT)}
 
@@ -88,6 +93,7 @@ class GroupWorkload:
     adapt_inc: float = 50.0
     adapt_iters: int = 400
     patience: int = 6
+    lr_decay: float = 1.0
 
     @property
     def seeds(self):
@@ -97,6 +103,6 @@ class GroupWorkload:
 
 BATCHED_BOX = GroupWorkload("batched_box", 3, 256, "box", 6, 3, grid_sizes=(32, 64, 128), widths=(32, 64, 128),
                             k_range=(4, 32), train_steps=2000, per_obj=1 << 12, eval_per_obj=1 << 16,
-                            val_per_obj=1 << 16)
+                            val_per_obj=1 << 16, adapt_iters=300, lr_decay=0.99)
 
 GROUP_WORKLOADS = {BATCHED_BOX.name: BATCHED_BOX}

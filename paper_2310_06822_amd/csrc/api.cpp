@@ -1,5 +1,6 @@
 // extern "C" entry points of libnbound (declared and documented in nbound.h):
 // argument checks, handle life cycle, and the launch sequences.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -74,16 +75,20 @@ nb_status train_partials(nb_bound* b, const float* q, const uint8_t* y, int64_t 
   const float tau = tau_of(1e-5f);
   if (b->precision != NB_BF16) return f32_train_partials(b, q, y, n, alpha, beta, tau, n_wg, s);
   const BF16TrainPlan plan = bf16_train_plan(n);
-  if (b->tr_cap < plan.padded) {
-    // grows the activation / gradient work space (synchronising)
+  const int slots = bf16_act_slots(b->n_hidden, b->recompute);
+  if (b->tr_cap < plan.padded || b->tr_slots != slots) {
+    // (re)sizes the activation / gradient work space (synchronising)
     NB_HIP(hipStreamSynchronize(s));
+    const int64_t cap = std::max(plan.padded, b->tr_cap);
     dev_free_u16(b->tr_act);
     dev_free_u16(b->tr_grad);
     b->tr_cap = 0;
-    const size_t per = (size_t)plan.padded * b->width;
-    NB_HIP(hipMalloc(reinterpret_cast<void**>(&b->tr_act), per * (b->n_hidden - 1) * sizeof(uint16_t)));
+    b->tr_slots = 0;
+    const size_t per = (size_t)cap * b->width;
+    NB_HIP(hipMalloc(reinterpret_cast<void**>(&b->tr_act), per * slots * sizeof(uint16_t)));
     NB_HIP(hipMalloc(reinterpret_cast<void**>(&b->tr_grad), per * 2 * sizeof(uint16_t)));
-    b->tr_cap = plan.padded;
+    b->tr_cap = cap;
+    b->tr_slots = slots;
   }
   *n_wg = plan.n_wg;
   return bf16_train_partials(b, q, y, n, alpha, beta, tau, plan, s);
@@ -374,6 +379,14 @@ nb_status nb_bound_shape(const nb_bound* b, int* in_dim, int* n_hidden, int* wid
 nb_status nb_bound_num_variants(const nb_bound* b, int* count) {
   NB_REQUIRE(b && count, "NULL argument");
   *count = b->precision == NB_BF16 ? bf16_variants_for(b->width) : 1;
+  return NB_OK;
+}
+
+nb_status nb_bound_set_recompute(nb_bound* b, int every) {
+  NB_REQUIRE(b, "bound is NULL");
+  NB_REQUIRE(every == 0 || (every >= 2 && every <= 64), "checkpoint interval must be 0 or 2..64");
+  NB_REQUIRE(b->precision == NB_BF16 || every == 0, "activation recomputation applies to bfloat16 training");
+  b->recompute = every;
   return NB_OK;
 }
 

@@ -522,13 +522,38 @@ struct TrainJob {
   const float* theta = nullptr;
   const bf16x8* pack = nullptr;
   const bf16x8* packT = nullptr;
-  uint16_t* act = nullptr;          // member 0: A_l at act + l * Bp * W
+  uint16_t* act = nullptr;          // member 0: activation slots, slot(l) at act + slot(l) * Bp * W
+  int every = 0;                    // checkpoint interval of the activation recomputation (0: keep all)
   uint16_t* grad = nullptr;         // member 0: D ping-pong at grad + k * Bp * W
   float* partial = nullptr;
   float* aux = nullptr;
   float alpha = 1, beta = 1, inv_n = 1, tau = 0;
   TrObjs T{};
 };
+
+// Activation slots of the layer-wise training pass.  every = 0 keeps every
+// hidden activation A_0 .. A_{NH-2}.  every = k >= 2 keeps the checkpoints
+// A_0, A_k, A_2k, ... and one segment of k - 1 scratch slots: the forward
+// writes each segment's other activations into the scratch slots, and the
+// backward recomputes a segment's activations from its checkpoint (the same
+// kernel, so the same bits) when it moves down into that segment.
+struct ActSlots {
+  int every = 0, n_act = 0, n_ckpt = 0;
+  int slot(int l) const {
+    if (every < 2) return l;
+    return l % every == 0 ? l / every : n_ckpt + (l % every) - 1;
+  }
+  int count() const { return every < 2 ? n_act : n_ckpt + std::min(every - 1, n_act - 1); }
+  int segment(int l) const { return every < 2 ? 0 : l / every; }
+};
+
+ActSlots act_slots(int NH, int every) {
+  ActSlots a;
+  a.every = every;
+  a.n_act = NH - 1;
+  a.n_ckpt = every < 2 ? 0 : (NH - 2) / every + 1;
+  return a;
+}
 
 template <int W>
 nb_status train_w(const TrainJob& J, hipStream_t s) {
@@ -538,36 +563,44 @@ nb_status train_w(const TrainJob& J, hipStream_t s) {
   const dim3 grid((unsigned)J.plan.n_wg, (unsigned)J.members);
   const size_t lds = T::lds_bytes();
   const int64_t stride = J.plan.padded * W;
-  uint16_t* A = J.act;
+  const ActSlots S = act_slots(NH, J.every);
+  auto A = [&](int l) { return J.act + (int64_t)S.slot(l) * stride; };
   uint16_t* D[2] = {J.grad, J.grad + stride};
   const unsigned wx = (unsigned)std::max<int64_t>(
       1, std::min<int64_t>(J.plan.padded / 64, std::max<int64_t>(1, 4 * (int64_t)nb_cu_count() / J.members)));
   const dim3 wide(wx, (unsigned)J.members);
 
-  k_tr_first<W><<<wide, 256, 0, s>>>(J.q, J.n, in_dim, J.plan.padded, J.pack, J.theta, A, J.T);
-  NB_LAUNCHED();
   NB_TRY(allow_lds(k_tr_hidden<W, false>, lds));
   NB_TRY(allow_lds(k_tr_hidden<W, true>, lds));
   NB_TRY(allow_lds(k_tr_data<W>, (size_t)T::FH * 64 * 16));
-  for (int l = 1; l < NH - 1; ++l) {
-    k_tr_hidden<W, false><<<wide, 256, lds, s>>>(A + (l - 1) * stride, J.n, J.plan.padded, l, in_dim, NH, J.pack,
-                                                 J.theta, A + l * stride, nullptr, 0, 0, 0, J.tau, nullptr, nullptr,
-                                                 J.T);
+  auto hidden = [&](int l) -> nb_status {   // A_l = relu(W_l A_{l-1} + b_l)
+    k_tr_hidden<W, false><<<wide, 256, lds, s>>>(A(l - 1), J.n, J.plan.padded, l, in_dim, NH, J.pack, J.theta, A(l),
+                                                 nullptr, 0, 0, 0, J.tau, nullptr, nullptr, J.T);
     NB_LAUNCHED();
-  }
+    return NB_OK;
+  };
+  k_tr_first<W><<<wide, 256, 0, s>>>(J.q, J.n, in_dim, J.plan.padded, J.pack, J.theta, A(0), J.T);
+  NB_LAUNCHED();
+  for (int l = 1; l < NH - 1; ++l) NB_TRY(hidden(l));
   // head: layer NH-1, output layer, loss, D_{NH-1}
   int cur = 0;
-  k_tr_hidden<W, true><<<grid, 256, lds, s>>>(A + (NH - 2) * stride, J.n, CH, NH - 1, in_dim, NH, J.pack, J.theta,
-                                              D[cur], J.y, J.alpha, J.beta, J.inv_n, J.tau, J.partial, J.aux, J.T);
+  k_tr_hidden<W, true><<<grid, 256, lds, s>>>(A(NH - 2), J.n, CH, NH - 1, in_dim, NH, J.pack, J.theta, D[cur], J.y,
+                                              J.alpha, J.beta, J.inv_n, J.tau, J.partial, J.aux, J.T);
   NB_LAUNCHED();
   constexpr int WW = W >= 256 ? 8 : 4;
   const size_t wlds = (size_t)4 * W * kTS * 2 + (size_t)(WW * 64 / (W / 2)) * W * 4;
   NB_TRY(allow_lds(k_tr_weight<W, WW>, wlds));
+  int valid_seg = S.segment(NH - 2);   // the segment whose activations the scratch slots hold
   for (int l = NH - 1; l >= 1; --l) {
-    k_tr_weight<W, WW><<<grid, WW * 64, wlds, s>>>(D[cur], A + (l - 1) * stride, CH, l, in_dim, NH, J.partial, J.T);
+    if (S.segment(l - 1) != valid_seg) {
+      valid_seg = S.segment(l - 1);
+      const int c = valid_seg * S.every;
+      for (int r = c + 1; r <= std::min(c + S.every - 1, NH - 2); ++r) NB_TRY(hidden(r));
+    }
+    k_tr_weight<W, WW><<<grid, WW * 64, wlds, s>>>(D[cur], A(l - 1), CH, l, in_dim, NH, J.partial, J.T);
     NB_LAUNCHED();
-    k_tr_data<W><<<wide, 256, (size_t)T::FH * 64 * 16, s>>>(D[cur], A + (l - 1) * stride, J.plan.padded, l, J.packT,
-                                                           D[cur ^ 1], J.T);
+    k_tr_data<W><<<wide, 256, (size_t)T::FH * 64 * 16, s>>>(D[cur], A(l - 1), J.plan.padded, l, J.packT, D[cur ^ 1],
+                                                           J.T);
     NB_LAUNCHED();
     cur ^= 1;
   }
@@ -633,6 +666,7 @@ nb_status bf16_train_partials(const nb_bound* b, const float* q, const uint8_t* 
   J.pack = reinterpret_cast<const bf16x8*>(b->pack16);
   J.packT = reinterpret_cast<const bf16x8*>(b->pack16t);
   J.act = b->tr_act;
+  J.every = b->recompute;
   J.grad = b->tr_grad;
   J.partial = b->partial;
   J.aux = b->aux;
@@ -673,3 +707,5 @@ nb_status bf16_group_train_class(const nb_group* gr, int width, const int* d_mem
   J.T = TrObjs{d_members, gr->d_poff, gr->d_pkoff, gr->d_ptoff, per_obj, per_a, per_d, 0, alpha_obj};
   return train_dispatch(width, J, s);
 }
+
+int bf16_act_slots(int n_hidden, int every) { return act_slots(n_hidden, every).count(); }

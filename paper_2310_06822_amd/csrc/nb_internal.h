@@ -85,7 +85,9 @@ struct nb_bound {
   // bfloat16 training: transposed weight fragments, activations and gradients in HBM
   uint16_t* pack16t = nullptr;
   int64_t pack16t_elems = 0;
-  uint16_t* tr_act = nullptr;      // (n_hidden - 1) x [padded batch][width]
+  uint16_t* tr_act = nullptr;      // activation slots x [padded batch][width]
+  int recompute = 0;               // activation checkpoint interval (0: keep every activation)
+  int tr_slots = 0;                // activation slots tr_act holds
   uint16_t* tr_grad = nullptr;     // 2 x [padded batch][width]
   int64_t tr_cap = 0;              // padded batch the two above hold
 };
@@ -186,6 +188,8 @@ struct BF16TrainPlan {
 BF16TrainPlan bf16_train_plan(int64_t n, int max_wg = 256);
 bool bf16_train_supported(int in_dim, int n_hidden, int width);
 int64_t bf16_packt_elems(int n_hidden, int width);
+// Activation buffers of one training pass (n_hidden - 1 without recomputation).
+int bf16_act_slots(int n_hidden, int every);
 nb_status bf16_pack_t(const nb_bound* b, hipStream_t s);
 nb_status bf16_train_partials(const nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha,
                               float beta, float tau, const BF16TrainPlan& plan, hipStream_t s);

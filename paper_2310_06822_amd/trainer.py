@@ -43,6 +43,8 @@ class Schedule:
     patience: int = 6
     max_iters: int = 400
     val_n: int = 1 << 24
+    lr_decay: float = 1.0     # learning-rate factor per continuation iteration (1: constant)
+    lr_min: float = 1e-5
 
 
 @dataclass
@@ -91,11 +93,13 @@ def train(bound: Bound, ind: Indicator, kind: str, seed: int, sched: Schedule, v
     lam = sched.lam_max
     if val is not None:
         ok = 0
+        lr = sched.lr
         while ok < sched.patience and res.iters < sched.max_iters:
             for _ in range(sched.k):
-                nb_bound_train_step(bound.handle, ind.handle, k, seed, step, sched.batch, a, sched.beta, sched.lr,
+                nb_bound_train_step(bound.handle, ind.handle, k, seed, step, sched.batch, a, sched.beta, lr,
                                     lam, lam)
                 step += 1
+            lr = max(sched.lr_min, lr * sched.lr_decay)
             val = validation_set(ind, kind, val_seed, sched.val_n, draw=res.iters, out=val)
             fn = int(bound.counts(*val)[3].item())
             res.val_fn_history.append(fn)
@@ -172,6 +176,7 @@ def train_group(group, kind: str, seed: int, sched: Schedule, val_seed: int | No
     clean_all = 0
     if val_seed is not None and sched.max_iters > 0:
         val = None
+        lr_now = sched.lr
         a_dev = torch.from_numpy(alpha).cuda()
         lr_dev = torch.from_numpy(lr).cuda()
         while clean_all < sched.patience and res.iters < sched.max_iters:
@@ -180,11 +185,12 @@ def train_group(group, kind: str, seed: int, sched: Schedule, val_seed: int | No
                     nb_group_train_step(group.handle, group.n_obj, k, seed, step, sched.batch, 0.0, sched.beta,
                                         sched.lr, alpha_obj=a_dev, lr_obj=lr_dev)
                     step += 1
+            lr_now = max(sched.lr_min, lr_now * sched.lr_decay)
             val = group_validation_set(group, kind, val_seed, sched.val_n, draw=res.iters, out=val)
             fn = group.counts(*val)[:, 3].cpu().numpy()
             bad = fn > 0
             alpha[bad] += sched.inc
-            lr[bad] = sched.lr
+            lr[(lr > 0) | bad] = lr_now
             clean[bad] = 0
             clean[~bad] += 1
             lr[clean >= sched.patience] = 0.0

@@ -441,3 +441,40 @@ def test_train_steps_bf16_rays(c2_grid):
         assert abs(host(loss)[0] - hist[t][0]) <= 2e-3 * abs(hist[t][0]), t
     d_gpu = host(b.params()).astype(np.float64) - theta0
     assert _rel_frob(d_gpu, th - theta0) <= 5e-2
+
+
+@pytest.mark.parametrize("in_dim,width,nh", [(4, 256, 6), (6, 128, 4), (3, 256, 8), (6, 64, 5), (6, 32, 3)])
+def test_bf16_recompute_bit_identical(in_dim, width, nh):
+    """Checkpointed activation recomputation gives the same gradient bits as
+    keeping every activation, for several checkpoint intervals."""
+    n = 3001
+    q = synth.points(111, n, in_dim)
+    y = (synth.points(112, n, 1)[:, 0] > 0.1).astype(np.uint8)
+    theta = synth.init_params(113 + nh, in_dim, [width] * nh)
+    b = nb.Bound(in_dim, nh, width, nb.BF16)
+    b.set_params(theta)
+    grads = {}
+    for every in (0, 2, 3, nh):
+        nb.nb_bound_set_recompute(b.handle, every)
+        g = torch.empty(b.n_params, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        nb.nb_bound_loss_grad(b.handle, cuda(q), cuda(y), 5.0, 1.0, g, loss)
+        grads[every] = bits(host(g))
+    for every in (2, 3, nh):
+        assert np.array_equal(grads[every], grads[0]), every
+
+
+def test_bf16_recompute_training_step(c2_grid):
+    """A fused training step with recomputation matches the one without."""
+    _, _, grid = c2_grid
+    ind = nb.Indicator.voxels(cuda(grid), 128)
+    theta0 = synth.init_params(4003, 6, [128] * 4)
+    out = []
+    for every in (0, 2):
+        b = nb.Bound(6, 4, 128, nb.BF16)
+        nb.nb_bound_set_recompute(b.handle, every)
+        b.set_params(theta0)
+        for t in range(3):
+            nb.nb_bound_train_step(b.handle, ind.handle, nb.RAY, 9, t, 5000, 3.0, 1.0, 1e-3)
+        out.append(bits(host(b.params())))
+    assert np.array_equal(out[0], out[1])
