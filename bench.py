@@ -134,6 +134,8 @@ def run_workload(W, args, with_cpu: bool):
 
     ind = build_indicator(W, nb, synth)
     bound = nb.Bound(W.in_dim, W.n_hidden, W.width, prec)
+    if W.recompute:
+        nb.nb_bound_set_recompute(bound.handle, W.recompute)
     theta0 = synth.init_params(seeds["init"], W.in_dim, widths)
 
     # ---- training (Alg. 1 on the device): ramp, then the step-wise schedule
@@ -148,7 +150,8 @@ def run_workload(W, args, with_cpu: bool):
     bound.set_params(theta0)
     nb.nb_bound_train_step(bound.handle, ind.handle, kind, seeds["train"], 0, W.batch, 1.0)   # work space
     bound.set_params(theta0)
-    res = trainer.train(bound, ind, W.kind, seeds["train"], sched, val_seed=seeds["val"])
+    res = trainer.train(bound, ind, W.kind, seeds["train"], sched, val_seed=seeds["val"],
+                        log=lambda m: log(f"[{W.name}] {m}"))
     log(f"[{W.name}] train: {res.steps} steps x {W.batch} in {res.seconds:.2f} s -> {res.samples_per_s:.3e} "
         f"samples/s; alpha final {res.alpha_final:g}, schedule iterations {res.iters}, converged {res.converged}")
 
@@ -191,7 +194,8 @@ def run_workload(W, args, with_cpu: bool):
         "value": value, "ms_per_step": wall * 1e3 / args.steps, "dtype": W.precision,
         "config": {"workload": W.name, "query": W.kind, "queries_per_step": n_eval,
                    "net": f"{W.in_dim}x{W.width}^{W.n_hidden}x1 relu {W.precision}",
-                   "train_steps": res.steps, "train_batch": W.batch, "scene": W.scene},
+                   "train_steps": res.steps, "train_batch": W.batch, "scene": W.scene,
+                   "activation_checkpoint_interval": W.recompute},
         "train_samples_per_s": res.samples_per_s,
         "train": {"steps": res.steps, "batch": W.batch, "seconds": res.seconds, "alpha_final": res.alpha_final,
                   "schedule_iterations": res.iters, "validation_fn_zero": res.converged,

@@ -38,6 +38,7 @@ class Workload:
     adapt_inc: float = 50.0
     adapt_iters: int = 400
     lr_decay: float = 1.0
+    recompute: int = 0         # activation checkpoint interval of bfloat16 training (0: keep all)
     bench_also: bool = False   # measured by `bench.py --also`
 
     @property
@@ -65,7 +66,7 @@ VOXEL3D_RAY = Workload("voxel3d_ray", 2, "ray", 3, 6, 128, 4, "bf16",
 METABALL4D_POINT = Workload("metaball4d_point", 4, "point", 4, 4, 256, 6, "bf16",
                             scene={"type": "metaballs4d", "k": 24, "rlo": 0.05, "rhi": 0.2},
                             train_steps=2000, batch=1 << 20, eval_n=1 << 24, adapt_k=100, adapt_iters=150,
-                            lr_decay=0.99)
+                            lr_decay=0.99, recompute=3)
 
 WORKLOADS = {w.name: w for w in (DISC2D_POINT, VOXEL3D_POINT, VOXEL3D_RAY, METABALL4D_POINT)}
 

@@ -138,12 +138,16 @@ struct Stream256 {
   static constexpr int W = 256, RB = 16, KS = 8, FH = RB * KS, HALF = FH / 2;
   static constexpr int NB = 3, THREADS = 256, WAVES = THREADS / 64;
   static constexpr int PER = HALF * 64 / THREADS;    // 16-byte fragment slices per thread per chunk
+  static constexpr int IN_WAVE = NB * 16 * 8;        // staged input floats per wave (in_dim <= 8)
+  static constexpr size_t bias_bytes() { return ((size_t)(NH * W + W + 1) * 4 + 15) / 16 * 16; }
   static constexpr size_t lds_bytes() {
-    return (size_t)(RB * 64 + 2 * HALF * 64) * 16 + (size_t)(NH * W + W + 1) * 4;
+    return (size_t)(RB * 64 + 2 * HALF * 64) * 16 + bias_bytes() + (size_t)WAVES * IN_WAVE * 4;
   }
 };
 
-template <int NH>
+// SPLIT: row blocks (of four) whose products precede the next K step's
+// fragment loads (a tuning variant; every SPLIT gives identical results).
+template <int NH, int SPLIT>
 __global__ __launch_bounds__(256, 1) void k_fwd_bf16_stream(const float* __restrict__ q, int64_t n, int in_dim,
                                                           const bf16x8* __restrict__ pack,
                                                           const float* __restrict__ theta, float tau,
@@ -157,6 +161,21 @@ __global__ __launch_bounds__(256, 1) void k_fwd_bf16_stream(const float* __restr
   bf16x8* sbuf = sfirst + RB * 64;                                        // [2][HALF * 64]
   float* sbias = reinterpret_cast<float*>(sbuf + 2 * S::HALF * 64);
   const float* swo = sbias + NH * W;
+  // each wave's next-tile inputs, copied straight into LDS during the last
+  // layer of the current tile (no registers held across the layers)
+  float* sin = reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(sbias) + S::bias_bytes()) +
+               (threadIdx.x >> 6) * S::IN_WAVE;
+  auto stage_inputs = [&](int64_t q0s) {
+    const int64_t first = q0s * in_dim;
+    const int64_t end = (q0s + NB * 16 < n ? q0s + NB * 16 : n) * in_dim;   // floats of valid queries
+#pragma unroll
+    for (int i = 0; i < S::IN_WAVE / 64; ++i) {
+      const int64_t e = first + i * 64 + (threadIdx.x & 63);
+      if (i * 64 < NB * 16 * in_dim && e < end)
+        __builtin_amdgcn_global_load_lds((const void*)(q + e), (__attribute__((address_space(3))) void*)(sin + i * 64),
+                                         4, 0, 0);
+    }
+  };
 
   for (int i = threadIdx.x; i < RB * 64; i += S::THREADS) sfirst[i] = pack[i];
   for (int i = threadIdx.x; i < NH * W; i += S::THREADS) sbias[i] = theta[nb_b_off(i / W, in_dim, W, NH) + i % W];
@@ -188,6 +207,8 @@ __global__ __launch_bounds__(256, 1) void k_fwd_bf16_stream(const float* __restr
 #pragma unroll
     for (int i = 0; i < S::PER; ++i) sbuf[threadIdx.x + i * S::THREADS] = src[threadIdx.x + i * S::THREADS];
   }
+  stage_inputs(((int64_t)blockIdx.x * S::WAVES + (threadIdx.x >> 6)) * NB * 16);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
 
   const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4, wave = threadIdx.x >> 6;
@@ -199,7 +220,16 @@ __global__ __launch_bounds__(256, 1) void k_fwd_bf16_stream(const float* __restr
     floatx4 acc[NB][RB];
     {
       bf16x8 xb[NB];
-      load_inputs<NB>(q, n, in_dim, q0, c, grp, xb);
+      {
+        float xr[NB][8];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const bool valid = q0 + nb * 16 + c < n;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) xr[nb][j] = (valid && j < in_dim) ? sin[(nb * 16 + c) * in_dim + j] : 0.0f;
+        }
+        split_inputs<NB>(xr, grp, xb);
+      }
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo) {
         const float* b = sbias + 16 * mo + 4 * grp;
@@ -224,6 +254,8 @@ __global__ __launch_bounds__(256, 1) void k_fwd_bf16_stream(const float* __restr
         const bf16x8* buf = sbuf + (k & 1) * S::HALF * 64;
         const bool more = k + 1 < total_chunks;
         if (more) prefetch(k + 1, sbuf + ((k + 1) & 1) * S::HALF * 64);
+        if (l == NH - 1 && h == 0 && tile + gridDim.x < tiles)
+          stage_inputs(((tile + gridDim.x) * S::WAVES + wave) * NB * 16);
         // four row blocks at a time: 4 x NB independent accumulation chains per K step
 #pragma unroll
         for (int m4 = 0; m4 < RB / 2; m4 += 4) {
@@ -235,18 +267,37 @@ __global__ __launch_bounds__(256, 1) void k_fwd_bf16_stream(const float* __restr
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = bi;
           }
+          // two fragment slots: K step ks + 1's fragments load while ks computes
+          bf16x8 fa[4], fb[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) fa[u] = buf[((m4 + u) * KS + 0) * 64 + lane];
 #pragma unroll
           for (int ks = 0; ks < KS; ++ks) {
-            bf16x8 a[4];
+            bf16x8(&cur)[4] = (ks & 1) ? fb : fa;
+            bf16x8(&nxt)[4] = (ks & 1) ? fa : fb;
+            // SPLIT of the four row blocks' products, then the next step's
+            // loads, then the rest: the loads land behind the remaining products
 #pragma unroll
-            for (int u = 0; u < 4; ++u) a[u] = buf[((m4 + u) * KS + ks) * 64 + lane];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < SPLIT; ++u)
 #pragma unroll
               for (int nb = 0; nb < NB; ++nb) {
                 const int mo = h * (RB / 2) + m4 + u;
-                acc[nb][mo] = mfma32(a[u], act[nb][ks], acc[nb][mo]);
+                acc[nb][mo] = mfma32(cur[u], act[nb][ks], acc[nb][mo]);
               }
+            __builtin_amdgcn_sched_barrier(0);
+            if (ks + 1 < KS) {
+#pragma unroll
+              for (int u = 0; u < 4; ++u) nxt[u] = buf[((m4 + u) * KS + ks + 1) * 64 + lane];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = SPLIT; u < 4; ++u)
+#pragma unroll
+              for (int nb = 0; nb < NB; ++nb) {
+                const int mo = h * (RB / 2) + m4 + u;
+                acc[nb][mo] = mfma32(cur[u], act[nb][ks], acc[nb][mo]);
+              }
+            __builtin_amdgcn_sched_barrier(0);
           }
         }
         if (h == 1 && l < NH - 1) {
@@ -294,7 +345,7 @@ __global__ __launch_bounds__(256, 1) void k_fwd_bf16_stream(const float* __restr
   }
 }
 
-template <int NH>
+template <int NH, int SPLIT>
 nb_status stream_launch(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
                         const uint8_t* g, unsigned long long* counts, hipStream_t s) {
   using S = Stream256<NH>;
@@ -303,35 +354,45 @@ nb_status stream_launch(const nb_bound* b, const float* q, int64_t n, float tau,
   int dev = 0;
   NB_HIP(hipGetDevice(&dev));
   if (dev >= 0 && dev < 64 && !attr_set[dev]) {
-    NB_HIP(hipFuncSetAttribute((const void*)k_fwd_bf16_stream<NH>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    NB_HIP(hipFuncSetAttribute((const void*)k_fwd_bf16_stream<NH, SPLIT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     attr_set[dev] = true;
   }
   const int64_t tiles = (n + S::WAVES * S::NB * 16 - 1) / (S::WAVES * S::NB * 16);
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, nb_cu_count()));
-  k_fwd_bf16_stream<NH><<<grid, S::THREADS, lds, s>>>(q, n, b->in_dim, reinterpret_cast<const bf16x8*>(b->pack16),
+  k_fwd_bf16_stream<NH, SPLIT><<<grid, S::THREADS, lds, s>>>(q, n, b->in_dim, reinterpret_cast<const bf16x8*>(b->pack16),
                                                       b->theta, tau, logits, h, g, counts);
   NB_LAUNCHED();
   return NB_OK;
 }
 
 int bf16_variants() { return 6; }
-int bf16_variants_for(int width) { return width == 256 ? 1 : 6; }
+int bf16_variants_for(int width) { return width == 256 ? 3 : 6; }
 
 // Variant v: (query blocks per wave, threads per workgroup) =
 //   0: (2, 768)   1: (2, 512)   2: (3, 512)   3: (1, 1024)   4: (4, 256)   5: (2, 256)
 // Variant 0 (three waves per SIMD) measured fastest for widths 32..128.
+template <int NH>
+nb_status stream_nh(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
+                    const uint8_t* g, unsigned long long* counts, hipStream_t s) {
+  switch (b->variant) {
+    case 1: return stream_launch<NH, 1>(b, q, n, tau, logits, h, g, counts, s);
+    case 2: return stream_launch<NH, 3>(b, q, n, tau, logits, h, g, counts, s);
+    default: return stream_launch<NH, 2>(b, q, n, tau, logits, h, g, counts, s);
+  }
+}
+
 nb_status bf16_forward(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
                        const uint8_t* g, unsigned long long* counts, hipStream_t s) {
   if (b->width == 256) {
     switch (b->n_hidden) {
-      case 2: return stream_launch<2>(b, q, n, tau, logits, h, g, counts, s);
-      case 3: return stream_launch<3>(b, q, n, tau, logits, h, g, counts, s);
-      case 4: return stream_launch<4>(b, q, n, tau, logits, h, g, counts, s);
-      case 5: return stream_launch<5>(b, q, n, tau, logits, h, g, counts, s);
-      case 6: return stream_launch<6>(b, q, n, tau, logits, h, g, counts, s);
-      case 7: return stream_launch<7>(b, q, n, tau, logits, h, g, counts, s);
-      case 8: return stream_launch<8>(b, q, n, tau, logits, h, g, counts, s);
+      case 2: return stream_nh<2>(b, q, n, tau, logits, h, g, counts, s);
+      case 3: return stream_nh<3>(b, q, n, tau, logits, h, g, counts, s);
+      case 4: return stream_nh<4>(b, q, n, tau, logits, h, g, counts, s);
+      case 5: return stream_nh<5>(b, q, n, tau, logits, h, g, counts, s);
+      case 6: return stream_nh<6>(b, q, n, tau, logits, h, g, counts, s);
+      case 7: return stream_nh<7>(b, q, n, tau, logits, h, g, counts, s);
+      case 8: return stream_nh<8>(b, q, n, tau, logits, h, g, counts, s);
       default: break;
     }
   }

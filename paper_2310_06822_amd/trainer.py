@@ -89,6 +89,9 @@ def train(bound: Bound, ind: Indicator, kind: str, seed: int, sched: Schedule, v
         lam = sched.lam_max * frac
         nb_bound_train_step(bound.handle, ind.handle, k, seed, step, sched.batch, a, sched.beta, sched.lr, lam, lam)
         step += 1
+        if log and (t + 1) % 1000 == 0:
+            torch.cuda.synchronize()
+            log(f"ramp step {t + 1}/{T}: alpha {a:g}")
     a = sched.alpha_max
     lam = sched.lam_max
     if val is not None:
@@ -170,6 +173,9 @@ def train_group(group, kind: str, seed: int, sched: Schedule, val_seed: int | No
         a = 1.0 + (sched.alpha_max - 1.0) * (t / (T - 1) if T > 1 else 1.0)
         nb_group_train_step(group.handle, group.n_obj, k, seed, step, sched.batch, a, sched.beta, sched.lr)
         step += 1
+        if log and (t + 1) % 1000 == 0:
+            torch.cuda.synchronize()
+            log(f"group ramp step {t + 1}/{T}: alpha {a:g}")
     alpha = np.full(group.n_obj, sched.alpha_max, dtype=np.float32)
     lr = np.full(group.n_obj, sched.lr, dtype=np.float32)
     clean = np.zeros(group.n_obj, dtype=np.int64)

@@ -478,3 +478,20 @@ def test_bf16_recompute_training_step(c2_grid):
             nb.nb_bound_train_step(b.handle, ind.handle, nb.RAY, 9, t, 5000, 3.0, 1.0, 1e-3)
         out.append(bits(host(b.params())))
     assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("in_dim,width,nh", [(6, 128, 4), (4, 256, 6), (3, 64, 3), (6, 32, 2)])
+def test_forward_bf16_variants_identical(in_dim, width, nh):
+    """Every tile-shape variant of the bfloat16 forward gives the same bits."""
+    theta = synth.init_params(120 + nh, in_dim, [width] * nh)
+    q = cuda(synth.points(121, 5003, in_dim))
+    b = nb.Bound(in_dim, nh, width, nb.BF16)
+    b.set_params(theta)
+    ref = None
+    for v in range(nb.nb_bound_num_variants(b.handle)):
+        nb.nb_bound_set_variant(b.handle, v)
+        z, _ = b.forward(q)
+        zb = bits(host(z))
+        if ref is None:
+            ref = zb
+        assert np.array_equal(zb, ref), v
