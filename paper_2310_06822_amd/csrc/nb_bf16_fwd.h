@@ -104,24 +104,38 @@ __device__ __forceinline__ void bf16_fwd_tile_x(const bf16x8* __restrict__ swt, 
 #pragma unroll
           for (int j = 0; j < 8; ++j) act[nb][ks][j] = (__bf16)fmaxf(acc[nb][2 * ks + j / 4][j % 4], 0.0f);
       const bf16x8* fr = swt + (RB + (l - 1) * N::FH) * 64 + lane;
-      // two fragment slots: row block mo computes while mo + 1's fragments load
+      // row block mo's bias quad (16-byte aligned: sbias is, W is a multiple of 4)
+      const floatx4* sb4 = reinterpret_cast<const floatx4*>(sbias + l * W) + grp;
+      // two slots of fragments and bias: row block mo + 1's load while mo
+      // computes, issued after mo's first K step so that the remaining K
+      // steps' products cover their latency (all of them when KS = 1)
+      constexpr int SPLITK = KS > 1 ? 1 : 0;
       bf16x8 fa[KS], fb[KS];
+      floatx4 ba, bb;
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) fa[ks] = fr[ks * 64];
+      ba = sb4[0];
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo) {
         bf16x8(&cur)[KS] = (mo & 1) ? fb : fa;
         bf16x8(&nxt)[KS] = (mo & 1) ? fa : fb;
+        floatx4& bcur = (mo & 1) ? bb : ba;
+        floatx4& bnxt = (mo & 1) ? ba : bb;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = bcur;
+#pragma unroll
+        for (int ks = 0; ks < SPLITK; ++ks)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = mfma32(cur[ks], act[nb][ks], acc[nb][mo]);
+        __builtin_amdgcn_sched_barrier(0);
         if (mo + 1 < RB) {
 #pragma unroll
           for (int ks = 0; ks < KS; ++ks) nxt[ks] = fr[((mo + 1) * KS + ks) * 64];
+          bnxt = sb4[4 * (mo + 1)];
         }
-        const float* b = sbias + l * W + 16 * mo + 4 * grp;
-        const floatx4 bi = floatx4{b[0], b[1], b[2], b[3]};
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = bi;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
+        for (int ks = SPLITK; ks < KS; ++ks)
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = mfma32(cur[ks], act[nb][ks], acc[nb][mo]);
         __builtin_amdgcn_sched_barrier(0);
