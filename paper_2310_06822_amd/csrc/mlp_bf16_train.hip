@@ -151,10 +151,22 @@ struct TrHidden {
   static constexpr size_t lds_bytes() { return (size_t)FH * 64 * 16 + (size_t)(2 * W + 1) * 4; }
 };
 
+// Threads per workgroup of the hidden-layer and data-gradient kernels.  A
+// width-256 layer's fragments fill 128 KB of LDS, one workgroup per CU: it
+// takes 16 waves (8 for the head, whose per-lane output-layer sums need more
+// registers) so that each SIMD has several waves to hide memory latency.
+template <int W, bool HEAD>
+constexpr int tr_threads() { return W >= 256 ? (HEAD ? 512 : 1024) : 256; }
+// Row blocks unrolled per step of the output-neuron loop: all of them up to
+// width 64; two from width 128 on, where full unrolling hoists more fragment
+// loads than the registers of several waves per SIMD hold.
+template <int W>
+constexpr int kMoUnroll() { return W >= 128 ? 2 : W / 16; }
+
 // A_l = relu(W_l A_{l-1} + b_l) (HEAD = false), or for the last hidden layer
 // (HEAD = true) the output logit, Eq. 1 and its gradient.
 template <int W, bool HEAD>
-__global__ __launch_bounds__(256) void k_tr_hidden(const uint16_t* __restrict__ Ain, int64_t n, int64_t CH, int l,
+__global__ __launch_bounds__((tr_threads<W, HEAD>())) void k_tr_hidden(const uint16_t* __restrict__ Ain, int64_t n, int64_t CH, int l,
                                                    int in_dim, int NH, const bf16x8* __restrict__ pack,
                                                    const float* __restrict__ theta, uint16_t* __restrict__ Aout,
                                                    const uint8_t* __restrict__ y, float alpha, float beta, float inv_n,
@@ -203,21 +215,27 @@ __global__ __launch_bounds__(256) void k_tr_hidden(const uint16_t* __restrict__ 
     bf16x8 bop[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) bop[ks] = gather_fwd_operand(row, ks, grp);
-    floatx4 acc[RB];
-#pragma unroll
-    for (int mo = 0; mo < RB; ++mo) {
-      const float* b = sb + 16 * mo + 4 * grp;
-      acc[mo] = floatx4{b[0], b[1], b[2], b[3]};
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) acc[mo] = nb_mfma_bf16(sw[(mo * KS + ks) * 64 + lane], bop[ks], acc[mo]);
-    }
     if (!HEAD) {
+      // each row block is stored as soon as it is done (short live ranges)
       uint16_t* out = Aout + qi * W;
+#pragma unroll(kMoUnroll<W>())
+      for (int mo = 0; mo < RB; ++mo) {
+        const float* b = sb + 16 * mo + 4 * grp;
+        floatx4 a = floatx4{b[0], b[1], b[2], b[3]};
 #pragma unroll
-      for (int mo = 0; mo < RB; ++mo)
-        *reinterpret_cast<uint2*>(out + 16 * mo + 4 * grp) = pack4(fmaxf(acc[mo][0], 0.0f), fmaxf(acc[mo][1], 0.0f),
-                                                                  fmaxf(acc[mo][2], 0.0f), fmaxf(acc[mo][3], 0.0f));
+        for (int ks = 0; ks < KS; ++ks) a = nb_mfma_bf16(sw[(mo * KS + ks) * 64 + lane], bop[ks], a);
+        *reinterpret_cast<uint2*>(out + 16 * mo + 4 * grp) =
+            pack4(fmaxf(a[0], 0.0f), fmaxf(a[1], 0.0f), fmaxf(a[2], 0.0f), fmaxf(a[3], 0.0f));
+      }
     } else {
+      floatx4 acc[RB];
+#pragma unroll(kMoUnroll<W>())
+      for (int mo = 0; mo < RB; ++mo) {
+        const float* b = sb + 16 * mo + 4 * grp;
+        acc[mo] = floatx4{b[0], b[1], b[2], b[3]};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) acc[mo] = nb_mfma_bf16(sw[(mo * KS + ks) * 64 + lane], bop[ks], acc[mo]);
+      }
       const float* wo = sb + W;
       float p = 0.0f;
 #pragma unroll
@@ -311,7 +329,7 @@ __global__ __launch_bounds__(256) void k_tr_hidden(const uint16_t* __restrict__ 
 
 // D_{l-1} = (W_l^T D_l) * [A_{l-1} > 0]
 template <int W>
-__global__ __launch_bounds__(256) void k_tr_data(const uint16_t* __restrict__ Dl, const uint16_t* __restrict__ Aprev,
+__global__ __launch_bounds__((tr_threads<W, false>())) void k_tr_data(const uint16_t* __restrict__ Dl, const uint16_t* __restrict__ Aprev,
                                                  int64_t Bp, int l, const bf16x8* __restrict__ packT,
                                                  uint16_t* __restrict__ Dprev, TrObjs TO) {
   using T = TrHidden<W>;
@@ -335,7 +353,7 @@ __global__ __launch_bounds__(256) void k_tr_data(const uint16_t* __restrict__ Dl
     for (int ks = 0; ks < KS; ++ks) bop[ks] = *reinterpret_cast<const bf16x8*>(Dl + qi * W + 32 * ks + 8 * grp);
     const uint16_t* arow = Aprev + qi * W;
     uint16_t* out = Dprev + qi * W;
-#pragma unroll
+#pragma unroll(kMoUnroll<W>())
     for (int mo = 0; mo < RB; ++mo) {
       floatx4 acc = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -574,7 +592,7 @@ nb_status train_w(const TrainJob& J, hipStream_t s) {
   NB_TRY(allow_lds(k_tr_hidden<W, true>, lds));
   NB_TRY(allow_lds(k_tr_data<W>, (size_t)T::FH * 64 * 16));
   auto hidden = [&](int l) -> nb_status {   // A_l = relu(W_l A_{l-1} + b_l)
-    k_tr_hidden<W, false><<<wide, 256, lds, s>>>(A(l - 1), J.n, J.plan.padded, l, in_dim, NH, J.pack, J.theta, A(l),
+    k_tr_hidden<W, false><<<wide, tr_threads<W, false>(), lds, s>>>(A(l - 1), J.n, J.plan.padded, l, in_dim, NH, J.pack, J.theta, A(l),
                                                  nullptr, 0, 0, 0, J.tau, nullptr, nullptr, J.T);
     NB_LAUNCHED();
     return NB_OK;
@@ -584,7 +602,7 @@ nb_status train_w(const TrainJob& J, hipStream_t s) {
   for (int l = 1; l < NH - 1; ++l) NB_TRY(hidden(l));
   // head: layer NH-1, output layer, loss, D_{NH-1}
   int cur = 0;
-  k_tr_hidden<W, true><<<grid, 256, lds, s>>>(A(NH - 2), J.n, CH, NH - 1, in_dim, NH, J.pack, J.theta, D[cur], J.y,
+  k_tr_hidden<W, true><<<grid, tr_threads<W, true>(), lds, s>>>(A(NH - 2), J.n, CH, NH - 1, in_dim, NH, J.pack, J.theta, D[cur], J.y,
                                               J.alpha, J.beta, J.inv_n, J.tau, J.partial, J.aux, J.T);
   NB_LAUNCHED();
   constexpr int WW = W >= 256 ? 8 : 4;
@@ -599,7 +617,7 @@ nb_status train_w(const TrainJob& J, hipStream_t s) {
     }
     k_tr_weight<W, WW><<<grid, WW * 64, wlds, s>>>(D[cur], A(l - 1), CH, l, in_dim, NH, J.partial, J.T);
     NB_LAUNCHED();
-    k_tr_data<W><<<wide, 256, (size_t)T::FH * 64 * 16, s>>>(D[cur], A(l - 1), J.plan.padded, l, J.packT, D[cur ^ 1],
+    k_tr_data<W><<<wide, tr_threads<W, false>(), (size_t)T::FH * 64 * 16, s>>>(D[cur], A(l - 1), J.plan.padded, l, J.packT, D[cur ^ 1],
                                                            J.T);
     NB_LAUNCHED();
     cur ^= 1;
