@@ -118,6 +118,40 @@ def timed(fn, steps, warmup, torch):
     return float(np.mean([a.elapsed_time(b) for a, b in ev])), wall
 
 
+def run_early_out(W, args, nb, synth, trainer, ind, bound, q, g, kind, prec, bound_ms, torch):
+    """Neural early-out: a small bound trained on the same stream with the same
+    schedule answers first; only its positives reach the workload's bound."""
+    ew, enh = W.early
+    small = nb.Bound(W.in_dim, enh, ew, prec)
+    theta0 = synth.init_params(W.seeds["init"] + 100, W.in_dim, [ew] * enh)
+    over = {"steps": args.train_steps} if args.train_steps is not None else {}
+    if args.no_adapt:
+        over["max_iters"] = 0
+    sched = W.schedule(**over)
+    small.set_params(theta0)
+    nb.nb_bound_train_step(small.handle, ind.handle, kind, W.seeds["train"], 0, W.batch, 1.0)
+    small.set_params(theta0)
+    res = trainer.train(small, ind, W.kind, W.seeds["train"], sched, val_seed=W.seeds["val"],
+                        log=lambda m: log(f"[{W.name} early] {m}"))
+    n = q.shape[0]
+    h = torch.empty(n, dtype=torch.uint8, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    eo_ms, wall = timed(lambda: nb.nb_early_out(small.handle, bound.handle, q, h, cnt), args.steps, args.warmup, torch)
+    small_counts = small.counts(q, g).tolist()
+    tp = int(((h == 1) & (g == 1)).sum().item())
+    fp = int(((h == 1) & (g == 0)).sum().item())
+    fn = int(((h == 0) & (g == 1)).sum().item())
+    second = int(cnt.item())
+    log(f"[{W.name}] early-out: {eo_ms:.3f} ms vs {bound_ms:.3f} ms, second bound on {second / n:.3f} of the queries, "
+        f"FN {fn} FP {fp}")
+    return {"net": f"{W.in_dim}x{ew}^{enh}x1 then {W.in_dim}x{W.width}^{W.n_hidden}x1",
+            "queries_per_s": n * args.steps / wall, "avg_ms": round(eo_ms, 4),
+            "speedup_vs_bound": bound_ms / eo_ms, "second_bound_fraction": second / n,
+            "early_train": {"steps": res.steps, "seconds": res.seconds, "validation_fn_zero": res.converged},
+            "early_bound_heldout": dict(zip(["tp", "fp", "tn", "fn"], small_counts)),
+            "heldout": {"n": n, "tp": tp, "fp": fp, "fn": fn, "fp_rate": fp / n}, "fn_zero": fn == 0}
+
+
 def run_workload(W, args, with_cpu: bool):
     import torch
 
@@ -180,6 +214,8 @@ def run_workload(W, args, with_cpu: bool):
                        args.warmup, torch)
     casc_ok = bool(torch.equal(ans, g))
 
+    early = run_early_out(W, args, nb, synth, trainer, ind, bound, q, g, kind, prec, kern_ms, torch) if W.early else None
+
     macs = W.in_dim * W.width + (W.n_hidden - 1) * W.width * W.width + W.width
     flop_per_q = 2 * macs
     peak = PEAK_TFLOPS[W.precision]
@@ -209,6 +245,8 @@ def run_workload(W, args, with_cpu: bool):
         "fn_zero": fn == 0,
         "roofline": roofline,
     }
+    if early:
+        out["early_out"] = early
     if with_cpu:
         out["cpu_baseline"] = cpu_baseline(W, bound.params().cpu().numpy())
     return out

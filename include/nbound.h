@@ -233,6 +233,21 @@ nb_status nb_bound_train_step(nb_bound* b, const nb_indicator* ind, int kind, ui
 nb_status nb_cascade(nb_bound* b, const nb_indicator* ind, int kind, const float* q, int64_t n, float eps,
                      uint8_t* answer, uint64_t* n_exact, void* stream);
 
+/* Neural early-out (Sec. 3, "Neural Early-out"): the early exit is a small
+ * network on the region that is trained inverse-conservatively against the
+ * complement 1 - g, i.e. it may only declare a region empty where g = 0.
+ * Written as a bound, that is a small conservative bound `first` (trained
+ * with the usual FN-weighted loss; its negative decisions are the exits).
+ * Every query is decided by `first`; the ones it reports positive are
+ * gathered, decided by the larger `second`, and scattered back, so
+ * h = h_first AND h_second (uint8[n], overwritten), conservative whenever
+ * both are.  n_second (device uint64[1]) receives the number of queries
+ * `second` evaluated.  Both bounds take the same input size; the work space
+ * lives on `second` (the first call with a larger n synchronises `stream`).
+ * n <= 2^31 - 1. */
+nb_status nb_early_out(const nb_bound* first, nb_bound* second, const float* q, int64_t n, float eps, uint8_t* h,
+                       uint64_t* n_second, void* stream);
+
 /* ------------------------------------------------------------------------
  * Groups of per-object bounds.  The paper fits one bound per object and does
  * not generalise across objects (Sec. 3.4, "Training"); a group holds n_obj

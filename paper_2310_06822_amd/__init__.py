@@ -254,6 +254,13 @@ def nb_cascade(b, ind, kind: int, q: torch.Tensor, answer: torch.Tensor, n_exact
                             _stream(stream)))
 
 
+def nb_early_out(first, second, q: torch.Tensor, h: torch.Tensor, n_second: torch.Tensor, eps: float = EPS_OUT,
+                 stream=None):
+    n = _rows(q, nb_bound_shape(first)[0])
+    _check(lib().nb_early_out(first, second, _dev(q, torch.float32, "q"), n, float(eps), _dev(h, torch.uint8, "h", n),
+                              _dev(n_second, torch.int64, "n_second", 1), _stream(stream)))
+
+
 # ------------------------------------------------------------------ groups
 
 def nb_group_create(in_dim: int, widths, n_hidden: int, precision: int = BF16) -> C.c_void_p:

@@ -357,6 +357,8 @@ nb_status nb_bound_destroy(nb_bound* b) {
   dev_free(b->batch_q);
   dev_free(b->batch_y);
   dev_free(b->cascade_idx);
+  dev_free(b->early_q);
+  dev_free(b->early_h);
   delete b;
   return NB_OK;
 }
@@ -531,6 +533,47 @@ nb_status nb_bound_train_step(nb_bound* b, const nb_indicator* ind, int kind, ui
   NB_TRY(launch_reduce(b, n_wg, nullptr, loss, (float)(1.0 / (double)batch),
                        reinterpret_cast<unsigned long long*>(counts), a, s));
   return repack(b, s);
+}
+
+namespace {
+nb_status bound_forward(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
+                        const uint8_t* g, unsigned long long* counts, hipStream_t s,
+                        const unsigned long long* n_dev = nullptr) {
+  if (b->precision == NB_BF16) return bf16_forward(b, q, n, tau, logits, h, g, counts, s, n_dev);
+  return f32_forward(b, q, n, tau, logits, h, g, counts, s, n_dev);
+}
+}  // namespace
+
+nb_status nb_early_out(const nb_bound* first, nb_bound* second, const float* q, int64_t n, float eps, uint8_t* h,
+                       uint64_t* n_second, void* stream) {
+  NB_REQUIRE(first && second && q && h && n_second, "NULL argument");
+  NB_REQUIRE(first != second, "the two bounds must differ");
+  NB_REQUIRE(first->in_dim == second->in_dim, "the bounds take %d and %d inputs", first->in_dim, second->in_dim);
+  NB_REQUIRE(n > 0 && n <= (int64_t)0x7FFFFFFF, "n must be in 1..2^31-1");
+  NB_REQUIRE(eps >= 0.0f && eps < 0.5f, "eps must be in [0, 0.5)");
+  hipStream_t s = as_stream(stream);
+  if (second->cascade_cap < n || second->early_cap < n) {
+    // grows the work space (synchronising)
+    NB_HIP(hipStreamSynchronize(s));
+    dev_free(second->cascade_idx);
+    dev_free(second->early_q);
+    dev_free(second->early_h);
+    second->cascade_cap = 0;
+    second->early_cap = 0;
+    NB_TRY(dev_alloc(&second->cascade_idx, (size_t)n));
+    NB_TRY(dev_alloc(&second->early_q, (size_t)n * second->in_dim));
+    NB_TRY(dev_alloc(&second->early_h, (size_t)n));
+    second->cascade_cap = n;
+    second->early_cap = n;
+  }
+  auto* cnt = reinterpret_cast<unsigned long long*>(n_second);
+  const float tau = tau_of(eps);
+  NB_TRY(launch_zero_u64(cnt, 1, s));
+  NB_TRY(bound_forward(first, q, n, tau, nullptr, h, nullptr, nullptr, s));
+  NB_TRY(launch_compact_positive(h, n, second->cascade_idx, cnt, s));
+  NB_TRY(launch_gather_rows(q, second->in_dim, second->cascade_idx, cnt, n, second->early_q, s));
+  NB_TRY(bound_forward(second, second->early_q, n, tau, nullptr, second->early_h, nullptr, nullptr, s, cnt));
+  return launch_scatter_u8(second->early_h, second->cascade_idx, cnt, n, h, s);
 }
 
 nb_status nb_cascade(nb_bound* b, const nb_indicator* ind, int kind, const float* q, int64_t n, float eps,

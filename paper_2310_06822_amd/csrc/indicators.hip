@@ -239,6 +239,12 @@ nb_status launch_query_exact(const nb_indicator* ind, int kind, const float* q, 
   return NB_OK;
 }
 
+nb_status launch_compact_positive(const uint8_t* h, int64_t n, int32_t* idx, unsigned long long* count, hipStream_t s) {
+  k_compact_positive<<<(unsigned)((n + 256 * kCompactPer - 1) / (256 * kCompactPer)), 256, 0, s>>>(h, n, idx, count);
+  NB_LAUNCHED();
+  return NB_OK;
+}
+
 nb_status launch_cascade_exact(const nb_indicator* ind, int kind, const float* q, const uint8_t* h, int64_t n,
                                int32_t* idx, unsigned long long* count, uint8_t* answer, hipStream_t s) {
   NB_REQUIRE(kind == NB_QUERY_POINT || ind->type == IND_VOXELS, "ray, box and plane queries need a voxel indicator");

@@ -44,8 +44,10 @@ template <int W, int NH, int NB, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_fwd_bf16(const float* __restrict__ q, int64_t n, int in_dim,
                                                   const bf16x8* __restrict__ pack, const float* __restrict__ theta,
                                                   float tau, float* __restrict__ logits, uint8_t* __restrict__ hout,
-                                                  const uint8_t* __restrict__ g, unsigned long long* __restrict__ counts) {
+                                                  const uint8_t* __restrict__ g, unsigned long long* __restrict__ counts,
+                                                  const unsigned long long* __restrict__ n_dev) {
   using N = B16<W, NH>;
+  if (n_dev && (int64_t)*n_dev < n) n = (int64_t)*n_dev;   // rows counted on the device
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   bf16x8* swt = reinterpret_cast<bf16x8*>(smem_raw);
   float* sbias = reinterpret_cast<float*>(smem_raw + (size_t)N::NFWD * 64 * 16);
@@ -71,7 +73,7 @@ __global__ __launch_bounds__(THREADS) void k_fwd_bf16(const float* __restrict__ 
 
 template <int W, int NH, int NB, int THREADS>
 nb_status fwd_launch(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
-                     const uint8_t* g, unsigned long long* counts, hipStream_t s) {
+                     const uint8_t* g, unsigned long long* counts, const unsigned long long* n_dev, hipStream_t s) {
   using N = B16<W, NH>;
   const size_t lds = N::lds_bytes();
   static bool attr_set[64] = {false};
@@ -87,7 +89,7 @@ nb_status fwd_launch(const nb_bound* b, const float* q, int64_t n, float tau, fl
   const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(4, (160 * 1024) / (int64_t)lds));
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, per_cu * nb_cu_count()));
   k_fwd_bf16<W, NH, NB, THREADS><<<grid, THREADS, lds, s>>>(q, n, b->in_dim, reinterpret_cast<const bf16x8*>(b->pack16),
-                                                    b->theta, tau, logits, h, g, counts);
+                                                    b->theta, tau, logits, h, g, counts, n_dev);
   NB_LAUNCHED();
   return NB_OK;
 }
@@ -153,8 +155,10 @@ __global__ __launch_bounds__(256, 1) void k_fwd_bf16_stream(const float* __restr
                                                           const float* __restrict__ theta, float tau,
                                                           float* __restrict__ logits, uint8_t* __restrict__ hout,
                                                           const uint8_t* __restrict__ g,
-                                                          unsigned long long* __restrict__ counts) {
+                                                          unsigned long long* __restrict__ counts,
+                                                          const unsigned long long* __restrict__ n_dev) {
   using S = Stream256<NH>;
+  if (n_dev && (int64_t)*n_dev < n) n = (int64_t)*n_dev;   // rows counted on the device
   constexpr int W = S::W, RB = S::RB, KS = S::KS, NB = S::NB;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   bf16x8* sfirst = reinterpret_cast<bf16x8*>(smem_raw);
@@ -347,7 +351,8 @@ __global__ __launch_bounds__(256, 1) void k_fwd_bf16_stream(const float* __restr
 
 template <int NH, int SPLIT>
 nb_status stream_launch(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
-                        const uint8_t* g, unsigned long long* counts, hipStream_t s) {
+                        const uint8_t* g, unsigned long long* counts, const unsigned long long* n_dev,
+                        hipStream_t s) {
   using S = Stream256<NH>;
   const size_t lds = S::lds_bytes();
   static bool attr_set[64] = {false};
@@ -361,7 +366,7 @@ nb_status stream_launch(const nb_bound* b, const float* q, int64_t n, float tau,
   const int64_t tiles = (n + S::WAVES * S::NB * 16 - 1) / (S::WAVES * S::NB * 16);
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, nb_cu_count()));
   k_fwd_bf16_stream<NH, SPLIT><<<grid, S::THREADS, lds, s>>>(q, n, b->in_dim, reinterpret_cast<const bf16x8*>(b->pack16),
-                                                      b->theta, tau, logits, h, g, counts);
+                                                      b->theta, tau, logits, h, g, counts, n_dev);
   NB_LAUNCHED();
   return NB_OK;
 }
@@ -374,37 +379,37 @@ int bf16_variants_for(int width) { return width == 256 ? 3 : 6; }
 // Variant 0 (three waves per SIMD) measured fastest for widths 32..128.
 template <int NH>
 nb_status stream_nh(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
-                    const uint8_t* g, unsigned long long* counts, hipStream_t s) {
+                    const uint8_t* g, unsigned long long* counts, const unsigned long long* n_dev, hipStream_t s) {
   switch (b->variant) {
-    case 1: return stream_launch<NH, 1>(b, q, n, tau, logits, h, g, counts, s);
-    case 2: return stream_launch<NH, 3>(b, q, n, tau, logits, h, g, counts, s);
-    default: return stream_launch<NH, 2>(b, q, n, tau, logits, h, g, counts, s);
+    case 1: return stream_launch<NH, 1>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+    case 2: return stream_launch<NH, 3>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+    default: return stream_launch<NH, 2>(b, q, n, tau, logits, h, g, counts, n_dev, s);
   }
 }
 
 nb_status bf16_forward(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
-                       const uint8_t* g, unsigned long long* counts, hipStream_t s) {
+                       const uint8_t* g, unsigned long long* counts, hipStream_t s, const unsigned long long* n_dev) {
   if (b->width == 256) {
     switch (b->n_hidden) {
-      case 2: return stream_nh<2>(b, q, n, tau, logits, h, g, counts, s);
-      case 3: return stream_nh<3>(b, q, n, tau, logits, h, g, counts, s);
-      case 4: return stream_nh<4>(b, q, n, tau, logits, h, g, counts, s);
-      case 5: return stream_nh<5>(b, q, n, tau, logits, h, g, counts, s);
-      case 6: return stream_nh<6>(b, q, n, tau, logits, h, g, counts, s);
-      case 7: return stream_nh<7>(b, q, n, tau, logits, h, g, counts, s);
-      case 8: return stream_nh<8>(b, q, n, tau, logits, h, g, counts, s);
+      case 2: return stream_nh<2>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+      case 3: return stream_nh<3>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+      case 4: return stream_nh<4>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+      case 5: return stream_nh<5>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+      case 6: return stream_nh<6>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+      case 7: return stream_nh<7>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+      case 8: return stream_nh<8>(b, q, n, tau, logits, h, g, counts, n_dev, s);
       default: break;
     }
   }
 #define X(WW, H)                                                                  \
   if (b->width == WW && b->n_hidden == H) {                                       \
     switch (b->variant) {                                                         \
-      case 1: return fwd_launch<WW, H, 2, 512>(b, q, n, tau, logits, h, g, counts, s);  \
-      case 2: return fwd_launch<WW, H, 3, 512>(b, q, n, tau, logits, h, g, counts, s);  \
-      case 3: return fwd_launch<WW, H, 1, 1024>(b, q, n, tau, logits, h, g, counts, s); \
-      case 4: return fwd_launch<WW, H, 4, 256>(b, q, n, tau, logits, h, g, counts, s);  \
-      case 5: return fwd_launch<WW, H, 2, 256>(b, q, n, tau, logits, h, g, counts, s);  \
-      default: return fwd_launch<WW, H, 2, 768>(b, q, n, tau, logits, h, g, counts, s); \
+      case 1: return fwd_launch<WW, H, 2, 512>(b, q, n, tau, logits, h, g, counts, n_dev, s);  \
+      case 2: return fwd_launch<WW, H, 3, 512>(b, q, n, tau, logits, h, g, counts, n_dev, s);  \
+      case 3: return fwd_launch<WW, H, 1, 1024>(b, q, n, tau, logits, h, g, counts, n_dev, s); \
+      case 4: return fwd_launch<WW, H, 4, 256>(b, q, n, tau, logits, h, g, counts, n_dev, s);  \
+      case 5: return fwd_launch<WW, H, 2, 256>(b, q, n, tau, logits, h, g, counts, n_dev, s);  \
+      default: return fwd_launch<WW, H, 2, 768>(b, q, n, tau, logits, h, g, counts, n_dev, s); \
     }                                                                             \
   }
   NB_BF16_CASES(X)

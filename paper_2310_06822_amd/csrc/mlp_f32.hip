@@ -92,8 +92,10 @@ template <int KIN, int W, int NH>
 __global__ __launch_bounds__(256) void k_fwd(const float* __restrict__ q, int64_t n, int in_dim,
                                              const float* __restrict__ pack, const float* __restrict__ theta,
                                              float tau, float* __restrict__ logits, uint8_t* __restrict__ hout,
-                                             const uint8_t* __restrict__ g, unsigned long long* __restrict__ counts) {
+                                             const uint8_t* __restrict__ g, unsigned long long* __restrict__ counts,
+                                             const unsigned long long* __restrict__ n_dev) {
   using N = Net<KIN, W, NH>;
+  if (n_dev && (int64_t)*n_dev < n) n = (int64_t)*n_dev;   // rows counted on the device
   constexpr int RB = N::RB;
   const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4;
 
@@ -477,12 +479,12 @@ constexpr int kMaxWG = 256;
 
 template <int KIN, int W, int NH>
 nb_status fwd_launch(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
-                     const uint8_t* g, unsigned long long* counts, hipStream_t s) {
+                     const uint8_t* g, unsigned long long* counts, const unsigned long long* n_dev, hipStream_t s) {
   const int64_t nblk = (n + 15) / 16;
   const int64_t want = (nblk + 3) / 4;
   const int64_t cap = (int64_t)nb_cu_count() * 2;
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min(want, cap));
-  k_fwd<KIN, W, NH><<<grid, 256, 0, s>>>(q, n, b->in_dim, b->pack, b->theta, tau, logits, h, g, counts);
+  k_fwd<KIN, W, NH><<<grid, 256, 0, s>>>(q, n, b->in_dim, b->pack, b->theta, tau, logits, h, g, counts, n_dev);
   NB_LAUNCHED();
   return NB_OK;
 }
@@ -542,10 +544,11 @@ nb_status f32_pack(const nb_bound* b, hipStream_t s) {
 }
 
 nb_status f32_forward(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
-                      const uint8_t* g, unsigned long long* counts, hipStream_t s) {
+                      const uint8_t* g, unsigned long long* counts, hipStream_t s, const unsigned long long* n_dev) {
   const int kin = kin_of(b->in_dim);
-#define X(K, WW, H) \
-  if (kin == K && b->width == WW && b->n_hidden == H) return fwd_launch<K, WW, H>(b, q, n, tau, logits, h, g, counts, s);
+#define X(K, WW, H)                                                                  \
+  if (kin == K && b->width == WW && b->n_hidden == H)                                \
+    return fwd_launch<K, WW, H>(b, q, n, tau, logits, h, g, counts, n_dev, s);
   NB_F32_CASES(X)
 #undef X
   nb_set_error("float32 bound %d x %d^%d has no kernel", b->in_dim, b->width, b->n_hidden);

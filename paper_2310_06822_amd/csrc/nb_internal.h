@@ -82,6 +82,10 @@ struct nb_bound {
   int batch_cap_dim = 0;
   int32_t* cascade_idx = nullptr;  // positive-query index list of nb_cascade
   int64_t cascade_cap = 0;
+  // early-out work space (on the second bound): gathered rows and decisions
+  float* early_q = nullptr;
+  uint8_t* early_h = nullptr;
+  int64_t early_cap = 0;
   // bfloat16 training: transposed weight fragments, activations and gradients in HBM
   uint16_t* pack16t = nullptr;
   int64_t pack16t_elems = 0;
@@ -153,6 +157,7 @@ nb_status launch_query_exact(const nb_indicator* ind, int kind, const float* q, 
 nb_status launch_voxelize(const float* params_dev, int k, float iso, int n, uint8_t* grid, hipStream_t s);
 nb_status launch_cascade_exact(const nb_indicator* ind, int kind, const float* q, const uint8_t* h, int64_t n,
                                int32_t* idx, unsigned long long* count, uint8_t* answer, hipStream_t s);
+nb_status launch_compact_positive(const uint8_t* h, int64_t n, int32_t* idx, unsigned long long* count, hipStream_t s);
 nb_status launch_collect_occupied(const uint8_t* grid, int64_t cells, int32_t* out, int64_t* count_dev,
                                   hipStream_t s);
 
@@ -160,8 +165,10 @@ nb_status launch_collect_occupied(const uint8_t* grid, int64_t cells, int32_t* o
 bool f32_supported(int in_dim, int n_hidden, int width);
 int64_t f32_pack_floats(int in_dim, int n_hidden, int width);
 nb_status f32_pack(const nb_bound* b, hipStream_t s);
+// n_dev (device, nullable): evaluate only the first min(n, *n_dev) rows.
 nb_status f32_forward(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
-                      const uint8_t* g, unsigned long long* counts, hipStream_t s);
+                      const uint8_t* g, unsigned long long* counts, hipStream_t s,
+                      const unsigned long long* n_dev = nullptr);
 // Per-workgroup partial gradients into b->partial / b->aux; returns the
 // number of workgroups used through n_wg.
 nb_status f32_train_partials(const nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha,
@@ -175,7 +182,8 @@ nb_status bf16_pack(const nb_bound* b, hipStream_t s);
 int bf16_variants();
 int bf16_variants_for(int width);
 nb_status bf16_forward(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
-                       const uint8_t* g, unsigned long long* counts, hipStream_t s);
+                       const uint8_t* g, unsigned long long* counts, hipStream_t s,
+                       const unsigned long long* n_dev = nullptr);
 
 // mlp_bf16_train.hip
 struct BF16TrainPlan {
@@ -199,6 +207,12 @@ nb_status bf16_group_train_class(const nb_group* gr, int width, const int* d_mem
                                  const float* alpha_obj, float beta,
                                  float tau, const BF16TrainPlan& plan, uint16_t* act, uint16_t* grad,
                                  hipStream_t s);
+
+// early.hip
+nb_status launch_gather_rows(const float* q, int d, const int32_t* idx, const unsigned long long* count, int64_t n_max,
+                             float* qc, hipStream_t s);
+nb_status launch_scatter_u8(const uint8_t* hc, const int32_t* idx, const unsigned long long* count, int64_t n_max,
+                            uint8_t* h, hipStream_t s);
 
 // group.hip
 int group_variants();

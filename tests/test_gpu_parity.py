@@ -495,3 +495,45 @@ def test_forward_bf16_variants_identical(in_dim, width, nh):
         if ref is None:
             ref = zb
         assert np.array_equal(zb, ref), v
+
+
+# ------------------------------------------------------------ early-out
+
+@pytest.mark.parametrize("first,second,n", [
+    ((3, 32, 1, "f32"), (3, 64, 3, "f32"), 70001),
+    ((6, 32, 2, "bf16"), (6, 128, 4, "bf16"), 4099),
+    ((4, 16, 2, "f32"), (4, 256, 6, "bf16"), 3001),
+    ((3, 32, 1, "f32"), (3, 64, 3, "f32"), 1),
+])
+def test_early_out(first, second, n):
+    """h = h_first AND h_second, the second bound evaluated only on the first's
+    positives (Sec. 3, "Neural Early-out"): equal bit for bit to the two
+    bounds' own decisions, and to the oracle's outside the |z| < 1e-4 band."""
+    nets = []
+    q = synth.points(140, n, first[0])
+    qs = synth.points(141, 2001, first[0])
+    for k, (d, w, nh, p) in enumerate((first, second)):
+        theta = synth.init_params(130 + k + w, d, [w] * nh)
+        # output bias at minus the median logit: each bound reports about half positive
+        theta[-1] -= np.median(mlp.forward(theta, d, [w] * nh, qs, bf16=(p == "bf16")))
+        b = nb.Bound(d, nh, w, nb.BF16 if p == "bf16" else nb.F32)
+        b.set_params(theta)
+        nets.append((b, theta, d, [w] * nh, p == "bf16"))
+    qd = cuda(q)
+    h = torch.full((n,), 7, dtype=torch.uint8, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    nb.nb_early_out(nets[0][0].handle, nets[1][0].handle, qd, h, cnt)
+    h = host(h)
+    z1, h1 = nets[0][0].forward(qd)
+    z2, h2 = nets[1][0].forward(qd)
+    h1, h2 = host(h1), host(h2)
+    assert np.array_equal(h, h1 & h2)
+    assert int(host(cnt)[0]) == int(h1.sum())
+    ref = []
+    for b, theta, d, widths, bf in nets:
+        ref.append(mlp.forward(theta, d, widths, q, bf16=bf))
+    sure = (np.abs(ref[0]) > 1e-4) & (np.abs(ref[1]) > 1e-4)
+    expect = L.decide(ref[0]) & L.decide(ref[1])
+    assert np.array_equal(h[sure], expect[sure])
+    if n > 1000:
+        assert 0 < h1.sum() < n and 0 < h.sum() < h1.sum()
