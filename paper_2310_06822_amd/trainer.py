@@ -45,6 +45,9 @@ class Schedule:
     val_n: int = 1 << 24
     lr_decay: float = 1.0     # learning-rate factor per continuation iteration (1: constant)
     lr_min: float = 1e-5
+    # inverted ("certainly hit") bound: the FP weight follows the schedule and
+    # the continuation counts false positives, so h = 1 implies g = 1
+    inverted: bool = False
 
 
 @dataclass
@@ -87,7 +90,8 @@ def train(bound: Bound, ind: Indicator, kind: str, seed: int, sched: Schedule, v
         frac = t / (T - 1) if T > 1 else 1.0
         a = 1.0 + (sched.alpha_max - 1.0) * frac
         lam = sched.lam_max * frac
-        nb_bound_train_step(bound.handle, ind.handle, k, seed, step, sched.batch, a, sched.beta, sched.lr, lam, lam)
+        fn_w, fp_w = (sched.beta, a) if sched.inverted else (a, sched.beta)
+        nb_bound_train_step(bound.handle, ind.handle, k, seed, step, sched.batch, fn_w, fp_w, sched.lr, lam, lam)
         step += 1
         if log and (t + 1) % 1000 == 0:
             torch.cuda.synchronize()
@@ -98,13 +102,15 @@ def train(bound: Bound, ind: Indicator, kind: str, seed: int, sched: Schedule, v
         ok = 0
         lr = sched.lr
         while ok < sched.patience and res.iters < sched.max_iters:
+            fn_w, fp_w = (sched.beta, a) if sched.inverted else (a, sched.beta)
             for _ in range(sched.k):
-                nb_bound_train_step(bound.handle, ind.handle, k, seed, step, sched.batch, a, sched.beta, lr,
+                nb_bound_train_step(bound.handle, ind.handle, k, seed, step, sched.batch, fn_w, fp_w, lr,
                                     lam, lam)
                 step += 1
             lr = max(sched.lr_min, lr * sched.lr_decay)
             val = validation_set(ind, kind, val_seed, sched.val_n, draw=res.iters, out=val)
-            fn = int(bound.counts(*val)[3].item())
+            # the error the bound must not make: FN, or FP for an inverted bound
+            fn = int(bound.counts(*val)[1 if sched.inverted else 3].item())
             res.val_fn_history.append(fn)
             res.iters += 1
             if fn == 0:

@@ -537,3 +537,23 @@ def test_early_out(first, second, n):
     assert np.array_equal(h[sure], expect[sure])
     if n > 1000:
         assert 0 < h1.sum() < n and 0 < h.sum() < h1.sum()
+
+
+def test_inverted_bound_has_no_false_positives():
+    """An inverted ("certainly hit") bound, trained with the FP weight on the
+    schedule, reaches FP = 0 on held-out points while keeping true positives."""
+    from paper_2310_06822_amd import trainer
+    discs = synth.discs2d(1000, k=8)
+    ind = nb.Indicator.discs2d(discs)
+    b = nb.Bound(2, 3, 32, nb.F32)
+    b.set_params(synth.init_params(4000, 2, [32] * 3))
+    sched = trainer.Schedule(steps=1000, batch=4096, alpha_max=100.0, k=100, inc=50.0, max_iters=200,
+                             val_n=1 << 16, lr_decay=0.98, inverted=True)
+    res = trainer.train(b, ind, "point", 2000, sched, val_seed=5000)
+    assert res.converged
+    q = torch.empty((1 << 18, 2), dtype=torch.float32, device="cuda")
+    nb.nb_sample_queries(nb.POINT, 2, 3000, 0, q)
+    g = ind.query("point", q)
+    tp, fp, tn, fn = b.counts(q, g).tolist()
+    assert fp == 0
+    assert tp > 0.5 * (tp + fn)   # it still certifies most of the inside
