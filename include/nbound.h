@@ -249,6 +249,40 @@ nb_status nb_early_out(const nb_bound* first, nb_bound* second, const float* q, 
                        uint64_t* n_second, void* stream);
 
 /* ------------------------------------------------------------------------
+ * k-DOP bounds trained with the asymmetric loss (Sec. 4.1, "Methods"; the
+ * supplemental uses k = 4 directions): the planes of k slabs in 2-4 D.
+ * Parameters (device float32[k*d + 2k + 1]): directions n_1 .. n_k (d each),
+ * lower offsets lo_1 .. lo_k, upper offsets hi_1 .. hi_k, logit scale s.
+ * A region's projection onto n_j is [u_j, v_j] (a point: n.x; a box [a, b]:
+ * n.c -+ sum_i |n_i| e_i with c = (a+b)/2, e = (b-a)/2; a ray segment
+ * o + t w, t in [0, 4]: min / max of n.o and n.(o + 4w)), and the logit is
+ * z = s min_j min(hi_j - u_j, v_j - lo_j) (z >= 0 iff the region's
+ * projection meets every slab, necessary for meeting the k-DOP).  The
+ * decision and the loss are the network's.  Query kinds: points (d = 2, 3,
+ * 4), boxes and rays (d = 3).
+ * ---------------------------------------------------------------------- */
+typedef struct nb_kdop nb_kdop;
+
+nb_status nb_kdop_create(int dim, int k, nb_kdop** out);   /* k in 1..8 */
+nb_status nb_kdop_destroy(nb_kdop* b);
+nb_status nb_kdop_num_params(const nb_kdop* b, int64_t* n_params);
+/* set resets the Adam state. */
+nb_status nb_kdop_set_params(nb_kdop* b, const float* theta, int64_t n_params, void* stream);
+nb_status nb_kdop_get_params(const nb_kdop* b, float* theta, int64_t n_params, void* stream);
+/* logits float32[n] and/or h uint8[n]; with g and counts (uint64[4],
+ * overwritten) also TP, FP, TN, FN against g. */
+nb_status nb_kdop_forward(const nb_kdop* b, int kind, const float* q, int64_t n, float eps, float* logits, uint8_t* h,
+                          const uint8_t* g, uint64_t* counts, void* stream);
+/* One step of Alg. 1 on `batch` sampled regions labelled by `ind` (same
+ * dimension): Eq. 1 with (alpha, beta), the gradient of z through the
+ * arg-min slab (the first on ties, its upper side on ties), a fixed-order
+ * reduction and one Adam step (lr, 0.9, 0.999, 1e-8).  loss: float32[1]
+ * batch mean or NULL; counts: uint64[4] or NULL. */
+nb_status nb_kdop_train_step(nb_kdop* b, const nb_indicator* ind, int kind, uint64_t seed, uint64_t step,
+                             int64_t batch, float alpha, float beta, float lr, float* loss, uint64_t* counts,
+                             void* stream);
+
+/* ------------------------------------------------------------------------
  * Groups of per-object bounds.  The paper fits one bound per object and does
  * not generalise across objects (Sec. 3.4, "Training"); a group holds n_obj
  * bfloat16 bounds with a common input size and depth (2..4 hidden layers)

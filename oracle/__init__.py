@@ -22,6 +22,7 @@ Modules (each function cites the passage of the paper it follows):
   adam        Adam (Kingma & Ba 2014), the optimiser of Sec. 3.4 "Training".
   train       Alg. 1 as a training loop with the FN-weight ramp.
   cascade     bound-then-exact cascade and the benefit inequality (Sec. 6).
+  kdop        k-DOP bounds trained with the asymmetric loss (Sec. 4.1).
 
 Parity status: every function here is pinned by a test in tests/ against a
 closed form, a brute-force enumeration, a library routine or a value printed

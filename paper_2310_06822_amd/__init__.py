@@ -261,6 +261,70 @@ def nb_early_out(first, second, q: torch.Tensor, h: torch.Tensor, n_second: torc
                               _dev(n_second, torch.int64, "n_second", 1), _stream(stream)))
 
 
+# ------------------------------------------------------------------ k-DOPs
+
+def nb_kdop_forward(b, kind: int, q: torch.Tensor, eps: float = EPS_OUT, logits=None, h=None, g=None, counts=None,
+                    stream=None):
+    n = q.shape[0]
+    _check(lib().nb_kdop_forward(b, int(kind), _dev(q, torch.float32, "q"), n, float(eps),
+                                 _dev(logits, torch.float32, "logits", n), _dev(h, torch.uint8, "h", n),
+                                 _dev(g, torch.uint8, "g", n), _dev(counts, torch.int64, "counts", 4), _stream(stream)))
+
+
+def nb_kdop_train_step(b, ind, kind: int, seed: int, step: int, batch: int, alpha: float, beta: float = 1.0,
+                       lr: float = 1e-3, loss=None, counts=None, stream=None):
+    _check(lib().nb_kdop_train_step(b, ind, int(kind), int(seed), int(step), int(batch), float(alpha), float(beta),
+                                    float(lr), _dev(loss, torch.float32, "loss", 1),
+                                    _dev(counts, torch.int64, "counts", 4), _stream(stream)))
+
+
+class KDop:
+    """Owns an nb_kdop handle: k slabs in `dim` dimensions."""
+
+    def __init__(self, dim: int, k: int = 4):
+        self.dim, self.k = dim, k
+        h = C.c_void_p()
+        _check(lib().nb_kdop_create(int(dim), int(k), C.byref(h)))
+        self.handle = h
+        n = C.c_int64()
+        _check(lib().nb_kdop_num_params(h, C.byref(n)))
+        self.n_params = n.value
+
+    def set_params(self, theta):
+        if isinstance(theta, np.ndarray):
+            theta = torch.from_numpy(np.ascontiguousarray(theta, dtype=np.float32)).cuda()
+        _check(lib().nb_kdop_set_params(self.handle, _dev(theta, torch.float32, "theta", self.n_params),
+                                        self.n_params, None))
+
+    def params(self) -> torch.Tensor:
+        t = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        _check(lib().nb_kdop_get_params(self.handle, _dev(t, torch.float32, "theta"), self.n_params, None))
+        return t
+
+    def forward(self, kind, q: torch.Tensor, eps: float = EPS_OUT):
+        n = q.shape[0]
+        z = torch.empty(n, dtype=torch.float32, device=q.device)
+        h = torch.empty(n, dtype=torch.uint8, device=q.device)
+        nb_kdop_forward(self.handle, KINDS.get(kind, kind), q, eps, logits=z, h=h)
+        return z, h
+
+    def counts(self, kind, q: torch.Tensor, g: torch.Tensor, eps: float = EPS_OUT) -> torch.Tensor:
+        c = torch.empty(4, dtype=torch.int64, device=q.device)
+        nb_kdop_forward(self.handle, KINDS.get(kind, kind), q, eps, g=g, counts=c)
+        return c
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().nb_kdop_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # ------------------------------------------------------------------ groups
 
 def nb_group_create(in_dim: int, widths, n_hidden: int, precision: int = BF16) -> C.c_void_p:

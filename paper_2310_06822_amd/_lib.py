@@ -45,6 +45,13 @@ SIGNATURES = {
     "nb_bound_train_step": (i32, [vp, vp, C.c_int, u64, u64, i64, f32, f32, f32, f32, f32, vp, vp, vp]),
     "nb_cascade": (i32, [vp, vp, C.c_int, vp, i64, f32, vp, vp, vp]),
     "nb_early_out": (i32, [vp, vp, vp, i64, f32, vp, vp, vp]),
+    "nb_kdop_create": (i32, [C.c_int, C.c_int, PP]),
+    "nb_kdop_destroy": (i32, [vp]),
+    "nb_kdop_num_params": (i32, [vp, C.POINTER(i64)]),
+    "nb_kdop_set_params": (i32, [vp, vp, i64, vp]),
+    "nb_kdop_get_params": (i32, [vp, vp, i64, vp]),
+    "nb_kdop_forward": (i32, [vp, C.c_int, vp, i64, f32, vp, vp, vp, vp, vp]),
+    "nb_kdop_train_step": (i32, [vp, vp, C.c_int, u64, u64, i64, f32, f32, f32, vp, vp, vp]),
     "nb_group_create": (i32, [C.c_int, C.c_int, vp, C.c_int, C.c_int, PP]),
     "nb_group_destroy": (i32, [vp]),
     "nb_group_num_params": (i32, [vp, C.POINTER(i64)]),

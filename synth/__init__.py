@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "rng", "discs2d", "metaballs3d", "metaballs4d", "random_grid",
     "points", "points4d", "rays", "boxes", "planes", "init_params",
-    "layer_shapes", "num_params", "seed_for", "object_set",
+    "layer_shapes", "num_params", "seed_for", "object_set", "kdop_init",
 ]
 
 # Seed bases per stream: scene / training stream / held-out eval / init.
@@ -180,3 +180,22 @@ def init_params(seed: int, in_dim: int, widths) -> np.ndarray:
         parts.append(g.uniform(-bound, bound, size=(o * i,)))
         parts.append(g.uniform(-bound, bound, size=(o,)))
     return np.ascontiguousarray(np.concatenate(parts).astype(np.float32))
+
+
+def kdop_init(d: int, k: int, scale: float = 10.0, seed: int | None = None) -> np.ndarray:
+    """Initial k-DOP parameters [n_1..n_k, lo, hi, s]: the d axes first, then
+    unit diagonals (sign patterns of the first axes), optionally jittered by
+    a seeded draw; slabs start at the projection of the cube [-1, 1]^d, so
+    the initial k-DOP contains every query domain."""
+    dirs = [np.eye(d)[i] for i in range(d)]
+    signs = [np.array([1.0] + [(1.0 if (m >> i) & 1 == 0 else -1.0) for i in range(d - 1)]) for m in range(2 ** (d - 1))]
+    dirs += [sg / np.sqrt(d) for sg in signs]
+    if k > len(dirs):
+        raise ValueError(f"at most {len(dirs)} directions in {d}-D")
+    N = np.array(dirs[:k], dtype=np.float64)
+    if seed is not None:
+        N = N + 0.05 * rng(seed).standard_normal(N.shape)
+        N /= np.linalg.norm(N, axis=1, keepdims=True)
+    ext = np.abs(N).sum(axis=1)
+    theta = np.concatenate([N.ravel(), -ext, ext, [scale]])
+    return np.ascontiguousarray(theta.astype(np.float32))

@@ -94,3 +94,15 @@ def test_group_arguments():
     assert lib.nb_group_set_variant(None, 0) == 1
     if nb.nb_device_count() == 0:
         assert lib.nb_group_create(3, 6, wp, 3, 1, C.byref(h)) == 2
+
+
+def test_kdop_arguments():
+    lib = _lib.load()
+    h = C.c_void_p()
+    assert lib.nb_kdop_create(3, 4, None) == 1
+    assert lib.nb_kdop_create(1, 4, C.byref(h)) == 1
+    assert lib.nb_kdop_create(3, 9, C.byref(h)) == 1
+    assert lib.nb_kdop_destroy(None) == 0
+    assert lib.nb_kdop_forward(None, 0, None, 10, 1e-5, None, None, None, None, None) == 1
+    if nb.nb_device_count() == 0:
+        assert lib.nb_kdop_create(3, 4, C.byref(h)) == 2
