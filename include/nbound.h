@@ -173,6 +173,16 @@ nb_status nb_bound_set_variant(nb_bound* b, int variant);
  * more forward pass.  Float32 bounds accept only 0. */
 nb_status nb_bound_set_recompute(nb_bound* b, int every);
 
+/* Hidden-layer activation: NB_ACT_RELU (default) or NB_ACT_SINE, the paper's
+ * sinusoidal activation a = sin z (Sec. 3.4, "Architecture"; derivative
+ * cos z in training).  Sine is available for float32 bounds of width 32 or
+ * 64 with 1..3 hidden layers (narrower layers, such as the paper's 25 or 50
+ * neurons, run exactly as zero-padded ones: sin 0 = 0 and the padding gets
+ * no gradient); anything else returns NB_ERR_UNSUPPORTED. */
+#define NB_ACT_RELU 0
+#define NB_ACT_SINE 1
+nb_status nb_bound_set_activation(nb_bound* b, int activation);
+
 /* Copy theta (device, float32[n_params]) into the bound; resets the Adam
  * moments and step count to zero. */
 nb_status nb_bound_set_params(nb_bound* b, const float* theta, int64_t n_params, void* stream);

@@ -5,7 +5,8 @@ by a sigmoid and rounded to {0, 1}.  Layer sizes are written "a x b x c"
 (supplemental architecture tables) and mean in_dim -> hidden widths -> 1
 output logit, with a bias on every layer; the 3 x 50 x 50 network then has
 the 2,801 parameters the paper quotes (Sec. 6, "Limitations").  Hidden
-layers here use ReLU.
+layers use ReLU, or (act="sine") the paper's sinusoidal activation
+a = sin(z) (Sec. 3.4, "Architecture").
 
 Parameters are one flat vector, layer by layer: W_l[out, in] row-major, then
 b_l[out].  Forward and backward run in float64 on float32 inputs.
@@ -76,7 +77,19 @@ def _hidden_bf16(l: int, n_layers: int) -> bool:
     return 0 < l < n_layers - 1
 
 
-def forward(theta, in_dim: int, widths, x, bf16: bool = False, keep: bool = False):
+def _act(z, act: str):
+    if act == "relu":
+        return np.maximum(z, 0.0)
+    if act == "sine":
+        return np.sin(z)
+    raise ValueError(act)
+
+
+def _act_deriv(z, act: str):
+    return (z > 0.0).astype(np.float64) if act == "relu" else np.cos(z)
+
+
+def forward(theta, in_dim: int, widths, x, bf16: bool = False, keep: bool = False, act: str = "relu"):
     """Logits z [n] (float64).  With keep=True also returns the per-layer
     inputs a_{l-1} and pre-activations z_l used by the backward pass."""
     layers = unpack(theta, in_dim, widths)
@@ -94,32 +107,33 @@ def forward(theta, in_dim: int, widths, x, bf16: bool = False, keep: bool = Fals
         else:
             z = a @ W.T + b
         pre.append(z)
-        a = np.maximum(z, 0.0) if l + 1 < len(layers) else z
+        a = _act(z, act) if l + 1 < len(layers) else z
     z = a[:, 0]
     if keep:
         return z, inputs, pre
     return z
 
 
-def abs_forward(theta, in_dim: int, widths, x, bf16: bool = False) -> np.ndarray:
+def abs_forward(theta, in_dim: int, widths, x, bf16: bool = False, act: str = "relu") -> np.ndarray:
     """Scale s = |W_L| |a_{L-1}| + |b_L| of the last layer, per query: the sum
     of the magnitudes of the terms that make up the logit."""
     layers = unpack(theta, in_dim, widths)
-    _, inputs, _ = forward(theta, in_dim, widths, x, bf16=bf16, keep=True)
+    _, inputs, _ = forward(theta, in_dim, widths, x, bf16=bf16, keep=True, act=act)
     W, b = layers[-1]
     return (np.abs(inputs[-1]) @ np.abs(W).T)[:, 0] + abs(b[0])
 
 
-def backward(theta, in_dim: int, widths, x, dz, bf16: bool = False) -> np.ndarray:
+def backward(theta, in_dim: int, widths, x, dz, bf16: bool = False, act: str = "relu") -> np.ndarray:
     """Gradient of sum_i dz_i * z_i with respect to theta (flat, float64).
-    delta_L = dz; delta_{l-1} = (W_l^T delta_l) * 1[z_{l-1} > 0];
+    delta_L = dz; delta_{l-1} = (W_l^T delta_l) * act'(z_{l-1})
+    (1[z > 0] for ReLU, cos z for sine);
     dW_l = sum_i delta_l a_{l-1}^T, db_l = sum_i delta_l.
     In bfloat16 mode the weights and layer inputs are the rounded ones the
     forward pass used (the first layer's input is the float32 query); the
     gradient is taken with respect to the float32 master weights (straight
     through the rounding)."""
     layers = unpack(theta, in_dim, widths)
-    _, inputs, pre = forward(theta, in_dim, widths, x, bf16=bf16, keep=True)
+    _, inputs, pre = forward(theta, in_dim, widths, x, bf16=bf16, keep=True, act=act)
     delta = np.asarray(dz, dtype=np.float64)[:, None]
     grads = [None] * len(layers)
     for l in range(len(layers) - 1, -1, -1):
@@ -128,7 +142,7 @@ def backward(theta, in_dim: int, widths, x, dz, bf16: bool = False) -> np.ndarra
             W = bf16_round(W.astype(np.float32)).astype(np.float64)
         grads[l] = (delta.T @ inputs[l], delta.sum(axis=0))
         if l:
-            delta = (delta @ W) * (pre[l - 1] > 0.0)
+            delta = (delta @ W) * _act_deriv(pre[l - 1], act)
     return pack(grads)
 
 

@@ -183,6 +183,13 @@ def nb_bound_num_variants(b) -> int:
     return n.value
 
 
+RELU, SINE = 0, 1
+
+
+def nb_bound_set_activation(b, activation: int):
+    _check(lib().nb_bound_set_activation(b, int(activation)))
+
+
 def nb_bound_set_recompute(b, every: int):
     _check(lib().nb_bound_set_recompute(b, int(every)))
 

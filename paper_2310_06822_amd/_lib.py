@@ -35,6 +35,7 @@ SIGNATURES = {
     "nb_bound_num_variants": (i32, [vp, C.POINTER(C.c_int)]),
     "nb_bound_set_variant": (i32, [vp, C.c_int]),
     "nb_bound_set_recompute": (i32, [vp, C.c_int]),
+    "nb_bound_set_activation": (i32, [vp, C.c_int]),
     "nb_bound_set_params": (i32, [vp, vp, i64, vp]),
     "nb_bound_get_params": (i32, [vp, vp, i64, vp]),
     "nb_bound_get_state": (i32, [vp, vp, vp, i64, C.POINTER(i64), vp]),

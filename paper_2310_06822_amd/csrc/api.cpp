@@ -384,6 +384,17 @@ nb_status nb_bound_num_variants(const nb_bound* b, int* count) {
   return NB_OK;
 }
 
+nb_status nb_bound_set_activation(nb_bound* b, int activation) {
+  NB_REQUIRE(b, "bound is NULL");
+  NB_REQUIRE(activation == NB_ACT_RELU || activation == NB_ACT_SINE, "unknown activation %d", activation);
+  if (activation == NB_ACT_SINE && !(b->precision == NB_F32 && f32_sine_supported(b->in_dim, b->n_hidden, b->width))) {
+    nb_set_error("sine activations run on float32 bounds of width 32 or 64 with 1..3 hidden layers");
+    return NB_ERR_UNSUPPORTED;
+  }
+  b->activation = activation;
+  return NB_OK;
+}
+
 nb_status nb_bound_set_recompute(nb_bound* b, int every) {
   NB_REQUIRE(b, "bound is NULL");
   NB_REQUIRE(every == 0 || (every >= 2 && every <= 64), "checkpoint interval must be 0 or 2..64");

@@ -1,6 +1,6 @@
 // The bound h_theta as a float32 MLP on the matrix cores (Sec. 3.4,
 // "Architecture": an MLP whose output logit goes through a sigmoid and is
-// rounded to {0,1}; ReLU hidden layers here).
+// rounded to {0,1}; ReLU hidden layers, or the paper's sinusoidal ones).
 //
 // Matrix-core mapping (v_mfma_f32_16x16x4f32, one wave of 64 lanes):
 //   neurons are MFMA rows, queries are MFMA columns.  A wave takes 16
@@ -34,6 +34,21 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Hidden activation ACT: 0 ReLU, 1 sine (sin z; the paper's choice).  The
+// training kernel keeps per layer the value the backward pass needs: the
+// ReLU output itself (its sign is the derivative), or the pre-activation z
+// for sine (value sin z, derivative cos z).
+template <int ACT>
+__device__ __forceinline__ float act_apply(float z) { return ACT == 0 ? fmaxf(z, 0.0f) : sinf(z); }
+template <int ACT>
+__device__ __forceinline__ float act_store(float z) { return ACT == 0 ? fmaxf(z, 0.0f) : z; }
+template <int ACT>
+__device__ __forceinline__ float act_value(float kept) { return ACT == 0 ? kept : sinf(kept); }
+template <int ACT>
+__device__ __forceinline__ float act_grad(float kept, float g) {
+  return ACT == 0 ? (kept > 0.0f ? g : 0.0f) : g * cosf(kept);
 }
 
 // Orders LDS traffic of one wave: the hardware executes a wave's LDS
@@ -88,7 +103,7 @@ __global__ void k_pack(const float* __restrict__ theta, int in_dim, int W, int N
 
 // ------------------------------------------------------------------ forward
 
-template <int KIN, int W, int NH>
+template <int KIN, int W, int NH, int ACT>
 __global__ __launch_bounds__(256) void k_fwd(const float* __restrict__ q, int64_t n, int in_dim,
                                              const float* __restrict__ pack, const float* __restrict__ theta,
                                              float tau, float* __restrict__ logits, uint8_t* __restrict__ hout,
@@ -137,7 +152,7 @@ __global__ __launch_bounds__(256) void k_fwd(const float* __restrict__ q, int64_
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a[mo * 4 + r] = fmaxf(acc[mo][r], 0.0f);
+        for (int r = 0; r < 4; ++r) a[mo * 4 + r] = act_apply<ACT>(acc[mo][r]);
     }
 #pragma unroll
     for (int l = 1; l < NH; ++l) {
@@ -157,7 +172,7 @@ __global__ __launch_bounds__(256) void k_fwd(const float* __restrict__ q, int64_
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a[mo * 4 + r] = fmaxf(acc[mo][r], 0.0f);
+        for (int r = 0; r < 4; ++r) a[mo * 4 + r] = act_apply<ACT>(acc[mo][r]);
     }
     float p = 0.0f;
 #pragma unroll
@@ -202,7 +217,7 @@ struct TrainLds {
   }
 };
 
-template <int KIN, int W, int NH>
+template <int KIN, int W, int NH, int ACT>
 __global__ __launch_bounds__(256, 1) void k_train(const float* __restrict__ q, const uint8_t* __restrict__ y,
                                                   int64_t n, int in_dim, int bpw, const float* __restrict__ pack,
                                                   const float* __restrict__ theta, float alpha, float beta,
@@ -282,7 +297,7 @@ __global__ __launch_bounds__(256, 1) void k_train(const float* __restrict__ q, c
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) act[0][mo * 4 + r] = fmaxf(acc[mo][r], 0.0f);
+        for (int r = 0; r < 4; ++r) act[0][mo * 4 + r] = act_store<ACT>(acc[mo][r]);
     }
 #pragma unroll
     for (int l = 1; l < NH; ++l) {
@@ -293,22 +308,28 @@ __global__ __launch_bounds__(256, 1) void k_train(const float* __restrict__ q, c
         acc[mo] = floatx4{b[0], b[1], b[2], b[3]};
       }
       const float* fr = spack + (N::F1 + (l - 1) * N::FH) * 64 + lane;
+      float av[RB * 4];
+#pragma unroll
+      for (int i = 0; i < RB * 4; ++i) av[i] = act_value<ACT>(act[l - 1][i]);
 #pragma unroll
       for (int mi = 0; mi < RB; ++mi)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-          for (int mo = 0; mo < RB; ++mo) acc[mo] = mfma4(fr[((mo * RB + mi) * 4 + r) * 64], act[l - 1][mi * 4 + r], acc[mo]);
+          for (int mo = 0; mo < RB; ++mo) acc[mo] = mfma4(fr[((mo * RB + mi) * 4 + r) * 64], av[mi * 4 + r], acc[mo]);
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) act[l][mo * 4 + r] = fmaxf(acc[mo][r], 0.0f);
+        for (int r = 0; r < 4; ++r) act[l][mo * 4 + r] = act_store<ACT>(acc[mo][r]);
     }
+    float alast[RB * 4];
+#pragma unroll
+    for (int i = 0; i < RB * 4; ++i) alast[i] = act_value<ACT>(act[NH - 1][i]);
     float p = 0.0f;
 #pragma unroll
     for (int mo = 0; mo < RB; ++mo)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) p = fmaf(swo[16 * mo + 4 * grp + r], act[NH - 1][mo * 4 + r], p);
+      for (int r = 0; r < 4; ++r) p = fmaf(swo[16 * mo + 4 * grp + r], alast[mo * 4 + r], p);
     p += __shfl_xor(p, 16);
     p += __shfl_xor(p, 32);
     const float z = p + bo;
@@ -339,8 +360,8 @@ __global__ __launch_bounds__(256, 1) void k_train(const float* __restrict__ q, c
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = mo * 4 + r;
-        gwo[i] = fmaf(dz, act[NH - 1][i], gwo[i]);
-        d[i] = act[NH - 1][i] > 0.0f ? dz * swo[16 * mo + 4 * grp + r] : 0.0f;
+        gwo[i] = fmaf(dz, alast[i], gwo[i]);
+        d[i] = act_grad<ACT>(act[NH - 1][i], dz * swo[16 * mo + 4 * grp + r]);
       }
 
 #pragma unroll
@@ -352,7 +373,7 @@ __global__ __launch_bounds__(256, 1) void k_train(const float* __restrict__ q, c
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           dt[(16 * mo + 4 * grp + r) * kLDT + c] = d[mo * 4 + r];
-          at[(16 * mo + 4 * grp + r) * kLDT + c] = act[l - 1][mo * 4 + r];
+          at[(16 * mo + 4 * grp + r) * kLDT + c] = act_value<ACT>(act[l - 1][mo * 4 + r]);
         }
       wave_lds_sync();
 #pragma unroll
@@ -377,7 +398,7 @@ __global__ __launch_bounds__(256, 1) void k_train(const float* __restrict__ q, c
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) d[mo * 4 + r] = act[l - 1][mo * 4 + r] > 0.0f ? acc[mo][r] : 0.0f;
+        for (int r = 0; r < 4; ++r) d[mo * 4 + r] = act_grad<ACT>(act[l - 1][mo * 4 + r], acc[mo][r]);
       wave_lds_sync();
     }
 
@@ -477,19 +498,19 @@ __global__ __launch_bounds__(256, 1) void k_train(const float* __restrict__ q, c
 
 constexpr int kMaxWG = 256;
 
-template <int KIN, int W, int NH>
+template <int KIN, int W, int NH, int ACT>
 nb_status fwd_launch(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
                      const uint8_t* g, unsigned long long* counts, const unsigned long long* n_dev, hipStream_t s) {
   const int64_t nblk = (n + 15) / 16;
   const int64_t want = (nblk + 3) / 4;
   const int64_t cap = (int64_t)nb_cu_count() * 2;
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min(want, cap));
-  k_fwd<KIN, W, NH><<<grid, 256, 0, s>>>(q, n, b->in_dim, b->pack, b->theta, tau, logits, h, g, counts, n_dev);
+  k_fwd<KIN, W, NH, ACT><<<grid, 256, 0, s>>>(q, n, b->in_dim, b->pack, b->theta, tau, logits, h, g, counts, n_dev);
   NB_LAUNCHED();
   return NB_OK;
 }
 
-template <int KIN, int W, int NH>
+template <int KIN, int W, int NH, int ACT>
 nb_status train_launch(const nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha, float beta,
                        float tau, int* n_wg, hipStream_t s) {
   using L = TrainLds<KIN, W, NH>;
@@ -501,11 +522,11 @@ nb_status train_launch(const nb_bound* b, const float* q, const uint8_t* y, int6
   int dev = 0;
   NB_HIP(hipGetDevice(&dev));
   if (dev >= 0 && dev < 64 && !attr_set[dev]) {
-    NB_HIP(hipFuncSetAttribute((const void*)k_train<KIN, W, NH>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    NB_HIP(hipFuncSetAttribute((const void*)k_train<KIN, W, NH, ACT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     attr_set[dev] = true;
   }
-  k_train<KIN, W, NH><<<grid, 256, lds, s>>>(q, y, n, b->in_dim, bpw, b->pack, b->theta, alpha, beta,
+  k_train<KIN, W, NH, ACT><<<grid, 256, lds, s>>>(q, y, n, b->in_dim, bpw, b->pack, b->theta, alpha, beta,
                                              (float)(1.0 / (double)n), tau, b->partial, b->aux);
   NB_LAUNCHED();
   *n_wg = grid;
@@ -521,9 +542,19 @@ nb_status train_launch(const nb_bound* b, const float* q, const uint8_t* y, int6
   X(2, 32, 1) X(2, 32, 2) X(2, 32, 3) X(2, 32, 4) \
   X(2, 64, 1) X(2, 64, 2) X(2, 64, 3) X(2, 64, 4)
 
+// Sine instances (the paper's own architectures: widths up to 64 with the
+// neurons of a 25- or 50-wide layer zero-padded, 1..3 hidden layers).
+#define NB_F32_SINE_CASES(X) \
+  X(1, 32, 1) X(1, 32, 2) X(1, 32, 3) X(1, 64, 1) X(1, 64, 2) X(1, 64, 3) \
+  X(2, 32, 1) X(2, 32, 2) X(2, 32, 3) X(2, 64, 1) X(2, 64, 2) X(2, 64, 3)
+
 inline int kin_of(int in_dim) { return (in_dim + 3) / 4; }
 
 }  // namespace
+
+bool f32_sine_supported(int in_dim, int n_hidden, int width) {
+  return in_dim >= 1 && in_dim <= 8 && n_hidden >= 1 && n_hidden <= 3 && (width == 32 || width == 64);
+}
 
 bool f32_supported(int in_dim, int n_hidden, int width) {
   return in_dim >= 1 && in_dim <= 8 && n_hidden >= 1 && n_hidden <= 4 && (width == 16 || width == 32 || width == 64);
@@ -546,11 +577,19 @@ nb_status f32_pack(const nb_bound* b, hipStream_t s) {
 nb_status f32_forward(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
                       const uint8_t* g, unsigned long long* counts, hipStream_t s, const unsigned long long* n_dev) {
   const int kin = kin_of(b->in_dim);
+  if (b->activation == NB_ACT_SINE) {
 #define X(K, WW, H)                                                                  \
   if (kin == K && b->width == WW && b->n_hidden == H)                                \
-    return fwd_launch<K, WW, H>(b, q, n, tau, logits, h, g, counts, n_dev, s);
-  NB_F32_CASES(X)
+    return fwd_launch<K, WW, H, 1>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+    NB_F32_SINE_CASES(X)
 #undef X
+  } else {
+#define X(K, WW, H)                                                                  \
+  if (kin == K && b->width == WW && b->n_hidden == H)                                \
+    return fwd_launch<K, WW, H, 0>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+    NB_F32_CASES(X)
+#undef X
+  }
   nb_set_error("float32 bound %d x %d^%d has no kernel", b->in_dim, b->width, b->n_hidden);
   return NB_ERR_UNSUPPORTED;
 }
@@ -558,11 +597,19 @@ nb_status f32_forward(const nb_bound* b, const float* q, int64_t n, float tau, f
 nb_status f32_train_partials(const nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha,
                              float beta, float tau, int* n_wg, hipStream_t s) {
   const int kin = kin_of(b->in_dim);
+  if (b->activation == NB_ACT_SINE) {
 #define X(K, WW, H)                                                  \
   if (kin == K && b->width == WW && b->n_hidden == H)                \
-    return train_launch<K, WW, H>(b, q, y, n, alpha, beta, tau, n_wg, s);
-  NB_F32_CASES(X)
+    return train_launch<K, WW, H, 1>(b, q, y, n, alpha, beta, tau, n_wg, s);
+    NB_F32_SINE_CASES(X)
 #undef X
+  } else {
+#define X(K, WW, H)                                                  \
+  if (kin == K && b->width == WW && b->n_hidden == H)                \
+    return train_launch<K, WW, H, 0>(b, q, y, n, alpha, beta, tau, n_wg, s);
+    NB_F32_CASES(X)
+#undef X
+  }
   nb_set_error("float32 bound %d x %d^%d has no kernel", b->in_dim, b->width, b->n_hidden);
   return NB_ERR_UNSUPPORTED;
 }

@@ -91,6 +91,7 @@ struct nb_bound {
   int64_t pack16t_elems = 0;
   uint16_t* tr_act = nullptr;      // activation slots x [padded batch][width]
   int recompute = 0;               // activation checkpoint interval (0: keep every activation)
+  int activation = 0;              // NB_ACT_RELU or NB_ACT_SINE
   int tr_slots = 0;                // activation slots tr_act holds
   uint16_t* tr_grad = nullptr;     // 2 x [padded batch][width]
   int64_t tr_cap = 0;              // padded batch the two above hold
@@ -163,6 +164,7 @@ nb_status launch_collect_occupied(const uint8_t* grid, int64_t cells, int32_t* o
 
 // mlp_f32.hip
 bool f32_supported(int in_dim, int n_hidden, int width);
+bool f32_sine_supported(int in_dim, int n_hidden, int width);
 int64_t f32_pack_floats(int in_dim, int n_hidden, int width);
 nb_status f32_pack(const nb_bound* b, hipStream_t s);
 // n_dev (device, nullable): evaluate only the first min(n, *n_dev) rows.

@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "rng", "discs2d", "metaballs3d", "metaballs4d", "random_grid",
     "points", "points4d", "rays", "boxes", "planes", "init_params",
-    "layer_shapes", "num_params", "seed_for", "object_set", "kdop_init",
+    "layer_shapes", "num_params", "seed_for", "object_set", "kdop_init", "pad_params",
 ]
 
 # Seed bases per stream: scene / training stream / held-out eval / init.
@@ -199,3 +199,20 @@ def kdop_init(d: int, k: int, scale: float = 10.0, seed: int | None = None) -> n
     ext = np.abs(N).sum(axis=1)
     theta = np.concatenate([N.ravel(), -ext, ext, [scale]])
     return np.ascontiguousarray(theta.astype(np.float32))
+
+
+def pad_params(theta, in_dim: int, widths, padded_widths) -> np.ndarray:
+    """Embed a network's flat parameters into a wider one of the same depth,
+    the extra neurons' weights and biases zero (a layout copy, no arithmetic)."""
+    src = layer_shapes(in_dim, widths)
+    dst = layer_shapes(in_dim, padded_widths)
+    out, off = [], 0
+    for (o, i), (po, pi) in zip(src, dst):
+        W = np.zeros((po, pi), dtype=np.asarray(theta).dtype)
+        b = np.zeros(po, dtype=W.dtype)
+        W[:o, :i] = np.asarray(theta[off:off + o * i]).reshape(o, i)
+        off += o * i
+        b[:o] = theta[off:off + o]
+        off += o
+        out += [W.ravel(), b]
+    return np.ascontiguousarray(np.concatenate(out))

@@ -557,3 +557,82 @@ def test_inverted_bound_has_no_false_positives():
     tp, fp, tn, fn = b.counts(q, g).tolist()
     assert fp == 0
     assert tp > 0.5 * (tp + fn)   # it still certifies most of the inside
+
+
+# ------------------------------------------------------ sine activations
+
+SINE_SHAPES = [(3, 64, 2), (2, 32, 2), (3, 64, 3), (6, 64, 1), (4, 32, 3)]
+
+
+@pytest.mark.parametrize("in_dim,width,nh", SINE_SHAPES)
+@pytest.mark.parametrize("n", [1, 17, 3005])
+def test_forward_sine_parity(in_dim, width, nh, n):
+    """Sinusoidal hidden layers (Sec. 3.4): logits within 1e-5 of the
+    magnitude of their terms, decisions equal outside the band."""
+    widths = [width] * nh
+    theta = synth.init_params(140 + in_dim + width + nh, in_dim, widths)
+    q = synth.points(141, n, in_dim)
+    b = nb.Bound(in_dim, nh, width)
+    nb.nb_bound_set_activation(b.handle, nb.SINE)
+    b.set_params(theta)
+    z, h = b.forward(cuda(q))
+    z, h = host(z).astype(np.float64), host(h)
+    ref = mlp.forward(theta, in_dim, widths, q, act="sine")
+    s = mlp.abs_forward(theta, in_dim, widths, q, act="sine")
+    assert np.all(np.abs(z - ref) <= 1e-5 * np.maximum(np.abs(ref), s))
+    band = np.abs(ref) < 1e-4
+    assert np.array_equal(h[~band], L.decide(ref)[~band])
+
+
+@pytest.mark.parametrize("in_dim,width,nh", SINE_SHAPES)
+def test_loss_grad_sine_parity(in_dim, width, nh):
+    widths = [width] * nh
+    theta = synth.init_params(150 + width + nh, in_dim, widths)
+    n = 4099
+    q = synth.points(151, n, in_dim)
+    y = (synth.points(152, n, 1)[:, 0] > 0.3).astype(np.uint8)
+    b = nb.Bound(in_dim, nh, width)
+    nb.nb_bound_set_activation(b.handle, nb.SINE)
+    b.set_params(theta)
+    grad = torch.empty(b.n_params, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    nb.nb_bound_loss_grad(b.handle, cuda(q), cuda(y), 6.0, 1.0, grad, loss)
+    z = mlp.forward(theta, in_dim, widths, q, act="sine")
+    gref = mlp.backward(theta, in_dim, widths, q, L.dloss_dz(z, y, 6.0, 1.0), act="sine")
+    assert abs(host(loss)[0] - L.loss(z, y, 6.0, 1.0)) <= 1e-5 * L.loss(z, y, 6.0, 1.0)
+    g = host(grad).astype(np.float64)
+    for (Wg, bg), (Wr, br) in zip(mlp.unpack(g, in_dim, widths), mlp.unpack(gref, in_dim, widths)):
+        assert _rel_frob(Wg, Wr) <= 1e-5
+        assert _rel_frob(bg, br) <= 1e-5
+
+
+def test_sine_paper_architecture_padded():
+    """The paper's 3 x 50 x 50 sine network run as 3 x 64 x 64 with zero
+    padding: the same logits as the unpadded oracle network, and a training
+    step leaves the padding at zero."""
+    theta50 = synth.init_params(160, 3, [50, 50])
+    theta = synth.pad_params(theta50, 3, [50, 50], [64, 64])
+    b = nb.Bound(3, 2, 64)
+    nb.nb_bound_set_activation(b.handle, nb.SINE)
+    b.set_params(theta)
+    q = synth.points(161, 5000, 3)
+    z, _ = b.forward(cuda(q))
+    ref = mlp.forward(theta50, 3, [50, 50], q, act="sine")
+    s = mlp.abs_forward(theta50, 3, [50, 50], q, act="sine")
+    assert np.all(np.abs(host(z) - ref) <= 1e-5 * np.maximum(np.abs(ref), s))
+    grid = I.voxelize_metaballs(*synth.metaballs3d(1001, k=16), 64)
+    ind = nb.Indicator.voxels(cuda(grid), 64)
+    for t in range(3):
+        nb.nb_bound_train_step(b.handle, ind.handle, nb.POINT, 5, t, 8192, 10.0)
+    th = host(b.params())
+    mask = synth.pad_params(np.ones_like(theta50), 3, [50, 50], [64, 64]) != 0
+    assert np.all(th[~mask] == 0) and np.any(th[mask] != theta[mask])
+
+
+def test_sine_unsupported_shapes():
+    b = nb.Bound(6, 4, 128, nb.BF16)
+    with pytest.raises(nb.NBError):
+        nb.nb_bound_set_activation(b.handle, nb.SINE)
+    b = nb.Bound(3, 4, 64)
+    with pytest.raises(nb.NBError):
+        nb.nb_bound_set_activation(b.handle, nb.SINE)

@@ -285,3 +285,64 @@ def test_throughput_units_table2():
     # Table 2 throughput = 10M queries / time: 70.82 ms -> 0.14 G rays/s, 2.58 ms -> 3.88
     assert round(1e7 / 70.82e-3 / 1e9, 2) == 0.14
     assert round(1e7 / 2.58e-3 / 1e9, 2) == 3.88
+
+
+# ------------------------------------------------------------- sine networks
+
+class _Sin(torch.nn.Module):
+    def forward(self, x):
+        return torch.sin(x)
+
+
+def _torch_sine_net(theta, in_dim, widths):
+    mods = []
+    layers = mlp.unpack(theta, in_dim, widths)
+    for l, (W, b) in enumerate(layers):
+        lin = torch.nn.Linear(W.shape[1], W.shape[0]).double()
+        with torch.no_grad():
+            lin.weight.copy_(torch.from_numpy(W))
+            lin.bias.copy_(torch.from_numpy(b))
+        mods.append(lin)
+        if l + 1 < len(layers):
+            mods.append(_Sin())
+    return torch.nn.Sequential(*mods)
+
+
+def test_sine_forward_backward_vs_torch():
+    """Sinusoidal hidden activations (Sec. 3.4): forward and the gradient of
+    Eq. 1 against torch float64 autograd."""
+    in_dim, widths = 3, [50, 50]
+    theta = synth.init_params(21, in_dim, widths)
+    x = synth.points(22, 300, in_dim)
+    y = (synth.points(23, 300, 1)[:, 0] > 0).astype(np.uint8)
+    z = mlp.forward(theta, in_dim, widths, x, act="sine")
+    net = _torch_sine_net(theta, in_dim, widths)
+    zt = net(torch.from_numpy(x.astype(np.float64)))[:, 0]
+    assert np.allclose(z, zt.detach().numpy(), rtol=1e-12, atol=1e-13)
+    g = mlp.backward(theta, in_dim, widths, x, L.dloss_dz(z, y, 5.0, 1.0), act="sine")
+    yt = torch.from_numpy(y.astype(np.float64))
+    lt = (5.0 * yt * torch.nn.functional.softplus(-zt) + (1 - yt) * torch.nn.functional.softplus(zt)).mean()
+    lt.backward()
+    ref = np.concatenate([np.concatenate([m.weight.grad.numpy().ravel(), m.bias.grad.numpy()])
+                          for m in net if isinstance(m, torch.nn.Linear)])
+    assert np.allclose(g, ref, rtol=1e-10, atol=1e-14)
+
+
+def test_sine_zero_padding_is_exact():
+    """A sine network padded with zero neurons computes the same logits and
+    its padded parameters get zero gradient (sin 0 = 0; the padding's
+    outgoing weights are zero), so a 3 x 50 x 50 network runs exactly as a
+    3 x 64 x 64 one."""
+    in_dim, small, big = 3, [50, 50], [64, 64]
+    theta = synth.init_params(24, in_dim, small)
+    padded = synth.pad_params(theta, in_dim, small, big)
+    x = synth.points(25, 200, in_dim)
+    y = (synth.points(26, 200, 1)[:, 0] > 0.1).astype(np.uint8)
+    z = mlp.forward(theta, in_dim, small, x, act="sine")
+    zp = mlp.forward(padded, in_dim, big, x, act="sine")
+    assert np.allclose(z, zp, rtol=1e-12, atol=1e-14)
+    gp = mlp.backward(padded, in_dim, big, x, L.dloss_dz(zp, y, 3.0, 1.0), act="sine")
+    mask = synth.pad_params(np.ones_like(theta), in_dim, small, big) != 0
+    assert np.all(gp[~mask] == 0)
+    g = mlp.backward(theta, in_dim, small, x, L.dloss_dz(z, y, 3.0, 1.0), act="sine")
+    assert np.allclose(gp[mask], g, rtol=1e-10, atol=1e-14)
