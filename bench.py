@@ -170,7 +170,13 @@ def run_workload(W, args, with_cpu: bool):
     bound = nb.Bound(W.in_dim, W.n_hidden, W.width, prec)
     if W.recompute:
         nb.nb_bound_set_recompute(bound.handle, W.recompute)
-    theta0 = synth.init_params(seeds["init"], W.in_dim, widths)
+    if W.act == "sine":
+        nb.nb_bound_set_activation(bound.handle, nb.SINE)
+    if W.real_width:
+        real = [W.real_width] * W.n_hidden
+        theta0 = synth.pad_params(synth.init_params(seeds["init"], W.in_dim, real), W.in_dim, real, widths)
+    else:
+        theta0 = synth.init_params(seeds["init"], W.in_dim, widths)
 
     # ---- training (Alg. 1 on the device): ramp, then the step-wise schedule
     over = {"steps": args.train_steps} if args.train_steps is not None else {}
@@ -216,7 +222,8 @@ def run_workload(W, args, with_cpu: bool):
 
     early = run_early_out(W, args, nb, synth, trainer, ind, bound, q, g, kind, prec, kern_ms, torch) if W.early else None
 
-    macs = W.in_dim * W.width + (W.n_hidden - 1) * W.width * W.width + W.width
+    wr = W.real_width or W.width   # algorithmic work of the network itself (not its zero padding)
+    macs = W.in_dim * wr + (W.n_hidden - 1) * wr * wr + wr
     flop_per_q = 2 * macs
     peak = PEAK_TFLOPS[W.precision]
     achieved = flop_per_q * n_eval / (kern_ms / 1e3) / 1e12
@@ -231,7 +238,8 @@ def run_workload(W, args, with_cpu: bool):
         "config": {"workload": W.name, "query": W.kind, "queries_per_step": n_eval,
                    "net": f"{W.in_dim}x{W.width}^{W.n_hidden}x1 relu {W.precision}",
                    "train_steps": res.steps, "train_batch": W.batch, "scene": W.scene,
-                   "activation_checkpoint_interval": W.recompute},
+                   "activation_checkpoint_interval": W.recompute, "activation": W.act,
+                   "real_width": W.real_width or W.width},
         "train_samples_per_s": res.samples_per_s,
         "train": {"steps": res.steps, "batch": W.batch, "seconds": res.seconds, "alpha_final": res.alpha_final,
                   "schedule_iterations": res.iters, "validation_fn_zero": res.converged,

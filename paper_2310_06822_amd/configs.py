@@ -40,6 +40,8 @@ class Workload:
     lr_decay: float = 1.0
     recompute: int = 0         # activation checkpoint interval of bfloat16 training (0: keep all)
     early: tuple = ()          # (width, n_hidden) of an early-out bound in front of this one, or ()
+    act: str = "relu"          # hidden activation: "relu" or "sine" (the paper's)
+    real_width: int = 0        # neurons per hidden layer before zero padding to `width` (0: width)
     bench_also: bool = False   # measured by `bench.py --also`
 
     @property
@@ -69,7 +71,15 @@ METABALL4D_POINT = Workload("metaball4d_point", 4, "point", 4, 4, 256, 6, "bf16"
                             train_steps=2000, batch=1 << 20, eval_n=1 << 24, adapt_k=100, adapt_iters=150,
                             lr_decay=0.99, recompute=3)
 
-WORKLOADS = {w.name: w for w in (DISC2D_POINT, VOXEL3D_POINT, VOXEL3D_RAY, METABALL4D_POINT)}
+# The 3-D point workload with the paper's own network: 3 x 50 x 50 with sine
+# activations (Sec. 3.4; supplemental architecture table), run as 3 x 64 x 64
+# with zero padding.
+VOXEL3D_POINT_SINE = Workload("voxel3d_point_sine", 1, "point", 3, 3, 64, 2, "f32",
+                              scene={"type": "metaball_voxels", "k": 16, "n": 128, "rlo": 0.05, "rhi": 0.25},
+                              train_steps=5000, batch=1 << 16, eval_n=1 << 24, act="sine", real_width=50,
+                              bench_also=True)
+
+WORKLOADS = {w.name: w for w in (DISC2D_POINT, VOXEL3D_POINT, VOXEL3D_RAY, METABALL4D_POINT, VOXEL3D_POINT_SINE)}
 
 
 @dataclass(frozen=True)
