@@ -61,7 +61,7 @@ def committed_traffic(name: str, source: str):
         return None
 
 
-def cpu_baseline(W, theta, seconds: float = 10.0):
+def cpu_baseline(W, theta, seconds: float = 15.0):
     """Oracle forward + decision on a bounded sample of held-out queries."""
     import synth
     from oracle import loss as L, mlp
@@ -152,6 +152,28 @@ def run_early_out(W, args, nb, synth, trainer, ind, bound, q, g, kind, prec, bou
             "heldout": {"n": n, "tp": tp, "fp": fp, "fn": fn, "fp_rate": fp / n}, "fn_zero": fn == 0}
 
 
+def run_kdop(W, args, nb, synth, trainer, ind, q, g, bound_ms, torch):
+    """The paper's OurkDOP: k slabs trained with the same loss and schedule."""
+    kd = nb.KDop(W.dim, W.kdop_k)
+    kd.set_params(synth.kdop_init(W.dim, W.kdop_k))
+    over = {"steps": args.train_steps} if args.train_steps is not None else {}
+    if args.no_adapt:
+        over["max_iters"] = 0
+    sched = W.schedule(**over)
+    sched.lr = 3e-3
+    res = trainer.train(kd, ind, W.kind, W.seeds["train"], sched, val_seed=W.seeds["val"],
+                        log=lambda m: log(f"[{W.name} kdop] {m}"))
+    n = q.shape[0]
+    h = torch.empty(n, dtype=torch.uint8, device="cuda")
+    ms, wall = timed(lambda: nb.nb_kdop_forward(kd.handle, nb.KINDS[W.kind], q, h=h), args.steps, args.warmup, torch)
+    tp, fp, tn, fn = kd.counts(W.kind, q, g).tolist()
+    log(f"[{W.name}] k-DOP (k={W.kdop_k}): {ms:.3f} ms, FN {fn} FP {fp}")
+    return {"k": W.kdop_k, "queries_per_s": n * args.steps / wall, "avg_ms": round(ms, 4),
+            "speedup_vs_bound": bound_ms / ms,
+            "train": {"steps": res.steps, "seconds": res.seconds, "validation_fn_zero": res.converged},
+            "heldout": {"n": n, "tp": tp, "fp": fp, "tn": tn, "fn": fn, "fp_rate": fp / n}, "fn_zero": fn == 0}
+
+
 def run_workload(W, args, with_cpu: bool):
     import torch
 
@@ -221,6 +243,7 @@ def run_workload(W, args, with_cpu: bool):
     casc_ok = bool(torch.equal(ans, g))
 
     early = run_early_out(W, args, nb, synth, trainer, ind, bound, q, g, kind, prec, kern_ms, torch) if W.early else None
+    kdop = run_kdop(W, args, nb, synth, trainer, ind, q, g, kern_ms, torch) if W.kdop_k else None
 
     wr = W.real_width or W.width   # algorithmic work of the network itself (not its zero padding)
     macs = W.in_dim * wr + (W.n_hidden - 1) * wr * wr + wr
@@ -255,6 +278,8 @@ def run_workload(W, args, with_cpu: bool):
     }
     if early:
         out["early_out"] = early
+    if kdop:
+        out["kdop"] = kdop
     if with_cpu:
         out["cpu_baseline"] = cpu_baseline(W, bound.params().cpu().numpy())
     return out

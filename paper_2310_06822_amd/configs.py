@@ -42,6 +42,7 @@ class Workload:
     early: tuple = ()          # (width, n_hidden) of an early-out bound in front of this one, or ()
     act: str = "relu"          # hidden activation: "relu" or "sine" (the paper's)
     real_width: int = 0        # neurons per hidden layer before zero padding to `width` (0: width)
+    kdop_k: int = 0            # also train and measure a k-DOP with k directions (0: none)
     bench_also: bool = False   # measured by `bench.py --also`
 
     @property
@@ -62,7 +63,7 @@ DISC2D_POINT = Workload("disc2d_point", 0, "point", 2, 2, 32, 3, "f32",
                         scene={"type": "discs", "k": 8}, train_steps=200, batch=1024, eval_n=1 << 16)
 VOXEL3D_POINT = Workload("voxel3d_point", 1, "point", 3, 3, 64, 3, "f32",
                          scene={"type": "metaball_voxels", "k": 16, "n": 128, "rlo": 0.05, "rhi": 0.25},
-                         train_steps=5000, batch=1 << 16, eval_n=1 << 24, early=(32, 1))
+                         train_steps=5000, batch=1 << 16, eval_n=1 << 24, early=(32, 1), kdop_k=4)
 VOXEL3D_RAY = Workload("voxel3d_ray", 2, "ray", 3, 6, 128, 4, "bf16",
                        scene={"type": "metaball_voxels", "k": 16, "n": 128, "rlo": 0.05, "rhi": 0.25, "seed_of": 1},
                        train_steps=5000, batch=1 << 18, eval_n=1 << 24, lr_decay=0.99, bench_also=True)

@@ -26,7 +26,8 @@ from dataclasses import dataclass, field
 
 import torch
 
-from . import KINDS, POINT, Bound, Indicator, nb_bound_train_step, nb_query_exact, nb_sample_queries
+from . import KINDS, POINT, Bound, Indicator, KDop, nb_bound_train_step, nb_kdop_train_step, nb_query_exact, \
+    nb_sample_queries
 
 
 @dataclass
@@ -77,9 +78,21 @@ def validation_set(ind: Indicator, kind: str, seed: int, n: int, draw: int = 0, 
     return q, g
 
 
-def train(bound: Bound, ind: Indicator, kind: str, seed: int, sched: Schedule, val_seed: int | None = None,
+def train(bound, ind: Indicator, kind: str, seed: int, sched: Schedule, val_seed: int | None = None,
           log=None) -> TrainResult:
+    """Train a Bound (or a KDop: its planes take the same loss and schedule)."""
     k = KINDS[kind]
+    if isinstance(bound, KDop):
+        def nb_bound_train_step(h, ih, kk, sd, st, batch, a, b, lr, lam1, lam2):
+            nb_kdop_train_step(h, ih, kk, sd, st, batch, a, b, lr)
+
+        def counts(q, g):
+            return bound.counts(kind, q, g)
+    else:
+        from . import nb_bound_train_step
+
+        def counts(q, g):
+            return bound.counts(q, g)
     res = TrainResult()
     val = validation_set(ind, kind, val_seed, sched.val_n) if (val_seed is not None and sched.max_iters > 0) else None
     torch.cuda.synchronize()
@@ -110,7 +123,7 @@ def train(bound: Bound, ind: Indicator, kind: str, seed: int, sched: Schedule, v
             lr = max(sched.lr_min, lr * sched.lr_decay)
             val = validation_set(ind, kind, val_seed, sched.val_n, draw=res.iters, out=val)
             # the error the bound must not make: FN, or FP for an inverted bound
-            fn = int(bound.counts(*val)[1 if sched.inverted else 3].item())
+            fn = int(counts(*val)[1 if sched.inverted else 3].item())
             res.val_fn_history.append(fn)
             res.iters += 1
             if fn == 0:
