@@ -333,7 +333,9 @@ nb_status nb_group_query_exact(const nb_group* g, int kind, const float* q, cons
  * tiles of queries of one object, objects ordered by width, runs of tiles of
  * equal estimated cost per workgroup, weights loaded into LDS once per run.
  * logits float32[n] and/or h uint8[n]; with g_exact (uint8[n]) and counts
- * (uint64[n_obj][4], overwritten) also each object's TP, FP, TN, FN. */
+ * (uint64[n_obj][4], overwritten) also each object's TP, FP, TN, FN.  An
+ * object whose rows qoff[o] .. qoff[o+1]-1 do not lie inside [0, n) is
+ * skipped (its outputs are left as they are, its counts stay 0). */
 nb_status nb_group_forward(const nb_group* g, const float* q, const int64_t* qoff, int64_t n, float eps,
                            float* logits, uint8_t* h, const uint8_t* g_exact, uint64_t* counts, void* stream);
 /* Tile-shape variants of the grouped forward (threads per workgroup and

@@ -69,7 +69,7 @@ VOXEL3D_RAY = Workload("voxel3d_ray", 2, "ray", 3, 6, 128, 4, "bf16",
                        train_steps=5000, batch=1 << 18, eval_n=1 << 24, lr_decay=0.99, bench_also=True)
 METABALL4D_POINT = Workload("metaball4d_point", 4, "point", 4, 4, 256, 6, "bf16",
                             scene={"type": "metaballs4d", "k": 24, "rlo": 0.05, "rhi": 0.2},
-                            train_steps=2000, batch=1 << 20, eval_n=1 << 24, adapt_k=100, adapt_iters=150,
+                            train_steps=2000, batch=1 << 20, eval_n=1 << 24, adapt_k=100, adapt_iters=400,
                             lr_decay=0.99, recompute=3)
 
 # The 3-D point workload with the paper's own network: 3 x 50 x 50 with sine

@@ -433,6 +433,8 @@ nb_status nb_kdop_train_step(nb_kdop* b, const nb_indicator* ind, int kind, uint
   NB_REQUIRE(lr > 0 && std::isfinite(alpha) && std::isfinite(beta) && alpha >= 0 && beta >= 0,
              "invalid learning rate or loss weights");
   NB_REQUIRE(ind->dim == b->d, "the indicator is %d-D, the k-DOP %d-D", ind->dim, b->d);
+  NB_REQUIRE(kind == NB_QUERY_POINT || (b->d == 3 && (kind == NB_QUERY_BOX || kind == NB_QUERY_RAY)),
+             "k-DOP bounds take points in 2-4 D and boxes or rays in 3-D (got kind %d in %d-D)", kind, b->d);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (b->batch_cap < batch) {
     NB_HIP(hipStreamSynchronize(s));

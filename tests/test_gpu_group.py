@@ -251,3 +251,19 @@ def test_group_errors():
         nb.nb_group_train_step(gr.handle, 2, nb.BOX, 1, 0, 64, 1.0)
     with pytest.raises(nb.NBError):
         gr.set_params(torch.zeros(gr.n_params + 1, device="cuda"))
+
+
+def test_group_forward_skips_objects_outside_the_batch():
+    """An object whose row range runs past n is skipped; the others are
+    computed as usual and nothing past n is touched."""
+    gr, thetas = _group(6, [64, 32, 128], 3, 700)
+    n = 300
+    q = synth.points(701, n, 6)
+    qoff = cuda(np.array([0, 150, 5000, 5000], np.int64))   # object 1 claims rows past n
+    z = torch.full((n,), -3.0, dtype=torch.float32, device="cuda")
+    nb.nb_group_forward(gr.handle, gr.n_obj, 6, cuda(q), qoff, logits=z)
+    z = host(z).astype(np.float64)
+    ref = mlp.forward(thetas[0], 6, [64] * 3, q[:150], bf16=True)
+    s = mlp.abs_forward(thetas[0], 6, [64] * 3, q[:150], bf16=True)
+    assert np.all(np.abs(z[:150] - ref) <= 1e-3 * np.maximum(np.abs(ref), s))
+    assert np.all(z[150:] == -3.0)
