@@ -316,7 +316,7 @@ def run_group_workload(GW, args):
     sched = trainer.Schedule(steps=args.train_steps if args.train_steps is not None else GW.train_steps,
                              batch=GW.per_obj, alpha_max=GW.alpha_max, k=GW.adapt_k, inc=GW.adapt_inc,
                              patience=GW.patience, max_iters=0 if args.no_adapt else GW.adapt_iters,
-                             val_n=GW.val_per_obj, lr_decay=GW.lr_decay)
+                             val_n=GW.val_per_obj, lr_decay=GW.lr_decay, cont_batch=GW.cont_batch)
     if getattr(args, "lr_decay", None) is not None:
         sched.lr_decay = args.lr_decay
     if getattr(args, "adapt_iters", None) is not None and not args.no_adapt:

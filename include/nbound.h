@@ -353,6 +353,11 @@ nb_status nb_group_set_variant(nb_group* g, int variant);
  * float32[n_obj] per-object mean loss or NULL; counts: uint64[n_obj][4] or
  * NULL.  The first step with a new per_obj synchronises `stream` to size the
  * work space. */
+/* Restrict training to the objects with active_host[o] != 0 (host uint8[n_obj];
+ * NULL: all).  The others' networks are neither evaluated nor updated by
+ * nb_group_train_step, and their loss and counts entries are not written.
+ * Synchronous (uploads the member lists). */
+nb_status nb_group_set_active(nb_group* g, const uint8_t* active_host);
 nb_status nb_group_train_step(nb_group* g, int kind, uint64_t seed, uint64_t step, int64_t per_obj, float alpha,
                               const float* alpha_obj, float beta, float lr, const float* lr_obj, float* loss,
                               uint64_t* counts, void* stream);

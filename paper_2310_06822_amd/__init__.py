@@ -380,6 +380,11 @@ def nb_group_set_box_method(g, method: int):
     _check(lib().nb_group_set_box_method(g, int(method)))
 
 
+def nb_group_set_active(g, active=None):
+    a = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
+    _check(lib().nb_group_set_active(g, None if a is None else a.ctypes.data_as(C.c_void_p)))
+
+
 def _qoff(qoff: torch.Tensor, n_obj: int, n: int):
     if qoff.numel() != n_obj + 1:
         raise ValueError("qoff must have n_obj + 1 entries")

@@ -61,6 +61,7 @@ SIGNATURES = {
     "nb_group_get_params": (i32, [vp, vp, i64, vp]),
     "nb_group_set_voxels": (i32, [vp, vp, vp]),
     "nb_group_set_box_method": (i32, [vp, C.c_int]),
+    "nb_group_set_active": (i32, [vp, vp]),
     "nb_group_query_exact": (i32, [vp, C.c_int, vp, vp, i64, vp, vp]),
     "nb_group_forward": (i32, [vp, vp, vp, i64, f32, vp, vp, vp, vp, vp]),
     "nb_group_num_variants": (i32, [vp, C.POINTER(C.c_int)]),

@@ -107,6 +107,7 @@ class GroupWorkload:
     adapt_iters: int = 400
     patience: int = 6
     lr_decay: float = 1.0
+    cont_batch: int = 0        # per-object batch of the continuation (0: per_obj)
 
     @property
     def seeds(self):

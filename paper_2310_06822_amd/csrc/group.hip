@@ -317,8 +317,12 @@ __global__ __launch_bounds__(256) void k_group_reduce(const float* __restrict__ 
                                                       const int64_t* __restrict__ poff, const int* __restrict__ widths,
                                                       int in_dim, int NH, float* __restrict__ theta,
                                                       float* __restrict__ m, float* __restrict__ v, AdamArgs adam,
-                                                      const float* __restrict__ lr_obj) {
+                                                      const float* __restrict__ lr_obj,
+                                                      const uint8_t* __restrict__ active) {
   const int o = blockIdx.y;
+  // an object outside the trained set has no partials this step; a learning
+  // rate of 0 freezes it
+  if (!active[o] || (lr_obj && lr_obj[o] == 0.0f)) return;
   const int64_t Po = poff[o + 1] - poff[o];
   const int64_t pl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (pl >= Po) return;
@@ -336,9 +340,10 @@ __global__ __launch_bounds__(256) void k_group_reduce(const float* __restrict__ 
 
 // Per-object mean loss and confusion counts of a grouped training step.
 __global__ void k_group_aux(const float* __restrict__ aux, int n_wg, int n_obj, float loss_scale,
-                            float* __restrict__ loss, unsigned long long* __restrict__ counts) {
+                            const uint8_t* __restrict__ active, float* __restrict__ loss,
+                            unsigned long long* __restrict__ counts) {
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= n_obj) return;
+  if (o >= n_obj || !active[o]) return;
   float ls = 0.0f;
   unsigned long long cs[4] = {0, 0, 0, 0};
   const float* a = aux + (int64_t)o * n_wg * 8;
@@ -359,11 +364,11 @@ nb_status group_reduce_adam(const nb_group* gr, int n_wg, const AdamArgs& adam, 
                             unsigned long long* counts, float loss_scale, hipStream_t s) {
   const dim3 grid((unsigned)((gr->max_obj_params + 255) / 256), (unsigned)gr->n_obj);
   k_group_reduce<<<grid, 256, 0, s>>>(gr->partial, n_wg, gr->d_poff, gr->d_widths, gr->in_dim, gr->n_hidden, gr->theta,
-                                      gr->m, gr->v, adam, lr_obj);
+                                      gr->m, gr->v, adam, lr_obj, gr->d_active);
   NB_LAUNCHED();
   if (loss || counts) {
-    k_group_aux<<<(unsigned)((gr->n_obj + 255) / 256), 256, 0, s>>>(gr->aux, n_wg, gr->n_obj, loss_scale, loss,
-                                                                   counts);
+    k_group_aux<<<(unsigned)((gr->n_obj + 255) / 256), 256, 0, s>>>(gr->aux, n_wg, gr->n_obj, loss_scale,
+                                                                   gr->d_active, loss, counts);
     NB_LAUNCHED();
   }
   return NB_OK;

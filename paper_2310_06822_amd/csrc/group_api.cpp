@@ -53,6 +53,7 @@ nb_status nb_group_destroy(nb_group* g) {
   free_p(g->d_ptoff);
   free_p(g->d_perm);
   free_p(g->d_class);
+  free_p(g->d_active);
   free_p(g->theta);
   free_p(g->m);
   free_p(g->v);
@@ -115,10 +116,12 @@ nb_status nb_group_create(int n_obj, int in_dim, const int* widths_host, int n_h
   std::iota(perm.begin(), perm.end(), 0);
   std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return g->widths[a] > g->widths[b]; });
   g->classes.assign(3, {});
+  g->class_all.assign(3, 0);
   std::vector<int> cls;
   for (int c = 0; c < 3; ++c) {
     for (int o = 0; o < n_obj; ++o)
       if (g->widths[o] == kClassWidths[c]) g->classes[c].push_back(o);
+    g->class_all[c] = (int)g->classes[c].size();
     cls.insert(cls.end(), g->classes[c].begin(), g->classes[c].end());
   }
   g->n_wg_cap = std::max(1, std::min(4 * nb_cu_count(), 1 << 14));
@@ -128,6 +131,7 @@ nb_status nb_group_create(int n_obj, int in_dim, const int* widths_host, int n_h
   if (st == NB_OK) st = upload(&g->d_ptoff, g->ptoff);
   if (st == NB_OK) st = upload(&g->d_perm, perm);
   if (st == NB_OK) st = upload(&g->d_class, cls);
+  if (st == NB_OK) st = upload(&g->d_active, std::vector<uint8_t>(n_obj, 1));
   if (st == NB_OK) st = alloc_n(&g->theta, (size_t)g->n_params);
   if (st == NB_OK) st = alloc_n(&g->m, (size_t)g->n_params);
   if (st == NB_OK) st = alloc_n(&g->v, (size_t)g->n_params);
@@ -212,6 +216,24 @@ nb_status nb_group_set_voxels(nb_group* g, const uint8_t* grids, const int* n_ho
   return NB_OK;
 }
 
+nb_status nb_group_set_active(nb_group* g, const uint8_t* active_host) {
+  NB_REQUIRE(g, "group is NULL");
+  std::vector<int> cls;
+  for (int c = 0; c < 3; ++c) {
+    g->classes[c].clear();
+    for (int o = 0; o < g->n_obj; ++o)
+      if (g->widths[o] == kClassWidths[c] && (!active_host || active_host[o])) g->classes[c].push_back(o);
+    cls.insert(cls.end(), g->classes[c].begin(), g->classes[c].end());
+  }
+  if (!cls.empty())
+    NB_HIP(hipMemcpy(g->d_class, cls.data(), cls.size() * sizeof(int), hipMemcpyHostToDevice));
+  std::vector<uint8_t> act(g->n_obj, 1);
+  if (active_host)
+    for (int o = 0; o < g->n_obj; ++o) act[o] = active_host[o] ? 1 : 0;
+  NB_HIP(hipMemcpy(g->d_active, act.data(), act.size(), hipMemcpyHostToDevice));
+  return NB_OK;
+}
+
 nb_status nb_group_set_box_method(nb_group* g, int method) {
   NB_REQUIRE(g, "group is NULL");
   NB_REQUIRE(method == 0 || method == 1, "box method must be 0 (scan) or 1 (count table)");
@@ -283,7 +305,7 @@ nb_status nb_group_train_step(nb_group* g, int kind, uint64_t seed, uint64_t ste
     g->tr_per_obj = 0;
     int64_t ws = 0;
     for (int c = 0; c < 3; ++c)
-      ws += (int64_t)g->classes[c].size() * (g->n_hidden + 1) * plan.padded * kClassWidths[c];
+      ws += (int64_t)g->class_all[c] * (g->n_hidden + 1) * plan.padded * kClassWidths[c];
     NB_TRY(alloc_n(&g->partial, (size_t)plan.n_wg * g->n_params));
     NB_TRY(alloc_n(&g->aux, (size_t)g->n_obj * plan.n_wg * 8));
     NB_TRY(alloc_n(&g->tr_ws, (size_t)ws));

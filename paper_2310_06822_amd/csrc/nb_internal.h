@@ -109,7 +109,9 @@ struct nb_group {
   std::vector<int64_t> poff;        // parameter offsets [n_obj + 1]
   std::vector<int64_t> pkoff;       // forward-pack offsets, 16-byte slices [n_obj + 1]
   std::vector<int64_t> ptoff;       // transposed-pack offsets, 16-byte slices [n_obj + 1]
-  std::vector<std::vector<int>> classes;   // object ids per width class (32, 64, 128)
+  std::vector<std::vector<int>> classes;   // trained object ids per width class (32, 64, 128)
+  std::vector<int> class_all;              // objects per width class (work-space sizing)
+  uint8_t* d_active = nullptr;             // [n_obj]: 1 for objects the training step updates
   int* d_widths = nullptr;
   int64_t* d_poff = nullptr;
   int64_t* d_pkoff = nullptr;

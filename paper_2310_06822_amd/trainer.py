@@ -49,6 +49,9 @@ class Schedule:
     # inverted ("certainly hit") bound: the FP weight follows the schedule and
     # the continuation counts false positives, so h = 1 implies g = 1
     inverted: bool = False
+    # groups: per-object batch of the continuation (0: the ramp's), which
+    # trains only the objects still in training
+    cont_batch: int = 0
 
 
 @dataclass
@@ -181,7 +184,7 @@ def train_group(group, kind: str, seed: int, sched: Schedule, val_seed: int | No
     sched.batch is the per-object batch."""
     import numpy as np
 
-    from . import nb_group_train_step
+    from . import nb_group_set_active, nb_group_train_step
     k = KINDS[kind]
     res = GroupTrainResult()
     torch.cuda.synchronize()
@@ -195,6 +198,7 @@ def train_group(group, kind: str, seed: int, sched: Schedule, val_seed: int | No
         if log and (t + 1) % 1000 == 0:
             torch.cuda.synchronize()
             log(f"group ramp step {t + 1}/{T}: alpha {a:g}")
+    samples = step * sched.batch * group.n_obj
     alpha = np.full(group.n_obj, sched.alpha_max, dtype=np.float32)
     lr = np.full(group.n_obj, sched.lr, dtype=np.float32)
     clean = np.zeros(group.n_obj, dtype=np.int64)
@@ -206,10 +210,13 @@ def train_group(group, kind: str, seed: int, sched: Schedule, val_seed: int | No
         lr_dev = torch.from_numpy(lr).cuda()
         while clean_all < sched.patience and res.iters < sched.max_iters:
             if (lr > 0).any():
+                # only the objects still training are evaluated and updated
+                nb_group_set_active(group.handle, (lr > 0).astype(np.uint8))
                 for _ in range(sched.k):
-                    nb_group_train_step(group.handle, group.n_obj, k, seed, step, sched.batch, 0.0, sched.beta,
-                                        sched.lr, alpha_obj=a_dev, lr_obj=lr_dev)
+                    nb_group_train_step(group.handle, group.n_obj, k, seed, step, sched.cont_batch or sched.batch,
+                                        0.0, sched.beta, sched.lr, alpha_obj=a_dev, lr_obj=lr_dev)
                     step += 1
+                samples += sched.k * (sched.cont_batch or sched.batch) * int((lr > 0).sum())
             lr_now = max(sched.lr_min, lr_now * sched.lr_decay)
             val = group_validation_set(group, kind, val_seed, sched.val_n, draw=res.iters, out=val)
             fn = group.counts(*val)[:, 3].cpu().numpy()
@@ -229,10 +236,11 @@ def train_group(group, kind: str, seed: int, sched: Schedule, val_seed: int | No
                 log(f"group schedule iteration {res.iters}: step {step}, validation FN {int(fn.sum())} over "
                     f"{int(bad.sum())} objects, {int((lr > 0).sum())} training, alpha max {alpha.max():g}")
         res.converged = clean_all >= sched.patience
+        nb_group_set_active(group.handle, None)
     torch.cuda.synchronize()
     res.seconds = time.perf_counter() - t0
     res.steps = step
-    res.samples = step * sched.batch * group.n_obj
+    res.samples = samples
     res.alpha_final = float(alpha.max())
     res.alpha_obj = alpha.tolist()
     return res

@@ -267,3 +267,28 @@ def test_group_forward_skips_objects_outside_the_batch():
     s = mlp.abs_forward(thetas[0], 6, [64] * 3, q[:150], bf16=True)
     assert np.all(np.abs(z[:150] - ref) <= 1e-3 * np.maximum(np.abs(ref), s))
     assert np.all(z[150:] == -3.0)
+
+
+def test_group_active_subset():
+    """Training only a subset: the others stay bit for bit (and their loss
+    entries unwritten); the trained ones match a run that trains everyone."""
+    widths, nh, sizes = [64, 32, 128, 64], 3, [64, 32, 32, 64]
+    grids = _objects(81, sizes)
+    outs = []
+    for subset in (None, [1, 0, 1, 0]):
+        gr, thetas = _group(6, widths, nh, 810)
+        gr.set_voxels(cuda(np.concatenate(grids)), sizes)
+        nb.nb_group_set_active(gr.handle, subset)
+        loss = torch.full((4,), -1.0, dtype=torch.float32, device="cuda")
+        for t in range(2):
+            nb.nb_group_train_step(gr.handle, 4, nb.BOX, 12, t, 2000, 5.0, loss=loss)
+        outs.append((host(gr.params()), host(loss), gr.offsets.copy(), thetas))
+    (th_all, l_all, off, thetas), (th_sub, l_sub, _, _) = outs
+    for o in range(4):
+        a, b = off[o], off[o + 1]
+        if o in (1, 3):
+            assert np.array_equal(th_sub[a:b], thetas[o].astype(np.float32)), o
+            assert l_sub[o] == -1.0
+        else:
+            assert np.array_equal(bits(th_sub[a:b]), bits(th_all[a:b])), o
+            assert l_sub[o] == l_all[o]
