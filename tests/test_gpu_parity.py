@@ -636,3 +636,32 @@ def test_sine_unsupported_shapes():
     b = nb.Bound(3, 4, 64)
     with pytest.raises(nb.NBError):
         nb.nb_bound_set_activation(b.handle, nb.SINE)
+
+
+def test_trained_bound_gain_over_exact_test_alone(c2_grid):
+    """What the learned part buys (Sec. 6): a bound trained on the device with
+    Alg. 1 (ramp + step-wise schedule) is conservative on held-out queries, so
+    the cascade returns exactly the exact test's answers while running the
+    exact test on a small fraction of the queries; without the bound every
+    query needs the exact test."""
+    from paper_2310_06822_amd import trainer
+    _, _, grid = c2_grid
+    ind = nb.Indicator.voxels(cuda(grid), 128)
+    b = nb.Bound(3, 3, 64, nb.F32)
+    b.set_params(synth.init_params(4001, 3, [64] * 3))
+    sched = trainer.Schedule(steps=5000, batch=1 << 16, alpha_max=100.0, k=250, inc=50.0, max_iters=200,
+                             val_n=1 << 22)
+    res = trainer.train(b, ind, "point", 2001, sched, val_seed=5001)
+    n = 1 << 22
+    q = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    nb.nb_sample_queries(nb.POINT, 3, 3001, 0, q)
+    g = ind.query("point", q)
+    ans = torch.empty(n, dtype=torch.uint8, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    nb.nb_cascade(b.handle, ind.handle, nb.POINT, q, ans, cnt)
+    n_exact = int(host(cnt)[0])
+    positives = int(host(g).sum())
+    assert res.converged
+    assert torch.equal(ans, g)                  # conservative: the cascade is the exact test
+    assert n_exact < 0.25 * n                   # the exact test runs on under a quarter of the queries
+    assert n_exact >= positives                 # (it still sees every true hit)
