@@ -80,7 +80,15 @@ VOXEL3D_POINT_SINE = Workload("voxel3d_point_sine", 1, "point", 3, 3, 64, 2, "f3
                               train_steps=5000, batch=1 << 16, eval_n=1 << 24, act="sine", real_width=50,
                               bench_also=True)
 
-WORKLOADS = {w.name: w for w in (DISC2D_POINT, VOXEL3D_POINT, VOXEL3D_RAY, METABALL4D_POINT, VOXEL3D_POINT_SINE)}
+# Plane queries (Sec. 4.2 "Query types") over the 3-D point workload's grid,
+# with the ray workload's network: p0 uniform in the cube, unit normal
+# uniform on the sphere.
+VOXEL3D_PLANE = Workload("voxel3d_plane", 5, "plane", 3, 6, 128, 4, "bf16",
+                         scene={"type": "metaball_voxels", "k": 16, "n": 128, "rlo": 0.05, "rhi": 0.25, "seed_of": 1},
+                         train_steps=5000, batch=1 << 18, eval_n=1 << 24, lr_decay=0.99, bench_also=True)
+
+WORKLOADS = {w.name: w for w in (DISC2D_POINT, VOXEL3D_POINT, VOXEL3D_RAY, METABALL4D_POINT, VOXEL3D_POINT_SINE,
+                                 VOXEL3D_PLANE)}
 
 
 @dataclass(frozen=True)

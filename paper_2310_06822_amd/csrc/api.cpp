@@ -175,6 +175,18 @@ nb_status nb_indicator_voxels(const uint8_t* grid, int n, nb_indicator** out) {
   if (st == NB_OK) st = dev_alloc(&ind->ray_t, 256);
   if (st == NB_OK) st = dev_alloc(&ind->occupied, (size_t)cells);
   if (st == NB_OK) st = dev_alloc(&ind->occupied_count, 1);
+  ind->mask_words = (n + 63) / 64;
+  if (st == NB_OK) st = dev_alloc(&ind->centre, (size_t)n);
+  if (st == NB_OK) st = dev_alloc(&ind->colmask, (size_t)3 * n * n * ind->mask_words);
+  if (st == NB_OK) {
+    // cell centres, computed in double and rounded once (the plane query's)
+    std::vector<float> c((size_t)n);
+    for (int i = 0; i < n; ++i) c[(size_t)i] = (float)((2.0 * i + 1.0) / n - 1.0);
+    if (hipMemcpy(ind->centre, c.data(), sizeof(float) * n, hipMemcpyHostToDevice) != hipSuccess) {
+      nb_set_error("hipMemcpy of the cell centres failed");
+      st = NB_ERR_HIP;
+    }
+  }
   if (st == NB_OK) {
     // ray sample parameters t_j = 4 j / 255, computed in double and rounded once
     float t[256];
@@ -186,6 +198,7 @@ nb_status nb_indicator_voxels(const uint8_t* grid, int n, nb_indicator** out) {
     }
   }
   if (st == NB_OK) st = launch_collect_occupied(ind->grid, cells, ind->occupied, ind->occupied_count, nullptr);
+  if (st == NB_OK) st = launch_column_masks(ind->grid, n, ind->mask_words, ind->colmask, nullptr);
   if (st == NB_OK && hipDeviceSynchronize() != hipSuccess) {
     nb_set_error("building the occupied-cell list failed");
     st = NB_ERR_HIP;
@@ -242,6 +255,8 @@ nb_status nb_indicator_destroy(nb_indicator* ind) {
   dev_free(ind->ray_t);
   dev_free(ind->occupied);
   dev_free(ind->occupied_count);
+  dev_free(ind->centre);
+  dev_free(ind->colmask);
   delete ind;
   return NB_OK;
 }

@@ -28,11 +28,15 @@ struct IndView {
   const float* ray_t;
   const int32_t* occupied;
   const int64_t* occupied_count;
+  const float* centre;
+  const uint64_t* colmask;
+  int mask_words;
 };
 
 IndView view_of(const nb_indicator* ind) {
-  return IndView{ind->type, ind->k, ind->n, ind->iso, ind->params, ind->grid, ind->ray_t, ind->occupied,
-                 ind->occupied_count};
+  return IndView{ind->type,     ind->k,        ind->n,          ind->iso,      ind->params,
+                 ind->grid,     ind->ray_t,    ind->occupied,   ind->occupied_count,
+                 ind->centre,   ind->colmask,  ind->mask_words};
 }
 
 // ------------------------------------------------------------------- points
@@ -69,24 +73,167 @@ __device__ __forceinline__ uint8_t metaballs4d_at(const float* __restrict__ row,
 
 // ------------------------------------------------------------------- planes
 
-// g = 1 iff an occupied cell (centre c, half width 1/n) meets the plane:
-// |n.(c - p0)| <= (1/n) (|n_x| + |n_y| + |n_z|), dot product summed x, y, z.
-__device__ __forceinline__ uint8_t voxel_plane_at(const float* __restrict__ row, const int32_t* __restrict__ occ,
-                                                  const int64_t* __restrict__ n_occ, int gn) {
-  const float px = row[0], py = row[1], pz = row[2], nx = row[3], ny = row[4], nz = row[5];
-  const float h = (float)(1.0 / (double)gn);
-  const float rad = h * ((fabsf(nx) + fabsf(ny)) + fabsf(nz));
-  const int64_t m = *n_occ;
-  for (int64_t c = 0; c < m; ++c) {
-    const int32_t idx = occ[c];
-    const int ix = idx % gn, jy = (idx / gn) % gn, kz = idx / (gn * gn);
-    const float cx = (float)((2.0 * ix + 1.0) / gn - 1.0);
-    const float cy = (float)((2.0 * jy + 1.0) / gn - 1.0);
-    const float cz = (float)((2.0 * kz + 1.0) / gn - 1.0);
-    const float e = (nx * (cx - px) + ny * (cy - py)) + nz * (cz - pz);
-    if (fabsf(e) <= rad) return 1;
+// The definition: g = 1 iff an occupied cell (centre c, half width h = 1/n)
+// meets the plane through p0 with normal m, i.e.
+//   |m.(c - p0)| <= h (|m_x| + |m_y| + |m_z|)
+// (the plane / axis-aligned box overlap test), the dot product summed x, y, z
+// in float32 and the centres c = (2i + 1)/n - 1 rounded once from double.
+//
+// Evaluating that over every occupied cell costs O(n^3).  The query below
+// is O(n^2) and gives the same answer bit for bit: along the dominant axis a
+// of m (|m_a| = max), each column of cells (fixed coordinates on the two
+// other axes) meets the slab |m.(c - p0)| <= rad in an interval of at most
+// about four cells.  For every column the interval is computed in double,
+// widened by a bound on the float32 rounding error of the predicate (so it
+// holds every cell for which the float32 predicate can be true) and by one
+// cell; its occupied cells come from the column's occupancy bits, and each
+// is then tested with the float32 predicate itself.  One wave takes one
+// plane; its lanes take the columns in a scattered order (a plane that meets
+// the object is usually settled in the first pass of 64 columns) and stop
+// together at the first hit.  Planes with a non-finite value or a normal
+// whose largest component is outside [2^-60, 2^60] (where the error bound
+// would not hold) take the plain loop over the occupied-cell list instead.
+
+struct PlaneRow {
+  float px, py, pz, mx, my, mz, rad;
+};
+
+__device__ __forceinline__ bool plane_meets(const PlaneRow& r, const float* __restrict__ centre, int ix, int jy,
+                                            int kz) {
+  const float cx = centre[ix], cy = centre[jy], cz = centre[kz];
+  const float e = (r.mx * (cx - r.px) + r.my * (cy - r.py)) + r.mz * (cz - r.pz);
+  return fabsf(e) <= r.rad;
+}
+
+__device__ __forceinline__ float pick3(int a, float x, float y, float z) { return a == 0 ? x : (a == 1 ? y : z); }
+
+// The definition over the occupied-cell list, one wave per plane.
+__device__ uint8_t plane_wave_list(const IndView& v, const PlaneRow& r, int lane) {
+  const int gn = v.n;
+  const int64_t m = *v.occupied_count;
+  for (int64_t base = 0; base < m; base += 64) {
+    const int64_t c = base + lane;
+    bool hit = false;
+    if (c < m) {
+      const int32_t idx = v.occupied[c];
+      hit = plane_meets(r, v.centre, idx % gn, (idx / gn) % gn, idx / (gn * gn));
+    }
+    if (__ballot(hit)) return 1;
   }
   return 0;
+}
+
+__device__ uint8_t plane_wave(const IndView& v, const float* __restrict__ row, int lane) {
+  PlaneRow r;
+  r.px = row[0];
+  r.py = row[1];
+  r.pz = row[2];
+  r.mx = row[3];
+  r.my = row[4];
+  r.mz = row[5];
+  const int gn = v.n;
+  const float h = (float)(1.0 / (double)gn);
+  r.rad = h * ((fabsf(r.mx) + fabsf(r.my)) + fabsf(r.mz));
+  const float ax = fabsf(r.mx), ay = fabsf(r.my), az = fabsf(r.mz);
+  const int a = (az > ax && az > ay) ? 2 : (ay > ax ? 1 : 0);   // dominant axis (lowest on ties)
+  const float amax = pick3(a, ax, ay, az);
+  const bool regular = amax >= 0x1p-60f && amax <= 0x1p60f && isfinite(r.px) && isfinite(r.py) &&
+                       isfinite(r.pz) && isfinite(r.mx) && isfinite(r.my) && isfinite(r.mz);
+  if (!regular) return plane_wave_list(v, r, lane);
+
+  const int sa = a == 0 ? 1 : 0, ta = a == 2 ? 1 : 2;   // the two other axes, increasing
+  const double u = 0x1p-24;
+  const double S = (double)ax * (1.0 + fabs((double)r.px)) + (double)ay * (1.0 + fabs((double)r.py)) +
+                   (double)az * (1.0 + fabs((double)r.pz));
+  // |float32 e - exact e| <= 5 u S (+ subnormal terms); 16 u S + 2^-140 covers it
+  const double err = 16.0 * u * S + 0x1p-140;
+  const double N = (double)gn;
+  const double ma = pick3(a, r.mx, r.my, r.mz), ms = pick3(sa, r.mx, r.my, r.mz), mt = pick3(ta, r.mx, r.my, r.mz);
+  const double pa = pick3(a, r.px, r.py, r.pz), ps = pick3(sa, r.px, r.py, r.pz), pt = pick3(ta, r.px, r.py, r.pz);
+  // centre of the interval, in cell units along a, as K0 + s Ks + t Kt
+  const double Ks = -ms / ma, Kt = -mt / ma;
+  const double K0 = ((pa + 1.0) * N - 1.0) * 0.5 - (N / (2.0 * ma)) * (ms * (1.0 / N - 1.0 - ps) +
+                                                                         mt * (1.0 / N - 1.0 - pt));
+  const double Kw = ((double)r.rad + err) * N / (2.0 * fabs(ma)) + 1.0;
+
+  const int cols = gn * gn;
+  // scattered column order: col -> col * P mod n^2 with P a prime above
+  // 1024 (a bijection, since n <= 1024)
+  const int P = 40009;
+  const int step = (int)((64ll * P) % cols);
+  int col = (int)(((int64_t)lane * P) % cols);
+  const float inv_n = 1.0f / (float)gn;
+  const uint64_t* mask_a = v.colmask + (size_t)a * cols * v.mask_words;
+  for (int base = 0; base < cols; base += 64) {
+    bool hit = false;
+    if (base + lane < cols) {
+      int t = (int)((float)col * inv_n);
+      int s = col - t * gn;
+      if (s < 0) { s += gn; --t; }
+      if (s >= gn) { s -= gn; ++t; }
+      const double kc = fma((double)t, Kt, fma((double)s, Ks, K0));
+      const double lo_d = fmax(floor(kc - Kw), 0.0), hi_d = fmin(ceil(kc + Kw), N - 1.0);
+      if (lo_d <= hi_d) {
+        const int lo = (int)lo_d, hi = (int)hi_d;
+        const uint64_t* colbits = mask_a + ((size_t)t * gn + s) * v.mask_words;
+        for (int w = lo >> 6; w <= (hi >> 6) && !hit; ++w) {
+          uint64_t bits = colbits[w];
+          const int b0 = w * 64;
+          if (lo > b0) bits &= ~0ull << (lo - b0);
+          if (hi - b0 < 63) bits &= (2ull << (hi - b0)) - 1ull;
+          while (bits && !hit) {
+            const int k = b0 + __builtin_ctzll(bits);
+            bits &= bits - 1ull;
+            const int ix = a == 0 ? k : s;
+            const int jy = a == 1 ? k : (a == 0 ? s : t);
+            const int kz = a == 2 ? k : t;
+            hit = plane_meets(r, v.centre, ix, jy, kz);
+          }
+        }
+      }
+    }
+    if (__ballot(hit)) return 1;
+    col += step;
+    if (col >= cols) col -= cols;
+  }
+  return 0;
+}
+
+// g[i] (or answer[idx[t]] for a listed subset) for plane queries, one wave
+// per plane, grid-stride over planes.
+template <bool LISTED>
+__global__ __launch_bounds__(256) void k_plane_exact(IndView v, const float* __restrict__ q, int64_t n,
+                                                     const int32_t* __restrict__ idx,
+                                                     const unsigned long long* __restrict__ count,
+                                                     uint8_t* __restrict__ g) {
+  const int lane = threadIdx.x & 63;
+  const int64_t m = LISTED ? (int64_t)*count : n;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < m; t += waves) {
+    const int64_t i = LISTED ? (int64_t)idx[t] : t;
+    const uint8_t hit = plane_wave(v, q + 6 * i, lane);
+    if (lane == 0) g[i] = hit;
+  }
+}
+
+// Column occupancy bits for the plane query (layout in nb_indicator).
+__global__ void k_column_masks(const uint8_t* __restrict__ grid, int gn, int words, uint64_t* __restrict__ mask) {
+  const int64_t total = 3ll * gn * gn * words;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= total) return;
+  const int w = (int)(id % words);
+  const int64_t col = id / words;
+  const int s = (int)(col % gn), t = (int)((col / gn) % gn), a = (int)(col / ((int64_t)gn * gn));
+  uint64_t bits = 0;
+  for (int b = 0; b < 64; ++b) {
+    const int c = 64 * w + b;
+    if (c >= gn) break;
+    const int i = a == 0 ? c : s;
+    const int j = a == 0 ? s : (a == 1 ? c : t);
+    const int k = a == 2 ? c : t;
+    if (grid[((int64_t)k * gn + j) * gn + i]) bits |= 1ull << b;
+  }
+  mask[id] = bits;
 }
 
 // ------------------------------------------------------------- dispatch
@@ -99,9 +246,9 @@ __device__ __forceinline__ uint8_t exact_at(const IndView& v, const float* __res
     const float* r = q + 3 * i;
     return voxel_at(v.grid, v.n, (float)v.n * 0.5f, r[0], r[1], r[2]);
   }
+  static_assert(KIND != NB_QUERY_PLANE, "plane queries run one wave per plane (k_plane_exact)");
   if (KIND == NB_QUERY_RAY) return voxel_ray_at(q + 6 * i, v.grid, v.n, v.ray_t);
-  if (KIND == NB_QUERY_BOX) return voxel_box_at(q + 6 * i, v.grid, v.n);
-  return voxel_plane_at(q + 6 * i, v.occupied, v.occupied_count, v.n);
+  return voxel_box_at(q + 6 * i, v.grid, v.n);
 }
 
 template <int KIND>
@@ -217,6 +364,11 @@ __global__ void k_collect_occupied(const uint8_t* __restrict__ grid, int64_t cel
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
+// one wave per plane, grid-stride beyond 2^16 blocks (2^18 waves)
+inline unsigned plane_blocks(int64_t n) {
+  return (unsigned)std::min<int64_t>((n + kThreads / 64 - 1) / (kThreads / 64), 65536);
+}
+
 }  // namespace
 
 nb_status launch_query_exact(const nb_indicator* ind, int kind, const float* q, int64_t n, uint8_t* g,
@@ -232,7 +384,9 @@ nb_status launch_query_exact(const nb_indicator* ind, int kind, const float* q, 
     case NB_QUERY_POINT: k_exact<NB_QUERY_POINT><<<blocks, kThreads, 0, s>>>(v, q, n, g); break;
     case NB_QUERY_RAY: k_exact<NB_QUERY_RAY><<<blocks, kThreads, 0, s>>>(v, q, n, g); break;
     case NB_QUERY_BOX: k_exact<NB_QUERY_BOX><<<blocks, kThreads, 0, s>>>(v, q, n, g); break;
-    case NB_QUERY_PLANE: k_exact<NB_QUERY_PLANE><<<blocks, kThreads, 0, s>>>(v, q, n, g); break;
+    case NB_QUERY_PLANE:
+      k_plane_exact<false><<<plane_blocks(n), kThreads, 0, s>>>(v, q, n, nullptr, nullptr, g);
+      break;
     default: NB_REQUIRE(false, "unknown query kind %d", kind);
   }
   NB_LAUNCHED();
@@ -257,7 +411,9 @@ nb_status launch_cascade_exact(const nb_indicator* ind, int kind, const float* q
     case NB_QUERY_POINT: k_cascade_exact<NB_QUERY_POINT><<<blocks, kThreads, 0, s>>>(v, q, idx, count, answer); break;
     case NB_QUERY_RAY: k_cascade_exact<NB_QUERY_RAY><<<blocks, kThreads, 0, s>>>(v, q, idx, count, answer); break;
     case NB_QUERY_BOX: k_cascade_exact<NB_QUERY_BOX><<<blocks, kThreads, 0, s>>>(v, q, idx, count, answer); break;
-    case NB_QUERY_PLANE: k_cascade_exact<NB_QUERY_PLANE><<<blocks, kThreads, 0, s>>>(v, q, idx, count, answer); break;
+    case NB_QUERY_PLANE:
+      k_plane_exact<true><<<plane_blocks(n), kThreads, 0, s>>>(v, q, n, idx, count, answer);
+      break;
     default: NB_REQUIRE(false, "unknown query kind %d", kind);
   }
   NB_LAUNCHED();
@@ -274,6 +430,12 @@ nb_status launch_voxelize(const float* params_dev, int k, float iso, int n, uint
 nb_status launch_collect_occupied(const uint8_t* grid, int64_t cells, int32_t* out, int64_t* count_dev,
                                   hipStream_t s) {
   k_collect_occupied<<<1, kThreads, 0, s>>>(grid, cells, out, count_dev);
+  NB_LAUNCHED();
+  return NB_OK;
+}
+
+nb_status launch_column_masks(const uint8_t* grid, int n, int words, uint64_t* mask, hipStream_t s) {
+  k_column_masks<<<blocks_for(3ll * n * n * words), kThreads, 0, s>>>(grid, n, words, mask);
   NB_LAUNCHED();
   return NB_OK;
 }

@@ -57,6 +57,12 @@ struct nb_indicator {
   float* ray_t = nullptr;        // 256 sample parameters of the ray query
   int32_t* occupied = nullptr;        // linear indices of occupied cells (plane query)
   int64_t* occupied_count = nullptr;  // device int64: number of entries in `occupied`
+  // plane query: cell centres (2i + 1)/n - 1 rounded to float, [n]; column
+  // occupancy bits, [3][n][n][mask_words] (axis, then the two other axes
+  // in increasing order, the higher one outer), bit b of word w = cell 64 w + b
+  float* centre = nullptr;
+  uint64_t* colmask = nullptr;
+  int mask_words = 0;
 };
 
 struct nb_bound {
@@ -163,6 +169,7 @@ nb_status launch_cascade_exact(const nb_indicator* ind, int kind, const float* q
 nb_status launch_compact_positive(const uint8_t* h, int64_t n, int32_t* idx, unsigned long long* count, hipStream_t s);
 nb_status launch_collect_occupied(const uint8_t* grid, int64_t cells, int32_t* out, int64_t* count_dev,
                                   hipStream_t s);
+nb_status launch_column_masks(const uint8_t* grid, int n, int words, uint64_t* mask, hipStream_t s);
 
 // mlp_f32.hip
 bool f32_supported(int in_dim, int n_hidden, int width);

@@ -127,6 +127,68 @@ def test_exact_planes():
     assert 0.05 < ref.mean() < 0.95
 
 
+def _plane_edge_cases(n, seed):
+    """Planes that stress the column search of the plane test: far-away
+    points p0 (on and off the cube), scaled normals (tiny, huge, subnormal
+    components, zero), axis-aligned planes on cell faces (|e| = rad exactly),
+    ties between normal components, non-finite values, and planes through the
+    cube whose p0 lies up to 1e7 away along the plane (large rounding error
+    in the float32 predicate)."""
+    g = np.random.default_rng(seed)
+    base = synth.planes(seed, 40)
+    rows = list(base)
+    for sc in (1e3, 1e6, 1e20):
+        b = base[:8].copy()
+        b[:, :3] *= sc
+        rows += list(b)
+    for sc in (1e-3, 1e5, 1e-20, 1e20, 2.0 ** -70):
+        b = base[8:14].copy()
+        b[:, 3:] *= sc
+        rows += list(b)
+    for ax in range(3):
+        for f in range(0, n + 1, max(1, n // 5)):
+            x = np.float32(-1.0 + 2.0 * f / n)
+            r = [0.0] * 6
+            r[ax], r[3 + ax] = x, 1.0
+            rows.append(r)
+            r = [0.0] * 6
+            r[ax], r[3 + ax], r[3 + (ax + 1) % 3] = x, -0.5, 1e-30
+            rows.append(r)
+    for lam in (1e3, 1e4, 1e5, 1e6, 1e7):
+        for _ in range(6):
+            nrm = g.normal(size=3)
+            nrm /= np.linalg.norm(nrm)
+            tv = np.cross(nrm, g.normal(size=3))
+            tv /= np.linalg.norm(tv)
+            rows.append(list(g.uniform(-0.8, 0.8, 3) + lam * tv) + list(nrm))
+    rows += [[0.1, 0.2, 0.3, 0.7071, 0.7071, 0.0], [0.1, 0.2, -0.3, 0.577, -0.577, 0.577],
+             [0.0, 0.0, 0.0, 1e-40, 1.0, 1e-42], [0.3, 0.3, 0.3, 0.0, 0.0, 0.0],
+             [np.nan, 0, 0, 0, 0, 1], [0, 0, 0, np.inf, 0, 1], [np.inf, 0, 0, 1, 0, 0],
+             [1.5, 0, 0, 1, 0, 0], [-1.0, 0.0, 0.0, 1, 0, 0], [1.0, 0, 0, -1, 0, 0]]
+    return np.asarray(rows, dtype=np.float32)
+
+
+@pytest.mark.parametrize("n,k", [(16, 6), (33, 8), (64, 12), (128, 16)])
+def test_exact_planes_edge_cases(n, k):
+    c, r = synth.metaballs3d(50 + n, k=k, rlo=0.05, rhi=0.25)
+    grid = I.voxelize_metaballs(c, r, n)
+    ind = nb.Indicator.voxels(cuda(grid), n)
+    q = _plane_edge_cases(n, n)
+    with np.errstate(invalid="ignore", over="ignore"):
+        ref = I.voxel_planes(q, grid, n)
+    assert np.array_equal(host(ind.query("plane", cuda(q))), ref)
+    assert 0.2 < ref.mean() < 0.9
+
+
+def test_exact_planes_empty_and_full_grids():
+    q = synth.planes(12, 777)
+    empty = nb.Indicator.voxels(cuda(np.zeros(20 ** 3, np.uint8)), 20)
+    assert host(empty.query("plane", cuda(q))).sum() == 0
+    full = np.ones(20 ** 3, np.uint8)
+    ind = nb.Indicator.voxels(cuda(full), 20)
+    assert np.array_equal(host(ind.query("plane", cuda(q))), I.voxel_planes(q, full, 20))
+
+
 def test_exact_metaballs4d():
     a, b, r = synth.metaballs4d(1004)
     ind = nb.Indicator.metaballs4d(a, b, r)
@@ -312,7 +374,8 @@ def test_train_steps_parity(cfg, c2_grid):
 
 # ------------------------------------------------------------------ cascade
 
-@pytest.mark.parametrize("kind,prec", [("point", nb.F32), ("ray", nb.BF16), ("box", nb.BF16), ("point", nb.BF16)])
+@pytest.mark.parametrize("kind,prec", [("point", nb.F32), ("ray", nb.BF16), ("box", nb.BF16), ("point", nb.BF16),
+                                       ("plane", nb.BF16)])
 def test_cascade(kind, prec, c2_grid):
     _, _, grid = c2_grid
     ind = nb.Indicator.voxels(cuda(grid), 128)
@@ -322,9 +385,9 @@ def test_cascade(kind, prec, c2_grid):
     else:
         width, nh = 128, 4
     theta = synth.init_params(90, in_dim, [width] * nh)
-    n = 20011
+    n = 3001 if kind == "plane" else 20011
     q = {"point": lambda: synth.points(91, n, 3), "ray": lambda: synth.rays(92, n),
-         "box": lambda: synth.boxes(93, n)}[kind]()
+         "box": lambda: synth.boxes(93, n), "plane": lambda: synth.planes(96, n)}[kind]()
     # centre the output bias so that about half of the queries are positive
     theta[-1] -= np.float32(np.median(mlp.forward(theta, in_dim, [width] * nh, q, bf16=prec == nb.BF16)))
     b = nb.Bound(in_dim, nh, width, prec)
@@ -335,7 +398,8 @@ def test_cascade(kind, prec, c2_grid):
     nb.nb_cascade(b.handle, ind.handle, nb.KINDS[kind], qd, ans, cnt)
     _, h = b.forward(qd)
     h = host(h)
-    g = {"point": I.voxel_points, "ray": I.voxel_rays, "box": I.voxel_boxes}[kind](q, grid, 128)
+    g = {"point": I.voxel_points, "ray": I.voxel_rays, "box": I.voxel_boxes,
+         "plane": I.voxel_planes}[kind](q, grid, 128)
     assert np.array_equal(host(ans), h & g)
     assert int(host(cnt)[0]) == int(h.sum())
     assert 0 < h.sum() < n
