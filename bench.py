@@ -407,6 +407,152 @@ def run_group_workload(GW, args):
     }
 
 
+def hier_tree(HW):
+    """Breadth-first child ranges of the complete tree that splits space
+    fan_axis ways per axis at each level, each node's level, and the lattice
+    cell (x fastest) of each leaf."""
+    f3 = HW.fan_axis ** 3
+    first = [0]
+    for d in range(HW.depth):
+        first.append(first[-1] + f3 ** d)
+    n_nodes = first[-1]
+    cb, ce, level, leaf_cell = [0] * n_nodes, [0] * n_nodes, [0] * n_nodes, {}
+    L = HW.lattice
+    for d in range(HW.depth):
+        for k in range(f3 ** d):
+            v = first[d] + k
+            level[v] = d
+            if d + 1 < HW.depth:
+                cb[v], ce[v] = first[d + 1] + k * f3, first[d + 1] + (k + 1) * f3
+            else:
+                x = y = z = 0
+                for i in range(d):      # path digits, most significant first
+                    j = (k // f3 ** (d - 1 - i)) % f3
+                    a = HW.fan_axis
+                    x = x * a + j % a
+                    y = y * a + (j // a) % a
+                    z = z * a + j // (a * a)
+                leaf_cell[v] = x + L * (y + L * z)
+    return cb, ce, level, leaf_cell
+
+
+def run_hier_workload(HW, args):
+    import torch
+
+    import paper_2310_06822_amd as nb
+    import synth
+    from paper_2310_06822_amd import trainer
+
+    cb, ce, level, leaf_cell = hier_tree(HW)
+    n_nodes = len(cb)
+    widths = [HW.widths[level[v]] for v in range(n_nodes)]
+    objs = synth.lattice_objects(HW.seeds["scene"], HW.lattice, HW.k_range, HW.rlo, HW.rhi)
+    cells = HW.n ** 3
+    grids = torch.zeros(n_nodes * cells, dtype=torch.uint8, device="cuda")
+    for v in reversed(range(n_nodes)):          # children before their parents
+        gv = grids[v * cells:(v + 1) * cells]
+        if cb[v] == ce[v]:
+            c, r = objs[leaf_cell[v]]
+            nb.nb_voxelize_metaballs(c, r, 1.0, HW.n, gv)
+        else:
+            for c in range(cb[v], ce[v]):
+                torch.bitwise_or(gv, grids[c * cells:(c + 1) * cells], out=gv)
+    group = nb.Group(3, widths, HW.n_hidden)
+    group.set_voxels(grids, [HW.n] * n_nodes)
+    occupancy = [float(grids[v * cells:(v + 1) * cells].float().mean()) for v in (0, 1, n_nodes - 1)]
+    del grids
+    theta0 = np.concatenate([synth.init_params(HW.seeds["init"] + v, 3, [w] * HW.n_hidden)
+                             for v, w in enumerate(widths)]).astype(np.float32)
+    sched = trainer.Schedule(steps=args.train_steps if args.train_steps is not None else HW.train_steps,
+                             batch=HW.per_obj, alpha_max=HW.alpha_max, k=HW.adapt_k, inc=HW.adapt_inc,
+                             patience=HW.patience, max_iters=0 if args.no_adapt else HW.adapt_iters,
+                             val_n=HW.val_per_obj, lr_decay=HW.lr_decay)
+    if getattr(args, "adapt_iters", None) is not None and not args.no_adapt:
+        sched.max_iters = args.adapt_iters
+    group.set_params(theta0)
+    nb.nb_group_train_step(group.handle, n_nodes, nb.POINT, HW.seeds["train"], 0, HW.per_obj, 1.0)   # work space
+    group.set_params(theta0)
+    res = trainer.train_group(group, "point", HW.seeds["train"], sched, val_seed=HW.seeds["val"],
+                              log=lambda m: log(f"[{HW.name}] {m}"))
+    log(f"[{HW.name}] train: {res.steps} steps x {n_nodes} x {HW.per_obj} in {res.seconds:.2f} s -> "
+        f"{res.samples_per_s:.3e} samples/s; converged {res.converged}")
+
+    hier = nb.Hierarchy(group, cb, ce)
+    n_eval = args.eval_n if args.eval_n is not None else HW.eval_n
+    q = torch.empty((n_eval, 3), dtype=torch.float32, device="cuda")
+    nb.nb_sample_queries(nb.POINT, 3, HW.seeds["eval"], 0, q)
+    hier_ms, wall = timed(lambda: hier.query(q), args.steps, args.warmup, torch)
+    leaf_off, qidx = hier.query(q)
+    pairs = hier.level_pairs()
+
+    def flop(w):
+        return 2 * (3 * w + (HW.n_hidden - 1) * w * w + w)
+
+    hier_flop = float(sum(int(pairs[d]) * flop(HW.widths[d]) for d in range(HW.depth)))
+
+    # every leaf's exact answer on the first m rows, against the pairs found
+    m = min(HW.check_n, n_eval)
+    leaves = [v for v in range(n_nodes) if cb[v] == ce[v]]
+    nl = len(leaves)
+    q_rep = q[:m].repeat(nl, 1)
+    sizes = np.zeros(n_nodes, dtype=np.int64)
+    sizes[leaves] = m
+    qoff_rep = torch.from_numpy(np.concatenate([[0], np.cumsum(sizes)])).cuda()
+    g_rep = torch.empty(nl * m, dtype=torch.uint8, device="cuda")
+    nb.nb_group_query_exact(group.handle, n_nodes, nb.POINT, q_rep, qoff_rep, g_rep)
+    loff = leaf_off.cpu().numpy()
+    leaf_of_pair = torch.repeat_interleave(torch.arange(nl, device="cuda"),
+                                           torch.from_numpy(np.diff(loff)).cuda())
+    sel = qidx < m
+    mark = torch.zeros((nl, m), dtype=torch.bool, device="cuda")
+    mark[leaf_of_pair[sel], qidx[sel].long()] = True
+    G = g_rep.view(nl, m).bool()
+    fn = int((G & ~mark).sum())
+    fp = int((mark & ~G).sum())
+    tp = int((G & mark).sum())
+    fn_leaves = int((G & ~mark).any(1).sum())
+    # the flat alternative: every leaf's bound on every row (no tree), and
+    # every leaf's exact test on every row
+    h_rep = torch.empty(nl * m, dtype=torch.uint8, device="cuda")
+    flat_ms, _ = timed(lambda: nb.nb_group_forward(group.handle, n_nodes, 3, q_rep, qoff_rep, h=h_rep),
+                       args.steps, args.warmup, torch)
+    flat_exact_ms, _ = timed(lambda: nb.nb_group_query_exact(group.handle, n_nodes, nb.POINT, q_rep, qoff_rep, g_rep),
+                             args.steps, args.warmup, torch)
+    flat_fn = int((G & ~h_rep.view(nl, m).bool()).sum())
+    del q_rep, g_rep, h_rep, mark, G
+    hier_rate = n_eval / (hier_ms / 1e3)
+    log(f"[{HW.name}] hierarchy query {n_eval}: {hier_ms:.3f} ms ({hier_rate:.3e} q/s), pairs per level "
+        f"{list(map(int, pairs))}, output {int(qidx.numel())}; FN {fn} over {fn_leaves} leaves, FP {fp} "
+        f"(checked {m} rows x {nl} leaves); flat leaves {flat_ms * n_eval / m:.3f} ms-equivalent")
+    achieved = hier_flop / (hier_ms / 1e3) / 1e12
+    return {
+        "bound_queries_per_s": hier_rate,
+        "config": {"workload": HW.name, "query": "point", "nodes": n_nodes, "leaves": nl, "depth": HW.depth,
+                   "tree": f"complete, {HW.fan_axis ** 3} children per node (space split {HW.fan_axis} ways per axis)",
+                   "net": f"3x{{{'|'.join(map(str, HW.widths))}}}^{HW.n_hidden}x1 relu bf16, width per level",
+                   "world_grid": HW.n, "occupancy_root_octant_leaf": [round(x, 5) for x in occupancy],
+                   "queries_per_step": n_eval, "train_per_object": HW.per_obj},
+        "ms_per_query_batch": hier_ms,
+        "level_pairs": [int(x) for x in pairs],
+        "output_pairs": int(qidx.numel()),
+        "leaves_per_query": int(qidx.numel()) / n_eval,
+        "train_samples_per_s": res.samples_per_s,
+        "train": {"steps": res.steps, "seconds": res.seconds, "schedule_iterations": res.iters,
+                  "validation_fn_zero": res.converged, "validation_fn_history": res.val_fn_history[-20:],
+                  "objects_with_fn_history": res.objects_with_fn[-20:]},
+        "heldout": {"rows": m, "leaves": nl, "tp": tp, "fp": fp, "fn": fn, "leaves_with_fn": fn_leaves,
+                    "fp_rate_per_pair": fp / (m * nl), "flat_leaf_bounds_fn": flat_fn},
+        "fn_zero": fn == 0,
+        "flat_leaf_bounds_queries_per_s": m / (flat_ms / 1e3),
+        "hierarchy_speedup_vs_flat_leaf_bounds": (flat_ms / m) / (hier_ms / n_eval),
+        "flat_exact_queries_per_s": m / (flat_exact_ms / 1e3),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["bf16"],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["bf16"], 4), "traffic": None,
+                     "kernel": "nb_hier_query (grouped forward per level + scan + expansion; host sync per level)",
+                     "flop": hier_flop},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -430,7 +576,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2310_06822_amd.configs import GROUP_WORKLOADS, WORKLOADS
+    from paper_2310_06822_amd.configs import GROUP_WORKLOADS, HIER_WORKLOADS, WORKLOADS
 
     torch.cuda.set_device(0)
     W = WORKLOADS[args.workload]
@@ -452,6 +598,8 @@ def main():
     if args.also:
         for name, GW in GROUP_WORKLOADS.items():
             out["also"][name] = run_group_workload(GW, args)
+        for name, HW in HIER_WORKLOADS.items():
+            out["also"][name] = run_hier_workload(HW, args)
     if args.copy_calibration:
         src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
         dst = torch.empty_like(src)

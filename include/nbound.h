@@ -362,6 +362,48 @@ nb_status nb_group_train_step(nb_group* g, int kind, uint64_t seed, uint64_t ste
                               const float* alpha_obj, float beta, float lr, const float* lr_obj, float* loss,
                               uint64_t* counts, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Neural bounding hierarchies (Sec. 3.3).  The tree is supplied by the
+ * user; its nodes are the objects of a group (node i = object i), and each
+ * node's network is meant to bound, conservatively, the union of the
+ * indicators of the leaves below it (a leaf bounds its own object), so
+ * that a region meeting a leaf's object is positive at every node on the
+ * path from the root.  Nodes are numbered breadth first with node 0 the
+ * root: node p's children are the nodes child_begin[p] .. child_end[p]-1,
+ * and the children ranges taken in parent order are exactly 1 .. n_obj-1
+ * (empty range: p is a leaf).  Leaves are ranked in node order.
+ * ------------------------------------------------------------------------ */
+typedef struct nb_hier nb_hier;
+
+/* child_begin_host, child_end_host: int32[n_obj] (copied).  The hierarchy
+ * refers to g, which must outlive it; g's parameters are read at each
+ * query.  NB_ERR_INVALID_ARG if the ranges do not describe such a tree. */
+nb_status nb_hier_create(nb_group* g, const int32_t* child_begin_host, const int32_t* child_end_host,
+                         nb_hier** out);
+nb_status nb_hier_destroy(nb_hier* h);
+nb_status nb_hier_num_leaves(const nb_hier* h, int32_t* n_leaves);
+/* nodes_host: int32[n_leaves], the node of each leaf rank. */
+nb_status nb_hier_leaf_nodes(const nb_hier* h, int32_t* nodes_host);
+/* Number of tree levels (the root's level is 0). */
+nb_status nb_hier_depth(const nb_hier* h, int32_t* depth);
+/* pairs_host: int64[depth], the (row, node) pairs each level of the last
+ * nb_hier_query evaluated (level 0: the rows; zeros before any query). */
+nb_status nb_hier_level_pairs(const nb_hier* h, int64_t* pairs_host);
+/* Descend the tree with every row of q (float32[n][in_dim] on the device;
+ * one decision !(z < tau(eps)) per visited (row, node) pair, as the grouped
+ * forward): the output holds each pair (row, leaf) whose leaf and all of
+ * whose ancestors decide positive, grouped by leaf rank.  leaf_off (device
+ * int64[n_leaves + 1]) receives the segments; leaf r's rows are
+ * qidx_out[leaf_off[r] .. leaf_off[r+1]-1] (device int32[cap]) in increasing
+ * order.  *n_pairs_host receives the number of pairs.  Work space grows
+ * inside the handle as needed; the call synchronises `stream` once per tree
+ * level (the host sizes each level).  If the pairs exceed cap, entries
+ * beyond cap are not written and NB_ERR_INVALID_ARG is returned with
+ * *n_pairs_host set, so the caller can retry with a larger buffer.  n must
+ * be below 2^31, as must the pairs of every level. */
+nb_status nb_hier_query(nb_hier* h, const float* q, int64_t n, float eps, int32_t* qidx_out, int64_t cap,
+                        int64_t* leaf_off, int64_t* n_pairs_host, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,6 +23,8 @@ Modules (each function cites the passage of the paper it follows):
   train       Alg. 1 as a training loop with the FN-weight ramp.
   cascade     bound-then-exact cascade and the benefit inequality (Sec. 6).
   kdop        k-DOP bounds trained with the asymmetric loss (Sec. 4.1).
+  hierarchy   neural bounding hierarchies: a user tree of bounds, descended
+              from the root (Sec. 3.3).
 
 Parity status: every function here is pinned by a test in tests/ against a
 closed form, a brute-force enumeration, a library routine or a value printed

@@ -480,6 +480,101 @@ class Group:
             pass
 
 
+# ------------------------------------------------------------ hierarchies
+
+def nb_hier_create(g, child_begin, child_end) -> C.c_void_p:
+    b = np.ascontiguousarray(child_begin, dtype=np.int32)
+    e = np.ascontiguousarray(child_end, dtype=np.int32)
+    h = C.c_void_p()
+    _check(lib().nb_hier_create(g, b.ctypes.data_as(C.c_void_p), e.ctypes.data_as(C.c_void_p), C.byref(h)))
+    return h
+
+
+def nb_hier_destroy(h):
+    _check(lib().nb_hier_destroy(h))
+
+
+def nb_hier_num_leaves(h) -> int:
+    n = C.c_int32()
+    _check(lib().nb_hier_num_leaves(h, C.byref(n)))
+    return n.value
+
+
+def nb_hier_leaf_nodes(h, n_leaves: int) -> np.ndarray:
+    out = np.zeros(n_leaves, dtype=np.int32)
+    _check(lib().nb_hier_leaf_nodes(h, out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def nb_hier_depth(h) -> int:
+    d = C.c_int32()
+    _check(lib().nb_hier_depth(h, C.byref(d)))
+    return d.value
+
+
+def nb_hier_level_pairs(h, depth: int) -> np.ndarray:
+    out = np.zeros(depth, dtype=np.int64)
+    _check(lib().nb_hier_level_pairs(h, out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def nb_hier_query(h, in_dim: int, q: torch.Tensor, qidx_out: torch.Tensor | None, leaf_off: torch.Tensor,
+                  eps: float = EPS_OUT, stream=None, check: bool = True) -> int:
+    """Number of (row, leaf) pairs.  With check=False a too-small qidx_out
+    (or None) does not raise: compare the returned count with its size."""
+    n = _rows(q, in_dim)
+    cap = 0 if qidx_out is None else qidx_out.numel()
+    npairs = C.c_int64(-1)
+    st = lib().nb_hier_query(h, _dev(q, torch.float32, "q"), n, float(eps), _dev(qidx_out, torch.int32, "qidx_out"),
+                             cap, _dev(leaf_off, torch.int64, "leaf_off"), C.byref(npairs), _stream(stream))
+    if st != 0 and (check or npairs.value <= cap):
+        _check(st)
+    return npairs.value
+
+
+class Hierarchy:
+    """A user-supplied tree over the objects of a Group (node i = object i,
+    breadth-first order, node 0 the root, children of p = child_begin[p] ..
+    child_end[p]-1)."""
+
+    def __init__(self, group: Group, child_begin, child_end):
+        if len(child_begin) != group.n_obj or len(child_end) != group.n_obj:
+            raise ValueError(f"the tree needs one child range per object of the group ({group.n_obj})")
+        self.group = group
+        self.handle = nb_hier_create(group.handle, child_begin, child_end)
+        self.n_leaves = nb_hier_num_leaves(self.handle)
+        self.leaf_nodes = nb_hier_leaf_nodes(self.handle, self.n_leaves)
+        self.depth = nb_hier_depth(self.handle)
+        self._out = None
+
+    def level_pairs(self) -> np.ndarray:
+        """(row, node) pairs per level of the last query."""
+        return nb_hier_level_pairs(self.handle, self.depth)
+
+    def query(self, q: torch.Tensor, eps: float = EPS_OUT):
+        """(leaf_off int64[n_leaves + 1], qidx int32[pairs]) on the device;
+        the output buffer grows when the pairs do not fit."""
+        leaf_off = torch.empty(self.n_leaves + 1, dtype=torch.int64, device=q.device)
+        if self._out is None:
+            self._out = torch.empty(max(q.shape[0], 1 << 16), dtype=torch.int32, device=q.device)
+        n = nb_hier_query(self.handle, self.group.in_dim, q, self._out, leaf_off, eps, check=False)
+        if n > self._out.numel():
+            self._out = torch.empty(n + n // 4 + 1, dtype=torch.int32, device=q.device)
+            n = nb_hier_query(self.handle, self.group.in_dim, q, self._out, leaf_off, eps)
+        return leaf_off, self._out[:n]
+
+    def close(self):
+        if self.handle:
+            nb_hier_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # ------------------------------------------------------------ conveniences
 
 class Indicator:

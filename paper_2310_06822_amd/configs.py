@@ -128,3 +128,53 @@ BATCHED_BOX = GroupWorkload("batched_box", 3, 256, "box", 6, 3, grid_sizes=(32, 
                             val_per_obj=1 << 16, adapt_iters=300, lr_decay=0.99)
 
 GROUP_WORKLOADS = {BATCHED_BOX.name: BATCHED_BOX}
+
+
+@dataclass(frozen=True)
+class HierWorkload:
+    """A neural bounding hierarchy (Sec. 3.3) over objects placed in one
+    scene: one small metaball cluster per cell of a lattice^3 arrangement of
+    [-1, 1]^3 (lattice = fan_axis^(depth-1)), grouped by a complete tree that
+    splits space fan_axis ways per axis at each level (an octree for
+    fan_axis 2).  Every node's bound is trained, as one member of a group, on
+    the union of the voxelised clusters below it (world grid of size n);
+    widths are per level, root first."""
+    name: str
+    index: int
+    fan_axis: int
+    depth: int
+    n: int
+    widths: tuple
+    n_hidden: int
+    k_range: tuple
+    rlo: float
+    rhi: float
+    train_steps: int
+    per_obj: int
+    eval_n: int
+    check_n: int              # held-out rows checked against every leaf's exact answer
+    val_per_obj: int
+    alpha_max: float = 100.0
+    adapt_k: int = 250
+    adapt_inc: float = 50.0
+    adapt_iters: int = 300
+    patience: int = 6
+    lr_decay: float = 0.99
+
+    @property
+    def lattice(self):
+        return self.fan_axis ** (self.depth - 1)
+
+    @property
+    def seeds(self):
+        return {"scene": 1000 + self.index, "train": 2000 + self.index, "eval": 3000 + self.index,
+                "init": 4000 + self.index, "val": 5000 + self.index}
+
+
+# 64 clusters on a 4 x 4 x 4 lattice under an octree: root, 8 octants, 64
+# leaves (73 bounds); 3-D point queries.
+HIER_BLOBS = HierWorkload("hier_blobs", 6, 2, 3, 128, widths=(128, 64, 32), n_hidden=3, k_range=(2, 5),
+                          rlo=0.03, rhi=0.08, train_steps=2000, per_obj=1 << 12, eval_n=1 << 24, check_n=1 << 22,
+                          val_per_obj=1 << 16)
+
+HIER_WORKLOADS = {HIER_BLOBS.name: HIER_BLOBS}

@@ -1,0 +1,453 @@
+// Neural bounding hierarchies (Sec. 3.3): a user-supplied tree over the
+// objects of a group, each node's network a conservative bound of the union
+// of the indicators below it, so that a region that meets a leaf's object is
+// reported by every node on the path from the root to that leaf.
+//
+// A query descends the tree level by level.  Each level is one grouped
+// forward over (region, node) pairs held contiguously per node, which keeps
+// MFMA tiles full of one network's queries instead of letting lanes walk
+// different paths: the positives of node p are found by a device-wide
+// exclusive scan of the decisions (their ranks inside p's segment keep the
+// regions' order), and each is copied to every child of p at the same rank,
+// or, when p is a leaf, its region index is written to p's output segment.
+// The host reads one pair count per level to size the next level.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "nb_internal.h"
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 16;                        // flags per thread
+constexpr int kScanBlock = kScanThreads * kScanPer;  // 4096 flags per block
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+float tau_of(float eps) { return (float)std::log((0.5 - (double)eps) / (0.5 + (double)eps)); }
+
+// Inclusive scan of one int64 per thread over a block of kScanThreads.
+__device__ __forceinline__ int64_t block_inclusive(int64_t x, int64_t* sh_waves) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int64_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) sh_waves[wave] = x;
+  __syncthreads();
+  int64_t before = 0;
+  for (int w = 0; w < wave; ++w) before += sh_waves[w];
+  __syncthreads();
+  return x + before;
+}
+
+// Exclusive ranks of the flags inside each 4096-flag block, and the blocks'
+// totals.  local[i] = number of nonzero h[j], j < i, in i's block.
+__global__ __launch_bounds__(kScanThreads) void k_scan_local(const uint8_t* __restrict__ h, int64_t n,
+                                                             int32_t* __restrict__ local,
+                                                             int64_t* __restrict__ bsum) {
+  __shared__ int64_t sh[kScanThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer;
+  int f[kScanPer];
+  int tot = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    f[k] = (base + k < n && h[base + k] != 0) ? 1 : 0;
+    tot += f[k];
+  }
+  const int64_t incl = block_inclusive(tot, sh);
+  int run = (int)(incl - tot);
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    if (base + k < n) local[base + k] = run;
+    run += f[k];
+  }
+  if (threadIdx.x == kScanThreads - 1) bsum[blockIdx.x] = incl;
+}
+
+// Exclusive prefix of the block totals in place (one block); total[0] = sum.
+__global__ __launch_bounds__(kScanThreads) void k_scan_blocks(int64_t* __restrict__ bsum, int64_t nb,
+                                                              int64_t* __restrict__ total) {
+  __shared__ int64_t sh[kScanThreads / 64];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
+    const int64_t b = b0 + threadIdx.x;
+    const int64_t x = b < nb ? bsum[b] : 0;
+    const int64_t incl = block_inclusive(x, sh);
+    const int64_t c = carry;
+    if (b < nb) bsum[b] = c + incl - x;
+    __syncthreads();
+    if (threadIdx.x == kScanThreads - 1) carry = c + incl;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) total[0] = carry;
+}
+
+// Global exclusive rank of pair i (i == n gives the level's positive count).
+__device__ __forceinline__ int64_t rank_of(int64_t i, int64_t n, const int32_t* __restrict__ local,
+                                           const int64_t* __restrict__ bpre, const int64_t* __restrict__ total) {
+  return i == n ? total[0] : (int64_t)local[i] + bpre[i / kScanBlock];
+}
+
+// Per level (one block): the next level's per-node row offsets (every node of
+// the group: nodes before the next level empty at 0, nodes after it empty at
+// the end), the output offsets of this level's leaves, and the running sizes
+// sizes[0] = rows of the next level, sizes[1] = output pairs so far.
+__global__ __launch_bounds__(kScanThreads) void k_hier_offsets(
+    int n_obj, int lvl_a, int lvl_b, int nxt_a, int nxt_b, const int64_t* __restrict__ qoff, int64_t n, int empty,
+    const int32_t* __restrict__ local, const int64_t* __restrict__ bpre, const int64_t* __restrict__ total,
+    const int32_t* __restrict__ parent, const int32_t* __restrict__ leaf_rank, int64_t* __restrict__ qoff_next,
+    int64_t* __restrict__ out_off, int64_t* __restrict__ sizes) {
+  __shared__ int64_t sh[kScanThreads / 64];
+  __shared__ int64_t carry;
+  auto positives = [&](int p) -> int64_t {
+    if (empty) return 0;
+    return rank_of(qoff[p + 1], n, local, bpre, total) - rank_of(qoff[p], n, local, bpre, total);
+  };
+  // next level: node c gets as many rows as its parent has positives
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int c0 = nxt_a; c0 < nxt_b; c0 += kScanThreads) {
+    const int c = c0 + threadIdx.x;
+    const int64_t x = c < nxt_b ? positives(parent[c]) : 0;
+    const int64_t incl = block_inclusive(x, sh);
+    const int64_t base = carry;
+    if (c < nxt_b) qoff_next[c] = base + incl - x;
+    __syncthreads();
+    if (threadIdx.x == kScanThreads - 1) carry = base + incl;
+    __syncthreads();
+  }
+  const int64_t rows_next = carry;
+  for (int o = threadIdx.x; o <= n_obj; o += kScanThreads) {
+    if (o < nxt_a) qoff_next[o] = 0;
+    if (o >= nxt_b) qoff_next[o] = rows_next;
+  }
+  __syncthreads();
+  // this level's leaves, in node order: output segments after the ones so far
+  if (threadIdx.x == 0) carry = sizes[1];
+  __syncthreads();
+  for (int p0 = lvl_a; p0 < lvl_b; p0 += kScanThreads) {
+    const int p = p0 + threadIdx.x;
+    const bool leaf = p < lvl_b && leaf_rank[p] >= 0;
+    const int64_t x = leaf ? positives(p) : 0;
+    const int64_t incl = block_inclusive(x, sh);
+    const int64_t base = carry;
+    if (leaf) out_off[leaf_rank[p]] = base + incl - x;
+    __syncthreads();
+    if (threadIdx.x == kScanThreads - 1) carry = base + incl;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    sizes[0] = rows_next;
+    sizes[1] = carry;
+  }
+}
+
+// Copy every positive pair to its node's children (or to the output when the
+// node is a leaf) at its rank among the node's positives.
+__global__ __launch_bounds__(256) void k_hier_expand(
+    int in_dim, int64_t n, const uint8_t* __restrict__ h, const float* __restrict__ rows,
+    const int32_t* __restrict__ qidx, const int32_t* __restrict__ node, const int64_t* __restrict__ qoff,
+    const int32_t* __restrict__ local, const int64_t* __restrict__ bpre, const int64_t* __restrict__ total,
+    const int32_t* __restrict__ child_b, const int32_t* __restrict__ child_e, const int32_t* __restrict__ leaf_rank,
+    const int64_t* __restrict__ qoff_next, float* __restrict__ rows_next, int32_t* __restrict__ qidx_next,
+    int32_t* __restrict__ node_next, const int64_t* __restrict__ out_off, int32_t* __restrict__ out, int64_t cap) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || h[i] == 0) return;
+  const int p = node ? node[i] : 0;
+  const int32_t qi = qidx ? qidx[i] : (int32_t)i;
+  const int64_t r = rank_of(i, n, local, bpre, total) - rank_of(qoff[p], n, local, bpre, total);
+  const int lr = leaf_rank[p];
+  if (lr >= 0) {
+    const int64_t dst = out_off[lr] + r;
+    if (dst < cap) out[dst] = qi;
+    return;
+  }
+  const float* src = rows + i * in_dim;
+  for (int c = child_b[p]; c < child_e[p]; ++c) {
+    const int64_t dst = qoff_next[c] + r;
+    for (int d = 0; d < in_dim; ++d) rows_next[dst * in_dim + d] = src[d];
+    qidx_next[dst] = qi;
+    node_next[dst] = c;
+  }
+}
+
+__global__ void k_set_i64(int64_t* __restrict__ p, int64_t v) { *p = v; }
+
+}  // namespace
+
+struct nb_hier {
+  nb_group* g = nullptr;
+  int n_nodes = 0, n_leaves = 0, device = 0;
+  std::vector<int> child_b, child_e, parent, level, leaf_rank;
+  std::vector<int> lvl_first;   // nodes of level l: lvl_first[l] .. lvl_first[l+1]-1
+  int32_t *d_child_b = nullptr, *d_child_e = nullptr, *d_parent = nullptr, *d_leaf_rank = nullptr;
+  // two pair buffers (rows, region index, node), decisions, scan, offsets
+  int64_t pcap[2] = {0, 0};
+  float* rows[2] = {nullptr, nullptr};
+  int32_t* qidx[2] = {nullptr, nullptr};
+  int32_t* node[2] = {nullptr, nullptr};
+  int64_t scap = 0;
+  uint8_t* h = nullptr;
+  int32_t* local = nullptr;
+  int64_t* bsum = nullptr;
+  int64_t* qoff[2] = {nullptr, nullptr};
+  int64_t* misc = nullptr;      // [0] scan total, [1] rows of the next level, [2] output pairs so far
+  std::vector<int64_t> level_pairs;   // (row, node) pairs per level of the last query
+  int64_t* host_sizes = nullptr;   // pinned [2]
+};
+
+namespace {
+
+template <class T>
+nb_status hier_alloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return NB_OK;
+  NB_HIP(hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)));
+  return NB_OK;
+}
+
+template <class T>
+void hier_free(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+void free_pair_set(nb_hier* t, int k) {
+  hier_free(t->rows[k]);
+  hier_free(t->qidx[k]);
+  hier_free(t->node[k]);
+  t->pcap[k] = 0;
+}
+
+void free_scan(nb_hier* t) {
+  hier_free(t->h);
+  hier_free(t->local);
+  hier_free(t->bsum);
+  t->scap = 0;
+}
+
+int64_t grown(int64_t need) { return std::max<int64_t>(need + need / 4, 1 << 16); }
+
+// Pair set k holds at least `need` pairs.  Called with the stream idle and
+// set k unused by any pending work.
+nb_status ensure_pairs(nb_hier* t, int k, int64_t need) {
+  if (need <= t->pcap[k]) return NB_OK;
+  free_pair_set(t, k);
+  const int64_t cap = grown(need);
+  NB_TRY(hier_alloc(&t->rows[k], (size_t)cap * t->g->in_dim));
+  NB_TRY(hier_alloc(&t->qidx[k], (size_t)cap));
+  NB_TRY(hier_alloc(&t->node[k], (size_t)cap));
+  t->pcap[k] = cap;
+  return NB_OK;
+}
+
+// Decisions and scan space for `need` pairs (stream idle).
+nb_status ensure_scan(nb_hier* t, int64_t need) {
+  if (need <= t->scap) return NB_OK;
+  free_scan(t);
+  const int64_t cap = grown(need);
+  NB_TRY(hier_alloc(&t->h, (size_t)cap));
+  NB_TRY(hier_alloc(&t->local, (size_t)cap));
+  NB_TRY(hier_alloc(&t->bsum, (size_t)(cap / kScanBlock + 2)));
+  t->scap = cap;
+  return NB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nb_status nb_hier_create(nb_group* g, const int32_t* child_begin_host, const int32_t* child_end_host,
+                         nb_hier** out) {
+  NB_REQUIRE(out && g && child_begin_host && child_end_host, "NULL argument");
+  *out = nullptr;
+  const int n = g->n_obj;
+  // children ranges, concatenated in parent order, must be exactly 1 .. n-1
+  int next = 1;
+  for (int p = 0; p < n; ++p) {
+    const int b = child_begin_host[p], e = child_end_host[p];
+    NB_REQUIRE(e >= b, "node %d: child range [%d, %d) is reversed", p, b, e);
+    if (e == b) continue;
+    NB_REQUIRE(b == next && e <= n,
+               "node %d: children must be the next unused nodes in breadth-first order (expected %d, got [%d, %d))",
+               p, next, b, e);
+    NB_REQUIRE(b > p, "node %d: a child must come after its parent", p);
+    next = e;
+  }
+  NB_REQUIRE(next == n, "nodes %d .. %d have no parent (breadth-first order, node 0 the root)", next, n - 1);
+  auto* t = new nb_hier();
+  t->g = g;
+  t->n_nodes = n;
+  t->device = g->device;
+  t->child_b.assign(child_begin_host, child_begin_host + n);
+  t->child_e.assign(child_end_host, child_end_host + n);
+  t->parent.assign(n, -1);
+  t->level.assign(n, 0);
+  t->leaf_rank.assign(n, -1);
+  for (int p = 0; p < n; ++p)
+    for (int c = t->child_b[p]; c < t->child_e[p]; ++c) {
+      t->parent[c] = p;
+      t->level[c] = t->level[p] + 1;
+    }
+  for (int p = 0; p < n; ++p)
+    if (t->child_b[p] == t->child_e[p]) t->leaf_rank[p] = t->n_leaves++;
+  const int depth = t->level[n - 1] + 1;
+  t->lvl_first.assign(depth + 1, n);
+  for (int p = n - 1; p >= 0; --p) t->lvl_first[t->level[p]] = p;
+  nb_status st = NB_OK;
+  if (st == NB_OK) st = hier_alloc(&t->d_child_b, n);
+  if (st == NB_OK) st = hier_alloc(&t->d_child_e, n);
+  if (st == NB_OK) st = hier_alloc(&t->d_parent, n);
+  if (st == NB_OK) st = hier_alloc(&t->d_leaf_rank, n);
+  if (st == NB_OK) st = hier_alloc(&t->qoff[0], (size_t)n + 1);
+  if (st == NB_OK) st = hier_alloc(&t->qoff[1], (size_t)n + 1);
+  if (st == NB_OK) st = hier_alloc(&t->misc, 4);
+  if (st == NB_OK && hipHostMalloc(reinterpret_cast<void**>(&t->host_sizes), 2 * sizeof(int64_t)) != hipSuccess) {
+    nb_set_error("hipHostMalloc of the level sizes failed");
+    st = NB_ERR_OOM;
+  }
+  if (st == NB_OK) {
+    const size_t bytes = sizeof(int32_t) * n;
+    if (hipMemcpy(t->d_child_b, t->child_b.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t->d_child_e, t->child_e.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t->d_parent, t->parent.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t->d_leaf_rank, t->leaf_rank.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+      nb_set_error("hipMemcpy of the tree failed");
+      st = NB_ERR_HIP;
+    }
+  }
+  if (st != NB_OK) {
+    nb_hier_destroy(t);
+    return st;
+  }
+  *out = t;
+  return NB_OK;
+}
+
+nb_status nb_hier_destroy(nb_hier* t) {
+  if (!t) return NB_OK;
+  free_pair_set(t, 0);
+  free_pair_set(t, 1);
+  free_scan(t);
+  hier_free(t->d_child_b);
+  hier_free(t->d_child_e);
+  hier_free(t->d_parent);
+  hier_free(t->d_leaf_rank);
+  hier_free(t->qoff[0]);
+  hier_free(t->qoff[1]);
+  hier_free(t->misc);
+  if (t->host_sizes) (void)hipHostFree(t->host_sizes);
+  delete t;
+  return NB_OK;
+}
+
+nb_status nb_hier_num_leaves(const nb_hier* t, int32_t* out) {
+  NB_REQUIRE(t && out, "NULL argument");
+  *out = t->n_leaves;
+  return NB_OK;
+}
+
+nb_status nb_hier_depth(const nb_hier* t, int32_t* depth) {
+  NB_REQUIRE(t && depth, "NULL argument");
+  *depth = (int32_t)t->lvl_first.size() - 1;
+  return NB_OK;
+}
+
+nb_status nb_hier_level_pairs(const nb_hier* t, int64_t* pairs_host) {
+  NB_REQUIRE(t && pairs_host, "NULL argument");
+  const int depth = (int)t->lvl_first.size() - 1;
+  for (int l = 0; l < depth; ++l) pairs_host[l] = l < (int)t->level_pairs.size() ? t->level_pairs[l] : 0;
+  return NB_OK;
+}
+
+nb_status nb_hier_leaf_nodes(const nb_hier* t, int32_t* nodes_host) {
+  NB_REQUIRE(t && nodes_host, "NULL argument");
+  for (int p = 0; p < t->n_nodes; ++p)
+    if (t->leaf_rank[p] >= 0) nodes_host[t->leaf_rank[p]] = p;
+  return NB_OK;
+}
+
+nb_status nb_hier_query(nb_hier* t, const float* q, int64_t n, float eps, int32_t* qidx_out, int64_t cap,
+                        int64_t* leaf_off, int64_t* n_pairs_host, void* stream) {
+  NB_REQUIRE(t && q && leaf_off && n_pairs_host, "NULL argument");
+  NB_REQUIRE(n > 0 && n <= (int64_t)0x7FFFFFFF, "n must be in 1 .. 2^31 - 1");
+  NB_REQUIRE(cap >= 0 && (cap == 0 || qidx_out), "qidx_out must hold cap >= 0 entries");
+  NB_REQUIRE(eps >= 0.0f && eps < 0.5f, "eps must be in [0, 0.5)");
+  int dev = -1;
+  NB_HIP(hipGetDevice(&dev));
+  NB_REQUIRE(dev == t->device, "the hierarchy lives on device %d, the current device is %d", t->device, dev);
+  hipStream_t s = as_stream(stream);
+  const float tau = tau_of(eps);
+  const int in_dim = t->g->in_dim;
+  const int depth = (int)t->lvl_first.size() - 1;
+  t->level_pairs.assign(depth, 0);
+  NB_HIP(hipStreamSynchronize(s));
+  // level 0: the root over the caller's rows, region index = row
+  k_set_i64<<<1, 1, 0, s>>>(t->misc + 2, 0);
+  NB_LAUNCHED();
+  {
+    std::vector<int64_t> q0((size_t)t->n_nodes + 1, n);
+    q0[0] = 0;
+    NB_HIP(hipMemcpyAsync(t->qoff[0], q0.data(), sizeof(int64_t) * q0.size(), hipMemcpyHostToDevice, s));
+    NB_HIP(hipStreamSynchronize(s));
+  }
+  const float* rows = q;
+  const int32_t* qidx = nullptr;
+  const int32_t* node = nullptr;
+  int64_t rows_n = n;
+  int cur = 0;   // pair set read by this level (written by the previous level's expansion)
+  for (int l = 0; l < depth; ++l) {
+    const int la = t->lvl_first[l], lb = t->lvl_first[l + 1];
+    const int na = l + 1 < depth ? t->lvl_first[l + 1] : t->n_nodes;
+    const int nbn = l + 1 < depth ? t->lvl_first[l + 2] : t->n_nodes;
+    const int empty = rows_n == 0;
+    t->level_pairs[l] = rows_n;
+    const int64_t* qoff = t->qoff[l & 1];
+    int64_t* qoff_next = t->qoff[(l + 1) & 1];
+    if (!empty) {
+      NB_TRY(ensure_scan(t, rows_n));   // the stream is idle: synchronised below, and before the loop
+      NB_TRY(group_forward(t->g, rows, qoff, rows_n, tau, nullptr, t->h, nullptr, nullptr, s));
+      const int64_t nblk = (rows_n + kScanBlock - 1) / kScanBlock;
+      k_scan_local<<<(unsigned)nblk, kScanThreads, 0, s>>>(t->h, rows_n, t->local, t->bsum);
+      NB_LAUNCHED();
+      k_scan_blocks<<<1, kScanThreads, 0, s>>>(t->bsum, nblk, t->misc);
+      NB_LAUNCHED();
+    }
+    k_hier_offsets<<<1, kScanThreads, 0, s>>>(t->n_nodes, la, lb, na, nbn, qoff, rows_n, empty, t->local, t->bsum,
+                                             t->misc, t->d_parent, t->d_leaf_rank, qoff_next, leaf_off,
+                                             t->misc + 1);
+    NB_LAUNCHED();
+    NB_HIP(hipMemcpyAsync(t->host_sizes, t->misc + 1, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    NB_HIP(hipStreamSynchronize(s));
+    const int64_t next_n = t->host_sizes[0];
+    NB_REQUIRE(next_n <= (int64_t)0x7FFFFFFF, "level %d holds %lld (region, node) pairs, more than 2^31 - 1", l + 1,
+               (long long)next_n);
+    if (!empty) {
+      const int nxt = 1 - cur;
+      NB_TRY(ensure_pairs(t, nxt, next_n));   // set nxt was read by the level before this one: finished
+      k_hier_expand<<<(unsigned)((rows_n + 255) / 256), 256, 0, s>>>(
+          in_dim, rows_n, t->h, rows, qidx, node, qoff, t->local, t->bsum, t->misc, t->d_child_b, t->d_child_e,
+          t->d_leaf_rank, qoff_next, t->rows[nxt], t->qidx[nxt], t->node[nxt], leaf_off, qidx_out, cap);
+      NB_LAUNCHED();
+      NB_HIP(hipStreamSynchronize(s));
+      rows = t->rows[nxt];
+      qidx = t->qidx[nxt];
+      node = t->node[nxt];
+      cur = nxt;
+    }
+    rows_n = next_n;
+  }
+  const int64_t pairs = t->host_sizes[1];
+  k_set_i64<<<1, 1, 0, s>>>(leaf_off + t->n_leaves, pairs);
+  NB_LAUNCHED();
+  *n_pairs_host = pairs;
+  NB_REQUIRE(pairs <= cap, "the traversal found %lld (region, leaf) pairs, more than cap = %lld", (long long)pairs,
+             (long long)cap);
+  return NB_OK;
+}
+
+}  // extern "C"

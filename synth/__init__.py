@@ -85,6 +85,27 @@ def object_set(seed: int, n_obj: int, grid_sizes=(32, 64, 128), widths=(32, 64, 
     return out
 
 
+def lattice_objects(seed: int, lattice: int, k_range=(2, 5), rlo: float = 0.03, rhi: float = 0.08,
+                    spread: float = 0.5):
+    """One small metaball cluster per cell of a lattice^3 arrangement of
+    [-1, 1]^3 (cells x fastest): k balls (k uniform in k_range inclusive)
+    with centres uniform within `spread` of the cell's half width around the
+    cell centre and radii uniform in [rlo, rhi].  List of (centres [k,3]
+    float32, radii [k] float32)."""
+    g = rng(seed)
+    half = 1.0 / lattice
+    out = []
+    for cz in range(lattice):
+        for cy in range(lattice):
+            for cx in range(lattice):
+                mid = np.array([-1.0 + (2 * cx + 1) * half, -1.0 + (2 * cy + 1) * half, -1.0 + (2 * cz + 1) * half])
+                k = int(g.integers(k_range[0], k_range[1] + 1))
+                c = mid + g.uniform(-spread * half, spread * half, size=(k, 3))
+                r = g.uniform(rlo, rhi, size=(k,))
+                out.append((np.ascontiguousarray(c.astype(np.float32)), np.ascontiguousarray(r.astype(np.float32))))
+    return out
+
+
 def random_grid(seed: int, n: int, density: float = 0.1) -> np.ndarray:
     """Random occupancy grid uint8[n*n*n], x fastest (index (k*n + j)*n + i)."""
     g = rng(seed)
