@@ -174,7 +174,7 @@ class HierWorkload:
 # 64 clusters on a 4 x 4 x 4 lattice under an octree: root, 8 octants, 64
 # leaves (73 bounds); 3-D point queries.
 HIER_BLOBS = HierWorkload("hier_blobs", 6, 2, 3, 128, widths=(128, 64, 32), n_hidden=3, k_range=(2, 5),
-                          rlo=0.03, rhi=0.08, train_steps=2000, per_obj=1 << 12, eval_n=1 << 24, check_n=1 << 22,
-                          val_per_obj=1 << 16)
+                          rlo=0.03, rhi=0.08, train_steps=2000, per_obj=1 << 14, eval_n=1 << 24, check_n=1 << 22,
+                          val_per_obj=1 << 20)
 
 HIER_WORKLOADS = {HIER_BLOBS.name: HIER_BLOBS}
