@@ -178,6 +178,10 @@ nb_status nb_indicator_voxels(const uint8_t* grid, int n, nb_indicator** out) {
   ind->mask_words = (n + 63) / 64;
   if (st == NB_OK) st = dev_alloc(&ind->centre, (size_t)n);
   if (st == NB_OK) st = dev_alloc(&ind->colmask, (size_t)3 * n * n * ind->mask_words);
+  ind->coarse_n = (n + 7) / 8;
+  ind->coarse_words = (ind->coarse_n + 63) / 64;
+  if (st == NB_OK)
+    st = dev_alloc(&ind->coarse_mask, (size_t)3 * ind->coarse_n * ind->coarse_n * ind->coarse_words);
   if (st == NB_OK) {
     // cell centres, computed in double and rounded once (the plane query's)
     std::vector<float> c((size_t)n);
@@ -198,7 +202,9 @@ nb_status nb_indicator_voxels(const uint8_t* grid, int n, nb_indicator** out) {
     }
   }
   if (st == NB_OK) st = launch_collect_occupied(ind->grid, cells, ind->occupied, ind->occupied_count, nullptr);
-  if (st == NB_OK) st = launch_column_masks(ind->grid, n, ind->mask_words, ind->colmask, nullptr);
+  if (st == NB_OK)
+    st = launch_column_masks(ind->grid, n, ind->mask_words, ind->colmask, ind->coarse_n, ind->coarse_words,
+                             ind->coarse_mask, nullptr);
   if (st == NB_OK && hipDeviceSynchronize() != hipSuccess) {
     nb_set_error("building the occupied-cell list failed");
     st = NB_ERR_HIP;
@@ -257,6 +263,7 @@ nb_status nb_indicator_destroy(nb_indicator* ind) {
   dev_free(ind->occupied_count);
   dev_free(ind->centre);
   dev_free(ind->colmask);
+  dev_free(ind->coarse_mask);
   delete ind;
   return NB_OK;
 }

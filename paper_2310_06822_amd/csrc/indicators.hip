@@ -31,12 +31,15 @@ struct IndView {
   const float* centre;
   const uint64_t* colmask;
   int mask_words;
+  const uint64_t* coarse_mask;
+  int coarse_n, coarse_words;
 };
 
 IndView view_of(const nb_indicator* ind) {
   return IndView{ind->type,     ind->k,        ind->n,          ind->iso,      ind->params,
                  ind->grid,     ind->ray_t,    ind->occupied,   ind->occupied_count,
-                 ind->centre,   ind->colmask,  ind->mask_words};
+                 ind->centre,   ind->colmask,  ind->mask_words, ind->coarse_mask, ind->coarse_n,
+                 ind->coarse_words};
 }
 
 // ------------------------------------------------------------------- points
@@ -87,10 +90,15 @@ __device__ __forceinline__ uint8_t metaballs4d_at(const float* __restrict__ row,
 // widened by a bound on the float32 rounding error of the predicate (so it
 // holds every cell for which the float32 predicate can be true) and by one
 // cell; its occupied cells come from the column's occupancy bits, and each
-// is then tested with the float32 predicate itself.  One wave takes one
-// plane; its lanes take the columns in a scattered order (a plane that meets
-// the object is usually settled in the first pass of 64 columns) and stop
-// together at the first hit.  Planes with a non-finite value or a normal
+// is then tested with the float32 predicate itself.  A coarse level in front
+// does the same for columns of 8 x 8 cells against blocks of 8 x 8 x 8 cells:
+// the union of the fine intervals of a coarse column, widened by one more
+// cell, is tested against the coarse occupancy bits, and only the coarse
+// columns that pass are searched cell column by cell column, so a plane that
+// misses the object is usually rejected after n^2/4096 coarse tests.  One
+// wave takes one plane (64 coarse columns, then the 64 cell columns of one
+// coarse column, per pass) and stops at the first hit.  Planes with a
+// non-finite value or a normal
 // whose largest component is outside [2^-60, 2^60] (where the error bound
 // would not hold) take the plain loop over the occupied-cell list instead.
 
@@ -121,6 +129,21 @@ __device__ uint8_t plane_wave_list(const IndView& v, const PlaneRow& r, int lane
     if (__ballot(hit)) return 1;
   }
   return 0;
+}
+
+// Bits lo .. hi (absolute positions) of word w of a bit row.
+__device__ __forceinline__ uint64_t word_range(uint64_t bits, int w, int lo, int hi) {
+  const int b0 = w * 64;
+  if (lo > b0) bits &= ~0ull << (lo - b0);
+  if (hi - b0 < 63) bits &= (2ull << (hi - b0)) - 1ull;
+  return bits;
+}
+
+// Any of the bits lo .. hi of a bit row set?
+__device__ __forceinline__ bool any_bits(const uint64_t* __restrict__ row, int lo, int hi) {
+  for (int w = lo >> 6; w <= (hi >> 6); ++w)
+    if (word_range(row[w], w, lo, hi)) return true;
+  return false;
 }
 
 __device__ uint8_t plane_wave(const IndView& v, const float* __restrict__ row, int lane) {
@@ -156,45 +179,53 @@ __device__ uint8_t plane_wave(const IndView& v, const float* __restrict__ row, i
                                                                          mt * (1.0 / N - 1.0 - pt));
   const double Kw = ((double)r.rad + err) * N / (2.0 * fabs(ma)) + 1.0;
 
-  const int cols = gn * gn;
-  // scattered column order: col -> col * P mod n^2 with P a prime above
-  // 1024 (a bijection, since n <= 1024)
-  const int P = 40009;
-  const int step = (int)((64ll * P) % cols);
-  int col = (int)(((int64_t)lane * P) % cols);
-  const float inv_n = 1.0f / (float)gn;
-  const uint64_t* mask_a = v.colmask + (size_t)a * cols * v.mask_words;
-  for (int base = 0; base < cols; base += 64) {
-    bool hit = false;
-    if (base + lane < cols) {
-      int t = (int)((float)col * inv_n);
-      int s = col - t * gn;
-      if (s < 0) { s += gn; --t; }
-      if (s >= gn) { s -= gn; ++t; }
-      const double kc = fma((double)t, Kt, fma((double)s, Ks, K0));
-      const double lo_d = fmax(floor(kc - Kw), 0.0), hi_d = fmin(ceil(kc + Kw), N - 1.0);
+  const uint64_t* mask_a = v.colmask + (size_t)a * gn * gn * v.mask_words;
+  const int C = v.coarse_n;
+  const int ccols = C * C;
+  const uint64_t* cmask_a = v.coarse_mask + (size_t)a * ccols * v.coarse_words;
+  for (int base = 0; base < ccols; base += 64) {
+    const int cc = base + lane;
+    bool flag = false;
+    if (cc < ccols) {
+      // coarse column (cs, ct): cells s in [8 cs, 8 cs + 7], t in [8 ct, 8 ct + 7]
+      const int ct = cc / C, cs = cc - ct * C;
+      const double s0 = 8.0 * cs, s1 = fmin(s0 + 7.0, N - 1.0), t0 = 8.0 * ct, t1 = fmin(t0 + 7.0, N - 1.0);
+      const double kmin = K0 + fmin(s0 * Ks, s1 * Ks) + fmin(t0 * Kt, t1 * Kt);
+      const double kmax = K0 + fmax(s0 * Ks, s1 * Ks) + fmax(t0 * Kt, t1 * Kt);
+      const double lo_d = fmax(floor(kmin - Kw) - 1.0, 0.0), hi_d = fmin(ceil(kmax + Kw) + 1.0, N - 1.0);
       if (lo_d <= hi_d) {
-        const int lo = (int)lo_d, hi = (int)hi_d;
-        const uint64_t* colbits = mask_a + ((size_t)t * gn + s) * v.mask_words;
-        for (int w = lo >> 6; w <= (hi >> 6) && !hit; ++w) {
-          uint64_t bits = colbits[w];
-          const int b0 = w * 64;
-          if (lo > b0) bits &= ~0ull << (lo - b0);
-          if (hi - b0 < 63) bits &= (2ull << (hi - b0)) - 1ull;
-          while (bits && !hit) {
-            const int k = b0 + __builtin_ctzll(bits);
-            bits &= bits - 1ull;
-            const int ix = a == 0 ? k : s;
-            const int jy = a == 1 ? k : (a == 0 ? s : t);
-            const int kz = a == 2 ? k : t;
-            hit = plane_meets(r, v.centre, ix, jy, kz);
+        const int lo = (int)lo_d >> 3, hi = (int)hi_d >> 3;
+        flag = any_bits(cmask_a + (size_t)cc * v.coarse_words, lo, hi);
+      }
+    }
+    uint64_t todo = __ballot(flag);   // the same on every lane
+    while (todo) {
+      const int cc2 = base + __builtin_ctzll(todo);
+      todo &= todo - 1ull;
+      const int ct = cc2 / C, cs = cc2 - ct * C;
+      const int s = 8 * cs + (lane & 7), t = 8 * ct + (lane >> 3);
+      bool hit = false;
+      if (s < gn && t < gn) {
+        const double kc = fma((double)t, Kt, fma((double)s, Ks, K0));
+        const double lo_d = fmax(floor(kc - Kw), 0.0), hi_d = fmin(ceil(kc + Kw), N - 1.0);
+        if (lo_d <= hi_d) {
+          const int lo = (int)lo_d, hi = (int)hi_d;
+          const uint64_t* colbits = mask_a + ((size_t)t * gn + s) * v.mask_words;
+          for (int w = lo >> 6; w <= (hi >> 6) && !hit; ++w) {
+            uint64_t bits = word_range(colbits[w], w, lo, hi);
+            while (bits && !hit) {
+              const int k = w * 64 + __builtin_ctzll(bits);
+              bits &= bits - 1ull;
+              const int ix = a == 0 ? k : s;
+              const int jy = a == 1 ? k : (a == 0 ? s : t);
+              const int kz = a == 2 ? k : t;
+              hit = plane_meets(r, v.centre, ix, jy, kz);
+            }
           }
         }
       }
+      if (__ballot(hit)) return 1;
     }
-    if (__ballot(hit)) return 1;
-    col += step;
-    if (col >= cols) col -= cols;
   }
   return 0;
 }
@@ -307,6 +338,37 @@ __global__ void k_cascade_exact(IndView v, const float* __restrict__ q, const in
     const int64_t i = idx[t];
     answer[i] = exact_at<KIND>(v, q, i);
   }
+}
+
+// Coarse occupancy bits: for each axis and column of 8 x 8 cells (coarse
+// coordinates of the two other axes, the higher one outer), bit K of word
+// w is set iff a cell of the column with coordinate 8 (64 w + K) .. +7 along
+// the axis is occupied.  Built from the cell column bits.
+__global__ void k_coarse_masks(const uint64_t* __restrict__ mask, int gn, int words, int C, int cwords,
+                               uint64_t* __restrict__ cmask) {
+  const int64_t total = 3ll * C * C * cwords;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= total) return;
+  const int wc = (int)(id % cwords);
+  const int64_t col = id / cwords;
+  const int cs = (int)(col % C), ct = (int)((col / C) % C), a = (int)(col / ((int64_t)C * C));
+  uint64_t bits = 0;
+  for (int dt = 0; dt < 8; ++dt) {
+    const int t = 8 * ct + dt;
+    if (t >= gn) break;
+    for (int ds = 0; ds < 8; ++ds) {
+      const int s = 8 * cs + ds;
+      if (s >= gn) break;
+      const uint64_t* fine = mask + (((int64_t)a * gn + t) * gn + s) * words;
+      for (int K = 0; K < 64; ++K) {
+        const int kc = 64 * wc + K;
+        if (kc >= C) break;
+        const int f = 8 * kc;
+        if ((fine[f >> 6] >> (f & 63)) & 0xFFull) bits |= 1ull << K;
+      }
+    }
+  }
+  cmask[id] = bits;
 }
 
 // ----------------------------------------------------------- voxelisation
@@ -434,8 +496,12 @@ nb_status launch_collect_occupied(const uint8_t* grid, int64_t cells, int32_t* o
   return NB_OK;
 }
 
-nb_status launch_column_masks(const uint8_t* grid, int n, int words, uint64_t* mask, hipStream_t s) {
+nb_status launch_column_masks(const uint8_t* grid, int n, int words, uint64_t* mask, int coarse_n, int coarse_words,
+                              uint64_t* coarse_mask, hipStream_t s) {
   k_column_masks<<<blocks_for(3ll * n * n * words), kThreads, 0, s>>>(grid, n, words, mask);
+  NB_LAUNCHED();
+  k_coarse_masks<<<blocks_for(3ll * coarse_n * coarse_n * coarse_words), kThreads, 0, s>>>(
+      mask, n, words, coarse_n, coarse_words, coarse_mask);
   NB_LAUNCHED();
   return NB_OK;
 }

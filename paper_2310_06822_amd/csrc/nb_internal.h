@@ -63,6 +63,10 @@ struct nb_indicator {
   float* centre = nullptr;
   uint64_t* colmask = nullptr;
   int mask_words = 0;
+  // the same per column of 8 x 8 cells over blocks of 8 x 8 x 8 cells:
+  // [3][C][C][coarse_words], C = ceil(n / 8)
+  uint64_t* coarse_mask = nullptr;
+  int coarse_n = 0, coarse_words = 0;
 };
 
 struct nb_bound {
@@ -169,7 +173,8 @@ nb_status launch_cascade_exact(const nb_indicator* ind, int kind, const float* q
 nb_status launch_compact_positive(const uint8_t* h, int64_t n, int32_t* idx, unsigned long long* count, hipStream_t s);
 nb_status launch_collect_occupied(const uint8_t* grid, int64_t cells, int32_t* out, int64_t* count_dev,
                                   hipStream_t s);
-nb_status launch_column_masks(const uint8_t* grid, int n, int words, uint64_t* mask, hipStream_t s);
+nb_status launch_column_masks(const uint8_t* grid, int n, int words, uint64_t* mask, int coarse_n, int coarse_words,
+                              uint64_t* coarse_mask, hipStream_t s);
 
 // mlp_f32.hip
 bool f32_supported(int in_dim, int n_hidden, int width);

@@ -127,16 +127,25 @@ def test_exact_planes():
     assert 0.05 < ref.mean() < 0.95
 
 
-def _plane_edge_cases(n, seed):
+def _plane_edge_cases(n, seed, grid):
     """Planes that stress the column search of the plane test: far-away
     points p0 (on and off the cube), scaled normals (tiny, huge, subnormal
     components, zero), axis-aligned planes on cell faces (|e| = rad exactly),
-    ties between normal components, non-finite values, and planes through the
+    ties between normal components, non-finite values, planes through the
     cube whose p0 lies up to 1e7 away along the plane (large rounding error
-    in the float32 predicate)."""
+    in the float32 predicate), and planes grazing the object: just inside or
+    just outside the extreme occupied cell along a random normal."""
     g = np.random.default_rng(seed)
     base = synth.planes(seed, 40)
     rows = list(base)
+    P = np.stack(I._occupied_cells(grid, n), 1).astype(np.float64)
+    for _ in range(20):
+        nrm = g.normal(size=3)
+        nrm /= np.linalg.norm(nrm)
+        j = int(np.argmax(P @ nrm))
+        rad = np.abs(nrm).sum() / n
+        for d in (0.3, 0.9, 0.999, 1.001, 1.2):
+            rows.append(list(P[j] + d * rad * nrm) + list(nrm))
     for sc in (1e3, 1e6, 1e20):
         b = base[:8].copy()
         b[:, :3] *= sc
@@ -168,12 +177,12 @@ def _plane_edge_cases(n, seed):
     return np.asarray(rows, dtype=np.float32)
 
 
-@pytest.mark.parametrize("n,k", [(16, 6), (33, 8), (64, 12), (128, 16)])
+@pytest.mark.parametrize("n,k", [(5, 2), (16, 6), (33, 8), (64, 12), (128, 16)])
 def test_exact_planes_edge_cases(n, k):
     c, r = synth.metaballs3d(50 + n, k=k, rlo=0.05, rhi=0.25)
     grid = I.voxelize_metaballs(c, r, n)
     ind = nb.Indicator.voxels(cuda(grid), n)
-    q = _plane_edge_cases(n, n)
+    q = _plane_edge_cases(n, n, grid)
     with np.errstate(invalid="ignore", over="ignore"):
         ref = I.voxel_planes(q, grid, n)
     assert np.array_equal(host(ind.query("plane", cuda(q))), ref)
