@@ -441,7 +441,7 @@ def run_hier_workload(HW, args):
 
     import paper_2310_06822_amd as nb
     import synth
-    from paper_2310_06822_amd import trainer
+    from paper_2310_06822_amd import autotune, trainer
 
     cb, ce, level, leaf_cell = hier_tree(HW)
     n_nodes = len(cb)
@@ -481,6 +481,7 @@ def run_hier_workload(HW, args):
     n_eval = args.eval_n if args.eval_n is not None else HW.eval_n
     q = torch.empty((n_eval, 3), dtype=torch.float32, device="cuda")
     nb.nb_sample_queries(nb.POINT, 3, HW.seeds["eval"], 0, q)
+    variant = autotune.tune_hierarchy(hier, q)
     hier_ms, wall = timed(lambda: hier.query(q), args.steps, args.warmup, torch)
     leaf_off, qidx = hier.query(q)
     pairs = hier.level_pairs()
@@ -549,7 +550,7 @@ def run_hier_workload(HW, args):
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["bf16"],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["bf16"], 4), "traffic": None,
                      "kernel": "nb_hier_query (grouped forward per level + scan + expansion; host sync per level)",
-                     "flop": hier_flop},
+                     "flop": hier_flop, "tile_variant": variant},
     }
 
 

@@ -9,6 +9,8 @@ batch with HIP events, keeps the fastest, and remembers the choice per
 
 from __future__ import annotations
 
+import time
+
 import torch
 
 from . import Bound, nb_bound_forward, nb_bound_num_variants, nb_bound_set_variant
@@ -85,3 +87,24 @@ def tune_group(group, q: torch.Tensor, qoff: torch.Tensor, reps: int = 5) -> int
     v = _CACHE[k][0]
     nb_group_set_variant(group.handle, v)
     return v
+
+
+def tune_hierarchy(hier, q: torch.Tensor, reps: int = 3) -> int:
+    """Select the grouped-forward tile shape under which a whole hierarchy
+    query (every level) runs fastest for these rows; returns it."""
+    from . import nb_group_num_variants, nb_group_set_variant
+    g = hier.group
+    best, best_ms = 0, float("inf")
+    for v in range(nb_group_num_variants(g.handle)):
+        nb_group_set_variant(g.handle, v)
+        hier.query(q)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            hier.query(q)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        if ms < best_ms:
+            best, best_ms = v, ms
+    nb_group_set_variant(g.handle, best)
+    return best
