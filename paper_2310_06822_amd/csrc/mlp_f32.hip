@@ -41,7 +41,11 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
 // ReLU output itself (its sign is the derivative), or the pre-activation z
 // for sine (value sin z, derivative cos z).
 template <int ACT>
-__device__ __forceinline__ float act_apply(float z) { return ACT == 0 ? fmaxf(z, 0.0f) : sinf(z); }
+__device__ __forceinline__ float act_apply(float z) {
+  // ReLU as the median of (z, 0, FLT_MAX): max(z, 0) in one instruction for
+  // every finite z (+inf becomes FLT_MAX)
+  return ACT == 0 ? __builtin_amdgcn_fmed3f(z, 0.0f, 3.40282347e38f) : sinf(z);
+}
 template <int ACT>
 __device__ __forceinline__ float act_store(float z) { return ACT == 0 ? fmaxf(z, 0.0f) : z; }
 template <int ACT>
@@ -103,8 +107,21 @@ __global__ void k_pack(const float* __restrict__ theta, int in_dim, int W, int N
 
 // ------------------------------------------------------------------ forward
 
+// Waves per SIMD the forward asks the register allocator for: two while the
+// weights held in registers leave room (all but the widest, deepest nets).
+// Width-64 networks read their hidden weights from LDS (one 16-byte read
+// per lane feeds four products), which frees the registers for four waves
+// per SIMD; narrower ones keep them in registers.
+template <int W>
+constexpr bool fwd_lds_weights() { return W >= 64; }
+template <int W, int NH, int ACT>
+constexpr int fwd_waves() {
+  return fwd_lds_weights<W>() ? 4 : (W * W * (NH - 1) > 64 * 64 * (ACT == 0 ? 2 : 1) ? 1 : 2);
+}
+
 template <int KIN, int W, int NH, int ACT>
-__global__ __launch_bounds__(256) void k_fwd(const float* __restrict__ q, int64_t n, int in_dim,
+__global__ __launch_bounds__(256, (fwd_waves<W, NH, ACT>())) void k_fwd(const float* __restrict__ q, int64_t n,
+                                                                   int in_dim,
                                              const float* __restrict__ pack, const float* __restrict__ theta,
                                              float tau, float* __restrict__ logits, uint8_t* __restrict__ hout,
                                              const uint8_t* __restrict__ g, unsigned long long* __restrict__ counts,
@@ -117,10 +134,24 @@ __global__ __launch_bounds__(256) void k_fwd(const float* __restrict__ q, int64_
   float w1[N::F1];
 #pragma unroll
   for (int f = 0; f < N::F1; ++f) w1[f] = pack[f * 64 + lane];
-  constexpr int NWH = (NH - 1) * N::FH > 0 ? (NH - 1) * N::FH : 1;
+  constexpr bool kLdsW = fwd_lds_weights<W>();
+  constexpr int NWH = (!kLdsW && (NH - 1) * N::FH > 0) ? (NH - 1) * N::FH : 1;
   float wh[NWH];
+  if constexpr (!kLdsW) {
 #pragma unroll
-  for (int f = 0; f < (NH - 1) * N::FH; ++f) wh[f] = pack[(N::F1 + f) * 64 + lane];
+    for (int f = 0; f < (NH - 1) * N::FH; ++f) wh[f] = pack[(N::F1 + f) * 64 + lane];
+  }
+  // LDS copy of the hidden weights: entry ((l-1) RB^2 + mo RB + mi) * 64 + lane
+  // holds fragments r = 0..3 of (layer l, row block mo, column block mi)
+  constexpr int NW4 = (kLdsW && NH > 1) ? (NH - 1) * RB * RB * 64 : 1;
+  __shared__ floatx4 swh[NW4];
+  if constexpr (kLdsW) {
+    for (int i = threadIdx.x; i < (NH - 1) * RB * RB * 64; i += blockDim.x) {
+      const int f0 = N::F1 + (i >> 6) * 4, ln = i & 63;
+      swh[i] = floatx4{pack[f0 * 64 + ln], pack[(f0 + 1) * 64 + ln], pack[(f0 + 2) * 64 + ln],
+                       pack[(f0 + 3) * 64 + ln]};
+    }
+  }
   float wo[RB * 4];
 #pragma unroll
   for (int mo = 0; mo < RB; ++mo)
@@ -128,15 +159,32 @@ __global__ __launch_bounds__(256) void k_fwd(const float* __restrict__ q, int64_
     for (int r = 0; r < 4; ++r) wo[mo * 4 + r] = theta[nb_w_off(NH, in_dim, W) + 16 * mo + 4 * grp + r];
   const float bo = theta[nb_b_off(NH, in_dim, W, NH)];
 
+  // hidden biases in LDS: read there, they do not queue behind the input
+  // prefetch in the vector-memory counter
+  __shared__ float sb[NH * W];
+  for (int i = threadIdx.x; i < NH * W; i += blockDim.x) sb[i] = theta[nb_b_off(i / W, in_dim, W, NH) + i % W];
+  __syncthreads();
+
   unsigned cnt[4] = {0u, 0u, 0u, 0u};
   const int64_t nblk = (n + 15) / 16;
   const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
-  for (int64_t blk = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); blk < nblk; blk += nwaves) {
+  // Raw inputs of a block: the load is always in bounds (row and input
+  // clamped); values outside the rows or inputs are zeroed where they are
+  // used.
+  auto load_raw = [&](int64_t blk, float* raw) {
+    const int64_t qi = std::min<int64_t>(blk * 16 + c, n - 1);
+#pragma unroll
+    for (int s = 0; s < KIN; ++s) raw[s] = q[qi * in_dim + std::min(4 * s + grp, in_dim - 1)];
+  };
+  auto process = [&](int64_t blk, const float* raw) {
     const int64_t qi = blk * 16 + c;
     const bool valid = qi < n;
+    float xs[KIN];
+#pragma unroll
+    for (int s = 0; s < KIN; ++s) xs[s] = (valid && 4 * s + grp < in_dim) ? raw[s] : 0.0f;
     float a[RB * 4];
     {
-      const float* b0 = theta + nb_b_off(0, in_dim, W, NH);
+      const float* b0 = sb;
       floatx4 acc[RB];
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo)
@@ -144,10 +192,8 @@ __global__ __launch_bounds__(256) void k_fwd(const float* __restrict__ q, int64_
                           b0[16 * mo + 4 * grp + 3]};
 #pragma unroll
       for (int s = 0; s < KIN; ++s) {
-        const int k = 4 * s + grp;
-        const float x = (valid && k < in_dim) ? q[qi * in_dim + k] : 0.0f;
 #pragma unroll
-        for (int mo = 0; mo < RB; ++mo) acc[mo] = mfma4(w1[mo * KIN + s], x, acc[mo]);
+        for (int mo = 0; mo < RB; ++mo) acc[mo] = mfma4(w1[mo * KIN + s], xs[s], acc[mo]);
       }
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo)
@@ -156,19 +202,33 @@ __global__ __launch_bounds__(256) void k_fwd(const float* __restrict__ q, int64_
     }
 #pragma unroll
     for (int l = 1; l < NH; ++l) {
-      const float* bl = theta + nb_b_off(l, in_dim, W, NH);
+      const float* bl = sb + l * W;
       floatx4 acc[RB];
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo)
         acc[mo] = floatx4{bl[16 * mo + 4 * grp], bl[16 * mo + 4 * grp + 1], bl[16 * mo + 4 * grp + 2],
                           bl[16 * mo + 4 * grp + 3]};
+      // every acc[mo] takes its products in (mi, r) order either way
+      if constexpr (kLdsW) {
 #pragma unroll
-      for (int mi = 0; mi < RB; ++mi)
+        for (int mi = 0; mi < RB; ++mi) {
+          floatx4 w4[RB];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+          for (int mo = 0; mo < RB; ++mo) w4[mo] = swh[((l - 1) * RB * RB + mo * RB + mi) * 64 + lane];
 #pragma unroll
-          for (int mo = 0; mo < RB; ++mo)
-            acc[mo] = mfma4(wh[(l - 1) * N::FH + (mo * RB + mi) * 4 + r], a[mi * 4 + r], acc[mo]);
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int mo = 0; mo < RB; ++mo) acc[mo] = mfma4(w4[mo][r], a[mi * 4 + r], acc[mo]);
+        }
+      } else {
+#pragma unroll
+        for (int mi = 0; mi < RB; ++mi)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int mo = 0; mo < RB; ++mo)
+              acc[mo] = mfma4(wh[(l - 1) * N::FH + (mo * RB + mi) * 4 + r], a[mi * 4 + r], acc[mo]);
+      }
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo)
 #pragma unroll
@@ -193,6 +253,19 @@ __global__ __launch_bounds__(256) void k_fwd(const float* __restrict__ q, int64_
       cnt[2] += __popcll(__ballot(own && !pos && !gv));
       cnt[3] += __popcll(__ballot(own && !pos && gv));
     }
+  };
+  // the block index is the same on every lane of the wave: keep it scalar
+  int64_t blk = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t last = nblk - 1;
+  float rnext[KIN];
+  if (blk < nblk) load_raw(blk, rnext);
+  for (; blk < nblk; blk += nwaves) {
+    float raw[KIN];
+#pragma unroll
+    for (int s = 0; s < KIN; ++s) raw[s] = rnext[s];
+    load_raw(std::min(blk + nwaves, last), rnext);   // the next block's inputs load while this one computes
+    __builtin_amdgcn_sched_barrier(0);               // keep the load issued ahead of the products
+    process(blk, raw);
   }
   if (counts && lane == 0) {
 #pragma unroll
@@ -503,7 +576,7 @@ nb_status fwd_launch(const nb_bound* b, const float* q, int64_t n, float tau, fl
                      const uint8_t* g, unsigned long long* counts, const unsigned long long* n_dev, hipStream_t s) {
   const int64_t nblk = (n + 15) / 16;
   const int64_t want = (nblk + 3) / 4;
-  const int64_t cap = (int64_t)nb_cu_count() * 2;
+  const int64_t cap = (int64_t)nb_cu_count() * std::max(2, fwd_waves<W, NH, ACT>());
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min(want, cap));
   k_fwd<KIN, W, NH, ACT><<<grid, 256, 0, s>>>(q, n, b->in_dim, b->pack, b->theta, tau, logits, h, g, counts, n_dev);
   NB_LAUNCHED();
