@@ -293,27 +293,44 @@ __global__ __launch_bounds__(kKdopThreads) void k_kdop_train(const float* __rest
   }
 }
 
-// Sum of the partials in workgroup order, then Adam; loss and counts.
-__global__ void k_kdop_reduce(const float* __restrict__ partial, const float* __restrict__ aux, int n_wg, int P,
-                              float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v,
-                              AdamArgs adam, float* __restrict__ loss, float loss_scale,
-                              unsigned long long* __restrict__ counts) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+// One block per parameter (and a last block for the loss and counts): the
+// workgroup partials are summed by a fixed pairwise tree (deterministic), then
+// Adam.
+constexpr int kReduceThreads = 256;
+static_assert(kKdopMaxWG <= kReduceThreads, "one reduction thread per training workgroup");
+
+__global__ __launch_bounds__(kReduceThreads) void k_kdop_reduce(
+    const float* __restrict__ partial, const float* __restrict__ aux, int n_wg, int P, float* __restrict__ theta,
+    float* __restrict__ m, float* __restrict__ v, AdamArgs adam, float* __restrict__ loss, float loss_scale,
+    unsigned long long* __restrict__ counts) {
+  __shared__ float sf[kReduceThreads];
+  __shared__ unsigned long long sc[4][kReduceThreads];
+  const int t = threadIdx.x, p = blockIdx.x;
   if (p < P) {
-    float tot = partial[p];
-    for (int w = 1; w < n_wg; ++w) tot += partial[(int64_t)w * P + p];
-    nb_adam_update(p, tot, theta, m, v, adam, false);
+    sf[t] = t < n_wg ? partial[(int64_t)t * P + p] : 0.0f;
+  } else {
+    sf[t] = t < n_wg ? aux[t * 8] : 0.0f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sc[c][t] = t < n_wg ? (unsigned long long)__float_as_uint(aux[t * 8 + 1 + c]) : 0ull;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    float ls = 0.0f;
-    unsigned long long cs[4] = {0, 0, 0, 0};
-    for (int w = 0; w < n_wg; ++w) {
-      ls += aux[w * 8];
-      for (int c = 0; c < 4; ++c) cs[c] += __float_as_uint(aux[w * 8 + 1 + c]);
+  __syncthreads();
+  for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
+    if (t < h) {
+      sf[t] += sf[t + h];
+      if (p == P)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sc[c][t] += sc[c][t + h];
     }
-    if (loss) *loss = ls * loss_scale;
+    __syncthreads();
+  }
+  if (t != 0) return;
+  if (p < P) {
+    nb_adam_update(p, sf[0], theta, m, v, adam, false);
+  } else {
+    if (loss) *loss = sf[0] * loss_scale;
     if (counts)
-      for (int c = 0; c < 4; ++c) counts[c] = cs[c];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) counts[c] = sc[c][0];
   }
 }
 
@@ -469,9 +486,9 @@ nb_status nb_kdop_train_step(nb_kdop* b, const nb_indicator* ind, int kind, uint
   a.eps = 1e-8f;
   a.bc1 = (float)(1.0 - std::pow((double)a.b1, (double)b->adam_t));
   a.bc2 = (float)(1.0 - std::pow((double)a.b2, (double)b->adam_t));
-  k_kdop_reduce<<<(unsigned)((b->P + 63) / 64), 64, 0, s>>>(b->partial, b->aux, n_wg, (int)b->P, b->theta, b->m,
-                                                             b->v, a, loss, inv_n,
-                                                             reinterpret_cast<unsigned long long*>(counts));
+  k_kdop_reduce<<<(unsigned)b->P + 1, kReduceThreads, 0, s>>>(b->partial, b->aux, n_wg, (int)b->P, b->theta, b->m,
+                                                               b->v, a, loss, inv_n,
+                                                               reinterpret_cast<unsigned long long*>(counts));
   NB_LAUNCHED();
   return NB_OK;
 }
