@@ -247,9 +247,12 @@ __global__ __launch_bounds__(256, 1) void k_fwd_bf16_stream(const float* __restr
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
+      for (int ks = 0; ks < KS; ++ks) {
+        float v[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) act[nb][ks][j] = (__bf16)fmaxf(acc[nb][2 * ks + j / 4][j % 4], 0.0f);
+        for (int j = 0; j < 8; ++j) v[j] = acc[nb][2 * ks + j / 4][j % 4];
+        act[nb][ks] = nb_relu_bf16x8(v);
+      }
 
 #pragma unroll 1
     for (int l = 1; l < NH; ++l) {
@@ -308,9 +311,12 @@ __global__ __launch_bounds__(256, 1) void k_fwd_bf16_stream(const float* __restr
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
+            for (int ks = 0; ks < KS; ++ks) {
+              float v[8];
 #pragma unroll
-              for (int j = 0; j < 8; ++j) act[nb][ks][j] = (__bf16)fmaxf(acc[nb][2 * ks + j / 4][j % 4], 0.0f);
+              for (int j = 0; j < 8; ++j) v[j] = acc[nb][2 * ks + j / 4][j % 4];
+              act[nb][ks] = nb_relu_bf16x8(v);
+            }
         }
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
@@ -322,7 +328,7 @@ __global__ __launch_bounds__(256, 1) void k_fwd_bf16_stream(const float* __restr
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) p = fmaf(swo[16 * mo + 4 * grp + r], fmaxf(acc[nb][mo][r], 0.0f), p);
+        for (int r = 0; r < 4; ++r) p = fmaf(swo[16 * mo + 4 * grp + r], nb_relu(acc[nb][mo][r]), p);
       p += __shfl_xor(p, 16);
       p += __shfl_xor(p, 32);
       const float z = p + bo;

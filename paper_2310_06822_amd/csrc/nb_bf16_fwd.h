@@ -100,9 +100,12 @@ __device__ __forceinline__ void bf16_fwd_tile_x(const bf16x8* __restrict__ swt, 
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
+        for (int ks = 0; ks < KS; ++ks) {
+          float v[8];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) act[nb][ks][j] = (__bf16)fmaxf(acc[nb][2 * ks + j / 4][j % 4], 0.0f);
+          for (int j = 0; j < 8; ++j) v[j] = acc[nb][2 * ks + j / 4][j % 4];
+          act[nb][ks] = nb_relu_bf16x8(v);
+        }
       const bf16x8* fr = swt + (RB + (l - 1) * N::FH) * 64 + lane;
       // row block mo's bias quad (16-byte aligned: sbias is, W is a multiple of 4)
       const floatx4* sb4 = reinterpret_cast<const floatx4*>(sbias + l * W) + grp;
@@ -147,7 +150,7 @@ __device__ __forceinline__ void bf16_fwd_tile_x(const bf16x8* __restrict__ swt, 
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) p = fmaf(swo[16 * mo + 4 * grp + r], fmaxf(acc[nb][mo][r], 0.0f), p);
+        for (int r = 0; r < 4; ++r) p = fmaf(swo[16 * mo + 4 * grp + r], nb_relu(acc[nb][mo][r]), p);
       p += __shfl_xor(p, 16);
       p += __shfl_xor(p, 32);
       const float z = p + bo;

@@ -9,6 +9,31 @@
 typedef __bf16 nb_bf16x8 __attribute__((ext_vector_type(8)));
 typedef float nb_floatx4 __attribute__((ext_vector_type(4)));
 
+typedef __bf16 nb_bf16x2 __attribute__((ext_vector_type(2)));
+typedef float nb_float2 __attribute__((ext_vector_type(2)));
+typedef short nb_short2 __attribute__((ext_vector_type(2)));
+typedef unsigned nb_uint4 __attribute__((ext_vector_type(4)));
+
+// max(z, 0) in one instruction for every finite z (+inf becomes FLT_MAX).
+__device__ __forceinline__ float nb_relu(float z) { return __builtin_amdgcn_fmed3f(z, 0.0f, 3.40282347e38f); }
+
+// max(v_j, 0) rounded to bfloat16 for 8 values: each pair is rounded to
+// nearest even by one packed conversion, then a packed signed 16-bit max with
+// 0 clears the negative ones (a bfloat16 with its sign bit set is a negative
+// 16-bit integer).  The same bits as rounding max(v_j, 0), NaN aside, in 8
+// instructions.
+__device__ __forceinline__ nb_bf16x8 nb_relu_bf16x8(const float (&v)[8]) {
+  nb_uint4 u;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const nb_float2 f = {v[2 * p], v[2 * p + 1]};
+    const nb_bf16x2 b = __builtin_convertvector(f, nb_bf16x2);
+    const nb_short2 m = __builtin_elementwise_max(__builtin_bit_cast(nb_short2, b), (nb_short2)0);
+    u[p] = __builtin_bit_cast(unsigned, m);
+  }
+  return __builtin_bit_cast(nb_bf16x8, u);
+}
+
 // Offsets into theta for an in_dim -> W^NH -> 1 network (linear-layer layout):
 // layer l's weight matrix starts at nb_w_off(l), its bias at nb_b_off(l).
 __host__ __device__ inline int64_t nb_w_off(int l, int in_dim, int W) {
