@@ -56,7 +56,7 @@ enum {
   NB_ERR_HIP = 3,         /* a HIP runtime call failed (message has the code) */
   NB_ERR_OOM = 4,         /* device allocation failed */
   NB_ERR_NONFINITE = 5,   /* reserved: non-finite loss detected */
-  NB_ERR_UNSUPPORTED = 6  /* valid request this build has no kernel for */
+  NB_ERR_UNSUPPORTED = 6  /* valid request the library has no kernel for */
 };
 
 /* Query kinds (Sec. 4.2, "Query types"). */

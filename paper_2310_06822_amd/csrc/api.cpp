@@ -56,7 +56,7 @@ nb_status repack(const nb_bound* b, hipStream_t s) {
 
 nb_status require_training(const nb_bound* b) {
   if (b->precision == NB_BF16 && !bf16_train_supported(b->in_dim, b->n_hidden, b->width)) {
-    nb_set_error("training a bfloat16 bound %d x %d^%d has no kernel in this build", b->in_dim, b->width,
+    nb_set_error("training a bfloat16 bound %d x %d^%d has no kernel in this library", b->in_dim, b->width,
                  b->n_hidden);
     return NB_ERR_UNSUPPORTED;
   }

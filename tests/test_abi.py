@@ -58,7 +58,7 @@ def test_invalid_arguments():
 def test_unsupported_shape_reported():
     lib = _lib.load()
     h = C.c_void_p()
-    # shapes this build has no kernel for
+    # shapes the library has no kernel for
     assert lib.nb_bound_create(3, 3, 48, 0, C.byref(h)) == 6
     assert lib.nb_bound_create(3, 5, 64, 0, C.byref(h)) == 6
     assert lib.nb_bound_create(3, 6, 128, 1, C.byref(h)) == 6
