@@ -33,7 +33,10 @@
  *   - The decision uses the output epsilon of the supplemental "Numerics"
  *     paragraph: h = 1 iff sigmoid(z) + eps >= 1/2, evaluated as
  *     !(z < tau) with tau = ln((1/2 - eps)/(1/2 + eps)) rounded to float32.
- *     NaN logits give h = 1 (the conservative side).
+ *     NaN logits give h = 1 (the conservative side).  A query row with a
+ *     non-finite value (NaN or +-inf) cannot be bounded: every forward
+ *     (single, grouped, streamed, early-out, k-DOP) gives it logit NaN and
+ *     so h = 1; such rows never raise an error.
  *   - The handles (nb_indicator, nb_bound) own device memory on the device
  *     that was current when they were created; use them with that device
  *     current.  A handle may be used from one stream at a time.

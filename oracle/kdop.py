@@ -74,7 +74,10 @@ def margins(theta, d: int, k: int, kind: str, q):
 def forward(theta, d: int, k: int, kind: str, q):
     """Logits z = s min_j m_j, float64[n]."""
     s = unpack(theta, d, k)[3]
-    return s * margins(theta, d, k, kind, q).min(axis=1)
+    with np.errstate(invalid="ignore"):
+        z = s * margins(theta, d, k, kind, q).min(axis=1)
+    # a region with a non-finite parameter: NaN, decided positive
+    return np.where(np.all(np.isfinite(np.asarray(q, dtype=np.float64)), axis=1), z, np.nan)
 
 
 def backward(theta, d: int, k: int, kind: str, q, dz):

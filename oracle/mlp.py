@@ -109,6 +109,9 @@ def forward(theta, in_dim: int, widths, x, bf16: bool = False, keep: bool = Fals
         pre.append(z)
         a = _act(z, act) if l + 1 < len(layers) else z
     z = a[:, 0]
+    # a region with a non-finite parameter cannot be bounded: its logit is NaN,
+    # which the decision takes as positive (the conservative side, h >= g)
+    z = np.where(np.all(np.isfinite(np.asarray(x, dtype=np.float32)), axis=1), z, np.nan)
     if keep:
         return z, inputs, pre
     return z

@@ -133,11 +133,16 @@ __global__ __launch_bounds__(kKdopThreads) void k_kdop_fwd(const float* __restri
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad; i += stride) {
     const bool valid = i < n;
     float r[R];
+    bool bad = false;
 #pragma unroll
-    for (int t = 0; t < R; ++t) r[t] = valid ? q[i * R + t] : 0.0f;
+    for (int t = 0; t < R; ++t) {
+      r[t] = valid ? q[i * R + t] : 0.0f;
+      bad = bad || !isfinite(r[t]);
+    }
     int jb;
     bool sh;
-    const float z = P.s * margin<D, KIND>(P, k, r, jb, sh);
+    const float m = P.s * margin<D, KIND>(P, k, r, jb, sh);
+    const float z = bad ? __builtin_nanf("") : m;   // non-finite row: NaN, decided positive
     const bool pos = !(z < tau);
     if (valid) {
       if (logits) logits[i] = z;

@@ -222,6 +222,7 @@ __global__ __launch_bounds__(256, 1) void k_fwd_bf16_stream(const float* __restr
   for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int64_t q0 = (tile * S::WAVES + wave) * NB * 16;
     floatx4 acc[NB][RB];
+    bool bad[NB];   // rows with a non-finite value
     {
       bf16x8 xb[NB];
       {
@@ -229,8 +230,12 @@ __global__ __launch_bounds__(256, 1) void k_fwd_bf16_stream(const float* __restr
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
           const bool valid = q0 + nb * 16 + c < n;
+          bad[nb] = false;
 #pragma unroll
-          for (int j = 0; j < 8; ++j) xr[nb][j] = (valid && j < in_dim) ? sin[(nb * 16 + c) * in_dim + j] : 0.0f;
+          for (int j = 0; j < 8; ++j) {
+            xr[nb][j] = (valid && j < in_dim) ? sin[(nb * 16 + c) * in_dim + j] : 0.0f;
+            bad[nb] = bad[nb] || !isfinite(xr[nb][j]);
+          }
         }
         split_inputs<NB>(xr, grp, xb);
       }
@@ -331,7 +336,7 @@ __global__ __launch_bounds__(256, 1) void k_fwd_bf16_stream(const float* __restr
         for (int r = 0; r < 4; ++r) p = fmaf(swo[16 * mo + 4 * grp + r], nb_relu(acc[nb][mo][r]), p);
       p += __shfl_xor(p, 16);
       p += __shfl_xor(p, 32);
-      const float z = p + bo;
+      const float z = bad[nb] ? __builtin_nanf("") : p + bo;   // non-finite row: NaN, decided positive
       const int64_t qi = q0 + nb * 16 + c;
       const bool own = grp == 0 && qi < n;
       const bool pos = !(z < tau);

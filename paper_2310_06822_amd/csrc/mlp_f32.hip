@@ -180,8 +180,13 @@ __global__ __launch_bounds__(256, (fwd_waves<W, NH, ACT>())) void k_fwd(const fl
     const int64_t qi = blk * 16 + c;
     const bool valid = qi < n;
     float xs[KIN];
+    int bad = 0;   // a non-finite input value in this lane's share of the row
 #pragma unroll
-    for (int s = 0; s < KIN; ++s) xs[s] = (valid && 4 * s + grp < in_dim) ? raw[s] : 0.0f;
+    for (int s = 0; s < KIN; ++s) {
+      const bool use = valid && 4 * s + grp < in_dim;
+      xs[s] = use ? raw[s] : 0.0f;
+      bad |= use && !isfinite(raw[s]);
+    }
     float a[RB * 4];
     {
       const float* b0 = sb;
@@ -239,7 +244,10 @@ __global__ __launch_bounds__(256, (fwd_waves<W, NH, ACT>())) void k_fwd(const fl
     for (int i = 0; i < RB * 4; ++i) p = fmaf(wo[i], a[i], p);
     p += __shfl_xor(p, 16);
     p += __shfl_xor(p, 32);
-    const float z = p + bo;
+    bad |= __shfl_xor(bad, 16);
+    bad |= __shfl_xor(bad, 32);
+    // a row with a non-finite value gets logit NaN, hence a positive decision
+    const float z = bad ? __builtin_nanf("") : p + bo;
     const bool pos = !(z < tau);
     const bool own = grp == 0 && valid;
     if (own) {

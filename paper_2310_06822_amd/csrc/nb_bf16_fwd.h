@@ -81,6 +81,15 @@ __device__ __forceinline__ void bf16_fwd_tile_x(const bf16x8* __restrict__ swt, 
   const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4;
   const float* swo = sbias + NH * W;
   const float bo = swo[W];
+  // rows with a non-finite value (every lane of a query column holds the
+  // whole row; values beyond in_dim are zero)
+  bool bad[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    bad[nb] = false;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) bad[nb] = bad[nb] || !isfinite(xr[nb][j]);
+  }
     floatx4 acc[NB][RB];
     {
       bf16x8 xb[NB];
@@ -153,7 +162,7 @@ __device__ __forceinline__ void bf16_fwd_tile_x(const bf16x8* __restrict__ swt, 
         for (int r = 0; r < 4; ++r) p = fmaf(swo[16 * mo + 4 * grp + r], nb_relu(acc[nb][mo][r]), p);
       p += __shfl_xor(p, 16);
       p += __shfl_xor(p, 32);
-      const float z = p + bo;
+      const float z = bad[nb] ? __builtin_nanf("") : p + bo;   // non-finite row: NaN, decided positive
       const int64_t qi = q0 + nb * 16 + c;
       const bool own = grp == 0 && qi < n;
       const bool pos = !(z < tau);

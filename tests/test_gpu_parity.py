@@ -738,3 +738,58 @@ def test_trained_bound_gain_over_exact_test_alone(c2_grid):
     assert torch.equal(ans, g)                  # conservative: the cascade is the exact test
     assert n_exact < 0.25 * n                   # the exact test runs on under a quarter of the queries
     assert n_exact >= positives                 # (it still sees every true hit)
+
+
+def _with_nonfinite(q, seed, frac=0.03):
+    """A copy of q with a non-finite value (NaN, +inf or -inf) in a random
+    column of about frac of the rows; also the mask of those rows."""
+    g = np.random.default_rng(seed)
+    bad = g.random(q.shape[0]) < frac
+    bad[0] = bad[-1] = True
+    qb = q.copy()
+    vals = np.array([np.nan, np.inf, -np.inf], np.float32)
+    for r in np.nonzero(bad)[0]:
+        qb[r, g.integers(q.shape[1])] = vals[g.integers(3)]
+    return qb, bad
+
+
+def _check_nonfinite(forward, q, seed):
+    qb, bad = _with_nonfinite(q, seed)
+    z, h = forward(cuda(qb))
+    z0, h0 = forward(cuda(q))
+    z, h, z0, h0 = host(z), host(h), host(z0), host(h0)
+    assert np.all(np.isnan(z[bad])) and np.all(h[bad] == 1)
+    assert np.array_equal(bits(z[~bad]), bits(z0[~bad])) and np.array_equal(h[~bad], h0[~bad])
+
+
+@pytest.mark.parametrize("prec,act,d,w,nh", [(nb.F32, "relu", 3, 64, 3), (nb.F32, "relu", 5, 32, 2),
+                                             (nb.F32, "sine", 3, 64, 2), (nb.BF16, "relu", 6, 128, 4),
+                                             (nb.BF16, "relu", 4, 256, 3)])
+def test_nonfinite_rows_decided_positive(prec, act, d, w, nh):
+    """Boundary rule: a query row with a NaN or infinite value gets logit NaN
+    and decision 1 (the conservative side); the other rows are untouched."""
+    b = nb.Bound(d, nh, w, prec)
+    if act == "sine":
+        nb.nb_bound_set_activation(b.handle, nb.SINE)
+    b.set_params(synth.init_params(150 + w, d, [w] * nh))
+    _check_nonfinite(b.forward, synth.points(151, 3001, d), 152)
+
+
+def test_nonfinite_rows_grouped_kdop_and_early_out():
+    q = synth.points(160, 2001, 6)
+    gr = nb.Group(6, [64, 128], 3)
+    gr.set_params(np.concatenate([synth.init_params(161 + o, 6, [w] * 3) for o, w in enumerate([64, 128])]))
+    qoff = cuda(np.array([0, 900, 2001], np.int64))
+    _check_nonfinite(lambda x: gr.forward(x, qoff), q, 162)
+    kd = nb.KDop(3, 4)
+    kd.set_params(synth.kdop_init(3, 4, seed=163))
+    q3 = synth.points(164, 2001, 3)
+    _check_nonfinite(lambda x: kd.forward("point", x), q3, 165)
+    first, second = nb.Bound(3, 1, 32), nb.Bound(3, 3, 64)
+    first.set_params(synth.init_params(166, 3, [32]))
+    second.set_params(synth.init_params(167, 3, [64] * 3))
+    qb, bad = _with_nonfinite(q3, 168)
+    h = torch.empty(q3.shape[0], dtype=torch.uint8, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    nb.nb_early_out(first.handle, second.handle, cuda(qb), h, cnt)
+    assert np.all(host(h)[bad] == 1)

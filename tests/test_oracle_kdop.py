@@ -103,3 +103,15 @@ def test_conservative_for_regions_meeting_the_kdop():
     t = g.uniform(0, 4, (len(x), 1))
     rays = np.concatenate([x - t * w, w], axis=1)
     assert np.all(kdop.forward(th, d, k, "ray", rays) >= -1e-9)
+
+
+def test_kdop_nonfinite_rows_are_nan():
+    th = synth.kdop_init(3, 4, seed=3)
+    q = synth.points(4, 20, 3)
+    q[5, 1] = np.nan
+    q[7, 0] = -np.inf
+    z = kdop.forward(th, 3, 4, "point", q)
+    assert np.isnan(z[5]) and np.isnan(z[7])
+    ok = np.ones(20, bool)
+    ok[[5, 7]] = False
+    assert np.array_equal(z[ok], kdop.forward(th, 3, 4, "point", q[ok]))

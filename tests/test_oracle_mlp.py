@@ -346,3 +346,20 @@ def test_sine_zero_padding_is_exact():
     assert np.all(gp[~mask] == 0)
     g = mlp.backward(theta, in_dim, small, x, L.dloss_dz(z, y, 3.0, 1.0), act="sine")
     assert np.allclose(gp[mask], g, rtol=1e-10, atol=1e-14)
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_nonfinite_rows_are_nan_and_positive(bf16):
+    """A region with a non-finite parameter gets logit NaN and decision 1;
+    every other row's logit is what it is without those rows."""
+    in_dim, widths = 6, [32] * 2
+    theta = synth.init_params(77, in_dim, widths)
+    q = synth.points(78, 50, in_dim)
+    bad = np.zeros(50, bool)
+    for r, v in ((3, np.nan), (10, np.inf), (11, -np.inf), (49, np.nan)):
+        q[r, r % in_dim] = v
+        bad[r] = True
+    z = mlp.forward(theta, in_dim, widths, q, bf16=bf16)
+    assert np.all(np.isnan(z[bad])) and np.all(np.isfinite(z[~bad]))
+    assert np.all(L.decide(z[bad]) == 1)
+    assert np.array_equal(z[~bad], mlp.forward(theta, in_dim, widths, q[~bad], bf16=bf16))
