@@ -58,7 +58,7 @@ enum {
   NB_ERR_NO_DEVICE = 2,   /* no HIP device visible */
   NB_ERR_HIP = 3,         /* a HIP runtime call failed (message has the code) */
   NB_ERR_OOM = 4,         /* device allocation failed */
-  NB_ERR_NONFINITE = 5,   /* reserved: non-finite loss detected */
+  NB_ERR_NONFINITE = 5,   /* a training step met a non-finite loss or gradient (see *_sync) */
   NB_ERR_UNSUPPORTED = 6  /* valid request the library has no kernel for */
 };
 
@@ -233,6 +233,12 @@ nb_status nb_bound_adam_step(nb_bound* b, const float* grad, float lr, float bet
 nb_status nb_bound_train_step(nb_bound* b, const nb_indicator* ind, int kind, uint64_t seed, uint64_t step,
                               int64_t batch, float alpha, float beta, float lr, float lam1, float lam2,
                               float* loss, uint64_t* counts, void* stream);
+/* Synchronise `stream` and report whether a training call since the last
+ * check (nb_bound_train_step, nb_bound_loss_grad) met a non-finite loss or
+ * gradient: NB_ERR_NONFINITE if so (the flag is then cleared; the parameters
+ * updated from such a gradient are not finite either), NB_OK otherwise.  The
+ * training calls themselves never synchronise to look. */
+nb_status nb_bound_sync(nb_bound* b, void* stream);
 
 /* ------------------------------------------------------------------------
  * Cascade (Sec. 1, Sec. 6 "Tightness"): the bound screens the queries and
@@ -294,6 +300,8 @@ nb_status nb_kdop_forward(const nb_kdop* b, int kind, const float* q, int64_t n,
 nb_status nb_kdop_train_step(nb_kdop* b, const nb_indicator* ind, int kind, uint64_t seed, uint64_t step,
                              int64_t batch, float alpha, float beta, float lr, float* loss, uint64_t* counts,
                              void* stream);
+/* As nb_bound_sync, for the k-DOP's training steps. */
+nb_status nb_kdop_sync(nb_kdop* b, void* stream);
 
 /* ------------------------------------------------------------------------
  * Groups of per-object bounds.  The paper fits one bound per object and does
@@ -364,6 +372,8 @@ nb_status nb_group_set_active(nb_group* g, const uint8_t* active_host);
 nb_status nb_group_train_step(nb_group* g, int kind, uint64_t seed, uint64_t step, int64_t per_obj, float alpha,
                               const float* alpha_obj, float beta, float lr, const float* lr_obj, float* loss,
                               uint64_t* counts, void* stream);
+/* As nb_bound_sync, for the group's training steps (any object). */
+nb_status nb_group_sync(nb_group* g, void* stream);
 
 /* ------------------------------------------------------------------------
  * Neural bounding hierarchies (Sec. 3.3).  The tree is supplied by the

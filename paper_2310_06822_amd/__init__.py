@@ -480,6 +480,22 @@ class Group:
             pass
 
 
+# ------------------------------------------------------- training health
+
+def nb_bound_sync(b, stream=None):
+    """Raise NBError (NB_ERR_NONFINITE) if a training call since the last
+    check met a non-finite loss or gradient; synchronises the stream."""
+    _check(lib().nb_bound_sync(b, _stream(stream)))
+
+
+def nb_group_sync(g, stream=None):
+    _check(lib().nb_group_sync(g, _stream(stream)))
+
+
+def nb_kdop_sync(b, stream=None):
+    _check(lib().nb_kdop_sync(b, _stream(stream)))
+
+
 # ------------------------------------------------------------ hierarchies
 
 def nb_hier_create(g, child_begin, child_end) -> C.c_void_p:

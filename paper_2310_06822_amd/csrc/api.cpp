@@ -346,8 +346,10 @@ nb_status nb_bound_create(int in_dim, int n_hidden, int width, int precision, nb
   if (st == NB_OK) st = dev_alloc(&b->pack16t, (size_t)b->pack16t_elems);
   if (st == NB_OK) st = dev_alloc(&b->partial, (size_t)f32_max_workgroups() * P);
   if (st == NB_OK) st = dev_alloc(&b->aux, (size_t)f32_max_workgroups() * 8);
+  if (st == NB_OK) st = dev_alloc(&b->d_nonfinite, 1);
   if (st == NB_OK) {
     if (hipMemset(b->theta, 0, P * 4) != hipSuccess || hipMemset(b->m, 0, P * 4) != hipSuccess ||
+        hipMemset(b->d_nonfinite, 0, sizeof(unsigned)) != hipSuccess ||
         hipMemset(b->v, 0, P * 4) != hipSuccess ||
         (b->pack && hipMemset(b->pack, 0, (size_t)b->pack_floats * 4) != hipSuccess) ||
         (b->pack16 && hipMemset(b->pack16, 0, (size_t)b->pack16_elems * 2) != hipSuccess)) {
@@ -376,6 +378,7 @@ nb_status nb_bound_destroy(nb_bound* b) {
   dev_free(b->tr_grad);
   dev_free(b->partial);
   dev_free(b->aux);
+  dev_free(b->d_nonfinite);
   dev_free(b->batch_q);
   dev_free(b->batch_y);
   dev_free(b->cascade_idx);
@@ -632,6 +635,19 @@ nb_status nb_cascade(nb_bound* b, const nb_indicator* ind, int kind, const float
   else
     NB_TRY(f32_forward(b, q, n, tau, nullptr, answer, nullptr, nullptr, s));
   return launch_cascade_exact(ind, kind, q, answer, n, b->cascade_idx, cnt, answer, s);
+}
+
+nb_status nb_bound_sync(nb_bound* b, void* stream) {
+  NB_REQUIRE(b, "bound is NULL");
+  NB_HIP(hipStreamSynchronize(as_stream(stream)));
+  unsigned flag = 0;
+  NB_HIP(hipMemcpy(&flag, b->d_nonfinite, sizeof(flag), hipMemcpyDeviceToHost));
+  if (flag) {
+    NB_HIP(hipMemset(b->d_nonfinite, 0, sizeof(unsigned)));
+    nb_set_error("a training step since the last check met a non-finite loss or gradient");
+    return NB_ERR_NONFINITE;
+  }
+  return NB_OK;
 }
 
 }  // extern "C"

@@ -318,7 +318,8 @@ __global__ __launch_bounds__(256) void k_group_reduce(const float* __restrict__ 
                                                       int in_dim, int NH, float* __restrict__ theta,
                                                       float* __restrict__ m, float* __restrict__ v, AdamArgs adam,
                                                       const float* __restrict__ lr_obj,
-                                                      const uint8_t* __restrict__ active) {
+                                                      const uint8_t* __restrict__ active,
+                                                      unsigned* __restrict__ nonfinite) {
   const int o = blockIdx.y;
   // an object outside the trained set has no partials this step; a learning
   // rate of 0 freezes it
@@ -332,6 +333,7 @@ __global__ __launch_bounds__(256) void k_group_reduce(const float* __restrict__ 
   float tot = part[0];
 #pragma unroll
   for (int i = 1; i < 8; ++i) tot += part[i];
+  if (!isfinite(tot)) *nonfinite = 1u;
   AdamArgs a = adam;
   if (lr_obj) a.lr = lr_obj[o];
   // a learning rate of 0 freezes the object: parameters and moments stay
@@ -364,7 +366,7 @@ nb_status group_reduce_adam(const nb_group* gr, int n_wg, const AdamArgs& adam, 
                             unsigned long long* counts, float loss_scale, hipStream_t s) {
   const dim3 grid((unsigned)((gr->max_obj_params + 255) / 256), (unsigned)gr->n_obj);
   k_group_reduce<<<grid, 256, 0, s>>>(gr->partial, n_wg, gr->d_poff, gr->d_widths, gr->in_dim, gr->n_hidden, gr->theta,
-                                      gr->m, gr->v, adam, lr_obj, gr->d_active);
+                                      gr->m, gr->v, adam, lr_obj, gr->d_active, gr->d_nonfinite);
   NB_LAUNCHED();
   if (loss || counts) {
     k_group_aux<<<(unsigned)((gr->n_obj + 255) / 256), 256, 0, s>>>(gr->aux, n_wg, gr->n_obj, loss_scale,

@@ -54,6 +54,7 @@ nb_status nb_group_destroy(nb_group* g) {
   free_p(g->d_perm);
   free_p(g->d_class);
   free_p(g->d_active);
+  free_p(g->d_nonfinite);
   free_p(g->theta);
   free_p(g->m);
   free_p(g->v);
@@ -132,6 +133,7 @@ nb_status nb_group_create(int n_obj, int in_dim, const int* widths_host, int n_h
   if (st == NB_OK) st = upload(&g->d_perm, perm);
   if (st == NB_OK) st = upload(&g->d_class, cls);
   if (st == NB_OK) st = upload(&g->d_active, std::vector<uint8_t>(n_obj, 1));
+  if (st == NB_OK) st = upload(&g->d_nonfinite, std::vector<unsigned>(1, 0u));
   if (st == NB_OK) st = alloc_n(&g->theta, (size_t)g->n_params);
   if (st == NB_OK) st = alloc_n(&g->m, (size_t)g->n_params);
   if (st == NB_OK) st = alloc_n(&g->v, (size_t)g->n_params);
@@ -348,6 +350,19 @@ nb_status nb_group_train_step(nb_group* g, int kind, uint64_t seed, uint64_t ste
   NB_TRY(group_reduce_adam(g, plan.n_wg, a, lr_obj, loss, reinterpret_cast<unsigned long long*>(counts),
                            (float)(1.0 / (double)per_obj), s));
   return group_pack(g, s);
+}
+
+nb_status nb_group_sync(nb_group* g, void* stream) {
+  NB_REQUIRE(g, "group is NULL");
+  NB_HIP(hipStreamSynchronize(as_stream(stream)));
+  unsigned flag = 0;
+  NB_HIP(hipMemcpy(&flag, g->d_nonfinite, sizeof(flag), hipMemcpyDeviceToHost));
+  if (flag) {
+    NB_HIP(hipMemset(g->d_nonfinite, 0, sizeof(unsigned)));
+    nb_set_error("a grouped training step since the last check met a non-finite gradient");
+    return NB_ERR_NONFINITE;
+  }
+  return NB_OK;
 }
 
 }  // extern "C"

@@ -30,6 +30,7 @@ struct nb_kdop {
   float* v = nullptr;
   float* partial = nullptr;   // [kKdopMaxWG][P]
   float* aux = nullptr;       // [kKdopMaxWG][8]: loss, TP, FP, TN, FN
+  unsigned* nonfinite = nullptr;   // device flag: a training step met a non-finite loss or gradient
   float* batch_q = nullptr;
   uint8_t* batch_y = nullptr;
   int64_t batch_cap = 0;
@@ -307,7 +308,7 @@ static_assert(kKdopMaxWG <= kReduceThreads, "one reduction thread per training w
 __global__ __launch_bounds__(kReduceThreads) void k_kdop_reduce(
     const float* __restrict__ partial, const float* __restrict__ aux, int n_wg, int P, float* __restrict__ theta,
     float* __restrict__ m, float* __restrict__ v, AdamArgs adam, float* __restrict__ loss, float loss_scale,
-    unsigned long long* __restrict__ counts) {
+    unsigned long long* __restrict__ counts, unsigned* __restrict__ nonfinite) {
   __shared__ float sf[kReduceThreads];
   __shared__ unsigned long long sc[4][kReduceThreads];
   const int t = threadIdx.x, p = blockIdx.x;
@@ -329,6 +330,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_kdop_reduce(
     __syncthreads();
   }
   if (t != 0) return;
+  if (!isfinite(sf[0])) *nonfinite = 1u;
   if (p < P) {
     nb_adam_update(p, sf[0], theta, m, v, adam, false);
   } else {
@@ -369,6 +371,7 @@ nb_status nb_kdop_destroy(nb_kdop* b) {
   for (float* p : {b->theta, b->m, b->v, b->partial, b->aux, b->batch_q})
     if (p) (void)hipFree(p);
   if (b->batch_y) (void)hipFree(b->batch_y);
+  if (b->nonfinite) (void)hipFree(b->nonfinite);
   delete b;
   return NB_OK;
 }
@@ -391,9 +394,10 @@ nb_status nb_kdop_create(int dim, int k, nb_kdop** out) {
   bool ok = hipMalloc((void**)&b->theta, b->P * 4) == hipSuccess && hipMalloc((void**)&b->m, b->P * 4) == hipSuccess &&
             hipMalloc((void**)&b->v, b->P * 4) == hipSuccess &&
             hipMalloc((void**)&b->partial, (size_t)kKdopMaxWG * b->P * 4) == hipSuccess &&
-            hipMalloc((void**)&b->aux, (size_t)kKdopMaxWG * 8 * 4) == hipSuccess;
+            hipMalloc((void**)&b->aux, (size_t)kKdopMaxWG * 8 * 4) == hipSuccess &&
+            hipMalloc((void**)&b->nonfinite, sizeof(unsigned)) == hipSuccess;
   ok = ok && hipMemset(b->theta, 0, b->P * 4) == hipSuccess && hipMemset(b->m, 0, b->P * 4) == hipSuccess &&
-       hipMemset(b->v, 0, b->P * 4) == hipSuccess;
+       hipMemset(b->v, 0, b->P * 4) == hipSuccess && hipMemset(b->nonfinite, 0, sizeof(unsigned)) == hipSuccess;
   if (!ok) {
     nb_set_error("allocating the k-DOP state failed");
     nb_kdop_destroy(b);
@@ -493,8 +497,22 @@ nb_status nb_kdop_train_step(nb_kdop* b, const nb_indicator* ind, int kind, uint
   a.bc2 = (float)(1.0 - std::pow((double)a.b2, (double)b->adam_t));
   k_kdop_reduce<<<(unsigned)b->P + 1, kReduceThreads, 0, s>>>(b->partial, b->aux, n_wg, (int)b->P, b->theta, b->m,
                                                                b->v, a, loss, inv_n,
-                                                               reinterpret_cast<unsigned long long*>(counts));
+                                                               reinterpret_cast<unsigned long long*>(counts),
+                                                               b->nonfinite);
   NB_LAUNCHED();
+  return NB_OK;
+}
+
+nb_status nb_kdop_sync(nb_kdop* b, void* stream) {
+  NB_REQUIRE(b, "k-DOP is NULL");
+  NB_HIP(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+  unsigned flag = 0;
+  NB_HIP(hipMemcpy(&flag, b->nonfinite, sizeof(flag), hipMemcpyDeviceToHost));
+  if (flag) {
+    NB_HIP(hipMemset(b->nonfinite, 0, sizeof(unsigned)));
+    nb_set_error("a k-DOP training step since the last check met a non-finite loss or gradient");
+    return NB_ERR_NONFINITE;
+  }
   return NB_OK;
 }
 

@@ -105,6 +105,7 @@ struct nb_bound {
   int tr_slots = 0;                // activation slots tr_act holds
   uint16_t* tr_grad = nullptr;     // 2 x [padded batch][width]
   int64_t tr_cap = 0;              // padded batch the two above hold
+  unsigned* d_nonfinite = nullptr; // device flag: a training step met a non-finite loss or gradient
 };
 
 struct AdamArgs {
@@ -156,6 +157,7 @@ struct nb_group {
   float* batch_q = nullptr;
   uint8_t* batch_y = nullptr;
   int64_t* d_qoff_train = nullptr;
+  unsigned* d_nonfinite = nullptr;  // device flag: a training step met a non-finite loss or gradient
 };
 
 // ------------------------------------------------------- kernel launchers

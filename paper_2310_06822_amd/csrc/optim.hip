@@ -27,7 +27,8 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
                                                 float* __restrict__ theta, float* __restrict__ m,
                                                 float* __restrict__ v, AdamArgs adam, int in_dim, int width,
                                                 int n_hidden, float* __restrict__ loss, float loss_scale,
-                                                unsigned long long* __restrict__ counts) {
+                                                unsigned long long* __restrict__ counts,
+                                                unsigned* __restrict__ nonfinite) {
   __shared__ float part[kParts][kParamsPerBlock];
   const int t = threadIdx.x, j = t % kParamsPerBlock, k = t / kParamsPerBlock;
   const int64_t p = (int64_t)blockIdx.x * kParamsPerBlock + j;
@@ -41,10 +42,11 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
 #pragma unroll
     for (int i = 1; i < kParts; ++i) tot += part[i][t];
     if (grad) grad[p] = tot;
+    if (!isfinite(tot)) *nonfinite = 1u;
     if (adam.enabled) adam_update(p, tot, theta, m, v, adam, in_dim, width, n_hidden);
   }
   // loss and counts: the last block's first wave, lanes strided over workgroups
-  if (blockIdx.x == gridDim.x - 1 && t < 64 && (loss || counts)) {
+  if (blockIdx.x == gridDim.x - 1 && t < 64) {
     float ls = 0.0f;
     unsigned long long cs[4] = {0, 0, 0, 0};
     for (int w = t; w < n_wg; w += 64) {
@@ -56,6 +58,7 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
       for (int i = 0; i < 4; ++i) cs[i] += __shfl_xor(cs[i], msk);
     }
     if (t == 0) {
+      if (!isfinite(ls)) *nonfinite = 1u;
       if (loss) *loss = ls * loss_scale;
       if (counts)
         for (int i = 0; i < 4; ++i) counts[i] = cs[i];
@@ -81,7 +84,7 @@ nb_status launch_reduce(const nb_bound* b, int n_wg, float* grad, float* loss, f
   const int64_t P = b->n_params;
   const unsigned grid = (unsigned)((P + kParamsPerBlock - 1) / kParamsPerBlock);
   k_reduce<<<grid, 256, 0, s>>>(b->partial, b->aux, n_wg, P, grad, b->theta, b->m, b->v, adam, b->in_dim,
-                                b->width, b->n_hidden, loss, loss_scale, counts);
+                                b->width, b->n_hidden, loss, loss_scale, counts, b->d_nonfinite);
   NB_LAUNCHED();
   return NB_OK;
 }

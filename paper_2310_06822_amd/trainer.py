@@ -86,6 +86,8 @@ def train(bound, ind: Indicator, kind: str, seed: int, sched: Schedule, val_seed
     """Train a Bound (or a KDop: its planes take the same loss and schedule)."""
     k = KINDS[kind]
     if isinstance(bound, KDop):
+        from . import nb_kdop_sync as sync
+
         def nb_bound_train_step(h, ih, kk, sd, st, batch, a, b, lr, lam1, lam2):
             nb_kdop_train_step(h, ih, kk, sd, st, batch, a, b, lr)
 
@@ -93,6 +95,7 @@ def train(bound, ind: Indicator, kind: str, seed: int, sched: Schedule, val_seed
             return bound.counts(kind, q, g)
     else:
         from . import nb_bound_train_step
+        from . import nb_bound_sync as sync
 
         def counts(q, g):
             return bound.counts(q, g)
@@ -110,8 +113,9 @@ def train(bound, ind: Indicator, kind: str, seed: int, sched: Schedule, val_seed
         nb_bound_train_step(bound.handle, ind.handle, k, seed, step, sched.batch, fn_w, fp_w, sched.lr, lam, lam)
         step += 1
         if log and (t + 1) % 1000 == 0:
-            torch.cuda.synchronize()
+            sync(bound.handle)   # raises if a step met a non-finite loss or gradient
             log(f"ramp step {t + 1}/{T}: alpha {a:g}")
+    sync(bound.handle)
     a = sched.alpha_max
     lam = sched.lam_max
     if val is not None:
@@ -124,6 +128,7 @@ def train(bound, ind: Indicator, kind: str, seed: int, sched: Schedule, val_seed
                                     lam, lam)
                 step += 1
             lr = max(sched.lr_min, lr * sched.lr_decay)
+            sync(bound.handle)
             val = validation_set(ind, kind, val_seed, sched.val_n, draw=res.iters, out=val)
             # the error the bound must not make: FN, or FP for an inverted bound
             fn = int(counts(*val)[1 if sched.inverted else 3].item())
@@ -184,7 +189,7 @@ def train_group(group, kind: str, seed: int, sched: Schedule, val_seed: int | No
     sched.batch is the per-object batch."""
     import numpy as np
 
-    from . import nb_group_set_active, nb_group_train_step
+    from . import nb_group_set_active, nb_group_sync, nb_group_train_step
     k = KINDS[kind]
     res = GroupTrainResult()
     torch.cuda.synchronize()
@@ -196,8 +201,9 @@ def train_group(group, kind: str, seed: int, sched: Schedule, val_seed: int | No
         nb_group_train_step(group.handle, group.n_obj, k, seed, step, sched.batch, a, sched.beta, sched.lr)
         step += 1
         if log and (t + 1) % 1000 == 0:
-            torch.cuda.synchronize()
+            nb_group_sync(group.handle)   # raises if a step met a non-finite gradient
             log(f"group ramp step {t + 1}/{T}: alpha {a:g}")
+    nb_group_sync(group.handle)
     samples = step * sched.batch * group.n_obj
     alpha = np.full(group.n_obj, sched.alpha_max, dtype=np.float32)
     lr = np.full(group.n_obj, sched.lr, dtype=np.float32)
@@ -218,6 +224,7 @@ def train_group(group, kind: str, seed: int, sched: Schedule, val_seed: int | No
                     step += 1
                 samples += sched.k * (sched.cont_batch or sched.batch) * int((lr > 0).sum())
             lr_now = max(sched.lr_min, lr_now * sched.lr_decay)
+            nb_group_sync(group.handle)
             val = group_validation_set(group, kind, val_seed, sched.val_n, draw=res.iters, out=val)
             fn = group.counts(*val)[:, 3].cpu().numpy()
             bad = fn > 0

@@ -793,3 +793,42 @@ def test_nonfinite_rows_grouped_kdop_and_early_out():
     cnt = torch.empty(1, dtype=torch.int64, device="cuda")
     nb.nb_early_out(first.handle, second.handle, cuda(qb), h, cnt)
     assert np.all(host(h)[bad] == 1)
+
+
+def test_nonfinite_training_is_reported_on_sync(c2_grid):
+    """A training step that meets a non-finite loss or gradient is reported
+    (NB_ERR_NONFINITE) by the next sync call, which then clears the flag; a
+    healthy run reports nothing."""
+    _, _, grid = c2_grid
+    ind = nb.Indicator.voxels(cuda(grid), 128)
+    for prec, d, w, nh, kind in ((nb.F32, 3, 64, 3, nb.POINT), (nb.BF16, 6, 128, 4, nb.RAY)):
+        b = nb.Bound(d, nh, w, prec)
+        b.set_params(synth.init_params(170 + w, d, [w] * nh))
+        for t in range(3):
+            nb.nb_bound_train_step(b.handle, ind.handle, kind, 171, t, 4096, 1.0)
+        nb.nb_bound_sync(b.handle)
+        b.set_params(np.full(b.n_params, 3e38, np.float32))   # the logits overflow
+        nb.nb_bound_train_step(b.handle, ind.handle, kind, 171, 3, 4096, 1.0)
+        with pytest.raises(nb.NBError) as e:
+            nb.nb_bound_sync(b.handle)
+        assert "non-finite" in str(e.value)
+        nb.nb_bound_sync(b.handle)   # cleared
+    gr = nb.Group(3, [32, 64], 2)
+    gr.set_params(np.concatenate([synth.init_params(172 + o, 3, [w] * 2) for o, w in enumerate([32, 64])]))
+    gs = [I.voxelize_metaballs(*synth.metaballs3d(173 + o, k=6), 32) for o in range(2)]
+    gr.set_voxels(cuda(np.concatenate(gs)), [32, 32])
+    nb.nb_group_train_step(gr.handle, 2, nb.POINT, 174, 0, 1024, 1.0)
+    nb.nb_group_sync(gr.handle)
+    th = host(gr.params())
+    th[: gr.offsets[1]] = 3e38
+    gr.set_params(th)
+    nb.nb_group_train_step(gr.handle, 2, nb.POINT, 174, 1, 1024, 1.0)
+    with pytest.raises(nb.NBError):
+        nb.nb_group_sync(gr.handle)
+    nb.nb_group_sync(gr.handle)
+    kd = nb.KDop(3, 4)
+    kd.set_params(np.full(3 * 4 + 2 * 4 + 1, 3e38, np.float32))
+    nb.nb_kdop_train_step(kd.handle, ind.handle, nb.POINT, 176, 0, 4096, 1.0, 1.0, 1e-3)
+    with pytest.raises(nb.NBError):
+        nb.nb_kdop_sync(kd.handle)
+    nb.nb_kdop_sync(kd.handle)
