@@ -82,10 +82,21 @@ def cpu_baseline(W, theta, seconds: float = 15.0):
     for _ in range(reps):
         L.decide(mlp.forward(theta, W.in_dim, widths, q, bf16=bf16))
     dt = time.perf_counter() - t0
-    return {"value": reps * chunk / dt, "unit": "bound queries/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{reps} x {chunk} queries of the {W.name} workload, float64 numpy forward"
-                      f"{' (bfloat16 rounding model)' if bf16 else ''} + decision, {dt:.1f} s, "
-                      f"{os.cpu_count()} host cores"}
+    out = {"value": reps * chunk / dt, "unit": "bound queries/s", "cores": int(cores), "kind": "oracle",
+           "sample": f"{reps} x {chunk} queries of the {W.name} workload, float64 numpy forward"
+                     f"{' (bfloat16 rounding model)' if bf16 else ''} + decision, {dt:.1f} s, "
+                     f"{os.cpu_count()} host cores"}
+    try:   # the same on one core, a shorter sample
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(1):
+            reps1 = max(1, reps // max(1, int(cores)))
+            t0 = time.perf_counter()
+            for _ in range(reps1):
+                L.decide(mlp.forward(theta, W.in_dim, widths, q, bf16=bf16))
+            out["value_one_core"] = reps1 * chunk / (time.perf_counter() - t0)
+    except Exception:
+        pass
+    return out
 
 
 def build_indicator(W, nb, synth):
