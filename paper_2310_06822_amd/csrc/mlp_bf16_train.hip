@@ -472,49 +472,71 @@ __global__ __launch_bounds__(WAVES * 64) void k_tr_weight(const uint16_t* __rest
 // takes neuron t % W and every S-th query of each 256-query slab (S = 1024 / W,
 // subset t / W); the slab's inputs sit in LDS; the S subset sums are added in
 // subset order at the end.
-constexpr int kFG = 1024;
-constexpr int kFGSlab = 256;
+constexpr int kFG = 512;
 
+// dW_0 = sum_i delta_0 x^T and db_0 = sum_i delta_0 over a chunk of the batch,
+// one partial per workgroup.  A lane takes 8 neurons of a sample (one 16-byte
+// load of delta_0); the lanes of a wave holding the same neurons are summed by
+// a fixed butterfly, then the waves in order through LDS (deterministic).
+template <int W>
 __global__ __launch_bounds__(kFG) void k_tr_first_grad(const uint16_t* __restrict__ D0, const float* __restrict__ q,
-                                                       int64_t n, int64_t CH, int in_dim, int W, int NH,
+                                                       int64_t n, int64_t CH, int in_dim, int NH,
                                                        float* __restrict__ partial, TrObjs TO) {
+  constexpr int G = W / 8;        // lanes per sample
+  constexpr int S = kFG / G;      // samples per workgroup pass
+  static_assert(64 % G == 0, "a wave holds whole samples");
   const TrObj ob = tr_obj(TO);
   const int64_t P = ob.P;
   D0 += ob.member * TO.ms_d;
   q += ob.o * TO.q_stride * in_dim;
   partial += (int64_t)gridDim.x * ob.poff;
-  __shared__ float red[kFG * 9];
-  __shared__ float sx[kFGSlab * 8];
-  const int S = kFG / W, nn = threadIdx.x % W, sub = threadIdx.x / W;
+  __shared__ float red[G * 72];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane % G, sub = threadIdx.x / G;
   const int64_t base = (int64_t)blockIdx.x * CH;
   const int64_t end = base + CH < n ? base + CH : n;
-  float acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // dW_0[nn][0..7], db_0[nn]
-  for (int64_t s0 = base; s0 < end; s0 += kFGSlab) {
-    const int len = (int)(end - s0 < kFGSlab ? end - s0 : kFGSlab);
-    __syncthreads();
-    for (int i = threadIdx.x; i < len * in_dim; i += kFG) sx[(i / in_dim) * 8 + i % in_dim] = q[s0 * in_dim + i];
-    __syncthreads();
-    for (int j = sub; j < len; j += S) {
-      const float d = (float)bf16_of(D0[(s0 + j) * W + nn]);
-      acc[8] += d;
+  float acc[8][9];   // neuron 8 g + e: dW_0 row (8 inputs), then db_0
+#pragma unroll
+  for (int e = 0; e < 8; ++e)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[e][k] = 0.0f;
+  // the lanes of a sample read the same input row (one transaction)
+#pragma unroll 2
+  for (int64_t i = base + sub; i < end; i += S) {
+    const uint4 v = *reinterpret_cast<const uint4*>(D0 + i * W + 8 * g);
+    float xs[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) xs[k] = k < in_dim ? q[i * in_dim + k] : 0.0f;
+    float d[8];
+    unpack4(uint2{v.x, v.y}, d);
+    unpack4(uint2{v.z, v.w}, d + 4);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      acc[e][8] += d[e];
 #pragma unroll
       for (int k = 0; k < 8; ++k)
-        if (k < in_dim) acc[k] = fmaf(d, sx[j * 8 + k], acc[k]);
+        if (k < in_dim) acc[e][k] = fmaf(d[e], xs[k], acc[e][k]);
     }
   }
 #pragma unroll
-  for (int k = 0; k < 9; ++k) red[threadIdx.x * 9 + k] = acc[k];
-  __syncthreads();
-  if (threadIdx.x < W) {
-    float tot[9];
+  for (int off = G; off < 64; off <<= 1)
 #pragma unroll
-    for (int k = 0; k < 9; ++k) tot[k] = red[threadIdx.x * 9 + k];
-    for (int s2 = 1; s2 < S; ++s2)
+    for (int e = 0; e < 8; ++e)
 #pragma unroll
-      for (int k = 0; k < 9; ++k) tot[k] += red[(s2 * W + threadIdx.x) * 9 + k];
-    float* out = partial + (int64_t)blockIdx.x * P;
-    for (int k = 0; k < in_dim; ++k) out[(int64_t)threadIdx.x * in_dim + k] = tot[k];
-    out[nb_b_off(0, in_dim, W, NH) + threadIdx.x] = tot[8];
+      for (int k = 0; k < 9; ++k) acc[e][k] += __shfl_xor(acc[e][k], off);
+  for (int w = 0; w < kFG / 64; ++w) {
+    if (wave == w && lane < G)
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) red[g * 72 + e * 9 + k] = (w == 0 ? 0.0f : red[g * 72 + e * 9 + k]) + acc[e][k];
+    __syncthreads();
+  }
+  float* out = partial + (int64_t)blockIdx.x * P;
+  for (int t = threadIdx.x; t < W * 9; t += kFG) {
+    const int nn = t / 9, k = t % 9;
+    const float tot = red[(nn / 8) * 72 + (nn % 8) * 9 + k];
+    if (k < in_dim) out[(int64_t)nn * in_dim + k] = tot;
+    else if (k == 8) out[nb_b_off(0, in_dim, W, NH) + nn] = tot;
   }
 }
 
@@ -622,7 +644,7 @@ nb_status train_w(const TrainJob& J, hipStream_t s) {
     NB_LAUNCHED();
     cur ^= 1;
   }
-  k_tr_first_grad<<<grid, kFG, 0, s>>>(D[cur], J.q, J.n, CH, in_dim, W, NH, J.partial, J.T);
+  k_tr_first_grad<W><<<grid, kFG, 0, s>>>(D[cur], J.q, J.n, CH, in_dim, NH, J.partial, J.T);
   NB_LAUNCHED();
   return NB_OK;
 }
