@@ -153,10 +153,12 @@ struct TrHidden {
 
 // Threads per workgroup of the hidden-layer and data-gradient kernels.  A
 // width-256 layer's fragments fill 128 KB of LDS, one workgroup per CU: it
-// takes 16 waves (8 for the head, whose per-lane output-layer sums need more
-// registers) so that each SIMD has several waves to hide memory latency.
+// takes 16 waves so that each SIMD has several waves to hide memory latency.
+// The head runs one workgroup per chunk of the batch (one partial each), so
+// it takes 8 waves at every width (its per-lane output-layer sums need more
+// registers than 16 waves allow).
 template <int W, bool HEAD>
-constexpr int tr_threads() { return W >= 256 ? (HEAD ? 512 : 1024) : 256; }
+constexpr int tr_threads() { return HEAD ? 512 : (W >= 256 ? 1024 : 256); }
 // Row blocks unrolled per step of the output-neuron loop: all of them up to
 // width 64; two from width 128 on, where full unrolling hoists more fragment
 // loads than the registers of several waves per SIMD hold.
