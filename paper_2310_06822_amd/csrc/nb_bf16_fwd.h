@@ -56,20 +56,12 @@ __device__ __forceinline__ void split_inputs(const float (&xr)[NB][8], int grp, 
     }
 }
 
-template <int NB>
-__device__ __forceinline__ void load_inputs(const float* __restrict__ q, int64_t n, int in_dim, int64_t q0, int c,
-                                            int grp, bf16x8 (&xb)[NB]) {
-  float xr[NB][8];
-  load_raw<NB>(q, n, in_dim, q0, c, xr);
-  split_inputs<NB>(xr, grp, xb);
-}
-
 // One wave's share of the forward pass: NB blocks of 16 queries starting at
-// q0 (queries >= n_end are padding), weights and biases already in LDS.
-// Writes logits / decisions of the valid queries and adds their confusion
-// counts against g to cnt (when counts is non-null).
-// As bf16_fwd_tile, with the tile's raw inputs already in registers (the
-// grouped kernel loads the next tile's inputs while this one computes).
+// q0 (queries >= n are padding), weights and biases already in LDS, the
+// tile's raw inputs already in registers (the grouped kernel loads the next
+// tile's inputs while this one computes).  Writes logits / decisions of the
+// valid queries and adds their confusion counts against g to cnt (when
+// counts is non-null).
 template <int W, int NH, int NB>
 __device__ __forceinline__ void bf16_fwd_tile_x(const bf16x8* __restrict__ swt, const float* __restrict__ sbias,
                                                 const float (&xr)[NB][8], int64_t n, int64_t q0, float tau,
@@ -180,6 +172,7 @@ __device__ __forceinline__ void bf16_fwd_tile_x(const bf16x8* __restrict__ swt, 
     }
   }
 
+// As bf16_fwd_tile_x, loading the tile's inputs first.
 template <int W, int NH, int NB>
 __device__ __forceinline__ void bf16_fwd_tile(const bf16x8* __restrict__ swt, const float* __restrict__ sbias,
                                               const float* __restrict__ q, int64_t n, int in_dim, int64_t q0,
