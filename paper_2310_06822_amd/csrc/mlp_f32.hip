@@ -213,7 +213,10 @@ __global__ __launch_bounds__(256, (fwd_waves<W, NH, ACT>())) void k_fwd(const fl
       for (int mo = 0; mo < RB; ++mo)
         acc[mo] = floatx4{bl[16 * mo + 4 * grp], bl[16 * mo + 4 * grp + 1], bl[16 * mo + 4 * grp + 2],
                           bl[16 * mo + 4 * grp + 3]};
-      // every acc[mo] takes its products in (mi, r) order either way
+      // every acc[mo] takes its products in (mi, r) order either way; the
+      // wave's issue priority is raised over its products so that a wave
+      // feeding the matrix core wins issue over waves in their VALU work
+      __builtin_amdgcn_s_setprio(1);
       if constexpr (kLdsW) {
 #pragma unroll
         for (int mi = 0; mi < RB; ++mi) {
@@ -234,6 +237,7 @@ __global__ __launch_bounds__(256, (fwd_waves<W, NH, ACT>())) void k_fwd(const fl
             for (int mo = 0; mo < RB; ++mo)
               acc[mo] = mfma4(wh[(l - 1) * N::FH + (mo * RB + mi) * 4 + r], a[mi * 4 + r], acc[mo]);
       }
+      __builtin_amdgcn_s_setprio(0);
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo)
 #pragma unroll
