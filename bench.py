@@ -74,14 +74,19 @@ def cpu_baseline(W, theta, seconds: float = 15.0):
     bf16 = W.precision == "bf16"
     chunk = 1 << 14
     q = synth.points(W.seeds["eval"], chunk, W.in_dim)
-    t0 = time.perf_counter()
-    L.decide(mlp.forward(theta, W.in_dim, widths, q, bf16=bf16))
-    dt = time.perf_counter() - t0
-    reps = max(1, int(seconds / max(dt, 1e-3)))
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        L.decide(mlp.forward(theta, W.in_dim, widths, q, bf16=bf16))
-    dt = time.perf_counter() - t0
+
+    def timed(limit):
+        """Chunks run back to back until `limit` seconds have passed."""
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            L.decide(mlp.forward(theta, W.in_dim, widths, q, bf16=bf16))
+            reps += 1
+            dt = time.perf_counter() - t0
+            if dt >= limit:
+                return reps, dt
+
+    L.decide(mlp.forward(theta, W.in_dim, widths, q, bf16=bf16))   # warm-up (thread pool, first touch)
+    reps, dt = timed(seconds)
     out = {"value": reps * chunk / dt, "unit": "bound queries/s", "cores": int(cores), "kind": "oracle",
            "sample": f"{reps} x {chunk} queries of the {W.name} workload, float64 numpy forward"
                      f"{' (bfloat16 rounding model)' if bf16 else ''} + decision, {dt:.1f} s, "
@@ -89,11 +94,8 @@ def cpu_baseline(W, theta, seconds: float = 15.0):
     try:   # the same on one core, a shorter sample
         from threadpoolctl import threadpool_limits
         with threadpool_limits(1):
-            reps1 = max(1, reps // max(1, int(cores)))
-            t0 = time.perf_counter()
-            for _ in range(reps1):
-                L.decide(mlp.forward(theta, W.in_dim, widths, q, bf16=bf16))
-            out["value_one_core"] = reps1 * chunk / (time.perf_counter() - t0)
+            reps1, dt1 = timed(seconds / 3)
+            out["value_one_core"] = reps1 * chunk / dt1
     except Exception:
         pass
     return out
