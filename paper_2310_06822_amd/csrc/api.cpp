@@ -405,7 +405,7 @@ nb_status nb_bound_shape(const nb_bound* b, int* in_dim, int* n_hidden, int* wid
 
 nb_status nb_bound_num_variants(const nb_bound* b, int* count) {
   NB_REQUIRE(b && count, "NULL argument");
-  *count = b->precision == NB_BF16 ? bf16_variants_for(b->width) : 1;
+  *count = b->precision == NB_BF16 ? bf16_variants_for(b->width, b->n_hidden) : 1;
   return NB_OK;
 }
 

@@ -130,15 +130,15 @@ nb_status bf16_pack(const nb_bound* b, hipStream_t s) {
 //
 // A 256-wide hidden layer is 128 KiB of bfloat16 fragments, so the layers
 // stream through LDS in 64 KiB half-layer chunks (row blocks 0..7, then
-// 8..15), double-buffered: while the waves multiply chunk c, each thread
-// holds its share of chunk c + 1 in registers and stores it to the other
-// buffer afterwards.  A workgroup of 4 waves takes 128 queries per pass
-// (2 blocks of 16 per wave); the first-layer fragments and biases stay
-// resident.
-template <int NH>
+// 8..15), double-buffered: while the waves multiply chunk c, chunk c + 1
+// copies from global memory straight into the other buffer.  One workgroup
+// per CU takes WAVES * NB * 16 queries per pass (4 waves x 3 blocks, or 8
+// waves x 2 blocks: two waves per SIMD, each chunk serving 256 queries); the
+// first-layer fragments and biases stay resident.
+template <int NH, int NB_, int THREADS_>
 struct Stream256 {
   static constexpr int W = 256, RB = 16, KS = 8, FH = RB * KS, HALF = FH / 2;
-  static constexpr int NB = 3, THREADS = 256, WAVES = THREADS / 64;
+  static constexpr int NB = NB_, THREADS = THREADS_, WAVES = THREADS / 64;
   static constexpr int PER = HALF * 64 / THREADS;    // 16-byte fragment slices per thread per chunk
   static constexpr int IN_WAVE = NB * 16 * 8;        // staged input floats per wave (in_dim <= 8)
   static constexpr size_t bias_bytes() { return ((size_t)(NH * W + W + 1) * 4 + 15) / 16 * 16; }
@@ -148,16 +148,17 @@ struct Stream256 {
 };
 
 // SPLIT: row blocks (of four) whose products precede the next K step's
-// fragment loads (a tuning variant; every SPLIT gives identical results).
-template <int NH, int SPLIT>
-__global__ __launch_bounds__(256, 1) void k_fwd_bf16_stream(const float* __restrict__ q, int64_t n, int in_dim,
+// fragment loads; (NB, THREADS): blocks of 16 queries per wave and threads
+// of the one workgroup per CU (tuning variants; all give identical results).
+template <int NH, int SPLIT, int NB_, int THREADS_>
+__global__ __launch_bounds__(THREADS_, 1) void k_fwd_bf16_stream(const float* __restrict__ q, int64_t n, int in_dim,
                                                           const bf16x8* __restrict__ pack,
                                                           const float* __restrict__ theta, float tau,
                                                           float* __restrict__ logits, uint8_t* __restrict__ hout,
                                                           const uint8_t* __restrict__ g,
                                                           unsigned long long* __restrict__ counts,
                                                           const unsigned long long* __restrict__ n_dev) {
-  using S = Stream256<NH>;
+  using S = Stream256<NH, NB_, THREADS_>;
   if (n_dev && (int64_t)*n_dev < n) n = (int64_t)*n_dev;   // rows counted on the device
   constexpr int W = S::W, RB = S::RB, KS = S::KS, NB = S::NB;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -360,41 +361,56 @@ __global__ __launch_bounds__(256, 1) void k_fwd_bf16_stream(const float* __restr
   }
 }
 
-template <int NH, int SPLIT>
+template <int NH, int SPLIT, int NB, int THREADS>
 nb_status stream_launch(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
                         const uint8_t* g, unsigned long long* counts, const unsigned long long* n_dev,
                         hipStream_t s) {
-  using S = Stream256<NH>;
+  using S = Stream256<NH, NB, THREADS>;
+  static_assert(S::lds_bytes() <= 160 * 1024, "streamed forward exceeds the CU's LDS");
   const size_t lds = S::lds_bytes();
   static bool attr_set[64] = {false};
   int dev = 0;
   NB_HIP(hipGetDevice(&dev));
   if (dev >= 0 && dev < 64 && !attr_set[dev]) {
-    NB_HIP(hipFuncSetAttribute((const void*)k_fwd_bf16_stream<NH, SPLIT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    NB_HIP(hipFuncSetAttribute((const void*)k_fwd_bf16_stream<NH, SPLIT, NB, THREADS>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     attr_set[dev] = true;
   }
   const int64_t tiles = (n + S::WAVES * S::NB * 16 - 1) / (S::WAVES * S::NB * 16);
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, nb_cu_count()));
-  k_fwd_bf16_stream<NH, SPLIT><<<grid, S::THREADS, lds, s>>>(q, n, b->in_dim, reinterpret_cast<const bf16x8*>(b->pack16),
+  k_fwd_bf16_stream<NH, SPLIT, NB, THREADS><<<grid, S::THREADS, lds, s>>>(q, n, b->in_dim, reinterpret_cast<const bf16x8*>(b->pack16),
                                                       b->theta, tau, logits, h, g, counts, n_dev);
   NB_LAUNCHED();
   return NB_OK;
 }
 
 int bf16_variants() { return 6; }
-int bf16_variants_for(int width) { return width == 256 ? 3 : 6; }
+int bf16_variants_for(int width, int n_hidden) { return width == 256 ? (n_hidden <= 6 ? 5 : 3) : 6; }
 
 // Variant v: (query blocks per wave, threads per workgroup) =
 //   0: (2, 768)   1: (2, 512)   2: (3, 512)   3: (1, 1024)   4: (4, 256)   5: (2, 256)
 // Variant 0 (three waves per SIMD) measured fastest for widths 32..128.
+// Width 256 (streamed): (SPLIT, blocks per wave, threads) =
+//   0: (2, 3, 256)   1: (1, 3, 256)   2: (3, 3, 256)   3: (2, 2, 512)   4: (1, 2, 512)
+// (variants 3 and 4 up to 6 hidden layers).
 template <int NH>
 nb_status stream_nh(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
                     const uint8_t* g, unsigned long long* counts, const unsigned long long* n_dev, hipStream_t s) {
   switch (b->variant) {
-    case 1: return stream_launch<NH, 1>(b, q, n, tau, logits, h, g, counts, n_dev, s);
-    case 2: return stream_launch<NH, 3>(b, q, n, tau, logits, h, g, counts, n_dev, s);
-    default: return stream_launch<NH, 2>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+    case 1: return stream_launch<NH, 1, 3, 256>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+    case 2: return stream_launch<NH, 3, 3, 256>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+    case 3:
+    case 4:
+      // eight waves fit the CU's LDS up to six hidden layers (the biases grow with depth)
+      if constexpr (Stream256<NH, 2, 512>::lds_bytes() <= 160 * 1024) {
+        if (b->variant == 3) return stream_launch<NH, 2, 2, 512>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+        return stream_launch<NH, 1, 2, 512>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+      } else {
+        nb_set_error("streamed variant %d needs at most 6 hidden layers", b->variant);
+        return NB_ERR_UNSUPPORTED;
+      }
+    default: return stream_launch<NH, 2, 3, 256>(b, q, n, tau, logits, h, g, counts, n_dev, s);
   }
 }
 

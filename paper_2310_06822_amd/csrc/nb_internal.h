@@ -198,7 +198,7 @@ bool bf16_supported(int in_dim, int n_hidden, int width);
 int64_t bf16_pack_elems(int in_dim, int n_hidden, int width);
 nb_status bf16_pack(const nb_bound* b, hipStream_t s);
 int bf16_variants();
-int bf16_variants_for(int width);
+int bf16_variants_for(int width, int n_hidden);
 nb_status bf16_forward(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
                        const uint8_t* g, unsigned long long* counts, hipStream_t s,
                        const unsigned long long* n_dev = nullptr);

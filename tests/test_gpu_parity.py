@@ -553,7 +553,7 @@ def test_bf16_recompute_training_step(c2_grid):
     assert np.array_equal(out[0], out[1])
 
 
-@pytest.mark.parametrize("in_dim,width,nh", [(6, 128, 4), (4, 256, 6), (3, 64, 3), (6, 32, 2)])
+@pytest.mark.parametrize("in_dim,width,nh", [(6, 128, 4), (4, 256, 6), (4, 256, 8), (3, 64, 3), (6, 32, 2)])
 def test_forward_bf16_variants_identical(in_dim, width, nh):
     """Every tile-shape variant of the bfloat16 forward gives the same bits."""
     theta = synth.init_params(120 + nh, in_dim, [width] * nh)
