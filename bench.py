@@ -267,7 +267,8 @@ def run_workload(W, args, with_cpu: bool):
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4),
                 "traffic": committed_traffic(f"{W.name}_forward_traffic.txt", src),
-                "kernel": f"{'k_fwd_bf16' if prec == nb.BF16 else 'k_fwd'} ({W.precision} MLP forward + decision)",
+                "kernel": f"{('k_fwd_bf16_stream' if W.width == 256 else 'k_fwd_bf16') if prec == nb.BF16 else 'k_fwd'} "
+                          f"({W.precision} MLP forward + decision)",
                 "flop_per_query": flop_per_q, "avg_launch_ms": round(kern_ms, 4)}
     out = {
         "value": value, "ms_per_step": wall * 1e3 / args.steps, "dtype": W.precision,
