@@ -148,8 +148,8 @@ nb_status nb_sample_queries(int kind, int dim, uint64_t seed, uint64_t step, int
 
 /* ------------------------------------------------------------------------
  * Bound h_theta (Sec. 3.4): in_dim -> width x n_hidden (ReLU) -> 1 logit.
- * Supported: in_dim 1..8;  NB_F32: width 16, 32 or 64 with n_hidden 1..4;
- * NB_BF16: width 32 or 64 with n_hidden 1..6, width 128 with n_hidden 1..5,
+ * Supported: in_dim 1..8;  NB_F32: width 16, 32 or 64 with n_hidden 1..4,
+ * width 80 with n_hidden 1..2;  NB_BF16: width 32 or 64 with n_hidden 1..6, width 128 with n_hidden 1..5,
  * width 256 with n_hidden 2..8 (its layers stream through LDS); training
  * needs n_hidden >= 2.  Other shapes give NB_ERR_UNSUPPORTED.
  * The handle owns float32 master parameters, Adam moments and work space.
@@ -179,9 +179,10 @@ nb_status nb_bound_set_recompute(nb_bound* b, int every);
 /* Hidden-layer activation: NB_ACT_RELU (default) or NB_ACT_SINE, the paper's
  * sinusoidal activation a = sin z (Sec. 3.4, "Architecture"; derivative
  * cos z in training).  Sine is available for float32 bounds of width 32 or
- * 64 with 1..3 hidden layers (narrower layers, such as the paper's 25 or 50
- * neurons, run exactly as zero-padded ones: sin 0 = 0 and the padding gets
- * no gradient); anything else returns NB_ERR_UNSUPPORTED. */
+ * 64 with 1..3 hidden layers and of width 80 with 1..2 (narrower layers, such
+ * as the paper's 25, 50 or 75 neurons, run exactly as zero-padded ones:
+ * sin 0 = 0 and the padding gets no gradient); anything else returns
+ * NB_ERR_UNSUPPORTED. */
 #define NB_ACT_RELU 0
 #define NB_ACT_SINE 1
 nb_status nb_bound_set_activation(nb_bound* b, int activation);

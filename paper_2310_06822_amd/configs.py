@@ -80,6 +80,14 @@ VOXEL3D_POINT_SINE = Workload("voxel3d_point_sine", 1, "point", 3, 3, 64, 2, "f3
                               train_steps=5000, batch=1 << 16, eval_n=1 << 24, act="sine", real_width=50,
                               bench_also=True)
 
+# The 4-D point workload with the paper's own network: 4 x 75 x 75 with sine
+# activations (supplemental architecture table), run as 4 x 80 x 80 with zero
+# padding, in float32.
+METABALL4D_POINT_SINE = Workload("metaball4d_point_sine", 4, "point", 4, 4, 80, 2, "f32",
+                                 scene={"type": "metaballs4d", "k": 24, "rlo": 0.05, "rhi": 0.2},
+                                 train_steps=5000, batch=1 << 16, eval_n=1 << 24, act="sine", real_width=75,
+                                 bench_also=True)
+
 # Plane queries (Sec. 4.2 "Query types") over the 3-D point workload's grid,
 # with the ray workload's network: p0 uniform in the cube, unit normal
 # uniform on the sphere.
@@ -88,7 +96,7 @@ VOXEL3D_PLANE = Workload("voxel3d_plane", 5, "plane", 3, 6, 128, 4, "bf16",
                          train_steps=5000, batch=1 << 18, eval_n=1 << 24, lr_decay=0.99, bench_also=True)
 
 WORKLOADS = {w.name: w for w in (DISC2D_POINT, VOXEL3D_POINT, VOXEL3D_RAY, METABALL4D_POINT, VOXEL3D_POINT_SINE,
-                                 VOXEL3D_PLANE)}
+                                 METABALL4D_POINT_SINE, VOXEL3D_PLANE)}
 
 
 @dataclass(frozen=True)

@@ -109,14 +109,16 @@ __global__ void k_pack(const float* __restrict__ theta, int in_dim, int W, int N
 
 // Waves per SIMD the forward asks the register allocator for: two while the
 // weights held in registers leave room (all but the widest, deepest nets).
-// Width-64 networks read their hidden weights from LDS (one 16-byte read
-// per lane feeds four products), which frees the registers for four waves
-// per SIMD; narrower ones keep them in registers.
+// Networks 64 or more wide read their hidden weights from LDS (one 16-byte
+// read per lane feeds four products), which frees the registers for four
+// waves per SIMD (two for sine at width 80); narrower ones keep them in
+// registers.
 template <int W>
 constexpr bool fwd_lds_weights() { return W >= 64; }
 template <int W, int NH, int ACT>
 constexpr int fwd_waves() {
-  return fwd_lds_weights<W>() ? 4 : (W * W * (NH - 1) > 64 * 64 * (ACT == 0 ? 2 : 1) ? 1 : 2);
+  return fwd_lds_weights<W>() ? (ACT == 1 && W > 64 ? 2 : 4)   // sine beyond 64 wide: registers for sin
+                              : (W * W * (NH - 1) > 64 * 64 * (ACT == 0 ? 2 : 1) ? 1 : 2);
 }
 
 template <int KIN, int W, int NH, int ACT>
@@ -618,31 +620,37 @@ nb_status train_launch(const nb_bound* b, const float* q, const uint8_t* y, int6
   return NB_OK;
 }
 
-// (KIN, W, NH) instances: inputs 1..8, widths 16/32/64, 1..4 hidden layers.
+// (KIN, W, NH) instances: inputs 1..8, widths 16/32/64 with 1..4 hidden
+// layers, width 80 (the paper's 75-wide networks, zero-padded) with 1..2.
 #define NB_F32_CASES(X) \
   X(1, 16, 1) X(1, 16, 2) X(1, 16, 3) X(1, 16, 4) \
   X(1, 32, 1) X(1, 32, 2) X(1, 32, 3) X(1, 32, 4) \
   X(1, 64, 1) X(1, 64, 2) X(1, 64, 3) X(1, 64, 4) \
+  X(1, 80, 1) X(1, 80, 2)                         \
   X(2, 16, 1) X(2, 16, 2) X(2, 16, 3) X(2, 16, 4) \
   X(2, 32, 1) X(2, 32, 2) X(2, 32, 3) X(2, 32, 4) \
-  X(2, 64, 1) X(2, 64, 2) X(2, 64, 3) X(2, 64, 4)
+  X(2, 64, 1) X(2, 64, 2) X(2, 64, 3) X(2, 64, 4) \
+  X(2, 80, 1) X(2, 80, 2)
 
-// Sine instances (the paper's own architectures: widths up to 64 with the
-// neurons of a 25- or 50-wide layer zero-padded, 1..3 hidden layers).
+// Sine instances (the paper's own architectures: the neurons of a 25-, 50-
+// or 75-wide layer zero-padded to 32, 64 or 80; 1..3 hidden layers, 1..2 at
+// width 80).
 #define NB_F32_SINE_CASES(X) \
-  X(1, 32, 1) X(1, 32, 2) X(1, 32, 3) X(1, 64, 1) X(1, 64, 2) X(1, 64, 3) \
-  X(2, 32, 1) X(2, 32, 2) X(2, 32, 3) X(2, 64, 1) X(2, 64, 2) X(2, 64, 3)
+  X(1, 32, 1) X(1, 32, 2) X(1, 32, 3) X(1, 64, 1) X(1, 64, 2) X(1, 64, 3) X(1, 80, 1) X(1, 80, 2) \
+  X(2, 32, 1) X(2, 32, 2) X(2, 32, 3) X(2, 64, 1) X(2, 64, 2) X(2, 64, 3) X(2, 80, 1) X(2, 80, 2)
 
 inline int kin_of(int in_dim) { return (in_dim + 3) / 4; }
 
 }  // namespace
 
 bool f32_sine_supported(int in_dim, int n_hidden, int width) {
-  return in_dim >= 1 && in_dim <= 8 && n_hidden >= 1 && n_hidden <= 3 && (width == 32 || width == 64);
+  return in_dim >= 1 && in_dim <= 8 && n_hidden >= 1 &&
+         (((width == 32 || width == 64) && n_hidden <= 3) || (width == 80 && n_hidden <= 2));
 }
 
 bool f32_supported(int in_dim, int n_hidden, int width) {
-  return in_dim >= 1 && in_dim <= 8 && n_hidden >= 1 && n_hidden <= 4 && (width == 16 || width == 32 || width == 64);
+  return in_dim >= 1 && in_dim <= 8 && n_hidden >= 1 &&
+         (((width == 16 || width == 32 || width == 64) && n_hidden <= 4) || (width == 80 && n_hidden <= 2));
 }
 
 int64_t f32_pack_floats(int in_dim, int n_hidden, int width) {

@@ -61,20 +61,26 @@ def _check_all_rows(z, h, g, counts):
 
 
 @pytest.mark.parametrize("name", ["disc2d_point", "voxel3d_point", "voxel3d_ray", "voxel3d_plane",
-                                  "metaball4d_point"])
+                                  "metaball4d_point", "voxel3d_point_sine", "metaball4d_point_sine"])
 def test_full_size_forward_and_exact(name):
     W = configs.WORKLOADS[name]
     kind = nb.KINDS[W.kind]
     bf16 = W.precision == "bf16"
     widths = [W.width] * W.n_hidden
     ind, exact = _scene(W)
-    theta = synth.init_params(W.seeds["init"], W.in_dim, widths)
+    if W.real_width:   # the paper's narrower layers, zero-padded
+        real = [W.real_width] * W.n_hidden
+        theta = synth.pad_params(synth.init_params(W.seeds["init"], W.in_dim, real), W.in_dim, real, widths)
+    else:
+        theta = synth.init_params(W.seeds["init"], W.in_dim, widths)
     # centre the output bias so that about half of the queries are positive
     theta[-1] -= np.float32(np.median(mlp.forward(theta, W.in_dim, widths, synth.points(7, 2000, W.in_dim),
-                                                 bf16=bf16)))
+                                                 bf16=bf16, act=W.act)))
     b = nb.Bound(W.in_dim, W.n_hidden, W.width, nb.BF16 if bf16 else nb.F32)
     if W.recompute:
         nb.nb_bound_set_recompute(b.handle, W.recompute)
+    if W.act == "sine":
+        nb.nb_bound_set_activation(b.handle, nb.SINE)
     b.set_params(theta)
     q = torch.empty((W.eval_n, W.in_dim), dtype=torch.float32, device="cuda")
     nb.nb_sample_queries(kind, W.dim, W.seeds["eval"], 0, q)
@@ -87,8 +93,8 @@ def test_full_size_forward_and_exact(name):
     idx = np.sort(np.random.default_rng(W.index).choice(W.eval_n, N_SAMPLE, replace=False))
     it = torch.from_numpy(idx).cuda()
     qs = host(q[it])
-    ref = mlp.forward(theta, W.in_dim, widths, qs, bf16=bf16)
-    s = mlp.abs_forward(theta, W.in_dim, widths, qs, bf16=bf16)
+    ref = mlp.forward(theta, W.in_dim, widths, qs, bf16=bf16, act=W.act)
+    s = mlp.abs_forward(theta, W.in_dim, widths, qs, bf16=bf16, act=W.act)
     _check_rows(host(z[it]), host(h[it]), ref, s, bf16)
     assert np.array_equal(host(g[it]).astype(bool), exact(W.kind, qs).astype(bool))
     hs = host(h)

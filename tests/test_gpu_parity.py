@@ -208,7 +208,7 @@ def test_exact_metaballs4d():
 
 # ------------------------------------------------------------ MLP forward
 
-SHAPES = [(2, 32, 3), (3, 64, 3), (6, 16, 2), (4, 32, 4), (3, 16, 1), (6, 64, 4), (8, 64, 2)]
+SHAPES = [(2, 32, 3), (3, 64, 3), (6, 16, 2), (4, 32, 4), (3, 16, 1), (6, 64, 4), (8, 64, 2), (4, 80, 2), (8, 80, 1)]
 
 
 def _check_logits(z, theta, in_dim, widths, q, rtol=1e-5):
@@ -634,7 +634,7 @@ def test_inverted_bound_has_no_false_positives():
 
 # ------------------------------------------------------ sine activations
 
-SINE_SHAPES = [(3, 64, 2), (2, 32, 2), (3, 64, 3), (6, 64, 1), (4, 32, 3)]
+SINE_SHAPES = [(3, 64, 2), (2, 32, 2), (3, 64, 3), (6, 64, 1), (4, 32, 3), (4, 80, 2), (8, 80, 2), (6, 80, 1)]
 
 
 @pytest.mark.parametrize("in_dim,width,nh", SINE_SHAPES)
@@ -679,26 +679,30 @@ def test_loss_grad_sine_parity(in_dim, width, nh):
         assert _rel_frob(bg, br) <= 1e-5
 
 
-def test_sine_paper_architecture_padded():
-    """The paper's 3 x 50 x 50 sine network run as 3 x 64 x 64 with zero
-    padding: the same logits as the unpadded oracle network, and a training
-    step leaves the padding at zero."""
-    theta50 = synth.init_params(160, 3, [50, 50])
-    theta = synth.pad_params(theta50, 3, [50, 50], [64, 64])
-    b = nb.Bound(3, 2, 64)
+@pytest.mark.parametrize("in_dim,real,padded", [(3, 50, 64), (4, 75, 80)])
+def test_sine_paper_architecture_padded(in_dim, real, padded):
+    """The paper's sine networks (3 x 50 x 50 for 3-D points, 4 x 75 x 75 for
+    4-D points) run zero-padded to 64 / 80: the same logits as the unpadded
+    oracle network, and a training step leaves the padding at zero."""
+    small, big = [real] * 2, [padded] * 2
+    theta_s = synth.init_params(160, in_dim, small)
+    theta = synth.pad_params(theta_s, in_dim, small, big)
+    b = nb.Bound(in_dim, 2, padded)
     nb.nb_bound_set_activation(b.handle, nb.SINE)
     b.set_params(theta)
-    q = synth.points(161, 5000, 3)
+    q = synth.points(161, 5000, in_dim)
     z, _ = b.forward(cuda(q))
-    ref = mlp.forward(theta50, 3, [50, 50], q, act="sine")
-    s = mlp.abs_forward(theta50, 3, [50, 50], q, act="sine")
+    ref = mlp.forward(theta_s, in_dim, small, q, act="sine")
+    s = mlp.abs_forward(theta_s, in_dim, small, q, act="sine")
     assert np.all(np.abs(host(z) - ref) <= 1e-5 * np.maximum(np.abs(ref), s))
-    grid = I.voxelize_metaballs(*synth.metaballs3d(1001, k=16), 64)
-    ind = nb.Indicator.voxels(cuda(grid), 64)
+    if in_dim == 3:
+        ind = nb.Indicator.voxels(cuda(I.voxelize_metaballs(*synth.metaballs3d(1001, k=16), 64)), 64)
+    else:
+        ind = nb.Indicator.metaballs4d(*synth.metaballs4d(1005, k=24))
     for t in range(3):
         nb.nb_bound_train_step(b.handle, ind.handle, nb.POINT, 5, t, 8192, 10.0)
     th = host(b.params())
-    mask = synth.pad_params(np.ones_like(theta50), 3, [50, 50], [64, 64]) != 0
+    mask = synth.pad_params(np.ones_like(theta_s), in_dim, small, big) != 0
     assert np.all(th[~mask] == 0) and np.any(th[mask] != theta[mask])
 
 
@@ -709,6 +713,8 @@ def test_sine_unsupported_shapes():
     b = nb.Bound(3, 4, 64)
     with pytest.raises(nb.NBError):
         nb.nb_bound_set_activation(b.handle, nb.SINE)
+    with pytest.raises(nb.NBError):   # width 80 holds at most two hidden layers
+        nb.Bound(4, 3, 80)
 
 
 def test_trained_bound_gain_over_exact_test_alone(c2_grid):

@@ -328,12 +328,12 @@ def test_sine_forward_backward_vs_torch():
     assert np.allclose(g, ref, rtol=1e-10, atol=1e-14)
 
 
-def test_sine_zero_padding_is_exact():
+@pytest.mark.parametrize("in_dim,small,big", [(3, [50, 50], [64, 64]), (4, [75, 75], [80, 80])])
+def test_sine_zero_padding_is_exact(in_dim, small, big):
     """A sine network padded with zero neurons computes the same logits and
     its padded parameters get zero gradient (sin 0 = 0; the padding's
     outgoing weights are zero), so a 3 x 50 x 50 network runs exactly as a
-    3 x 64 x 64 one."""
-    in_dim, small, big = 3, [50, 50], [64, 64]
+    3 x 64 x 64 one and a 4 x 75 x 75 one as a 4 x 80 x 80 one."""
     theta = synth.init_params(24, in_dim, small)
     padded = synth.pad_params(theta, in_dim, small, big)
     x = synth.points(25, 200, in_dim)
