@@ -33,8 +33,20 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
   const int t = threadIdx.x, j = t % kParamsPerBlock, k = t / kParamsPerBlock;
   const int64_t p = (int64_t)blockIdx.x * kParamsPerBlock + j;
   float s = 0.0f;
-  if (p < P)
-    for (int w = k; w < n_wg; w += kParts) s += partial[(int64_t)w * P + p];
+  if (p < P) {
+    // partials k, k + 8, k + 16, ... added in that order; eight loads are in
+    // flight at a time instead of one per add
+    const float* src = partial + p;
+    int w = k;
+    for (; w + 7 * kParts < n_wg; w += 8 * kParts) {
+      float x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = src[(int64_t)(w + u * kParts) * P];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += x[u];
+    }
+    for (; w < n_wg; w += kParts) s += src[(int64_t)w * P];
+  }
   part[k][j] = s;
   __syncthreads();
   if (t < kParamsPerBlock && p < P) {
