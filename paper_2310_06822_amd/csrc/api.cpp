@@ -566,9 +566,10 @@ nb_status nb_bound_train_step(nb_bound* b, const nb_indicator* ind, int kind, ui
   int n_wg = 0;
   NB_TRY(train_partials(b, b->batch_q, b->batch_y, batch, alpha, beta, &n_wg, s));
   const AdamArgs a = adam_args(b, lr, 0.9f, 0.999f, 1e-8f, lam1, lam2);
+  const bool fused = b->precision == NB_F32;   // the reduction writes the float32 fragments itself
   NB_TRY(launch_reduce(b, n_wg, nullptr, loss, (float)(1.0 / (double)batch),
-                       reinterpret_cast<unsigned long long*>(counts), a, s));
-  return repack(b, s);
+                       reinterpret_cast<unsigned long long*>(counts), a, s, fused));
+  return fused ? NB_OK : repack(b, s);
 }
 
 namespace {

@@ -247,9 +247,11 @@ nb_status group_reduce_adam(const nb_group* gr, int n_wg, const AdamArgs& adam, 
 
 // optim.hip
 // Reduce partials over n_wg workgroups: writes grad (if non-null), loss and
-// counts (if non-null); with adam != 0 also applies one Adam step to theta.
+// counts (if non-null); with adam != 0 also applies one Adam step to theta,
+// and with pack_f32 (float32 bounds) writes the updated weights to their
+// packed fragments, so that no repack is needed after the step.
 nb_status launch_reduce(const nb_bound* b, int n_wg, float* grad, float* loss, float loss_scale,
-                        unsigned long long* counts, const AdamArgs& adam, hipStream_t s);
+                        unsigned long long* counts, const AdamArgs& adam, hipStream_t s, bool pack_f32 = false);
 nb_status launch_adam(const nb_bound* b, const float* grad, const AdamArgs& adam, hipStream_t s);
 nb_status launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
 // 1 for entries of theta that belong to a weight matrix (regularised), 0 for biases.

@@ -43,6 +43,37 @@ __host__ __device__ inline int64_t nb_b_off(int l, int in_dim, int W, int NH) {
   return nb_w_off(l, in_dim, W) + (int64_t)(l == 0 ? in_dim : W) * (l == NH ? 1 : W);
 }
 
+// Writes the value of float32 weight p to every packed-fragment slot that
+// holds it, in the layout the float32 forward and training kernels read
+// (KIN = ceil(in_dim / 4) input steps, RB = W / 16 row blocks; lane
+// 16 g + c of a fragment):
+//   first layer W0[row][k]: fragment (row / 16) KIN + k / 4, g = k % 4,
+//     c = row % 16;
+//   hidden W_l[row][col]: forward fragment (mo, mi, r) = (row / 16, col / 16,
+//     col % 4) with g = (col % 16) / 4, c = row % 16, and the transposed copy
+//     (mo, mi, r) = (col / 16, row / 16, row % 4) with g = (row % 16) / 4,
+//     c = col % 16.
+// Biases and output weights are read from theta and have no slot.
+__device__ inline void nb_f32_pack_put(int64_t p, float v, float* __restrict__ pack, int in_dim, int W, int NH) {
+  const int RB = W / 16, KIN = (in_dim + 3) / 4, F1 = RB * KIN, FH = RB * RB * 4, NFWD = F1 + (NH - 1) * FH;
+  if (p < (int64_t)W * in_dim) {
+    const int row = (int)(p / in_dim), k = (int)(p % in_dim);
+    pack[(int64_t)((row >> 4) * KIN + (k >> 2)) * 64 + (k & 3) * 16 + (row & 15)] = v;
+    return;
+  }
+  for (int l = 1; l < NH; ++l) {
+    const int64_t off = nb_w_off(l, in_dim, W);
+    if (p >= off && p < off + (int64_t)W * W) {
+      const int e = (int)(p - off), row = e / W, col = e % W;
+      pack[(int64_t)(F1 + (l - 1) * FH + ((row >> 4) * RB + (col >> 4)) * 4 + (col & 3)) * 64 +
+           ((col & 15) >> 2) * 16 + (row & 15)] = v;
+      pack[(int64_t)(NFWD + (l - 1) * FH + ((col >> 4) * RB + (row >> 4)) * 4 + (row & 3)) * 64 +
+           ((row & 15) >> 2) * 16 + (col & 15)] = v;
+      return;
+    }
+  }
+}
+
 // bfloat16 round-to-nearest-even of a float32, from its bit pattern.
 __host__ __device__ inline uint16_t nb_bf16_bits(float v) {
   uint32_t u;

@@ -10,6 +10,7 @@
 // lam1 sign(W) + 2 lam2 W to their gradient.
 #include "nb_internal.h"
 #include "nb_adam.h"
+#include "nb_mlp.h"
 
 namespace {
 
@@ -28,7 +29,7 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
                                                 float* __restrict__ v, AdamArgs adam, int in_dim, int width,
                                                 int n_hidden, float* __restrict__ loss, float loss_scale,
                                                 unsigned long long* __restrict__ counts,
-                                                unsigned* __restrict__ nonfinite) {
+                                                unsigned* __restrict__ nonfinite, float* __restrict__ pack) {
   __shared__ float part[kParts][kParamsPerBlock];
   const int t = threadIdx.x, j = t % kParamsPerBlock, k = t / kParamsPerBlock;
   const int64_t p = (int64_t)blockIdx.x * kParamsPerBlock + j;
@@ -55,7 +56,11 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
     for (int i = 1; i < kParts; ++i) tot += part[i][t];
     if (grad) grad[p] = tot;
     if (!isfinite(tot)) *nonfinite = 1u;
-    if (adam.enabled) adam_update(p, tot, theta, m, v, adam, in_dim, width, n_hidden);
+    if (adam.enabled) {
+      adam_update(p, tot, theta, m, v, adam, in_dim, width, n_hidden);
+      // float32 bounds: the updated weight goes straight to its packed slots
+      if (pack) nb_f32_pack_put(p, theta[p], pack, in_dim, width, n_hidden);
+    }
   }
   // loss and counts: the last block's first wave, lanes strided over workgroups
   if (blockIdx.x == gridDim.x - 1 && t < 64) {
@@ -92,11 +97,12 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
 }  // namespace
 
 nb_status launch_reduce(const nb_bound* b, int n_wg, float* grad, float* loss, float loss_scale,
-                        unsigned long long* counts, const AdamArgs& adam, hipStream_t s) {
+                        unsigned long long* counts, const AdamArgs& adam, hipStream_t s, bool pack_f32) {
   const int64_t P = b->n_params;
   const unsigned grid = (unsigned)((P + kParamsPerBlock - 1) / kParamsPerBlock);
+  float* pack = pack_f32 && adam.enabled && b->precision == NB_F32 ? b->pack : nullptr;
   k_reduce<<<grid, 256, 0, s>>>(b->partial, b->aux, n_wg, P, grad, b->theta, b->m, b->v, adam, b->in_dim,
-                                b->width, b->n_hidden, loss, loss_scale, counts, b->d_nonfinite);
+                                b->width, b->n_hidden, loss, loss_scale, counts, b->d_nonfinite, pack);
   NB_LAUNCHED();
   return NB_OK;
 }

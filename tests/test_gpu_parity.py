@@ -381,6 +381,33 @@ def test_train_steps_parity(cfg, c2_grid):
     assert _rel_frob(d_gpu, d_ref) <= 1e-2
 
 
+@pytest.mark.parametrize("in_dim,width,nh,act,kind", [(3, 64, 3, "relu", "point"), (6, 32, 2, "relu", "ray"),
+                                                      (4, 80, 2, "sine", "point"), (2, 16, 4, "relu", "point")])
+def test_train_step_packs_weights(in_dim, width, nh, act, kind, c2_grid):
+    """A float32 training step writes its updated weights straight into the
+    packed fragments the kernels read: the logits after a few steps are
+    bit-identical to those after rebuilding every fragment from theta."""
+    _, _, grid = c2_grid
+    if in_dim == 4:
+        ind = nb.Indicator.metaballs4d(*synth.metaballs4d(1005, k=24))
+    elif in_dim == 2:
+        ind = nb.Indicator.discs2d(synth.discs2d(1000))
+    else:
+        ind = nb.Indicator.voxels(cuda(grid), 128)
+    b = nb.Bound(in_dim, nh, width)
+    if act == "sine":
+        nb.nb_bound_set_activation(b.handle, nb.SINE)
+    b.set_params(synth.init_params(170 + width, in_dim, [width] * nh))
+    for t in range(3):
+        nb.nb_bound_train_step(b.handle, ind.handle, nb.KINDS[kind], 171, t, 4096, 5.0, 1.0, 1e-2)
+    q = cuda(synth.points(172, 3001, in_dim))
+    z_fused, _ = b.forward(q)
+    z_fused = bits(host(z_fused))
+    b.set_params(b.params().clone())   # rebuilds every fragment from theta
+    z_full, _ = b.forward(q)
+    assert np.array_equal(z_fused, bits(host(z_full)))
+
+
 # ------------------------------------------------------------------ cascade
 
 @pytest.mark.parametrize("kind,prec", [("point", nb.F32), ("ray", nb.BF16), ("box", nb.BF16), ("point", nb.BF16),
