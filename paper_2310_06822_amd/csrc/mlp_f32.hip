@@ -36,6 +36,37 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// sin x by Cody and Waite's argument reduction (Cody & Waite,
+// "Software Manual for the Elementary Functions", 1980): x = k pi/2 + r with
+// k = rint(x 2/pi) and r = x - k pi/2, pi/2 split into a float32 head and
+// tail so that two fused multiply-adds leave r accurate to float32 rounding
+// for |x| <= 2^16 (the dropped remainder of pi/2 is below 2e-15).  Then the
+// Taylor series of sin and cos on |r| <= pi/4 (truncation below 2e-9) and the
+// quadrant k mod 4 picks +-sin r or +-cos r.  Larger or non-finite arguments
+// take the library's sinf.  The forward's sine activation uses it.
+constexpr float kPio2Hi = 0x1.921fb6p+0f;    // float32 nearest to pi/2
+constexpr float kPio2Lo = -0x1.777a5cp-25f;  // float32 nearest to pi/2 - kPio2Hi
+constexpr float kTwoOverPi = 0x1.45f306p-1f;
+__device__ __forceinline__ void sin_cos_poly(float x, float& sp, float& cp, int& q) {
+  const float k = rintf(x * kTwoOverPi);
+  float r = fmaf(-k, kPio2Hi, x);
+  r = fmaf(-k, kPio2Lo, r);
+  q = (int)k & 3;   // k mod 4 (two's complement keeps it right for k < 0)
+  const float r2 = r * r;
+  sp = fmaf(r2 * r, fmaf(r2, fmaf(r2, fmaf(r2, 1.0f / 362880, -1.0f / 5040), 1.0f / 120), -1.0f / 6), r);
+  cp = fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, -1.0f / 3628800, 1.0f / 40320), -1.0f / 720), 1.0f / 24),
+                 -0.5f),
+            1.0f);
+}
+__device__ __forceinline__ float nb_sin(float x) {
+  if (!(fabsf(x) <= 65536.0f)) return sinf(x);
+  float sp, cp;
+  int q;
+  sin_cos_poly(x, sp, cp, q);
+  const float v = (q & 1) ? cp : sp;   // sin(k pi/2 + r) = sin r, cos r, -sin r, -cos r
+  return (q & 2) ? -v : v;
+}
+
 // Hidden activation ACT: 0 ReLU, 1 sine (sin z; the paper's choice).  The
 // training kernel keeps per layer the value the backward pass needs: the
 // ReLU output itself (its sign is the derivative), or the pre-activation z
@@ -44,10 +75,11 @@ template <int ACT>
 __device__ __forceinline__ float act_apply(float z) {
   // ReLU as the median of (z, 0, FLT_MAX): max(z, 0) in one instruction for
   // every finite z (+inf becomes FLT_MAX)
-  return ACT == 0 ? __builtin_amdgcn_fmed3f(z, 0.0f, 3.40282347e38f) : sinf(z);
+  return ACT == 0 ? __builtin_amdgcn_fmed3f(z, 0.0f, 3.40282347e38f) : nb_sin(z);
 }
 template <int ACT>
 __device__ __forceinline__ float act_store(float z) { return ACT == 0 ? fmaxf(z, 0.0f) : z; }
+// The training kernel evaluates sin and cos with the library's sinf / cosf.
 template <int ACT>
 __device__ __forceinline__ float act_value(float kept) { return ACT == 0 ? kept : sinf(kept); }
 template <int ACT>
@@ -111,14 +143,12 @@ __global__ void k_pack(const float* __restrict__ theta, int in_dim, int W, int N
 // weights held in registers leave room (all but the widest, deepest nets).
 // Networks 64 or more wide read their hidden weights from LDS (one 16-byte
 // read per lane feeds four products), which frees the registers for four
-// waves per SIMD (two for sine at width 80); narrower ones keep them in
-// registers.
+// waves per SIMD; narrower ones keep them in registers.
 template <int W>
 constexpr bool fwd_lds_weights() { return W >= 64; }
 template <int W, int NH, int ACT>
 constexpr int fwd_waves() {
-  return fwd_lds_weights<W>() ? (ACT == 1 && W > 64 ? 2 : 4)   // sine beyond 64 wide: registers for sin
-                              : (W * W * (NH - 1) > 64 * 64 * (ACT == 0 ? 2 : 1) ? 1 : 2);
+  return fwd_lds_weights<W>() ? 4 : (W * W * (NH - 1) > 64 * 64 * (ACT == 0 ? 2 : 1) ? 1 : 2);
 }
 
 template <int KIN, int W, int NH, int ACT>

@@ -208,7 +208,7 @@ def test_exact_metaballs4d():
 
 # ------------------------------------------------------------ MLP forward
 
-SHAPES = [(2, 32, 3), (3, 64, 3), (6, 16, 2), (4, 32, 4), (3, 16, 1), (6, 64, 4), (8, 64, 2), (4, 80, 2), (8, 80, 1)]
+SHAPES = [(2, 32, 3), (3, 64, 3), (6, 16, 2), (4, 32, 4), (3, 16, 1), (6, 64, 4), (8, 64, 2), (4, 80, 2), (8, 80, 1), (8, 80, 2)]
 
 
 def _check_logits(z, theta, in_dim, widths, q, rtol=1e-5):
@@ -682,6 +682,26 @@ def test_forward_sine_parity(in_dim, width, nh, n):
     assert np.all(np.abs(z - ref) <= 1e-5 * np.maximum(np.abs(ref), s))
     band = np.abs(ref) < 1e-4
     assert np.array_equal(h[~band], L.decide(ref)[~band])
+
+
+def test_sine_activation_accuracy():
+    """The kernels' sine against float64 sin: a 1 -> 32 -> 1 sine network with
+    one neuron passing x through (weights 1 in and out, the rest 0) returns
+    sin x exactly up to the activation's own error, here bounded by 2e-7 for
+    |x| up to 2^16 (the reduced-argument path) and beyond (the fallback)."""
+    theta = np.zeros(32 + 32 + 32 + 1, np.float32)   # W0 [32x1], b0, w_out [1x32], b_out
+    theta[0] = 1.0
+    theta[64] = 1.0
+    b = nb.Bound(1, 1, 32)
+    nb.nb_bound_set_activation(b.handle, nb.SINE)
+    b.set_params(theta)
+    rng = np.random.default_rng(11)
+    x = np.concatenate([rng.uniform(-8, 8, 20000), rng.uniform(-1000, 1000, 20000),
+                        rng.uniform(-65536, 65536, 20000), rng.uniform(-3e6, 3e6, 2000),
+                        np.float32([0.0, -0.0, np.pi / 2, np.pi, 65536.0, -65536.0, 65537.0, 1e-30])]).astype(np.float32)
+    z, _ = b.forward(cuda(x[:, None]))
+    err = np.abs(host(z).astype(np.float64) - np.sin(x.astype(np.float64)))
+    assert err.max() <= 2e-7, (err.max(), x[err.argmax()])
 
 
 @pytest.mark.parametrize("in_dim,width,nh", SINE_SHAPES)
