@@ -6,11 +6,15 @@
 // A query descends the tree level by level.  Each level is one grouped
 // forward over (region, node) pairs held contiguously per node, which keeps
 // MFMA tiles full of one network's queries instead of letting lanes walk
-// different paths: the positives of node p are found by a device-wide
-// exclusive scan of the decisions (their ranks inside p's segment keep the
-// regions' order), and each is copied to every child of p at the same rank,
-// or, when p is a leaf, its region index is written to p's output segment.
-// The host reads one pair count per level to size the next level.
+// different paths.  The positive pairs are compacted into an ascending index
+// list (block counts, a scan of the block totals, then each block writes its
+// positives at its offset), so node p's positives are a contiguous run of
+// that list, found by binary search on p's segment bounds, in the regions'
+// order.  The next level is then built one thread per positive: the thread
+// finds its node by binary search over the nodes' runs, reads its region
+// once and copies it to every child's segment at its rank among the node's
+// positives (or, at a leaf, writes the region index to the leaf's output
+// segment).  The host reads the level's counts to size the next level.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -42,28 +46,51 @@ __device__ __forceinline__ int64_t block_inclusive(int64_t x, int64_t* sh_waves)
   return x + before;
 }
 
-// Exclusive ranks of the flags inside each 4096-flag block, and the blocks'
-// totals.  local[i] = number of nonzero h[j], j < i, in i's block.
-__global__ __launch_bounds__(kScanThreads) void k_scan_local(const uint8_t* __restrict__ h, int64_t n,
-                                                             int32_t* __restrict__ local,
-                                                             int64_t* __restrict__ bsum) {
+// The 16 decision flags of a thread (1 for a nonzero byte), zero beyond n;
+// one 16-byte load when the run is whole (h is 256-byte aligned, base a
+// multiple of 16).
+__device__ __forceinline__ void load_flags16(const uint8_t* __restrict__ h, int64_t n, int64_t base, int (&f)[kScanPer]) {
+  if (base + kScanPer <= n) {
+    const uint4 v = *reinterpret_cast<const uint4*>(h + base);
+    const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) f[k] = ((w[k >> 2] >> (8 * (k & 3))) & 0xffu) != 0u;
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) f[k] = (base + k < n && h[base + k] != 0) ? 1 : 0;
+  }
+}
+
+// Positive count of each 4096-flag block.
+__global__ __launch_bounds__(kScanThreads) void k_flag_counts(const uint8_t* __restrict__ h, int64_t n,
+                                                              int64_t* __restrict__ bsum) {
+  __shared__ int64_t sh[kScanThreads / 64];
+  int f[kScanPer];
+  load_flags16(h, n, (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer, f);
+  int tot = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) tot += f[k];
+  const int64_t incl = block_inclusive(tot, sh);
+  if (threadIdx.x == kScanThreads - 1) bsum[blockIdx.x] = incl;
+}
+
+// Ascending list of the positive pairs: block b writes its positives from
+// offset bpre[b] (the exclusive prefix of the block counts) on, in order.
+__global__ __launch_bounds__(kScanThreads) void k_compact(const uint8_t* __restrict__ h, int64_t n,
+                                                          const int64_t* __restrict__ bpre,
+                                                          int32_t* __restrict__ pos_idx) {
   __shared__ int64_t sh[kScanThreads / 64];
   const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer;
   int f[kScanPer];
+  load_flags16(h, n, base, f);
   int tot = 0;
 #pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    f[k] = (base + k < n && h[base + k] != 0) ? 1 : 0;
-    tot += f[k];
-  }
+  for (int k = 0; k < kScanPer; ++k) tot += f[k];
   const int64_t incl = block_inclusive(tot, sh);
-  int run = (int)(incl - tot);
+  int64_t at = bpre[blockIdx.x] + incl - tot;
 #pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    if (base + k < n) local[base + k] = run;
-    run += f[k];
-  }
-  if (threadIdx.x == kScanThreads - 1) bsum[blockIdx.x] = incl;
+  for (int k = 0; k < kScanPer; ++k)
+    if (f[k]) pos_idx[at++] = (int32_t)(base + k);
 }
 
 // Exclusive prefix of the block totals in place (one block); total[0] = sum.
@@ -86,27 +113,49 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_blocks(int64_t* __restric
   if (threadIdx.x == 0) total[0] = carry;
 }
 
-// Global exclusive rank of pair i (i == n gives the level's positive count).
-__device__ __forceinline__ int64_t rank_of(int64_t i, int64_t n, const int32_t* __restrict__ local,
-                                           const int64_t* __restrict__ bpre, const int64_t* __restrict__ total) {
-  return i == n ? total[0] : (int64_t)local[i] + bpre[i / kScanBlock];
+// Number of positive pairs with index below x: a lower bound in the
+// ascending positive list of `total` entries.
+__device__ __forceinline__ int64_t positives_below(int64_t x, const int32_t* __restrict__ pos_idx, int64_t total) {
+  int64_t lo = 0, hi = total;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)pos_idx[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
 }
 
-// Per level (one block): the next level's per-node row offsets (every node of
-// the group: nodes before the next level empty at 0, nodes after it empty at
-// the end), the output offsets of this level's leaves, and the running sizes
-// sizes[0] = rows of the next level, sizes[1] = output pairs so far.
+// Last index c in [a, b) with off[c] <= x, for nondecreasing off with
+// off[a] <= x (the segment that holds x; empty segments are skipped).
+__device__ __forceinline__ int segment_of(const int64_t* __restrict__ off, int a, int b, int64_t x) {
+  int lo = a, hi = b - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Per level (one block): the first positive (prank) and positive count
+// (pcnt) of this level's nodes, the next level's per-node row offsets (every
+// node of the group: nodes before the next level empty at 0, nodes after it
+// empty at the end), the output offsets of this level's leaves, and the
+// running sizes sizes[0] = rows of the next level, sizes[1] = output pairs so
+// far.
 __global__ __launch_bounds__(kScanThreads) void k_hier_offsets(
-    int n_obj, int lvl_a, int lvl_b, int nxt_a, int nxt_b, const int64_t* __restrict__ qoff, int64_t n, int empty,
-    const int32_t* __restrict__ local, const int64_t* __restrict__ bpre, const int64_t* __restrict__ total,
-    const int32_t* __restrict__ parent, const int32_t* __restrict__ leaf_rank, int64_t* __restrict__ qoff_next,
-    int64_t* __restrict__ out_off, int64_t* __restrict__ sizes) {
+    int n_obj, int lvl_a, int lvl_b, int nxt_a, int nxt_b, const int64_t* __restrict__ qoff, int empty,
+    const int32_t* __restrict__ pos_idx, const int64_t* __restrict__ total, const int32_t* __restrict__ parent,
+    const int32_t* __restrict__ leaf_rank, int64_t* __restrict__ prank, int64_t* __restrict__ pcnt,
+    int64_t* __restrict__ qoff_next, int64_t* __restrict__ out_off, int64_t* __restrict__ sizes) {
   __shared__ int64_t sh[kScanThreads / 64];
   __shared__ int64_t carry;
-  auto positives = [&](int p) -> int64_t {
-    if (empty) return 0;
-    return rank_of(qoff[p + 1], n, local, bpre, total) - rank_of(qoff[p], n, local, bpre, total);
-  };
+  const int64_t npos = empty ? 0 : total[0];
+  for (int p = lvl_a + threadIdx.x; p < lvl_b; p += kScanThreads) {
+    const int64_t a = empty ? 0 : positives_below(qoff[p], pos_idx, npos);
+    prank[p] = a;
+    pcnt[p] = empty ? 0 : positives_below(qoff[p + 1], pos_idx, npos) - a;
+  }
+  __syncthreads();
+  auto positives = [&](int p) -> int64_t { return pcnt[p]; };
   // next level: node c gets as many rows as its parent has positives
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
@@ -146,32 +195,45 @@ __global__ __launch_bounds__(kScanThreads) void k_hier_offsets(
   }
 }
 
-// Copy every positive pair to its node's children (or to the output when the
-// node is a leaf) at its rank among the node's positives.
+// One thread per positive pair k of this level (in the ascending positive
+// list): its node p (the segment of this level's positive runs, staged in
+// LDS, that holds k) and its rank r among p's positives.  The thread reads
+// the pair's region once; a leaf writes the region index to its output
+// segment at rank r (entries at or beyond cap are not written), an inner
+// node copies the region to every child's segment at rank r, so consecutive
+// positives of a node write consecutive rows of each child.
 __global__ __launch_bounds__(256) void k_hier_expand(
-    int in_dim, int64_t n, const uint8_t* __restrict__ h, const float* __restrict__ rows,
-    const int32_t* __restrict__ qidx, const int32_t* __restrict__ node, const int64_t* __restrict__ qoff,
-    const int32_t* __restrict__ local, const int64_t* __restrict__ bpre, const int64_t* __restrict__ total,
-    const int32_t* __restrict__ child_b, const int32_t* __restrict__ child_e, const int32_t* __restrict__ leaf_rank,
-    const int64_t* __restrict__ qoff_next, float* __restrict__ rows_next, int32_t* __restrict__ qidx_next,
-    int32_t* __restrict__ node_next, const int64_t* __restrict__ out_off, int32_t* __restrict__ out, int64_t cap) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || h[i] == 0) return;
-  const int p = node ? node[i] : 0;
-  const int32_t qi = qidx ? qidx[i] : (int32_t)i;
-  const int64_t r = rank_of(i, n, local, bpre, total) - rank_of(qoff[p], n, local, bpre, total);
+    int in_dim, int64_t n_pos, int lvl_a, int lvl_b, const int64_t* __restrict__ prank,
+    const int32_t* __restrict__ pos_idx, const int32_t* __restrict__ child_b, const int32_t* __restrict__ child_e,
+    const int32_t* __restrict__ leaf_rank, const int64_t* __restrict__ qoff_next, const int64_t* __restrict__ out_off,
+    const float* __restrict__ rows, const int32_t* __restrict__ qidx, float* __restrict__ rows_next,
+    int32_t* __restrict__ qidx_next, int32_t* __restrict__ out, int64_t cap) {
+  extern __shared__ int64_t sfirst[];   // [nl] first positive of each node of the level
+  const int nl = lvl_b - lvl_a;
+  for (int i = threadIdx.x; i < nl; i += blockDim.x) sfirst[i] = prank[lvl_a + i];
+  __syncthreads();
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_pos) return;
+  const int i = segment_of(sfirst, 0, nl, k);
+  const int p = lvl_a + i;
+  const int64_t r = k - sfirst[i];
+  const int64_t src = pos_idx[k];
+  const int32_t qi = qidx ? qidx[src] : (int32_t)src;
   const int lr = leaf_rank[p];
   if (lr >= 0) {
-    const int64_t dst = out_off[lr] + r;
-    if (dst < cap) out[dst] = qi;
+    const int64_t u = out_off[lr] + r;
+    if (u < cap) out[u] = qi;
     return;
   }
-  const float* src = rows + i * in_dim;
+  float x[8];   // in_dim <= 8; unrolled so that x stays in registers
+#pragma unroll
+  for (int d = 0; d < 8; ++d) x[d] = d < in_dim ? rows[src * in_dim + d] : 0.0f;
   for (int c = child_b[p]; c < child_e[p]; ++c) {
     const int64_t dst = qoff_next[c] + r;
-    for (int d = 0; d < in_dim; ++d) rows_next[dst * in_dim + d] = src[d];
+#pragma unroll
+    for (int d = 0; d < 8; ++d)
+      if (d < in_dim) rows_next[dst * in_dim + d] = x[d];
     qidx_next[dst] = qi;
-    node_next[dst] = c;
   }
 }
 
@@ -183,21 +245,21 @@ struct nb_hier {
   nb_group* g = nullptr;
   int n_nodes = 0, n_leaves = 0, device = 0;
   std::vector<int> child_b, child_e, parent, level, leaf_rank;
-  std::vector<int> lvl_first;   // nodes of level l: lvl_first[l] .. lvl_first[l+1]-1
+  std::vector<int> lvl_first;       // nodes of level l: lvl_first[l] .. lvl_first[l+1]-1
   int32_t *d_child_b = nullptr, *d_child_e = nullptr, *d_parent = nullptr, *d_leaf_rank = nullptr;
-  // two pair buffers (rows, region index, node), decisions, scan, offsets
+  int64_t *d_prank = nullptr, *d_pcnt = nullptr;    // per node: first positive, positive count
+  // two pair buffers (rows, region index), decisions, positive list, scan, offsets
   int64_t pcap[2] = {0, 0};
   float* rows[2] = {nullptr, nullptr};
   int32_t* qidx[2] = {nullptr, nullptr};
-  int32_t* node[2] = {nullptr, nullptr};
   int64_t scap = 0;
   uint8_t* h = nullptr;
-  int32_t* local = nullptr;
+  int32_t* pos_idx = nullptr;
   int64_t* bsum = nullptr;
   int64_t* qoff[2] = {nullptr, nullptr};
   int64_t* misc = nullptr;      // [0] scan total, [1] rows of the next level, [2] output pairs so far
   std::vector<int64_t> level_pairs;   // (row, node) pairs per level of the last query
-  int64_t* host_sizes = nullptr;   // pinned [2]
+  int64_t* host_sizes = nullptr;   // pinned [3]: misc[0..2] of the last level
 };
 
 namespace {
@@ -219,13 +281,12 @@ void hier_free(T*& p) {
 void free_pair_set(nb_hier* t, int k) {
   hier_free(t->rows[k]);
   hier_free(t->qidx[k]);
-  hier_free(t->node[k]);
   t->pcap[k] = 0;
 }
 
 void free_scan(nb_hier* t) {
   hier_free(t->h);
-  hier_free(t->local);
+  hier_free(t->pos_idx);
   hier_free(t->bsum);
   t->scap = 0;
 }
@@ -240,7 +301,6 @@ nb_status ensure_pairs(nb_hier* t, int k, int64_t need) {
   const int64_t cap = grown(need);
   NB_TRY(hier_alloc(&t->rows[k], (size_t)cap * t->g->in_dim));
   NB_TRY(hier_alloc(&t->qidx[k], (size_t)cap));
-  NB_TRY(hier_alloc(&t->node[k], (size_t)cap));
   t->pcap[k] = cap;
   return NB_OK;
 }
@@ -251,7 +311,7 @@ nb_status ensure_scan(nb_hier* t, int64_t need) {
   free_scan(t);
   const int64_t cap = grown(need);
   NB_TRY(hier_alloc(&t->h, (size_t)cap));
-  NB_TRY(hier_alloc(&t->local, (size_t)cap));
+  NB_TRY(hier_alloc(&t->pos_idx, (size_t)cap));
   NB_TRY(hier_alloc(&t->bsum, (size_t)(cap / kScanBlock + 2)));
   t->scap = cap;
   return NB_OK;
@@ -303,10 +363,12 @@ nb_status nb_hier_create(nb_group* g, const int32_t* child_begin_host, const int
   if (st == NB_OK) st = hier_alloc(&t->d_child_e, n);
   if (st == NB_OK) st = hier_alloc(&t->d_parent, n);
   if (st == NB_OK) st = hier_alloc(&t->d_leaf_rank, n);
+  if (st == NB_OK) st = hier_alloc(&t->d_prank, n);
+  if (st == NB_OK) st = hier_alloc(&t->d_pcnt, n);
   if (st == NB_OK) st = hier_alloc(&t->qoff[0], (size_t)n + 1);
   if (st == NB_OK) st = hier_alloc(&t->qoff[1], (size_t)n + 1);
   if (st == NB_OK) st = hier_alloc(&t->misc, 4);
-  if (st == NB_OK && hipHostMalloc(reinterpret_cast<void**>(&t->host_sizes), 2 * sizeof(int64_t)) != hipSuccess) {
+  if (st == NB_OK && hipHostMalloc(reinterpret_cast<void**>(&t->host_sizes), 3 * sizeof(int64_t)) != hipSuccess) {
     nb_set_error("hipHostMalloc of the level sizes failed");
     st = NB_ERR_OOM;
   }
@@ -337,6 +399,8 @@ nb_status nb_hier_destroy(nb_hier* t) {
   hier_free(t->d_child_e);
   hier_free(t->d_parent);
   hier_free(t->d_leaf_rank);
+  hier_free(t->d_prank);
+  hier_free(t->d_pcnt);
   hier_free(t->qoff[0]);
   hier_free(t->qoff[1]);
   hier_free(t->misc);
@@ -397,9 +461,8 @@ nb_status nb_hier_query(nb_hier* t, const float* q, int64_t n, float eps, int32_
   }
   const float* rows = q;
   const int32_t* qidx = nullptr;
-  const int32_t* node = nullptr;
-  int64_t rows_n = n;
-  int cur = 0;   // pair set read by this level (written by the previous level's expansion)
+  int64_t rows_n = n, pairs_before = 0;
+  int cur = 0;   // pair set read by this level (written by the previous level)
   for (int l = 0; l < depth; ++l) {
     const int la = t->lvl_first[l], lb = t->lvl_first[l + 1];
     const int na = l + 1 < depth ? t->lvl_first[l + 1] : t->n_nodes;
@@ -412,36 +475,42 @@ nb_status nb_hier_query(nb_hier* t, const float* q, int64_t n, float eps, int32_
       NB_TRY(ensure_scan(t, rows_n));   // the stream is idle: synchronised below, and before the loop
       NB_TRY(group_forward(t->g, rows, qoff, rows_n, tau, nullptr, t->h, nullptr, nullptr, s));
       const int64_t nblk = (rows_n + kScanBlock - 1) / kScanBlock;
-      k_scan_local<<<(unsigned)nblk, kScanThreads, 0, s>>>(t->h, rows_n, t->local, t->bsum);
+      k_flag_counts<<<(unsigned)nblk, kScanThreads, 0, s>>>(t->h, rows_n, t->bsum);
       NB_LAUNCHED();
       k_scan_blocks<<<1, kScanThreads, 0, s>>>(t->bsum, nblk, t->misc);
       NB_LAUNCHED();
+      k_compact<<<(unsigned)nblk, kScanThreads, 0, s>>>(t->h, rows_n, t->bsum, t->pos_idx);
+      NB_LAUNCHED();
     }
-    k_hier_offsets<<<1, kScanThreads, 0, s>>>(t->n_nodes, la, lb, na, nbn, qoff, rows_n, empty, t->local, t->bsum,
-                                             t->misc, t->d_parent, t->d_leaf_rank, qoff_next, leaf_off,
+    k_hier_offsets<<<1, kScanThreads, 0, s>>>(t->n_nodes, la, lb, na, nbn, qoff, empty, t->pos_idx, t->misc,
+                                             t->d_parent, t->d_leaf_rank, t->d_prank, t->d_pcnt, qoff_next, leaf_off,
                                              t->misc + 1);
     NB_LAUNCHED();
-    NB_HIP(hipMemcpyAsync(t->host_sizes, t->misc + 1, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    NB_HIP(hipMemcpyAsync(t->host_sizes, t->misc, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     NB_HIP(hipStreamSynchronize(s));
-    const int64_t next_n = t->host_sizes[0];
+    const int64_t next_n = t->host_sizes[1], pairs_after = t->host_sizes[2];
     NB_REQUIRE(next_n <= (int64_t)0x7FFFFFFF, "level %d holds %lld (region, node) pairs, more than 2^31 - 1", l + 1,
                (long long)next_n);
     if (!empty) {
       const int nxt = 1 - cur;
-      NB_TRY(ensure_pairs(t, nxt, next_n));   // set nxt was read by the level before this one: finished
-      k_hier_expand<<<(unsigned)((rows_n + 255) / 256), 256, 0, s>>>(
-          in_dim, rows_n, t->h, rows, qidx, node, qoff, t->local, t->bsum, t->misc, t->d_child_b, t->d_child_e,
-          t->d_leaf_rank, qoff_next, t->rows[nxt], t->qidx[nxt], t->node[nxt], leaf_off, qidx_out, cap);
-      NB_LAUNCHED();
+      const int64_t n_pos = t->host_sizes[0];   // this level's positives (the scan total)
+      if (next_n > 0) NB_TRY(ensure_pairs(t, nxt, next_n));   // set nxt was read by the level before: finished
+      if (n_pos > 0) {
+        const size_t lds = sizeof(int64_t) * (size_t)(lb - la);   // at most 4096 x 8 B
+        k_hier_expand<<<(unsigned)((n_pos + 255) / 256), 256, lds, s>>>(
+            in_dim, n_pos, la, lb, t->d_prank, t->pos_idx, t->d_child_b, t->d_child_e, t->d_leaf_rank, qoff_next,
+            leaf_off, rows, qidx, t->rows[nxt], t->qidx[nxt], qidx_out, cap);
+        NB_LAUNCHED();
+      }
       NB_HIP(hipStreamSynchronize(s));
       rows = t->rows[nxt];
       qidx = t->qidx[nxt];
-      node = t->node[nxt];
       cur = nxt;
     }
+    pairs_before = pairs_after;
     rows_n = next_n;
   }
-  const int64_t pairs = t->host_sizes[1];
+  const int64_t pairs = t->host_sizes[2];
   k_set_i64<<<1, 1, 0, s>>>(leaf_off + t->n_leaves, pairs);
   NB_LAUNCHED();
   *n_pairs_host = pairs;
