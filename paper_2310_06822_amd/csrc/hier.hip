@@ -30,7 +30,8 @@ constexpr int kScanBlock = kScanThreads * kScanPer;  // 4096 flags per block
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 float tau_of(float eps) { return (float)std::log((0.5 - (double)eps) / (0.5 + (double)eps)); }
 
-// Inclusive scan of one int64 per thread over a block of kScanThreads.
+// Inclusive scan of one int64 per thread over the block (sh_waves holds one
+// entry per wave of the block).
 __device__ __forceinline__ int64_t block_inclusive(int64_t x, int64_t* sh_waves) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -93,24 +94,24 @@ __global__ __launch_bounds__(kScanThreads) void k_compact(const uint8_t* __restr
     if (f[k]) pos_idx[at++] = (int32_t)(base + k);
 }
 
-// Exclusive prefix of the block totals in place (one block); total[0] = sum.
-__global__ __launch_bounds__(kScanThreads) void k_scan_blocks(int64_t* __restrict__ bsum, int64_t nb,
-                                                              int64_t* __restrict__ total) {
-  __shared__ int64_t sh[kScanThreads / 64];
-  __shared__ int64_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
-    const int64_t b = b0 + threadIdx.x;
-    const int64_t x = b < nb ? bsum[b] : 0;
-    const int64_t incl = block_inclusive(x, sh);
-    const int64_t c = carry;
-    if (b < nb) bsum[b] = c + incl - x;
-    __syncthreads();
-    if (threadIdx.x == kScanThreads - 1) carry = c + incl;
-    __syncthreads();
+// Exclusive prefix of the block totals in place (one block of 1024 threads,
+// each summing a contiguous run of the totals first); total[0] = sum.
+constexpr int kPrefixThreads = 1024;
+__global__ __launch_bounds__(kPrefixThreads) void k_scan_blocks(int64_t* __restrict__ bsum, int64_t nb,
+                                                                int64_t* __restrict__ total) {
+  __shared__ int64_t sh[kPrefixThreads / 64];
+  const int64_t per = (nb + kPrefixThreads - 1) / kPrefixThreads;
+  const int64_t b0 = (int64_t)threadIdx.x * per, b1 = b0 + per < nb ? b0 + per : nb;
+  int64_t sum = 0;
+  for (int64_t b = b0; b < b1; ++b) sum += bsum[b];
+  const int64_t incl = block_inclusive(sum, sh);
+  int64_t run = incl - sum;
+  for (int64_t b = b0; b < b1; ++b) {
+    const int64_t x = bsum[b];
+    bsum[b] = run;
+    run += x;
   }
-  if (threadIdx.x == 0) total[0] = carry;
+  if (threadIdx.x == kPrefixThreads - 1) total[0] = incl;
 }
 
 // Number of positive pairs with index below x: a lower bound in the
@@ -477,7 +478,7 @@ nb_status nb_hier_query(nb_hier* t, const float* q, int64_t n, float eps, int32_
       const int64_t nblk = (rows_n + kScanBlock - 1) / kScanBlock;
       k_flag_counts<<<(unsigned)nblk, kScanThreads, 0, s>>>(t->h, rows_n, t->bsum);
       NB_LAUNCHED();
-      k_scan_blocks<<<1, kScanThreads, 0, s>>>(t->bsum, nblk, t->misc);
+      k_scan_blocks<<<1, kPrefixThreads, 0, s>>>(t->bsum, nblk, t->misc);
       NB_LAUNCHED();
       k_compact<<<(unsigned)nblk, kScanThreads, 0, s>>>(t->h, rows_n, t->bsum, t->pos_idx);
       NB_LAUNCHED();

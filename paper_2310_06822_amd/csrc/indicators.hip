@@ -289,6 +289,41 @@ __global__ void k_exact(IndView v, const float* __restrict__ q, int64_t n, uint8
   g[i] = exact_at<KIND>(v, q, i);
 }
 
+// Rays with L lanes each: lane s of a ray's group takes samples j0 + s,
+// j0 + s + L, ... of the clipped range; after every round of L samples a wave
+// ballot tells the group whether any of its lanes hit, and the group stops
+// at the first such round.  The answer is the OR over the same samples with
+// the same arithmetic as the one-lane test; only where it stops differs.
+// Small batches (training labels) get L times the threads.
+template <int L>
+__global__ __launch_bounds__(256) void k_exact_ray_split(IndView v, const float* __restrict__ q, int64_t n,
+                                                         uint8_t* __restrict__ g) {
+  static_assert(L == 2 || L == 4 || L == 8, "lanes per ray");
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / L;
+  if (i >= n) return;   // whole groups: blockDim is a multiple of L
+  const int sub = threadIdx.x & (L - 1), gbase = (threadIdx.x & 63) & ~(L - 1);
+  const float* row = q + 6 * i;
+  int j0, j1;
+  bool found = false;
+  if (ray_sample_range(row, j0, j1)) {   // the same range on every lane of the group
+    const float ox = row[0], oy = row[1], oz = row[2], dx = row[3], dy = row[4], dz = row[5];
+    const float half_n = (float)v.n * 0.5f;
+    for (int jb = j0; jb <= j1; jb += L) {
+      const int j = jb + sub;
+      bool hit = false;
+      if (j <= j1) {
+        const float t = v.ray_t[j];
+        hit = voxel_at(v.grid, v.n, half_n, ox + t * dx, oy + t * dy, oz + t * dz) != 0;
+      }
+      if ((__ballot(hit) >> gbase) & ((1ull << L) - 1)) {
+        found = true;
+        break;
+      }
+    }
+  }
+  if (sub == 0) g[i] = found;
+}
+
 // ------------------------------------------------------------- cascade
 
 // Indices of the queries the bound calls positive.  Each block takes 4096
@@ -425,6 +460,7 @@ __global__ void k_collect_occupied(const uint8_t* __restrict__ grid, int64_t cel
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+constexpr int64_t kRaySplitMax = int64_t(1) << 21;
 
 // one wave per plane, grid-stride beyond 2^16 blocks (2^18 waves)
 inline unsigned plane_blocks(int64_t n) {
@@ -444,7 +480,14 @@ nb_status launch_query_exact(const nb_indicator* ind, int kind, const float* q, 
   const IndView v = view_of(ind);
   switch (kind) {
     case NB_QUERY_POINT: k_exact<NB_QUERY_POINT><<<blocks, kThreads, 0, s>>>(v, q, n, g); break;
-    case NB_QUERY_RAY: k_exact<NB_QUERY_RAY><<<blocks, kThreads, 0, s>>>(v, q, n, g); break;
+    case NB_QUERY_RAY:
+      if (n <= (int64_t(1) << 19))
+        k_exact_ray_split<8><<<blocks_for(8 * n), kThreads, 0, s>>>(v, q, n, g);
+      else if (n <= kRaySplitMax)   // four lanes per ray up to 2^21 rays
+        k_exact_ray_split<4><<<blocks_for(4 * n), kThreads, 0, s>>>(v, q, n, g);
+      else
+        k_exact<NB_QUERY_RAY><<<blocks, kThreads, 0, s>>>(v, q, n, g);
+      break;
     case NB_QUERY_BOX: k_exact<NB_QUERY_BOX><<<blocks, kThreads, 0, s>>>(v, q, n, g); break;
     case NB_QUERY_PLANE:
       k_plane_exact<false><<<plane_blocks(n), kThreads, 0, s>>>(v, q, n, nullptr, nullptr, g);

@@ -82,6 +82,21 @@ def test_exact_voxel_points(c2_grid):
     assert np.array_equal(host(g), I.voxel_points(q, grid, 128))
 
 
+@pytest.mark.parametrize("n", [(1 << 19) - 3, (1 << 19) + 77, (1 << 21) + 5])
+def test_exact_rays_every_launch_shape(n, c2_grid):
+    """The ray test runs with 8 lanes per ray up to 2^19 rays, 4 up to 2^21
+    and 1 beyond: each shape against the oracle on a seeded sample of rows."""
+    _, _, grid = c2_grid
+    ind = nb.Indicator.voxels(cuda(grid), 128)
+    q = torch.empty((n, 6), dtype=torch.float32, device="cuda")
+    nb.nb_sample_queries(nb.RAY, 3, 31, 0, q)
+    g = host(ind.query("ray", q))
+    rows = np.sort(np.random.default_rng(n).choice(n, 4000, replace=False))
+    qs = host(q[torch.from_numpy(rows).cuda()])
+    assert np.array_equal(g[rows], I.voxel_rays(qs, grid, 128))
+    assert 0.02 < g.mean() < 0.98
+
+
 def test_exact_rays(c2_grid):
     _, _, grid = c2_grid
     ind = nb.Indicator.voxels(cuda(grid), 128)
