@@ -414,7 +414,9 @@ nb_status nb_hier_level_pairs(const nb_hier* h, int64_t* pairs_host);
  * level (the host sizes each level).  If the pairs exceed cap, entries
  * beyond cap are not written and NB_ERR_INVALID_ARG is returned with
  * *n_pairs_host set, so the caller can retry with a larger buffer.  n must
- * be below 2^31, as must the pairs of every level. */
+ * be below 2^31, as must the pairs of every level.  The handle's work space
+ * and its group are shared by every call: calls on one hierarchy must not
+ * overlap (one host thread at a time). */
 nb_status nb_hier_query(nb_hier* h, const float* q, int64_t n, float eps, int32_t* qidx_out, int64_t cap,
                         int64_t* leaf_off, int64_t* n_pairs_host, void* stream);
 
