@@ -22,7 +22,8 @@
 //   dW_l += delta_l a_{l-1}^T                          (MFMA over queries; the
 //            two operands are transposed through a per-wave LDS tile)
 // and writes one partial gradient per workgroup; a second kernel sums the
-// partials in a fixed order (deterministic) and applies Adam.
+// partials in a fixed order (deterministic), applies Adam and writes the
+// updated weights into their packed fragments.
 #include <algorithm>
 
 #include "nb_internal.h"
