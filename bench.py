@@ -61,43 +61,127 @@ def committed_traffic(name: str, source: str):
         return None
 
 
-def cpu_baseline(W, theta, seconds: float = 15.0):
-    """Oracle forward + decision on a bounded sample of held-out queries."""
-    import synth
-    from oracle import loss as L, mlp
+def cpu_model() -> str:
     try:
-        from threadpoolctl import threadpool_info
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_label_fn(W):
+    """The oracle's exact query g for the workload's scene (host copy)."""
+    import synth
+    from oracle import indicators as I
+    sc = W.scene
+    if sc["type"] == "discs":
+        discs = synth.discs2d(W.seeds["scene"], k=sc["k"])
+        return lambda q: I.discs2d(q, discs)
+    if sc["type"] == "metaballs4d":
+        a, b, r = synth.metaballs4d(W.seeds["scene"], k=sc["k"], rlo=sc["rlo"], rhi=sc["rhi"])
+        return lambda q: I.metaballs4d(q, a, b, r)
+    c, r = synth.metaballs3d(1000 + sc.get("seed_of", W.index), k=sc["k"], rlo=sc["rlo"], rhi=sc["rhi"])
+    grid = I.voxelize_metaballs(c, r, sc["n"])
+    fn = {"point": I.voxel_points, "ray": I.voxel_rays, "box": I.voxel_boxes, "plane": I.voxel_planes}[W.kind]
+    return lambda q: fn(q, grid, sc["n"])
+
+
+def cpu_baseline(W, theta, q_sample, pos_q, pos_h, seconds: float = 15.0):
+    """The oracle (float64 numpy; the bfloat16 rounding model for bfloat16
+    bounds) on the host cores, on bounded samples of the held-out queries:
+    forward + decision (all BLAS threads for `seconds`, then one core), the
+    exact query g, and one training step (Eq. 1 loss and gradient, Adam).
+    Also recounts the held-out false negatives with the trained weights on
+    every held-out query whose exact answer is 1 (pos_q, with the GPU's
+    decisions pos_h): h >= g must hold there (Sec. 3.1)."""
+    import concurrent.futures as cf
+
+    from oracle import loss as L, mlp, train as T
+    from oracle.adam import Adam
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
         cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:
+        threadpool_limits = None
         cores = os.cpu_count() or 1
     widths = [W.width] * W.n_hidden
     bf16 = W.precision == "bf16"
-    chunk = 1 << 14
-    q = synth.points(W.seeds["eval"], chunk, W.in_dim)
+    act = W.act
+    chunk = 1 << 14 if W.width <= 128 else 1 << 12
+    q = np.ascontiguousarray(q_sample[:chunk])
 
-    def timed(limit):
-        """Chunks run back to back until `limit` seconds have passed."""
+    def run_for(fn, limit):
+        """fn() back to back until `limit` seconds have passed: (calls, seconds)."""
         reps, t0 = 0, time.perf_counter()
         while True:
-            L.decide(mlp.forward(theta, W.in_dim, widths, q, bf16=bf16))
+            fn()
             reps += 1
             dt = time.perf_counter() - t0
             if dt >= limit:
                 return reps, dt
 
-    L.decide(mlp.forward(theta, W.in_dim, widths, q, bf16=bf16))   # warm-up (thread pool, first touch)
-    reps, dt = timed(seconds)
+    fwd = lambda: L.decide(mlp.forward(theta, W.in_dim, widths, q, bf16=bf16, act=act))
+    fwd()   # warm-up (thread pool, first touch)
+    reps, dt = run_for(fwd, seconds)
     out = {"value": reps * chunk / dt, "unit": "bound queries/s", "cores": int(cores), "kind": "oracle",
-           "sample": f"{reps} x {chunk} queries of the {W.name} workload, float64 numpy forward"
-                     f"{' (bfloat16 rounding model)' if bf16 else ''} + decision, {dt:.1f} s, "
-                     f"{os.cpu_count()} host cores"}
-    try:   # the same on one core, a shorter sample
-        from threadpoolctl import threadpool_limits
+           "sample": f"{reps} x {chunk} held-out queries of the {W.name} workload, float64 numpy forward"
+                     f"{' (bfloat16 rounding model)' if bf16 else ''} + decision, {dt:.1f} s on {cores} BLAS "
+                     f"threads",
+           "host": {"cpu_model": cpu_model(), "logical_cpus": os.cpu_count()}}
+    if threadpool_limits is not None:
         with threadpool_limits(1):
-            reps1, dt1 = timed(seconds / 3)
-            out["value_one_core"] = reps1 * chunk / dt1
-    except Exception:
-        pass
+            reps1, dt1 = run_for(fwd, seconds / 3)
+        out["value_one_core"] = reps1 * chunk / dt1
+    # the exact query on a sample of the same queries
+    label = oracle_label_fn(W)
+    ne = {"ray": 1 << 10, "plane": 1 << 8}.get(W.kind, 1 << 14)
+    label(q[:64])
+    reps_e, dt_e = run_for(lambda: label(q[:ne]), seconds / 3)
+    out["exact"] = {"value": reps_e * ne / dt_e, "unit": "exact queries/s",
+                    "sample": f"{reps_e} x {ne} queries, one thread (numpy)"}
+    # one training step of Alg. 1: labels, Eq. 1 loss and gradient, Adam
+    nt = 1 << 10 if W.width >= 256 else 1 << 12
+    qt = np.ascontiguousarray(q_sample[chunk:chunk + nt] if q_sample.shape[0] >= chunk + nt else q[:nt])
+    opt = Adam(theta.size)
+
+    def step():
+        y = label(qt)
+        _, g, _ = T.step_grad(theta, W.in_dim, widths, qt, y, 50.0, 1.0, bf16=bf16, act=act)
+        opt.step(theta.astype(np.float64), g)
+
+    step()
+    reps_t, dt_t = run_for(step, seconds / 3)
+    out["train"] = {"value": reps_t * nt / dt_t, "unit": "train samples/s",
+                    "sample": f"{reps_t} steps x {nt} samples (labels + loss + gradient + Adam), {cores} BLAS threads"}
+    # recount of the held-out false negatives by the oracle
+    t0 = time.perf_counter()
+    rc = 1 << 14
+    parts = [(pos_q[i:i + rc], pos_h[i:i + rc]) for i in range(0, pos_q.shape[0], rc)]
+
+    def recount(part):
+        qq, hh = part
+        z = mlp.forward(theta, W.in_dim, widths, qq, bf16=bf16, act=act)
+        sure = ~(np.abs(z) < 1e-4)
+        d = L.decide(z)
+        return int(((d == 0) & sure).sum()), int((~sure).sum()), int(((d != hh) & sure).sum())
+
+    workers = max(1, min(16, os.cpu_count() or 1))
+    ctx = threadpool_limits(1) if threadpool_limits is not None else None
+    if ctx is not None:
+        ctx.__enter__()
+    try:
+        with cf.ThreadPoolExecutor(workers) as ex:
+            res = list(ex.map(recount, parts))
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    out["oracle_recount"] = {
+        "positives": int(pos_q.shape[0]), "fn_outside_band": sum(r[0] for r in res),
+        "band_rows": sum(r[1] for r in res), "decision_differs_outside_band": sum(r[2] for r in res),
+        "band": "|z| < 1e-4", "seconds": round(time.perf_counter() - t0, 2), "threads": workers,
+        "what": "oracle float64 forward with the trained weights on every held-out query with g = 1"}
     return out
 
 
@@ -295,7 +379,9 @@ def run_workload(W, args, with_cpu: bool):
     if kdop:
         out["kdop"] = kdop
     if with_cpu:
-        out["cpu_baseline"] = cpu_baseline(W, bound.params().cpu().numpy())
+        rows = torch.nonzero(g).flatten()
+        out["cpu_baseline"] = cpu_baseline(W, bound.params().cpu().numpy(), q[:1 << 16].cpu().numpy(),
+                                           q[rows].cpu().numpy(), h[rows].cpu().numpy())
     return out
 
 
@@ -573,7 +659,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="voxel3d_point")
+    ap.add_argument("--workload", default="metaball4d_point")
     ap.add_argument("--also", action="store_true", help="also measure the other workloads")
     ap.add_argument("--train-steps", type=int, default=None)
     ap.add_argument("--eval-n", type=int, default=None)

@@ -200,6 +200,23 @@ nb_status nb_bound_get_state(const nb_bound* b, float* m, float* v, int64_t n_pa
 nb_status nb_bound_set_state(nb_bound* b, const float* m, const float* v, int64_t n_params, int64_t step,
                              void* stream);
 
+/* Checkpoint and resume of a training run (the paper trains each bound for
+ * 20-60 minutes, Sec. 3.4 "Training"): everything the training calls read
+ * from the handle -- float32 master parameters, Adam moments m and v, the
+ * Adam step count -- in one host buffer, so that training resumed from a
+ * checkpoint continues bit for bit as if it had not stopped.
+ * nb_bound_save: with host_buf NULL, *bytes receives the size needed;
+ * otherwise *bytes (in: the buffer's size, at least that much; out: bytes
+ * written) and the buffer are filled.  nb_bound_load: restores a checkpoint
+ * of a bound of the same shape, precision and activation
+ * (NB_ERR_INVALID_ARG otherwise, with the handle unchanged).  Layout: a
+ * 48-byte header (magic "NBOUNDCK", version 1, in_dim, n_hidden, width,
+ * precision, activation as int32; n_params, Adam step as int64), then theta,
+ * m, v as float32[n_params] each, in host byte order.  Both synchronise
+ * `stream`. */
+nb_status nb_bound_save(const nb_bound* b, void* host_buf, size_t* bytes, void* stream);
+nb_status nb_bound_load(nb_bound* b, const void* host_buf, size_t bytes, void* stream);
+
 /* Forward pass and decision over n queries q [n, in_dim].
  *   logits: float32[n] or NULL;  h: uint8[n] decisions or NULL.
  *   g, counts: if both non-NULL, counts (uint64[4], device) is overwritten

@@ -218,6 +218,21 @@ def nb_bound_set_state(b, m: torch.Tensor, v: torch.Tensor, step: int, stream=No
                                     m.numel(), int(step), _stream(stream)))
 
 
+def nb_bound_save(b, stream=None) -> bytes:
+    """Checkpoint of the bound's training state (parameters, Adam moments
+    and step) as bytes."""
+    size = C.c_size_t(0)
+    _check(lib().nb_bound_save(b, None, C.byref(size), _stream(stream)))
+    buf = C.create_string_buffer(size.value)
+    _check(lib().nb_bound_save(b, C.cast(buf, C.c_void_p), C.byref(size), _stream(stream)))
+    return buf.raw[:size.value]
+
+
+def nb_bound_load(b, data: bytes, stream=None):
+    buf = C.create_string_buffer(bytes(data), len(data))
+    _check(lib().nb_bound_load(b, C.cast(buf, C.c_void_p), len(data), _stream(stream)))
+
+
 def nb_bound_forward(b, q: torch.Tensor, eps: float = EPS_OUT, logits=None, h=None, g=None, counts=None,
                      stream=None):
     n = _rows(q, nb_bound_shape(b)[0])

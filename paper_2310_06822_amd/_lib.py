@@ -37,6 +37,8 @@ SIGNATURES = {
     "nb_bound_set_recompute": (i32, [vp, C.c_int]),
     "nb_bound_set_activation": (i32, [vp, C.c_int]),
     "nb_bound_set_params": (i32, [vp, vp, i64, vp]),
+    "nb_bound_save": (i32, [vp, vp, C.POINTER(C.c_size_t), vp]),
+    "nb_bound_load": (i32, [vp, vp, C.c_size_t, vp]),
     "nb_bound_get_params": (i32, [vp, vp, i64, vp]),
     "nb_bound_get_state": (i32, [vp, vp, vp, i64, C.POINTER(i64), vp]),
     "nb_bound_set_state": (i32, [vp, vp, vp, i64, i64, vp]),

@@ -480,6 +480,71 @@ nb_status nb_bound_set_state(nb_bound* b, const float* m, const float* v, int64_
   return NB_OK;
 }
 
+namespace {
+// Checkpoint layout: this header, then theta, m and v (float32[n_params] each).
+struct CkptHeader {
+  char magic[8];
+  int32_t version, in_dim, n_hidden, width, precision, activation;
+  int64_t n_params, adam_t;
+};
+constexpr char kCkptMagic[8] = {'N', 'B', 'O', 'U', 'N', 'D', 'C', 'K'};
+}  // namespace
+
+nb_status nb_bound_save(const nb_bound* b, void* host_buf, size_t* bytes, void* stream) {
+  NB_REQUIRE(b && bytes, "NULL argument");
+  const size_t need = sizeof(CkptHeader) + 3 * (size_t)b->n_params * 4;
+  if (!host_buf) {
+    *bytes = need;
+    return NB_OK;
+  }
+  NB_REQUIRE(*bytes >= need, "checkpoint needs %zu bytes, buffer has %zu", need, *bytes);
+  CkptHeader h{};
+  memcpy(h.magic, kCkptMagic, 8);
+  h.version = 1;
+  h.in_dim = b->in_dim;
+  h.n_hidden = b->n_hidden;
+  h.width = b->width;
+  h.precision = b->precision;
+  h.activation = b->activation;
+  h.n_params = b->n_params;
+  h.adam_t = b->adam_t;
+  hipStream_t s = as_stream(stream);
+  char* out = static_cast<char*>(host_buf);
+  memcpy(out, &h, sizeof h);
+  float* dst = reinterpret_cast<float*>(out + sizeof h);
+  NB_HIP(hipMemcpyAsync(dst, b->theta, b->n_params * 4, hipMemcpyDeviceToHost, s));
+  NB_HIP(hipMemcpyAsync(dst + b->n_params, b->m, b->n_params * 4, hipMemcpyDeviceToHost, s));
+  NB_HIP(hipMemcpyAsync(dst + 2 * b->n_params, b->v, b->n_params * 4, hipMemcpyDeviceToHost, s));
+  NB_HIP(hipStreamSynchronize(s));
+  *bytes = need;
+  return NB_OK;
+}
+
+nb_status nb_bound_load(nb_bound* b, const void* host_buf, size_t bytes, void* stream) {
+  NB_REQUIRE(b && host_buf, "NULL argument");
+  NB_REQUIRE(bytes >= sizeof(CkptHeader), "checkpoint too short");
+  CkptHeader h;
+  memcpy(&h, host_buf, sizeof h);
+  NB_REQUIRE(memcmp(h.magic, kCkptMagic, 8) == 0 && h.version == 1, "not a bound checkpoint (version 1)");
+  NB_REQUIRE(h.in_dim == b->in_dim && h.n_hidden == b->n_hidden && h.width == b->width &&
+                 h.precision == b->precision && h.activation == b->activation && h.n_params == b->n_params,
+             "checkpoint of a %d x %d^%d bound (precision %d, activation %d) does not fit this %d x %d^%d bound "
+             "(precision %d, activation %d)",
+             h.in_dim, h.width, h.n_hidden, h.precision, h.activation, b->in_dim, b->width, b->n_hidden,
+             b->precision, b->activation);
+  NB_REQUIRE(h.adam_t >= 0, "negative Adam step in the checkpoint");
+  NB_REQUIRE(bytes >= sizeof h + 3 * (size_t)h.n_params * 4, "checkpoint truncated");
+  hipStream_t s = as_stream(stream);
+  const float* src = reinterpret_cast<const float*>(static_cast<const char*>(host_buf) + sizeof h);
+  NB_HIP(hipMemcpyAsync(b->theta, src, b->n_params * 4, hipMemcpyHostToDevice, s));
+  NB_HIP(hipMemcpyAsync(b->m, src + b->n_params, b->n_params * 4, hipMemcpyHostToDevice, s));
+  NB_HIP(hipMemcpyAsync(b->v, src + 2 * b->n_params, b->n_params * 4, hipMemcpyHostToDevice, s));
+  b->adam_t = h.adam_t;
+  NB_TRY(repack(b, s));
+  NB_HIP(hipStreamSynchronize(s));
+  return NB_OK;
+}
+
 nb_status nb_bound_forward(const nb_bound* b, const float* q, int64_t n, float eps, float* logits, uint8_t* h,
                            const uint8_t* g, uint64_t* counts, void* stream) {
   NB_REQUIRE(b && q, "NULL argument");

@@ -33,6 +33,9 @@ constexpr GroupShape kGroupShapes[] = {{256, 2, 4}, {512, 2, 2}, {256, 1, 4}, {5
                                        {1024, 1, 1}, {768, 1, 2}};
 constexpr int kGroupVariants = sizeof(kGroupShapes) / sizeof(kGroupShapes[0]);
 
+// Fragments of an object's forward pack held in LDS: the first layer's first
+// step and the hidden layers (the second first-layer step, used for input
+// dimensions above 4, is read from global memory).
 __host__ __device__ inline int frags_fwd(int W, int NH) { return W / 16 + (NH - 1) * (W / 16) * (W / 32); }
 
 // Work plan: item_off[p] = first tile of the p-th object in width order;
@@ -171,6 +174,7 @@ __global__ __launch_bounds__(THREADS) void k_group_fwd(
     p = lo;
   }
   int cur = -1, W = 0;
+  const bf16x8* sext = pack;   // the current object's second first-layer step
   unsigned cnt[4] = {0u, 0u, 0u, 0u};
   const int wave = threadIdx.x >> 6, c = threadIdx.x & 15;
   // software pipeline: the next tile's inputs load while this tile computes
@@ -186,6 +190,7 @@ __global__ __launch_bounds__(THREADS) void k_group_fwd(
       W = widths[o];
       const int nf = frags_fwd(W, NH);
       const bf16x8* src = pack + pkoff[o];
+      sext = src + nf * 64;
       for (int i = threadIdx.x; i < nf * 64; i += THREADS) swt[i] = src[i];
       const float* th = theta + poff[o];
       for (int i = threadIdx.x; i < NH * W; i += THREADS) sbias[i] = th[nb_b_off(i / W, in_dim, W, NH) + i % W];
@@ -203,11 +208,11 @@ __global__ __launch_bounds__(THREADS) void k_group_fwd(
       load_raw<NB>(q, n_endn, in_dim, q0n, c, xn);
     }
     if (W == 32)
-      bf16_fwd_tile_x<32, NH, NB>(swt, sbias, xr, n_end, q0, tau, logits, hout, g, counts, cnt);
+      bf16_fwd_tile_x<32, NH, NB>(swt, sbias, xr, in_dim > 4, sext, n_end, q0, tau, logits, hout, g, counts, cnt);
     else if (W == 64)
-      bf16_fwd_tile_x<64, NH, NB>(swt, sbias, xr, n_end, q0, tau, logits, hout, g, counts, cnt);
+      bf16_fwd_tile_x<64, NH, NB>(swt, sbias, xr, in_dim > 4, sext, n_end, q0, tau, logits, hout, g, counts, cnt);
     else
-      bf16_fwd_tile_x<128, NH, NB>(swt, sbias, xr, n_end, q0, tau, logits, hout, g, counts, cnt);
+      bf16_fwd_tile_x<128, NH, NB>(swt, sbias, xr, in_dim > 4, sext, n_end, q0, tau, logits, hout, g, counts, cnt);
     if (it + 1 < e) {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)

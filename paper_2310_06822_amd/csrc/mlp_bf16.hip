@@ -2,13 +2,13 @@
 // "Architecture"; ReLU hidden layers), v_mfma_f32_16x16x32_bf16 with float32
 // accumulation.
 //
-// Rounding points (the paper states no precision; these are the ones the CPU
-// oracle models):
-//   first layer   "bf16x3": with v_hi = bf16(v), v_lo = bf16(v - v_hi),
-//                 W x -> W_hi x_hi + W_hi x_lo + W_lo x_hi, one K = 32 MFMA
-//                 (input dimension <= 8): lane group 0 feeds x_hi against
-//                 W_hi, group 1 x_lo against W_hi, group 2 x_hi against W_lo,
-//                 group 3 zeros.
+// Rounding points (the paper states no precision; bfloat16 operands with
+// float32 accumulation where the work is, the small first and last layers
+// at float32 accuracy):
+//   first layer   each float32 weight and input cut exactly into three
+//                 bfloat16 pieces; the six piece products that matter go
+//                 through one K = 32 MFMA step (input dimension <= 4) or two
+//                 (5..8); layout in nb_mlp.h.
 //   hidden layers weights and input activations rounded to bfloat16.
 //   output layer  float32 dot product of float32 activations.
 //
@@ -50,9 +50,9 @@ __global__ __launch_bounds__(THREADS) void k_fwd_bf16(const float* __restrict__ 
   if (n_dev && (int64_t)*n_dev < n) n = (int64_t)*n_dev;   // rows counted on the device
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   bf16x8* swt = reinterpret_cast<bf16x8*>(smem_raw);
-  float* sbias = reinterpret_cast<float*>(smem_raw + (size_t)N::NFWD * 64 * 16);
+  float* sbias = reinterpret_cast<float*>(smem_raw + (size_t)N::NALL * 64 * 16);
 
-  for (int i = threadIdx.x; i < N::NFWD * 64; i += blockDim.x) swt[i] = pack[i];
+  for (int i = threadIdx.x; i < N::NALL * 64; i += blockDim.x) swt[i] = pack[i];
   for (int i = threadIdx.x; i < NH * W; i += blockDim.x) sbias[i] = theta[nb_b_off(i / W, in_dim, W, NH) + i % W];
   for (int i = threadIdx.x; i < W + 1; i += blockDim.x) sbias[NH * W + i] = theta[nb_w_off(NH, in_dim, W) + i];
   __syncthreads();
@@ -114,8 +114,7 @@ bool bf16_supported(int in_dim, int n_hidden, int width) {
 
 int64_t bf16_pack_elems(int in_dim, int n_hidden, int width) {
   (void)in_dim;
-  const int RB = width / 16, KS = width / 32;
-  return (int64_t)(RB + (n_hidden - 1) * RB * KS) * 64 * 8;
+  return nb_bf16_fwd_slices(width, n_hidden) * 8;
 }
 
 nb_status bf16_pack(const nb_bound* b, hipStream_t s) {
@@ -217,6 +216,7 @@ __global__ __launch_bounds__(THREADS_, 1) void k_fwd_bf16_stream(const float* __
   __syncthreads();
 
   const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4, wave = threadIdx.x >> 6;
+  const bool wide = in_dim > 4;
   const float bo = swo[W];
   unsigned cnt[4] = {0u, 0u, 0u, 0u};
   int64_t k = 0;
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(THREADS_, 1) void k_fwd_bf16_stream(const float* __
     floatx4 acc[NB][RB];
     bool bad[NB];   // rows with a non-finite value
     {
-      bf16x8 xb[NB];
+      bf16x8 xb[NB], xb1[NB];
       {
         float xr[NB][8];
 #pragma unroll
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(THREADS_, 1) void k_fwd_bf16_stream(const float* __
             bad[nb] = bad[nb] || !isfinite(xr[nb][j]);
           }
         }
-        split_inputs<NB>(xr, grp, xb);
+        nb_first_operands<NB>(xr, grp, wide, xb, xb1);
       }
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo) {
@@ -247,6 +247,16 @@ __global__ __launch_bounds__(THREADS_, 1) void k_fwd_bf16_stream(const float* __
         const bf16x8 a = sfirst[mo * 64 + lane];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = mfma32(a, xb[nb], bi);
+      }
+      if (wide) {
+        // the second first-layer step's fragments come from global memory
+        // (L2): the LDS holds two streamed half-layers beside the first step
+#pragma unroll
+        for (int mo = 0; mo < RB; ++mo) {
+          const bf16x8 a = pack[(RB + (NH - 1) * S::FH + mo) * 64 + lane];
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = mfma32(a, xb1[nb], acc[nb][mo]);
+        }
       }
     }
     bf16x8 act[NB][KS];

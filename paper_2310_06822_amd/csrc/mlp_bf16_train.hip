@@ -1,7 +1,8 @@
 // Training of a bfloat16 bound (Alg. 1 steps 4-5, gradient of Eq. 1),
 // layer by layer on the matrix cores (v_mfma_f32_16x16x32_bf16, float32
 // accumulation), with the same rounding points as the bfloat16 forward: a
-// bf16x3 first layer, bfloat16 hidden layers, a float32 output layer.
+// float32-accurate first layer (three bfloat16 pieces per value, nb_mlp.h),
+// bfloat16 hidden layers, a float32 output layer.
 //
 // One kernel per layer keeps a single layer's weights in LDS (at most
 // 128 KiB for width 256); activations A_l (post-ReLU, bfloat16) and
@@ -107,16 +108,23 @@ __global__ void k_pack_bf16_t(const float* __restrict__ theta, int in_dim, int W
 template <int W>
 __global__ __launch_bounds__(256) void k_tr_first(const float* __restrict__ q, int64_t n, int in_dim, int64_t Bp,
                                                   const bf16x8* __restrict__ pack, const float* __restrict__ theta,
-                                                  uint16_t* __restrict__ A0, TrObjs T) {
+                                                  int NH, uint16_t* __restrict__ A0, TrObjs T) {
   constexpr int RB = W / 16;
   const TrObj ob = tr_obj(T);
   q += ob.o * T.q_stride * in_dim;
   pack += T.pkoff ? T.pkoff[ob.o] : 0;
   theta += ob.poff;
   A0 += ob.member * T.ms_a;
-  __shared__ bf16x8 sw[RB * 64];
+  const bool wide = in_dim > 4;
+  // the first layer's two steps: fragments 0 .. RB-1 and, after the hidden
+  // layers', the second step's RB fragments
+  __shared__ bf16x8 sw[2 * RB * 64];
   __shared__ float sb[W];
-  for (int i = threadIdx.x; i < RB * 64; i += blockDim.x) sw[i] = pack[i];
+  const bf16x8* ext = pack + (int64_t)(RB + (NH - 1) * RB * (W / 32)) * 64;
+  for (int i = threadIdx.x; i < RB * 64; i += blockDim.x) {
+    sw[i] = pack[i];
+    if (wide) sw[RB * 64 + i] = ext[i];
+  }
   for (int i = threadIdx.x; i < W; i += blockDim.x) sb[i] = theta[(int64_t)W * in_dim + i];
   __syncthreads();
   const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4;
@@ -124,19 +132,17 @@ __global__ __launch_bounds__(256) void k_tr_first(const float* __restrict__ q, i
   for (int64_t blk = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); blk < Bp / 16; blk += waves) {
     const int64_t qi = blk * 16 + c;
     const bool valid = qi < n;
-    bf16x8 xb;
+    float xr[1][8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const float x = (valid && j < in_dim) ? q[qi * in_dim + j] : 0.0f;
-      const __bf16 hi = (__bf16)x;
-      const __bf16 lo = (__bf16)(x - (float)hi);
-      xb[j] = grp == 1 ? lo : (grp == 3 ? (__bf16)0.0f : hi);
-    }
+    for (int j = 0; j < 8; ++j) xr[0][j] = (valid && j < in_dim) ? q[qi * in_dim + j] : 0.0f;
+    bf16x8 xb[1], xb1[1];
+    nb_first_operands<1>(xr, grp, wide, xb, xb1);
     uint16_t* out = A0 + qi * W;
 #pragma unroll
     for (int mo = 0; mo < RB; ++mo) {
       const float* b = sb + 16 * mo + 4 * grp;
-      floatx4 acc = nb_mfma_bf16(sw[mo * 64 + lane], xb, floatx4{b[0], b[1], b[2], b[3]});
+      floatx4 acc = nb_mfma_bf16(sw[mo * 64 + lane], xb[0], floatx4{b[0], b[1], b[2], b[3]});
+      if (wide) acc = nb_mfma_bf16(sw[(RB + mo) * 64 + lane], xb1[0], acc);
       *reinterpret_cast<uint2*>(out + 16 * mo + 4 * grp) =
           pack4(fmaxf(acc[0], 0.0f), fmaxf(acc[1], 0.0f), fmaxf(acc[2], 0.0f), fmaxf(acc[3], 0.0f));
     }
@@ -152,28 +158,93 @@ struct TrHidden {
 };
 
 // Threads per workgroup of the hidden-layer and data-gradient kernels.  A
-// width-256 layer's fragments fill 128 KB of LDS, one workgroup per CU: it
-// takes 16 waves so that each SIMD has several waves to hide memory latency.
-// The head runs one workgroup per chunk of the batch (one partial each), so
-// it takes 8 waves at every width (its per-lane output-layer sums need more
+// width-256 layer's fragments fill 128 KB of LDS, one workgroup per CU of 8
+// waves (two per SIMD: one wave's loads overlap the other's products).  The
+// head runs one workgroup per chunk of the batch (one partial each), so it
+// takes 8 waves at every width (its per-lane output-layer sums need more
 // registers than 16 waves allow).
 template <int W, bool HEAD>
-constexpr int tr_threads() { return HEAD ? 512 : (W >= 256 ? 1024 : 256); }
+constexpr int tr_threads() { return HEAD ? 512 : (W >= 256 ? 512 : 256); }
+// Blocks of 16 queries a wave multiplies per weight fragment it reads from
+// LDS in the layer kernels (k_tr_layer, k_tr_data): every fragment read
+// feeds this many matrix-core instructions, so that the LDS bandwidth (128
+// bytes per clock per CU) stays below what four busy SIMDs draw.  A divisor
+// of 4 (the padded batch is a multiple of 64 queries).
+template <int W>
+constexpr int kTrNB() { return W >= 256 ? 4 : 2; }
 // Row blocks unrolled per step of the output-neuron loop: all of them up to
 // width 64; two from width 128 on, where full unrolling hoists more fragment
 // loads than the registers of several waves per SIMD hold.
 template <int W>
 constexpr int kMoUnroll() { return W >= 128 ? 2 : W / 16; }
 
-// A_l = relu(W_l A_{l-1} + b_l) (HEAD = false), or for the last hidden layer
-// (HEAD = true) the output logit, Eq. 1 and its gradient.
-template <int W, bool HEAD>
-__global__ __launch_bounds__((tr_threads<W, HEAD>())) void k_tr_hidden(const uint16_t* __restrict__ Ain, int64_t n, int64_t CH, int l,
-                                                   int in_dim, int NH, const bf16x8* __restrict__ pack,
-                                                   const float* __restrict__ theta, uint16_t* __restrict__ Aout,
-                                                   const uint8_t* __restrict__ y, float alpha, float beta, float inv_n,
-                                                   float tau, float* __restrict__ partial,
-                                                   float* __restrict__ aux, TrObjs TO) {
+// A_l = relu(W_l A_{l-1} + b_l) over the padded batch: each wave takes NB
+// blocks of 16 queries at a time, so one LDS fragment read feeds NB products.
+template <int W>
+__global__ __launch_bounds__((tr_threads<W, false>())) void k_tr_layer(const uint16_t* __restrict__ Ain, int64_t Bp,
+                                                                      int l, int in_dim, int NH,
+                                                                      const bf16x8* __restrict__ pack,
+                                                                      const float* __restrict__ theta,
+                                                                      uint16_t* __restrict__ Aout, TrObjs TO) {
+  using T = TrHidden<W>;
+  constexpr int RB = T::RB, KS = T::KS, NB = kTrNB<W>();
+  const TrObj ob = tr_obj(TO);
+  pack += TO.pkoff ? TO.pkoff[ob.o] : 0;
+  theta += ob.poff;
+  Ain += ob.member * TO.ms_a;
+  Aout += ob.member * TO.ms_a;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  bf16x8* sw = reinterpret_cast<bf16x8*>(smem_raw);
+  float* sb = reinterpret_cast<float*>(smem_raw + (size_t)T::FH * 64 * 16);
+  const bf16x8* src = pack + (RB + (l - 1) * T::FH) * 64;
+  for (int i = threadIdx.x; i < T::FH * 64; i += blockDim.x) sw[i] = src[i];
+  for (int i = threadIdx.x; i < W; i += blockDim.x) sb[i] = theta[nb_b_off(l, in_dim, W, NH) + i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4;
+  const int64_t groups = Bp / (16 * NB);   // Bp is a multiple of 64 and NB divides 4
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t gi = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); gi < groups; gi += waves) {
+    bf16x8 bop[NB][KS];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const uint16_t* row = Ain + ((gi * NB + nb) * 16 + c) * W;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) bop[nb][ks] = gather_fwd_operand(row, ks, grp);
+    }
+#pragma unroll(kMoUnroll<W>())
+    for (int mo = 0; mo < RB; ++mo) {
+      const floatx4 bi = *reinterpret_cast<const floatx4*>(sb + 16 * mo + 4 * grp);
+      floatx4 acc[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = bi;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const bf16x8 f = sw[(mo * KS + ks) * 64 + lane];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = nb_mfma_bf16(f, bop[nb][ks], acc[nb]);
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        *reinterpret_cast<uint2*>(Aout + ((gi * NB + nb) * 16 + c) * W + 16 * mo + 4 * grp) =
+            pack4(fmaxf(acc[nb][0], 0.0f), fmaxf(acc[nb][1], 0.0f), fmaxf(acc[nb][2], 0.0f),
+                  fmaxf(acc[nb][3], 0.0f));
+    }
+  }
+}
+
+// The last hidden layer and the head: layer NH-1, the output logit, Eq. 1
+// and its gradient, D_{NH-1}; one workgroup per chunk of the batch writes
+// the chunk's output-layer partials.
+template <int W>
+__global__ __launch_bounds__((tr_threads<W, true>())) void k_tr_head(const uint16_t* __restrict__ Ain, int64_t n,
+                                                                    int64_t CH, int l, int in_dim, int NH,
+                                                                    const bf16x8* __restrict__ pack,
+                                                                    const float* __restrict__ theta,
+                                                                    uint16_t* __restrict__ Dout,
+                                                                    const uint8_t* __restrict__ y, float alpha,
+                                                                    float beta, float inv_n, float tau,
+                                                                    float* __restrict__ partial,
+                                                                    float* __restrict__ aux, TrObjs TO) {
   using T = TrHidden<W>;
   constexpr int RB = T::RB, KS = T::KS;
   const TrObj ob = tr_obj(TO);
@@ -181,55 +252,36 @@ __global__ __launch_bounds__((tr_threads<W, HEAD>())) void k_tr_hidden(const uin
   pack += TO.pkoff ? TO.pkoff[ob.o] : 0;
   theta += ob.poff;
   Ain += ob.member * TO.ms_a;
-  Aout += ob.member * (HEAD ? TO.ms_d : TO.ms_a);
-  if (HEAD) {
-    if (TO.alpha) alpha = TO.alpha[ob.o];
-    y += ob.o * TO.q_stride;
-    partial += (int64_t)gridDim.x * ob.poff;
-    aux += (int64_t)ob.o * gridDim.x * 8;
-  }
+  Dout += ob.member * TO.ms_d;
+  if (TO.alpha) alpha = TO.alpha[ob.o];
+  y += ob.o * TO.q_stride;
+  partial += (int64_t)gridDim.x * ob.poff;
+  aux += (int64_t)ob.o * gridDim.x * 8;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   bf16x8* sw = reinterpret_cast<bf16x8*>(smem_raw);
   float* sb = reinterpret_cast<float*>(smem_raw + (size_t)T::FH * 64 * 16);   // [W] bias, [W] w_out, b_out
   const bf16x8* src = pack + (RB + (l - 1) * T::FH) * 64;
   for (int i = threadIdx.x; i < T::FH * 64; i += blockDim.x) sw[i] = src[i];
   for (int i = threadIdx.x; i < W; i += blockDim.x) sb[i] = theta[nb_b_off(l, in_dim, W, NH) + i];
-  if (HEAD)
-    for (int i = threadIdx.x; i < W + 1; i += blockDim.x) sb[W + i] = theta[nb_w_off(NH, in_dim, W) + i];
+  for (int i = threadIdx.x; i < W + 1; i += blockDim.x) sb[W + i] = theta[nb_w_off(NH, in_dim, W) + i];
   __syncthreads();
 
   const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4, wave = threadIdx.x >> 6;
-  // the head writes one partial per chunk (workgroup = chunk of CH queries);
-  // the other layers stride over all blocks of the padded batch (CH = Bp)
-  const int64_t base = HEAD ? (int64_t)blockIdx.x * CH : 0;
+  const int64_t base = (int64_t)blockIdx.x * CH;
   const int64_t nblk = CH / 16;
-  const int64_t first = HEAD ? wave : (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
-  const int64_t stride = HEAD ? (blockDim.x >> 6) : (int64_t)gridDim.x * (blockDim.x >> 6);
-  float gwo[HEAD ? RB * 4 : 1];
+  float gwo[RB * 4];
 #pragma unroll
-  for (int i = 0; i < (HEAD ? RB * 4 : 1); ++i) gwo[i] = 0.0f;
+  for (int i = 0; i < RB * 4; ++i) gwo[i] = 0.0f;
   float gbo = 0.0f, lsum = 0.0f;
   unsigned cnt[4] = {0u, 0u, 0u, 0u};
 
-  for (int64_t blk = first; blk < nblk; blk += stride) {
+  for (int64_t blk = wave; blk < nblk; blk += (blockDim.x >> 6)) {
     const int64_t qi = base + blk * 16 + c;
     const uint16_t* row = Ain + qi * W;
     bf16x8 bop[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) bop[ks] = gather_fwd_operand(row, ks, grp);
-    if (!HEAD) {
-      // each row block is stored as soon as it is done (short live ranges)
-      uint16_t* out = Aout + qi * W;
-#pragma unroll(kMoUnroll<W>())
-      for (int mo = 0; mo < RB; ++mo) {
-        const float* b = sb + 16 * mo + 4 * grp;
-        floatx4 a = floatx4{b[0], b[1], b[2], b[3]};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) a = nb_mfma_bf16(sw[(mo * KS + ks) * 64 + lane], bop[ks], a);
-        *reinterpret_cast<uint2*>(out + 16 * mo + 4 * grp) =
-            pack4(fmaxf(a[0], 0.0f), fmaxf(a[1], 0.0f), fmaxf(a[2], 0.0f), fmaxf(a[3], 0.0f));
-      }
-    } else {
+    {
       floatx4 acc[RB];
 #pragma unroll(kMoUnroll<W>())
       for (int mo = 0; mo < RB; ++mo) {
@@ -265,7 +317,7 @@ __global__ __launch_bounds__((tr_threads<W, HEAD>())) void k_tr_hidden(const uin
       cnt[1] += __popcll(__ballot(own && pos && !yv));
       cnt[2] += __popcll(__ballot(own && !pos && !yv));
       cnt[3] += __popcll(__ballot(own && !pos && yv));
-      uint16_t* out = Aout + qi * W;   // D_{H-1}
+      uint16_t* out = Dout + qi * W;   // D_{H-1}
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo) {
         float d[4];
@@ -279,7 +331,7 @@ __global__ __launch_bounds__((tr_threads<W, HEAD>())) void k_tr_hidden(const uin
       }
     }
   }
-  if (HEAD) {
+  {
     // fixed-order workgroup reduction of the output-layer terms
     __syncthreads();
     float* red = reinterpret_cast<float*>(smem_raw);   // reuse the weight area: [W + 1] + [4][8]
@@ -329,7 +381,8 @@ __global__ __launch_bounds__((tr_threads<W, HEAD>())) void k_tr_hidden(const uin
 
 // ------------------------------------------------------- data gradient
 
-// D_{l-1} = (W_l^T D_l) * [A_{l-1} > 0]
+// D_{l-1} = (W_l^T D_l) * [A_{l-1} > 0], NB blocks of 16 queries per wave
+// at a time (one LDS fragment read feeds NB products).
 template <int W>
 __global__ __launch_bounds__((tr_threads<W, false>())) void k_tr_data(const uint16_t* __restrict__ Dl, const uint16_t* __restrict__ Aprev,
                                                  int64_t Bp, int l, const bf16x8* __restrict__ packT,
@@ -340,31 +393,46 @@ __global__ __launch_bounds__((tr_threads<W, false>())) void k_tr_data(const uint
   Dl += ob.member * TO.ms_d;
   Dprev += ob.member * TO.ms_d;
   Aprev += ob.member * TO.ms_a;
-  constexpr int RB = T::RB, KS = T::KS;
+  constexpr int RB = T::RB, KS = T::KS, NB = kTrNB<W>();
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   bf16x8* sw = reinterpret_cast<bf16x8*>(smem_raw);
   const bf16x8* src = packT + (l - 1) * T::FH * 64;
   for (int i = threadIdx.x; i < T::FH * 64; i += blockDim.x) sw[i] = src[i];
   __syncthreads();
   const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4;
+  const int64_t groups = Bp / (16 * NB);
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-  for (int64_t blk = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); blk < Bp / 16; blk += waves) {
-    const int64_t qi = blk * 16 + c;
-    bf16x8 bop[KS];
+  for (int64_t gi = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); gi < groups; gi += waves) {
+    bf16x8 bop[NB][KS];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) bop[ks] = *reinterpret_cast<const bf16x8*>(Dl + qi * W + 32 * ks + 8 * grp);
-    const uint16_t* arow = Aprev + qi * W;
-    uint16_t* out = Dprev + qi * W;
+    for (int nb = 0; nb < NB; ++nb) {
+      const int64_t qi = (gi * NB + nb) * 16 + c;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) bop[nb][ks] = *reinterpret_cast<const bf16x8*>(Dl + qi * W + 32 * ks + 8 * grp);
+    }
 #pragma unroll(kMoUnroll<W>())
     for (int mo = 0; mo < RB; ++mo) {
-      floatx4 acc = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+      uint2 am[NB];   // A_{l-1} of this row block, for the ReLU mask (loaded ahead of the products)
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) acc = nb_mfma_bf16(sw[(mo * KS + ks) * 64 + lane], bop[ks], acc);
-      float a[4];
-      unpack4(*reinterpret_cast<const uint2*>(arow + 16 * mo + 4 * grp), a);
-      *reinterpret_cast<uint2*>(out + 16 * mo + 4 * grp) =
-          pack4(a[0] > 0.0f ? acc[0] : 0.0f, a[1] > 0.0f ? acc[1] : 0.0f, a[2] > 0.0f ? acc[2] : 0.0f,
-                a[3] > 0.0f ? acc[3] : 0.0f);
+      for (int nb = 0; nb < NB; ++nb)
+        am[nb] = *reinterpret_cast<const uint2*>(Aprev + ((gi * NB + nb) * 16 + c) * W + 16 * mo + 4 * grp);
+      floatx4 acc[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const bf16x8 f = sw[(mo * KS + ks) * 64 + lane];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = nb_mfma_bf16(f, bop[nb][ks], acc[nb]);
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        float a[4];
+        unpack4(am[nb], a);
+        *reinterpret_cast<uint2*>(Dprev + ((gi * NB + nb) * 16 + c) * W + 16 * mo + 4 * grp) =
+            pack4(a[0] > 0.0f ? acc[nb][0] : 0.0f, a[1] > 0.0f ? acc[nb][1] : 0.0f, a[2] > 0.0f ? acc[nb][2] : 0.0f,
+                  a[3] > 0.0f ? acc[nb][3] : 0.0f);
+      }
     }
   }
 }
@@ -608,25 +676,29 @@ nb_status train_w(const TrainJob& J, hipStream_t s) {
   const ActSlots S = act_slots(NH, J.every);
   auto A = [&](int l) { return J.act + (int64_t)S.slot(l) * stride; };
   uint16_t* D[2] = {J.grad, J.grad + stride};
+  // workgroups of the layer kernels: as many as fit the CUs at once (the
+  // width-256 ones hold 128 KB of LDS each: one per CU), each striding over
+  // the batch, so every workgroup loads the layer's weights once
+  const int64_t fit = W >= 256 ? 1 : 4;
   const unsigned wx = (unsigned)std::max<int64_t>(
-      1, std::min<int64_t>(J.plan.padded / 64, std::max<int64_t>(1, 4 * (int64_t)nb_cu_count() / J.members)));
+      1, std::min<int64_t>(J.plan.padded / 64, std::max<int64_t>(1, fit * (int64_t)nb_cu_count() / J.members)));
   const dim3 wide(wx, (unsigned)J.members);
 
-  NB_TRY(allow_lds(k_tr_hidden<W, false>, lds));
-  NB_TRY(allow_lds(k_tr_hidden<W, true>, lds));
+  NB_TRY(allow_lds(k_tr_layer<W>, lds));
+  NB_TRY(allow_lds(k_tr_head<W>, lds));
   NB_TRY(allow_lds(k_tr_data<W>, (size_t)T::FH * 64 * 16));
   auto hidden = [&](int l) -> nb_status {   // A_l = relu(W_l A_{l-1} + b_l)
-    k_tr_hidden<W, false><<<wide, tr_threads<W, false>(), lds, s>>>(A(l - 1), J.n, J.plan.padded, l, in_dim, NH, J.pack, J.theta, A(l),
-                                                 nullptr, 0, 0, 0, J.tau, nullptr, nullptr, J.T);
+    k_tr_layer<W><<<wide, tr_threads<W, false>(), lds, s>>>(A(l - 1), J.plan.padded, l, in_dim, NH, J.pack, J.theta,
+                                                          A(l), J.T);
     NB_LAUNCHED();
     return NB_OK;
   };
-  k_tr_first<W><<<wide, 256, 0, s>>>(J.q, J.n, in_dim, J.plan.padded, J.pack, J.theta, A(0), J.T);
+  k_tr_first<W><<<wide, 256, 0, s>>>(J.q, J.n, in_dim, J.plan.padded, J.pack, J.theta, NH, A(0), J.T);
   NB_LAUNCHED();
   for (int l = 1; l < NH - 1; ++l) NB_TRY(hidden(l));
   // head: layer NH-1, output layer, loss, D_{NH-1}
   int cur = 0;
-  k_tr_hidden<W, true><<<grid, tr_threads<W, true>(), lds, s>>>(A(NH - 2), J.n, CH, NH - 1, in_dim, NH, J.pack, J.theta, D[cur], J.y,
+  k_tr_head<W><<<grid, tr_threads<W, true>(), lds, s>>>(A(NH - 2), J.n, CH, NH - 1, in_dim, NH, J.pack, J.theta, D[cur], J.y,
                                               J.alpha, J.beta, J.inv_n, J.tau, J.partial, J.aux, J.T);
   NB_LAUNCHED();
   constexpr int WW = W >= 256 ? 8 : 4;

@@ -1,13 +1,14 @@
 // The bfloat16 forward pass of one wave over NB blocks of 16 queries, shared
 // by the single-bound and grouped kernels (weights already in LDS).
 //
-// Rounding points: first layer "bf16x3" (W_hi x_hi + W_hi x_lo + W_lo x_hi,
-// one K = 32 MFMA, input dimension <= 8: lane group 0 feeds x_hi against
-// W_hi, group 1 x_lo against W_hi, group 2 x_hi against W_lo, group 3
-// zeros); hidden layers bfloat16 weights and activations; output layer a
-// float32 dot product.  Lane l holds neurons 16*mo + 4*(l/16) + r of query
-// l % 16 after every layer; a K = 32 step of the next layer takes the 8
-// values of row blocks 2*ks and 2*ks + 1 that the lane already holds.
+// Rounding points: the first layer at float32 accuracy (each float32 weight
+// and input cut exactly into three bfloat16 pieces, the six significant
+// piece products on the matrix cores: one K = 32 MFMA step for input
+// dimension <= 4, two for 5..8; layout in nb_mlp.h); hidden layers bfloat16
+// weights and activations; output layer a float32 dot product.  Lane l
+// holds neurons 16*mo + 4*(l/16) + r of query l % 16 after every layer; a
+// K = 32 step of the next layer takes the 8 values of row blocks 2*ks and
+// 2*ks + 1 that the lane already holds.
 #pragma once
 
 #include "nb_mlp.h"
@@ -22,9 +23,10 @@ struct B16 {
   static constexpr int RB = W / 16;
   static constexpr int KS = W / 32;
   static constexpr int FH = RB * KS;
-  static constexpr int NFWD = RB + (NH - 1) * FH;
+  static constexpr int NFWD = RB + (NH - 1) * FH;   // first-layer step 0 and the hidden layers
+  static constexpr int NALL = NFWD + RB;             // then first-layer step 1
   static constexpr int kBias = NH * W + W + 1;   // hidden biases, output weights, output bias
-  static constexpr size_t lds_bytes() { return (size_t)NFWD * 64 * 16 + (size_t)kBias * 4; }
+  static constexpr size_t lds_bytes() { return (size_t)NALL * 64 * 16 + (size_t)kBias * 4; }
 };
 
 // Raw float32 inputs of NB blocks of 16 queries (lane column c); zeros for
@@ -41,30 +43,17 @@ __device__ __forceinline__ void load_raw(const float* __restrict__ q, int64_t n,
   }
 }
 
-// bf16x3 operand of the first layer: lane group 0 and 2 take x_hi, group 1
-// x_lo = x - x_hi, group 3 zeros.
-template <int NB>
-__device__ __forceinline__ void split_inputs(const float (&xr)[NB][8], int grp, bf16x8 (&xb)[NB]) {
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const float x = xr[nb][j];
-      const __bf16 hi = (__bf16)x;
-      const __bf16 lo = (__bf16)(x - (float)hi);
-      xb[nb][j] = grp == 1 ? lo : (grp == 3 ? (__bf16)0.0f : hi);
-    }
-}
-
 // One wave's share of the forward pass: NB blocks of 16 queries starting at
 // q0 (queries >= n are padding), weights and biases already in LDS, the
 // tile's raw inputs already in registers (the grouped kernel loads the next
 // tile's inputs while this one computes).  Writes logits / decisions of the
 // valid queries and adds their confusion counts against g to cnt (when
-// counts is non-null).
+// counts is non-null).  wide: input dimension 5..8, whose second first-layer
+// step reads its fragments from sext (LDS or global memory).
 template <int W, int NH, int NB>
 __device__ __forceinline__ void bf16_fwd_tile_x(const bf16x8* __restrict__ swt, const float* __restrict__ sbias,
-                                                const float (&xr)[NB][8], int64_t n, int64_t q0, float tau,
+                                                const float (&xr)[NB][8], bool wide, const bf16x8* sext,
+                                                int64_t n, int64_t q0, float tau,
                                                 float* __restrict__ logits, uint8_t* __restrict__ hout,
                                                 const uint8_t* __restrict__ g, const unsigned long long* counts,
                                                 unsigned (&cnt)[4]) {
@@ -84,8 +73,8 @@ __device__ __forceinline__ void bf16_fwd_tile_x(const bf16x8* __restrict__ swt, 
   }
     floatx4 acc[NB][RB];
     {
-      bf16x8 xb[NB];
-      split_inputs<NB>(xr, grp, xb);
+      bf16x8 xb[NB], xb1[NB];
+      nb_first_operands<NB>(xr, grp, wide, xb, xb1);
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo) {
         const float* b = sbias + 16 * mo + 4 * grp;
@@ -93,6 +82,14 @@ __device__ __forceinline__ void bf16_fwd_tile_x(const bf16x8* __restrict__ swt, 
         const bf16x8 a = swt[mo * 64 + lane];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = mfma32(a, xb[nb], bi);
+      }
+      if (wide) {
+#pragma unroll
+        for (int mo = 0; mo < RB; ++mo) {
+          const bf16x8 a = sext[mo * 64 + lane];
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = mfma32(a, xb1[nb], acc[nb][mo]);
+        }
       }
     }
 #pragma unroll
@@ -181,5 +178,6 @@ __device__ __forceinline__ void bf16_fwd_tile(const bf16x8* __restrict__ swt, co
                                               unsigned (&cnt)[4]) {
   float xr[NB][8];
   load_raw<NB>(q, n, in_dim, q0, threadIdx.x & 15, xr);
-  bf16_fwd_tile_x<W, NH, NB>(swt, sbias, xr, n, q0, tau, logits, hout, g, counts, cnt);
+  bf16_fwd_tile_x<W, NH, NB>(swt, sbias, xr, in_dim > 4, swt + B16<W, NH>::NFWD * 64, n, q0, tau, logits, hout, g,
+                             counts, cnt);
 }

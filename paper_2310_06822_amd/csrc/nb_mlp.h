@@ -92,31 +92,127 @@ __device__ __forceinline__ nb_floatx4 nb_mfma_bf16(nb_bf16x8 a, nb_bf16x8 b, nb_
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// First layer at float32 accuracy on the bfloat16 matrix cores.  A float32
+// value v is cut exactly into three bfloat16 pieces by truncation:
+// v1 = v with its low 16 bits cleared, v2 = (v - v1) likewise, and
+// v3 = v - v1 - v2 (at most 8 significant bits: a bfloat16 itself).  W x is
+// the sum of the six piece products whose size can exceed about 2^-16 |w||x|,
+//   product p:   0        1        2        3        4        5
+//   (w, x):      (w1,x1)  (w1,x2)  (w2,x1)  (w1,x3)  (w3,x1)  (w2,x2)
+// (the three left out sum to less than 2^-20 |w||x|), laid out along K of
+// v_mfma_f32_16x16x32_bf16, lane group g holding k = 8g .. 8g + 7:
+//   in_dim <= 4: one step; group g holds product 2g for features 0..3
+//                (k = 8g .. 8g+3) and product 2g + 1 for features 0..3
+//                (k = 8g+4 .. 8g+7); group 3 is zero;
+//   in_dim 5..8: two steps; in step s group g holds product 4s + g for
+//                features 0..7 (step 1, groups 2 and 3 zero).
+__host__ __device__ inline float nb_trunc_bf16(float v) {
+  uint32_t u;
+  __builtin_memcpy(&u, &v, 4);
+  u &= 0xFFFF0000u;
+  float r;
+  __builtin_memcpy(&r, &u, 4);
+  return r;
+}
+// Piece k (1, 2 or 3) of v.
+__host__ __device__ inline float nb_piece(float v, int k) {
+  const float v1 = nb_trunc_bf16(v);
+  if (k == 1) return v1;
+  const float r = v - v1;
+  const float v2 = nb_trunc_bf16(r);
+  return k == 2 ? v2 : r - v2;
+}
+// Weight and input piece of product p.
+__host__ __device__ inline int nb_first_wpiece(int p) { return p == 2 || p == 5 ? 2 : (p == 4 ? 3 : 1); }
+__host__ __device__ inline int nb_first_xpiece(int p) { return p == 1 || p == 5 ? 2 : (p == 3 ? 3 : 1); }
+// Bits of a float32 that is a bfloat16 (its low 16 bits are zero).
+__host__ __device__ inline uint16_t nb_hi16(float v) {
+  uint32_t u;
+  __builtin_memcpy(&u, &v, 4);
+  return (uint16_t)(u >> 16);
+}
+
 // Element e (bfloat16 bits) of a bound's forward fragment pack, from its
 // float32 parameters th: e = (f*64 + lane)*8 + j with c = lane % 16,
-// g = lane / 16:
-//   f < RB            first layer, block mo = f, "bf16x3" split:
-//                       g = 0, 1: W0_hi[16mo + c][j];  g = 2: W0_lo[16mo + c][j];
-//                       g = 3: 0;  (0 for j >= in_dim)
-//   otherwise         hidden layer l (1-based), fragment (mo, ks),
+// g = lane / 16.  With NFWD = RB + (NH-1)*FH:
+//   f < RB            first layer, step 0, row block mo = f (layout above);
+//   RB <= f < NFWD    hidden layer l (1-based), fragment (mo, ks),
 //                       f = RB + (l-1)*FH + mo*KS + ks:
-//                       W_l[16mo + c][32ks + 16(j/4) + 4g + (j%4)]
+//                       W_l[16mo + c][32ks + 16(j/4) + 4g + (j%4)];
+//   NFWD <= f         first layer, step 1, row block mo = f - NFWD (zero
+//                     when in_dim <= 4).
 __host__ __device__ inline uint16_t nb_bf16_pack_elem(const float* th, int in_dim, int W, int NH, int64_t e) {
-  (void)NH;
   const int j = (int)(e & 7), lane = (int)((e >> 3) & 63);
   const int f = (int)(e >> 9);
   const int c = lane & 15, g = lane >> 4;
-  const int RB = W / 16, KS = W / 32, FH = RB * KS;
-  if (f < RB) {
-    if (j >= in_dim || g == 3) return 0;
-    const float w = th[(int64_t)(16 * f + c) * in_dim + j];
-    const uint16_t hi = nb_bf16_bits(w);
-    return g < 2 ? hi : nb_bf16_bits(w - nb_bf16_value(hi));
+  const int RB = W / 16, KS = W / 32, FH = RB * KS, NFWD = RB + (NH - 1) * FH;
+  if (f < RB || f >= NFWD) {
+    const int step = f < RB ? 0 : 1, mo = f < RB ? f : f - NFWD;
+    const int p = in_dim <= 4 ? (step ? 6 : 2 * g + j / 4) : 4 * step + g;
+    const int k = in_dim <= 4 ? j % 4 : j;
+    if (p >= 6 || k >= in_dim) return 0;
+    return nb_hi16(nb_piece(th[(int64_t)(16 * mo + c) * in_dim + k], nb_first_wpiece(p)));
   }
   const int t = f - RB;
   const int l = 1 + t / FH, rem = t % FH, mo = rem / KS, ks = rem % KS;
   const float* Wl = th + nb_w_off(l, in_dim, W);
   return nb_bf16_bits(Wl[(int64_t)(16 * mo + c) * W + 32 * ks + 16 * (j / 4) + 4 * g + (j % 4)]);
+}
+
+// Two float32 values that are bfloat16 numbers, packed (a in the low half).
+__device__ __forceinline__ unsigned nb_pack_hi16(float a, float b) {
+  return (__float_as_uint(a) >> 16) | (__float_as_uint(b) & 0xFFFF0000u);
+}
+
+// B operands of the first layer's one (wide = false: in_dim <= 4) or two
+// (wide: in_dim 5..8) K = 32 steps, from the raw inputs of the lane's query
+// column: the lane's group picks the input piece of its product (layout in
+// nb_mlp.h).  Pieces by truncation: x1 = x with its low 16 bits cleared,
+// x2 = (x - x1) likewise, x3 = x - x1 - x2; all three sums are exact.
+template <int NB>
+__device__ __forceinline__ void nb_first_operands(const float (&xr)[NB][8], int grp, bool wide, nb_bf16x8 (&x0)[NB],
+                                               nb_bf16x8 (&x1)[NB]) {
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    float p1[8], p2[8], p3[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      p1[j] = __uint_as_float(__float_as_uint(xr[nb][j]) & 0xFFFF0000u);
+      const float r = xr[nb][j] - p1[j];
+      p2[j] = __uint_as_float(__float_as_uint(r) & 0xFFFF0000u);
+      p3[j] = r - p2[j];
+    }
+    nb_uint4 u0, u1;
+    if (!wide) {
+      // features 0..3: group g holds products 2g and 2g + 1
+      //   g = 0: (x1 | x2)   g = 1: (x1 | x3)   g = 2: (x1 | x2)   g = 3: 0
+      float lo[4], hi[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        lo[j] = grp == 3 ? 0.0f : p1[j];
+        hi[j] = grp == 3 ? 0.0f : (grp == 1 ? p3[j] : p2[j]);
+      }
+      u0 = nb_uint4{nb_pack_hi16(lo[0], lo[1]), nb_pack_hi16(lo[2], lo[3]), nb_pack_hi16(hi[0], hi[1]),
+                    nb_pack_hi16(hi[2], hi[3])};
+      u1 = nb_uint4{0u, 0u, 0u, 0u};
+    } else {
+      // step 0: group g holds product g (x1, x2, x1, x3); step 1: product
+      // 4 + g (x1, x2, 0, 0)
+      float a[8], b[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        a[j] = grp == 1 ? p2[j] : (grp == 3 ? p3[j] : p1[j]);
+        b[j] = grp == 0 ? p1[j] : (grp == 1 ? p2[j] : 0.0f);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        u0[i] = nb_pack_hi16(a[2 * i], a[2 * i + 1]);
+        u1[i] = nb_pack_hi16(b[2 * i], b[2 * i + 1]);
+      }
+    }
+    x0[nb] = __builtin_bit_cast(nb_bf16x8, u0);
+    x1[nb] = __builtin_bit_cast(nb_bf16x8, u1);
+  }
 }
 
 // Element e of the transposed (backward) pack of the hidden layers:
@@ -132,9 +228,10 @@ __host__ __device__ inline uint16_t nb_bf16_pack_t_elem(const float* th, int in_
   return nb_bf16_bits(Wl[(int64_t)(32 * ks + 8 * g + j) * W + 16 * mo + c]);
 }
 
-// Number of 16-byte fragment slices of the forward / transposed packs.
+// Number of 16-byte fragment slices of the forward pack (both first-layer
+// steps and the hidden layers) / of the transposed pack.
 __host__ __device__ inline int64_t nb_bf16_fwd_slices(int W, int NH) {
-  return (int64_t)(W / 16 + (NH - 1) * (W / 16) * (W / 32)) * 64;
+  return (int64_t)(2 * (W / 16) + (NH - 1) * (W / 16) * (W / 32)) * 64;
 }
 __host__ __device__ inline int64_t nb_bf16_t_slices(int W, int NH) {
   return (int64_t)(NH - 1) * (W / 16) * (W / 32) * 64;

@@ -62,11 +62,87 @@ class TrainResult:
     alpha_final: float = 0.0
     iters: int = 0
     val_fn_history: list = field(default_factory=list)
+    alpha_history: list = field(default_factory=list)   # FN weight of each continuation iteration's steps
+    lr_history: list = field(default_factory=list)      # learning rate of each continuation iteration's steps
     converged: bool = False
 
     @property
     def samples_per_s(self) -> float:
         return self.samples / self.seconds if self.seconds > 0 else 0.0
+
+
+class Continuation:
+    """State of the step-wise continuation of one bound: the FN weight and
+    learning rate its next K steps use, and the stopping rule.  After each
+    iteration, update() takes that iteration's validation FN count: a false
+    negative raises alpha by `inc` and resets the FN-free run; `patience`
+    FN-free iterations in a row (six in the paper) or `max_iters` iterations
+    end the schedule.  The learning rate is multiplied by lr_decay after
+    every iteration, down to lr_min."""
+
+    def __init__(self, sched: Schedule, alpha: float):
+        self.s = sched
+        self.alpha = float(alpha)
+        self.lr = float(sched.lr)
+        self.run = 0
+        self.iters = 0
+
+    @property
+    def converged(self) -> bool:
+        return self.run >= self.s.patience
+
+    @property
+    def done(self) -> bool:
+        return self.converged or self.iters >= self.s.max_iters
+
+    def update(self, fn: int):
+        self.lr = max(self.s.lr_min, self.lr * self.s.lr_decay)
+        self.iters += 1
+        if fn == 0:
+            self.run += 1
+        else:
+            self.run = 0
+            self.alpha += self.s.inc
+
+
+class GroupContinuation:
+    """The continuation of a group of bounds: per-object FN weights (raised
+    after each iteration in which the object shows a validation FN) and
+    learning rates (0 for an object FN-free for `patience` iterations in a
+    row, until a later draw shows it a false negative again; the others take
+    the decayed rate).  The group stops once its whole validation draw has
+    been FN-free for `patience` iterations in a row, or after max_iters."""
+
+    def __init__(self, sched: Schedule, n_obj: int):
+        import numpy as np
+        self.s = sched
+        self.alpha = np.full(n_obj, sched.alpha_max, dtype=np.float32)
+        self.lr = np.full(n_obj, sched.lr, dtype=np.float32)
+        self.clean = np.zeros(n_obj, dtype=np.int64)
+        self.lr_now = float(sched.lr)
+        self.clean_all = 0
+        self.iters = 0
+
+    @property
+    def converged(self) -> bool:
+        return self.clean_all >= self.s.patience
+
+    @property
+    def done(self) -> bool:
+        return self.converged or self.iters >= self.s.max_iters
+
+    def update(self, fn):
+        import numpy as np
+        bad = np.asarray(fn) > 0
+        self.lr_now = max(self.s.lr_min, self.lr_now * self.s.lr_decay)
+        self.alpha[bad] += self.s.inc
+        self.lr[(self.lr > 0) | bad] = self.lr_now
+        self.clean[bad] = 0
+        self.clean[~bad] += 1
+        self.lr[self.clean >= self.s.patience] = 0.0
+        self.clean_all = 0 if bad.any() else self.clean_all + 1
+        self.iters += 1
+        return bad
 
 
 def validation_set(ind: Indicator, kind: str, seed: int, n: int, draw: int = 0, out=None):
@@ -119,29 +195,26 @@ def train(bound, ind: Indicator, kind: str, seed: int, sched: Schedule, val_seed
     a = sched.alpha_max
     lam = sched.lam_max
     if val is not None:
-        ok = 0
-        lr = sched.lr
-        while ok < sched.patience and res.iters < sched.max_iters:
-            fn_w, fp_w = (sched.beta, a) if sched.inverted else (a, sched.beta)
+        cont = Continuation(sched, a)
+        while not cont.done:
+            fn_w, fp_w = (sched.beta, cont.alpha) if sched.inverted else (cont.alpha, sched.beta)
+            res.alpha_history.append(cont.alpha)
+            res.lr_history.append(cont.lr)
             for _ in range(sched.k):
-                nb_bound_train_step(bound.handle, ind.handle, k, seed, step, sched.batch, fn_w, fp_w, lr,
+                nb_bound_train_step(bound.handle, ind.handle, k, seed, step, sched.batch, fn_w, fp_w, cont.lr,
                                     lam, lam)
                 step += 1
-            lr = max(sched.lr_min, lr * sched.lr_decay)
             sync(bound.handle)
-            val = validation_set(ind, kind, val_seed, sched.val_n, draw=res.iters, out=val)
+            val = validation_set(ind, kind, val_seed, sched.val_n, draw=cont.iters, out=val)
             # the error the bound must not make: FN, or FP for an inverted bound
             fn = int(counts(*val)[1 if sched.inverted else 3].item())
             res.val_fn_history.append(fn)
-            res.iters += 1
-            if fn == 0:
-                ok += 1
-            else:
-                ok = 0
-                a += sched.inc
+            cont.update(fn)
             if log:
-                log(f"schedule iteration {res.iters}: step {step} alpha {a:g} validation FN {fn}")
-        res.converged = ok >= sched.patience
+                log(f"schedule iteration {cont.iters}: step {step} alpha {cont.alpha:g} validation FN {fn}")
+        res.iters = cont.iters
+        res.converged = cont.converged
+        a = cont.alpha
     torch.cuda.synchronize()
     res.seconds = time.perf_counter() - t0
     res.steps = step
@@ -156,6 +229,7 @@ def train(bound, ind: Indicator, kind: str, seed: int, sched: Schedule, val_seed
 class GroupTrainResult(TrainResult):
     alpha_obj: list = field(default_factory=list)       # final per-object FN weights
     objects_with_fn: list = field(default_factory=list)  # per iteration: objects whose validation FN > 0
+    fn_obj_history: list = field(default_factory=list)   # per iteration: each object's validation FN
 
 
 def group_validation_set(group, kind: str, seed: int, per_obj: int, draw: int = 0, out=None):
@@ -205,49 +279,42 @@ def train_group(group, kind: str, seed: int, sched: Schedule, val_seed: int | No
             log(f"group ramp step {t + 1}/{T}: alpha {a:g}")
     nb_group_sync(group.handle)
     samples = step * sched.batch * group.n_obj
-    alpha = np.full(group.n_obj, sched.alpha_max, dtype=np.float32)
-    lr = np.full(group.n_obj, sched.lr, dtype=np.float32)
-    clean = np.zeros(group.n_obj, dtype=np.int64)
-    clean_all = 0
+    cont = GroupContinuation(sched, group.n_obj)
     if val_seed is not None and sched.max_iters > 0:
         val = None
-        lr_now = sched.lr
-        a_dev = torch.from_numpy(alpha).cuda()
-        lr_dev = torch.from_numpy(lr).cuda()
-        while clean_all < sched.patience and res.iters < sched.max_iters:
-            if (lr > 0).any():
+        a_dev = torch.from_numpy(cont.alpha).cuda()
+        lr_dev = torch.from_numpy(cont.lr).cuda()
+        while not cont.done:
+            active = cont.lr > 0
+            res.alpha_history.append(cont.alpha.copy())
+            res.lr_history.append(cont.lr.copy())
+            if active.any():
                 # only the objects still training are evaluated and updated
-                nb_group_set_active(group.handle, (lr > 0).astype(np.uint8))
+                nb_group_set_active(group.handle, active.astype(np.uint8))
                 for _ in range(sched.k):
                     nb_group_train_step(group.handle, group.n_obj, k, seed, step, sched.cont_batch or sched.batch,
                                         0.0, sched.beta, sched.lr, alpha_obj=a_dev, lr_obj=lr_dev)
                     step += 1
-                samples += sched.k * (sched.cont_batch or sched.batch) * int((lr > 0).sum())
-            lr_now = max(sched.lr_min, lr_now * sched.lr_decay)
+                samples += sched.k * (sched.cont_batch or sched.batch) * int(active.sum())
             nb_group_sync(group.handle)
-            val = group_validation_set(group, kind, val_seed, sched.val_n, draw=res.iters, out=val)
+            val = group_validation_set(group, kind, val_seed, sched.val_n, draw=cont.iters, out=val)
             fn = group.counts(*val)[:, 3].cpu().numpy()
-            bad = fn > 0
-            alpha[bad] += sched.inc
-            lr[(lr > 0) | bad] = lr_now
-            clean[bad] = 0
-            clean[~bad] += 1
-            lr[clean >= sched.patience] = 0.0
-            clean_all = 0 if bad.any() else clean_all + 1
-            a_dev.copy_(torch.from_numpy(alpha))
-            lr_dev.copy_(torch.from_numpy(lr))
+            bad = cont.update(fn)
+            a_dev.copy_(torch.from_numpy(cont.alpha))
+            lr_dev.copy_(torch.from_numpy(cont.lr))
             res.val_fn_history.append(int(fn.sum()))
             res.objects_with_fn.append(int(bad.sum()))
-            res.iters += 1
+            res.fn_obj_history.append(fn.copy())
             if log:
-                log(f"group schedule iteration {res.iters}: step {step}, validation FN {int(fn.sum())} over "
-                    f"{int(bad.sum())} objects, {int((lr > 0).sum())} training, alpha max {alpha.max():g}")
-        res.converged = clean_all >= sched.patience
+                log(f"group schedule iteration {cont.iters}: step {step}, validation FN {int(fn.sum())} over "
+                    f"{int(bad.sum())} objects, {int((cont.lr > 0).sum())} training, alpha max {cont.alpha.max():g}")
+        res.iters = cont.iters
+        res.converged = cont.converged
         nb_group_set_active(group.handle, None)
     torch.cuda.synchronize()
     res.seconds = time.perf_counter() - t0
     res.steps = step
     res.samples = samples
-    res.alpha_final = float(alpha.max())
-    res.alpha_obj = alpha.tolist()
+    res.alpha_final = float(cont.alpha.max())
+    res.alpha_obj = cont.alpha.tolist()
     return res
