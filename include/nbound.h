@@ -270,6 +270,19 @@ nb_status nb_bound_sync(nb_bound* b, void* stream);
 nb_status nb_cascade(nb_bound* b, const nb_indicator* ind, int kind, const float* q, int64_t n, float eps,
                      uint8_t* answer, uint64_t* n_exact, void* stream);
 
+/* nb_cascade without any device allocation, for callers that cannot
+ * allocate (code under stream capture, tight serving loops).  Same
+ * arguments, result and errors as nb_cascade, except that the positives'
+ * index list lives in a library-owned device array of NB_CASCADE_NOALLOC_MAX
+ * int32 entries (16 MiB, one per GPU, held until the process ends) instead
+ * of the bound: n above NB_CASCADE_NOALLOC_MAX gives NB_ERR_INVALID_ARG.
+ * The call never synchronises and never allocates.  All calls on one GPU
+ * share that array: calls whose work overlaps on one GPU (other streams,
+ * other threads) race and must be ordered by the caller. */
+#define NB_CASCADE_NOALLOC_MAX (1 << 22)
+nb_status nb_cascade_noalloc(nb_bound* b, const nb_indicator* ind, int kind, const float* q, int64_t n, float eps,
+                             uint8_t* answer, uint64_t* n_exact, void* stream);
+
 /* Neural early-out (Sec. 3, "Neural Early-out"): the early exit is a small
  * network on the region that is trained inverse-conservatively against the
  * complement 1 - g, i.e. it may only declare a region empty where g = 0.

@@ -276,6 +276,21 @@ def nb_cascade(b, ind, kind: int, q: torch.Tensor, answer: torch.Tensor, n_exact
                             _stream(stream)))
 
 
+CASCADE_NOALLOC_MAX = 1 << 22
+
+
+def nb_cascade_noalloc(b, ind, kind: int, q: torch.Tensor, answer: torch.Tensor, n_exact: torch.Tensor,
+                       eps: float = EPS_OUT, stream=None):
+    """nb_cascade with its index list in the library's per-GPU device array
+    (no allocation; at most CASCADE_NOALLOC_MAX queries)."""
+    n = _rows(q, nb_bound_shape(b)[0])
+    if _query_cols(int(kind), nb_indicator_dim(ind)) != q.shape[1]:
+        raise ValueError("query width does not match the indicator and kind")
+    _check(lib().nb_cascade_noalloc(b, ind, int(kind), _dev(q, torch.float32, "q"), n, float(eps),
+                                    _dev(answer, torch.uint8, "answer", n), _dev(n_exact, torch.int64, "n_exact", 1),
+                                    _stream(stream)))
+
+
 def nb_early_out(first, second, q: torch.Tensor, h: torch.Tensor, n_second: torch.Tensor, eps: float = EPS_OUT,
                  stream=None):
     n = _rows(q, nb_bound_shape(first)[0])

@@ -47,6 +47,7 @@ SIGNATURES = {
     "nb_bound_adam_step": (i32, [vp, vp, f32, f32, f32, f32, f32, f32, vp]),
     "nb_bound_train_step": (i32, [vp, vp, C.c_int, u64, u64, i64, f32, f32, f32, f32, f32, vp, vp, vp]),
     "nb_cascade": (i32, [vp, vp, C.c_int, vp, i64, f32, vp, vp, vp]),
+    "nb_cascade_noalloc": (i32, [vp, vp, C.c_int, vp, i64, f32, vp, vp, vp]),
     "nb_early_out": (i32, [vp, vp, vp, i64, f32, vp, vp, vp]),
     "nb_kdop_create": (i32, [C.c_int, C.c_int, PP]),
     "nb_kdop_destroy": (i32, [vp]),

@@ -703,6 +703,26 @@ nb_status nb_cascade(nb_bound* b, const nb_indicator* ind, int kind, const float
   return launch_cascade_exact(ind, kind, q, answer, n, b->cascade_idx, cnt, answer, s);
 }
 
+nb_status nb_cascade_noalloc(nb_bound* b, const nb_indicator* ind, int kind, const float* q, int64_t n, float eps,
+                             uint8_t* answer, uint64_t* n_exact, void* stream) {
+  NB_REQUIRE(b && ind && q && answer && n_exact, "NULL argument");
+  NB_REQUIRE(kind >= NB_QUERY_POINT && kind <= NB_QUERY_PLANE, "unknown query kind %d", kind);
+  NB_REQUIRE(n > 0 && n <= (int64_t)NB_CASCADE_NOALLOC_MAX, "n must be in 1..%d", NB_CASCADE_NOALLOC_MAX);
+  NB_REQUIRE(eps >= 0.0f && eps < 0.5f, "eps must be in [0, 0.5)");
+  NB_REQUIRE(kind_dim(kind, ind->dim) == b->in_dim, "bound input dimension %d does not match the query", b->in_dim);
+  hipStream_t s = as_stream(stream);
+  int32_t* idx = nullptr;
+  NB_TRY(cascade_scratch(&idx));
+  auto* cnt = reinterpret_cast<unsigned long long*>(n_exact);
+  NB_TRY(launch_zero_u64(cnt, 1, s));
+  const float tau = tau_of(eps);
+  if (b->precision == NB_BF16)
+    NB_TRY(bf16_forward(b, q, n, tau, nullptr, answer, nullptr, nullptr, s));
+  else
+    NB_TRY(f32_forward(b, q, n, tau, nullptr, answer, nullptr, nullptr, s));
+  return launch_cascade_exact(ind, kind, q, answer, n, idx, cnt, answer, s);
+}
+
 nb_status nb_bound_sync(nb_bound* b, void* stream) {
   NB_REQUIRE(b, "bound is NULL");
   NB_HIP(hipStreamSynchronize(as_stream(stream)));

@@ -11,6 +11,7 @@
 // n - 1 at p = 1; a point with a coordinate outside the cube (or NaN) has
 // f = 0.
 #include <algorithm>
+#include <mutex>
 
 #include "nb_internal.h"
 #include "nb_voxel.h"
@@ -522,6 +523,29 @@ nb_status launch_cascade_exact(const nb_indicator* ind, int kind, const float* q
     default: NB_REQUIRE(false, "unknown query kind %d", kind);
   }
   NB_LAUNCHED();
+  return NB_OK;
+}
+
+// Index list of the allocation-free cascade (nb_cascade_noalloc): a
+// file-scope device array, one copy per GPU, held until the process ends.
+// Host code never passes the array's name to a kernel: it looks up the
+// array's device address once per device (hipGetSymbolAddress) and passes
+// that.
+static __device__ __align__(256) int32_t scratch[NB_CASCADE_NOALLOC_MAX];
+
+nb_status cascade_scratch(int32_t** out) {
+  static std::mutex mu;
+  static int32_t* ptr[kMaxDevices] = {};
+  int dev = 0;
+  NB_HIP(hipGetDevice(&dev));
+  NB_REQUIRE(dev >= 0 && dev < kMaxDevices, "device %d beyond the %d the library tracks", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    NB_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    ptr[dev] = static_cast<int32_t*>(p);
+  }
+  *out = ptr[dev];
   return NB_OK;
 }
 

@@ -173,6 +173,10 @@ nb_status launch_voxelize(const float* params_dev, int k, float iso, int n, uint
 nb_status launch_cascade_exact(const nb_indicator* ind, int kind, const float* q, const uint8_t* h, int64_t n,
                                int32_t* idx, unsigned long long* count, uint8_t* answer, hipStream_t s);
 nb_status launch_compact_positive(const uint8_t* h, int64_t n, int32_t* idx, unsigned long long* count, hipStream_t s);
+// Device address (on the current device) of the allocation-free cascade's
+// index list, NB_CASCADE_NOALLOC_MAX int32 entries.
+constexpr int kMaxDevices = 64;
+nb_status cascade_scratch(int32_t** out);
 nb_status launch_collect_occupied(const uint8_t* grid, int64_t cells, int32_t* out, int64_t* count_dev,
                                   hipStream_t s);
 nb_status launch_column_masks(const uint8_t* grid, int n, int words, uint64_t* mask, int coarse_n, int coarse_words,
