@@ -74,21 +74,28 @@ __device__ __forceinline__ void unpack4(uint2 u, float v[4]) {
   v[3] = (float)bf16_of((uint16_t)(u.y >> 16));
 }
 
-// B operand of a forward K = 32 step in the permuted order of the forward
-// pack: lane group g takes neurons 32ks + 4g + {0..3} and 32ks + 16 + 4g + {0..3}.
-__device__ __forceinline__ bf16x8 gather_fwd_operand(const uint16_t* __restrict__ row, int ks, int g) {
-  const uint2 lo = *reinterpret_cast<const uint2*>(row + 32 * ks + 4 * g);
-  const uint2 hi = *reinterpret_cast<const uint2*>(row + 32 * ks + 16 + 4 * g);
-  bf16x8 v;
-  v[0] = bf16_of((uint16_t)(lo.x & 0xFFFF));
-  v[1] = bf16_of((uint16_t)(lo.x >> 16));
-  v[2] = bf16_of((uint16_t)(lo.y & 0xFFFF));
-  v[3] = bf16_of((uint16_t)(lo.y >> 16));
-  v[4] = bf16_of((uint16_t)(hi.x & 0xFFFF));
-  v[5] = bf16_of((uint16_t)(hi.x >> 16));
-  v[6] = bf16_of((uint16_t)(hi.y & 0xFFFF));
-  v[7] = bf16_of((uint16_t)(hi.y >> 16));
-  return v;
+// Activation rows A_l in HBM are kept in the order in which the next layer
+// reads them as its B operand ("operand order"): within each 32-neuron block
+// ks, position 8g + j holds neuron 4g + j for j < 4 and 16 + 4g + (j - 4) for
+// j >= 4.  Lane group g of a forward K = 32 step then loads its 8 values
+// with one 16-byte load at 32ks + 8g, and the lane that produced them (it
+// holds rows 4g .. 4g+3 of row blocks 2ks and 2ks + 1) stores them with one
+// 16-byte store.  Gradient rows D_l stay in neuron order.
+__device__ __forceinline__ int act_neuron(int p) {   // neuron at position p of an activation row
+  return (p & ~31) + 16 * ((p >> 2) & 1) + 4 * ((p >> 3) & 3) + (p & 3);
+}
+__device__ __forceinline__ int act_pos(int n) {      // position of neuron n
+  return (n & ~31) + 8 * ((n >> 2) & 3) + 4 * ((n >> 4) & 1) + (n & 3);
+}
+__device__ __forceinline__ bf16x8 load_fwd_operand(const uint16_t* __restrict__ row, int ks, int g) {
+  return *reinterpret_cast<const bf16x8*>(row + 32 * ks + 8 * g);
+}
+// ReLU of two row blocks' accumulators (rows 4g .. 4g+3 of blocks 2ks, 2ks + 1),
+// rounded to bfloat16, as the 16 bytes at 32ks + 8g of an activation row.
+__device__ __forceinline__ uint4 relu_pair(floatx4 a, floatx4 b) {
+  const uint2 lo = pack4(fmaxf(a[0], 0.0f), fmaxf(a[1], 0.0f), fmaxf(a[2], 0.0f), fmaxf(a[3], 0.0f));
+  const uint2 hi = pack4(fmaxf(b[0], 0.0f), fmaxf(b[1], 0.0f), fmaxf(b[2], 0.0f), fmaxf(b[3], 0.0f));
+  return uint4{lo.x, lo.y, hi.x, hi.y};
 }
 
 // ---------------------------------------------------------- transposed pack
@@ -139,12 +146,16 @@ __global__ __launch_bounds__(256) void k_tr_first(const float* __restrict__ q, i
     nb_first_operands<1>(xr, grp, wide, xb, xb1);
     uint16_t* out = A0 + qi * W;
 #pragma unroll
-    for (int mo = 0; mo < RB; ++mo) {
-      const float* b = sb + 16 * mo + 4 * grp;
-      floatx4 acc = nb_mfma_bf16(sw[mo * 64 + lane], xb[0], floatx4{b[0], b[1], b[2], b[3]});
-      if (wide) acc = nb_mfma_bf16(sw[(RB + mo) * 64 + lane], xb1[0], acc);
-      *reinterpret_cast<uint2*>(out + 16 * mo + 4 * grp) =
-          pack4(fmaxf(acc[0], 0.0f), fmaxf(acc[1], 0.0f), fmaxf(acc[2], 0.0f), fmaxf(acc[3], 0.0f));
+    for (int ks = 0; ks < RB / 2; ++ks) {
+      floatx4 acc[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int mo = 2 * ks + h;
+        const float* b = sb + 16 * mo + 4 * grp;
+        acc[h] = nb_mfma_bf16(sw[mo * 64 + lane], xb[0], floatx4{b[0], b[1], b[2], b[3]});
+        if (wide) acc[h] = nb_mfma_bf16(sw[(RB + mo) * 64 + lane], xb1[0], acc[h]);
+      }
+      *reinterpret_cast<uint4*>(out + 32 * ks + 8 * grp) = relu_pair(acc[0], acc[1]);
     }
   }
 }
@@ -160,11 +171,13 @@ struct TrHidden {
 // Threads per workgroup of the hidden-layer and data-gradient kernels.  A
 // width-256 layer's fragments fill 128 KB of LDS, one workgroup per CU of 8
 // waves (two per SIMD: one wave's loads overlap the other's products).  The
-// head runs one workgroup per chunk of the batch (one partial each), so it
-// takes 8 waves at every width (its per-lane output-layer sums need more
-// registers than 16 waves allow).
+// head runs one workgroup per chunk of the batch (one partial each) with 8
+// waves up to width 128; at width 256 its per-lane accumulators (the layer's
+// 64 outputs and 64 output-weight gradients per lane, plus the next block's
+// operands in flight) need more than the 256 registers of two waves per
+// SIMD, so it runs one wave per SIMD with up to 512.
 template <int W, bool HEAD>
-constexpr int tr_threads() { return HEAD ? 512 : (W >= 256 ? 512 : 256); }
+constexpr int tr_threads() { return HEAD ? (W >= 256 ? 256 : 512) : (W >= 256 ? 512 : 256); }
 // Blocks of 16 queries a wave multiplies per weight fragment it reads from
 // LDS in the layer kernels (k_tr_layer, k_tr_data): every fragment read
 // feeds this many matrix-core instructions, so that the LDS bandwidth (128
@@ -209,25 +222,29 @@ __global__ __launch_bounds__((tr_threads<W, false>())) void k_tr_layer(const uin
     for (int nb = 0; nb < NB; ++nb) {
       const uint16_t* row = Ain + ((gi * NB + nb) * 16 + c) * W;
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) bop[nb][ks] = gather_fwd_operand(row, ks, grp);
+      for (int ks = 0; ks < KS; ++ks) bop[nb][ks] = load_fwd_operand(row, ks, grp);
     }
-#pragma unroll(kMoUnroll<W>())
-    for (int mo = 0; mo < RB; ++mo) {
-      const floatx4 bi = *reinterpret_cast<const floatx4*>(sb + 16 * mo + 4 * grp);
-      floatx4 acc[NB];
+    // row blocks in pairs: a pair's activations are one 16-byte store per query
+#pragma unroll(kMoUnroll<W>() / 2)
+    for (int kp = 0; kp < RB / 2; ++kp) {
+      floatx4 acc[2][NB];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[nb] = bi;
+      for (int h = 0; h < 2; ++h) {
+        const int mo = 2 * kp + h;
+        const floatx4 bi = *reinterpret_cast<const floatx4*>(sb + 16 * mo + 4 * grp);
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const bf16x8 f = sw[(mo * KS + ks) * 64 + lane];
+        for (int nb = 0; nb < NB; ++nb) acc[h][nb] = bi;
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb] = nb_mfma_bf16(f, bop[nb][ks], acc[nb]);
+        for (int ks = 0; ks < KS; ++ks) {
+          const bf16x8 f = sw[(mo * KS + ks) * 64 + lane];
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[h][nb] = nb_mfma_bf16(f, bop[nb][ks], acc[h][nb]);
+        }
       }
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
-        *reinterpret_cast<uint2*>(Aout + ((gi * NB + nb) * 16 + c) * W + 16 * mo + 4 * grp) =
-            pack4(fmaxf(acc[nb][0], 0.0f), fmaxf(acc[nb][1], 0.0f), fmaxf(acc[nb][2], 0.0f),
-                  fmaxf(acc[nb][3], 0.0f));
+        *reinterpret_cast<uint4*>(Aout + ((gi * NB + nb) * 16 + c) * W + 32 * kp + 8 * grp) =
+            relu_pair(acc[0][nb], acc[1][nb]);
     }
   }
 }
@@ -275,20 +292,35 @@ __global__ __launch_bounds__((tr_threads<W, true>())) void k_tr_head(const uint1
   float gbo = 0.0f, lsum = 0.0f;
   unsigned cnt[4] = {0u, 0u, 0u, 0u};
 
+  // the next block's operands load while this block computes
+  bf16x8 nxt[KS];
+  if (wave < nblk) {
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) nxt[ks] = load_fwd_operand(Ain + (base + wave * 16 + c) * W, ks, grp);
+  }
   for (int64_t blk = wave; blk < nblk; blk += (blockDim.x >> 6)) {
     const int64_t qi = base + blk * 16 + c;
-    const uint16_t* row = Ain + qi * W;
     bf16x8 bop[KS];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) bop[ks] = gather_fwd_operand(row, ks, grp);
+    for (int ks = 0; ks < KS; ++ks) bop[ks] = nxt[ks];
+    if (blk + (blockDim.x >> 6) < nblk) {
+      const uint16_t* row = Ain + (qi + 16 * (int64_t)(blockDim.x >> 6)) * W;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) nxt[ks] = load_fwd_operand(row, ks, grp);
+    }
     {
+      // every row block stays in registers (unrolled in full); a scheduling
+      // barrier after each row block keeps its fragment loads from being
+      // hoisted above the earlier blocks' products (which would need a
+      // register per loaded fragment)
       floatx4 acc[RB];
-#pragma unroll(kMoUnroll<W>())
+#pragma unroll
       for (int mo = 0; mo < RB; ++mo) {
         const float* b = sb + 16 * mo + 4 * grp;
         acc[mo] = floatx4{b[0], b[1], b[2], b[3]};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) acc[mo] = nb_mfma_bf16(sw[(mo * KS + ks) * 64 + lane], bop[ks], acc[mo]);
+        __builtin_amdgcn_sched_barrier(0);
       }
       const float* wo = sb + W;
       float p = 0.0f;
@@ -415,7 +447,7 @@ __global__ __launch_bounds__((tr_threads<W, false>())) void k_tr_data(const uint
       uint2 am[NB];   // A_{l-1} of this row block, for the ReLU mask (loaded ahead of the products)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
-        am[nb] = *reinterpret_cast<const uint2*>(Aprev + ((gi * NB + nb) * 16 + c) * W + 16 * mo + 4 * grp);
+        am[nb] = *reinterpret_cast<const uint2*>(Aprev + ((gi * NB + nb) * 16 + c) * W + act_pos(16 * mo + 4 * grp));
       floatx4 acc[NB];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[nb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -493,7 +525,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_tr_weight(const uint16_t* __rest
       db1 += (float)bf16_of(d1[i]);
     }
     uint16_t* rd0 = sD[bufi] + (2 * pr) * kTS + gq * QPT;
-    uint16_t* ra0 = sA[bufi] + (2 * pr) * kTS + gq * QPT;
+    uint16_t* ra0 = sA[bufi] + act_neuron(2 * pr) * kTS + gq * QPT;   // positions 2pr, 2pr+1: two consecutive neurons
 #pragma unroll
     for (int i = 0; i < QPT; i += 2) {
       *reinterpret_cast<uint32_t*>(rd0 + i) = (uint32_t)d0[i] | ((uint32_t)d0[i + 1] << 16);
