@@ -41,9 +41,17 @@ def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
-def committed_traffic(name: str, source: str):
+def sources_sha256(sources) -> str:
+    """SHA-256 over the bytes of the given files (repository paths), in order."""
+    h = hashlib.sha256()
+    for src in sources:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return h.hexdigest()
+
+
+def committed_traffic(name: str, sources):
     """HBM bytes per launch from a committed rocprofv3 counter summary, or None
-    if the kernel source has changed since the counters were taken."""
+    if a source file of the kernel has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -52,8 +60,9 @@ def committed_traffic(name: str, source: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(os.path.join(ROOT, source), "rb").read()).hexdigest()
-    if kv.get("source_sha256") != sha:
+    if kv.get("sources", kv.get("source")) != " ".join(sources):
+        return None
+    if kv.get("source_sha256") != sources_sha256(sources):
         return None
     try:
         return int(float(kv["traffic_bytes_per_launch"]))
@@ -347,10 +356,12 @@ def run_workload(W, args, with_cpu: bool):
     flop_per_q = 2 * macs
     peak = PEAK_TFLOPS[W.precision]
     achieved = flop_per_q * n_eval / (kern_ms / 1e3) / 1e12
-    src = "paper_2310_06822_amd/csrc/" + ("mlp_bf16.hip" if prec == nb.BF16 else "mlp_f32.hip")
+    csrc = "paper_2310_06822_amd/csrc/"
+    srcs = ([csrc + "mlp_bf16.hip", csrc + "nb_bf16_fwd.h", csrc + "nb_mlp.h"] if prec == nb.BF16
+            else [csrc + "mlp_f32.hip", csrc + "nb_mlp.h"])
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4),
-                "traffic": committed_traffic(f"{W.name}_forward_traffic.txt", src),
+                "traffic": committed_traffic(f"{W.name}_forward_traffic.txt", srcs),
                 "kernel": f"{('k_fwd_bf16_stream' if W.width == 256 else 'k_fwd_bf16') if prec == nb.BF16 else 'k_fwd'} "
                           f"({W.precision} MLP forward + decision)",
                 "flop_per_query": flop_per_q, "avg_launch_ms": round(kern_ms, 4)}

@@ -43,6 +43,7 @@ class Workload:
     act: str = "relu"          # hidden activation: "relu" or "sine" (the paper's)
     real_width: int = 0        # neurons per hidden layer before zero padding to `width` (0: width)
     kdop_k: int = 0            # also train and measure a k-DOP with k directions (0: none)
+    val_n: int = 0             # validation draw per scheduling iteration (0: min(eval_n, 2^24))
     bench_also: bool = False   # measured by `bench.py --also`
 
     @property
@@ -53,7 +54,8 @@ class Workload:
     def schedule(self, **kw):
         from .trainer import Schedule
         args = dict(steps=self.train_steps, batch=self.batch, alpha_max=self.alpha_max, k=self.adapt_k,
-                    inc=self.adapt_inc, max_iters=self.adapt_iters, val_n=min(self.eval_n, 1 << 24),
+                    inc=self.adapt_inc, max_iters=self.adapt_iters,
+                    val_n=self.val_n or min(self.eval_n, 1 << 24),
                     lr_decay=self.lr_decay)
         args.update(kw)
         return Schedule(**args)
@@ -69,8 +71,8 @@ VOXEL3D_RAY = Workload("voxel3d_ray", 2, "ray", 3, 6, 128, 4, "bf16",
                        train_steps=5000, batch=1 << 18, eval_n=1 << 24, lr_decay=0.99, bench_also=True)
 METABALL4D_POINT = Workload("metaball4d_point", 4, "point", 4, 4, 256, 6, "bf16",
                             scene={"type": "metaballs4d", "k": 24, "rlo": 0.05, "rhi": 0.2},
-                            train_steps=2000, batch=1 << 20, eval_n=1 << 24, adapt_k=100, adapt_iters=400,
-                            lr_decay=0.99, recompute=3)
+                            train_steps=2000, batch=1 << 20, eval_n=1 << 24, adapt_k=100, adapt_iters=500,
+                            lr_decay=0.99, recompute=3, val_n=1 << 26)
 
 # The 3-D point workload with the paper's own network: 3 x 50 x 50 with sine
 # activations (Sec. 3.4; supplemental architecture table), run as 3 x 64 x 64

@@ -745,8 +745,8 @@ nb_status train_w(const TrainJob& J, hipStream_t s) {
     }
     k_tr_weight<W, WW><<<grid, WW * 64, wlds, s>>>(D[cur], A(l - 1), CH, l, in_dim, NH, J.partial, J.T);
     NB_LAUNCHED();
-    k_tr_data<W><<<wide, tr_threads<W, false>(), (size_t)T::FH * 64 * 16, s>>>(D[cur], A(l - 1), J.plan.padded, l, J.packT, D[cur ^ 1],
-                                                           J.T);
+    k_tr_data<W><<<wide, tr_threads<W, false>(), (size_t)T::FH * 64 * 16, s>>>(D[cur], A(l - 1), J.plan.padded, l,
+                                                                             J.packT, D[cur ^ 1], J.T);
     NB_LAUNCHED();
     cur ^= 1;
   }
