@@ -135,7 +135,7 @@ class GroupWorkload:
 
 BATCHED_BOX = GroupWorkload("batched_box", 3, 256, "box", 6, 3, grid_sizes=(32, 64, 128), widths=(32, 64, 128),
                             k_range=(4, 32), train_steps=2000, per_obj=1 << 12, eval_per_obj=1 << 16,
-                            val_per_obj=1 << 18, adapt_k=50, adapt_iters=1500, lr_decay=0.998)
+                            val_per_obj=1 << 18, adapt_k=50, adapt_iters=1500)
 
 GROUP_WORKLOADS = {BATCHED_BOX.name: BATCHED_BOX}
 

@@ -442,28 +442,34 @@ __global__ __launch_bounds__((tr_threads<W, false>())) void k_tr_data(const uint
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) bop[nb][ks] = *reinterpret_cast<const bf16x8*>(Dl + qi * W + 32 * ks + 8 * grp);
     }
-#pragma unroll(kMoUnroll<W>())
-    for (int mo = 0; mo < RB; ++mo) {
-      uint2 am[NB];   // A_{l-1} of this row block, for the ReLU mask (loaded ahead of the products)
+    // row blocks in pairs: a pair's ReLU mask is one 16-byte load of A_{l-1}
+    // (operand order), loaded ahead of the pair's products
+#pragma unroll(kMoUnroll<W>() / 2)
+    for (int kp = 0; kp < RB / 2; ++kp) {
+      uint4 am[NB];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
-        am[nb] = *reinterpret_cast<const uint2*>(Aprev + ((gi * NB + nb) * 16 + c) * W + act_pos(16 * mo + 4 * grp));
-      floatx4 acc[NB];
+        am[nb] = *reinterpret_cast<const uint4*>(Aprev + ((gi * NB + nb) * 16 + c) * W + 32 * kp + 8 * grp);
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[nb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+      for (int h = 0; h < 2; ++h) {
+        const int mo = 2 * kp + h;
+        floatx4 acc[NB];
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const bf16x8 f = sw[(mo * KS + ks) * 64 + lane];
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb] = nb_mfma_bf16(f, bop[nb][ks], acc[nb]);
-      }
+        for (int ks = 0; ks < KS; ++ks) {
+          const bf16x8 f = sw[(mo * KS + ks) * 64 + lane];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        float a[4];
-        unpack4(am[nb], a);
-        *reinterpret_cast<uint2*>(Dprev + ((gi * NB + nb) * 16 + c) * W + 16 * mo + 4 * grp) =
-            pack4(a[0] > 0.0f ? acc[nb][0] : 0.0f, a[1] > 0.0f ? acc[nb][1] : 0.0f, a[2] > 0.0f ? acc[nb][2] : 0.0f,
-                  a[3] > 0.0f ? acc[nb][3] : 0.0f);
+          for (int nb = 0; nb < NB; ++nb) acc[nb] = nb_mfma_bf16(f, bop[nb][ks], acc[nb]);
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          float a[4];
+          unpack4(h ? uint2{am[nb].z, am[nb].w} : uint2{am[nb].x, am[nb].y}, a);
+          *reinterpret_cast<uint2*>(Dprev + ((gi * NB + nb) * 16 + c) * W + 16 * mo + 4 * grp) =
+              pack4(a[0] > 0.0f ? acc[nb][0] : 0.0f, a[1] > 0.0f ? acc[nb][1] : 0.0f,
+                    a[2] > 0.0f ? acc[nb][2] : 0.0f, a[3] > 0.0f ? acc[nb][3] : 0.0f);
+        }
       }
     }
   }
