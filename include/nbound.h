@@ -176,6 +176,19 @@ nb_status nb_bound_set_variant(nb_bound* b, int variant);
  * more forward pass.  Float32 bounds accept only 0. */
 nb_status nb_bound_set_recompute(nb_bound* b, int every);
 
+/* Training kernel of a bfloat16 bound (Alg. 1 steps 4-5).  NB_TRAIN_AUTO
+ * (default) runs one fused kernel per step for widths 32, 64 and 128 with
+ * 2..4 hidden layers and input size <= 8: forward, Eq. 1 and backward of a
+ * chunk of the batch on one workgroup, activations and gradients kept on the
+ * chip, and the layer-wise kernels (activations of the batch in HBM, one
+ * launch per layer and pass) for every other shape.  NB_TRAIN_LAYERWISE
+ * forces the layer-wise kernels.  Both compute the same gradient to within
+ * float32 summation order.  Repacks the bound's transposed weight fragments
+ * on `stream` (the two kernels read them in different orders). */
+#define NB_TRAIN_AUTO 0
+#define NB_TRAIN_LAYERWISE 1
+nb_status nb_bound_set_train_kernel(nb_bound* b, int kernel, void* stream);
+
 /* Hidden-layer activation: NB_ACT_RELU (default) or NB_ACT_SINE, the paper's
  * sinusoidal activation a = sin z (Sec. 3.4, "Architecture"; derivative
  * cos z in training).  Sine is available for float32 bounds of width 32 or

@@ -194,6 +194,13 @@ def nb_bound_set_recompute(b, every: int):
     _check(lib().nb_bound_set_recompute(b, int(every)))
 
 
+TRAIN_AUTO, TRAIN_LAYERWISE = 0, 1
+
+
+def nb_bound_set_train_kernel(b, kernel: int, stream=None):
+    _check(lib().nb_bound_set_train_kernel(b, int(kernel), _stream(stream)))
+
+
 def nb_bound_set_variant(b, variant: int):
     _check(lib().nb_bound_set_variant(b, int(variant)))
 

@@ -35,6 +35,7 @@ SIGNATURES = {
     "nb_bound_num_variants": (i32, [vp, C.POINTER(C.c_int)]),
     "nb_bound_set_variant": (i32, [vp, C.c_int]),
     "nb_bound_set_recompute": (i32, [vp, C.c_int]),
+    "nb_bound_set_train_kernel": (i32, [vp, C.c_int, vp]),
     "nb_bound_set_activation": (i32, [vp, C.c_int]),
     "nb_bound_set_params": (i32, [vp, vp, i64, vp]),
     "nb_bound_save": (i32, [vp, vp, C.POINTER(C.c_size_t), vp]),

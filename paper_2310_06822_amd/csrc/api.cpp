@@ -76,7 +76,8 @@ nb_status train_partials(nb_bound* b, const float* q, const uint8_t* y, int64_t 
   if (b->precision != NB_BF16) return f32_train_partials(b, q, y, n, alpha, beta, tau, n_wg, s);
   const BF16TrainPlan plan = bf16_train_plan(n);
   const int slots = bf16_act_slots(b->n_hidden, b->recompute);
-  if (b->tr_cap < plan.padded || b->tr_slots != slots) {
+  // the fused step keeps activations on the chip: no work space
+  if (!bf16_uses_fused(b) && (b->tr_cap < plan.padded || b->tr_slots != slots)) {
     // (re)sizes the activation / gradient work space (synchronising)
     NB_HIP(hipStreamSynchronize(s));
     const int64_t cap = std::max(plan.padded, b->tr_cap);
@@ -426,6 +427,15 @@ nb_status nb_bound_set_recompute(nb_bound* b, int every) {
   NB_REQUIRE(b->precision == NB_BF16 || every == 0, "activation recomputation applies to bfloat16 training");
   b->recompute = every;
   return NB_OK;
+}
+
+nb_status nb_bound_set_train_kernel(nb_bound* b, int kernel, void* stream) {
+  NB_REQUIRE(b, "bound is NULL");
+  NB_REQUIRE(kernel == NB_TRAIN_AUTO || kernel == NB_TRAIN_LAYERWISE, "unknown training kernel %d", kernel);
+  NB_REQUIRE(b->precision == NB_BF16 || kernel == NB_TRAIN_AUTO, "the training kernel choice applies to bfloat16");
+  if (b->train_kernel == kernel) return NB_OK;
+  b->train_kernel = kernel;
+  return b->precision == NB_BF16 ? bf16_pack_t(b, as_stream(stream)) : NB_OK;
 }
 
 nb_status nb_bound_set_variant(nb_bound* b, int variant) {

@@ -309,7 +309,8 @@ __global__ void k_group_pack(const float* __restrict__ theta, const int64_t* __r
     if (e < nf)
       pack[pkoff[o] * 8 + e] = nb_bf16_pack_elem(th, in_dim, W, NH, e);
     else
-      packT[ptoff[o] * 8 + (e - nf)] = nb_bf16_pack_t_elem(th, in_dim, W, NH, e - nf);
+      packT[ptoff[o] * 8 + (e - nf)] =
+          nb_bf16_pack_t_elem(th, in_dim, W, NH, e - nf, nb_bf16_fused_shape(in_dim, NH, W));
   }
 }
 

@@ -23,91 +23,22 @@
 // a fixed order, so a step is bit-reproducible.
 #include <algorithm>
 
+#include "nb_bf16_train.h"
 #include "nb_internal.h"
-#include "nb_mlp.h"
 
 namespace {
 
-typedef nb_bf16x8 bf16x8;
-typedef nb_floatx4 floatx4;
-
-// Which bound a workgroup trains: blockIdx.y selects a member of a list of
-// same-width bounds (a group's width class); a single bound has no list.
-struct TrObjs {
-  const int* objs;        // member -> object id (nullptr: one bound, object 0)
-  const int64_t* poff;    // parameter offset per object (nullptr: 0)
-  const int64_t* pkoff;   // forward-pack offset per object, 16-byte slices
-  const int64_t* ptoff;   // transposed-pack offset per object, 16-byte slices
-  int64_t q_stride;       // batch rows per object
-  int64_t ms_a, ms_d;     // activation / gradient workspace elements per member
-  int64_t P;              // parameters of the single bound (objs == nullptr)
-  const float* alpha;     // per-object FN weight of Eq. 1 (nullptr: the scalar alpha)
-};
-
-struct TrObj {
-  int o, member;
-  int64_t poff, P;
-};
-
-__device__ __forceinline__ TrObj tr_obj(const TrObjs& T) {
-  TrObj r;
-  r.member = blockIdx.y;
-  r.o = T.objs ? T.objs[r.member] : 0;
-  r.poff = T.poff ? T.poff[r.o] : 0;
-  r.P = T.poff ? T.poff[r.o + 1] - r.poff : T.P;
-  return r;
-}
-
-__device__ __forceinline__ uint16_t bits_of(__bf16 v) { return __builtin_bit_cast(uint16_t, v); }
-__device__ __forceinline__ __bf16 bf16_of(uint16_t v) { return __builtin_bit_cast(__bf16, v); }
-
-// Four float32 values rounded to bfloat16 and packed for one 8-byte store.
-__device__ __forceinline__ uint2 pack4(float a, float b, float c, float d) {
-  return uint2{(uint32_t)bits_of((__bf16)a) | ((uint32_t)bits_of((__bf16)b) << 16),
-               (uint32_t)bits_of((__bf16)c) | ((uint32_t)bits_of((__bf16)d) << 16)};
-}
-
-__device__ __forceinline__ void unpack4(uint2 u, float v[4]) {
-  v[0] = (float)bf16_of((uint16_t)(u.x & 0xFFFF));
-  v[1] = (float)bf16_of((uint16_t)(u.x >> 16));
-  v[2] = (float)bf16_of((uint16_t)(u.y & 0xFFFF));
-  v[3] = (float)bf16_of((uint16_t)(u.y >> 16));
-}
-
-// Activation rows A_l in HBM are kept in the order in which the next layer
-// reads them as its B operand ("operand order"): within each 32-neuron block
-// ks, position 8g + j holds neuron 4g + j for j < 4 and 16 + 4g + (j - 4) for
-// j >= 4.  Lane group g of a forward K = 32 step then loads its 8 values
-// with one 16-byte load at 32ks + 8g, and the lane that produced them (it
-// holds rows 4g .. 4g+3 of row blocks 2ks and 2ks + 1) stores them with one
-// 16-byte store.  Gradient rows D_l stay in neuron order.
-__device__ __forceinline__ int act_neuron(int p) {   // neuron at position p of an activation row
-  return (p & ~31) + 16 * ((p >> 2) & 1) + 4 * ((p >> 3) & 3) + (p & 3);
-}
-__device__ __forceinline__ int act_pos(int n) {      // position of neuron n
-  return (n & ~31) + 8 * ((n >> 2) & 3) + 4 * ((n >> 4) & 1) + (n & 3);
-}
-__device__ __forceinline__ bf16x8 load_fwd_operand(const uint16_t* __restrict__ row, int ks, int g) {
-  return *reinterpret_cast<const bf16x8*>(row + 32 * ks + 8 * g);
-}
-// ReLU of two row blocks' accumulators (rows 4g .. 4g+3 of blocks 2ks, 2ks + 1),
-// rounded to bfloat16, as the 16 bytes at 32ks + 8g of an activation row.
-__device__ __forceinline__ uint4 relu_pair(floatx4 a, floatx4 b) {
-  const uint2 lo = pack4(fmaxf(a[0], 0.0f), fmaxf(a[1], 0.0f), fmaxf(a[2], 0.0f), fmaxf(a[3], 0.0f));
-  const uint2 hi = pack4(fmaxf(b[0], 0.0f), fmaxf(b[1], 0.0f), fmaxf(b[2], 0.0f), fmaxf(b[3], 0.0f));
-  return uint4{lo.x, lo.y, hi.x, hi.y};
-}
-
 // ---------------------------------------------------------- transposed pack
 //
-// packT[((l-1)*FH + mo*KS + ks)*64 + lane][j] = W_l[32ks + 8g + j][16mo + c]:
-// the A operand of (W_l^T D) with the reduction over W_l's output neurons in
-// natural order.
+// packT[((l-1)*FH + mo*KS + ks)*64 + lane][j] = W_l[k(32ks + 8g + j)][16mo + c]:
+// the A operand of (W_l^T D), the reduction over W_l's output neurons in
+// natural order for the layer-wise kernels, in operand order for the fused
+// step (nb_bf16_pack_t_elem).
 __global__ void k_pack_bf16_t(const float* __restrict__ theta, int in_dim, int W, int NH, uint16_t* __restrict__ pack,
-                              int64_t total) {
+                              int64_t total, bool op) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  pack[idx] = nb_bf16_pack_t_elem(theta, in_dim, W, NH, idx);
+  pack[idx] = nb_bf16_pack_t_elem(theta, in_dim, W, NH, idx, op);
 }
 
 // ------------------------------------------------------------ first layer
@@ -648,18 +579,6 @@ __global__ __launch_bounds__(kFG) void k_tr_first_grad(const uint16_t* __restric
   }
 }
 
-// Raise a kernel's dynamic-LDS limit once per device.
-template <class K>
-nb_status allow_lds(K kernel, size_t bytes) {
-  static bool done[64] = {false};
-  int dev = 0;
-  NB_HIP(hipGetDevice(&dev));
-  if (dev < 0 || dev >= 64 || done[dev]) return NB_OK;
-  NB_HIP(hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-  done[dev] = true;
-  return NB_OK;
-}
-
 // One training pass over `members` same-width bounds (gridDim.y).
 struct TrainJob {
   int in_dim = 0, NH = 0, members = 1;
@@ -799,13 +718,39 @@ nb_status bf16_pack_t(const nb_bound* b, hipStream_t s) {
   const int64_t total = b->pack16t_elems;
   if (total == 0) return NB_OK;
   k_pack_bf16_t<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(b->theta, b->in_dim, b->width, b->n_hidden,
-                                                                b->pack16t, total);
+                                                                b->pack16t, total, bf16_uses_fused(b));
   NB_LAUNCHED();
   return NB_OK;
 }
 
+bool bf16_uses_fused(const nb_bound* b) {
+  return b->precision == NB_BF16 && b->train_kernel == NB_TRAIN_AUTO &&
+         bf16_fused_supported(b->in_dim, b->n_hidden, b->width);
+}
+
 nb_status bf16_train_partials(const nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha,
                               float beta, float tau, const BF16TrainPlan& plan, hipStream_t s) {
+  if (bf16_uses_fused(b)) {
+    FusedJob F;
+    F.in_dim = b->in_dim;
+    F.NH = b->n_hidden;
+    F.W = b->width;
+    F.n = n;
+    F.plan = plan;
+    F.q = q;
+    F.y = y;
+    F.theta = b->theta;
+    F.pack = reinterpret_cast<const bf16x8*>(b->pack16);
+    F.packT = reinterpret_cast<const bf16x8*>(b->pack16t);
+    F.partial = b->partial;
+    F.aux = b->aux;
+    F.alpha = alpha;
+    F.beta = beta;
+    F.inv_n = (float)(1.0 / (double)n);
+    F.tau = tau;
+    F.T = TrObjs{nullptr, nullptr, nullptr, nullptr, 0, 0, 0, b->n_params, nullptr};
+    return bf16_fused_train(F, s);
+  }
   TrainJob J;
   J.in_dim = b->in_dim;
   J.NH = b->n_hidden;
@@ -835,6 +780,28 @@ nb_status bf16_group_train_class(const nb_group* gr, int width, const int* d_mem
                                  const float* alpha_obj, float beta,
                                  float tau, const BF16TrainPlan& plan, uint16_t* act, uint16_t* grad,
                                  hipStream_t s) {
+  if (bf16_fused_supported(gr->in_dim, gr->n_hidden, width)) {
+    FusedJob F;
+    F.in_dim = gr->in_dim;
+    F.NH = gr->n_hidden;
+    F.W = width;
+    F.members = n_members;
+    F.n = per_obj;
+    F.plan = plan;
+    F.q = q;
+    F.y = y;
+    F.theta = gr->theta;
+    F.pack = reinterpret_cast<const bf16x8*>(gr->pack16);
+    F.packT = reinterpret_cast<const bf16x8*>(gr->pack16t);
+    F.partial = gr->partial;
+    F.aux = gr->aux;
+    F.alpha = alpha;
+    F.beta = beta;
+    F.inv_n = (float)(1.0 / (double)per_obj);
+    F.tau = tau;
+    F.T = TrObjs{d_members, gr->d_poff, gr->d_pkoff, gr->d_ptoff, per_obj, 0, 0, 0, alpha_obj};
+    return bf16_fused_train(F, s);
+  }
   TrainJob J;
   J.in_dim = gr->in_dim;
   J.NH = gr->n_hidden;

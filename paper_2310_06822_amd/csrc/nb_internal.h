@@ -101,6 +101,7 @@ struct nb_bound {
   int64_t pack16t_elems = 0;
   uint16_t* tr_act = nullptr;      // activation slots x [padded batch][width]
   int recompute = 0;               // activation checkpoint interval (0: keep every activation)
+  int train_kernel = 0;            // NB_TRAIN_AUTO (fused where it exists) or NB_TRAIN_LAYERWISE
   int activation = 0;              // NB_ACT_RELU or NB_ACT_SINE
   int tr_slots = 0;                // activation slots tr_act holds
   uint16_t* tr_grad = nullptr;     // 2 x [padded batch][width]
@@ -217,6 +218,11 @@ struct BF16TrainPlan {
 // queries (every chunk a workgroup writing one partial gradient).
 BF16TrainPlan bf16_train_plan(int64_t n, int max_wg = 256);
 bool bf16_train_supported(int in_dim, int n_hidden, int width);
+// mlp_bf16_fused.hip: shapes the fused training step covers
+bool bf16_fused_supported(int in_dim, int n_hidden, int width);
+// Whether a bfloat16 bound trains with the fused step (its transposed pack
+// is then in operand order).
+bool bf16_uses_fused(const nb_bound* b);
 int64_t bf16_packt_elems(int n_hidden, int width);
 // Activation buffers of one training pass (n_hidden - 1 without recomputation).
 int bf16_act_slots(int n_hidden, int every);

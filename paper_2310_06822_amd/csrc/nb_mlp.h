@@ -215,17 +215,36 @@ __device__ __forceinline__ void nb_first_operands(const float (&xr)[NB][8], int 
   }
 }
 
+// Neuron at position p of a K = 32 operand in "operand order": within each
+// 32-neuron block, position 8g + j holds neuron 4g + j for j < 4 and
+// 16 + 4g + (j - 4) for j >= 4 -- the order in which a lane of group g holds
+// the values of row blocks 2ks and 2ks + 1 after a layer's products.
+__host__ __device__ inline int nb_op_neuron(int p) {
+  return (p & ~31) + 16 * ((p >> 2) & 1) + 4 * ((p >> 3) & 3) + (p & 3);
+}
+
 // Element e of the transposed (backward) pack of the hidden layers:
-// packT[((l-1)*FH + mo*KS + ks)*64 + lane][j] = W_l[32ks + 8g + j][16mo + c]
-// (the A operand of W_l^T D with the reduction over W_l's outputs in order).
-__host__ __device__ inline uint16_t nb_bf16_pack_t_elem(const float* th, int in_dim, int W, int NH, int64_t e) {
+// packT[((l-1)*FH + mo*KS + ks)*64 + lane][j] = W_l[k(32ks + 8g + j)][16mo + c]
+// (the A operand of W_l^T D, the reduction running over W_l's outputs), with
+// k(p) = p when D is read in neuron order (the layer-wise kernels) and
+// k(p) = nb_op_neuron(p) when D comes straight from a layer's accumulators
+// (the fused training kernel).
+__host__ __device__ inline uint16_t nb_bf16_pack_t_elem(const float* th, int in_dim, int W, int NH, int64_t e,
+                                                        bool op) {
   (void)NH;
   const int j = (int)(e & 7), lane = (int)((e >> 3) & 63), f = (int)(e >> 9);
   const int c = lane & 15, g = lane >> 4;
   const int RB = W / 16, KS = W / 32, FH = RB * KS;
   const int l = 1 + f / FH, rem = f % FH, mo = rem / KS, ks = rem % KS;
   const float* Wl = th + nb_w_off(l, in_dim, W);
-  return nb_bf16_bits(Wl[(int64_t)(32 * ks + 8 * g + j) * W + 16 * mo + c]);
+  const int p = 32 * ks + 8 * g + j;
+  return nb_bf16_bits(Wl[(int64_t)(op ? nb_op_neuron(p) : p) * W + 16 * mo + c]);
+}
+
+// Shapes the fused bfloat16 training step covers (their transposed packs are
+// in operand order).
+__host__ __device__ inline bool nb_bf16_fused_shape(int in_dim, int n_hidden, int width) {
+  return in_dim >= 1 && in_dim <= 8 && n_hidden >= 2 && n_hidden <= 4 && (width == 32 || width == 64 || width == 128);
 }
 
 // Number of 16-byte fragment slices of the forward pack (both first-layer

@@ -613,15 +613,59 @@ def test_train_steps_bf16_rays(c2_grid):
     assert _rel_frob(d_gpu, th - theta0) <= 5e-2
 
 
+FUSED_SHAPES = [(6, 128, 4), (6, 128, 3), (3, 128, 2), (4, 64, 3), (6, 64, 4), (8, 64, 2), (6, 32, 2),
+                (2, 32, 4), (5, 32, 3)]
+
+
+@pytest.mark.parametrize("in_dim,width,nh", FUSED_SHAPES)
+@pytest.mark.parametrize("n", [7, 4099, 70001])
+def test_bf16_fused_vs_layerwise(in_dim, width, nh, n):
+    """The fused training kernel and the layer-wise kernels compute the same
+    loss, counts and gradient up to float32 summation order (single tile,
+    several tiles per chunk with a ragged last one)."""
+    q = synth.points(131, n, in_dim)
+    y = (synth.points(132, n, 1)[:, 0] > 0.3).astype(np.uint8)
+    theta = synth.init_params(133 + width + nh, in_dim, [width] * nh)
+    out = {}
+    for kern in (nb.TRAIN_AUTO, nb.TRAIN_LAYERWISE):
+        b = nb.Bound(in_dim, nh, width, nb.BF16)
+        nb.nb_bound_set_train_kernel(b.handle, kern)
+        b.set_params(theta)
+        g = torch.empty(b.n_params, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        cnt = torch.empty(4, dtype=torch.int64, device="cuda")
+        nb.nb_bound_loss_grad(b.handle, cuda(q), cuda(y), 7.0, 1.0, g, loss, cnt)
+        out[kern] = (host(g).astype(np.float64), float(host(loss)[0]), host(cnt))
+    gf, lf, cf = out[nb.TRAIN_AUTO]
+    gl, ll, cl = out[nb.TRAIN_LAYERWISE]
+    assert np.array_equal(cf, cl)
+    assert abs(lf - ll) <= 1e-5 * abs(ll)
+    widths = [width] * nh
+    for (Wf, bf), (Wl, bl) in zip(mlp.unpack(gf, in_dim, widths), mlp.unpack(gl, in_dim, widths)):
+        assert _rel_frob(Wf, Wl) <= 2e-3 and _rel_frob(bf, bl) <= 2e-3
+
+
+@pytest.mark.parametrize("in_dim,width,nh", [(6, 128, 4), (4, 64, 3), (6, 32, 2)])
+def test_loss_grad_bf16_fused_multi_tile(in_dim, width, nh):
+    """The fused kernel against the oracle on a batch whose chunks hold
+    several tiles of queries (70001: chunks of 320, the last tile half full)."""
+    n = 70001
+    q = synth.points(134, n, in_dim)
+    y = (synth.points(135, n, 1)[:, 0] > 0.2).astype(np.uint8)
+    _bf16_grad_check(in_dim, width, nh, q, y, 9.0, 1.5)
+
+
 @pytest.mark.parametrize("in_dim,width,nh", [(4, 256, 6), (6, 128, 4), (3, 256, 8), (6, 64, 5), (6, 32, 3)])
 def test_bf16_recompute_bit_identical(in_dim, width, nh):
     """Checkpointed activation recomputation gives the same gradient bits as
-    keeping every activation, for several checkpoint intervals."""
+    keeping every activation, for several checkpoint intervals (layer-wise
+    kernels: the fused one keeps no activations in memory)."""
     n = 3001
     q = synth.points(111, n, in_dim)
     y = (synth.points(112, n, 1)[:, 0] > 0.1).astype(np.uint8)
     theta = synth.init_params(113 + nh, in_dim, [width] * nh)
     b = nb.Bound(in_dim, nh, width, nb.BF16)
+    nb.nb_bound_set_train_kernel(b.handle, nb.TRAIN_LAYERWISE)
     b.set_params(theta)
     grads = {}
     for every in (0, 2, 3, nh):
@@ -642,6 +686,7 @@ def test_bf16_recompute_training_step(c2_grid):
     out = []
     for every in (0, 2):
         b = nb.Bound(6, 4, 128, nb.BF16)
+        nb.nb_bound_set_train_kernel(b.handle, nb.TRAIN_LAYERWISE)
         nb.nb_bound_set_recompute(b.handle, every)
         b.set_params(theta0)
         for t in range(3):
