@@ -46,8 +46,12 @@ namespace {
 template <int W, int NH>
 struct Fz {
   static constexpr int RB = W / 16, KS = W / 32, FH = RB * KS;
-  static constexpr int NB = 2, WAVES = 4, THREADS = 64 * WAVES;
+  // width 128: eight waves of one block of 16 queries (two waves per SIMD,
+  // 256 registers each); narrower: four waves of two blocks, two or more
+  // workgroups per CU.  A tile is 128 queries either way.
+  static constexpr int NB = W >= 128 ? 1 : 2, WAVES = W >= 128 ? 8 : 4, THREADS = 64 * WAVES;
   static constexpr int Q = 16 * NB * WAVES;   // queries per tile
+  static constexpr int GW = (RB * 4 + 15) / 16;   // output-weight gradient values per lane
   static constexpr int KQ = Q / 32;           // K = 32 steps over a tile's queries
   static constexpr int QP = Q + 8;            // LDS row stride (bfloat16) of the transposed tiles
   static constexpr int TILES = RB * RB, TPW = TILES / WAVES;   // 16 x 16 weight-gradient tiles per wave
@@ -65,6 +69,7 @@ struct Fz {
   // the end-of-chunk reduction reuses the transposed tiles' LDS
   static_assert(((size_t)(W + 8) + WAVES * 8 + (size_t)W * 32) * 4 <= LDS - OFF_DT, "reduction scratch");
   static_assert(LDS <= 160 * 1024, "fused training exceeds the CU's LDS");
+  static_assert(THREADS == (W >= 128 ? 512 : 256), "launch bounds");
 };
 
 // Eight float32 values rounded to bfloat16 (nearest even), as an operand.
@@ -116,14 +121,24 @@ __device__ __forceinline__ gptr<T> opaque(T* p) {
   return g;
 }
 
+// Sum over the 16 lanes of a row (rotations by 8, 4, 2, 1): every lane ends
+// with the total, each in a fixed order of its own.
+__device__ __forceinline__ float row_sum16(float v) {
+  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x128, 0xF, 0xF, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x124, 0xF, 0xF, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x122, 0xF, 0xF, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x121, 0xF, 0xF, false));
+  return v;
+}
+
 template <int W, int NH>
-__global__ __launch_bounds__(256, (W >= 128 ? 1 : 2)) void k_tr_fused(
+__global__ __launch_bounds__((W >= 128 ? 512 : 256), (W >= 128 ? 1 : 2)) void k_tr_fused(
     const float* __restrict__ q, const uint8_t* __restrict__ y, int64_t n, int64_t CH, int in_dim,
     const bf16x8* __restrict__ pack, const bf16x8* __restrict__ packT, const float* __restrict__ theta, float alpha,
     float beta, float inv_n, float tau, float* __restrict__ partial, float* __restrict__ aux, TrObjs TO) {
   using F = Fz<W, NH>;
   constexpr int RB = F::RB, KS = F::KS, FH = F::FH, NB = F::NB, WAVES = F::WAVES, Q = F::Q, QP = F::QP;
-  constexpr int TPW = F::TPW, RW = F::RW, R0 = F::R0, KQ = F::KQ;
+  constexpr int TPW = F::TPW, RW = F::RW, R0 = F::R0, KQ = F::KQ, GW = F::GW;
   constexpr bool DW_REGS = F::DW_REGS;
   const TrObj ob = tr_obj(TO);
   const int64_t P = ob.P;
@@ -190,9 +205,11 @@ __global__ __launch_bounds__(256, (W >= 128 ? 1 : 2)) void k_tr_fused(
 
   const floatx4 zero4 = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
   const bf16x8 ones = __builtin_bit_cast(bf16x8, nb_uint4{0x3F803F80u, 0x3F803F80u, 0x3F803F80u, 0x3F803F80u});
-  float gwo[RB * 4];
+  // output-weight gradient: lane c keeps the values i = c + 16 k (i = 4 mo + r:
+  // neuron 16 mo + 4 g + r) of every tile's row sums
+  float gwo[GW];
 #pragma unroll
-  for (int i = 0; i < RB * 4; ++i) gwo[i] = 0.0f;
+  for (int k = 0; k < GW; ++k) gwo[k] = 0.0f;
   float gbo = 0.0f, lsum = 0.0f;
   unsigned cnt[4] = {0u, 0u, 0u, 0u};
   floatx4 dbh[NH - 1][RW];                        // hidden-layer bias gradients of the wave's row blocks
@@ -287,6 +304,9 @@ __global__ __launch_bounds__(256, (W >= 128 ? 1 : 2)) void k_tr_fused(
           }
       } else {
         // output layer, Eq. 1 and dL/dz; D_{NH-1} = dz w_out [a > 0]
+        float gt[RB * 4];   // this tile's dz relu(a) per lane, summed over the wave's blocks
+#pragma unroll
+        for (int i = 0; i < RB * 4; ++i) gt[i] = 0.0f;
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
           float p = 0.0f;
@@ -323,11 +343,16 @@ __global__ __launch_bounds__(256, (W >= 128 ? 1 : 2)) void k_tr_fused(
             for (int j = 0; j < 8; ++j) {
               const int mo = 2 * ks + j / 4, r = j % 4;
               const float a = fmaxf(acc[nb][mo][r], 0.0f);
-              gwo[mo * 4 + r] = fmaf(dz, a, gwo[mo * 4 + r]);
+              gt[mo * 4 + r] = fmaf(dz, a, gt[mo * 4 + r]);
               d[j] = acc[nb][mo][r] > 0.0f ? dz * swo[16 * mo + 4 * grp + r] : 0.0f;
             }
             dop[nb][ks] = to_bf16x8(d);
           }
+        }
+#pragma unroll
+        for (int i = 0; i < RB * 4; ++i) {
+          const float t = row_sum16(gt[i]);
+          if ((i & 15) == c) gwo[i >> 4] += t;
         }
       }
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -479,10 +504,6 @@ __global__ __launch_bounds__(256, (W >= 128 ? 1 : 2)) void k_tr_fused(
   float* saux = red + W + 8;                                      // [WAVES][8] loss and counts
   float* red0 = saux + WAVES * 8;                                 // [W][32] first-layer tiles
 #pragma unroll
-  for (int i = 0; i < RB * 4; ++i)
-#pragma unroll
-    for (int m = 1; m < 16; m <<= 1) gwo[i] += __shfl_xor(gwo[i], m);
-#pragma unroll
   for (int m = 1; m < 64; m <<= 1) {
     gbo += __shfl_xor(gbo, m);
     lsum += __shfl_xor(lsum, m);
@@ -498,14 +519,13 @@ __global__ __launch_bounds__(256, (W >= 128 ? 1 : 2)) void k_tr_fused(
   }
   for (int w = 0; w < WAVES; ++w) {
     if (wave == w) {
-      if (c == 0) {
 #pragma unroll
-        for (int mo = 0; mo < RB; ++mo)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i = 16 * mo + 4 * grp + r;
-            red[i] = w == 0 ? gwo[mo * 4 + r] : red[i] + gwo[mo * 4 + r];
-          }
+      for (int k = 0; k < GW; ++k) {
+        const int i = c + 16 * k;
+        if (i < RB * 4) {
+          const int nrn = 16 * (i >> 2) + 4 * grp + (i & 3);
+          red[nrn] = w == 0 ? gwo[k] : red[nrn] + gwo[k];
+        }
       }
       if (lane == 0) {
         red[W] = w == 0 ? gbo : red[W] + gbo;
