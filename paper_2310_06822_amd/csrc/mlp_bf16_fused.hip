@@ -58,16 +58,20 @@ struct Fz {
   static constexpr bool DW_REGS = TPW * 4 * (NH - 1) <= 64;
   static constexpr int RW = TPW >= RB ? TPW / RB : 1;          // row blocks per wave (whole rows if TPW >= RB)
   static constexpr int R0 = (RB + WAVES - 1) / WAVES;          // first-layer gradient row blocks per wave
-  static constexpr int AT_ROWS = W > 32 ? W : 32;              // the input pieces need up to 25 rows
+  static constexpr int XROWS = 32;   // input-piece rows: 3 in_dim + 1 <= 25, read as two 16-row B tiles
   static constexpr int NBIAS = NH * W + W + 1;
+  // LDS: two streamed-layer buffers | biases, output weights | D^T | A^T |
+  // first-layer fragments (both steps) | input pieces and ones (x^T)
   static constexpr size_t OFF_B = (size_t)2 * FH * 64 * 16;
   static constexpr size_t OFF_DT = (OFF_B + (size_t)NBIAS * 4 + 15) / 16 * 16;
   static constexpr size_t OFF_AT = OFF_DT + (size_t)W * QP * 2;
-  static constexpr size_t LDS = OFF_AT + (size_t)AT_ROWS * QP * 2;
+  static constexpr size_t OFF_F1 = OFF_AT + (size_t)W * QP * 2;
+  static constexpr size_t OFF_X = OFF_F1 + (size_t)2 * RB * 64 * 16;
+  static constexpr size_t LDS = OFF_X + (size_t)XROWS * QP * 2;
   static_assert(TILES % WAVES == 0, "weight-gradient tiles must split evenly over the waves");
   static_assert(TPW < RB ? TPW == 1 : TPW % RB == 0, "a wave owns one tile or whole row blocks");
   // the end-of-chunk reduction reuses the transposed tiles' LDS
-  static_assert(((size_t)(W + 8) + WAVES * 8 + (size_t)W * 32) * 4 <= LDS - OFF_DT, "reduction scratch");
+  static_assert(((size_t)(W + 8) + WAVES * 8 + (size_t)W * 32) * 4 <= OFF_F1 - OFF_DT, "reduction scratch");
   static_assert(LDS <= 160 * 1024, "fused training exceeds the CU's LDS");
   static_assert(THREADS == (W >= 128 ? 512 : 256), "launch bounds");
 };
@@ -91,19 +95,95 @@ __device__ __forceinline__ uint16_t elem_bits(bf16x8 v, int j) {
 // Writes the operands op[nb][ks] of the wave's query blocks into a
 // [neuron][query] tile: element j of operand ks is neuron
 // nb_op_neuron(32 ks + 8 g + j), the lane's query column c of block nb.
+//
+// Dword m of an operand holds elements 2m and 2m + 1 (two neurons) of the
+// lane's query; the lanes of queries c and c ^ 1 swap halves (one DPP move
+// and one byte permute) so that the even lane writes neuron 2m and the odd
+// lane neuron 2m + 1, each for both queries, as one 32-bit store.
 template <int NB, int KS, int QP>
 __device__ __forceinline__ void store_transposed(uint16_t* __restrict__ dst, const bf16x8 (&op)[NB][KS], int col0,
                                                  int grp, int c) {
-  // one per-lane base (opaque, so that every store is base + immediate)
-  int lb = (4 * grp * QP + col0 + c) * 2;
+  const int odd = c & 1;
+  // one per-lane base (opaque, so that every store is base + immediate):
+  // row 4 g (+ 1 for the odd lane, its neuron 2m + 1), columns c & ~1, c | 1
+  int lb = ((4 * grp + odd) * QP + col0 + (c & ~1)) * 2;
   asm volatile("" : "+v"(lb));
-  uint16_t* b = reinterpret_cast<uint16_t*>(reinterpret_cast<unsigned char*>(dst) + lb);
+  unsigned char* b = reinterpret_cast<unsigned char*>(dst) + lb;
+  // v_perm_b32 selectors: even lane (own low half, partner's low half),
+  // odd lane (partner's high half, own high half)
+  const unsigned sel = odd ? 0x03020706u : 0x05040100u;
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
+    for (int ks = 0; ks < KS; ++ks) {
+      const nb_uint4 u = __builtin_bit_cast(nb_uint4, op[nb][ks]);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) b[(32 * ks + 16 * (j >> 2) + (j & 3)) * QP + nb * 16] = elem_bits(op[nb][ks], j);
+      for (int m = 0; m < 4; ++m) {
+        const unsigned pu = (unsigned)__builtin_amdgcn_mov_dpp((int)u[m], 0xB1, 0xF, 0xF, false);   // lane c ^ 1
+        const unsigned w = __builtin_amdgcn_perm(pu, u[m], sel);
+        // elements 2m, 2m + 1: neurons 32 ks + 16 (m / 2) + 4 g + 2 (m % 2) (+ 1)
+        *reinterpret_cast<unsigned*>(b + ((32 * ks + 16 * (m >> 1) + 2 * (m & 1)) * QP + nb * 16) * 2) = w;
+      }
+    }
+}
+
+// Reduce-scatter over the 16 lanes of a row: lane c ends with the row sums
+// of the values i = c + 16 k (k < V / 16), each in a fixed order.  Step t
+// pairs lane c with c ^ (1 << bt) for bt = 3, 0, 1, 2 and keeps the half of
+// its remaining values whose bit bt of i matches the lane's, adding the
+// partner's copy of that half.  The position of value i among the remaining
+// ones is i with the bits split so far taken out (rs_compress).
+__host__ __device__ constexpr int rs_compress(int i, int mask) {
+  int r = 0, o = 0;
+  for (int b = 0; b < 8; ++b)
+    if (!((mask >> b) & 1)) r |= ((i >> b) & 1) << o++;
+  return r;
+}
+__host__ __device__ constexpr int rs_expand(int j, int mask) {   // j with zero bits put in at the mask's positions
+  int r = 0, o = 0;
+  for (int b = 0; b < 8; ++b) {
+    if ((mask >> b) & 1) continue;
+    r |= ((j >> o++) & 1) << b;
+  }
+  return r;
+}
+
+template <int V>
+__device__ __forceinline__ void row_reduce_scatter(const float (&x)[V], int c, float (&out)[V / 16]) {
+  static_assert(V % 16 == 0 && V <= 64, "values per lane: a multiple of 16");
+  float a[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) a[i] = x[i];
+  constexpr int order[4] = {3, 0, 1, 2};
+  int mask = 0;   // bits split so far
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int bt = order[st];
+    const bool hi = (c >> bt) & 1;
+    const int nmask = mask | (1 << bt);
+    float nx[V / 2];
+#pragma unroll
+    for (int j = 0; j < (V >> (st + 1)); ++j) {
+      const int i0 = rs_expand(j, nmask), i1 = i0 | (1 << bt);
+      const float v0 = a[rs_compress(i0, mask)], v1 = a[rs_compress(i1, mask)];
+      const float keep = hi ? v1 : v0, send = hi ? v0 : v1;
+      float got;
+      if (bt == 3)
+        got = __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, send), 0x128, 0xF, 0xF, false));
+      else if (bt == 0)
+        got = __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, send), 0xB1, 0xF, 0xF, false));
+      else if (bt == 1)
+        got = __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, send), 0x4E, 0xF, 0xF, false));
+      else   // lane c ^ 4 (swizzle, bit mode: and 0x1f, xor 4)
+        got = __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, send), 0x101F));
+      nx[j] = keep + got;
+    }
+#pragma unroll
+    for (int j = 0; j < (V >> (st + 1)); ++j) a[j] = nx[j];
+    mask = nmask;
+  }
+#pragma unroll
+  for (int k = 0; k < V / 16; ++k) out[k] = a[k];
 }
 
 __device__ __forceinline__ bf16x8 lds16(const uint16_t* p) { return *reinterpret_cast<const bf16x8*>(p); }
@@ -119,16 +199,6 @@ __device__ __forceinline__ gptr<T> opaque(T* p) {
   gptr<T> g = (gptr<T>)p;
   asm volatile("" : "+s"(g));
   return g;
-}
-
-// Sum over the 16 lanes of a row (rotations by 8, 4, 2, 1): every lane ends
-// with the total, each in a fixed order of its own.
-__device__ __forceinline__ float row_sum16(float v) {
-  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x128, 0xF, 0xF, false));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x124, 0xF, 0xF, false));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x122, 0xF, 0xF, false));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x121, 0xF, 0xF, false));
-  return v;
 }
 
 template <int W, int NH>
@@ -157,12 +227,14 @@ __global__ __launch_bounds__((W >= 128 ? 512 : 256), (W >= 128 ? 1 : 2)) void k_
   // access: every LDS access is then a region base register plus an
   // immediate below 64 KB (the instruction's offset field), instead of one
   // address register per distinct offset
-  int obias = (int)F::OFF_B, odt = (int)F::OFF_DT, oat = (int)F::OFF_AT;
-  asm volatile("" : "+s"(obias), "+s"(odt), "+s"(oat));
+  int obias = (int)F::OFF_B, odt = (int)F::OFF_DT, oat = (int)F::OFF_AT, of1 = (int)F::OFF_F1, ox = (int)F::OFF_X;
+  asm volatile("" : "+s"(obias), "+s"(odt), "+s"(oat), "+s"(of1), "+s"(ox));
   bf16x8* sW = reinterpret_cast<bf16x8*>(smem_raw);
   float* sb = reinterpret_cast<float*>(smem_raw + obias);
   uint16_t* sDt = reinterpret_cast<uint16_t*>(smem_raw + odt);
   uint16_t* sAt = reinterpret_cast<uint16_t*>(smem_raw + oat);
+  bf16x8* sF1 = reinterpret_cast<bf16x8*>(smem_raw + of1);
+  uint16_t* sX = reinterpret_cast<uint16_t*>(smem_raw + ox);
   const float* swo = sb + NH * W;
 
   const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4;
@@ -200,6 +272,12 @@ __global__ __launch_bounds__((W >= 128 ? 512 : 256), (W >= 128 ? 1 : 2)) void k_
     for (int i = threadIdx.x; i < FH * 64; i += F::THREADS) sW[i] = src[i];
     for (int i = threadIdx.x; i < NH * W; i += F::THREADS) sb[i] = theta[nb_b_off(i / W, in_dim, W, NH) + i % W];
     for (int i = threadIdx.x; i < W + 1; i += F::THREADS) sb[NH * W + i] = theta[nb_w_off(NH, in_dim, W) + i];
+    // first layer: step 0, then (in_dim > 4) step 1, which follows the hidden layers in the pack
+    for (int i = threadIdx.x; i < RB * 64; i += F::THREADS) {
+      sF1[i] = pack[i];
+      if (wide) sF1[RB * 64 + i] = pack[(RB + (NH - 1) * FH) * 64 + i];
+    }
+    for (int i = threadIdx.x; i < Q; i += F::THREADS) sX[3 * in_dim * QP + i] = 0x3F80;   // 1.0: db_0
   }
   __syncthreads();
 
@@ -227,36 +305,54 @@ __global__ __launch_bounds__((W >= 128 ? 512 : 256), (W >= 128 ? 1 : 2)) void k_
   for (int i = 0; i < R0; ++i) dw0[i][0] = dw0[i][1] = zero4;
 
   const int col0 = wave * NB * 16;   // the wave's first query column in a tile
+  // a tile's inputs and labels, loaded one tile ahead (during the previous
+  // tile's backward pass) as they are: rows past the chunk's queries read
+  // the chunk's last query (every load in bounds, none under a branch) and
+  // are zeroed where the tile uses them, so that no instruction waits for
+  // the loads before then
+  float xraw[NB][8];
+  uint8_t yraw[NB];
+  auto load_inputs = [&](int tile) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int64_t qi = base + (int64_t)tile * Q + col0 + nb * 16 + c;
+      const int64_t qr = qi < vend ? qi : vend - 1;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) xraw[nb][j] = q[qr * in_dim + (j < in_dim ? j : in_dim - 1)];
+      yraw[nb] = y[qr];
+    }
+  };
+  load_inputs(0);
   for (int it = 0; it < iters; ++it) {
     const int64_t q0 = base + (int64_t)it * Q + col0;
     const bool last_tile = it + 1 == iters;
-    const gptr<const bf16x8> pk = opaque(pack);
+    float xr[NB][8];
+    int ylab[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const bool valid = q0 + nb * 16 + c < vend;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) xr[nb][j] = (valid && j < in_dim) ? xraw[nb][j] : 0.0f;
+      ylab[nb] = valid ? (int)yraw[nb] : 0;
+    }
     bf16x8 act[NH - 1][NB][KS];   // A_0 .. A_{NH-2}
     bf16x8 dop[NB][KS];           // D_l as the B operand of the next products
     floatx4 acc[NB][RB];
     // ---- first layer
     {
-      float xr[NB][8];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int64_t qi = q0 + nb * 16 + c;
-        const bool valid = qi < vend;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) xr[nb][j] = (valid && j < in_dim) ? q[qi * in_dim + j] : 0.0f;
-      }
       bf16x8 xb[NB], xb1[NB];
       nb_first_operands<NB>(xr, grp, wide, xb, xb1);
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo) {
         const floatx4 bi = *reinterpret_cast<const floatx4*>(sb + 16 * mo + 4 * grp);
-        const bf16x8 a = pk[mo * 64 + lane];
+        const bf16x8 a = sF1[mo * 64 + lane];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = nb_mfma_bf16(a, xb[nb], bi);
       }
       if (wide) {
 #pragma unroll
         for (int mo = 0; mo < RB; ++mo) {
-          const bf16x8 a = pk[(RB + (NH - 1) * FH + mo) * 64 + lane];
+          const bf16x8 a = sF1[(RB + mo) * 64 + lane];
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = nb_mfma_bf16(a, xb1[nb], acc[nb][mo]);
         }
@@ -307,19 +403,24 @@ __global__ __launch_bounds__((W >= 128 ? 512 : 256), (W >= 128 ? 1 : 2)) void k_
         float gt[RB * 4];   // this tile's dz relu(a) per lane, summed over the wave's blocks
 #pragma unroll
         for (int i = 0; i < RB * 4; ++i) gt[i] = 0.0f;
+        // the lane's output weights, read once (a read under the ReLU select
+        // below would become a branch around each LDS load)
+        floatx4 wo4[RB];
+#pragma unroll
+        for (int mo = 0; mo < RB; ++mo) wo4[mo] = *reinterpret_cast<const floatx4*>(swo + 16 * mo + 4 * grp);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
           float p = 0.0f;
 #pragma unroll
           for (int mo = 0; mo < RB; ++mo)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) p = fmaf(swo[16 * mo + 4 * grp + r], nb_relu(acc[nb][mo][r]), p);
+            for (int r = 0; r < 4; ++r) p = fmaf(wo4[mo][r], nb_relu(acc[nb][mo][r]), p);
           p += __shfl_xor(p, 16);
           p += __shfl_xor(p, 32);
           const float z = p + swo[W];
           const int64_t qi = q0 + nb * 16 + c;
           const bool valid = qi < vend;
-          const bool yv = valid && y[qi] != 0;
+          const bool yv = ylab[nb] != 0;
           const float e = expf(-fabsf(z));
           const float inv1pe = 1.0f / (1.0f + e);
           const float sig = z >= 0.0f ? inv1pe : e * inv1pe;
@@ -344,19 +445,47 @@ __global__ __launch_bounds__((W >= 128 ? 512 : 256), (W >= 128 ? 1 : 2)) void k_
               const int mo = 2 * ks + j / 4, r = j % 4;
               const float a = fmaxf(acc[nb][mo][r], 0.0f);
               gt[mo * 4 + r] = fmaf(dz, a, gt[mo * 4 + r]);
-              d[j] = acc[nb][mo][r] > 0.0f ? dz * swo[16 * mo + 4 * grp + r] : 0.0f;
+              const float dw = dz * wo4[mo][r];
+              d[j] = acc[nb][mo][r] > 0.0f ? dw : 0.0f;
             }
             dop[nb][ks] = to_bf16x8(d);
           }
         }
+        {
+          constexpr int V = RB * 4 < 16 ? 16 : RB * 4;
+          float gv[V], sums[V / 16];
 #pragma unroll
-        for (int i = 0; i < RB * 4; ++i) {
-          const float t = row_sum16(gt[i]);
-          if ((i & 15) == c) gwo[i >> 4] += t;
+          for (int i = 0; i < V; ++i) gv[i] = i < RB * 4 ? gt[i] : 0.0f;
+          row_reduce_scatter<V>(gv, c, sums);
+#pragma unroll
+          for (int k = 0; k < GW; ++k) gwo[k] += sums[k];
         }
       }
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
+      if (l == 1) {
+        // x^T for dW_0: the three pieces of every input (rows 3 f .. 3 f + 2);
+        // the previous tile's readers of these rows have all passed the
+        // barrier above
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int col = col0 + nb * 16 + c;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int f = grp + 4 * h;
+            if (f < in_dim) {
+              const float x = xr[nb][f];
+              const float x1 = __uint_as_float(__float_as_uint(x) & 0xFFFF0000u);
+              const float rr = x - x1;
+              const float x2 = __uint_as_float(__float_as_uint(rr) & 0xFFFF0000u);
+              const float x3 = rr - x2;
+              sX[(3 * f) * QP + col] = nb_hi16(x1);
+              sX[(3 * f + 1) * QP + col] = nb_hi16(x2);
+              sX[(3 * f + 2) * QP + col] = nb_hi16(x3);
+            }
+          }
+        }
+      }
     }
     // ---- backward stages: layers NH-1 .. 1
 #pragma unroll
@@ -364,7 +493,24 @@ __global__ __launch_bounds__((W >= 128 ? 512 : 256), (W >= 128 ? 1 : 2)) void k_
       const int st = NST - l;
       if (st + 1 < NST) prefetch(st + 1);
       else if (!last_tile) prefetch(0);
+      if (l == NH - 1 && !last_tile) load_inputs(it + 1);   // this tile's inputs and labels are used up
       const bf16x8* fw = sW + (st & 1) * FH * 64 + lane;
+      // partials of this layer's weight-gradient tiles (kept in memory):
+      // loaded here so that the transposes and the data gradient cover
+      // their latency
+      floatx4 dwm[DW_REGS ? 1 : TPW];
+      const gptr<float> R = opaque(out + nb_w_off(l, in_dim, W));
+      if constexpr (!DW_REGS) {
+        if (it == 0) {
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) dwm[t] = zero4;
+        } else {
+#pragma unroll
+          for (int t = 0; t < TPW; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dwm[t][r] = R[(int64_t)(wave * TPW + t) * 256 + lane * 4 + r];
+        }
+      }
       store_transposed<NB, KS, QP>(sDt, dop, col0, grp, c);
       store_transposed<NB, KS, QP>(sAt, act[l - 1], col0, grp, c);
       // D_{l-1} = (W_l^T D_l) [A_{l-1} > 0]
@@ -394,19 +540,8 @@ __global__ __launch_bounds__((W >= 128 ? 512 : 256), (W >= 128 ? 1 : 2)) void k_
       // dW_l += D_l A_{l-1}^T and db_l += D_l 1 over the tile's queries
       {
         floatx4 dw[TPW];
-        const gptr<float> R = opaque(out + nb_w_off(l, in_dim, W));
-        if constexpr (DW_REGS) {
 #pragma unroll
-          for (int t = 0; t < TPW; ++t) dw[t] = dwr[l - 1][t];
-        } else if (it == 0) {
-#pragma unroll
-          for (int t = 0; t < TPW; ++t) dw[t] = zero4;
-        } else {
-#pragma unroll
-          for (int t = 0; t < TPW; ++t)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) dw[t][r] = R[(int64_t)(wave * TPW + t) * 256 + lane * 4 + r];
-        }
+        for (int t = 0; t < TPW; ++t) dw[t] = DW_REGS ? dwr[l - 1][t] : dwm[t];
 #pragma unroll
         for (int s = 0; s < KQ; ++s) {
           if constexpr (TPW >= RB) {
@@ -455,36 +590,12 @@ __global__ __launch_bounds__((W >= 128 ? 512 : 256), (W >= 128 ? 1 : 2)) void k_
     // ---- first layer: dW_0 and db_0 from D_0 and the input pieces
     {
       store_transposed<NB, KS, QP>(sDt, dop, col0, grp, c);
-      // the inputs are read again (an opaque pointer: the first layer's
-      // loads are not kept alive across the tile)
-      const gptr<const float> qx = opaque(q);
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int64_t qi = q0 + nb * 16 + c;
-        const bool valid = qi < vend;
-        const int col = col0 + nb * 16 + c;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int f = grp + 4 * h;
-          if (f < in_dim) {
-            const float x = valid ? qx[qi * in_dim + f] : 0.0f;
-            const float x1 = __uint_as_float(__float_as_uint(x) & 0xFFFF0000u);
-            const float rr = x - x1;
-            const float x2 = __uint_as_float(__float_as_uint(rr) & 0xFFFF0000u);
-            const float x3 = rr - x2;
-            sAt[(3 * f) * QP + col] = nb_hi16(x1);
-            sAt[(3 * f + 1) * QP + col] = nb_hi16(x2);
-            sAt[(3 * f + 2) * QP + col] = nb_hi16(x3);
-          }
-        }
-        if (grp == 0) sAt[(3 * in_dim) * QP + col] = 0x3F80;   // 1.0: db_0
-      }
       __syncthreads();
       const bool two = 3 * in_dim + 1 > 16;
 #pragma unroll
       for (int s = 0; s < KQ; ++s) {
-        const bf16x8 b0 = lds16(sAt + c * QP + 32 * s + 8 * grp);
-        const bf16x8 b1 = lds16(sAt + (16 + c) * QP + 32 * s + 8 * grp);
+        const bf16x8 b0 = lds16(sX + c * QP + 32 * s + 8 * grp);
+        const bf16x8 b1 = lds16(sX + (16 + c) * QP + 32 * s + 8 * grp);
 #pragma unroll
         for (int i = 0; i < R0; ++i) {
           const int no = wave + i * WAVES;
