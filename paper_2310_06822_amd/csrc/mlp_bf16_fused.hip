@@ -43,13 +43,18 @@
 
 namespace {
 
-template <int W, int NH>
+// Waves per workgroup (WV): eight single-block waves or four two-block
+// waves; a tile is 128 queries either way.
+template <int W>
+constexpr int fz_waves() { return W >= 128 ? 8 : 4; }
+
+template <int W, int NH, int WV>
 struct Fz {
   static constexpr int RB = W / 16, KS = W / 32, FH = RB * KS;
   // width 128: eight waves of one block of 16 queries (two waves per SIMD,
   // 256 registers each); narrower: four waves of two blocks, two or more
   // workgroups per CU.  A tile is 128 queries either way.
-  static constexpr int NB = W >= 128 ? 1 : 2, WAVES = W >= 128 ? 8 : 4, THREADS = 64 * WAVES;
+  static constexpr int WAVES = WV, NB = 8 / WV, THREADS = 64 * WAVES;
   static constexpr int Q = 16 * NB * WAVES;   // queries per tile
   static constexpr int GW = (RB * 4 + 15) / 16;   // output-weight gradient values per lane
   static constexpr int KQ = Q / 32;           // K = 32 steps over a tile's queries
@@ -73,7 +78,7 @@ struct Fz {
   // the end-of-chunk reduction reuses the transposed tiles' LDS
   static_assert(((size_t)(W + 8) + WAVES * 8 + (size_t)W * 32) * 4 <= OFF_F1 - OFF_DT, "reduction scratch");
   static_assert(LDS <= 160 * 1024, "fused training exceeds the CU's LDS");
-  static_assert(THREADS == (W >= 128 ? 512 : 256), "launch bounds");
+  static_assert(WV == 4 || WV == 8, "four or eight waves");
 };
 
 // Eight float32 values rounded to bfloat16 (nearest even), as an operand.
@@ -201,12 +206,12 @@ __device__ __forceinline__ gptr<T> opaque(T* p) {
   return g;
 }
 
-template <int W, int NH>
-__global__ __launch_bounds__((W >= 128 ? 512 : 256), (W >= 128 ? 1 : 2)) void k_tr_fused(
+template <int W, int NH, int WV>
+__global__ __launch_bounds__(64 * WV, (WV == 8 || W >= 128 ? 1 : 2)) void k_tr_fused(
     const float* __restrict__ q, const uint8_t* __restrict__ y, int64_t n, int64_t CH, int in_dim,
     const bf16x8* __restrict__ pack, const bf16x8* __restrict__ packT, const float* __restrict__ theta, float alpha,
     float beta, float inv_n, float tau, float* __restrict__ partial, float* __restrict__ aux, TrObjs TO) {
-  using F = Fz<W, NH>;
+  using F = Fz<W, NH, WV>;
   constexpr int RB = F::RB, KS = F::KS, FH = F::FH, NB = F::NB, WAVES = F::WAVES, Q = F::Q, QP = F::QP;
   constexpr int TPW = F::TPW, RW = F::RW, R0 = F::R0, KQ = F::KQ, GW = F::GW;
   constexpr bool DW_REGS = F::DW_REGS;
@@ -691,12 +696,12 @@ __global__ __launch_bounds__((W >= 128 ? 512 : 256), (W >= 128 ? 1 : 2)) void k_
   }
 }
 
-template <int W, int NH>
+template <int W, int NH, int WV = fz_waves<W>()>
 nb_status fused_launch(const FusedJob& J, hipStream_t s) {
-  using F = Fz<W, NH>;
-  NB_TRY(allow_lds(k_tr_fused<W, NH>, F::LDS));
+  using F = Fz<W, NH, WV>;
+  NB_TRY(allow_lds(k_tr_fused<W, NH, WV>, F::LDS));
   const dim3 grid((unsigned)J.plan.n_wg, (unsigned)J.members);
-  k_tr_fused<W, NH><<<grid, F::THREADS, F::LDS, s>>>(J.q, J.y, J.n, J.plan.chunk, J.in_dim, J.pack, J.packT,
+  k_tr_fused<W, NH, WV><<<grid, F::THREADS, F::LDS, s>>>(J.q, J.y, J.n, J.plan.chunk, J.in_dim, J.pack, J.packT,
                                                      J.theta, J.alpha, J.beta, J.inv_n, J.tau, J.partial, J.aux,
                                                      J.T);
   NB_LAUNCHED();
