@@ -550,17 +550,23 @@ __global__ __launch_bounds__(64 * WV, (WV == 8 || W >= 128 ? 1 : 2)) void k_tr_f
 #pragma unroll
         for (int s = 0; s < KQ; ++s) {
           if constexpr (TPW >= RB) {
-            bf16x8 a[RW], b[RB];
+            bf16x8 a[RW];
 #pragma unroll
             for (int i = 0; i < RW; ++i) a[i] = lds16(sDt + (16 * (wave * RW + i) + c) * QP + 32 * s + 8 * grp);
+            // the column blocks' B fragments in groups of four (fewer live registers)
+            constexpr int KG = RB >= 4 ? 4 : RB;
 #pragma unroll
-            for (int k = 0; k < RB; ++k) b[k] = lds16(sAt + (16 * k + c) * QP + 32 * s + 8 * grp);
+            for (int k0 = 0; k0 < RB; k0 += KG) {
+              bf16x8 b[KG];
 #pragma unroll
-            for (int i = 0; i < RW; ++i) {
+              for (int k = 0; k < KG; ++k) b[k] = lds16(sAt + (16 * (k0 + k) + c) * QP + 32 * s + 8 * grp);
 #pragma unroll
-              for (int k = 0; k < RB; ++k) dw[i * RB + k] = nb_mfma_bf16(a[i], b[k], dw[i * RB + k]);
-              dbh[l - 1][i] = nb_mfma_bf16(a[i], ones, dbh[l - 1][i]);
+              for (int i = 0; i < RW; ++i)
+#pragma unroll
+                for (int k = 0; k < KG; ++k) dw[i * RB + k0 + k] = nb_mfma_bf16(a[i], b[k], dw[i * RB + k0 + k]);
             }
+#pragma unroll
+            for (int i = 0; i < RW; ++i) dbh[l - 1][i] = nb_mfma_bf16(a[i], ones, dbh[l - 1][i]);
           } else {
             const int no = wave / RB, ko = wave % RB;
             const bf16x8 a = lds16(sDt + (16 * no + c) * QP + 32 * s + 8 * grp);
