@@ -193,6 +193,39 @@ __device__ __forceinline__ void row_reduce_scatter(const float (&x)[V], int c, f
 
 __device__ __forceinline__ bf16x8 lds16(const uint16_t* p) { return *reinterpret_cast<const bf16x8*>(p); }
 
+// acc[nb][mo] += sum_ks W(mo, ks) op[nb][ks] over one layer's fragments fw
+// (lane offset included): row blocks in groups of up to four with the K
+// steps outermost, so that every group keeps four (x NB) independent
+// accumulation chains in flight, and two fragment slots, so that the next K
+// step's fragments load while the current one's products issue.  `between`
+// runs after each group (work to interleave with the products).
+template <int RB, int KS, int NB, class Between>
+__device__ __forceinline__ void layer_products(const bf16x8* __restrict__ fw, const bf16x8 (&op)[NB][KS],
+                                               floatx4 (&acc)[NB][RB], Between&& between) {
+  constexpr int G = RB < 4 ? RB : 4;
+#pragma unroll
+  for (int m0 = 0; m0 < RB; m0 += G) {
+    bf16x8 fa[G], fb[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) fa[u] = fw[((m0 + u) * KS) * 64];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      bf16x8(&cur)[G] = (ks & 1) ? fb : fa;
+      bf16x8(&nxt)[G] = (ks & 1) ? fa : fb;
+      if (ks + 1 < KS) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) nxt[u] = fw[((m0 + u) * KS + ks + 1) * 64];
+      }
+#pragma unroll
+      for (int u = 0; u < G; ++u)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb][m0 + u] = nb_mfma_bf16(cur[u], op[nb][ks], acc[nb][m0 + u]);
+    }
+    between(m0 / G);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // A wave-uniform global-memory pointer the compiler cannot see through:
 // addresses formed from it are computed where they are used instead of
 // being hoisted out of the tile loop and held in registers.  (Returned in
@@ -383,16 +416,8 @@ __global__ __launch_bounds__(64 * WV, (WV == 8 || W >= 128 ? 1 : 2)) void k_tr_f
         const floatx4 bi = *reinterpret_cast<const floatx4*>(sb + l * W + 16 * mo + 4 * grp);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = bi;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          const bf16x8 f = fw[(mo * KS + ks) * 64];
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = nb_mfma_bf16(f, act[l - 1][nb][ks], acc[nb][mo]);
-        }
-        // keeps the next row block's fragment loads from being hoisted
-        // above this one's products (a register per hoisted fragment)
-        __builtin_amdgcn_sched_barrier(0);
       }
+      layer_products<RB, KS, NB>(fw, act[l - 1], acc, [](int) {});
       if (l < NH - 1) {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
@@ -516,20 +541,25 @@ __global__ __launch_bounds__(64 * WV, (WV == 8 || W >= 128 ? 1 : 2)) void k_tr_f
             for (int r = 0; r < 4; ++r) dwm[t][r] = R[(int64_t)(wave * TPW + t) * 256 + lane * 4 + r];
         }
       }
-      store_transposed<NB, KS, QP>(sDt, dop, col0, grp, c);
-      store_transposed<NB, KS, QP>(sAt, act[l - 1], col0, grp, c);
-      // D_{l-1} = (W_l^T D_l) [A_{l-1} > 0]
+      // D_{l-1} = (W_l^T D_l) [A_{l-1} > 0]; the transposes of D_l and
+      // A_{l-1} for the weight gradient are written between the row-block
+      // groups' products (the LDS stores issue while the products run)
 #pragma unroll
-      for (int mo = 0; mo < RB; ++mo) {
+      for (int mo = 0; mo < RB; ++mo)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = zero4;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          const bf16x8 f = fw[(mo * KS + ks) * 64];
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = nb_mfma_bf16(f, dop[nb][ks], acc[nb][mo]);
-        }
-        __builtin_amdgcn_sched_barrier(0);
+      {
+        constexpr int NGRP = RB < 4 ? 1 : RB / 4;
+        layer_products<RB, KS, NB>(fw, dop, acc, [&](int gi) {
+          if (NGRP == 1) {
+            store_transposed<NB, KS, QP>(sDt, dop, col0, grp, c);
+            store_transposed<NB, KS, QP>(sAt, act[l - 1], col0, grp, c);
+          } else if (gi == 0) {
+            store_transposed<NB, KS, QP>(sDt, dop, col0, grp, c);
+          } else if (gi == 1) {
+            store_transposed<NB, KS, QP>(sAt, act[l - 1], col0, grp, c);
+          }
+        });
       }
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
