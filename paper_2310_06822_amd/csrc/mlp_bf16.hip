@@ -148,8 +148,12 @@ struct Stream256 {
 
 // SPLIT: row blocks (of four) whose products precede the next K step's
 // fragment loads; (NB, THREADS): blocks of 16 queries per wave and threads
-// of the one workgroup per CU (tuning variants; all give identical results).
-template <int NH, int SPLIT, int NB_, int THREADS_>
+// of the one workgroup per CU; HALVES: each half-layer's accumulators are
+// rounded into the next layer's operands (or summed into the output logit)
+// as soon as that half is done, before the chunk's barrier -- one half of
+// the accumulators is live instead of the whole layer (tuning variants; all
+// give identical results).
+template <int NH, int SPLIT, int NB_, int THREADS_, bool HALVES = false>
 __global__ __launch_bounds__(THREADS_, 1) void k_fwd_bf16_stream(const float* __restrict__ q, int64_t n, int in_dim,
                                                           const bf16x8* __restrict__ pack,
                                                           const float* __restrict__ theta, float tau,
@@ -161,14 +165,20 @@ __global__ __launch_bounds__(THREADS_, 1) void k_fwd_bf16_stream(const float* __
   if (n_dev && (int64_t)*n_dev < n) n = (int64_t)*n_dev;   // rows counted on the device
   constexpr int W = S::W, RB = S::RB, KS = S::KS, NB = S::NB;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  // LDS region offsets kept opaque (HALVES variants): every access is then a
+  // region base register plus an immediate below 64 KB, not one address
+  // register per distinct offset above 64 KB
+  int obuf = RB * 64 * 16, obias = (RB * 64 + 2 * S::HALF * 64) * 16;
+  if constexpr (HALVES) asm volatile("" : "+s"(obuf), "+s"(obias));
   bf16x8* sfirst = reinterpret_cast<bf16x8*>(smem_raw);
-  bf16x8* sbuf = sfirst + RB * 64;                                        // [2][HALF * 64]
-  float* sbias = reinterpret_cast<float*>(sbuf + 2 * S::HALF * 64);
+  bf16x8* sbuf = reinterpret_cast<bf16x8*>(smem_raw + obuf);              // [2][HALF * 64]
+  float* sbias = reinterpret_cast<float*>(smem_raw + obias);
   const float* swo = sbias + NH * W;
   // each wave's next-tile inputs, copied straight into LDS during the last
   // layer of the current tile (no registers held across the layers)
+  const int wave_u = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   float* sin = reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(sbias) + S::bias_bytes()) +
-               (threadIdx.x >> 6) * S::IN_WAVE;
+               (HALVES ? wave_u : (int)(threadIdx.x >> 6)) * S::IN_WAVE;
   auto stage_inputs = [&](int64_t q0s) {
     const int64_t first = q0s * in_dim;
     const int64_t end = (q0s + NB * 16 < n ? q0s + NB * 16 : n) * in_dim;   // floats of valid queries
@@ -201,7 +211,7 @@ __global__ __launch_bounds__(THREADS_, 1) void k_fwd_bf16_stream(const float* __
     const bf16x8* src = chunk_src(kk);
 #pragma unroll
     for (int i = 0; i < S::PER; ++i) {
-      const int slot = i * S::THREADS + (threadIdx.x & ~63);
+      const int slot = i * S::THREADS + (HALVES ? wave_u * 64 : (int)(threadIdx.x & ~63));
       __builtin_amdgcn_global_load_lds((const void*)(src + slot + (threadIdx.x & 63)),
                                        (__attribute__((address_space(3))) void*)(dst + slot), 16, 0, 0);
     }
@@ -222,7 +232,9 @@ __global__ __launch_bounds__(THREADS_, 1) void k_fwd_bf16_stream(const float* __
   int64_t k = 0;
   for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int64_t q0 = (tile * S::WAVES + wave) * NB * 16;
-    floatx4 acc[NB][RB];
+    constexpr int RA = HALVES ? RB / 2 : RB;   // row blocks of accumulators held at a time
+    floatx4 acc[NB][RA];
+    bf16x8 act[NB][KS];
     bool bad[NB];   // rows with a non-finite value
     {
       bf16x8 xb[NB], xb1[NB];
@@ -241,37 +253,49 @@ __global__ __launch_bounds__(THREADS_, 1) void k_fwd_bf16_stream(const float* __
         nb_first_operands<NB>(xr, grp, wide, xb, xb1);
       }
 #pragma unroll
-      for (int mo = 0; mo < RB; ++mo) {
-        const float* b = sbias + 16 * mo + 4 * grp;
-        const floatx4 bi = floatx4{b[0], b[1], b[2], b[3]};
-        const bf16x8 a = sfirst[mo * 64 + lane];
+      for (int h0 = 0; h0 < RB; h0 += RA) {   // the whole layer, or two halves
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = mfma32(a, xb[nb], bi);
-      }
-      if (wide) {
-        // the second first-layer step's fragments come from global memory
-        // (L2): the LDS holds two streamed half-layers beside the first step
+        for (int u = 0; u < RA; ++u) {
+          const int mo = h0 + u;
+          const float* b = sbias + 16 * mo + 4 * grp;
+          const floatx4 bi = floatx4{b[0], b[1], b[2], b[3]};
+          const bf16x8 a = sfirst[mo * 64 + lane];
 #pragma unroll
-        for (int mo = 0; mo < RB; ++mo) {
-          const bf16x8 a = pack[(RB + (NH - 1) * S::FH + mo) * 64 + lane];
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = mfma32(a, xb1[nb], acc[nb][mo]);
+          for (int nb = 0; nb < NB; ++nb) acc[nb][u] = mfma32(a, xb[nb], bi);
         }
+        if (wide) {
+          // the second first-layer step's fragments come from global memory
+          // (L2): the LDS holds two streamed half-layers beside the first step.
+          // HALVES: the base is made opaque here so that the per-fragment
+          // addresses are formed at the loads, not held across the tile loop
+          typedef const __attribute__((address_space(1))) bf16x8* gpk_t;
+          gpk_t pk = (gpk_t)pack;
+          if constexpr (HALVES) asm volatile("" : "+s"(pk));
+#pragma unroll
+          for (int u = 0; u < RA; ++u) {
+            const bf16x8 a = pk[(RB + (NH - 1) * S::FH + h0 + u) * 64 + lane];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[nb][u] = mfma32(a, xb1[nb], acc[nb][u]);
+          }
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int k = 0; k < RA / 2; ++k) {
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = acc[nb][2 * k + j / 4][j % 4];
+            act[nb][h0 / 2 + k] = nb_relu_bf16x8(v);
+          }
       }
     }
-    bf16x8 act[NB][KS];
+    float pout[NB];   // output-layer partial sums (HALVES: accumulated half by half)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        float v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = acc[nb][2 * ks + j / 4][j % 4];
-        act[nb][ks] = nb_relu_bf16x8(v);
-      }
+    for (int nb = 0; nb < NB; ++nb) pout[nb] = 0.0f;
 
 #pragma unroll 1
     for (int l = 1; l < NH; ++l) {
+      bf16x8 actn[NB][KS];   // HALVES: the next layer's operands, filled half by half
 #pragma unroll
       for (int h = 0; h < 2; ++h, ++k) {
         const bf16x8* buf = sbuf + (k & 1) * S::HALF * 64;
@@ -285,10 +309,11 @@ __global__ __launch_bounds__(THREADS_, 1) void k_fwd_bf16_stream(const float* __
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int mo = h * (RB / 2) + m4 + u;
+            const int ma = HALVES ? m4 + u : mo;
             const float* b = sbias + l * W + 16 * mo + 4 * grp;
             const floatx4 bi = floatx4{b[0], b[1], b[2], b[3]};
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = bi;
+            for (int nb = 0; nb < NB; ++nb) acc[nb][ma] = bi;
           }
           // two fragment slots: K step ks + 1's fragments load while ks computes
           bf16x8 fa[4], fb[4];
@@ -304,8 +329,8 @@ __global__ __launch_bounds__(THREADS_, 1) void k_fwd_bf16_stream(const float* __
             for (int u = 0; u < SPLIT; ++u)
 #pragma unroll
               for (int nb = 0; nb < NB; ++nb) {
-                const int mo = h * (RB / 2) + m4 + u;
-                acc[nb][mo] = mfma32(cur[u], act[nb][ks], acc[nb][mo]);
+                const int ma = HALVES ? m4 + u : h * (RB / 2) + m4 + u;
+                acc[nb][ma] = mfma32(cur[u], act[nb][ks], acc[nb][ma]);
               }
             __builtin_amdgcn_sched_barrier(0);
             if (ks + 1 < KS) {
@@ -317,13 +342,41 @@ __global__ __launch_bounds__(THREADS_, 1) void k_fwd_bf16_stream(const float* __
             for (int u = SPLIT; u < 4; ++u)
 #pragma unroll
               for (int nb = 0; nb < NB; ++nb) {
-                const int mo = h * (RB / 2) + m4 + u;
-                acc[nb][mo] = mfma32(cur[u], act[nb][ks], acc[nb][mo]);
+                const int ma = HALVES ? m4 + u : h * (RB / 2) + m4 + u;
+                acc[nb][ma] = mfma32(cur[u], act[nb][ks], acc[nb][ma]);
               }
             __builtin_amdgcn_sched_barrier(0);
           }
         }
-        if (h == 1 && l < NH - 1) {
+        if constexpr (HALVES) {
+          // this half's row blocks are done: round them into the next
+          // layer's operands, or (last layer) add their output terms
+          if (l < NH - 1) {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+              for (int kk = 0; kk < KS / 2; ++kk) {
+                float v[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = acc[nb][2 * kk + j / 4][j % 4];
+                actn[nb][h * (KS / 2) + kk] = nb_relu_bf16x8(v);
+              }
+            if (h == 1) {
+#pragma unroll
+              for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) act[nb][ks] = actn[nb][ks];
+            }
+          } else {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+              for (int u = 0; u < RA; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                  pout[nb] = fmaf(swo[16 * (h * RA + u) + 4 * grp + r], nb_relu(acc[nb][u][r]), pout[nb]);
+          }
+        } else if (h == 1 && l < NH - 1) {
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
@@ -340,11 +393,13 @@ __global__ __launch_bounds__(THREADS_, 1) void k_fwd_bf16_stream(const float* __
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      float p = 0.0f;
+      float p = pout[nb];
+      if constexpr (!HALVES) {
 #pragma unroll
-      for (int mo = 0; mo < RB; ++mo)
+        for (int mo = 0; mo < RA; ++mo)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) p = fmaf(swo[16 * mo + 4 * grp + r], nb_relu(acc[nb][mo][r]), p);
+          for (int r = 0; r < 4; ++r) p = fmaf(swo[16 * mo + 4 * grp + r], nb_relu(acc[nb][mo][r]), p);
+      }
       p += __shfl_xor(p, 16);
       p += __shfl_xor(p, 32);
       const float z = bad[nb] ? __builtin_nanf("") : p + bo;   // non-finite row: NaN, decided positive
@@ -371,7 +426,7 @@ __global__ __launch_bounds__(THREADS_, 1) void k_fwd_bf16_stream(const float* __
   }
 }
 
-template <int NH, int SPLIT, int NB, int THREADS>
+template <int NH, int SPLIT, int NB, int THREADS, bool HALVES = false>
 nb_status stream_launch(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
                         const uint8_t* g, unsigned long long* counts, const unsigned long long* n_dev,
                         hipStream_t s) {
@@ -382,28 +437,29 @@ nb_status stream_launch(const nb_bound* b, const float* q, int64_t n, float tau,
   int dev = 0;
   NB_HIP(hipGetDevice(&dev));
   if (dev >= 0 && dev < 64 && !attr_set[dev]) {
-    NB_HIP(hipFuncSetAttribute((const void*)k_fwd_bf16_stream<NH, SPLIT, NB, THREADS>,
+    NB_HIP(hipFuncSetAttribute((const void*)k_fwd_bf16_stream<NH, SPLIT, NB, THREADS, HALVES>,
                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     attr_set[dev] = true;
   }
   const int64_t tiles = (n + S::WAVES * S::NB * 16 - 1) / (S::WAVES * S::NB * 16);
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, nb_cu_count()));
-  k_fwd_bf16_stream<NH, SPLIT, NB, THREADS><<<grid, S::THREADS, lds, s>>>(q, n, b->in_dim, reinterpret_cast<const bf16x8*>(b->pack16),
+  k_fwd_bf16_stream<NH, SPLIT, NB, THREADS, HALVES><<<grid, S::THREADS, lds, s>>>(q, n, b->in_dim, reinterpret_cast<const bf16x8*>(b->pack16),
                                                       b->theta, tau, logits, h, g, counts, n_dev);
   NB_LAUNCHED();
   return NB_OK;
 }
 
 int bf16_variants() { return 6; }
-int bf16_variants_for(int width, int n_hidden) { return width == 256 ? (n_hidden <= 6 ? 5 : 3) : 6; }
+int bf16_variants_for(int width, int n_hidden) { return width == 256 ? (n_hidden <= 6 ? 7 : 3) : 6; }
 
 // Variant v: (query blocks per wave, threads per workgroup) =
 //   0: (2, 768)   1: (2, 512)   2: (3, 512)   3: (1, 1024)   4: (4, 256)   5: (2, 256)
 // Variant 0 (three waves per SIMD) measured fastest for widths 32..128.
 // Width 256 (streamed): (SPLIT, blocks per wave, threads) =
 //   0: (2, 3, 256)   1: (1, 3, 256)   2: (3, 3, 256)   3: (2, 2, 512)   4: (1, 2, 512)
-// (variants 3 and 4 up to 6 hidden layers).
+//   5, 6: variants 3 and 4 with half-layer accumulators (HALVES)
+// (variants 3 to 6 up to 6 hidden layers).
 template <int NH>
 nb_status stream_nh(const nb_bound* b, const float* q, int64_t n, float tau, float* logits, uint8_t* h,
                     const uint8_t* g, unsigned long long* counts, const unsigned long long* n_dev, hipStream_t s) {
@@ -412,10 +468,16 @@ nb_status stream_nh(const nb_bound* b, const float* q, int64_t n, float tau, flo
     case 2: return stream_launch<NH, 3, 3, 256>(b, q, n, tau, logits, h, g, counts, n_dev, s);
     case 3:
     case 4:
+    case 5:
+    case 6:
       // eight waves fit the CU's LDS up to six hidden layers (the biases grow with depth)
       if constexpr (Stream256<NH, 2, 512>::lds_bytes() <= 160 * 1024) {
-        if (b->variant == 3) return stream_launch<NH, 2, 2, 512>(b, q, n, tau, logits, h, g, counts, n_dev, s);
-        return stream_launch<NH, 1, 2, 512>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+        switch (b->variant) {
+          case 3: return stream_launch<NH, 2, 2, 512>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+          case 4: return stream_launch<NH, 1, 2, 512>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+          case 5: return stream_launch<NH, 2, 2, 512, true>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+          default: return stream_launch<NH, 1, 2, 512, true>(b, q, n, tau, logits, h, g, counts, n_dev, s);
+        }
       } else {
         nb_set_error("streamed variant %d needs at most 6 hidden layers", b->variant);
         return NB_ERR_UNSUPPORTED;
