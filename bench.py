@@ -49,25 +49,50 @@ def sources_sha256(sources) -> str:
     return h.hexdigest()
 
 
-def committed_traffic(name: str, sources):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, or None
-    if a source file of the kernel has changed since the counters were taken."""
+def committed_traffic(name: str, sources, kernel: str = ""):
+    """HBM bytes per launch from a committed rocprofv3 counter summary (the
+    line of `kernel`, the tuned variant's name, when the summary lists it), or
+    None if a source file of the kernel has changed since the counters were
+    taken."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
-    kv = {}
+    kv, per_variant = {}, {}
     for line in open(path):
-        if ":" in line and not line.startswith("#"):
+        if line.startswith("variant:"):
+            parts = [x.strip() for x in line[len("variant:"):].split("|")]
+            for x in parts[1:]:
+                if x.startswith("traffic_bytes"):
+                    per_variant[parts[0]] = int(x.split()[1])
+        elif ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     if kv.get("sources", kv.get("source")) != " ".join(sources):
         return None
     if kv.get("source_sha256") != sources_sha256(sources):
         return None
+    if kernel and kernel in per_variant:
+        return per_variant[kernel]
     try:
         return int(float(kv["traffic_bytes_per_launch"]))
     except (KeyError, ValueError):
         return None
+
+
+# Kernel names of the bfloat16 forward variants (the variant tables of
+# csrc/mlp_bf16.hip): widths 32..128 take (blocks per wave, threads), width
+# 256 (streamed) (SPLIT, blocks per wave, threads, half-layer accumulators).
+BF16_FWD_VARIANTS = [(2, 768), (2, 512), (3, 512), (1, 1024), (4, 256), (2, 256)]
+BF16_STREAM_VARIANTS = [(2, 3, 256, False), (1, 3, 256, False), (3, 3, 256, False), (2, 2, 512, False),
+                        (1, 2, 512, False), (2, 2, 512, True), (1, 2, 512, True)]
+
+
+def bf16_forward_kernel(width: int, n_hidden: int, variant: int) -> str:
+    if width == 256:
+        sp, nbk, th, hv = BF16_STREAM_VARIANTS[variant]
+        return f"k_fwd_bf16_stream<{n_hidden}, {sp}, {nbk}, {th}, {'true' if hv else 'false'}>"
+    nbk, th = BF16_FWD_VARIANTS[variant]
+    return f"k_fwd_bf16<{width}, {n_hidden}, {nbk}, {th}>"
 
 
 def cpu_model() -> str:
@@ -361,8 +386,10 @@ def run_workload(W, args, with_cpu: bool):
             else [csrc + "mlp_f32.hip", csrc + "nb_mlp.h"])
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4),
-                "traffic": committed_traffic(f"{W.name}_forward_traffic.txt", srcs),
-                "kernel": f"{('k_fwd_bf16_stream' if W.width == 256 else 'k_fwd_bf16') if prec == nb.BF16 else 'k_fwd'} "
+                "traffic": committed_traffic(f"{W.name}_forward_traffic.txt", srcs,
+                                             bf16_forward_kernel(W.width, W.n_hidden, variant) if prec == nb.BF16
+                                             else ""),
+                "kernel": f"{bf16_forward_kernel(W.width, W.n_hidden, variant) if prec == nb.BF16 else 'k_fwd'} "
                           f"({W.precision} MLP forward + decision)",
                 "flop_per_query": flop_per_q, "avg_launch_ms": round(kern_ms, 4)}
     out = {
