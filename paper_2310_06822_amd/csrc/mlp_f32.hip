@@ -20,7 +20,8 @@
 // dL/dz and backward for the queries of a workgroup:
 //   delta_{l-1} = (W_l^T delta_l) * [a_{l-1} > 0]   (MFMA, transposed packs)
 //   dW_l += delta_l a_{l-1}^T                          (MFMA over queries; the
-//            two operands are transposed through a per-wave LDS tile)
+//            operands go through workgroup-wide LDS tiles, every 16 x 16
+//            output tile owned by one wave)
 // and writes one partial gradient per workgroup; a second kernel sums the
 // partials in a fixed order (deterministic), applies Adam and writes the
 // updated weights into their packed fragments.
@@ -86,14 +87,6 @@ __device__ __forceinline__ float act_value(float kept) { return ACT == 0 ? kept 
 template <int ACT>
 __device__ __forceinline__ float act_grad(float kept, float g) {
   return ACT == 0 ? (kept > 0.0f ? g : 0.0f) : g * cosf(kept);
-}
-
-// Orders LDS traffic of one wave: the hardware executes a wave's LDS
-// operations in issue order; this keeps the compiler from moving them.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Geometry of an in_dim -> W^NH -> 1 network with KIN 4-wide input steps.
@@ -321,78 +314,119 @@ __global__ __launch_bounds__(256, (fwd_waves<W, NH, ACT>())) void k_fwd(const fl
 
 // ------------------------------------------------------------------ training
 
-constexpr int kLDT = 17;  // row stride of the per-wave transpose tiles (16 queries + pad)
-
-template <int KIN, int W, int NH>
-struct TrainLds {
+// Training with the weight-gradient tiles shared by the workgroup's waves.
+// Every wave runs the forward, Eq. 1 and the data gradients of its own block
+// of 16 queries in registers, as k_train does, and writes each layer's
+// delta and activation columns into workgroup-wide [neuron][query] tiles in
+// LDS; after a barrier every 16 x 16 weight-gradient tile is accumulated by
+// one wave (tiles dealt round robin), with K = the 16 * WV queries of the
+// iteration.  Bias and output-weight gradients are summed over the 16 lanes
+// of a row once per block (reduce-scatter: two or three registers per lane
+// instead of one per neuron) and over the waves, in order, at the end.  A
+// wave then holds a fraction of the weight-gradient accumulators, so eight
+// waves (two per SIMD) fit where the LDS allows, against one per SIMD.
+// Row stride of the shared tiles: 16 WV + 2 floats, so that the operand
+// reads (lane: row c, column g of a K step) hit distinct banks.
+template <int KIN, int W, int NH, int WV>
+struct TrainShared {
   using N = Net<KIN, W, NH>;
-  __host__ __device__ static int64_t P(int in_dim) { return nb_b_off(NH, in_dim, W, NH) + 1; }
-  static constexpr int kTile = W * kLDT;                 // one [W][17] tile
-  static constexpr int kBias = NH * W + W + 1;           // hidden biases, output weights, output bias
-  static int64_t floats(int in_dim) {
-    const int64_t head = std::max<int64_t>((int64_t)N::NPACK * 64, P(in_dim));
-    return head + kBias + 4 * 2 * kTile + 4 * 8;
+  static constexpr int RB = N::RB, V = RB * 4, V16 = (V + 15) / 16 * 16, GW = V16 / 16;
+  static constexpr int QT = 16 * WV, S = QT + 2, ROWS = W > 16 ? W : 16;
+  static constexpr int TILES = RB * RB, TPW = (TILES + WV - 1) / WV, R0 = (RB + WV - 1) / WV;
+  static constexpr int kBias = NH * W + W + 1;
+  // parameters: in_dim W + W, then (NH - 1) (W^2 + W), then W + 1
+  __host__ __device__ static constexpr int64_t P(int in_dim) {
+    return (int64_t)W * in_dim + W + (int64_t)(NH - 1) * ((int64_t)W * W + W) + W + 1;
   }
+  __host__ __device__ static constexpr int64_t head(int in_dim) {
+    return (int64_t)N::NPACK * 64 > P(in_dim) ? (int64_t)N::NPACK * 64 : P(in_dim);
+  }
+  __host__ __device__ static constexpr int64_t floats(int in_dim) {
+    return head(in_dim) + kBias + 2 * (int64_t)ROWS * S + WV * 8;
+  }
+  static_assert((int64_t)WV * (NH + 1) * W <= (int64_t)ROWS * S, "per-wave bias sums fit the delta tile");
 };
-
+// Eight waves where the LDS allows (for every input size the network takes);
+// four (one per SIMD, 512 registers each) for the sine networks of width 64
+// and more, whose library sine and cosine need more than the 256 registers
+// of two waves per SIMD.
 template <int KIN, int W, int NH, int ACT>
-__global__ __launch_bounds__(256, 1) void k_train(const float* __restrict__ q, const uint8_t* __restrict__ y,
-                                                  int64_t n, int in_dim, int bpw, const float* __restrict__ pack,
-                                                  const float* __restrict__ theta, float alpha, float beta,
-                                                  float inv_n, float tau, float* __restrict__ partial,
-                                                  float* __restrict__ aux) {
+constexpr int train_waves() {
+  if (ACT == 1 && W >= 64) return 4;
+  return TrainShared<KIN, W, NH, 8>::floats(4 * KIN) * 4 <= 160 * 1024 ? 8 : 4;
+}
+
+template <int KIN, int W, int NH, int ACT, int WV>
+__global__ __launch_bounds__(64 * WV, 1) void k_train_s(const float* __restrict__ q, const uint8_t* __restrict__ y,
+                                                         int64_t n, int in_dim, int bpw,
+                                                         const float* __restrict__ pack,
+                                                         const float* __restrict__ theta, float alpha, float beta,
+                                                         float inv_n, float tau, float* __restrict__ partial,
+                                                         float* __restrict__ aux) {
   using N = Net<KIN, W, NH>;
-  using L = TrainLds<KIN, W, NH>;
-  constexpr int RB = N::RB;
+  using T = TrainShared<KIN, W, NH, WV>;
+  constexpr int RB = N::RB, S = T::S, ROWS = T::ROWS, V16 = T::V16, GW = T::GW;
+  constexpr int TILES = T::TILES, TPW = T::TPW, R0 = T::R0;
   extern __shared__ float smem[];
-  const int64_t P = L::P(in_dim);
-  const int64_t head = std::max<int64_t>((int64_t)N::NPACK * 64, P);
+  const int64_t P = T::P(in_dim);
   float* spack = smem;                        // packed weights; later the reduction buffer
-  float* sbias = smem + head;                 // [NH][W] biases, [W] output weights, output bias
-  float* tiles = sbias + L::kBias;            // 4 waves x (delta tile, activation tile)
-  float* saux = tiles + 4 * 2 * L::kTile;     // [4][8] per-wave loss / counts
+  float* sbias = smem + T::head(in_dim);      // [NH][W] biases, [W] output weights, output bias
+  float* dT = sbias + T::kBias;               // [ROWS][S]: deltas of the iteration's queries
+  float* aT = dT + ROWS * S;                  // [ROWS][S]: activations (inputs for the first layer)
+  float* saux = aT + ROWS * S;                // [WV][8] per-wave loss / counts
 
   for (int i = threadIdx.x; i < N::NPACK * 64; i += blockDim.x) spack[i] = pack[i];
-  for (int i = threadIdx.x; i < NH * W; i += blockDim.x) {
-    const int l = i / W, j = i % W;
-    sbias[i] = theta[nb_b_off(l, in_dim, W, NH) + j];
-  }
+  for (int i = threadIdx.x; i < NH * W; i += blockDim.x) sbias[i] = theta[nb_b_off(i / W, in_dim, W, NH) + i % W];
   for (int i = threadIdx.x; i < W + 1; i += blockDim.x) sbias[NH * W + i] = theta[nb_w_off(NH, in_dim, W) + i];
   __syncthreads();
 
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4;
-  float* dt = tiles + wave * 2 * L::kTile;    // delta tile [W][kLDT]
-  float* at = dt + L::kTile;                  // activation / input tile [W][kLDT]
+  const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const float* swo = sbias + NH * W;
   const float bo = swo[W];
+  float wo[RB * 4];   // the lane's output weights (read once: under the ReLU select a read would branch)
+#pragma unroll
+  for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) wo[mo * 4 + r] = swo[16 * mo + 4 * grp + r];
 
-  floatx4 gW0[RB];
-  floatx4 gWh[NH > 1 ? NH - 1 : 1][RB][RB];
-  float gb[NH][RB * 4];
-  float gwo[RB * 4];
+  floatx4 gW0[R0];
+  floatx4 gWh[NH > 1 ? NH - 1 : 1][TPW];
+  float gb[NH][GW], gwo[GW];
   float gbo = 0.0f, lsum = 0.0f;
   unsigned cnt[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-  for (int i = 0; i < RB; ++i) gW0[i] = floatx4{0, 0, 0, 0};
+  for (int i = 0; i < R0; ++i) gW0[i] = floatx4{0, 0, 0, 0};
 #pragma unroll
-  for (int l = 0; l < NH - 1; ++l)
+  for (int l = 0; l < (NH > 1 ? NH - 1 : 1); ++l)
 #pragma unroll
-    for (int i = 0; i < RB; ++i)
+    for (int t = 0; t < TPW; ++t) gWh[l][t] = floatx4{0, 0, 0, 0};
 #pragma unroll
-      for (int j = 0; j < RB; ++j) gWh[l][i][j] = floatx4{0, 0, 0, 0};
+  for (int k = 0; k < GW; ++k) {
+    gwo[k] = 0.0f;
 #pragma unroll
-  for (int l = 0; l < NH; ++l)
+    for (int l = 0; l < NH; ++l) gb[l][k] = 0.0f;
+  }
+  // sum over the 16 lanes of a row of RB*4 per-lane values, scattered: lane
+  // c keeps the sums of values c + 16 k
+  auto row_sums = [&](const float (&v)[RB * 4], float (&acc)[GW]) {
+    float x[V16], sm[GW];
 #pragma unroll
-    for (int i = 0; i < RB * 4; ++i) gb[l][i] = 0.0f;
+    for (int i = 0; i < V16; ++i) x[i] = i < RB * 4 ? v[i] : 0.0f;
+    nb_row_reduce_scatter<V16>(x, c, sm);
 #pragma unroll
-  for (int i = 0; i < RB * 4; ++i) gwo[i] = 0.0f;
+    for (int k = 0; k < GW; ++k) acc[k] += sm[k];
+  };
 
   const int64_t nblk = (n + 15) / 16;
   const int64_t blk0 = (int64_t)blockIdx.x * bpw;
   const int64_t blk1 = blk0 + bpw < nblk ? blk0 + bpw : nblk;
-  for (int64_t blk = blk0 + wave; blk < blk1; blk += 4) {
+  const int iters = (bpw + WV - 1) / WV;
+  const int col = 16 * wave + c;   // the lane's query column in the shared tiles
+  for (int it = 0; it < iters; ++it) {
+    const int64_t blk = blk0 + (int64_t)it * WV + wave;
     const int64_t qi = blk * 16 + c;
-    const bool valid = qi < n;
+    const bool valid = blk < blk1 && qi < n;
     float xin[KIN];
 #pragma unroll
     for (int s = 0; s < KIN; ++s) {
@@ -445,9 +479,7 @@ __global__ __launch_bounds__(256, 1) void k_train(const float* __restrict__ q, c
     for (int i = 0; i < RB * 4; ++i) alast[i] = act_value<ACT>(act[NH - 1][i]);
     float p = 0.0f;
 #pragma unroll
-    for (int mo = 0; mo < RB; ++mo)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) p = fmaf(swo[16 * mo + 4 * grp + r], alast[mo * 4 + r], p);
+    for (int i = 0; i < RB * 4; ++i) p = fmaf(wo[i], alast[i], p);
     p += __shfl_xor(p, 16);
     p += __shfl_xor(p, 32);
     const float z = p + bo;
@@ -473,35 +505,25 @@ __global__ __launch_bounds__(256, 1) void k_train(const float* __restrict__ q, c
     cnt[3] += __popcll(__ballot(own && !pos && yv));
 
     float d[RB * 4];
+    {
+      float t[RB * 4];
 #pragma unroll
-    for (int mo = 0; mo < RB; ++mo)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = mo * 4 + r;
-        gwo[i] = fmaf(dz, alast[i], gwo[i]);
-        d[i] = act_grad<ACT>(act[NH - 1][i], dz * swo[16 * mo + 4 * grp + r]);
+      for (int i = 0; i < RB * 4; ++i) {
+        t[i] = dz * alast[i];
+        d[i] = act_grad<ACT>(act[NH - 1][i], dz * wo[i]);
       }
+      row_sums(t, gwo);
+    }
 
 #pragma unroll
     for (int l = NH - 1; l >= 1; --l) {
-#pragma unroll
-      for (int i = 0; i < RB * 4; ++i) gb[l][i] += d[i];
+      row_sums(d, gb[l]);
 #pragma unroll
       for (int mo = 0; mo < RB; ++mo)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          dt[(16 * mo + 4 * grp + r) * kLDT + c] = d[mo * 4 + r];
-          at[(16 * mo + 4 * grp + r) * kLDT + c] = act_value<ACT>(act[l - 1][mo * 4 + r]);
-        }
-      wave_lds_sync();
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int no = 0; no < RB; ++no) {
-          const float av = dt[(16 * no + c) * kLDT + 4 * s + grp];
-#pragma unroll
-          for (int ko = 0; ko < RB; ++ko)
-            gWh[l - 1][no][ko] = mfma4(av, at[(16 * ko + c) * kLDT + 4 * s + grp], gWh[l - 1][no][ko]);
+          dT[(16 * mo + 4 * grp + r) * S + col] = d[mo * 4 + r];
+          aT[(16 * mo + 4 * grp + r) * S + col] = act_value<ACT>(act[l - 1][mo * 4 + r]);
         }
       floatx4 acc[RB];
 #pragma unroll
@@ -517,99 +539,109 @@ __global__ __launch_bounds__(256, 1) void k_train(const float* __restrict__ q, c
       for (int mo = 0; mo < RB; ++mo)
 #pragma unroll
         for (int r = 0; r < 4; ++r) d[mo * 4 + r] = act_grad<ACT>(act[l - 1][mo * 4 + r], acc[mo][r]);
-      wave_lds_sync();
+      __syncthreads();
+      // dW_l += delta_l a_{l-1}^T over the iteration's queries, the wave's tiles
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const int Tt = wave + t * WV;
+        if (Tt < TILES) {
+          const int no = Tt / RB, ko = Tt % RB;
+          const float* ra = dT + (16 * no + c) * S + grp;
+          const float* rb = aT + (16 * ko + c) * S + grp;
+#pragma unroll 8
+          for (int s = 0; s < 4 * WV; ++s) gWh[l - 1][t] = mfma4(ra[4 * s], rb[4 * s], gWh[l - 1][t]);
+        }
+      }
+      __syncthreads();
     }
 
-    // first layer: dW0 += delta_0 x^T (inputs as a [16][16] tile, zero-padded)
-#pragma unroll
-    for (int i = 0; i < RB * 4; ++i) gb[0][i] += d[i];
+    // first layer: dW0 += delta_0 x^T (inputs as 16 rows, zero-padded)
+    row_sums(d, gb[0]);
 #pragma unroll
     for (int mo = 0; mo < RB; ++mo)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dt[(16 * mo + 4 * grp + r) * kLDT + c] = d[mo * 4 + r];
+      for (int r = 0; r < 4; ++r) dT[(16 * mo + 4 * grp + r) * S + col] = d[mo * 4 + r];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) at[(4 * s + grp) * kLDT + c] = s < KIN ? xin[s < KIN ? s : 0] : 0.0f;
-    wave_lds_sync();
+    for (int s = 0; s < 4; ++s) aT[(4 * s + grp) * S + col] = s < KIN ? xin[s < KIN ? s : 0] : 0.0f;
+    __syncthreads();
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int no = 0; no < RB; ++no)
-        gW0[no] = mfma4(dt[(16 * no + c) * kLDT + 4 * s + grp], at[c * kLDT + 4 * s + grp], gW0[no]);
-    wave_lds_sync();
+    for (int i = 0; i < R0; ++i) {
+      const int no = wave + i * WV;
+      if (no < RB) {
+        const float* ra = dT + (16 * no + c) * S + grp;
+        const float* rb = aT + c * S + grp;
+#pragma unroll 8
+        for (int s = 0; s < 4 * WV; ++s) gW0[i] = mfma4(ra[4 * s], rb[4 * s], gW0[i]);
+      }
+    }
+    __syncthreads();
   }
 
-  // ---- workgroup reduction in a fixed order: wave 0 stores, waves 1..3 add
-  __syncthreads();
+  // ---- partial of the chunk: weight-gradient tiles from their owners;
+  // bias and output-weight sums over the waves in order
   float* red = smem;
-#pragma unroll
-  for (int i = 0; i < RB * 4; ++i) {
-#pragma unroll
-    for (int m = 1; m < 16; m <<= 1) gwo[i] += __shfl_xor(gwo[i], m);
-#pragma unroll
-    for (int l = 0; l < NH; ++l)
-#pragma unroll
-      for (int m = 1; m < 16; m <<= 1) gb[l][i] += __shfl_xor(gb[l][i], m);
-  }
 #pragma unroll
   for (int m = 1; m < 64; m <<= 1) {
     gbo += __shfl_xor(gbo, m);
     lsum += __shfl_xor(lsum, m);
   }
-  for (int w = 0; w < 4; ++w) {
-    if (wave == w) {
-      auto put = [&](int64_t idx, float v) {
-        if (w == 0)
-          red[idx] = v;
-        else
-          red[idx] += v;
-      };
+  float* wsum = dT;   // [WV][NH + 1][W]: per wave, bias gradients of each layer then the output weights
 #pragma unroll
-      for (int no = 0; no < RB; ++no)
+  for (int k = 0; k < GW; ++k) {
+    const int i = c + 16 * k;
+    if (i < RB * 4) {
+      const int nrn = 16 * (i >> 2) + 4 * grp + (i & 3);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int nrow = 16 * no + 4 * grp + r;
-          if (c < in_dim) put((int64_t)nrow * in_dim + c, gW0[no][r]);
-        }
-#pragma unroll
-      for (int l = 1; l < NH; ++l)
-#pragma unroll
-        for (int no = 0; no < RB; ++no)
-#pragma unroll
-          for (int ko = 0; ko < RB; ++ko)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-              put(nb_w_off(l, in_dim, W) + (int64_t)(16 * no + 4 * grp + r) * W + 16 * ko + c, gWh[l - 1][no][ko][r]);
-      if (c == 0) {
-#pragma unroll
-        for (int mo = 0; mo < RB; ++mo)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int nrow = 16 * mo + 4 * grp + r;
-#pragma unroll
-            for (int l = 0; l < NH; ++l) put(nb_b_off(l, in_dim, W, NH) + nrow, gb[l][mo * 4 + r]);
-            put(nb_w_off(NH, in_dim, W) + nrow, gwo[mo * 4 + r]);
-          }
-      }
-      if (lane == 0) {
-        put(nb_b_off(NH, in_dim, W, NH), gbo);
-        saux[w * 8 + 0] = lsum;
-        for (int i = 0; i < 4; ++i) saux[w * 8 + 1 + i] = __uint_as_float(cnt[i]);
-      }
+      for (int l = 0; l < NH; ++l) wsum[(wave * (NH + 1) + l) * W + nrn] = gb[l][k];
+      wsum[(wave * (NH + 1) + NH) * W + nrn] = gwo[k];
     }
-    __syncthreads();
   }
-  float* out = partial + (int64_t)blockIdx.x * P;
-  for (int64_t i = threadIdx.x; i < P; i += blockDim.x) out[i] = red[i];
-  if (threadIdx.x == 0) {
-    float ls = 0.0f;
-    unsigned cs[4] = {0u, 0u, 0u, 0u};
-    for (int w = 0; w < 4; ++w) {
-      ls += saux[w * 8];
-      for (int i = 0; i < 4; ++i) cs[i] += __float_as_uint(saux[w * 8 + 1 + i]);
+  if (lane == 0) {
+    saux[wave * 8 + 0] = lsum;
+    saux[wave * 8 + 1] = gbo;
+    for (int i = 0; i < 4; ++i) saux[wave * 8 + 2 + i] = __uint_as_float(cnt[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < R0; ++i) {
+    const int no = wave + i * WV;
+    if (no < RB && c < in_dim)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[(int64_t)(16 * no + 4 * grp + r) * in_dim + c] = gW0[i][r];
+  }
+#pragma unroll
+  for (int l = 1; l < NH; ++l)
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int Tt = wave + t * WV;
+      if (Tt < TILES) {
+        const int no = Tt / RB, ko = Tt % RB;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          red[nb_w_off(l, in_dim, W) + (int64_t)(16 * no + 4 * grp + r) * W + 16 * ko + c] = gWh[l - 1][t][r];
+      }
     }
+  __syncthreads();
+  for (int i = threadIdx.x; i < (NH + 1) * W; i += blockDim.x) {
+    const int l = i / W, nrn = i % W;
+    float v = 0.0f;
+    for (int w = 0; w < WV; ++w) v += wsum[(w * (NH + 1) + l) * W + nrn];
+    red[l < NH ? nb_b_off(l, in_dim, W, NH) + nrn : nb_w_off(NH, in_dim, W) + nrn] = v;
+  }
+  if (threadIdx.x == 0) {
+    float ls = 0.0f, gbs = 0.0f;
+    unsigned cs[4] = {0u, 0u, 0u, 0u};
+    for (int w = 0; w < WV; ++w) {
+      ls += saux[w * 8];
+      gbs += saux[w * 8 + 1];
+      for (int i = 0; i < 4; ++i) cs[i] += __float_as_uint(saux[w * 8 + 2 + i]);
+    }
+    red[nb_b_off(NH, in_dim, W, NH)] = gbs;
     aux[blockIdx.x * 8] = ls;
     for (int i = 0; i < 4; ++i) aux[blockIdx.x * 8 + 1 + i] = __uint_as_float(cs[i]);
   }
+  __syncthreads();
+  float* out = partial + (int64_t)blockIdx.x * P;
+  for (int64_t i = threadIdx.x; i < P; i += blockDim.x) out[i] = red[i];
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -631,7 +663,8 @@ nb_status fwd_launch(const nb_bound* b, const float* q, int64_t n, float tau, fl
 template <int KIN, int W, int NH, int ACT>
 nb_status train_launch(const nb_bound* b, const float* q, const uint8_t* y, int64_t n, float alpha, float beta,
                        float tau, int* n_wg, hipStream_t s) {
-  using L = TrainLds<KIN, W, NH>;
+  constexpr int WV = train_waves<KIN, W, NH, ACT>();
+  using L = TrainShared<KIN, W, NH, WV>;
   const int64_t nblk = (n + 15) / 16;
   const int bpw = (int)((nblk + kMaxWG - 1) / kMaxWG);
   const int grid = (int)((nblk + bpw - 1) / bpw);
@@ -640,12 +673,13 @@ nb_status train_launch(const nb_bound* b, const float* q, const uint8_t* y, int6
   int dev = 0;
   NB_HIP(hipGetDevice(&dev));
   if (dev >= 0 && dev < 64 && !attr_set[dev]) {
-    NB_HIP(hipFuncSetAttribute((const void*)k_train<KIN, W, NH, ACT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
+    NB_HIP(hipFuncSetAttribute((const void*)k_train_s<KIN, W, NH, ACT, WV>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr_set[dev] = true;
   }
-  k_train<KIN, W, NH, ACT><<<grid, 256, lds, s>>>(q, y, n, b->in_dim, bpw, b->pack, b->theta, alpha, beta,
-                                             (float)(1.0 / (double)n), tau, b->partial, b->aux);
+  k_train_s<KIN, W, NH, ACT, WV><<<grid, 64 * WV, lds, s>>>(q, y, n, b->in_dim, bpw, b->pack, b->theta, alpha,
+                                                           beta, (float)(1.0 / (double)n), tau, b->partial,
+                                                           b->aux);
   NB_LAUNCHED();
   *n_wg = grid;
   return NB_OK;

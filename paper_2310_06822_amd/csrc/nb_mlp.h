@@ -74,6 +74,65 @@ __device__ inline void nb_f32_pack_put(int64_t p, float v, float* __restrict__ p
   }
 }
 
+// Reduce-scatter over the 16 lanes of a row: lane c ends with the row sums
+// of the values i = c + 16 k (k < V / 16), each in a fixed order.  Step t
+// pairs lane c with c ^ (1 << bt) for bt = 3, 0, 1, 2 and keeps the half of
+// its remaining values whose bit bt of i matches the lane's, adding the
+// partner's copy of that half.  The position of value i among the remaining
+// ones is i with the bits split so far taken out (nb_rs_compress).
+__host__ __device__ constexpr int nb_rs_compress(int i, int mask) {
+  int r = 0, o = 0;
+  for (int b = 0; b < 8; ++b)
+    if (!((mask >> b) & 1)) r |= ((i >> b) & 1) << o++;
+  return r;
+}
+__host__ __device__ constexpr int nb_rs_expand(int j, int mask) {   // j with zero bits put in at the mask's positions
+  int r = 0, o = 0;
+  for (int b = 0; b < 8; ++b) {
+    if ((mask >> b) & 1) continue;
+    r |= ((j >> o++) & 1) << b;
+  }
+  return r;
+}
+
+template <int V>
+__device__ __forceinline__ void nb_row_reduce_scatter(const float (&x)[V], int c, float (&out)[V / 16]) {
+  static_assert(V % 16 == 0 && V <= 64, "values per lane: a multiple of 16");
+  float a[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) a[i] = x[i];
+  constexpr int order[4] = {3, 0, 1, 2};
+  int mask = 0;   // bits split so far
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int bt = order[st];
+    const bool hi = (c >> bt) & 1;
+    const int nmask = mask | (1 << bt);
+    float nx[V / 2];
+#pragma unroll
+    for (int j = 0; j < (V >> (st + 1)); ++j) {
+      const int i0 = nb_rs_expand(j, nmask), i1 = i0 | (1 << bt);
+      const float v0 = a[nb_rs_compress(i0, mask)], v1 = a[nb_rs_compress(i1, mask)];
+      const float keep = hi ? v1 : v0, send = hi ? v0 : v1;
+      float got;
+      if (bt == 3)
+        got = __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, send), 0x128, 0xF, 0xF, false));
+      else if (bt == 0)
+        got = __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, send), 0xB1, 0xF, 0xF, false));
+      else if (bt == 1)
+        got = __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, send), 0x4E, 0xF, 0xF, false));
+      else   // lane c ^ 4 (swizzle, bit mode: and 0x1f, xor 4)
+        got = __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, send), 0x101F));
+      nx[j] = keep + got;
+    }
+#pragma unroll
+    for (int j = 0; j < (V >> (st + 1)); ++j) a[j] = nx[j];
+    mask = nmask;
+  }
+#pragma unroll
+  for (int k = 0; k < V / 16; ++k) out[k] = a[k];
+}
+
 // bfloat16 round-to-nearest-even of a float32, from its bit pattern.
 __host__ __device__ inline uint16_t nb_bf16_bits(float v) {
   uint32_t u;
