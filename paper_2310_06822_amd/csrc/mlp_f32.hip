@@ -45,7 +45,8 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
 // for |x| <= 2^16 (the dropped remainder of pi/2 is below 2e-15).  Then the
 // Taylor series of sin and cos on |r| <= pi/4 (truncation below 2e-9) and the
 // quadrant k mod 4 picks +-sin r or +-cos r.  Larger or non-finite arguments
-// take the library's sinf.  The forward's sine activation uses it.
+// take the library's sinf (cosf).  The forward's and the training kernel's sine
+// activations use it, and the training kernel its cosine for the derivative.
 constexpr float kPio2Hi = 0x1.921fb6p+0f;    // float32 nearest to pi/2
 constexpr float kPio2Lo = -0x1.777a5cp-25f;  // float32 nearest to pi/2 - kPio2Hi
 constexpr float kTwoOverPi = 0x1.45f306p-1f;
@@ -68,6 +69,15 @@ __device__ __forceinline__ float nb_sin(float x) {
   const float v = (q & 1) ? cp : sp;   // sin(k pi/2 + r) = sin r, cos r, -sin r, -cos r
   return (q & 2) ? -v : v;
 }
+// cos x by the same reduction: cos(k pi/2 + r) = cos r, -sin r, -cos r, sin r.
+__device__ __forceinline__ float nb_cos(float x) {
+  if (!(fabsf(x) <= 65536.0f)) return cosf(x);
+  float sp, cp;
+  int q;
+  sin_cos_poly(x, sp, cp, q);
+  const float v = (q & 1) ? sp : cp;
+  return ((q + 1) & 2) ? -v : v;
+}
 
 // Hidden activation ACT: 0 ReLU, 1 sine (sin z; the paper's choice).  The
 // training kernel keeps per layer the value the backward pass needs: the
@@ -81,12 +91,13 @@ __device__ __forceinline__ float act_apply(float z) {
 }
 template <int ACT>
 __device__ __forceinline__ float act_store(float z) { return ACT == 0 ? fmaxf(z, 0.0f) : z; }
-// The training kernel evaluates sin and cos with the library's sinf / cosf.
+// The training kernel evaluates sin and cos with the same reduction and
+// polynomials as the forward.
 template <int ACT>
-__device__ __forceinline__ float act_value(float kept) { return ACT == 0 ? kept : sinf(kept); }
+__device__ __forceinline__ float act_value(float kept) { return ACT == 0 ? kept : nb_sin(kept); }
 template <int ACT>
 __device__ __forceinline__ float act_grad(float kept, float g) {
-  return ACT == 0 ? (kept > 0.0f ? g : 0.0f) : g * cosf(kept);
+  return ACT == 0 ? (kept > 0.0f ? g : 0.0f) : g * nb_cos(kept);
 }
 
 // Geometry of an in_dim -> W^NH -> 1 network with KIN 4-wide input steps.
@@ -347,12 +358,12 @@ struct TrainShared {
   static_assert((int64_t)WV * (NH + 1) * W <= (int64_t)ROWS * S, "per-wave bias sums fit the delta tile");
 };
 // Eight waves where the LDS allows (for every input size the network takes);
-// four (one per SIMD, 512 registers each) for the sine networks of width 64
-// and more, whose library sine and cosine need more than the 256 registers
-// of two waves per SIMD.
+// four (one per SIMD, 512 registers each) for the 80-wide sine networks with
+// two hidden layers, whose activations, sines and cosines need more than the
+// 256 registers of two waves per SIMD.
 template <int KIN, int W, int NH, int ACT>
 constexpr int train_waves() {
-  if (ACT == 1 && W >= 64) return 4;
+  if (ACT == 1 && W >= 80 && NH >= 2) return 4;
   return TrainShared<KIN, W, NH, 8>::floats(4 * KIN) * 4 <= 160 * 1024 ? 8 : 4;
 }
 

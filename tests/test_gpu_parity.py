@@ -819,6 +819,33 @@ def test_sine_activation_accuracy():
     assert err.max() <= 2e-7, (err.max(), x[err.argmax()])
 
 
+def test_sine_derivative_accuracy():
+    """The training kernel's cosine (the sine activation's derivative) against
+    float64 cos: the same pass-through network trained on one query x at a
+    time has dL/db0[0] = dL/dz * cos x and dL/db_out = dL/dz, so their ratio
+    is cos x up to the activation's error and two roundings."""
+    theta = np.zeros(32 + 32 + 32 + 1, np.float32)
+    theta[0] = 1.0
+    theta[64] = 1.0
+    b = nb.Bound(1, 1, 32)
+    nb.nb_bound_set_activation(b.handle, nb.SINE)
+    b.set_params(theta)
+    rng = np.random.default_rng(12)
+    x = np.concatenate([rng.uniform(-8, 8, 40), rng.uniform(-1000, 1000, 40), rng.uniform(-65536, 65536, 40),
+                        rng.uniform(-3e6, 3e6, 8),
+                        np.float32([0.0, np.pi / 2, np.pi, -np.pi / 4, 65536.0, -65537.0])]).astype(np.float32)
+    grad = torch.empty(b.n_params, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    y = cuda(np.ones(1, np.uint8))
+    worst = 0.0
+    for v in x:
+        nb.nb_bound_loss_grad(b.handle, cuda(np.float32([[v]])), y, 1.0, 1.0, grad, loss)
+        g = host(grad).astype(np.float64)
+        assert g[96] != 0.0
+        worst = max(worst, abs(g[32] / g[96] - np.cos(np.float64(v))))
+    assert worst <= 3e-7, worst
+
+
 @pytest.mark.parametrize("in_dim,width,nh", SINE_SHAPES)
 def test_loss_grad_sine_parity(in_dim, width, nh):
     widths = [width] * nh
