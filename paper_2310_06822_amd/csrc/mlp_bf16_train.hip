@@ -591,6 +591,7 @@ struct TrainJob {
   const bf16x8* packT = nullptr;
   uint16_t* act = nullptr;          // member 0: activation slots, slot(l) at act + slot(l) * Bp * W
   int every = 0;                    // checkpoint interval of the activation recomputation (0: keep all)
+  bool stream_fwd = false;          // width 256: the forward half in one streamed launch
   uint16_t* grad = nullptr;         // member 0: D ping-pong at grad + k * Bp * W
   float* partial = nullptr;
   float* aux = nullptr;
@@ -650,14 +651,44 @@ nb_status train_w(const TrainJob& J, hipStream_t s) {
     NB_LAUNCHED();
     return NB_OK;
   };
-  k_tr_first<W><<<wide, 256, 0, s>>>(J.q, J.n, in_dim, J.plan.padded, J.pack, J.theta, NH, A(0), J.T);
-  NB_LAUNCHED();
-  for (int l = 1; l < NH - 1; ++l) NB_TRY(hidden(l));
-  // head: layer NH-1, output layer, loss, D_{NH-1}
   int cur = 0;
-  k_tr_head<W><<<grid, tr_threads<W, true>(), lds, s>>>(A(NH - 2), J.n, CH, NH - 1, in_dim, NH, J.pack, J.theta, D[cur], J.y,
-                                              J.alpha, J.beta, J.inv_n, J.tau, J.partial, J.aux, J.T);
-  NB_LAUNCHED();
+  if (W == 256 && J.stream_fwd && J.members == 1 && bf16_stream_forward_supported(in_dim, NH, W)) {
+    // one streamed launch: the activations the backward reads first (every
+    // one, or the checkpoints and the last segment), D_{NH-1}, output layer
+    StreamJob F;
+    F.in_dim = in_dim;
+    F.NH = NH;
+    F.n = J.n;
+    F.P = J.T.P;
+    F.plan = J.plan;
+    F.q = J.q;
+    F.y = J.y;
+    F.theta = J.theta;
+    F.pack = J.pack;
+    F.act = J.act;
+    F.act_stride = stride;
+    for (int l = 0; l < 8; ++l) {
+      const bool keep = l <= NH - 2 && (S.every < 2 || l % S.every == 0 || S.segment(l) == S.segment(NH - 2));
+      F.slots.s[l] = keep ? S.slot(l) : -1;
+    }
+    F.Dout = D[cur];
+    F.partial = J.partial;
+    F.aux = J.aux;
+    F.alpha = J.alpha;
+    F.beta = J.beta;
+    F.inv_n = J.inv_n;
+    F.tau = J.tau;
+    NB_TRY(bf16_stream_forward(F, s));
+  } else {
+    k_tr_first<W><<<wide, 256, 0, s>>>(J.q, J.n, in_dim, J.plan.padded, J.pack, J.theta, NH, A(0), J.T);
+    NB_LAUNCHED();
+    for (int l = 1; l < NH - 1; ++l) NB_TRY(hidden(l));
+    // head: layer NH-1, output layer, loss, D_{NH-1}
+    k_tr_head<W><<<grid, tr_threads<W, true>(), lds, s>>>(A(NH - 2), J.n, CH, NH - 1, in_dim, NH, J.pack, J.theta,
+                                                         D[cur], J.y, J.alpha, J.beta, J.inv_n, J.tau, J.partial,
+                                                         J.aux, J.T);
+    NB_LAUNCHED();
+  }
   constexpr int WW = W >= 256 ? 8 : 4;
   const size_t wlds = (size_t)4 * W * kTS * 2 + (size_t)(WW * 64 / (W / 2)) * W * 4;
   NB_TRY(allow_lds(k_tr_weight<W, WW>, wlds));
@@ -764,6 +795,7 @@ nb_status bf16_train_partials(const nb_bound* b, const float* q, const uint8_t* 
   J.packT = reinterpret_cast<const bf16x8*>(b->pack16t);
   J.act = b->tr_act;
   J.every = b->recompute;
+  J.stream_fwd = b->train_kernel == NB_TRAIN_AUTO;
   J.grad = b->tr_grad;
   J.partial = b->partial;
   J.aux = b->aux;

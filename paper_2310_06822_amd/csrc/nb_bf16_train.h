@@ -39,6 +39,34 @@ struct FusedJob {
 // Launches the fused training step (mlp_bf16_fused.hip).
 nb_status bf16_fused_train(const FusedJob& J, hipStream_t s);
 
+// Activation slot of each A_l (l = 0 .. NH-2) that the streamed training
+// forward writes; -1: not written (recomputed by the backward).
+struct StreamSlots {
+  int s[8];
+};
+
+// The forward half of a training step of one 256-wide bound in one launch
+// (mlp_bf16_stream_train.hip): the kept activation rows, D_{NH-1}, and the
+// chunk partials of the output layer, loss and counts.
+struct StreamJob {
+  int in_dim = 0, NH = 0;
+  int64_t n = 0, P = 0;
+  BF16TrainPlan plan;
+  const float* q = nullptr;
+  const uint8_t* y = nullptr;
+  const float* theta = nullptr;
+  const nb_bf16x8* pack = nullptr;
+  uint16_t* act = nullptr;       // slot k at act + k * act_stride
+  int64_t act_stride = 0;
+  StreamSlots slots{};
+  uint16_t* Dout = nullptr;      // D_{NH-1}, [padded batch][256]
+  float* partial = nullptr;
+  float* aux = nullptr;
+  float alpha = 1, beta = 1, inv_n = 1, tau = 0;
+};
+bool bf16_stream_forward_supported(int in_dim, int n_hidden, int width);
+nb_status bf16_stream_forward(const StreamJob& J, hipStream_t s);
+
 namespace {
 
 typedef nb_bf16x8 bf16x8;

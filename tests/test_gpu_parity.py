@@ -645,6 +645,45 @@ def test_bf16_fused_vs_layerwise(in_dim, width, nh, n):
         assert _rel_frob(Wf, Wl) <= 2e-3 and _rel_frob(bf, bl) <= 2e-3
 
 
+@pytest.mark.parametrize("in_dim,nh,every", [(4, 6, 3), (4, 6, 0), (8, 2, 0), (3, 3, 2), (5, 6, 2), (1, 4, 0), (6, 8, 3)])
+@pytest.mark.parametrize("n", [7, 4099, 70001])
+def test_bf16_stream_forward_vs_layerwise(in_dim, nh, every, n):
+    """Width 256: the streamed training forward (one launch for the first
+    layer, the hidden layers and the head) writes the same activation and
+    D_{NH-1} bits as the layer-wise kernels, so every hidden- and first-layer
+    gradient is bit-identical; the output layer's gradient and the loss are
+    summed in another order (float32 rounding only).  Checkpointed
+    recomputation included; 70001 gives chunks of 320 queries (a ragged
+    256-query tile) and 7 a chunk of one partial tile.  Eight hidden layers
+    take the layer-wise kernels either way (the streamed forward's LDS holds
+    up to six layers' biases)."""
+    q = synth.points(141, n, in_dim)
+    y = (synth.points(142, n, 1)[:, 0] > 0.25).astype(np.uint8)
+    theta = synth.init_params(143 + nh, in_dim, [256] * nh)
+    out = {}
+    for kern in (nb.TRAIN_AUTO, nb.TRAIN_LAYERWISE):
+        b = nb.Bound(in_dim, nh, 256, nb.BF16)
+        nb.nb_bound_set_train_kernel(b.handle, kern)
+        nb.nb_bound_set_recompute(b.handle, every)
+        b.set_params(theta)
+        g = torch.empty(b.n_params, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        cnt = torch.empty(4, dtype=torch.int64, device="cuda")
+        nb.nb_bound_loss_grad(b.handle, cuda(q), cuda(y), 7.0, 1.0, g, loss, cnt)
+        out[kern] = (host(g).astype(np.float64), float(host(loss)[0]), host(cnt))
+    gs, ls, cs = out[nb.TRAIN_AUTO]
+    gl, ll, cl = out[nb.TRAIN_LAYERWISE]
+    assert np.array_equal(cs, cl)
+    assert abs(ls - ll) <= 1e-5 * abs(ll)
+    layers_s = mlp.unpack(gs, in_dim, [256] * nh)
+    layers_l = mlp.unpack(gl, in_dim, [256] * nh)
+    for (Ws, bs), (Wl, bl) in zip(layers_s[:-1], layers_l[:-1]):
+        assert np.array_equal(Ws, Wl) and np.array_equal(bs, bl)
+    (Ws, bs), (Wl, bl) = layers_s[-1], layers_l[-1]
+    assert _rel_frob(Ws, Wl) <= 1e-5
+    assert abs(float(bs[0]) - float(bl[0])) <= 1e-5 * max(abs(float(bl[0])), float(np.abs(Wl).max()))
+
+
 @pytest.mark.parametrize("in_dim,width,nh", [(6, 128, 4), (4, 64, 3), (6, 32, 2)])
 def test_loss_grad_bf16_fused_multi_tile(in_dim, width, nh):
     """The fused kernel against the oracle on a batch whose chunks hold
