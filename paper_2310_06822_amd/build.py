@@ -23,7 +23,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnbound.so")
 
-SOURCES = ["api.cpp", "sampler.hip", "indicators.hip", "mlp_f32.hip", "mlp_bf16.hip", "mlp_bf16_train.hip", "mlp_bf16_fused.hip", "mlp_bf16_stream_train.hip", "optim.hip", "early.hip", "kdop.hip", "group.hip", "group_api.cpp", "hier.hip"]
+SOURCES = ["api.cpp", "sampler.hip", "indicators.hip", "mlp_f32.hip", "mlp_bf16.hip", "mlp_bf16_train.hip", "mlp_bf16_fused.hip", "mlp_bf16_train256.hip", "optim.hip", "early.hip", "kdop.hip", "group.hip", "group_api.cpp", "hier.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

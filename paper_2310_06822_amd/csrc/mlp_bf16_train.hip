@@ -591,7 +591,8 @@ struct TrainJob {
   const bf16x8* packT = nullptr;
   uint16_t* act = nullptr;          // member 0: activation slots, slot(l) at act + slot(l) * Bp * W
   int every = 0;                    // checkpoint interval of the activation recomputation (0: keep all)
-  bool stream_fwd = false;          // width 256: the forward half in one streamed launch
+  bool stream_fwd = false;          // width 256: the forward half in one streamed launch, and every
+                                    // backward layer's data and weight gradient in one launch
   uint16_t* grad = nullptr;         // member 0: D ping-pong at grad + k * Bp * W
   float* partial = nullptr;
   float* aux = nullptr;
@@ -699,11 +700,27 @@ nb_status train_w(const TrainJob& J, hipStream_t s) {
       const int c = valid_seg * S.every;
       for (int r = c + 1; r <= std::min(c + S.every - 1, NH - 2); ++r) NB_TRY(hidden(r));
     }
-    k_tr_weight<W, WW><<<grid, WW * 64, wlds, s>>>(D[cur], A(l - 1), CH, l, in_dim, NH, J.partial, J.T);
-    NB_LAUNCHED();
-    k_tr_data<W><<<wide, tr_threads<W, false>(), (size_t)T::FH * 64 * 16, s>>>(D[cur], A(l - 1), J.plan.padded, l,
-                                                                             J.packT, D[cur ^ 1], J.T);
-    NB_LAUNCHED();
+    if (W == 256 && J.stream_fwd && J.members == 1) {
+      // data and weight gradient in one launch: D_l, A_{l-1} read once
+      Back256Job B;
+      B.in_dim = in_dim;
+      B.NH = NH;
+      B.l = l;
+      B.P = J.T.P;
+      B.plan = J.plan;
+      B.Dl = D[cur];
+      B.Aprev = A(l - 1);
+      B.packT = J.packT;
+      B.Dprev = D[cur ^ 1];
+      B.partial = J.partial;
+      NB_TRY(bf16_back256(B, s));
+    } else {
+      k_tr_weight<W, WW><<<grid, WW * 64, wlds, s>>>(D[cur], A(l - 1), CH, l, in_dim, NH, J.partial, J.T);
+      NB_LAUNCHED();
+      k_tr_data<W><<<wide, tr_threads<W, false>(), (size_t)T::FH * 64 * 16, s>>>(D[cur], A(l - 1), J.plan.padded,
+                                                                               l, J.packT, D[cur ^ 1], J.T);
+      NB_LAUNCHED();
+    }
     cur ^= 1;
   }
   k_tr_first_grad<W><<<grid, kFG, 0, s>>>(D[cur], J.q, J.n, CH, in_dim, NH, J.partial, J.T);

@@ -1,30 +1,35 @@
-// Forward half of a bfloat16 training step for 256-wide bounds (Alg. 1
-// step 4 and Eq. 1), one launch in place of the layer-wise first-layer,
-// hidden-layer and head kernels.
+// Training kernels for 256-wide bfloat16 bounds (Alg. 1 steps 4-5,
+// gradient of Eq. 1) that replace groups of the layer-wise kernels.
 //
-// A 256-wide layer does not fit next to a second one in LDS, so, as in the
-// streamed forward, every hidden layer streams through two 64 KiB LDS
-// buffers in half-layer chunks (row blocks 0..7, then 8..15), copied straight
-// from global memory into the idle buffer while the waves multiply the other
-// one; the first layer's fragments and all biases stay resident.  One
-// workgroup of 8 waves (two per SIMD) takes one chunk of the batch in tiles
-// of 256 queries, two blocks of 16 per wave, so every streamed chunk serves
-// 256 queries.
+// k_tr_stream: the forward half of a step in one launch, in place of the
+// first-layer, hidden-layer and head kernels.  A 256-wide layer does not fit
+// next to a second one in LDS, so, as in the streamed forward, every hidden
+// layer streams through two 64 KiB LDS buffers in half-layer chunks (row
+// blocks 0..7, then 8..15), copied straight from global memory into the idle
+// buffer while the waves multiply the other one; the first layer's fragments
+// and all biases stay resident.  One workgroup of 8 waves (two per SIMD)
+// takes one chunk of the batch in tiles of 256 queries, two blocks of 16 per
+// wave, so every streamed chunk serves 256 queries.  What the backward reads
+// goes to HBM: the activation rows A_l that are kept (all of them, or the
+// checkpoints and the last segment when the backward recomputes the rest),
+// in the operand order of the layer-wise kernels, and D_{NH-1} = dL/dz w_out
+// [a > 0].  The output layer's gradient, the loss and the confusion counts
+// of the chunk go to the chunk's partial.
 //
-// What the backward kernels read goes to HBM: the activation rows A_l that
-// are kept (all of them, or the checkpoints and the last segment when the
-// backward recomputes the rest), in the same operand order and with the
-// same bits as the layer-wise kernels write them, and D_{NH-1} = dL/dz w_out
-// [a > 0] of the last hidden layer.  The output layer's gradient (w_out,
-// b_out), the loss and the confusion counts of the chunk go to the chunk's
-// partial; everything else of a tile stays on the chip.
+// k_tr_back: one layer of the backward pass, in place of the data- and
+// weight-gradient kernels, so that D_l and A_{l-1} are read from HBM once:
+//   D_{l-1} = (W_l^T D_l) [A_{l-1} > 0],  dW_l = sum_q D_l[q] A_{l-1}[q]^T,
+//   db_l = sum_q D_l[q].
+// W_l^T's fragments fill 128 KiB of LDS; the other 32 KiB hold the current
+// 32 queries' D_l and A_{l-1} transposed ([neuron][query] tiles), which the
+// weight gradient needs with the queries on the MFMA's K dimension.
 //
 // Rounding points and the order of every product are those of the
 // layer-wise kernels (bias first, K steps in order; the output logit summed
-// over row blocks in order), so the activations, the logits and D_{NH-1} are
-// bit-identical to theirs.  The output-weight sums go through a per-block
-// reduce-scatter over the 16 queries of a row and then the waves in order:
-// deterministic, but summed in another order than the layer-wise head.
+// over row blocks in order; weight-gradient tiles summed over the same
+// 32-query slabs in the same order), so activations, logits, D_l and dW_l
+// are bit-identical to theirs.  The output-weight and bias sums go through
+// other fixed orders: deterministic, float32 rounding apart.
 #include <algorithm>
 
 #include "nb_bf16_train.h"
@@ -396,12 +401,269 @@ nb_status stream_launch(const StreamJob& J, hipStream_t s) {
   return NB_OK;
 }
 
+// ------------------------------------------------------------ backward
+
+// LDS of k_tr_back: a ring of four 32-query steps of D_l and A_{l-1} rows
+// (16 KiB each, row-major as in HBM but with the 16-byte chunks of row q
+// permuted, chunk k at k ^ (q & 7), so that a 16-lane read of one chunk
+// from 16 rows hits distinct banks), loaded straight from global memory
+// three steps ahead; then the step's [neuron][32 query] transposed tiles.
+// W_l^T stays in registers (each wave's four row blocks, 128 per lane).
+struct Back256 {
+  static constexpr int W = 256, RB = 16, KS = 8, QS = 32, WAVES = 4, THREADS = 256, RING = 4;
+  static constexpr int SLOT = QS * W;                 // bfloat16 elements of one tensor's step
+  static constexpr size_t ring_bytes() { return (size_t)RING * 2 * SLOT * 2; }
+  static constexpr size_t tile_bytes() { return (size_t)W * QS * 2; }
+  static constexpr size_t lds_bytes() { return ring_bytes() + 2 * tile_bytes(); }
+};
+static_assert(Back256::lds_bytes() <= 160 * 1024, "backward layer: LDS of one CU");
+
+// Workgroup barrier for LDS traffic only: the wave's LDS operations are
+// complete (lgkmcnt 0), its global loads and stores stay in flight (a
+// __syncthreads would also wait for those).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Transposed tile: row i (neuron) of 32 queries, 64 bytes in four 16-byte
+// chunks of 8 queries; chunk k of row i sits at k ^ ((i >> 1) & 3), so that
+// the weight-gradient operand reads (lane c: row 16 b + c, chunk g) of 8
+// consecutive lanes hit distinct banks.
+__device__ __forceinline__ int tile_off(int row, int q) {
+  return row * 32 + (((q >> 3) ^ ((row >> 1) & 3)) << 3) + (q & 7);
+}
+
+// Writes the lane's operand (8 values of one query, element j = neuron
+// nrn(j)) into a transposed tile, two queries per 32-bit store: the lanes of
+// queries c and c ^ 1 swap dword halves (one DPP move, one byte permute);
+// the even lane writes neuron nrn(2m), the odd lane nrn(2m + 1), each for
+// both queries.  nrn(2m + 1) = nrn(2m) + 1.
+template <class NRN>
+__device__ __forceinline__ void tile_store(uint16_t* __restrict__ tile, bf16x8 v, int q, NRN nrn) {
+  const int odd = q & 1;
+  const unsigned sel = odd ? 0x03020706u : 0x05040100u;
+  const nb_uint4 u = __builtin_bit_cast(nb_uint4, v);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const unsigned pu = (unsigned)__builtin_amdgcn_mov_dpp((int)u[m], 0xB1, 0xF, 0xF, false);   // lane c ^ 1
+    const unsigned w = __builtin_amdgcn_perm(pu, u[m], sel);
+    const int row = nrn(2 * m) + odd;
+    *reinterpret_cast<unsigned*>(tile + tile_off(row, q & ~1)) = w;
+  }
+}
+
+// s_waitcnt vmcnt(n) for a wave-uniform n in {0, 8, ..., 48}.
+__device__ __forceinline__ void wait_vm(int n) {
+  switch (n) {
+    case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+    case 8: asm volatile("s_waitcnt vmcnt(8)" ::: "memory"); break;
+    case 16: asm volatile("s_waitcnt vmcnt(16)" ::: "memory"); break;
+    case 24: asm volatile("s_waitcnt vmcnt(24)" ::: "memory"); break;
+    case 32: asm volatile("s_waitcnt vmcnt(32)" ::: "memory"); break;
+    case 40: asm volatile("s_waitcnt vmcnt(40)" ::: "memory"); break;
+    default: asm volatile("s_waitcnt vmcnt(48)" ::: "memory"); break;
+  }
+}
+
+// One backward layer over one chunk of the batch (CH queries, a multiple of
+// 32) per workgroup of four waves.  Wave w: data gradient of row blocks
+// 4w .. 4w+3 for both 16-query blocks of every step (W_l^T's fragments of
+// those rows in registers); weight-gradient tiles of row blocks 4w .. 4w+3
+// against all 16 column blocks, and their bias rows (a fragment of ones as
+// the MFMA's B operand).  Per step every wave issues 8 ring loads (three
+// steps ahead, after the step's first barrier) and 8 stores of D_{l-1}, so
+// the loads of a step are complete once at most 8 x (steps of stores and
+// loads issued after them) remain.
+__global__ __launch_bounds__(256, 1) void k_tr_back(const uint16_t* __restrict__ Dl,
+                                                    const uint16_t* __restrict__ Aprev, int64_t CH, int l,
+                                                    int in_dim, int NH, const bf16x8* __restrict__ packT,
+                                                    uint16_t* __restrict__ Dprev, int64_t P,
+                                                    float* __restrict__ partial) {
+  using B = Back256;
+  constexpr int W = B::W, KS = B::KS;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  int otile = (int)B::ring_bytes();
+  asm volatile("" : "+s"(otile));
+  uint16_t* ring = reinterpret_cast<uint16_t*>(smem_raw);   // [RING][D slot, A slot]
+  uint16_t* sDT = reinterpret_cast<uint16_t*>(smem_raw + otile);
+  uint16_t* sAT = sDT + W * B::QS;
+  const int lane = threadIdx.x & 63, c0 = lane & 15, grp0 = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t cbeg = (int64_t)blockIdx.x * CH;
+  const int nst = (int)(CH / B::QS);
+
+  // the step's rows into ring slot (st & 3): 32 rows x 512 bytes per tensor
+  // are 1024 sixteen-byte units; wave w, instruction i fills units
+  // 64 (4 i + w) + lane, unit u = row q, chunk position p holding the row's
+  // chunk p ^ (q & 7)
+  // (the bases are opaque and the lane offsets formed here, so that no
+  // per-lane address is held across the loop)
+  auto load_step = [&](int st) {
+    const int64_t r0 = cbeg + (int64_t)st * B::QS;
+    uint16_t* slot = ring + (st & 3) * 2 * B::SLOT;
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const uint16_t* src = (t == 0 ? Dl : Aprev) + r0 * W;
+      asm volatile("" : "+s"(src));
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int u0 = 64 * (4 * i + wave);               // wave-uniform first unit
+        const int u = u0 + ln, qq = u >> 5, p = u & 31;
+        __builtin_amdgcn_global_load_lds((const void*)(src + qq * W + 8 * (p ^ (qq & 7))),
+                                         (__attribute__((address_space(3))) void*)(slot + t * B::SLOT + 8 * u0),
+                                         16, 0, 0);
+      }
+    }
+  };
+  // 16-byte chunk k of row q of a ring tensor
+  auto ring_chunk = [&](const uint16_t* base, int q, int k) {
+    return *reinterpret_cast<const bf16x8*>(base + q * W + 8 * (k ^ (q & 7)));
+  };
+
+  for (int st = 0; st < 3 && st < nst; ++st) load_step(st);
+
+  // W_l^T fragments of row blocks 4 wave .. + 3 (natural K order)
+  bf16x8 wt[4][KS];
+  {
+    const bf16x8* src = packT + (int64_t)(l - 1) * B::RB * KS * 64 + lane;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) wt[u][ks] = src[((4 * wave + u) * KS + ks) * 64];
+  }
+  floatx4 dw[4][16], db[4];
+  const floatx4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    db[a] = zero4;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) dw[a][b] = zero4;
+  }
+  nb_uint4 onesu;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) onesu[i] = 0x3F803F80u;
+  const bf16x8 ones = __builtin_bit_cast(bf16x8, onesu);
+  // lane offset of the weight-gradient operand reads (row 16 b + c, chunk grp)
+
+#pragma unroll 1
+  for (int st = 0; st < nst; ++st) {
+    // lane coordinates made opaque per step: the LDS addresses built from
+    // them are formed where they are used, not held across the loop
+    int c = c0, grp = grp0;
+    asm volatile("" : "+v"(c), "+v"(grp));
+    const int64_t r0 = cbeg + (int64_t)st * B::QS;
+    const uint16_t* sD = ring + (st & 3) * 2 * B::SLOT;
+    const uint16_t* sA = sD + B::SLOT;
+    // this step's rows have landed once at most the stores of the three
+    // steps before and the loads of the two after are outstanding
+    wait_vm(8 * ((st < 3 ? st : 3) + (nst - 1 - st < 2 ? nst - 1 - st : 2)));
+    lds_barrier();   // the step's rows are in LDS; every wave is done with step st - 1 (its slot, the tiles)
+    if (st + 3 < nst) load_step(st + 3);
+    // transposed tiles: wave w takes chunks 8w .. 8w+7 of both query blocks
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int q = 16 * (t & 1) + c, k = 8 * wave + 4 * (t >> 1) + grp;
+      tile_store(sDT, ring_chunk(sD, q, k), q, [&](int j) { return 8 * k + j; });
+      // A_{l-1} is in operand order: chunk k = 4 kp + g holds neurons 16 (2 kp + j / 4) + 4 g + j % 4
+      tile_store(sAT, ring_chunk(sA, q, k), q,
+                 [&](int j) { return 16 * (2 * (k >> 2) + j / 4) + 4 * (k & 3) + (j & 3); });
+    }
+    // D_{l-1} = (W_l^T D_l) [A_{l-1} > 0], row blocks 4w .. 4w+3, both query blocks
+    {
+      floatx4 acc[2][4];
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[nb][u] = zero4;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const bf16x8 b0 = ring_chunk(sD, c, 4 * ks + grp), b1 = ring_chunk(sD, 16 + c, 4 * ks + grp);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          acc[0][u] = nb_mfma_bf16(wt[u][ks], b0, acc[0][u]);
+          acc[1][u] = nb_mfma_bf16(wt[u][ks], b1, acc[1][u]);
+        }
+      }
+      typedef __attribute__((address_space(1))) unsigned long long* gst_t;
+      gst_t out = (gst_t)(Dprev + r0 * W);
+      asm volatile("" : "+s"(out));
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const int q = 16 * nb + c;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {   // row blocks 4w + 2h, 4w + 2h + 1: one 16-byte piece of A_{l-1}
+          const nb_uint4 au = __builtin_bit_cast(nb_uint4, ring_chunk(sA, q, 4 * (2 * wave + h) + grp));
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const int u = 2 * h + e, mo = 4 * wave + u;
+            float a[4];
+            unpack4(e ? uint2{au[2], au[3]} : uint2{au[0], au[1]}, a);
+            const uint2 pk = pack4(a[0] > 0.0f ? acc[nb][u][0] : 0.0f, a[1] > 0.0f ? acc[nb][u][1] : 0.0f,
+                                   a[2] > 0.0f ? acc[nb][u][2] : 0.0f, a[3] > 0.0f ? acc[nb][u][3] : 0.0f);
+            out[((int64_t)q * W + 16 * mo + 4 * grp) / 4] =
+                (unsigned long long)pk.x | ((unsigned long long)pk.y << 32);
+          }
+        }
+      }
+    }
+    lds_barrier();   // the transposed tiles are complete
+    // dW_l += D_l A_{l-1}^T, db_l += D_l 1 over the 32 queries (K)
+    {
+      typedef const __attribute__((address_space(3))) bf16x8* lop_t;
+      const int rd_off = c * 32 + ((grp ^ ((c >> 1) & 3)) << 3);   // row 16 b + c, chunk grp
+      lop_t dt = (lop_t)(sDT + rd_off);
+      lop_t at = (lop_t)(sAT + rd_off);
+      bf16x8 af[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) af[a] = dt[(16 * (4 * wave + a)) * 32 / 8];
+#pragma unroll
+      for (int b = 0; b < 16; ++b) {
+        const bf16x8 bf = at[(16 * b) * 32 / 8];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) dw[a][b] = nb_mfma_bf16(af[a], bf, dw[a][b]);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) db[a] = nb_mfma_bf16(af[a], ones, db[a]);
+    }
+  }
+
+  // the chunk's partial: the wave's weight-gradient tiles and bias rows
+  const int c = c0, grp = grp0;
+  float* out = partial + (int64_t)blockIdx.x * P;
+  const int64_t wo = nb_w_off(l, in_dim, W);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 16; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out[wo + (int64_t)(16 * (4 * wave + a) + 4 * grp + r) * W + 16 * b + c] = dw[a][b][r];
+  if (c == 0) {
+    const int64_t bo = nb_b_off(l, in_dim, W, NH);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[bo + 16 * (4 * wave + a) + 4 * grp + r] = db[a][r];
+  }
+}
 }  // namespace
 
 // Up to six hidden layers: the biases of seven or eight no longer fit the
 // LDS beside the two streamed half-layers, the first layer and the inputs.
 bool bf16_stream_forward_supported(int in_dim, int n_hidden, int width) {
   return width == 256 && in_dim >= 1 && in_dim <= 8 && n_hidden >= 2 && n_hidden <= 6;
+}
+
+nb_status bf16_back256(const Back256Job& J, hipStream_t s) {
+  if (J.plan.chunk % Back256::QS != 0) {
+    nb_set_error("backward layer kernel: chunk of %lld queries is not a multiple of 32", (long long)J.plan.chunk);
+    return NB_ERR_UNSUPPORTED;
+  }
+  NB_TRY(allow_lds(k_tr_back, Back256::lds_bytes()));
+  k_tr_back<<<(unsigned)J.plan.n_wg, Back256::THREADS, Back256::lds_bytes(), s>>>(
+      J.Dl, J.Aprev, J.plan.chunk, J.l, J.in_dim, J.NH, J.packT, J.Dprev, J.P, J.partial);
+  NB_LAUNCHED();
+  return NB_OK;
 }
 
 nb_status bf16_stream_forward(const StreamJob& J, hipStream_t s) {

@@ -46,7 +46,7 @@ struct StreamSlots {
 };
 
 // The forward half of a training step of one 256-wide bound in one launch
-// (mlp_bf16_stream_train.hip): the kept activation rows, D_{NH-1}, and the
+// (mlp_bf16_train256.hip): the kept activation rows, D_{NH-1}, and the
 // chunk partials of the output layer, loss and counts.
 struct StreamJob {
   int in_dim = 0, NH = 0;
@@ -64,6 +64,19 @@ struct StreamJob {
   float* aux = nullptr;
   float alpha = 1, beta = 1, inv_n = 1, tau = 0;
 };
+// One backward layer of a 256-wide bound (data and weight gradient in one
+// launch, mlp_bf16_train256.hip): D_{l-1} and the chunk partials of dW_l, db_l.
+struct Back256Job {
+  int in_dim = 0, NH = 0, l = 0;
+  int64_t P = 0;
+  BF16TrainPlan plan;
+  const uint16_t* Dl = nullptr;       // [padded batch][256], natural neuron order
+  const uint16_t* Aprev = nullptr;    // [padded batch][256], operand order
+  const nb_bf16x8* packT = nullptr;   // transposed fragments, natural K order
+  uint16_t* Dprev = nullptr;
+  float* partial = nullptr;
+};
+nb_status bf16_back256(const Back256Job& J, hipStream_t s);
 bool bf16_stream_forward_supported(int in_dim, int n_hidden, int width);
 nb_status bf16_stream_forward(const StreamJob& J, hipStream_t s);
 
