@@ -20,9 +20,12 @@
 // weight-gradient kernels, so that D_l and A_{l-1} are read from HBM once:
 //   D_{l-1} = (W_l^T D_l) [A_{l-1} > 0],  dW_l = sum_q D_l[q] A_{l-1}[q]^T,
 //   db_l = sum_q D_l[q].
-// W_l^T's fragments fill 128 KiB of LDS; the other 32 KiB hold the current
-// 32 queries' D_l and A_{l-1} transposed ([neuron][query] tiles), which the
-// weight gradient needs with the queries on the MFMA's K dimension.
+// One workgroup of four waves per CU takes one chunk of the batch in steps
+// of 32 queries: W_l^T's fragments stay in registers (each wave's four row
+// blocks), the steps' D_l and A_{l-1} rows stream into a four-step LDS ring
+// three steps ahead (direct-to-LDS loads), and the step's rows are written
+// once more transposed ([neuron][query] tiles) for the weight gradient,
+// which needs the queries on the MFMA's K dimension.
 //
 // Rounding points and the order of every product are those of the
 // layer-wise kernels (bias first, K steps in order; the output logit summed
@@ -450,16 +453,17 @@ __device__ __forceinline__ void tile_store(uint16_t* __restrict__ tile, bf16x8 v
   }
 }
 
-// s_waitcnt vmcnt(n) for a wave-uniform n in {0, 8, ..., 48}.
+// s_waitcnt vmcnt(n) for a wave-uniform n in {0, 4, ..., 28}.
 __device__ __forceinline__ void wait_vm(int n) {
   switch (n) {
     case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+    case 4: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
     case 8: asm volatile("s_waitcnt vmcnt(8)" ::: "memory"); break;
+    case 12: asm volatile("s_waitcnt vmcnt(12)" ::: "memory"); break;
     case 16: asm volatile("s_waitcnt vmcnt(16)" ::: "memory"); break;
+    case 20: asm volatile("s_waitcnt vmcnt(20)" ::: "memory"); break;
     case 24: asm volatile("s_waitcnt vmcnt(24)" ::: "memory"); break;
-    case 32: asm volatile("s_waitcnt vmcnt(32)" ::: "memory"); break;
-    case 40: asm volatile("s_waitcnt vmcnt(40)" ::: "memory"); break;
-    default: asm volatile("s_waitcnt vmcnt(48)" ::: "memory"); break;
+    default: asm volatile("s_waitcnt vmcnt(28)" ::: "memory"); break;
   }
 }
 
@@ -469,9 +473,9 @@ __device__ __forceinline__ void wait_vm(int n) {
 // those rows in registers); weight-gradient tiles of row blocks 4w .. 4w+3
 // against all 16 column blocks, and their bias rows (a fragment of ones as
 // the MFMA's B operand).  Per step every wave issues 8 ring loads (three
-// steps ahead, after the step's first barrier) and 8 stores of D_{l-1}, so
-// the loads of a step are complete once at most 8 x (steps of stores and
-// loads issued after them) remain.
+// steps ahead, after the step's first barrier) and 4 stores of D_{l-1}, and
+// nothing else that counts in vmcnt, so the loads of a step are complete
+// once no more than the stores and loads issued after them remain.
 __global__ __launch_bounds__(256, 1) void k_tr_back(const uint16_t* __restrict__ Dl,
                                                     const uint16_t* __restrict__ Aprev, int64_t CH, int l,
                                                     int in_dim, int NH, const bf16x8* __restrict__ packT,
@@ -555,20 +559,16 @@ __global__ __launch_bounds__(256, 1) void k_tr_back(const uint16_t* __restrict__
     const uint16_t* sD = ring + (st & 3) * 2 * B::SLOT;
     const uint16_t* sA = sD + B::SLOT;
     // this step's rows have landed once at most the stores of the three
-    // steps before and the loads of the two after are outstanding
-    wait_vm(8 * ((st < 3 ? st : 3) + (nst - 1 - st < 2 ? nst - 1 - st : 2)));
+    // steps before (4 each) and the loads of the two after (8 each) are
+    // outstanding
+    wait_vm(4 * (st < 3 ? st : 3) + 8 * (nst - 1 - st < 2 ? nst - 1 - st : 2));
     lds_barrier();   // the step's rows are in LDS; every wave is done with step st - 1 (its slot, the tiles)
     if (st + 3 < nst) load_step(st + 3);
-    // transposed tiles: wave w takes chunks 8w .. 8w+7 of both query blocks
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int q = 16 * (t & 1) + c, k = 8 * wave + 4 * (t >> 1) + grp;
-      tile_store(sDT, ring_chunk(sD, q, k), q, [&](int j) { return 8 * k + j; });
-      // A_{l-1} is in operand order: chunk k = 4 kp + g holds neurons 16 (2 kp + j / 4) + 4 g + j % 4
-      tile_store(sAT, ring_chunk(sA, q, k), q,
-                 [&](int j) { return 16 * (2 * (k >> 2) + j / 4) + 4 * (k & 3) + (j & 3); });
-    }
-    // D_{l-1} = (W_l^T D_l) [A_{l-1} > 0], row blocks 4w .. 4w+3, both query blocks
+    asm volatile("" ::: "memory");   // the loads issue before this step's stores (the counts above)
+    // D_{l-1} = (W_l^T D_l) [A_{l-1} > 0], row blocks 4w .. 4w+3, both query
+    // blocks.  The chunks the wave reads for it also fill its share of the
+    // transposed tiles: D_l's K steps 2w, 2w+1 and the A_{l-1} mask pieces
+    // (K steps 2w, 2w+1 of the operand-order rows).
     {
       floatx4 acc[2][4];
 #pragma unroll
@@ -578,31 +578,46 @@ __global__ __launch_bounds__(256, 1) void k_tr_back(const uint16_t* __restrict__
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         const bf16x8 b0 = ring_chunk(sD, c, 4 * ks + grp), b1 = ring_chunk(sD, 16 + c, 4 * ks + grp);
+        if ((ks >> 1) == wave) {
+          tile_store(sDT, b0, c, [&](int j) { return 32 * ks + 8 * grp + j; });
+          tile_store(sDT, b1, 16 + c, [&](int j) { return 32 * ks + 8 * grp + j; });
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           acc[0][u] = nb_mfma_bf16(wt[u][ks], b0, acc[0][u]);
           acc[1][u] = nb_mfma_bf16(wt[u][ks], b1, acc[1][u]);
         }
       }
-      typedef __attribute__((address_space(1))) unsigned long long* gst_t;
+      // stores: the lanes of rows g and g ^ 1 (same query) swap one row
+      // block's values (v_permlane16_swap), so that every lane writes 16
+      // bytes: 8 consecutive neurons of row block 4w + 2h (even g) or
+      // 4w + 2h + 1 (odd g)
+      typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+      typedef __attribute__((address_space(1))) u32x4* gst_t;
       gst_t out = (gst_t)(Dprev + r0 * W);
       asm volatile("" : "+s"(out));
+      const bool oddrow = grp & 1;
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb) {
         const int q = 16 * nb + c;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {   // row blocks 4w + 2h, 4w + 2h + 1: one 16-byte piece of A_{l-1}
-          const nb_uint4 au = __builtin_bit_cast(nb_uint4, ring_chunk(sA, q, 4 * (2 * wave + h) + grp));
+          const bf16x8 av = ring_chunk(sA, q, 4 * (2 * wave + h) + grp);
+          tile_store(sAT, av, q, [&](int j) { return 16 * (2 * (2 * wave + h) + j / 4) + 4 * grp + (j & 3); });
+          const nb_uint4 au = __builtin_bit_cast(nb_uint4, av);
+          uint2 pk[2];
 #pragma unroll
           for (int e = 0; e < 2; ++e) {
-            const int u = 2 * h + e, mo = 4 * wave + u;
+            const int u = 2 * h + e;
             float a[4];
             unpack4(e ? uint2{au[2], au[3]} : uint2{au[0], au[1]}, a);
-            const uint2 pk = pack4(a[0] > 0.0f ? acc[nb][u][0] : 0.0f, a[1] > 0.0f ? acc[nb][u][1] : 0.0f,
-                                   a[2] > 0.0f ? acc[nb][u][2] : 0.0f, a[3] > 0.0f ? acc[nb][u][3] : 0.0f);
-            out[((int64_t)q * W + 16 * mo + 4 * grp) / 4] =
-                (unsigned long long)pk.x | ((unsigned long long)pk.y << 32);
+            pk[e] = pack4(a[0] > 0.0f ? acc[nb][u][0] : 0.0f, a[1] > 0.0f ? acc[nb][u][1] : 0.0f,
+                          a[2] > 0.0f ? acc[nb][u][2] : 0.0f, a[3] > 0.0f ? acc[nb][u][3] : 0.0f);
           }
+          const auto sx = __builtin_amdgcn_permlane16_swap(pk[0].x, pk[1].x, false, false);
+          const auto sy = __builtin_amdgcn_permlane16_swap(pk[0].y, pk[1].y, false, false);
+          const int mo = 4 * wave + 2 * h + (oddrow ? 1 : 0);
+          out[((int64_t)q * W + 16 * mo + 4 * (grp & ~1)) / 8] = u32x4{sx[0], sy[0], sx[1], sy[1]};
         }
       }
     }
