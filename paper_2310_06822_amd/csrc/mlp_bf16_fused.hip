@@ -60,7 +60,11 @@ struct Fz {
   static constexpr int KQ = Q / 32;           // K = 32 steps over a tile's queries
   static constexpr int QP = Q + 8;            // LDS row stride (bfloat16) of the transposed tiles
   static constexpr int TILES = RB * RB, TPW = TILES / WAVES;   // 16 x 16 weight-gradient tiles per wave
-  static constexpr bool DW_REGS = TPW * 4 * (NH - 1) <= 64;
+  // hidden layers whose weight-gradient tiles stay in registers for the
+  // whole chunk: all of them if they fit 64 accumulator registers, otherwise
+  // as many as fit beside one layer's tiles in flight from the chunk's
+  // partial (the others' go through the partial once per tile)
+  static constexpr int NREG = TPW * 4 * (NH - 1) <= 64 ? NH - 1 : (64 - TPW * 4) / (TPW * 4);
   static constexpr int RW = TPW >= RB ? TPW / RB : 1;          // row blocks per wave (whole rows if TPW >= RB)
   static constexpr int R0 = (RB + WAVES - 1) / WAVES;          // first-layer gradient row blocks per wave
   static constexpr int XROWS = 32;   // input-piece rows: 3 in_dim + 1 <= 25, read as two 16-row B tiles
@@ -188,7 +192,8 @@ __global__ __launch_bounds__(64 * WV, (WV == 8 || W >= 128 ? 1 : 2)) void k_tr_f
   using F = Fz<W, NH, WV>;
   constexpr int RB = F::RB, KS = F::KS, FH = F::FH, NB = F::NB, WAVES = F::WAVES, Q = F::Q, QP = F::QP;
   constexpr int TPW = F::TPW, RW = F::RW, R0 = F::R0, KQ = F::KQ, GW = F::GW;
-  constexpr bool DW_REGS = F::DW_REGS;
+  constexpr int NREG = F::NREG;
+  auto in_regs = [](int l) { return l - 1 < NREG; };   // layer l's tiles in registers
   const TrObj ob = tr_obj(TO);
   const int64_t P = ob.P;
   pack += TO.pkoff ? TO.pkoff[ob.o] : 0;
@@ -270,16 +275,16 @@ __global__ __launch_bounds__(64 * WV, (WV == 8 || W >= 128 ? 1 : 2)) void k_tr_f
   float gbo = 0.0f, lsum = 0.0f;
   unsigned cnt[4] = {0u, 0u, 0u, 0u};
   floatx4 dbh[NH - 1][RW];                        // hidden-layer bias gradients of the wave's row blocks
-  floatx4 dwr[DW_REGS ? NH - 1 : 1][DW_REGS ? TPW : 1];   // weight gradients kept in registers
+  floatx4 dwr[NREG > 0 ? NREG : 1][TPW];         // weight gradients kept in registers (layers 1 .. NREG)
   floatx4 dw0[R0][2];                            // first-layer gradient tiles
 #pragma unroll
   for (int l = 0; l < NH - 1; ++l)
 #pragma unroll
     for (int i = 0; i < RW; ++i) dbh[l][i] = zero4;
 #pragma unroll
-  for (int l = 0; l < (DW_REGS ? NH - 1 : 1); ++l)
+  for (int l = 0; l < (NREG > 0 ? NREG : 1); ++l)
 #pragma unroll
-    for (int t = 0; t < (DW_REGS ? TPW : 1); ++t) dwr[l][t] = zero4;
+    for (int t = 0; t < TPW; ++t) dwr[l][t] = zero4;
 #pragma unroll
   for (int i = 0; i < R0; ++i) dw0[i][0] = dw0[i][1] = zero4;
 
@@ -469,9 +474,10 @@ __global__ __launch_bounds__(64 * WV, (WV == 8 || W >= 128 ? 1 : 2)) void k_tr_f
       // partials of this layer's weight-gradient tiles (kept in memory):
       // loaded here so that the transposes and the data gradient cover
       // their latency
-      floatx4 dwm[DW_REGS ? 1 : TPW];
+      floatx4 dwm[TPW];
       const gptr<float> R = opaque(out + nb_w_off(l, in_dim, W));
-      if constexpr (!DW_REGS) {
+      const int lr = in_regs(l) ? l - 1 : 0;   // (l is a constant here: the loop is unrolled)
+      if (!in_regs(l)) {
         if (it == 0) {
 #pragma unroll
           for (int t = 0; t < TPW; ++t) dwm[t] = zero4;
@@ -517,7 +523,7 @@ __global__ __launch_bounds__(64 * WV, (WV == 8 || W >= 128 ? 1 : 2)) void k_tr_f
       {
         floatx4 dw[TPW];
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) dw[t] = DW_REGS ? dwr[l - 1][t] : dwm[t];
+        for (int t = 0; t < TPW; ++t) dw[t] = in_regs(l) ? dwr[lr][t] : dwm[t];
 #pragma unroll
         for (int s = 0; s < KQ; ++s) {
           if constexpr (TPW >= RB) {
@@ -547,9 +553,9 @@ __global__ __launch_bounds__(64 * WV, (WV == 8 || W >= 128 ? 1 : 2)) void k_tr_f
           }
           __builtin_amdgcn_sched_barrier(0);
         }
-        if constexpr (DW_REGS) {
+        if (in_regs(l)) {
 #pragma unroll
-          for (int t = 0; t < TPW; ++t) dwr[l - 1][t] = dw[t];
+          for (int t = 0; t < TPW; ++t) dwr[lr][t] = dw[t];
         } else {
           if (last_tile) {
 #pragma unroll
@@ -661,13 +667,14 @@ __global__ __launch_bounds__(64 * WV, (WV == 8 || W >= 128 ? 1 : 2)) void k_tr_f
           for (int r = 0; r < 4; ++r) out[nb_b_off(l, in_dim, W, NH) + 16 * no + 4 * grp + r] = dbh[l - 1][i][r];
       }
     }
-    if constexpr (DW_REGS) {
+    if (in_regs(l)) {
 #pragma unroll
       for (int t = 0; t < TPW; ++t) {
         const int T = wave * TPW + t, no = T / RB, ko = T % RB;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          out[nb_w_off(l, in_dim, W) + (int64_t)(16 * no + 4 * grp + r) * W + 16 * ko + c] = dwr[l - 1][t][r];
+          out[nb_w_off(l, in_dim, W) + (int64_t)(16 * no + 4 * grp + r) * W + 16 * ko + c] =
+              dwr[in_regs(l) ? l - 1 : 0][t][r];
       }
     }
   }
