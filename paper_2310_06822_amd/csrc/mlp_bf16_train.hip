@@ -538,22 +538,36 @@ __global__ __launch_bounds__(kFG) void k_tr_first_grad(const uint16_t* __restric
   for (int e = 0; e < 8; ++e)
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc[e][k] = 0.0f;
-  // the lanes of a sample read the same input row (one transaction)
-#pragma unroll 2
-  for (int64_t i = base + sub; i < end; i += S) {
-    const uint4 v = *reinterpret_cast<const uint4*>(D0 + i * W + 8 * g);
-    float xs[8];
+  // U samples' loads in flight per lane before their products (the lanes of
+  // a sample read the same input row: one transaction); a sample past the
+  // chunk loads row `base` and adds zeros, so there are no branches and each
+  // lane's sums keep the order i = base + sub, + S, ...
+  constexpr int U = 8;
+  for (int64_t i0 = base + sub; i0 < end; i0 += U * S) {
+    uint4 v[U];
+    float xs[U][8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) xs[k] = k < in_dim ? q[i * in_dim + k] : 0.0f;
-    float d[8];
-    unpack4(uint2{v.x, v.y}, d);
-    unpack4(uint2{v.z, v.w}, d + 4);
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + (int64_t)u * S;
+      const int64_t ic = i < end ? i : base;
+      v[u] = *reinterpret_cast<const uint4*>(D0 + ic * W + 8 * g);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      acc[e][8] += d[e];
+      for (int k = 0; k < 8; ++k) xs[u][k] = k < in_dim ? q[ic * in_dim + k] : 0.0f;
+    }
 #pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (k < in_dim) acc[e][k] = fmaf(d[e], xs[k], acc[e][k]);
+    for (int u = 0; u < U; ++u) {
+      const bool valid = i0 + (int64_t)u * S < end;
+      float d[8];
+      unpack4(uint2{v[u].x, v[u].y}, d);
+      unpack4(uint2{v[u].z, v[u].w}, d + 4);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float de = valid ? d[e] : 0.0f;
+        acc[e][8] += de;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (k < in_dim) acc[e][k] = fmaf(de, xs[u][k], acc[e][k]);
+      }
     }
   }
 #pragma unroll
