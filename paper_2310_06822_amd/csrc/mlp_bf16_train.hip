@@ -711,8 +711,25 @@ nb_status train_w(const TrainJob& J, hipStream_t s) {
   for (int l = NH - 1; l >= 1; --l) {
     if (S.segment(l - 1) != valid_seg) {
       valid_seg = S.segment(l - 1);
-      const int c = valid_seg * S.every;
-      for (int r = c + 1; r <= std::min(c + S.every - 1, NH - 2); ++r) NB_TRY(hidden(r));
+      const int c = valid_seg * S.every, c1 = std::min(c + S.every - 1, NH - 2);
+      if (W == 256 && J.stream_fwd && J.members == 1 && c1 > c) {
+        // the segment's layers in one streamed launch from the checkpoint
+        RecomputeJob R;
+        R.in_dim = in_dim;
+        R.NH = NH;
+        R.l0 = c + 1;
+        R.l1 = c1;
+        R.plan = J.plan;
+        R.ain = A(c);
+        R.pack = J.pack;
+        R.theta = J.theta;
+        R.act = J.act;
+        R.act_stride = stride;
+        for (int r = 0; r < 8; ++r) R.slots.s[r] = r >= R.l0 && r <= R.l1 ? S.slot(r) : -1;
+        NB_TRY(bf16_recompute256(R, s));
+      } else {
+        for (int r = c + 1; r <= c1; ++r) NB_TRY(hidden(r));
+      }
     }
     if (W == 256 && J.stream_fwd && J.members == 1) {
       // data and weight gradient in one launch: D_l, A_{l-1} read once

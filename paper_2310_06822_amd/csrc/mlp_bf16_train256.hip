@@ -393,6 +393,141 @@ __global__ __launch_bounds__(512, 1) void k_tr_stream(const float* __restrict__ 
   }
 }
 
+// Recomputation of a segment A_{l0} .. A_{l1} of activation rows from the
+// checkpoint A_{l0-1} (width 256), one launch in place of one hidden-layer
+// launch per layer: the checkpoint rows are read once and every recomputed
+// row written once, the layers streaming through LDS in half-layer chunks
+// as in k_tr_stream (same products in the same order: the same bits).
+__global__ __launch_bounds__(512, 1) void k_tr_recompute(const uint16_t* __restrict__ ain, int64_t CH, int l0, int l1,
+                                                         int in_dim, int NH, const bf16x8* __restrict__ pack,
+                                                         const float* __restrict__ theta, uint16_t* __restrict__ act,
+                                                         int64_t act_stride, StreamSlots slots) {
+  using S = TrStream<6>;   // (the streaming shape; the biases below hold only the segment's layers)
+  constexpr int W = S::W, RB = S::RB, KS = S::KS, NB = S::NB, RA = RB / 2;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  int obias = 2 * S::HALF * 64 * 16;
+  asm volatile("" : "+s"(obias));
+  bf16x8* sbuf = reinterpret_cast<bf16x8*>(smem_raw);   // [2][HALF * 64]
+  float* sbias = reinterpret_cast<float*>(smem_raw + obias);   // [l1 - l0 + 1][W]
+  const int wave_u = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t cbeg = (int64_t)blockIdx.x * CH, cend = cbeg + CH;
+  const int nl = l1 - l0 + 1, nchunk = 2 * nl;
+  for (int i = threadIdx.x; i < nl * W; i += S::THREADS) sbias[i] = theta[nb_b_off(l0 + i / W, in_dim, W, NH) + i % W];
+  const int64_t tiles = (CH + S::TILE - 1) / S::TILE;
+  const int64_t total_chunks = tiles * nchunk;
+  auto chunk_src = [&](int64_t k) {
+    const int cc = (int)(k % nchunk), l = l0 + cc / 2, h = cc % 2;
+    return pack + (RB + (l - 1) * S::FH + h * S::HALF) * 64;
+  };
+  auto prefetch = [&](int64_t kk, bf16x8* dst) {
+    const bf16x8* src = chunk_src(kk);
+#pragma unroll
+    for (int i = 0; i < S::PER; ++i) {
+      const int slot = i * S::THREADS + wave_u * 64;
+      __builtin_amdgcn_global_load_lds((const void*)(src + slot + (threadIdx.x & 63)),
+                                       (__attribute__((address_space(3))) void*)(dst + slot), 16, 0, 0);
+    }
+  };
+  {
+    const bf16x8* src = chunk_src(0);
+#pragma unroll
+    for (int i = 0; i < S::PER; ++i) sbuf[threadIdx.x + i * S::THREADS] = src[threadIdx.x + i * S::THREADS];
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, c = lane & 15, grp = lane >> 4;
+  auto half_products = [&](const bf16x8* buf, int lb, int h, const bf16x8 (&opnd)[NB][KS], floatx4 (&acc)[NB][RA]) {
+#pragma unroll
+    for (int m4 = 0; m4 < RA; m4 += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float* b = sbias + lb * W + 16 * (h * RA + m4 + u) + 4 * grp;
+        const floatx4 bi = floatx4{b[0], b[1], b[2], b[3]};
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb][m4 + u] = bi;
+      }
+      bf16x8 fa[4], fb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) fa[u] = buf[((m4 + u) * KS + 0) * 64 + lane];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        bf16x8(&cur)[4] = (ks & 1) ? fb : fa;
+        bf16x8(&nx)[4] = (ks & 1) ? fa : fb;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb][m4] = nb_mfma_bf16(cur[0], opnd[nb][ks], acc[nb][m4]);
+        __builtin_amdgcn_sched_barrier(0);
+        if (ks + 1 < KS) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) nx[u] = buf[((m4 + u) * KS + ks + 1) * 64 + lane];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 1; u < 4; ++u)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[nb][m4 + u] = nb_mfma_bf16(cur[u], opnd[nb][ks], acc[nb][m4 + u]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  };
+
+  int64_t k = 0;
+#pragma unroll 1
+  for (int64_t t = 0; t < tiles; ++t) {
+    const int64_t q0 = cbeg + t * S::TILE + wave_u * NB * 16;
+    const bool rows = q0 < cend;   // whole blocks: the chunk is a multiple of 32 rows
+    bf16x8 opnd[NB][KS];
+    {
+      typedef const __attribute__((address_space(1))) bf16x8* gin_t;
+      gin_t src = (gin_t)(ain + (rows ? q0 : cbeg) * W);
+      asm volatile("" : "+s"(src));
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) opnd[nb][ks] = src[((nb * 16 + c) * W + 32 * ks + 8 * grp) / 8];
+    }
+    auto store_rows = [&](int l) {
+      if (!rows) return;
+      typedef __attribute__((address_space(1))) bf16x8* gact_t;
+      gact_t base = (gact_t)(act + (int64_t)slots.s[l] * act_stride + q0 * W);
+      asm volatile("" : "+s"(base));
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) base[((nb * 16 + c) * W + 32 * ks + 8 * grp) / 8] = opnd[nb][ks];
+    };
+#pragma unroll 1
+    for (int l = l0; l <= l1; ++l) {
+      bf16x8 nxt[NB][KS];
+#pragma unroll
+      for (int h = 0; h < 2; ++h, ++k) {
+        const bf16x8* buf = sbuf + (k & 1) * S::HALF * 64;
+        if (k + 1 < total_chunks) prefetch(k + 1, sbuf + ((k + 1) & 1) * S::HALF * 64);
+        if (h == 0 && l > l0) store_rows(l - 1);
+        floatx4 acc[NB][RA];
+        half_products(buf, l - l0, h, opnd, acc);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int kk = 0; kk < KS / 2; ++kk) {
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = acc[nb][2 * kk + j / 4][j % 4];
+            nxt[nb][h * (KS / 2) + kk] = nb_relu_bf16x8(v);
+          }
+        if (h == 1) {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) opnd[nb][ks] = nxt[nb][ks];
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+      }
+    }
+    store_rows(l1);
+  }
+}
+
 template <int NH>
 nb_status stream_launch(const StreamJob& J, hipStream_t s) {
   using S = TrStream<NH>;
@@ -677,6 +812,25 @@ nb_status bf16_back256(const Back256Job& J, hipStream_t s) {
   NB_TRY(allow_lds(k_tr_back, Back256::lds_bytes()));
   k_tr_back<<<(unsigned)J.plan.n_wg, Back256::THREADS, Back256::lds_bytes(), s>>>(
       J.Dl, J.Aprev, J.plan.chunk, J.l, J.in_dim, J.NH, J.packT, J.Dprev, J.P, J.partial);
+  NB_LAUNCHED();
+  return NB_OK;
+}
+
+nb_status bf16_recompute256(const RecomputeJob& J, hipStream_t s) {
+  using S = TrStream<6>;
+  const int nl = J.l1 - J.l0 + 1;
+  if (J.l0 < 1 || nl < 1 || J.l1 > J.NH - 2 || J.plan.chunk % 32 != 0) {
+    nb_set_error("recomputation kernel: unsupported segment %d .. %d", J.l0, J.l1);
+    return NB_ERR_UNSUPPORTED;
+  }
+  const size_t lds = (size_t)2 * S::HALF * 64 * 16 + (size_t)nl * 256 * 4;
+  if (lds > 160 * 1024) {
+    nb_set_error("recomputation kernel: a segment of %d layers does not fit the LDS", nl);
+    return NB_ERR_UNSUPPORTED;
+  }
+  NB_TRY(allow_lds(k_tr_recompute, 160 * 1024));
+  k_tr_recompute<<<(unsigned)J.plan.n_wg, S::THREADS, lds, s>>>(J.ain, J.plan.chunk, J.l0, J.l1, J.in_dim, J.NH,
+                                                              J.pack, J.theta, J.act, J.act_stride, J.slots);
   NB_LAUNCHED();
   return NB_OK;
 }

@@ -77,6 +77,19 @@ struct Back256Job {
   float* partial = nullptr;
 };
 nb_status bf16_back256(const Back256Job& J, hipStream_t s);
+// Recomputation of activation rows A_{l0} .. A_{l1} of a 256-wide bound from
+// the checkpoint A_{l0-1} in one launch (mlp_bf16_train256.hip).
+struct RecomputeJob {
+  int in_dim = 0, NH = 0, l0 = 0, l1 = 0;
+  BF16TrainPlan plan;
+  const uint16_t* ain = nullptr;      // A_{l0-1}
+  const nb_bf16x8* pack = nullptr;
+  const float* theta = nullptr;
+  uint16_t* act = nullptr;            // slot k at act + k * act_stride
+  int64_t act_stride = 0;
+  StreamSlots slots{};                // slot of each A_l written
+};
+nb_status bf16_recompute256(const RecomputeJob& J, hipStream_t s);
 bool bf16_stream_forward_supported(int in_dim, int n_hidden, int width);
 nb_status bf16_stream_forward(const StreamJob& J, hipStream_t s);
 
