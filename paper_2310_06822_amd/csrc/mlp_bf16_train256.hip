@@ -20,9 +20,9 @@
 // weight-gradient kernels, so that D_l and A_{l-1} are read from HBM once:
 //   D_{l-1} = (W_l^T D_l) [A_{l-1} > 0],  dW_l = sum_q D_l[q] A_{l-1}[q]^T,
 //   db_l = sum_q D_l[q].
-// One workgroup of four waves per CU takes one chunk of the batch in steps
-// of 32 queries: W_l^T's fragments stay in registers (each wave's four row
-// blocks), the steps' D_l and A_{l-1} rows stream into a four-step LDS ring
+// One workgroup of eight waves per CU (two per SIMD) takes one chunk of the
+// batch in steps of 32 queries: W_l^T's fragments stay in registers (each
+// wave's two row blocks), the steps' D_l and A_{l-1} rows stream into a four-step LDS ring
 // three steps ahead (direct-to-LDS loads), and the step's rows are written
 // once more transposed ([neuron][query] tiles) for the weight gradient,
 // which needs the queries on the MFMA's K dimension.
@@ -546,9 +546,10 @@ nb_status stream_launch(const StreamJob& J, hipStream_t s) {
 // permuted, chunk k at k ^ (q & 7), so that a 16-lane read of one chunk
 // from 16 rows hits distinct banks), loaded straight from global memory
 // three steps ahead; then the step's [neuron][32 query] transposed tiles.
-// W_l^T stays in registers (each wave's four row blocks, 128 per lane).
+// W_l^T stays in registers (each wave's 16 / WV row blocks).
 struct Back256 {
-  static constexpr int W = 256, RB = 16, KS = 8, QS = 32, WAVES = 4, THREADS = 256, RING = 4;
+  static constexpr int W = 256, RB = 16, KS = 8, QS = 32, RING = 4;
+  static constexpr int WAVES = 8;   // two per SIMD (measured 379 us per 2^20 samples against 455 with four)
   static constexpr int SLOT = QS * W;                 // bfloat16 elements of one tensor's step
   static constexpr size_t ring_bytes() { return (size_t)RING * 2 * SLOT * 2; }
   static constexpr size_t tile_bytes() { return (size_t)W * QS * 2; }
@@ -588,36 +589,66 @@ __device__ __forceinline__ void tile_store(uint16_t* __restrict__ tile, bf16x8 v
   }
 }
 
-// s_waitcnt vmcnt(n) for a wave-uniform n in {0, 4, ..., 28}.
+// s_waitcnt vmcnt(n) for a wave-uniform n in 0 .. 31.
 __device__ __forceinline__ void wait_vm(int n) {
   switch (n) {
     case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+    case 1: asm volatile("s_waitcnt vmcnt(1)" ::: "memory"); break;
+    case 2: asm volatile("s_waitcnt vmcnt(2)" ::: "memory"); break;
+    case 3: asm volatile("s_waitcnt vmcnt(3)" ::: "memory"); break;
     case 4: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
+    case 5: asm volatile("s_waitcnt vmcnt(5)" ::: "memory"); break;
+    case 6: asm volatile("s_waitcnt vmcnt(6)" ::: "memory"); break;
+    case 7: asm volatile("s_waitcnt vmcnt(7)" ::: "memory"); break;
     case 8: asm volatile("s_waitcnt vmcnt(8)" ::: "memory"); break;
+    case 9: asm volatile("s_waitcnt vmcnt(9)" ::: "memory"); break;
+    case 10: asm volatile("s_waitcnt vmcnt(10)" ::: "memory"); break;
+    case 11: asm volatile("s_waitcnt vmcnt(11)" ::: "memory"); break;
     case 12: asm volatile("s_waitcnt vmcnt(12)" ::: "memory"); break;
+    case 13: asm volatile("s_waitcnt vmcnt(13)" ::: "memory"); break;
+    case 14: asm volatile("s_waitcnt vmcnt(14)" ::: "memory"); break;
+    case 15: asm volatile("s_waitcnt vmcnt(15)" ::: "memory"); break;
     case 16: asm volatile("s_waitcnt vmcnt(16)" ::: "memory"); break;
+    case 17: asm volatile("s_waitcnt vmcnt(17)" ::: "memory"); break;
+    case 18: asm volatile("s_waitcnt vmcnt(18)" ::: "memory"); break;
+    case 19: asm volatile("s_waitcnt vmcnt(19)" ::: "memory"); break;
     case 20: asm volatile("s_waitcnt vmcnt(20)" ::: "memory"); break;
+    case 21: asm volatile("s_waitcnt vmcnt(21)" ::: "memory"); break;
+    case 22: asm volatile("s_waitcnt vmcnt(22)" ::: "memory"); break;
+    case 23: asm volatile("s_waitcnt vmcnt(23)" ::: "memory"); break;
     case 24: asm volatile("s_waitcnt vmcnt(24)" ::: "memory"); break;
-    default: asm volatile("s_waitcnt vmcnt(28)" ::: "memory"); break;
+    case 25: asm volatile("s_waitcnt vmcnt(25)" ::: "memory"); break;
+    case 26: asm volatile("s_waitcnt vmcnt(26)" ::: "memory"); break;
+    case 27: asm volatile("s_waitcnt vmcnt(27)" ::: "memory"); break;
+    case 28: asm volatile("s_waitcnt vmcnt(28)" ::: "memory"); break;
+    case 29: asm volatile("s_waitcnt vmcnt(29)" ::: "memory"); break;
+    case 30: asm volatile("s_waitcnt vmcnt(30)" ::: "memory"); break;
+    default: asm volatile("s_waitcnt vmcnt(31)" ::: "memory"); break;
   }
 }
 
 // One backward layer over one chunk of the batch (CH queries, a multiple of
-// 32) per workgroup of four waves.  Wave w: data gradient of row blocks
-// 4w .. 4w+3 for both 16-query blocks of every step (W_l^T's fragments of
-// those rows in registers); weight-gradient tiles of row blocks 4w .. 4w+3
-// against all 16 column blocks, and their bias rows (a fragment of ones as
-// the MFMA's B operand).  Per step every wave issues 8 ring loads (three
-// steps ahead, after the step's first barrier) and 4 stores of D_{l-1}, and
+// 32) per workgroup of WV waves (8: two per SIMD, 256 registers each; 4:
+// one per SIMD).  Wave w owns RPW = 16 / WV row blocks RPW w ..: their data
+// gradient for both 16-query blocks of every step (W_l^T's fragments of
+// those rows in registers), their weight-gradient tiles against all 16
+// column blocks, and their bias rows (a fragment of ones as the MFMA's B
+// operand).  Per step every wave issues 32 / WV ring loads (three steps
+// ahead, after the step's first barrier) and 16 / WV stores of D_{l-1}, and
 // nothing else that counts in vmcnt, so the loads of a step are complete
 // once no more than the stores and loads issued after them remain.
-__global__ __launch_bounds__(256, 1) void k_tr_back(const uint16_t* __restrict__ Dl,
+template <int WV>
+__global__ __launch_bounds__(64 * WV, 1) void k_tr_back(const uint16_t* __restrict__ Dl,
                                                     const uint16_t* __restrict__ Aprev, int64_t CH, int l,
                                                     int in_dim, int NH, const bf16x8* __restrict__ packT,
                                                     uint16_t* __restrict__ Dprev, int64_t P,
                                                     float* __restrict__ partial) {
   using B = Back256;
   constexpr int W = B::W, KS = B::KS;
+  constexpr int RPW = B::RB / WV;    // row blocks per wave (data gradient, weight-gradient rows)
+  constexpr int H = RPW / 2;         // A_{l-1} pieces per query block (two row blocks each)
+  constexpr int LI = 16 / WV;        // ring load instructions per tensor and step
+  constexpr int KPW = KS / WV;       // D_l K steps a wave transposes
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   int otile = (int)B::ring_bytes();
   asm volatile("" : "+s"(otile));
@@ -645,8 +676,8 @@ __global__ __launch_bounds__(256, 1) void k_tr_back(const uint16_t* __restrict__
       const uint16_t* src = (t == 0 ? Dl : Aprev) + r0 * W;
       asm volatile("" : "+s"(src));
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int u0 = 64 * (4 * i + wave);               // wave-uniform first unit
+      for (int i = 0; i < LI; ++i) {
+        const int u0 = 64 * (WV * i + wave);              // wave-uniform first unit
         const int u = u0 + ln, qq = u >> 5, p = u & 31;
         __builtin_amdgcn_global_load_lds((const void*)(src + qq * W + 8 * (p ^ (qq & 7))),
                                          (__attribute__((address_space(3))) void*)(slot + t * B::SLOT + 8 * u0),
@@ -661,19 +692,19 @@ __global__ __launch_bounds__(256, 1) void k_tr_back(const uint16_t* __restrict__
 
   for (int st = 0; st < 3 && st < nst; ++st) load_step(st);
 
-  // W_l^T fragments of row blocks 4 wave .. + 3 (natural K order)
-  bf16x8 wt[4][KS];
+  // W_l^T fragments of the wave's row blocks (natural K order)
+  bf16x8 wt[RPW][KS];
   {
     const bf16x8* src = packT + (int64_t)(l - 1) * B::RB * KS * 64 + lane;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < RPW; ++u)
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) wt[u][ks] = src[((4 * wave + u) * KS + ks) * 64];
+      for (int ks = 0; ks < KS; ++ks) wt[u][ks] = src[((RPW * wave + u) * KS + ks) * 64];
   }
-  floatx4 dw[4][16], db[4];
+  floatx4 dw[RPW][16], db[RPW];
   const floatx4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
+  for (int a = 0; a < RPW; ++a) {
     db[a] = zero4;
 #pragma unroll
     for (int b = 0; b < 16; ++b) dw[a][b] = zero4;
@@ -694,39 +725,39 @@ __global__ __launch_bounds__(256, 1) void k_tr_back(const uint16_t* __restrict__
     const uint16_t* sD = ring + (st & 3) * 2 * B::SLOT;
     const uint16_t* sA = sD + B::SLOT;
     // this step's rows have landed once at most the stores of the three
-    // steps before (4 each) and the loads of the two after (8 each) are
+    // steps before (2H each) and the loads of the two after (2LI each) are
     // outstanding
-    wait_vm(4 * (st < 3 ? st : 3) + 8 * (nst - 1 - st < 2 ? nst - 1 - st : 2));
+    wait_vm(2 * H * (st < 3 ? st : 3) + 2 * LI * (nst - 1 - st < 2 ? nst - 1 - st : 2));
     lds_barrier();   // the step's rows are in LDS; every wave is done with step st - 1 (its slot, the tiles)
     if (st + 3 < nst) load_step(st + 3);
     asm volatile("" ::: "memory");   // the loads issue before this step's stores (the counts above)
-    // D_{l-1} = (W_l^T D_l) [A_{l-1} > 0], row blocks 4w .. 4w+3, both query
+    // D_{l-1} = (W_l^T D_l) [A_{l-1} > 0], the wave's row blocks, both query
     // blocks.  The chunks the wave reads for it also fill its share of the
-    // transposed tiles: D_l's K steps 2w, 2w+1 and the A_{l-1} mask pieces
-    // (K steps 2w, 2w+1 of the operand-order rows).
+    // transposed tiles: D_l's K steps KPW w .. and the A_{l-1} mask pieces
+    // (K steps H w .. of the operand-order rows).
     {
-      floatx4 acc[2][4];
+      floatx4 acc[2][RPW];
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[nb][u] = zero4;
+        for (int u = 0; u < RPW; ++u) acc[nb][u] = zero4;
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         const bf16x8 b0 = ring_chunk(sD, c, 4 * ks + grp), b1 = ring_chunk(sD, 16 + c, 4 * ks + grp);
-        if ((ks >> 1) == wave) {
+        if (ks / KPW == wave) {
           tile_store(sDT, b0, c, [&](int j) { return 32 * ks + 8 * grp + j; });
           tile_store(sDT, b1, 16 + c, [&](int j) { return 32 * ks + 8 * grp + j; });
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < RPW; ++u) {
           acc[0][u] = nb_mfma_bf16(wt[u][ks], b0, acc[0][u]);
           acc[1][u] = nb_mfma_bf16(wt[u][ks], b1, acc[1][u]);
         }
       }
       // stores: the lanes of rows g and g ^ 1 (same query) swap one row
       // block's values (v_permlane16_swap), so that every lane writes 16
-      // bytes: 8 consecutive neurons of row block 4w + 2h (even g) or
-      // 4w + 2h + 1 (odd g)
+      // bytes: 8 consecutive neurons of row block RPW w + 2h (even g) or
+      // RPW w + 2h + 1 (odd g)
       typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
       typedef __attribute__((address_space(1))) u32x4* gst_t;
       gst_t out = (gst_t)(Dprev + r0 * W);
@@ -736,9 +767,10 @@ __global__ __launch_bounds__(256, 1) void k_tr_back(const uint16_t* __restrict__
       for (int nb = 0; nb < 2; ++nb) {
         const int q = 16 * nb + c;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {   // row blocks 4w + 2h, 4w + 2h + 1: one 16-byte piece of A_{l-1}
-          const bf16x8 av = ring_chunk(sA, q, 4 * (2 * wave + h) + grp);
-          tile_store(sAT, av, q, [&](int j) { return 16 * (2 * (2 * wave + h) + j / 4) + 4 * grp + (j & 3); });
+        for (int h = 0; h < H; ++h) {   // row blocks RPW w + 2h, + 1: one 16-byte piece of A_{l-1}
+          const int kp = H * wave + h;
+          const bf16x8 av = ring_chunk(sA, q, 4 * kp + grp);
+          tile_store(sAT, av, q, [&](int j) { return 16 * (2 * kp + j / 4) + 4 * grp + (j & 3); });
           const nb_uint4 au = __builtin_bit_cast(nb_uint4, av);
           uint2 pk[2];
 #pragma unroll
@@ -751,7 +783,7 @@ __global__ __launch_bounds__(256, 1) void k_tr_back(const uint16_t* __restrict__
           }
           const auto sx = __builtin_amdgcn_permlane16_swap(pk[0].x, pk[1].x, false, false);
           const auto sy = __builtin_amdgcn_permlane16_swap(pk[0].y, pk[1].y, false, false);
-          const int mo = 4 * wave + 2 * h + (oddrow ? 1 : 0);
+          const int mo = RPW * wave + 2 * h + (oddrow ? 1 : 0);
           out[((int64_t)q * W + 16 * mo + 4 * (grp & ~1)) / 8] = u32x4{sx[0], sy[0], sx[1], sy[1]};
         }
       }
@@ -763,17 +795,17 @@ __global__ __launch_bounds__(256, 1) void k_tr_back(const uint16_t* __restrict__
       const int rd_off = c * 32 + ((grp ^ ((c >> 1) & 3)) << 3);   // row 16 b + c, chunk grp
       lop_t dt = (lop_t)(sDT + rd_off);
       lop_t at = (lop_t)(sAT + rd_off);
-      bf16x8 af[4];
+      bf16x8 af[RPW];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) af[a] = dt[(16 * (4 * wave + a)) * 32 / 8];
+      for (int a = 0; a < RPW; ++a) af[a] = dt[(16 * (RPW * wave + a)) * 32 / 8];
 #pragma unroll
       for (int b = 0; b < 16; ++b) {
         const bf16x8 bf = at[(16 * b) * 32 / 8];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) dw[a][b] = nb_mfma_bf16(af[a], bf, dw[a][b]);
+        for (int a = 0; a < RPW; ++a) dw[a][b] = nb_mfma_bf16(af[a], bf, dw[a][b]);
       }
 #pragma unroll
-      for (int a = 0; a < 4; ++a) db[a] = nb_mfma_bf16(af[a], ones, db[a]);
+      for (int a = 0; a < RPW; ++a) db[a] = nb_mfma_bf16(af[a], ones, db[a]);
     }
   }
 
@@ -782,18 +814,18 @@ __global__ __launch_bounds__(256, 1) void k_tr_back(const uint16_t* __restrict__
   float* out = partial + (int64_t)blockIdx.x * P;
   const int64_t wo = nb_w_off(l, in_dim, W);
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < RPW; ++a)
 #pragma unroll
     for (int b = 0; b < 16; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        out[wo + (int64_t)(16 * (4 * wave + a) + 4 * grp + r) * W + 16 * b + c] = dw[a][b][r];
+        out[wo + (int64_t)(16 * (RPW * wave + a) + 4 * grp + r) * W + 16 * b + c] = dw[a][b][r];
   if (c == 0) {
     const int64_t bo = nb_b_off(l, in_dim, W, NH);
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < RPW; ++a)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) out[bo + 16 * (4 * wave + a) + 4 * grp + r] = db[a][r];
+      for (int r = 0; r < 4; ++r) out[bo + 16 * (RPW * wave + a) + 4 * grp + r] = db[a][r];
   }
 }
 }  // namespace
@@ -809,8 +841,9 @@ nb_status bf16_back256(const Back256Job& J, hipStream_t s) {
     nb_set_error("backward layer kernel: chunk of %lld queries is not a multiple of 32", (long long)J.plan.chunk);
     return NB_ERR_UNSUPPORTED;
   }
-  NB_TRY(allow_lds(k_tr_back, Back256::lds_bytes()));
-  k_tr_back<<<(unsigned)J.plan.n_wg, Back256::THREADS, Back256::lds_bytes(), s>>>(
+  constexpr int WV = Back256::WAVES;
+  NB_TRY(allow_lds(k_tr_back<WV>, Back256::lds_bytes()));
+  k_tr_back<WV><<<(unsigned)J.plan.n_wg, 64 * WV, Back256::lds_bytes(), s>>>(
       J.Dl, J.Aprev, J.plan.chunk, J.l, J.in_dim, J.NH, J.packT, J.Dprev, J.P, J.partial);
   NB_LAUNCHED();
   return NB_OK;
