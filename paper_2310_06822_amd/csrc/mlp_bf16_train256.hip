@@ -317,27 +317,40 @@ __global__ __launch_bounds__(512, 1) void k_tr_stream(const float* __restrict__ 
       // D_{NH-1} rows of the chunk (padding rows included: dz = 0 there).
       // The output weights are read again through a fresh base (not held
       // from the logit's loop) and taken before the selects (no branches).
+      // Row blocks in pairs: the lanes of rows g and g ^ 1 (same query) swap
+      // one row block's values (v_permlane16_swap), so that every lane
+      // writes 16 bytes, 8 consecutive neurons of row block 2p (even g) or
+      // 2p + 1 (odd g).
       if (q0 + nb * 16 < cend) {
-        typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-        typedef __attribute__((address_space(1))) u32x2* gd_t;
+        typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+        typedef __attribute__((address_space(1))) u32x4* gd_t;
         gd_t out = (gd_t)(Dout + (q0 + nb * 16) * W);
         asm volatile("" : "+s"(out));
         typedef const __attribute__((address_space(3))) float* lds_f;
         lds_f wo2 = (lds_f)(swo + 4 * grp);
         asm volatile("" : "+v"(wo2));
+        const bool oddrow = grp & 1;
 #pragma unroll
-        for (int mo = 0; mo < RB; ++mo) {
-          float w4[4], d[4];
+        for (int pr = 0; pr < RB / 2; ++pr) {
+          uint2 pk[2];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) w4[r] = wo2[16 * mo + r];
-          asm volatile("" : "+v"(w4[0]), "+v"(w4[1]), "+v"(w4[2]), "+v"(w4[3]));
+          for (int e = 0; e < 2; ++e) {
+            const int mo = 2 * pr + e;
+            float w4[4], d[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const float a = mo < RA ? acc0[nb][mo][r] : acc1[nb][mo - RA][r];
-            d[r] = a > 0.0f ? dz * w4[r] : 0.0f;
+            for (int r = 0; r < 4; ++r) w4[r] = wo2[16 * mo + r];
+            asm volatile("" : "+v"(w4[0]), "+v"(w4[1]), "+v"(w4[2]), "+v"(w4[3]));
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const float a = mo < RA ? acc0[nb][mo][r] : acc1[nb][mo - RA][r];
+              d[r] = a > 0.0f ? dz * w4[r] : 0.0f;
+            }
+            pk[e] = pack4(d[0], d[1], d[2], d[3]);
           }
-          const uint2 pk = pack4(d[0], d[1], d[2], d[3]);
-          out[(c * W + 16 * mo + 4 * grp) / 4] = u32x2{pk.x, pk.y};
+          const auto sx = __builtin_amdgcn_permlane16_swap(pk[0].x, pk[1].x, false, false);
+          const auto sy = __builtin_amdgcn_permlane16_swap(pk[0].y, pk[1].y, false, false);
+          const int mo = 2 * pr + (oddrow ? 1 : 0);
+          out[(c * W + 16 * mo + 4 * (grp & ~1)) / 8] = u32x4{sx[0], sy[0], sx[1], sy[1]};
         }
       }
       // output-weight terms dz a, summed over the block's 16 queries
