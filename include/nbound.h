@@ -394,9 +394,14 @@ nb_status nb_group_query_exact(const nb_group* g, int kind, const float* q, cons
 nb_status nb_group_forward(const nb_group* g, const float* q, const int64_t* qoff, int64_t n, float eps,
                            float* logits, uint8_t* h, const uint8_t* g_exact, uint64_t* counts, void* stream);
 /* Tile-shape variants of the grouped forward (threads per workgroup and
- * query blocks per wave); all give identical results.  Default 0. */
+ * query blocks per wave); all give identical results.  The forward runs one
+ * launch per width class, each with its own variant (default 0):
+ * nb_group_set_variant sets every class's, nb_group_set_width_variant the
+ * variant of the objects of one width (32, 64 or 128; NB_ERR_INVALID_ARG for
+ * another width or a variant outside 0 .. count-1). */
 nb_status nb_group_num_variants(const nb_group* g, int* count);
 nb_status nb_group_set_variant(nb_group* g, int variant);
+nb_status nb_group_set_width_variant(nb_group* g, int width, int variant);
 /* One training step of Alg. 1 for every object: per_obj regions of `kind`
  * per object (nb_sample_queries with n = n_obj * per_obj; object o takes rows
  * o*per_obj ..), labelled on the object's grid, Eq. 1 with FN weight alpha

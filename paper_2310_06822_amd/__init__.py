@@ -454,6 +454,10 @@ def nb_group_set_variant(g, variant: int):
     _check(lib().nb_group_set_variant(g, int(variant)))
 
 
+def nb_group_set_width_variant(g, width: int, variant: int):
+    _check(lib().nb_group_set_width_variant(g, int(width), int(variant)))
+
+
 def nb_group_train_step(g, n_obj: int, kind: int, seed: int, step: int, per_obj: int, alpha: float,
                         beta: float = 1.0, lr: float = 1e-3, loss=None, counts=None, alpha_obj=None, lr_obj=None,
                         stream=None):

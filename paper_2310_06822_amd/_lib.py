@@ -70,6 +70,7 @@ SIGNATURES = {
     "nb_group_forward": (i32, [vp, vp, vp, i64, f32, vp, vp, vp, vp, vp]),
     "nb_group_num_variants": (i32, [vp, C.POINTER(C.c_int)]),
     "nb_group_set_variant": (i32, [vp, C.c_int]),
+    "nb_group_set_width_variant": (i32, [vp, C.c_int, C.c_int]),
     "nb_group_train_step": (i32, [vp, C.c_int, u64, u64, i64, f32, vp, f32, f32, vp, vp, vp, vp]),
     "nb_bound_sync": (i32, [vp, vp]),
     "nb_group_sync": (i32, [vp, vp]),

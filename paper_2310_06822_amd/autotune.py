@@ -56,37 +56,56 @@ def report() -> dict:
     return {str(k): {"variant": v, "ms": ms} for k, (v, ms) in _CACHE.items()}
 
 
+def _time_group(group, q: torch.Tensor, qoff: torch.Tensor, h: torch.Tensor, reps: int) -> float:
+    from . import nb_group_forward
+    nb_group_forward(group.handle, group.n_obj, group.in_dim, q, qoff, h=h)   # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        nb_group_forward(group.handle, group.n_obj, group.in_dim, q, qoff, h=h)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def time_group_variants(group, q: torch.Tensor, qoff: torch.Tensor, reps: int = 5) -> list:
-    """Mean milliseconds per grouped forward (decision only) for every tile shape."""
-    from . import nb_group_forward, nb_group_num_variants, nb_group_set_variant
+    """Mean milliseconds per grouped forward (decision only) for every tile
+    shape, the same shape for every width class."""
+    from . import nb_group_num_variants, nb_group_set_variant
     h = torch.empty(q.shape[0], dtype=torch.uint8, device=q.device)
     out = []
     for v in range(nb_group_num_variants(group.handle)):
         nb_group_set_variant(group.handle, v)
-        nb_group_forward(group.handle, group.n_obj, group.in_dim, q, qoff, h=h)   # warm-up
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            nb_group_forward(group.handle, group.n_obj, group.in_dim, q, qoff, h=h)
-        e1.record()
-        torch.cuda.synchronize()
-        out.append(e0.elapsed_time(e1) / reps)
+        out.append(_time_group(group, q, qoff, h, reps))
     return out
 
 
-def tune_group(group, q: torch.Tensor, qoff: torch.Tensor, reps: int = 5) -> int:
-    """Select the fastest grouped-forward tile shape for this group and query
-    layout (keyed by the width mix, depth and batch size class); returns it."""
-    from . import nb_group_set_variant
+def tune_group(group, q: torch.Tensor, qoff: torch.Tensor, reps: int = 5) -> dict:
+    """Select the fastest grouped-forward tile shape of every width class for
+    this group and query layout (keyed by the width mix, depth and batch size
+    class); returns {width: variant}.  The classes run as separate launches,
+    so their times add and each class is tuned with the others held fixed."""
+    from . import nb_group_num_variants, nb_group_set_width_variant
     props = torch.cuda.get_device_properties(torch.cuda.current_device())
     k = ("group", group.in_dim, group.n_hidden, tuple(sorted(group.widths)), max(q.shape[0], 1).bit_length(),
          props.name)
     if k not in _CACHE:
-        ms = time_group_variants(group, q, qoff, reps)
-        _CACHE[k] = (min(range(len(ms)), key=ms.__getitem__), ms)
-    v = _CACHE[k][0]
-    nb_group_set_variant(group.handle, v)
-    return v
+        h = torch.empty(q.shape[0], dtype=torch.uint8, device=q.device)
+        nv = nb_group_num_variants(group.handle)
+        best, ms_all = {}, {}
+        for w in sorted(set(group.widths)):
+            ms = []
+            for v in range(nv):
+                nb_group_set_width_variant(group.handle, w, v)
+                ms.append(_time_group(group, q, qoff, h, reps))
+            best[w] = min(range(nv), key=ms.__getitem__)
+            ms_all[w] = ms
+            nb_group_set_width_variant(group.handle, w, best[w])
+        _CACHE[k] = (best, ms_all)
+    best = _CACHE[k][0]
+    for w, v in best.items():
+        nb_group_set_width_variant(group.handle, w, v)
+    return dict(best)
 
 
 def tune_hierarchy(hier, q: torch.Tensor, reps: int = 3) -> int:

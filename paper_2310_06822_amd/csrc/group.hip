@@ -1,16 +1,17 @@
-// Many per-object bounds in one launch.
+// Many per-object bounds queried and trained together.
 //
 // The paper trains one bound per object (Sec. 3.4, "Training": no
 // generalisation across objects).  A group holds n_obj bfloat16 bounds of a
 // common depth and input size but their own widths (32, 64 or 128), each
 // with its own voxel grid.  Queries arrive grouped by object (CSR offsets).
 //
-// Forward: one persistent launch.  A single-block planner lays the work out
-// as tiles of 128 queries, objects ordered by decreasing width, and gives
-// each workgroup a contiguous run of tiles of equal estimated cost
-// (proportional to width^2 per tile); a workgroup reloads weights into LDS
-// only when its run crosses into the next object, so every object's weights
-// are read about once per workgroup that touches it.
+// Forward: one persistent launch per width class, each kernel compiled for
+// its width so that its registers and LDS (not the widest class's) set its
+// occupancy.  A planner lays every class's work out as tiles of queries of
+// one object, objects ordered by decreasing width, and gives each workgroup
+// of the class an equal contiguous run of tiles; a workgroup reloads weights
+// into LDS only when its run crosses into the next object, so every object's
+// weights are read about once per workgroup that touches it.
 #include <algorithm>
 #include <numeric>
 #include <vector>
@@ -23,121 +24,83 @@
 
 namespace {
 
-// Forward tile shapes (the variants the tuner picks from): threads per
-// workgroup and 16-query blocks per wave; a work item (tile) is
-// threads / 64 * blocks * 16 queries of one object.
+// Forward tile shapes (the variants the tuner picks from, per width class):
+// threads per workgroup and 16-query blocks per wave; a work item (tile) is
+// threads / 64 * blocks * 16 queries of one object.  Width 128 takes at most
+// two blocks per wave (four would not fit its accumulators in registers).
 struct GroupShape {
-  int threads, blocks, wg_per_cu;
+  int threads, blocks;
 };
-constexpr GroupShape kGroupShapes[] = {{256, 2, 4}, {512, 2, 2}, {256, 1, 4}, {512, 1, 2},
-                                       {1024, 1, 1}, {768, 1, 2}};
+constexpr GroupShape kGroupShapes[] = {{256, 2}, {512, 2}, {256, 1}, {512, 1},
+                                       {1024, 1}, {768, 1}, {256, 4}, {512, 4}};
 constexpr int kGroupVariants = sizeof(kGroupShapes) / sizeof(kGroupShapes[0]);
+__host__ __device__ constexpr int group_blocks(int W, int blocks) { return W >= 128 && blocks > 2 ? 2 : blocks; }
 
 // Fragments of an object's forward pack held in LDS: the first layer's first
-// step and the hidden layers (the second first-layer step, used for input
-// dimensions above 4, is read from global memory).
-__host__ __device__ inline int frags_fwd(int W, int NH) { return W / 16 + (NH - 1) * (W / 16) * (W / 32); }
+// step and the hidden layers, then (widths 32 and 64) the second first-layer
+// step used for input dimensions above 4; width 128 reads that step from
+// global memory, which keeps two of its workgroups within one CU's LDS.
+__host__ __device__ constexpr int frags_fwd(int W, int NH) { return W / 16 + (NH - 1) * (W / 16) * (W / 32); }
+__host__ __device__ constexpr bool ext_in_lds(int W) { return W <= 64; }
+__host__ __device__ constexpr int frags_lds(int W, int NH) { return frags_fwd(W, NH) + (ext_in_lds(W) ? W / 16 : 0); }
+__host__ __device__ constexpr size_t group_lds_bytes(int W, int NH) {
+  return (size_t)frags_lds(W, NH) * 64 * 16 + (size_t)(NH * W + W + 1) * 4;
+}
 
-// Work plan: item_off[p] = first tile of the p-th object in width order;
-// wg_first[w] = first tile of workgroup w (wg_first[G] = total tiles).  One
-// block of 256 threads: prefix sums over objects (tiles and cost) by a block
-// scan, then every thread places its workgroup boundaries by binary search,
-// cutting the tile sequence at equal shares of the total cost.
-constexpr int kMaxGroup = 4096;
+// One width class of a grouped forward: the objects perm[p_lo .. p_lo +
+// n_obj) (all of one width), G workgroups, tiles of tile_q queries; its plan
+// goes to item_off[item_base ..] and wg_first[wg_base ..].
+struct ClassPlan {
+  int p_lo, n_obj, G, tile_q, item_base, wg_base;
+};
+struct GroupPlan {
+  ClassPlan c[3];
+};
 
-// Relative time of one tile by width: measured per-query forward times of
-// widths 32, 64 and 128 stand about 1 : 1.3 : 2.5 (the matrix work grows as
-// W^2, the per-query input, activation and output work does not).
-__device__ inline double tile_cost(int W) { return (double)W * W + 8192.0; }
-
-__global__ __launch_bounds__(256) void k_group_plan(const int64_t* __restrict__ qoff, int64_t n, int tile_q, int n_obj,
-                                                    const int* __restrict__ perm, const int* __restrict__ widths,
-                                                    int G, int64_t* __restrict__ item_off,
+// Work plan, one block of 256 threads per width class (blockIdx.x):
+// item_off[p] = first tile of the class's p-th object, item_off[n_obj] = the
+// class's tiles; wg_first[w] = first tile of workgroup w (wg_first[G] = all
+// tiles).  Every tile of a class costs the same, so the workgroups take
+// equal shares of the tile sequence: a block scan of the objects' tile
+// counts, then one division per workgroup boundary.
+__global__ __launch_bounds__(256) void k_group_plan(const int64_t* __restrict__ qoff, int64_t n, GroupPlan plan,
+                                                    const int* __restrict__ perm, int64_t* __restrict__ item_off,
                                                     int64_t* __restrict__ wg_first) {
-  __shared__ double cum[kMaxGroup + 1];   // cost of the tiles before object p (width order)
-  __shared__ int64_t sitem[kMaxGroup + 1];
-  __shared__ double scost[256];
   __shared__ int64_t stile[256];
+  const ClassPlan cp = plan.c[blockIdx.x];
+  const int* pm = perm + cp.p_lo;
+  int64_t* io = item_off + cp.item_base;
+  int64_t* wf = wg_first + cp.wg_base;
+  const int t = threadIdx.x, n_obj = cp.n_obj;
   // each thread takes a contiguous segment of objects; block scan of the
   // segment sums; then every thread writes its segment's prefixes
-  const int t = threadIdx.x;
   const int seg = (n_obj + 255) / 256;
   const int p0 = min(n_obj, t * seg), p1 = min(n_obj, p0 + seg);
   auto tiles_of = [&](int p) -> int64_t {
-    const int o = perm[p];
+    const int o = pm[p];
     const int64_t a = qoff[o], b = qoff[o + 1];   // rows outside [0, n): no tiles
     const int64_t nq = (a >= 0 && b <= n && b > a) ? b - a : 0;
-    return (nq + tile_q - 1) / tile_q;
+    return (nq + cp.tile_q - 1) / cp.tile_q;
   };
-  double c_sum = 0.0;
   int64_t t_sum = 0;
-  for (int p = p0; p < p1; ++p) {
-    const int64_t tl = tiles_of(p);
-    t_sum += tl;
-    c_sum += (double)tl * tile_cost(widths[perm[p]]);
-  }
-  scost[t] = c_sum;
+  for (int p = p0; p < p1; ++p) t_sum += tiles_of(p);
   stile[t] = t_sum;
   __syncthreads();
   for (int d = 1; d < 256; d <<= 1) {   // inclusive scan
-    const double cv = t >= d ? scost[t - d] : 0.0;
     const int64_t tv = t >= d ? stile[t - d] : 0;
     __syncthreads();
-    scost[t] += cv;
     stile[t] += tv;
     __syncthreads();
   }
-  double c_acc = t > 0 ? scost[t - 1] : 0.0;
   int64_t t_acc = t > 0 ? stile[t - 1] : 0;
   for (int p = p0; p < p1; ++p) {
-    cum[p] = c_acc;
-    sitem[p] = t_acc;
-    const int64_t tl = tiles_of(p);
-    t_acc += tl;
-    c_acc += (double)tl * tile_cost(widths[perm[p]]);
+    io[p] = t_acc;
+    t_acc += tiles_of(p);
   }
-  if (t == 255) {
-    cum[n_obj] = scost[255];
-    sitem[n_obj] = stile[255];
-  }
-  __syncthreads();
-  for (int p = threadIdx.x; p <= n_obj; p += blockDim.x) item_off[p] = sitem[p];
-  const double total = cum[n_obj];
-  const int64_t n_tiles = sitem[n_obj];
-  for (int w = threadIdx.x; w <= G; w += blockDim.x) {
-    int64_t t;
-    if (w == 0) {
-      t = 0;
-    } else if (w == G) {
-      t = n_tiles;
-    } else {
-      // smallest t with cost(tiles [0, t)) >= target
-      const double target = total * (double)w / (double)G;
-      int lo = 0, hi = n_obj;   // last p with cum[p] < target (cum[0] = 0)
-      if (target <= 0.0) {
-        t = 0;
-      } else {
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) / 2;
-          if (cum[mid] < target) lo = mid; else hi = mid;
-        }
-        const int o = perm[lo];
-        const double cost = tile_cost(widths[o]);
-        const int64_t k = (int64_t)ceil((target - cum[lo]) / cost);
-        t = sitem[lo] + k;
-        if (t > sitem[lo + 1]) t = sitem[lo + 1];
-      }
-    }
-    wg_first[w] = t;
-  }
+  const int64_t n_tiles = stile[255];
+  if (t == 0) io[n_obj] = n_tiles;
+  for (int w = t; w <= cp.G; w += 256) wf[w] = n_tiles * w / cp.G;
 }
-
-template <int NH>
-struct GroupLds {
-  static constexpr size_t bytes() {
-    return (size_t)frags_fwd(128, NH) * 64 * 16 + (size_t)(NH * 128 + 129) * 4;
-  }
-};
 
 // Adds a wave's confusion counts for object o to counts[o] and clears them.
 __device__ __forceinline__ void flush_counts(unsigned long long* __restrict__ counts, int o, unsigned (&cnt)[4]) {
@@ -149,21 +112,26 @@ __device__ __forceinline__ void flush_counts(unsigned long long* __restrict__ co
   }
 }
 
-template <int NH, int THREADS, int NB>
+// Forward + decision of one width class: a persistent workgroup runs its
+// share of the class's tiles in order, reloading weights into LDS when the
+// run crosses into the next object (so every object's weights are read
+// about once per workgroup that touches it).  perm, item_off and wg_first
+// are the class's.
+template <int W, int NH, int THREADS, int NB>
 __global__ __launch_bounds__(THREADS) void k_group_fwd(
     const float* __restrict__ q, const int64_t* __restrict__ qoff, int n_obj, int in_dim,
-    const int* __restrict__ perm, const int* __restrict__ widths, const int64_t* __restrict__ poff,
-    const int64_t* __restrict__ pkoff, const float* __restrict__ theta, const bf16x8* __restrict__ pack,
-    const int64_t* __restrict__ item_off, const int64_t* __restrict__ wg_first, float tau,
-    float* __restrict__ logits, uint8_t* __restrict__ hout, const uint8_t* __restrict__ g,
-    unsigned long long* __restrict__ counts) {
+    const int* __restrict__ perm, const int64_t* __restrict__ poff, const int64_t* __restrict__ pkoff,
+    const float* __restrict__ theta, const bf16x8* __restrict__ pack, const int64_t* __restrict__ item_off,
+    const int64_t* __restrict__ wg_first, float tau, float* __restrict__ logits, uint8_t* __restrict__ hout,
+    const uint8_t* __restrict__ g, unsigned long long* __restrict__ counts) {
   constexpr int TILE = THREADS / 64 * NB * 16;
+  constexpr int NF = frags_fwd(W, NH), NFL = frags_lds(W, NH);
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   bf16x8* swt = reinterpret_cast<bf16x8*>(smem_raw);
-  float* sbias = reinterpret_cast<float*>(smem_raw + (size_t)frags_fwd(128, NH) * 64 * 16);
+  float* sbias = reinterpret_cast<float*>(smem_raw + (size_t)NFL * 64 * 16);
   const int64_t s = wg_first[blockIdx.x], e = wg_first[blockIdx.x + 1];
   if (s >= e) return;
-  // object (in width order) of the first tile
+  // object (in the class's order) of the first tile
   int p = 0;
   {
     int lo = 0, hi = n_obj;   // last p with item_off[p] <= s
@@ -173,8 +141,9 @@ __global__ __launch_bounds__(THREADS) void k_group_fwd(
     }
     p = lo;
   }
-  int cur = -1, W = 0;
-  const bf16x8* sext = pack;   // the current object's second first-layer step
+  int cur = -1;
+  const bool wide = in_dim > 4;
+  const bf16x8* sext = ext_in_lds(W) ? swt + NF * 64 : pack;   // the second first-layer step
   unsigned cnt[4] = {0u, 0u, 0u, 0u};
   const int wave = threadIdx.x >> 6, c = threadIdx.x & 15;
   // software pipeline: the next tile's inputs load while this tile computes
@@ -187,11 +156,9 @@ __global__ __launch_bounds__(THREADS) void k_group_fwd(
     if (o != cur) {
       flush_counts(counts, cur, cnt);
       __syncthreads();
-      W = widths[o];
-      const int nf = frags_fwd(W, NH);
       const bf16x8* src = pack + pkoff[o];
-      sext = src + nf * 64;
-      for (int i = threadIdx.x; i < nf * 64; i += THREADS) swt[i] = src[i];
+      if (!ext_in_lds(W)) sext = src + NF * 64;
+      for (int i = threadIdx.x; i < NFL * 64; i += THREADS) swt[i] = src[i];
       const float* th = theta + poff[o];
       for (int i = threadIdx.x; i < NH * W; i += THREADS) sbias[i] = th[nb_b_off(i / W, in_dim, W, NH) + i % W];
       for (int i = threadIdx.x; i < W + 1; i += THREADS) sbias[NH * W + i] = th[nb_w_off(NH, in_dim, W) + i];
@@ -207,12 +174,7 @@ __global__ __launch_bounds__(THREADS) void k_group_fwd(
       n_endn = qoff[on + 1];
       load_raw<NB>(q, n_endn, in_dim, q0n, c, xn);
     }
-    if (W == 32)
-      bf16_fwd_tile_x<32, NH, NB>(swt, sbias, xr, in_dim > 4, sext, n_end, q0, tau, logits, hout, g, counts, cnt);
-    else if (W == 64)
-      bf16_fwd_tile_x<64, NH, NB>(swt, sbias, xr, in_dim > 4, sext, n_end, q0, tau, logits, hout, g, counts, cnt);
-    else
-      bf16_fwd_tile_x<128, NH, NB>(swt, sbias, xr, in_dim > 4, sext, n_end, q0, tau, logits, hout, g, counts, cnt);
+    bf16_fwd_tile_x<W, NH, NB>(swt, sbias, xr, wide, sext, n_end, q0, tau, logits, hout, g, counts, cnt);
     if (it + 1 < e) {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
@@ -386,80 +348,132 @@ int group_variants() { return kGroupVariants; }
 
 namespace {
 
-// Workgroups of a persistent launch: as many as fit on the chip at once
-// (LDS holds the widest object's weights).
-int group_wgs(const GroupShape& sh, size_t lds) {
-  const int fit = std::max(1, (int)((160 * 1024) / lds));
-  return std::max(1, std::min(std::min(sh.wg_per_cu, fit) * nb_cu_count(), 1 << 14));
-}
+// Arguments of one width class's forward launch.
+struct ClassLaunch {
+  const nb_group* gr;
+  const float* q;
+  const int64_t* qoff;
+  float tau;
+  float* logits;
+  uint8_t* h;
+  const uint8_t* g;
+  unsigned long long* counts;
+  hipStream_t s;
+  ClassPlan cp;
+};
 
-size_t group_lds(int NH) {
-  switch (NH) {
-    case 2: return GroupLds<2>::bytes();
-    case 3: return GroupLds<3>::bytes();
-    default: return GroupLds<4>::bytes();
-  }
-}
-
-template <int NH, int THREADS, int NB>
-nb_status group_fwd_launch(const nb_group* gr, const float* q, const int64_t* qoff, int G, float tau,
-                           float* logits, uint8_t* h, const uint8_t* g, unsigned long long* counts, hipStream_t s) {
-  const size_t lds = GroupLds<NH>::bytes();
-  static bool attr[64] = {false};
+// With launch false: sets the class's workgroup count (as many as are
+// resident on the device at once for this kernel's registers and LDS, from
+// the occupancy calculator, capped at the plan's capacity) and tile size.
+// With launch true: launches the class's forward with that plan.
+template <int W, int NH, int THREADS, int NB>
+nb_status class_fwd(bool launch, ClassLaunch& a) {
+  constexpr size_t lds = group_lds_bytes(W, NH);
+  static_assert(lds <= 160 * 1024, "grouped forward LDS");
+  const void* fn = reinterpret_cast<const void*>(k_group_fwd<W, NH, THREADS, NB>);
+  static int resident[64] = {0};
   int dev = 0;
   NB_HIP(hipGetDevice(&dev));
-  if (dev >= 0 && dev < 64 && !attr[dev]) {
-    NB_HIP(hipFuncSetAttribute((const void*)k_group_fwd<NH, THREADS, NB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds));
-    attr[dev] = true;
+  NB_REQUIRE(dev >= 0 && dev < 64, "device %d out of range", dev);
+  if (!resident[dev]) {
+    NB_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 0;
+    NB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, THREADS, lds));
+    resident[dev] = std::max(1, per_cu) * nb_cu_count();
   }
-  k_group_fwd<NH, THREADS, NB><<<G, THREADS, lds, s>>>(
-      q, qoff, gr->n_obj, gr->in_dim, gr->d_perm, gr->d_widths, gr->d_poff, gr->d_pkoff, gr->theta,
-      reinterpret_cast<const bf16x8*>(gr->pack16), gr->d_item_off, gr->d_wg_first, tau, logits, h, g, counts);
+  if (!launch) {
+    a.cp.G = std::max(1, std::min(resident[dev], a.gr->n_wg_cap));
+    a.cp.tile_q = THREADS / 64 * NB * 16;
+    return NB_OK;
+  }
+  const nb_group* gr = a.gr;
+  k_group_fwd<W, NH, THREADS, NB><<<a.cp.G, THREADS, lds, a.s>>>(
+      a.q, a.qoff, a.cp.n_obj, gr->in_dim, gr->d_perm + a.cp.p_lo, gr->d_poff, gr->d_pkoff, gr->theta,
+      reinterpret_cast<const bf16x8*>(gr->pack16), gr->d_item_off + a.cp.item_base, gr->d_wg_first + a.cp.wg_base,
+      a.tau, a.logits, a.h, a.g, a.counts);
   NB_LAUNCHED();
   return NB_OK;
 }
 
-template <int NH>
-nb_status group_fwd_nh(const nb_group* gr, int variant, const float* q, const int64_t* qoff, int G, float tau,
-                       float* logits, uint8_t* h, const uint8_t* g, unsigned long long* counts, hipStream_t s) {
+template <int W, int NH>
+nb_status class_fwd_v(int variant, bool launch, ClassLaunch& a) {
   switch (variant) {
-    case 0: return group_fwd_launch<NH, 256, 2>(gr, q, qoff, G, tau, logits, h, g, counts, s);
-    case 1: return group_fwd_launch<NH, 512, 2>(gr, q, qoff, G, tau, logits, h, g, counts, s);
-    case 2: return group_fwd_launch<NH, 256, 1>(gr, q, qoff, G, tau, logits, h, g, counts, s);
-    case 3: return group_fwd_launch<NH, 512, 1>(gr, q, qoff, G, tau, logits, h, g, counts, s);
-    case 4: return group_fwd_launch<NH, 1024, 1>(gr, q, qoff, G, tau, logits, h, g, counts, s);
-    case 5: return group_fwd_launch<NH, 768, 1>(gr, q, qoff, G, tau, logits, h, g, counts, s);
+    case 0: return class_fwd<W, NH, 256, group_blocks(W, 2)>(launch, a);
+    case 1: return class_fwd<W, NH, 512, group_blocks(W, 2)>(launch, a);
+    case 2: return class_fwd<W, NH, 256, 1>(launch, a);
+    case 3: return class_fwd<W, NH, 512, 1>(launch, a);
+    case 4: return class_fwd<W, NH, 1024, 1>(launch, a);
+    case 5: return class_fwd<W, NH, 768, 1>(launch, a);
+    case 6: return class_fwd<W, NH, 256, group_blocks(W, 4)>(launch, a);
+    case 7: return class_fwd<W, NH, 512, group_blocks(W, 4)>(launch, a);
     default: break;
   }
   nb_set_error("grouped forward variant %d out of range", variant);
   return NB_ERR_INVALID_ARG;
 }
 
-}  // namespace
-
-nb_status group_forward(const nb_group* gr, const float* q, const int64_t* qoff, int64_t n, float tau,
-                        float* logits, uint8_t* h, const uint8_t* g, unsigned long long* counts, hipStream_t s) {
-  const int v = gr->variant;
-  if (v < 0 || v >= kGroupVariants) {
-    nb_set_error("grouped forward variant %d out of range", v);
-    return NB_ERR_INVALID_ARG;
+template <int NH>
+nb_status class_fwd_w(int W, int variant, bool launch, ClassLaunch& a) {
+  switch (W) {
+    case 32: return class_fwd_v<32, NH>(variant, launch, a);
+    case 64: return class_fwd_v<64, NH>(variant, launch, a);
+    case 128: return class_fwd_v<128, NH>(variant, launch, a);
+    default: break;
   }
-  const GroupShape sh = kGroupShapes[v];
-  const int G = std::min(group_wgs(sh, group_lds(gr->n_hidden)), gr->n_wg_cap);
-  const int tile_q = sh.threads / 64 * sh.blocks * 16;
-  if (counts) NB_TRY(launch_zero_u64(counts, 4 * gr->n_obj, s));
-  k_group_plan<<<1, 256, 0, s>>>(qoff, n, tile_q, gr->n_obj, gr->d_perm, gr->d_widths, G, gr->d_item_off,
-                                 gr->d_wg_first);
-  NB_LAUNCHED();
-  switch (gr->n_hidden) {
-    case 2: return group_fwd_nh<2>(gr, v, q, qoff, G, tau, logits, h, g, counts, s);
-    case 3: return group_fwd_nh<3>(gr, v, q, qoff, G, tau, logits, h, g, counts, s);
-    case 4: return group_fwd_nh<4>(gr, v, q, qoff, G, tau, logits, h, g, counts, s);
+  nb_set_error("grouped forward width %d not supported", W);
+  return NB_ERR_UNSUPPORTED;
+}
+
+nb_status class_fwd_any(int NH, int W, int variant, bool launch, ClassLaunch& a) {
+  switch (NH) {
+    case 2: return class_fwd_w<2>(W, variant, launch, a);
+    case 3: return class_fwd_w<3>(W, variant, launch, a);
+    case 4: return class_fwd_w<4>(W, variant, launch, a);
     default: break;
   }
   nb_set_error("grouped forward supports 2..4 hidden layers");
   return NB_ERR_UNSUPPORTED;
+}
+
+}  // namespace
+
+// One persistent launch per width class (widths 128, 64, 32: the order of
+// d_perm), each kernel compiled for its own width, so that a narrow class
+// runs at the occupancy its own registers and LDS allow; one planner launch
+// lays out all classes first.
+nb_status group_forward(const nb_group* gr, const float* q, const int64_t* qoff, int64_t n, float tau,
+                        float* logits, uint8_t* h, const uint8_t* g, unsigned long long* counts, hipStream_t s) {
+  ClassLaunch a{gr, q, qoff, tau, logits, h, g, counts, s, {}};
+  GroupPlan plan{};
+  int nc = 0, widths[3] = {0, 0, 0}, variants[3] = {0, 0, 0};
+  int p_lo = 0, item_base = 0, wg_base = 0;
+  for (int c = 2; c >= 0; --c) {
+    const int cnt = gr->class_all[c];
+    if (cnt == 0) continue;
+    const int v = gr->class_variant[c];
+    if (v < 0 || v >= kGroupVariants) {
+      nb_set_error("grouped forward variant %d out of range", v);
+      return NB_ERR_INVALID_ARG;
+    }
+    a.cp = ClassPlan{p_lo, cnt, 0, 0, item_base, wg_base};
+    NB_TRY(class_fwd_any(gr->n_hidden, 32 << c, v, false, a));
+    plan.c[nc] = a.cp;
+    widths[nc] = 32 << c;
+    variants[nc] = v;
+    ++nc;
+    p_lo += cnt;
+    item_base += cnt + 1;
+    wg_base += a.cp.G + 1;
+  }
+  NB_REQUIRE(p_lo == gr->n_obj, "group widths must be 32, 64 or 128");
+  if (counts) NB_TRY(launch_zero_u64(counts, 4 * gr->n_obj, s));
+  k_group_plan<<<nc, 256, 0, s>>>(qoff, n, plan, gr->d_perm, gr->d_item_off, gr->d_wg_first);
+  NB_LAUNCHED();
+  for (int i = 0; i < nc; ++i) {
+    a.cp = plan.c[i];
+    NB_TRY(class_fwd_any(gr->n_hidden, widths[i], variants[i], true, a));
+  }
+  return NB_OK;
 }
 
 nb_status group_exact(const nb_group* gr, int kind, const float* q, const int64_t* qoff, int64_t n, uint8_t* g,

@@ -82,7 +82,7 @@ nb_status nb_group_create(int n_obj, int in_dim, const int* widths_host, int n_h
                           nb_group** out) {
   NB_REQUIRE(out && widths_host, "NULL argument");
   *out = nullptr;
-  NB_REQUIRE(n_obj >= 1 && n_obj <= 4096, "n_obj must be in 1..4096");   // the planner holds 4096 objects
+  NB_REQUIRE(n_obj >= 1 && n_obj <= 4096, "n_obj must be in 1..4096");
   NB_REQUIRE(in_dim >= 1 && in_dim <= 8, "in_dim must be in 1..8");
   NB_REQUIRE(n_hidden >= 2 && n_hidden <= 4, "grouped bounds take 2..4 hidden layers");
   NB_REQUIRE(precision == NB_BF16, "grouped bounds are bfloat16");
@@ -125,7 +125,7 @@ nb_status nb_group_create(int n_obj, int in_dim, const int* widths_host, int n_h
     g->class_all[c] = (int)g->classes[c].size();
     cls.insert(cls.end(), g->classes[c].begin(), g->classes[c].end());
   }
-  g->n_wg_cap = std::max(1, std::min(4 * nb_cu_count(), 1 << 14));
+  g->n_wg_cap = std::max(1, std::min(8 * nb_cu_count(), 1 << 14));
   nb_status st = upload(&g->d_widths, g->widths);
   if (st == NB_OK) st = upload(&g->d_poff, g->poff);
   if (st == NB_OK) st = upload(&g->d_pkoff, g->pkoff);
@@ -139,8 +139,8 @@ nb_status nb_group_create(int n_obj, int in_dim, const int* widths_host, int n_h
   if (st == NB_OK) st = alloc_n(&g->v, (size_t)g->n_params);
   if (st == NB_OK) st = alloc_n(&g->pack16, (size_t)g->pack_elems);
   if (st == NB_OK) st = alloc_n(&g->pack16t, (size_t)g->packt_elems);
-  if (st == NB_OK) st = alloc_n(&g->d_item_off, (size_t)n_obj + 1);
-  if (st == NB_OK) st = alloc_n(&g->d_wg_first, (size_t)g->n_wg_cap + 1);
+  if (st == NB_OK) st = alloc_n(&g->d_item_off, (size_t)n_obj + 3);
+  if (st == NB_OK) st = alloc_n(&g->d_wg_first, 3 * ((size_t)g->n_wg_cap + 1));
   if (st == NB_OK) st = alloc_n(&g->ray_t, 256);
   if (st == NB_OK) {
     float t[256];
@@ -275,7 +275,16 @@ nb_status nb_group_set_variant(nb_group* g, int variant) {
   NB_REQUIRE(g, "group is NULL");
   NB_REQUIRE(variant >= 0 && variant < group_variants(), "variant %d out of range 0..%d", variant,
              group_variants() - 1);
-  g->variant = variant;
+  for (int c = 0; c < 3; ++c) g->class_variant[c] = variant;
+  return NB_OK;
+}
+
+nb_status nb_group_set_width_variant(nb_group* g, int width, int variant) {
+  NB_REQUIRE(g, "group is NULL");
+  NB_REQUIRE(width == 32 || width == 64 || width == 128, "width must be 32, 64 or 128");
+  NB_REQUIRE(variant >= 0 && variant < group_variants(), "variant %d out of range 0..%d", variant,
+             group_variants() - 1);
+  g->class_variant[width == 32 ? 0 : width == 64 ? 1 : 2] = variant;
   return NB_OK;
 }
 

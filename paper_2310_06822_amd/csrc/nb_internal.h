@@ -146,10 +146,10 @@ struct nb_group {
   int64_t* d_toff = nullptr;
   int box_method = 1;               // 0: scan the box's cells, 1: count table
   // forward plan
-  int n_wg_cap = 0;                 // capacity of d_wg_first - 1 (workgroups of the widest variant grid)
-  int variant = 0;                  // grouped forward tile shape
-  int64_t* d_item_off = nullptr;
-  int64_t* d_wg_first = nullptr;
+  int n_wg_cap = 0;                 // most workgroups of one width class's forward launch
+  int class_variant[3] = {0, 0, 0};   // grouped forward tile shape per width class (32, 64, 128)
+  int64_t* d_item_off = nullptr;    // [n_obj + 3]: first tile of every object, per width class
+  int64_t* d_wg_first = nullptr;    // [3 (n_wg_cap + 1)]: first tile of every workgroup, per width class
   // training work space
   int64_t tr_per_obj = 0;
   float* partial = nullptr;         // [n_wg x P_o] blocks at n_wg * poff[o]

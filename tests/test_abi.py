@@ -92,6 +92,7 @@ def test_group_arguments():
     assert lib.nb_group_forward(None, None, None, 10, 1e-5, None, None, None, None, None) == 1
     assert lib.nb_group_train_step(None, 2, 1, 0, 64, 1.0, None, 1.0, 1e-3, None, None, None, None) == 1
     assert lib.nb_group_set_variant(None, 0) == 1
+    assert lib.nb_group_set_width_variant(None, 32, 0) == 1
     if nb.nb_device_count() == 0:
         assert lib.nb_group_create(3, 6, wp, 3, 1, C.byref(h)) == 2
 

@@ -123,6 +123,29 @@ def test_group_variants_and_counts():
             assert np.array_equal(c[o], L.counts(ho, yo)), (v, o)
 
 
+def test_group_width_variants():
+    """Each width class runs its own launch with its own tile shape: every
+    assignment of shapes to classes gives the same bits, and a bad width or
+    variant is refused."""
+    in_dim, widths, nh, counts = 6, [128, 32, 64, 32, 64, 128], 3, [5000, 3001, 17, 700, 4099, 1]
+    gr, thetas = _group(in_dim, widths, nh, 360)
+    q = cuda(np.concatenate([synth.boxes(370 + o, c) for o, c in enumerate(counts)]))
+    qoff = cuda(np.concatenate([[0], np.cumsum(counts)]).astype(np.int64))
+    nv = nb.nb_group_num_variants(gr.handle)
+    nb.nb_group_set_variant(gr.handle, 0)
+    ref = bits(host(gr.forward(q, qoff)[0]))
+    rng = np.random.default_rng(7)
+    for trial in range(6):
+        pick = {w: int(rng.integers(0, nv)) for w in (32, 64, 128)}
+        for w, v in pick.items():
+            nb.nb_group_set_width_variant(gr.handle, w, v)
+        assert np.array_equal(bits(host(gr.forward(q, qoff)[0])), ref), pick
+    with pytest.raises(RuntimeError):
+        nb.nb_group_set_width_variant(gr.handle, 48, 0)
+    with pytest.raises(RuntimeError):
+        nb.nb_group_set_width_variant(gr.handle, 32, nv)
+
+
 def test_group_forward_many_objects():
     """256 objects (the batched workload's count), 1..600 queries each."""
     rng = np.random.default_rng(5)
