@@ -36,15 +36,52 @@ constexpr GroupShape kGroupShapes[] = {{256, 2}, {512, 2}, {256, 1}, {512, 1},
 constexpr int kGroupVariants = sizeof(kGroupShapes) / sizeof(kGroupShapes[0]);
 __host__ __device__ constexpr int group_blocks(int W, int blocks) { return W >= 128 && blocks > 2 ? 2 : blocks; }
 
-// Fragments of an object's forward pack held in LDS: the first layer's first
-// step and the hidden layers, then (widths 32 and 64) the second first-layer
-// step used for input dimensions above 4; width 128 reads that step from
-// global memory, which keeps two of its workgroups within one CU's LDS.
+// Fragments of an object's forward pack held in LDS: the pack's first
+// first-layer step (unused here: the grouped kernel runs the first layer in
+// float32) and the hidden layers, then the biases and output weights.
 __host__ __device__ constexpr int frags_fwd(int W, int NH) { return W / 16 + (NH - 1) * (W / 16) * (W / 32); }
-__host__ __device__ constexpr bool ext_in_lds(int W) { return W <= 64; }
-__host__ __device__ constexpr int frags_lds(int W, int NH) { return frags_fwd(W, NH) + (ext_in_lds(W) ? W / 16 : 0); }
 __host__ __device__ constexpr size_t group_lds_bytes(int W, int NH) {
-  return (size_t)frags_lds(W, NH) * 64 * 16 + (size_t)(NH * W + W + 1) * 4;
+  return (size_t)frags_fwd(W, NH) * 64 * 16 + (size_t)(NH * W + W + 1) * 4;
+}
+
+// The inputs of one wave's NB blocks of 16 queries that the float32 first
+// layer takes from a lane: features grp and grp + 4 of query column c, as
+// loaded (col_inputs masks them).  Every load reads a row of the object (its
+// last row for padding queries, the last feature for features >= in_dim),
+// so none is predicated; each block's row base is wave-uniform, the lane's
+// offset from it 32-bit.
+template <int NB>
+__device__ __forceinline__ void load_cols(const float* __restrict__ q, int64_t n, int in_dim, int64_t q0, int c,
+                                          int grp, float (&x)[NB][2]) {
+  const int f0 = grp < in_dim ? grp : in_dim - 1, f1 = grp + 4 < in_dim ? grp + 4 : in_dim - 1;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int64_t b0 = q0 + nb * 16;
+    // rows b0 .. b0 + nv - 1 are the object's; a block wholly past its end
+    // reads its last row
+    const int nv = n - b0 <= 0 ? 0 : (n - b0 >= 16 ? 16 : (int)(n - b0));
+    const float* base = q + (nv > 0 ? b0 : n - 1) * in_dim;
+    const int r = c < nv ? c : (nv > 0 ? nv - 1 : 0);
+    x[nb][0] = base[r * in_dim + f0];
+    x[nb][1] = base[r * in_dim + f1];
+  }
+}
+
+// The loaded inputs with features >= in_dim and queries >= n set to zero.
+template <int NB>
+__device__ __forceinline__ void col_inputs(const float (&raw)[NB][2], int64_t n, int in_dim, int64_t q0, int c,
+                                           int grp, float (&x)[NB][2]) {
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int64_t b0 = q0 + nb * 16;
+    const int nv = n - b0 <= 0 ? 0 : (n - b0 >= 16 ? 16 : (int)(n - b0));
+    x[nb][0] = c < nv && grp < in_dim ? raw[nb][0] : 0.0f;
+    x[nb][1] = c < nv && grp + 4 < in_dim ? raw[nb][1] : 0.0f;
+  }
+}
+
+__device__ __forceinline__ floatx4 mfma_f32(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
 // One width class of a grouped forward: the objects perm[p_lo .. p_lo +
@@ -116,7 +153,10 @@ __device__ __forceinline__ void flush_counts(unsigned long long* __restrict__ co
 // share of the class's tiles in order, reloading weights into LDS when the
 // run crosses into the next object (so every object's weights are read
 // about once per workgroup that touches it).  perm, item_off and wg_first
-// are the class's.
+// are the class's.  The first layer runs on the float32 matrix cores
+// (16x16x4: lane group g supplies features g and g + 4, so a lane loads two
+// inputs and holds its slice of the first-layer weights in registers for
+// the whole object); the hidden layers and the output as for single bounds.
 template <int W, int NH, int THREADS, int NB>
 __global__ __launch_bounds__(THREADS) void k_group_fwd(
     const float* __restrict__ q, const int64_t* __restrict__ qoff, int n_obj, int in_dim,
@@ -125,10 +165,10 @@ __global__ __launch_bounds__(THREADS) void k_group_fwd(
     const int64_t* __restrict__ wg_first, float tau, float* __restrict__ logits, uint8_t* __restrict__ hout,
     const uint8_t* __restrict__ g, unsigned long long* __restrict__ counts) {
   constexpr int TILE = THREADS / 64 * NB * 16;
-  constexpr int NF = frags_fwd(W, NH), NFL = frags_lds(W, NH);
+  constexpr int NF = frags_fwd(W, NH), RB = W / 16;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   bf16x8* swt = reinterpret_cast<bf16x8*>(smem_raw);
-  float* sbias = reinterpret_cast<float*>(smem_raw + (size_t)NFL * 64 * 16);
+  float* sbias = reinterpret_cast<float*>(smem_raw + (size_t)NF * 64 * 16);
   const int64_t s = wg_first[blockIdx.x], e = wg_first[blockIdx.x + 1];
   if (s >= e) return;
   // object (in the class's order) of the first tile
@@ -143,46 +183,76 @@ __global__ __launch_bounds__(THREADS) void k_group_fwd(
   }
   int cur = -1;
   const bool wide = in_dim > 4;
-  const bf16x8* sext = ext_in_lds(W) ? swt + NF * 64 : pack;   // the second first-layer step
   unsigned cnt[4] = {0u, 0u, 0u, 0u};
-  const int wave = threadIdx.x >> 6, c = threadIdx.x & 15;
-  // software pipeline: the next tile's inputs load while this tile computes
-  float xr[NB][8];
-  int64_t q0 = qoff[perm[p]] + (s - item_off[p]) * TILE + wave * (NB * 16);
-  int64_t n_end = qoff[perm[p] + 1];
-  load_raw<NB>(q, n_end, in_dim, q0, c, xr);
-  for (int64_t it = s; it < e; ++it) {
+  // the wave index as a uniform value, so that tile offsets and row bases
+  // stay in scalar registers
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), c = lane & 15,
+            grp = lane >> 4;
+  float w1[RB][2];   // first-layer weights W1[16 mo + c][grp + 4 s] of the current object
+  // software pipeline: the next tile's inputs load into the other of two
+  // buffers while this tile computes (two tiles per loop turn, so that no
+  // copy between the buffers waits for the loads)
+  auto tile = [&](int64_t it, const float (&xr)[NB][2], int64_t q0, int64_t n_end, float (&xn)[NB][2],
+                  int64_t& q0n, int64_t& n_endn) {
     const int o = perm[p];
     if (o != cur) {
       flush_counts(counts, cur, cnt);
       __syncthreads();
       const bf16x8* src = pack + pkoff[o];
-      if (!ext_in_lds(W)) sext = src + NF * 64;
-      for (int i = threadIdx.x; i < NFL * 64; i += THREADS) swt[i] = src[i];
+      for (int i = threadIdx.x; i < NF * 64; i += THREADS) swt[i] = src[i];
       const float* th = theta + poff[o];
       for (int i = threadIdx.x; i < NH * W; i += THREADS) sbias[i] = th[nb_b_off(i / W, in_dim, W, NH) + i % W];
       for (int i = threadIdx.x; i < W + 1; i += THREADS) sbias[NH * W + i] = th[nb_w_off(NH, in_dim, W) + i];
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const int k = grp + 4 * t;
+          w1[mo][t] = k < in_dim ? th[(int64_t)(16 * mo + c) * in_dim + k] : 0.0f;
+        }
       __syncthreads();
       cur = o;
     }
-    float xn[NB][8];
-    int64_t q0n = 0, n_endn = 0;
     if (it + 1 < e) {
       while (it + 1 >= item_off[p + 1]) ++p;
       const int on = perm[p];
       q0n = qoff[on] + (it + 1 - item_off[p]) * TILE + wave * (NB * 16);
       n_endn = qoff[on + 1];
-      load_raw<NB>(q, n_endn, in_dim, q0n, c, xn);
+      load_cols<NB>(q, n_endn, in_dim, q0n, c, grp, xn);
     }
-    bf16_fwd_tile_x<W, NH, NB>(swt, sbias, xr, wide, sext, n_end, q0, tau, logits, hout, g, counts, cnt);
-    if (it + 1 < e) {
+    // the loads stay ahead of this tile's work
+    asm volatile("" ::: "memory");
+    float x[NB][2];
+    col_inputs<NB>(xr, n_end, in_dim, q0, c, grp, x);
+    // query columns with a non-finite input: OR over the column's four lanes
+    bool bad[NB];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) xr[nb][j] = xn[nb][j];
-      q0 = q0n;
-      n_end = n_endn;
+    for (int nb = 0; nb < NB; ++nb) {
+      const unsigned long long m = __ballot(!isfinite(x[nb][0]) || !isfinite(x[nb][1]));
+      bad[nb] = ((m | (m >> 16) | (m >> 32) | (m >> 48)) >> c) & 1ull;
     }
+    floatx4 acc[NB][RB];
+#pragma unroll
+    for (int mo = 0; mo < RB; ++mo) {
+      const floatx4 bi = *reinterpret_cast<const floatx4*>(sbias + 16 * mo + 4 * grp);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = mfma_f32(w1[mo][0], x[nb][0], bi);
+    }
+    if (wide) {
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = mfma_f32(w1[mo][1], x[nb][1], acc[nb][mo]);
+    }
+    bf16_fwd_rest<W, NH, NB>(acc, bad, swt, sbias, n_end, q0, tau, logits, hout, g, counts, cnt);
+  };
+  float xa[NB][2], xb[NB][2];
+  int64_t qa = qoff[perm[p]] + (s - item_off[p]) * TILE + wave * (NB * 16), na = qoff[perm[p] + 1];
+  int64_t qb = 0, nb_end = 0;
+  load_cols<NB>(q, na, in_dim, qa, c, grp, xa);
+  for (int64_t it = s; it < e; it += 2) {
+    tile(it, xa, qa, na, xb, qb, nb_end);
+    if (it + 1 < e) tile(it + 1, xb, qb, nb_end, xa, qa, na);
   }
   flush_counts(counts, cur, cnt);
 }
