@@ -133,9 +133,13 @@ class GroupWorkload:
                 "init": 4000 + self.index, "val": 5000 + self.index}
 
 
+# Validation draws of 2^20 boxes per object: the misses left after training
+# are rare boxes that touch an object's surface, and draws of 2^18 found too
+# few of them to raise the objects' FN weights far enough (held-out FN 1-10
+# in 2^24 boxes; 0 with 2^20).
 BATCHED_BOX = GroupWorkload("batched_box", 3, 256, "box", 6, 3, grid_sizes=(32, 64, 128), widths=(32, 64, 128),
                             k_range=(4, 32), train_steps=2000, per_obj=1 << 12, eval_per_obj=1 << 16,
-                            val_per_obj=1 << 18, adapt_k=50, adapt_iters=1500)
+                            val_per_obj=1 << 20, adapt_k=50, adapt_iters=1500)
 
 GROUP_WORKLOADS = {BATCHED_BOX.name: BATCHED_BOX}
 
