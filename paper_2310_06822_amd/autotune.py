@@ -108,22 +108,26 @@ def tune_group(group, q: torch.Tensor, qoff: torch.Tensor, reps: int = 5) -> dic
     return dict(best)
 
 
-def tune_hierarchy(hier, q: torch.Tensor, reps: int = 3) -> int:
-    """Select the grouped-forward tile shape under which a whole hierarchy
-    query (every level) runs fastest for these rows; returns it."""
-    from . import nb_group_num_variants, nb_group_set_variant
+def tune_hierarchy(hier, q: torch.Tensor, reps: int = 3) -> dict:
+    """Select the grouped-forward tile shape of every width class under which
+    a whole hierarchy query (every level) runs fastest for these rows, one
+    class at a time with the others held fixed; returns {width: variant}."""
+    from . import nb_group_num_variants, nb_group_set_width_variant
     g = hier.group
-    best, best_ms = 0, float("inf")
-    for v in range(nb_group_num_variants(g.handle)):
-        nb_group_set_variant(g.handle, v)
-        hier.query(q)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
+    best = {}
+    for w in sorted(set(g.widths)):
+        best_v, best_ms = 0, float("inf")
+        for v in range(nb_group_num_variants(g.handle)):
+            nb_group_set_width_variant(g.handle, w, v)
             hier.query(q)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / reps
-        if ms < best_ms:
-            best, best_ms = v, ms
-    nb_group_set_variant(g.handle, best)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                hier.query(q)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / reps
+            if ms < best_ms:
+                best_v, best_ms = v, ms
+        best[w] = best_v
+        nb_group_set_width_variant(g.handle, w, best_v)
     return best
