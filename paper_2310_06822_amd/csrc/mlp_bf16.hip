@@ -61,9 +61,57 @@ __global__ __launch_bounds__(THREADS) void k_fwd_bf16(const float* __restrict__ 
   const int waves = blockDim.x >> 6;
   unsigned cnt[4] = {0u, 0u, 0u, 0u};
   const int64_t tiles = (n + NB * 16 - 1) / (NB * 16);
+  // The first layer on the float32 matrix cores (16x16x4): lane group g
+  // supplies features g and g + 4 of its query column, so a lane loads two
+  // inputs per block and holds its slice of W_1 (rows 16 mo + c, columns g
+  // and g + 4) in registers; the hidden layers and the output follow
+  // bf16_fwd_rest.  Padding queries read the last row (no predicated loads)
+  // and are zeroed.
+  constexpr int RB = W / 16;
+  const int c = lane & 15, grp = lane >> 4;
+  const bool wide = in_dim > 4;
+  float w1[RB][2];
+#pragma unroll
+  for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int k = grp + 4 * t;
+      w1[mo][t] = k < in_dim ? theta[(int64_t)(16 * mo + c) * in_dim + k] : 0.0f;
+    }
+  const int f0 = grp < in_dim ? grp : in_dim - 1, f1 = grp + 4 < in_dim ? grp + 4 : in_dim - 1;
   for (int64_t tile = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6); tile < tiles;
-       tile += (int64_t)gridDim.x * waves)
-    bf16_fwd_tile<W, NH, NB>(swt, sbias, q, n, in_dim, tile * NB * 16, tau, logits, hout, g, counts, cnt);
+       tile += (int64_t)gridDim.x * waves) {
+    const int64_t q0 = tile * NB * 16;
+    float x[NB][2];
+    bool bad[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int64_t qi = q0 + nb * 16 + c;
+      const bool valid = qi < n;
+      const float* row = q + (valid ? qi : n - 1) * in_dim;
+      const float u0 = row[f0], u1 = row[f1];
+      x[nb][0] = valid && grp < in_dim ? u0 : 0.0f;
+      x[nb][1] = valid && grp + 4 < in_dim ? u1 : 0.0f;
+      const unsigned long long m = __ballot(!isfinite(x[nb][0]) || !isfinite(x[nb][1]));
+      bad[nb] = ((m | (m >> 16) | (m >> 32) | (m >> 48)) >> c) & 1ull;
+    }
+    floatx4 acc[NB][RB];
+#pragma unroll
+    for (int mo = 0; mo < RB; ++mo) {
+      const floatx4 bi = *reinterpret_cast<const floatx4*>(sbias + 16 * mo + 4 * grp);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[nb][mo] = __builtin_amdgcn_mfma_f32_16x16x4f32(w1[mo][0], x[nb][0], bi, 0, 0, 0);
+    }
+    if (wide) {
+#pragma unroll
+      for (int mo = 0; mo < RB; ++mo)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[nb][mo] = __builtin_amdgcn_mfma_f32_16x16x4f32(w1[mo][1], x[nb][1], acc[nb][mo], 0, 0, 0);
+    }
+    bf16_fwd_rest<W, NH, NB>(acc, bad, swt, sbias, n, q0, tau, logits, hout, g, counts, cnt);
+  }
   if (counts && lane == 0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)

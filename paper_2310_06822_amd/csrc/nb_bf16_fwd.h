@@ -1,10 +1,12 @@
-// The bfloat16 forward pass of one wave over NB blocks of 16 queries, shared
-// by the single-bound and grouped kernels (weights already in LDS).
+// The bfloat16 forward pass of one wave over NB blocks of 16 queries after
+// the first layer, shared by the single-bound and grouped kernels (weights
+// already in LDS).
 //
-// Rounding points: the first layer at float32 accuracy (each float32 weight
-// and input cut exactly into three bfloat16 pieces, the six significant
-// piece products on the matrix cores: one K = 32 MFMA step for input
-// dimension <= 4, two for 5..8; layout in nb_mlp.h); hidden layers bfloat16
+// Rounding points: the first layer at float32 accuracy (the resident
+// single-bound and grouped kernels on the float32 matrix cores; the
+// streamed and training kernels cut each float32 weight and input exactly
+// into three bfloat16 pieces and run the six significant piece products on
+// the bfloat16 matrix cores, layout in nb_mlp.h); hidden layers bfloat16
 // weights and activations; output layer a float32 dot product.  Lane l
 // holds neurons 16*mo + 4*(l/16) + r of query l % 16 after every layer; a
 // K = 32 step of the next layer takes the 8 values of row blocks 2*ks and
@@ -28,20 +30,6 @@ struct B16 {
   static constexpr int kBias = NH * W + W + 1;   // hidden biases, output weights, output bias
   static constexpr size_t lds_bytes() { return (size_t)NALL * 64 * 16 + (size_t)kBias * 4; }
 };
-
-// Raw float32 inputs of NB blocks of 16 queries (lane column c); zeros for
-// queries >= n and features >= in_dim.
-template <int NB>
-__device__ __forceinline__ void load_raw(const float* __restrict__ q, int64_t n, int in_dim, int64_t q0, int c,
-                                         float (&xr)[NB][8]) {
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    const int64_t qi = q0 + nb * 16 + c;
-    const bool valid = qi < n;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) xr[nb][j] = (valid && j < in_dim) ? q[qi * in_dim + j] : 0.0f;
-  }
-}
 
 // The hidden layers, output layer and decision of one wave's NB blocks of 16
 // queries starting at q0 (queries >= n are padding), from the first layer's
@@ -136,65 +124,4 @@ __device__ __forceinline__ void bf16_fwd_rest(floatx4 (&acc)[NB][W / 16], const 
       cnt[3] += __popcll(__ballot(own && !pos && gv));
     }
   }
-}
-
-// One wave's share of the forward pass: NB blocks of 16 queries starting at
-// q0 (queries >= n are padding), weights and biases already in LDS, the
-// tile's raw inputs already in registers.  The first layer runs on the
-// bfloat16 matrix cores with the three-piece split; then bf16_fwd_rest.
-// wide: input dimension 5..8, whose second first-layer step reads its
-// fragments from sext (LDS or global memory).
-template <int W, int NH, int NB>
-__device__ __forceinline__ void bf16_fwd_tile_x(const bf16x8* __restrict__ swt, const float* __restrict__ sbias,
-                                                const float (&xr)[NB][8], bool wide, const bf16x8* sext,
-                                                int64_t n, int64_t q0, float tau,
-                                                float* __restrict__ logits, uint8_t* __restrict__ hout,
-                                                const uint8_t* __restrict__ g, const unsigned long long* counts,
-                                                unsigned (&cnt)[4]) {
-  constexpr int RB = B16<W, NH>::RB;
-  const int lane = threadIdx.x & 63, grp = lane >> 4;
-  // rows with a non-finite value (every lane of a query column holds the
-  // whole row; values beyond in_dim are zero)
-  bool bad[NB];
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    bad[nb] = false;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) bad[nb] = bad[nb] || !isfinite(xr[nb][j]);
-  }
-  floatx4 acc[NB][RB];
-  {
-    bf16x8 xb[NB], xb1[NB];
-    nb_first_operands<NB>(xr, grp, wide, xb, xb1);
-#pragma unroll
-    for (int mo = 0; mo < RB; ++mo) {
-      const float* b = sbias + 16 * mo + 4 * grp;
-      const floatx4 bi = floatx4{b[0], b[1], b[2], b[3]};
-      const bf16x8 a = swt[mo * 64 + lane];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = mfma32(a, xb[nb], bi);
-    }
-    if (wide) {
-#pragma unroll
-      for (int mo = 0; mo < RB; ++mo) {
-        const bf16x8 a = sext[mo * 64 + lane];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb][mo] = mfma32(a, xb1[nb], acc[nb][mo]);
-      }
-    }
-  }
-  bf16_fwd_rest<W, NH, NB>(acc, bad, swt, sbias, n, q0, tau, logits, hout, g, counts, cnt);
-}
-
-// As bf16_fwd_tile_x, loading the tile's inputs first.
-template <int W, int NH, int NB>
-__device__ __forceinline__ void bf16_fwd_tile(const bf16x8* __restrict__ swt, const float* __restrict__ sbias,
-                                              const float* __restrict__ q, int64_t n, int in_dim, int64_t q0,
-                                              float tau, float* __restrict__ logits, uint8_t* __restrict__ hout,
-                                              const uint8_t* __restrict__ g, const unsigned long long* counts,
-                                              unsigned (&cnt)[4]) {
-  float xr[NB][8];
-  load_raw<NB>(q, n, in_dim, q0, threadIdx.x & 15, xr);
-  bf16_fwd_tile_x<W, NH, NB>(swt, sbias, xr, in_dim > 4, swt + B16<W, NH>::NFWD * 64, n, q0, tau, logits, hout, g,
-                             counts, cnt);
 }
