@@ -384,9 +384,10 @@ nb_status nb_group_set_box_method(nb_group* g, int method);
 nb_status nb_group_query_exact(const nb_group* g, int kind, const float* q, const int64_t* qoff, int64_t n,
                                uint8_t* g_out, void* stream);
 /* Forward + decision (Eq. 1's logit, h = !(z < tau(eps)) as for a single
- * bound) of every row with its object's bound in one persistent launch:
- * tiles of queries of one object, objects ordered by width, runs of tiles of
- * equal estimated cost per workgroup, weights loaded into LDS once per run.
+ * bound, bit for bit) of every row with its object's bound: one planner
+ * launch, then one persistent launch per width class (tiles of queries of
+ * one object, equal runs of tiles per workgroup, weights loaded into LDS
+ * once per run).
  * logits float32[n] and/or h uint8[n]; with g_exact (uint8[n]) and counts
  * (uint64[n_obj][4], overwritten) also each object's TP, FP, TN, FN.  An
  * object whose rows qoff[o] .. qoff[o+1]-1 do not lie inside [0, n) is
